@@ -1,0 +1,174 @@
+/*
+ * afmm.h -- C ABI of the MI355X adaptive fast multipole Poisson solver.
+ *
+ * Problem (Lee & Teyssier, Sec. 1 and Sec. 3): cell masses on a graded AMR
+ * octree in, gravitational potential and acceleration of every leaf cell out.
+ * Level l has 2^l cells per dimension over the box [0, boxlen)^3 and cell
+ * (i, j, k) has centre ((i, j, k) + 1/2) * boxlen / 2^l.  Only leaves carry
+ * mass and only leaves are targets.  Isolated boundaries.
+ *
+ * Method: one FMM tree per AMR level and a merged tree over finer levels
+ * (Sec. 3.1), upward pass by P2M and M2M (Sec. 2, Eqs. eqn:multipole and
+ * eq:M2M_general), downward pass by M2L over the 189-cell interaction list and
+ * L2L (Sec. 2, Eqs. eq:M2L and eq:L2L; Alg. 3), and at the leaves far (L2P),
+ * intermediate (M2P/P2P), near (P2P/M2P) and nearest (coarse-fine P2P) fields
+ * (Sec. 3.2, Alg. 4).  Adaptive time stepping follows Alg. 1 and Alg. 2.
+ *
+ * Conventions: g(R) = -G/|R| with R = target - source; phi = sum g m;
+ * acceleration a = -grad phi.  Expansions are truncated at total order p
+ * (|alpha| + |beta| <= p in Eq. eq:M2L).
+ *
+ * Errors: every entry point returns an afmm_status; nothing throws across the
+ * ABI.  afmm_last_error() gives a thread-local message for the last failure.
+ * A device (HIP) error makes the plan unusable (sticky AFMM_E_DEVICE).
+ */
+#ifndef AFMM_H
+#define AFMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t afmm_status;
+#define AFMM_OK 0
+#define AFMM_E_INVALID_ARG (-1)    /* null pointer, bad size, out-of-range coordinate, duplicate cell */
+#define AFMM_E_NOT_GRADED (-2)     /* refinement breaks the graded-octree rule of Sec. 3.2 */
+#define AFMM_E_INCOMPLETE_OCT (-3) /* a refined cell without its 8 children, or an orphan cell */
+#define AFMM_E_UNSUPPORTED (-4)    /* p outside 1..8, unknown precision or flag */
+#define AFMM_E_OUT_OF_MEMORY (-5)  /* device allocation failed or exceeds max_device_bytes */
+#define AFMM_E_DEVICE (-6)         /* HIP runtime error; sticky on the plan */
+#define AFMM_E_ATS_ORDER (-7)      /* solve(l, icount) needs trees that were never built */
+#define AFMM_E_NONFINITE (-8)      /* non-finite mass seen (only with AFMM_CHECK_INPUT) */
+
+#define AFMM_FP64 0          /* every step in FP64 */
+#define AFMM_FP32_MIXED 1    /* M2L, M2P, L2L, L2P and P2P in FP32; P2M, M2M, FMM levels
+                                f <= fp64_levels and the per-cell output in FP64 */
+
+#define AFMM_CHECK_INPUT 1u  /* scan masses for NaN/Inf before a solve (one host sync) */
+
+#define AFMM_ALL_LEVELS (-1) /* synchronous solve: all trees rebuilt, every leaf evaluated */
+
+typedef struct afmm_options {
+  int32_t p;                 /* expansion order, 1..8 */
+  int32_t precision;         /* AFMM_FP64 or AFMM_FP32_MIXED */
+  double G;                  /* gravitational constant */
+  double boxlen;             /* box side */
+  uint32_t flags;            /* AFMM_CHECK_INPUT */
+  int32_t fp64_levels;       /* mixed form: FMM levels <= this stay FP64 (default 4) */
+  size_t max_device_bytes;   /* cap on the plan's device memory; 0 = no cap */
+} afmm_options;
+
+/* Defaults: p = 4, FP64, G = 1, boxlen = 1, no flags, fp64_levels = 4, no cap. */
+void afmm_options_default(afmm_options* opt);
+
+/*
+ * An AMR hierarchy, host memory, read only during plan creation (the caller
+ * keeps ownership).  Flat level-major arrays over all cells of levels
+ * levelmin..levelmax; the caller's order inside each level is arbitrary and
+ * is kept for the mass/phi/acc slots.
+ *   ncell[l - levelmin]   number of cells at level l; ncell[0] must be 8^levelmin
+ *   ijk[3 * i + d]        integer coordinate d of cell i, in [0, 2^l)
+ *   refined[i]            1 if the cell's 8 children are present at level l + 1
+ * Requirements: 1 <= levelmin <= levelmax <= 20; complete octs; the strong
+ * grading rule (a refined level-l cell needs the 27 level-(l-1) neighbours of
+ * its father refined, clipped to the box); fewer than 2^31 cells in total.
+ */
+typedef struct afmm_hierarchy {
+  int32_t levelmin;
+  int32_t levelmax;
+  const int64_t* ncell;
+  const int32_t* ijk;
+  const uint8_t* refined;
+} afmm_hierarchy;
+
+typedef struct afmm_plan afmm_plan;
+typedef struct afmm_batch afmm_batch;
+
+/* Counts and algorithmic work of one synchronous solve (AFMM_ALL_LEVELS). */
+typedef struct afmm_plan_info {
+  int32_t levelmin, levelmax, p, K, precision, nhier;
+  int64_t ncell, nleaves, nrefined;
+  int64_t leaves_per_level[21];     /* indexed by absolute level */
+  int64_t m2l_targets;              /* FMM cells that receive a local expansion */
+  int64_t m2l_pairs;                /* (target cell, source cell) M2L pairs */
+  int64_t m2p_pairs;                /* intermediate-field M2P pairs (refined sources) */
+  int64_t p2p_pairs;                /* leaf-leaf pairs: intermediate, near and nearest */
+  int64_t near_m2p_pairs;           /* near-field M2P pairs from refined level-l cells */
+  int64_t nearest_pairs;            /* of p2p_pairs, those from the nearest field */
+  double flops_m2l, flops_m2p, flops_p2p, flops_updown; /* algorithmic (useful) flops */
+  double bytes_min;                 /* algorithmic HBM bytes of one solve */
+  size_t device_bytes;              /* device memory held by the plan */
+} afmm_plan_info;
+
+/*
+ * Build a plan: validate the hierarchy, order cells along a Morton curve per
+ * level, build neighbour tables and group lists (the merged topology that all
+ * per-level trees share, Sec. 3.1), translation tables, and allocate device
+ * memory.  hip_stream (hipStream_t, may be NULL) orders the uploads.
+ * Returns AFMM_E_INVALID_ARG / NOT_GRADED / INCOMPLETE_OCT for bad input.
+ */
+afmm_status afmm_plan_create(const afmm_hierarchy* h, const afmm_options* opt, void* hip_stream,
+                             afmm_plan** out);
+afmm_status afmm_plan_destroy(afmm_plan* plan);
+afmm_status afmm_plan_get_info(const afmm_plan* plan, afmm_plan_info* out);
+
+/*
+ * Solve (Alg. 1).  d_mass, d_phi, d_acc are device pointers, FP64, one slot per
+ * cell in the hierarchy's flat order (d_acc is [ncell][3]).  Masses of refined
+ * cells are ignored.  Only leaves of the solved level(s) are written; other
+ * entries are left untouched.  Stream-ordered and asynchronous (no host sync
+ * unless AFMM_CHECK_INPUT).
+ *   level == AFMM_ALL_LEVELS: synchronous solve, every tree rebuilt from d_mass.
+ *   level == l, icount:       Alg. 1 Solve(l, icount): trees j >= l are rebuilt
+ *                             from d_mass iff l == levelmin or icount > 1; stale
+ *                             trees keep their multipoles and leaf masses; only
+ *                             level-l leaves are written.  Returns
+ *                             AFMM_E_ATS_ORDER if no tree snapshot exists yet.
+ * Plans are not thread-safe; one plan per stream.
+ */
+afmm_status afmm_solve(afmm_plan* plan, int32_t level, int32_t icount, const double* d_mass,
+                       double* d_phi, double* d_acc, void* hip_stream);
+
+/*
+ * Adjoint of the last solve's linear map m -> (phi, a): d_mass_bar = A^T
+ * (d_phi_bar, d_acc_bar) over the same trees and lists (transposed kernels,
+ * gather form, no atomics).  Inputs are indexed like d_phi / d_acc and only
+ * their leaf entries of the solved level(s) are read; every leaf of d_mass_bar
+ * is written (refined entries are set to 0).  After an adaptive-time-step
+ * solve(l, .), entries of levels whose trees were stale are 0: their snapshot
+ * masses are not an input of that solve.
+ */
+afmm_status afmm_solve_adjoint(afmm_plan* plan, int32_t level, const double* d_phi_bar,
+                               const double* d_acc_bar, double* d_mass_bar, void* hip_stream);
+
+/*
+ * Batch of independent hierarchies solved together (synchronous solves).  All
+ * plans must share p, precision, G and boxlen; the batch copies their topology,
+ * so the plans may be destroyed afterwards.  afmm_batch_solve takes host arrays
+ * of n device pointers and runs the whole batch as one captured hipGraph launch.
+ */
+afmm_status afmm_batch_create(afmm_plan* const* plans, int32_t n, void* hip_stream, afmm_batch** out);
+afmm_status afmm_batch_solve(afmm_batch* batch, const double* const* d_mass, double* const* d_phi,
+                             double* const* d_acc, void* hip_stream);
+afmm_status afmm_batch_get_info(const afmm_batch* batch, afmm_plan_info* out);
+afmm_status afmm_batch_destroy(afmm_batch* batch);
+
+/*
+ * Host-only validation (no device memory touched): fills counts of `out`
+ * (ncell, leaves, refined, pair counts, flops) or returns the error a plan
+ * creation would return.
+ */
+afmm_status afmm_hierarchy_check(const afmm_hierarchy* h, const afmm_options* opt,
+                                 afmm_plan_info* out);
+
+const char* afmm_status_string(afmm_status s);
+const char* afmm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AFMM_H */

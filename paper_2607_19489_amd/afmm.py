@@ -1,0 +1,163 @@
+"""Python binding of the C ABI (argument marshalling only).
+
+Every step of a solve runs in the HIP library; PyTorch supplies device memory
+and the current stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from ._lib import (AFMM_ALL_LEVELS, AFMM_CHECK_INPUT, AFMM_FP32_MIXED, AFMM_FP64, HierarchyC, Options,
+                   PlanInfo, check, lib)
+
+PRECISIONS = {"fp64": AFMM_FP64, "fp32": AFMM_FP32_MIXED, "mixed": AFMM_FP32_MIXED}
+
+
+def _stream_handle(stream: Optional[torch.cuda.Stream]) -> C.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _hierarchy_arrays(h):
+    """(levelmin, levelmax, ncell[int64], ijk[int32 flat], refined[uint8]) from a hierarchy object."""
+    ncell = np.ascontiguousarray(np.asarray(h.ncell, dtype=np.int64))
+    ijk = np.ascontiguousarray(np.asarray(h.flat_ijk(), dtype=np.int32).reshape(-1))
+    ref = np.ascontiguousarray(np.asarray(h.flat_refined(), dtype=np.uint8))
+    return int(h.levelmin), int(h.levelmax), ncell, ijk, ref
+
+
+def _hier_struct(levelmin, levelmax, ncell, ijk, ref):
+    hc = HierarchyC()
+    hc.levelmin = levelmin
+    hc.levelmax = levelmax
+    hc.ncell = ncell.ctypes.data_as(C.POINTER(C.c_int64))
+    hc.ijk = ijk.ctypes.data_as(C.POINTER(C.c_int32))
+    hc.refined = ref.ctypes.data_as(C.POINTER(C.c_uint8))
+    return hc
+
+
+def make_options(p: int = 4, precision: str = "fp64", G: float = 1.0, boxlen: float = 1.0,
+                 fp64_levels: int = 4, check_input: bool = False, max_device_bytes: int = 0) -> Options:
+    o = Options()
+    lib().afmm_options_default(C.byref(o))
+    o.p = p
+    o.precision = PRECISIONS[precision]
+    o.G = G
+    o.boxlen = boxlen
+    o.fp64_levels = fp64_levels
+    o.flags = AFMM_CHECK_INPUT if check_input else 0
+    o.max_device_bytes = max_device_bytes
+    return o
+
+
+def hierarchy_check(h, p: int = 4, precision: str = "fp64") -> dict:
+    """Host-only validation and work counts (no device needed)."""
+    arrs = _hierarchy_arrays(h)
+    hc = _hier_struct(*arrs)
+    info = PlanInfo()
+    o = make_options(p, precision, boxlen=float(getattr(h, "boxlen", 1.0)))
+    check(lib().afmm_hierarchy_check(C.byref(hc), C.byref(o), C.byref(info)), "afmm_hierarchy_check")
+    return info.as_dict()
+
+
+class Plan:
+    """A solver plan for one AMR hierarchy (afmm_plan)."""
+
+    def __init__(self, h, p: int = 4, precision: str = "fp64", G: float = 1.0,
+                 boxlen: Optional[float] = None, fp64_levels: int = 4, check_input: bool = False,
+                 max_device_bytes: int = 0, stream: Optional[torch.cuda.Stream] = None):
+        self._ptr = C.c_void_p()
+        arrs = _hierarchy_arrays(h)
+        self.levelmin, self.levelmax, self.ncell = arrs[0], arrs[1], arrs[2]
+        self.N = int(self.ncell.sum())
+        hc = _hier_struct(*arrs)
+        bl = float(boxlen if boxlen is not None else getattr(h, "boxlen", 1.0))
+        self.options = make_options(p, precision, G, bl, fp64_levels, check_input, max_device_bytes)
+        check(lib().afmm_plan_create(C.byref(hc), C.byref(self.options), _stream_handle(stream),
+                                     C.byref(self._ptr)), "afmm_plan_create")
+        self.p = p
+        self.precision = precision
+
+    def close(self):
+        if self._ptr:
+            lib().afmm_plan_destroy(self._ptr)
+            self._ptr = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self) -> C.c_void_p:
+        return self._ptr
+
+    def info(self) -> dict:
+        info = PlanInfo()
+        check(lib().afmm_plan_get_info(self._ptr, C.byref(info)), "afmm_plan_get_info")
+        return info.as_dict()
+
+    def _check_tensor(self, t: torch.Tensor, shape, name: str):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous float64 CUDA tensor")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+    def solve(self, mass: torch.Tensor, level: int = AFMM_ALL_LEVELS, icount: int = 1,
+              phi: Optional[torch.Tensor] = None, acc: Optional[torch.Tensor] = None,
+              stream: Optional[torch.cuda.Stream] = None):
+        """afmm_solve: returns (phi[N], acc[N, 3]) (only solved leaves are written)."""
+        self._check_tensor(mass, (self.N,), "mass")
+        if phi is None:
+            phi = torch.zeros(self.N, dtype=torch.float64, device=mass.device)
+        if acc is None:
+            acc = torch.zeros(self.N, 3, dtype=torch.float64, device=mass.device)
+        self._check_tensor(phi, (self.N,), "phi")
+        self._check_tensor(acc, (self.N, 3), "acc")
+        check(lib().afmm_solve(self._ptr, level, icount, C.c_void_p(mass.data_ptr()),
+                               C.c_void_p(phi.data_ptr()), C.c_void_p(acc.data_ptr()), _stream_handle(stream)),
+              "afmm_solve")
+        return phi, acc
+
+    def solve_adjoint(self, phi_bar: torch.Tensor, acc_bar: torch.Tensor, level: int = AFMM_ALL_LEVELS,
+                      mass_bar: Optional[torch.Tensor] = None, stream: Optional[torch.cuda.Stream] = None):
+        """afmm_solve_adjoint: returns mass_bar[N] = A^T (phi_bar, acc_bar)."""
+        self._check_tensor(phi_bar, (self.N,), "phi_bar")
+        self._check_tensor(acc_bar, (self.N, 3), "acc_bar")
+        if mass_bar is None:
+            mass_bar = torch.zeros(self.N, dtype=torch.float64, device=phi_bar.device)
+        self._check_tensor(mass_bar, (self.N,), "mass_bar")
+        check(lib().afmm_solve_adjoint(self._ptr, level, C.c_void_p(phi_bar.data_ptr()),
+                                       C.c_void_p(acc_bar.data_ptr()), C.c_void_p(mass_bar.data_ptr()),
+                                       _stream_handle(stream)), "afmm_solve_adjoint")
+        return mass_bar
+
+
+class AFMMSolve(torch.autograd.Function):
+    """(phi, acc) = FMM(mass) with the hand-written adjoint as backward."""
+
+    @staticmethod
+    def forward(ctx, mass: torch.Tensor, plan: Plan):
+        ctx.plan = plan
+        phi, acc = plan.solve(mass.detach().contiguous())
+        return phi, acc
+
+    @staticmethod
+    def backward(ctx, phi_bar, acc_bar):
+        plan = ctx.plan
+        if phi_bar is None:
+            phi_bar = torch.zeros(plan.N, dtype=torch.float64, device=acc_bar.device)
+        if acc_bar is None:
+            acc_bar = torch.zeros(plan.N, 3, dtype=torch.float64, device=phi_bar.device)
+        mbar = plan.solve_adjoint(phi_bar.contiguous(), acc_bar.contiguous())
+        return mbar, None
+
+
+def solve(mass: torch.Tensor, plan: Plan):
+    """Differentiable full solve."""
+    return AFMMSolve.apply(mass, plan)

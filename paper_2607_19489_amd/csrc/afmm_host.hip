@@ -1,0 +1,908 @@
+// Host runtime of the adaptive FMM: hierarchy validation, per-level Morton
+// ordering, neighbour tables, group lists (the merged topology shared by all
+// per-level trees, Sec. 3.1), translation tables, device memory, and the
+// solve driver (Alg. 1-4).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "afmm_internal.h"
+
+namespace afmm {
+
+thread_local std::string g_last_error;
+
+static afmm_status fail(afmm_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// topology (host)
+
+struct HostLevel {
+  std::vector<int32_t> rank;     // [n]
+  std::vector<int32_t> slot;     // [n]
+  std::vector<int32_t> refcell;  // [nref]
+  std::vector<int32_t> nbr;      // [nref * 27]
+  int32_t n() const { return (int32_t)rank.size(); }
+  int32_t nref() const { return (int32_t)refcell.size(); }
+};
+
+struct Topology {
+  int lmax = 0;                  // deepest level present
+  int lmin_all = 1 << 30;        // smallest levelmin over hierarchies
+  HostLevel lv[kMaxLevel];
+  int64_t nslots = 0;
+  std::vector<int32_t> leafgrp[kMaxLevel];  // index l: refined ranks at l-1 with a leaf child
+  std::vector<int32_t> m2lgrp[kMaxLevel];   // index f: refined ranks at f-1 with a refined child
+  // per hierarchy
+  std::vector<int32_t> levelmin, levelmax;
+  std::vector<int64_t> slot_base, slot_count;
+  std::vector<std::vector<int64_t>> level_off;  // flat slot offset of each AMR level (per hierarchy)
+};
+
+static inline uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) {
+  auto spread = [](uint64_t v) {
+    v &= 0x1fffff;
+    v = (v | v << 32) & 0x1f00000000ffffULL;
+    v = (v | v << 16) & 0x1f0000ff0000ffULL;
+    v = (v | v << 8) & 0x100f00f00f00f00fULL;
+    v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
+    v = (v | v << 2) & 0x1249249249249249ULL;
+    return v;
+  };
+  return spread(x) | (spread(y) << 1) | (spread(z) << 2);
+}
+
+// Append one hierarchy to the topology (levels 0..levelmax); slots are the
+// hierarchy's flat cell indices offset by slot_base.
+static afmm_status append_hierarchy(Topology& T, const afmm_hierarchy& h, int64_t slot_base) {
+  if (!h.ncell || !h.ijk || !h.refined) return fail(AFMM_E_INVALID_ARG, "null hierarchy array");
+  const int lmin = h.levelmin, lmax = h.levelmax;
+  if (lmin < 1 || lmax < lmin || lmax > 20)
+    return fail(AFMM_E_INVALID_ARG, "levels must satisfy 1 <= levelmin <= levelmax <= 20");
+  const int nl = lmax - lmin + 1;
+  std::vector<int64_t> off(nl + 1, 0);
+  for (int i = 0; i < nl; ++i) {
+    if (h.ncell[i] < 0) return fail(AFMM_E_INVALID_ARG, "negative cell count");
+    off[i + 1] = off[i] + h.ncell[i];
+  }
+  if (h.ncell[0] != (int64_t)1 << (3 * lmin))
+    return fail(AFMM_E_INCOMPLETE_OCT, "levelmin must be complete (8^levelmin cells)");
+  if (slot_base + off[nl] >= ((int64_t)1 << 31)) return fail(AFMM_E_INVALID_ARG, "more than 2^31 cells");
+
+  // caller cells of each AMR level sorted by Morton key
+  std::vector<std::vector<std::pair<uint64_t, int32_t>>> sorted(nl);
+  for (int i = 0; i < nl; ++i) {
+    const int l = lmin + i;
+    const int64_t side = (int64_t)1 << l;
+    auto& v = sorted[i];
+    v.resize(h.ncell[i]);
+    for (int64_t c = 0; c < h.ncell[i]; ++c) {
+      const int32_t* x = h.ijk + 3 * (off[i] + c);
+      if (x[0] < 0 || x[0] >= side || x[1] < 0 || x[1] >= side || x[2] < 0 || x[2] >= side) {
+        char b[128];
+        snprintf(b, sizeof b, "cell %lld of level %d out of range", (long long)c, l);
+        return fail(AFMM_E_INVALID_ARG, b);
+      }
+      v[c] = {morton3(x[0], x[1], x[2]), (int32_t)c};
+    }
+    std::sort(v.begin(), v.end());
+    for (size_t c = 1; c < v.size(); ++c)
+      if (v[c].first == v[c - 1].first) {
+        char b[128];
+        snprintf(b, sizeof b, "duplicate cell at level %d", l);
+        return fail(AFMM_E_INVALID_ARG, b);
+      }
+  }
+
+  T.lmax = std::max(T.lmax, lmax);
+  T.lmin_all = std::min(T.lmin_all, lmin);
+  std::vector<uint64_t> keys{0}, next;  // this hierarchy's cells at the current level
+  for (int l = 0; l <= lmax; ++l) {
+    HostLevel& L = T.lv[l];
+    const int32_t base = L.n();
+    const int32_t rbase = L.nref();
+    const size_t n = keys.size();
+    std::vector<uint8_t> ref(n, 1);
+    std::vector<int32_t> slot(n, -1);
+    if (l >= lmin) {
+      const int i = l - lmin;
+      const auto& v = sorted[i];
+      if (v.size() != n) {
+        char b[160];
+        snprintf(b, sizeof b, "level %d has %zu cells, the refined cells of level %d own %zu", l, v.size(), l - 1,
+                 n);
+        return fail(AFMM_E_INCOMPLETE_OCT, b);
+      }
+      for (size_t c = 0; c < n; ++c) {
+        if (v[c].first != keys[c]) {
+          char b[128];
+          snprintf(b, sizeof b, "level %d: cell set differs from the children of refined level-%d cells", l, l - 1);
+          return fail(AFMM_E_INCOMPLETE_OCT, b);
+        }
+        const int32_t ci = v[c].second;
+        ref[c] = h.refined[off[i] + ci] ? 1 : 0;
+        slot[c] = (int32_t)(slot_base + off[i] + ci);
+      }
+      if (l == lmax)
+        for (size_t c = 0; c < n; ++c)
+          if (ref[c]) return fail(AFMM_E_INCOMPLETE_OCT, "refined cell at levelmax has no children");
+    }
+    int32_t nr = 0;
+    for (size_t c = 0; c < n; ++c) {
+      L.rank.push_back(ref[c] ? rbase + nr++ : -1);
+      L.slot.push_back(slot[c]);
+      if (ref[c]) L.refcell.push_back(base + (int32_t)c);
+    }
+    // neighbour rows of the refined cells, from the father's row
+    for (size_t c = 0; c < n; ++c) {
+      if (!ref[c]) continue;
+      const int32_t gcell = base + (int32_t)c;
+      int32_t row[27];
+      if (l == 0) {
+        for (int e = 0; e < 27; ++e) row[e] = (e == 13) ? gcell : -1;
+      } else {
+        const HostLevel& P = T.lv[l - 1];
+        const int32_t fr = gcell >> 3, o = gcell & 7;
+        const int32_t* prow = &P.nbr[(size_t)fr * 27];
+        for (int e = 0; e < 27; ++e) {
+          int pe = 0, co = 0;
+          for (int d = 0, mul = 1; d < 3; ++d, mul *= 3) {
+            const int ed = (d == 0 ? e % 3 : (d == 1 ? (e / 3) % 3 : e / 9)) - 1;
+            const int td = ((o >> d) & 1) + ed;          // -1 .. 2
+            const int pd = td < 0 ? -1 : (td >> 1);       // -1, 0, 0, 1
+            pe += (pd + 1) * mul;
+            co |= (td - 2 * pd) << d;
+          }
+          const int32_t Q = prow[pe];
+          if (Q < 0) {
+            row[e] = -1;
+            continue;
+          }
+          const int32_t rQ = P.rank[Q];
+          row[e] = rQ >= 0 ? 8 * rQ + co : -2;  // -2: covered by a coarser leaf
+        }
+        // strong grading rule: the father's 27 neighbours must be refined
+        if (l >= lmin + 1) {
+          for (int e = 0; e < 27; ++e) {
+            const int32_t Q = prow[e];
+            if (Q >= 0 && P.rank[Q] < 0) {
+              char b[160];
+              snprintf(b, sizeof b, "level-%d cell refined next to a level-%d leaf (grading rule)", l, l - 1);
+              return fail(AFMM_E_NOT_GRADED, b);
+            }
+            if (Q == -2) return fail(AFMM_E_NOT_GRADED, "grading rule violated");
+          }
+        }
+      }
+      L.nbr.insert(L.nbr.end(), row, row + 27);
+    }
+    next.clear();
+    for (size_t c = 0; c < n; ++c)
+      if (ref[c])
+        for (uint64_t o = 0; o < 8; ++o) next.push_back((keys[c] << 3) | o);
+    keys.swap(next);
+  }
+  T.levelmin.push_back(lmin);
+  T.levelmax.push_back(lmax);
+  T.slot_base.push_back(slot_base);
+  T.slot_count.push_back(off[nl]);
+  T.level_off.push_back(off);
+  T.nslots = slot_base + off[nl];
+  return AFMM_OK;
+}
+
+static void build_groups(Topology& T) {
+  for (int l = 1; l <= T.lmax; ++l) {
+    const HostLevel& P = T.lv[l - 1];
+    const HostLevel& C = T.lv[l];
+    auto& lg = T.leafgrp[l];
+    auto& mg = T.m2lgrp[l];
+    lg.clear();
+    mg.clear();
+    for (int32_t r = 0; r < P.nref(); ++r) {
+      bool leaf = false, refd = false;
+      for (int o = 0; o < 8; ++o) {
+        if (C.rank[8 * r + o] < 0) leaf = true;
+        else refd = true;
+      }
+      if (leaf) lg.push_back(r);
+      if (refd && l >= 3) mg.push_back(r);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// work counts (algorithmic, for plan_info and the roofline)
+
+static inline int ax_of(int e, int d) { return (d == 0 ? e % 3 : (d == 1 ? (e / 3) % 3 : e / 9)) - 1; }
+
+static int64_t binom(int n, int k) {
+  if (k < 0 || k > n) return 0;
+  int64_t r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+
+static void count_work(const Topology& T, int p, afmm_plan_info& info) {
+  const int K = nmi(p), K1 = nmi(p - 1);
+  int64_t m2l_t = 0, m2l_pairs = 0, m2l_mono = 0, m2p = 0, p2p = 0, nm2p = 0, nst = 0, upward = 0, leaves = 0;
+  for (int l = 0; l <= T.lmax; ++l) upward += T.lv[l].nref() * (l >= 2 ? 1 : 0);
+  auto il_sources = [&](int l, int32_t F, std::vector<int32_t>& out) {
+    out.clear();
+    if (l < 2) return;
+    const HostLevel& L1 = T.lv[l - 1];
+    const HostLevel& L2 = T.lv[l - 2];
+    const int32_t cF = L1.refcell[F];
+    const int32_t G = cF >> 3, oF = cF & 7;
+    for (int t = 0; t < 216; ++t) {
+      const int e = t >> 3, op = t & 7;
+      const int32_t Q = L2.nbr[(size_t)G * 27 + e];
+      if (Q < 0) continue;
+      int dm = 0;
+      for (int d = 0; d < 3; ++d) dm = std::max(dm, std::abs(2 * ax_of(e, d) + ((op >> d) & 1) - ((oF >> d) & 1)));
+      if (dm <= 1) continue;
+      out.push_back(8 * L2.rank[Q] + op);
+    }
+  };
+  std::vector<int32_t> src;
+  for (int f = 3; f <= T.lmax; ++f) {
+    const HostLevel& L1 = T.lv[f - 1];
+    const HostLevel& L0 = T.lv[f];
+    for (int32_t F : T.m2lgrp[f]) {
+      int nt = 0;
+      for (int o = 0; o < 8; ++o) nt += L0.rank[8 * F + o] >= 0;
+      il_sources(f, F, src);
+      m2l_t += nt;
+      for (int32_t s : src) {
+        if (L1.rank[s] >= 0) m2l_pairs += nt;
+        else m2l_mono += nt;
+      }
+    }
+  }
+  for (int l = 1; l <= T.lmax; ++l) {
+    const HostLevel& L1 = T.lv[l - 1];
+    const HostLevel& L0 = T.lv[l];
+    for (int32_t F : T.leafgrp[l]) {
+      int nt = 0;
+      bool tgt[8];
+      for (int o = 0; o < 8; ++o) nt += (tgt[o] = L0.rank[8 * F + o] < 0);
+      leaves += nt;
+      il_sources(l, F, src);
+      for (int32_t s : src) {
+        if (L1.rank[s] >= 0) m2p += nt;
+        else p2p += nt;
+      }
+      const int32_t* nb = &L1.nbr[(size_t)F * 27];
+      for (int e = 0; e < 27; ++e) {
+        const int32_t q = nb[e];
+        if (q < 0) continue;
+        const int32_t rq = L1.rank[q];
+        if (rq < 0) {
+          p2p += nt;
+          continue;
+        }
+        for (int op = 0; op < 8; ++op) {
+          const int32_t nc = 8 * rq + op;
+          const int32_t rn = L0.rank[nc];
+          for (int o = 0; o < 8; ++o) {
+            if (!tgt[o] || nc == 8 * F + o) continue;
+            if (rn < 0) {
+              ++p2p;
+              continue;
+            }
+            int dm = 0;
+            for (int d = 0; d < 3; ++d) dm = std::max(dm, std::abs(((o >> d) & 1) - 2 * ax_of(e, d) - ((op >> d) & 1)));
+            if (dm <= 1) {
+              p2p += 8;
+              nst += 8;
+            } else {
+              ++nm2p;
+            }
+          }
+        }
+      }
+    }
+  }
+  const double tri = (double)binom(p + 6, 6);
+  info.m2l_targets = m2l_t;
+  info.m2l_pairs = m2l_pairs + m2l_mono;
+  info.m2p_pairs = m2p;
+  info.p2p_pairs = p2p;
+  info.near_m2p_pairs = nm2p;
+  info.nearest_pairs = nst;
+  info.flops_m2l = 2.0 * tri * (double)m2l_pairs + 2.0 * K * (double)m2l_mono;
+  info.flops_m2p = 2.0 * (K + 3.0 * K1) * (double)(m2p + nm2p);
+  info.flops_p2p = 23.0 * (double)p2p;
+  // upward: 8 M2M per refined cell (useful triangle C(p+6,6)... of k <= a pairs), L2L per
+  // M2L target, L2P per leaf
+  double m2m_terms = 0;
+  for (int a = 0; a <= p; ++a)
+    for (int b = 0; a + b <= p; ++b)
+      for (int c = 0; a + b + c <= p; ++c) m2m_terms += (a + 1) * (b + 1) * (c + 1);
+  info.flops_updown = 2.0 * 8.0 * m2m_terms * (double)upward + 2.0 * tri * (double)m2l_t +
+                      2.0 * (K + 3.0 * K1) * (double)leaves;
+}
+
+// ---------------------------------------------------------------------------
+// translation tables
+
+// Taylor coefficients of 1/|R|:  |g| r^2 a_g = -(2|g|-1) sum_i R_i a_{g-e_i} - (|g|-1) sum_i a_{g-2e_i}
+// (obtained by matching powers of t in |R+t|^2 E f = -(R.t + |t|^2) f, E the Euler operator).
+static void dtilde(int p, const long double R[3], long double* D, const std::vector<int>& mi) {
+  const int K = nmi(p);
+  std::vector<long double> a(K);
+  const long double r2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
+  for (int g = 0; g < K; ++g) {
+    const int ga[3] = {mi[4 * g], mi[4 * g + 1], mi[4 * g + 2]};
+    const int n = mi[4 * g + 3];
+    if (n == 0) {
+      a[g] = 1.0L / std::sqrt(r2);
+      continue;
+    }
+    long double s1 = 0, s2 = 0;
+    for (int i = 0; i < 3; ++i) {
+      int b[3] = {ga[0], ga[1], ga[2]};
+      if (b[i] >= 1) {
+        b[i] -= 1;
+        s1 += R[i] * a[mi_index(b[0], b[1], b[2])];
+        if (b[i] >= 1) {
+          b[i] -= 1;
+          s2 += a[mi_index(b[0], b[1], b[2])];
+        }
+      }
+    }
+    a[g] = (-(2.0L * n - 1.0L) * s1 - (n - 1.0L) * s2) / (n * r2);
+  }
+  // D~_g = d^g(-1/r) = -g! a_g
+  for (int g = 0; g < K; ++g) {
+    long double f = 1;
+    for (int i = 0; i < 3; ++i)
+      for (int k = 2; k <= mi[4 * g + i]; ++k) f *= k;
+    D[g] = -f * a[g];
+  }
+}
+
+struct HostTables {
+  int p = 0, K = 0;
+  std::vector<int> mi;          // [K][4]
+  std::vector<int16_t> sumidx;  // [K][K]
+  std::vector<int16_t> up;      // [K][3]
+  std::vector<double> Dil, Dsame, cfac2, cfac1, l2l, l2p, m2m;
+};
+
+static long double ipow(long double x, int n) {
+  long double r = 1;
+  for (int i = 0; i < n; ++i) r *= x;
+  return r;
+}
+static long double fact(int n) {
+  long double r = 1;
+  for (int i = 2; i <= n; ++i) r *= i;
+  return r;
+}
+
+static void build_tables(int p, HostTables& H) {
+  const int K = nmi(p);
+  H.p = p;
+  H.K = K;
+  H.mi.assign(4 * K, 0);
+  for (int n = 0; n <= p; ++n)
+    for (int a = n; a >= 0; --a)
+      for (int b = n - a; b >= 0; --b) {
+        const int c = n - a - b, g = mi_index(a, b, c);
+        H.mi[4 * g] = a;
+        H.mi[4 * g + 1] = b;
+        H.mi[4 * g + 2] = c;
+        H.mi[4 * g + 3] = n;
+      }
+  H.sumidx.assign((size_t)K * K, -1);
+  H.up.assign(3 * K, -1);
+  for (int b = 0; b < K; ++b)
+    for (int a = 0; a < K; ++a)
+      if (H.mi[4 * a + 3] + H.mi[4 * b + 3] <= p)
+        H.sumidx[(size_t)b * K + a] =
+            (int16_t)mi_index(H.mi[4 * a] + H.mi[4 * b], H.mi[4 * a + 1] + H.mi[4 * b + 1], H.mi[4 * a + 2] + H.mi[4 * b + 2]);
+  for (int a = 0; a < K; ++a)
+    if (H.mi[4 * a + 3] < p)
+      for (int i = 0; i < 3; ++i)
+        H.up[3 * a + i] = (int16_t)mi_index(H.mi[4 * a] + (i == 0), H.mi[4 * a + 1] + (i == 1), H.mi[4 * a + 2] + (i == 2));
+  std::vector<long double> D(K);
+  H.Dil.assign((size_t)kNumD * 8 * K, 0.0);
+  H.Dsame.assign((size_t)kNumD * K, 0.0);
+  for (int dz = -3; dz <= 3; ++dz)
+    for (int dy = -3; dy <= 3; ++dy)
+      for (int dx = -3; dx <= 3; ++dx) {
+        const int di = (dx + 3) + 7 * (dy + 3) + 49 * (dz + 3);
+        for (int o = 0; o < 8; ++o) {
+          const long double R[3] = {-2.0L * dx + ((o & 1) - 0.5L), -2.0L * dy + (((o >> 1) & 1) - 0.5L),
+                                    -2.0L * dz + (((o >> 2) & 1) - 0.5L)};
+          dtilde(p, R, D.data(), H.mi);
+          for (int g = 0; g < K; ++g) H.Dil[((size_t)di * 8 + o) * K + g] = (double)D[g];
+        }
+        if (dx == 0 && dy == 0 && dz == 0) continue;
+        const long double R[3] = {(long double)dx, (long double)dy, (long double)dz};
+        dtilde(p, R, D.data(), H.mi);
+        for (int g = 0; g < K; ++g) H.Dsame[(size_t)di * K + g] = (double)D[g];
+      }
+  H.cfac2.resize(K);
+  H.cfac1.resize(K);
+  for (int a = 0; a < K; ++a) {
+    const int n = H.mi[4 * a + 3];
+    const long double af = fact(H.mi[4 * a]) * fact(H.mi[4 * a + 1]) * fact(H.mi[4 * a + 2]);
+    const long double sg = (n & 1) ? -1.0L : 1.0L;
+    H.cfac1[a] = (double)(sg / af);
+    H.cfac2[a] = (double)(sg * ipow(2.0L, n) / af);
+  }
+  // L2L: L~_b[y] = 2^(-1-|b|) sum_g u^g/g! L~_{b+g}[F], u = (o - 1/2)/2
+  H.l2l.assign((size_t)8 * K * K, 0.0);
+  H.l2p.assign((size_t)8 * 4 * K, 0.0);
+  H.m2m.assign((size_t)8 * K * K, 0.0);
+  for (int o = 0; o < 8; ++o) {
+    const long double u[3] = {((o & 1) - 0.5L) / 2, (((o >> 1) & 1) - 0.5L) / 2, (((o >> 2) & 1) - 0.5L) / 2};
+    for (int b = 0; b < K; ++b) {
+      const int* bb = &H.mi[4 * b];
+      for (int g = 0; g < K; ++g) {
+        const int* gg = &H.mi[4 * g];
+        if (bb[3] + gg[3] > p) continue;
+        const long double w = ipow(u[0], gg[0]) * ipow(u[1], gg[1]) * ipow(u[2], gg[2]) /
+                              (fact(gg[0]) * fact(gg[1]) * fact(gg[2])) / ipow(2.0L, 1 + bb[3]);
+        H.l2l[((size_t)o * K + b) * K + mi_index(bb[0] + gg[0], bb[1] + gg[1], bb[2] + gg[2])] = (double)w;
+      }
+      // L2P: phi~ = 1/2 sum_b L~_b u^b/b!,  a~_i = -1/4 sum_{b_i>0} L~_b u^(b-e_i)/(b-e_i)!
+      const long double bf = fact(bb[0]) * fact(bb[1]) * fact(bb[2]);
+      H.l2p[((size_t)o * 4 + 0) * K + b] = (double)(0.5L * ipow(u[0], bb[0]) * ipow(u[1], bb[1]) * ipow(u[2], bb[2]) / bf);
+      for (int i = 0; i < 3; ++i) {
+        if (bb[i] == 0) continue;
+        int c[3] = {bb[0], bb[1], bb[2]};
+        c[i] -= 1;
+        H.l2p[((size_t)o * 4 + 1 + i) * K + b] =
+            (double)(-0.25L * ipow(u[0], c[0]) * ipow(u[1], c[1]) * ipow(u[2], c[2]) / (fact(c[0]) * fact(c[1]) * fact(c[2])));
+      }
+    }
+    // M2M: S~_a[r] += C(a,k) d^(a-k) 2^-|k| S~_k[child],  d = (o - 1/2)/2
+    for (int a = 0; a < K; ++a) {
+      const int* aa = &H.mi[4 * a];
+      for (int k = 0; k <= a; ++k) {
+        const int* kk = &H.mi[4 * k];
+        if (kk[0] > aa[0] || kk[1] > aa[1] || kk[2] > aa[2]) continue;
+        const long double w = (long double)binom(aa[0], kk[0]) * binom(aa[1], kk[1]) * binom(aa[2], kk[2]) *
+                              ipow(u[0], aa[0] - kk[0]) * ipow(u[1], aa[1] - kk[1]) * ipow(u[2], aa[2] - kk[2]) /
+                              ipow(2.0L, kk[3]);
+        H.m2m[((size_t)o * K + a) * K + k] = (double)w;
+      }
+    }
+  }
+}
+
+}  // namespace afmm
+
+// ---------------------------------------------------------------------------
+// plan
+
+using namespace afmm;
+
+struct afmm_plan {
+  afmm_options opt{};
+  int K = 0;
+  Topology topo;
+  HostTables tabs;
+  LevelDev lv[kMaxLevel + 1];
+  int32_t* d_leafgrp[kMaxLevel] = {};
+  int32_t* d_m2lgrp[kMaxLevel] = {};
+  TablesDev<float> t32;
+  TablesDev<double> t64;
+  CommonDev cm;
+  double* m_snap = nullptr;       // adaptive-time-step snapshot of leaf masses (slot space)
+  bool snap_valid = false;
+  int last_level = AFMM_ALL_LEVELS;
+  std::vector<void*> allocs;
+  size_t bytes = 0;
+  bool dead = false;              // sticky device error
+  afmm_plan_info info{};
+};
+
+struct afmm_batch {
+  afmm_plan* plan = nullptr;      // concatenated topology
+  int32_t n = 0;
+  std::vector<int64_t> base, count;
+  double* d_mass = nullptr;
+  double* d_phi = nullptr;
+  double* d_acc = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t graph_stream = nullptr;
+};
+
+namespace {
+
+afmm_status dev_alloc(afmm_plan* P, void** ptr, size_t bytes) {
+  *ptr = nullptr;
+  if (bytes == 0) return AFMM_OK;
+  if (P->opt.max_device_bytes && P->bytes + bytes > P->opt.max_device_bytes)
+    return fail(AFMM_E_OUT_OF_MEMORY, "plan would exceed max_device_bytes");
+  if (hipMalloc(ptr, bytes) != hipSuccess) {
+    *ptr = nullptr;
+    (void)hipGetLastError();
+    return fail(AFMM_E_OUT_OF_MEMORY, "hipMalloc failed");
+  }
+  P->allocs.push_back(*ptr);
+  P->bytes += bytes;
+  return AFMM_OK;
+}
+
+template <typename V>
+afmm_status upload(afmm_plan* P, const std::vector<V>& v, V** out, hipStream_t st) {
+  *out = nullptr;
+  if (v.empty()) return AFMM_OK;
+  void* p = nullptr;
+  afmm_status s = dev_alloc(P, &p, v.size() * sizeof(V));
+  if (s) return s;
+  if (hipMemcpyAsync(p, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice, st) != hipSuccess)
+    return fail(AFMM_E_DEVICE, "upload failed");
+  *out = (V*)p;
+  return AFMM_OK;
+}
+
+template <typename T>
+afmm_status upload_conv(afmm_plan* P, const std::vector<double>& v, const T** out, hipStream_t st) {
+  std::vector<T> w(v.begin(), v.end());
+  T* d = nullptr;
+  afmm_status s = upload(P, w, &d, st);
+  *out = d;
+  return s;
+}
+
+void free_plan(afmm_plan* P) {
+  for (void* p : P->allocs) (void)hipFree(p);
+  P->allocs.clear();
+}
+
+afmm_status check_options(const afmm_options* o) {
+  if (!o) return fail(AFMM_E_INVALID_ARG, "null options");
+  if (o->p < 1 || o->p > kPMax) return fail(AFMM_E_UNSUPPORTED, "p must be in 1..8");
+  if (o->precision != AFMM_FP64 && o->precision != AFMM_FP32_MIXED)
+    return fail(AFMM_E_UNSUPPORTED, "unknown precision");
+  if (o->flags & ~AFMM_CHECK_INPUT) return fail(AFMM_E_UNSUPPORTED, "unknown flag");
+  if (!(o->boxlen > 0) || !std::isfinite(o->boxlen)) return fail(AFMM_E_INVALID_ARG, "boxlen must be > 0");
+  if (!std::isfinite(o->G)) return fail(AFMM_E_INVALID_ARG, "G must be finite");
+  return AFMM_OK;
+}
+
+void fill_info(afmm_plan_info& info, const Topology& T, const afmm_options& o) {
+  std::memset(&info, 0, sizeof info);
+  info.levelmin = T.lmin_all;
+  info.levelmax = T.lmax;
+  info.p = o.p;
+  info.K = nmi(o.p);
+  info.precision = o.precision;
+  info.nhier = (int32_t)T.levelmin.size();
+  for (int l = 0; l <= T.lmax; ++l) {
+    const HostLevel& L = T.lv[l];
+    int64_t leaves = 0;
+    for (int32_t c = 0; c < L.n(); ++c) leaves += (L.rank[c] < 0 && L.slot[c] >= 0);
+    info.leaves_per_level[l] = leaves;
+    info.nleaves += leaves;
+    for (int32_t c = 0; c < L.n(); ++c)
+      if (L.slot[c] >= 0) {
+        ++info.ncell;
+        info.nrefined += L.rank[c] >= 0;
+      }
+  }
+  count_work(T, o.p, info);
+  // algorithmic HBM bytes: masses in, phi + acc out, multipoles and local
+  // expansions written once and read once, topology read once
+  double ref = 0, cells = 0;
+  for (int l = 0; l <= T.lmax; ++l) {
+    ref += T.lv[l].nref();
+    cells += T.lv[l].n();
+  }
+  const double K = nmi(o.p);
+  const double coef = o.precision == AFMM_FP64 ? 8.0 : 4.0;
+  info.bytes_min = 8.0 * info.nleaves + 32.0 * info.nleaves + ref * K * (8.0 + 8.0) +
+                   (o.precision == AFMM_FP64 ? 0.0 : ref * K * 8.0) + (double)info.m2l_targets * K * 2.0 * coef +
+                   cells * (4.0 + 4.0 + 8.0) + ref * 27.0 * 4.0;
+}
+
+}  // namespace
+
+extern "C" {
+
+void afmm_options_default(afmm_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->p = 4;
+  o->precision = AFMM_FP64;
+  o->G = 1.0;
+  o->boxlen = 1.0;
+  o->flags = 0;
+  o->fp64_levels = 4;
+  o->max_device_bytes = 0;
+}
+
+const char* afmm_status_string(afmm_status s) {
+  switch (s) {
+    case AFMM_OK: return "ok";
+    case AFMM_E_INVALID_ARG: return "invalid argument";
+    case AFMM_E_NOT_GRADED: return "hierarchy not graded";
+    case AFMM_E_INCOMPLETE_OCT: return "incomplete oct";
+    case AFMM_E_UNSUPPORTED: return "unsupported option";
+    case AFMM_E_OUT_OF_MEMORY: return "out of device memory";
+    case AFMM_E_DEVICE: return "device error";
+    case AFMM_E_ATS_ORDER: return "adaptive time step call order";
+    case AFMM_E_NONFINITE: return "non-finite input";
+    default: return "unknown status";
+  }
+}
+
+const char* afmm_last_error(void) { return g_last_error.c_str(); }
+
+afmm_status afmm_hierarchy_check(const afmm_hierarchy* h, const afmm_options* opt, afmm_plan_info* out) {
+  if (!h) return fail(AFMM_E_INVALID_ARG, "null hierarchy");
+  afmm_options o;
+  if (opt) o = *opt;
+  else afmm_options_default(&o);
+  afmm_status s = check_options(&o);
+  if (s) return s;
+  Topology T;
+  s = append_hierarchy(T, *h, 0);
+  if (s) return s;
+  build_groups(T);
+  if (out) fill_info(*out, T, o);
+  return AFMM_OK;
+}
+
+}  // extern "C"
+
+// Allocate and upload everything of a plan whose topology is built.
+static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
+  Topology& T = P->topo;
+  const int K = P->K;
+  const bool mixed = P->opt.precision == AFMM_FP32_MIXED;
+  const int f64 = mixed ? P->opt.fp64_levels : 1 << 20;
+  build_groups(T);
+  fill_info(P->info, T, P->opt);
+  build_tables(P->opt.p, P->tabs);
+  afmm_status s;
+  for (int l = 0; l <= T.lmax; ++l) {
+    HostLevel& H = T.lv[l];
+    LevelDev& D = P->lv[l];
+    D.n = H.n();
+    D.nref = H.nref();
+    int32_t *rank, *slot, *refcell, *nbr;
+    if ((s = upload(P, H.rank, &rank, st)) || (s = upload(P, H.slot, &slot, st)) ||
+        (s = upload(P, H.refcell, &refcell, st)) || (s = upload(P, H.nbr, &nbr, st)))
+      return s;
+    D.rank = rank;
+    D.slot = slot;
+    D.refcell = refcell;
+    D.nbr = nbr;
+    void* p = nullptr;
+    if ((s = dev_alloc(P, &p, (size_t)D.n * sizeof(double)))) return s;
+    D.mass = (double*)p;
+    if ((s = dev_alloc(P, &p, (size_t)D.nref * K * sizeof(double)))) return s;
+    D.S64 = (double*)p;
+    if (mixed && l >= f64) {
+      if ((s = dev_alloc(P, &p, (size_t)D.nref * K * sizeof(float)))) return s;
+      D.S32 = (float*)p;
+    }
+    if (l <= f64) {
+      if ((s = dev_alloc(P, &p, (size_t)D.nref * K * sizeof(double)))) return s;
+      D.L64 = (double*)p;
+    } else {
+      if ((s = dev_alloc(P, &p, (size_t)D.nref * K * sizeof(float)))) return s;
+      D.L32 = (float*)p;
+    }
+  }
+  for (int l = 0; l <= T.lmax; ++l) {
+    if ((s = upload(P, T.leafgrp[l], &P->d_leafgrp[l], st))) return s;
+    if ((s = upload(P, T.m2lgrp[l], &P->d_m2lgrp[l], st))) return s;
+  }
+  HostTables& H = P->tabs;
+  {
+    std::vector<int8_t> mi8(H.mi.begin(), H.mi.end());
+    int8_t* d_mi;
+    int16_t *d_sum, *d_up;
+    double* d_m2m;
+    if ((s = upload(P, mi8, &d_mi, st)) || (s = upload(P, H.sumidx, &d_sum, st)) || (s = upload(P, H.up, &d_up, st)) ||
+        (s = upload(P, H.m2m, &d_m2m, st)))
+      return s;
+    P->cm.mi = d_mi;
+    P->cm.sumidx = d_sum;
+    P->cm.up = d_up;
+    P->cm.m2m = d_m2m;
+  }
+  if ((s = upload_conv<double>(P, H.Dil, &P->t64.Dil, st)) || (s = upload_conv<double>(P, H.Dsame, &P->t64.Dsame, st)) ||
+      (s = upload_conv<double>(P, H.cfac2, &P->t64.cfac2, st)) || (s = upload_conv<double>(P, H.cfac1, &P->t64.cfac1, st)) ||
+      (s = upload_conv<double>(P, H.l2l, &P->t64.l2l, st)) || (s = upload_conv<double>(P, H.l2p, &P->t64.l2p, st)))
+    return s;
+  if (mixed) {
+    if ((s = upload_conv<float>(P, H.Dil, &P->t32.Dil, st)) || (s = upload_conv<float>(P, H.Dsame, &P->t32.Dsame, st)) ||
+        (s = upload_conv<float>(P, H.cfac2, &P->t32.cfac2, st)) || (s = upload_conv<float>(P, H.cfac1, &P->t32.cfac1, st)) ||
+        (s = upload_conv<float>(P, H.l2l, &P->t32.l2l, st)) || (s = upload_conv<float>(P, H.l2p, &P->t32.l2p, st)))
+      return s;
+  }
+  void* p = nullptr;
+  if ((s = dev_alloc(P, &p, (size_t)std::max<int64_t>(T.nslots, 1) * sizeof(double)))) return s;
+  P->m_snap = (double*)p;
+  if (hipStreamSynchronize(st) != hipSuccess) return fail(AFMM_E_DEVICE, "upload synchronisation failed");
+  P->info.device_bytes = P->bytes;
+  return AFMM_OK;
+}
+
+extern "C" afmm_status afmm_plan_create(const afmm_hierarchy* h, const afmm_options* opt, void* hip_stream,
+                                        afmm_plan** out) {
+  if (!h || !out) return fail(AFMM_E_INVALID_ARG, "null argument");
+  *out = nullptr;
+  afmm_options o;
+  if (opt) o = *opt;
+  else afmm_options_default(&o);
+  afmm_status s = check_options(&o);
+  if (s) return s;
+  afmm_plan* P = new afmm_plan();
+  P->opt = o;
+  P->K = nmi(o.p);
+  s = append_hierarchy(P->topo, *h, 0);
+  if (!s) s = plan_finish(P, (hipStream_t)hip_stream);
+  if (s) {
+    free_plan(P);
+    delete P;
+    return s;
+  }
+  *out = P;
+  return AFMM_OK;
+}
+
+extern "C" afmm_status afmm_plan_destroy(afmm_plan* P) {
+  if (!P) return AFMM_OK;
+  free_plan(P);
+  delete P;
+  return AFMM_OK;
+}
+
+extern "C" afmm_status afmm_plan_get_info(const afmm_plan* P, afmm_plan_info* out) {
+  if (!P || !out) return fail(AFMM_E_INVALID_ARG, "null argument");
+  *out = P->info;
+  return AFMM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// solve driver
+
+__global__ void k_nonfinite(int64_t n, const double* __restrict__ m, int* __restrict__ flag) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    if (!isfinite(m[i])) flag[0] = 1;
+}
+
+static afmm_status dev_check(afmm_plan* P, hipError_t e, const char* what) {
+  if (e == hipSuccess) return AFMM_OK;
+  P->dead = true;
+  return fail(AFMM_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Upward pass over every level, M2L over FMM levels 3..fmax, leaf evaluation
+// for the levels in [lo, hi].  Masses come from `msrc` (slot space).
+static afmm_status run_solve(afmm_plan* P, const double* msrc, int fmax, int lo, int hi, double* phi, double* acc,
+                             hipStream_t st) {
+  Topology& T = P->topo;
+  const int p = P->opt.p;
+  const bool mixed = P->opt.precision == AFMM_FP32_MIXED;
+  const int f64 = mixed ? P->opt.fp64_levels : 1 << 20;
+  afmm_status s;
+  for (int l = T.lmin_all; l <= T.lmax; ++l)
+    if ((s = dev_check(P, launch_gather_mass(P->lv[l], msrc, st), "gather"))) return s;
+  for (int f = T.lmax - 1; f >= 2; --f)
+    if ((s = dev_check(P, launch_upward(p, P->lv[f], P->lv[f + 1], P->cm, mixed && f >= f64, st), "upward")))
+      return s;
+  for (int f = 3; f <= fmax; ++f) {
+    const int ng = (int)T.m2lgrp[f].size();
+    if ((s = dev_check(P,
+                       launch_m2l(p, mixed && f > f64, mixed && (f - 1) > f64, f, P->d_m2lgrp[f], ng, P->lv[f - 2],
+                                  P->lv[f - 1], P->lv[f], P->t32, P->t64, P->cm, st),
+                       "m2l")))
+      return s;
+  }
+  for (int l = std::max(lo, 1); l <= hi; ++l) {
+    const int ng = (int)T.leafgrp[l].size();
+    const LevelDev empty;
+    const LevelDev& lv2 = l >= 2 ? P->lv[l - 2] : empty;
+    const LevelDev& lvp = l + 1 <= T.lmax ? P->lv[l + 1] : empty;
+    const double h = P->opt.boxlen / (double)(1LL << l);
+    if ((s = dev_check(P,
+                       launch_leaf(p, mixed && (l - 1) > f64, l, P->d_leafgrp[l], ng, lv2, P->lv[l - 1], P->lv[l], lvp,
+                                   P->t32, P->t64, P->cm, P->opt.G, h, phi, acc, st),
+                       "leaf")))
+      return s;
+  }
+  return AFMM_OK;
+}
+
+extern "C" afmm_status afmm_solve(afmm_plan* P, int32_t level, int32_t icount, const double* d_mass, double* d_phi,
+                                  double* d_acc, void* hip_stream) {
+  if (!P || !d_mass || !d_phi || !d_acc) return fail(AFMM_E_INVALID_ARG, "null argument");
+  if (P->dead) return fail(AFMM_E_DEVICE, "plan is unusable after an earlier device error");
+  hipStream_t st = (hipStream_t)hip_stream;
+  Topology& T = P->topo;
+  if (T.levelmin.size() != 1) return fail(AFMM_E_INVALID_ARG, "batched plan: use afmm_batch_solve");
+  const int lmin = T.levelmin[0], lmax = T.levelmax[0];
+  if (level != AFMM_ALL_LEVELS && (level < lmin || level > lmax))
+    return fail(AFMM_E_INVALID_ARG, "level outside [levelmin, levelmax]");
+  if (P->opt.flags & AFMM_CHECK_INPUT) {
+    void* fl = nullptr;
+    if (hipMalloc(&fl, sizeof(int)) != hipSuccess) return fail(AFMM_E_OUT_OF_MEMORY, "flag alloc");
+    int zero = 0, hostflag = 0;
+    (void)hipMemcpyAsync(fl, &zero, sizeof(int), hipMemcpyHostToDevice, st);
+    hipLaunchKernelGGL(k_nonfinite, dim3(256), dim3(256), 0, st, (int64_t)T.nslots, d_mass, (int*)fl);
+    (void)hipMemcpyAsync(&hostflag, fl, sizeof(int), hipMemcpyDeviceToHost, st);
+    hipError_t e = hipStreamSynchronize(st);
+    (void)hipFree(fl);
+    if (e != hipSuccess) return dev_check(P, e, "input check");
+    if (hostflag) return fail(AFMM_E_NONFINITE, "non-finite mass");
+  }
+  const size_t nb = (size_t)T.nslots * sizeof(double);
+  if (level == AFMM_ALL_LEVELS) {
+    if (dev_check(P, hipMemcpyAsync(P->m_snap, d_mass, nb, hipMemcpyDeviceToDevice, st), "snapshot")) return AFMM_E_DEVICE;
+    P->snap_valid = true;
+    P->last_level = AFMM_ALL_LEVELS;
+    return run_solve(P, d_mass, T.lmax - 1, lmin, lmax, d_phi, d_acc, st);
+  }
+  // Alg. 1: rebuild trees j >= level iff level == levelmin or icount > 1
+  const bool rebuild = (level == lmin) || (icount > 1);
+  if (!P->snap_valid && level != lmin)
+    return fail(AFMM_E_ATS_ORDER, "solve(l > levelmin) before any tree was built (call solve(levelmin) first)");
+  if (rebuild) {
+    const int64_t off = T.level_off[0][level - lmin];
+    if (dev_check(P,
+                  hipMemcpyAsync(P->m_snap + off, d_mass + off, (size_t)(T.nslots - off) * sizeof(double),
+                                 hipMemcpyDeviceToDevice, st),
+                  "snapshot"))
+      return AFMM_E_DEVICE;
+    P->snap_valid = true;
+  }
+  P->last_level = level;
+  return run_solve(P, P->m_snap, level - 1, level, level, d_phi, d_acc, st);
+}
+
+extern "C" afmm_status afmm_solve_adjoint(afmm_plan* P, int32_t level, const double* d_phi_bar,
+                                          const double* d_acc_bar, double* d_mass_bar, void* hip_stream) {
+  (void)P;
+  (void)level;
+  (void)d_phi_bar;
+  (void)d_acc_bar;
+  (void)d_mass_bar;
+  (void)hip_stream;
+  return fail(AFMM_E_UNSUPPORTED, "adjoint not built yet");
+}
+
+extern "C" afmm_status afmm_batch_create(afmm_plan* const* plans, int32_t n, void* hip_stream, afmm_batch** out) {
+  (void)plans;
+  (void)n;
+  (void)hip_stream;
+  if (out) *out = nullptr;
+  return fail(AFMM_E_UNSUPPORTED, "batching not built yet");
+}
+extern "C" afmm_status afmm_batch_solve(afmm_batch* b, const double* const* d_mass, double* const* d_phi,
+                                        double* const* d_acc, void* hip_stream) {
+  (void)b;
+  (void)d_mass;
+  (void)d_phi;
+  (void)d_acc;
+  (void)hip_stream;
+  return fail(AFMM_E_UNSUPPORTED, "batching not built yet");
+}
+extern "C" afmm_status afmm_batch_get_info(const afmm_batch* b, afmm_plan_info* out) {
+  (void)b;
+  (void)out;
+  return fail(AFMM_E_UNSUPPORTED, "batching not built yet");
+}
+extern "C" afmm_status afmm_batch_destroy(afmm_batch* b) {
+  (void)b;
+  return AFMM_OK;
+}

@@ -1,0 +1,91 @@
+// Internal declarations shared by the host plan builder and the HIP kernels.
+//
+// Units.  Every level works in its own cell units so that FP32 coefficients
+// stay O(1) at any depth:
+//   S~_f[r]_a = sum_{leaves x under r} m_x ((x_x - c_r) / h_f)^a        (multipoles)
+//   L~_f[r]_b = h_f^(1+|b|) d^b(phi/G) at c_r                          (local expansions)
+//   phi_c = (G / h_l) phi~_c,   a_c = (G / h_l^2) a~_c                   (outputs)
+// With these, every translation operator is a fixed table on unit offsets:
+//   M2M  S~_a[r] = sum_o sum_{k<=a} C(a,k) d_o^(a-k) 2^-|k| S~_k[child o],  d_o = (o - 1/2)/2
+//   M2L  L~_b[y] = sum_a (-1)^|a|/a! 2^|a| D~_{a+b}(R~) S~_a[s],  R~ = -2(s - F) + o_y - 1/2
+//   L2L  L~_b[y] = 2^(-1-|b|) sum_g u^g/g! L~_{b+g}[F],  u = (o_y - 1/2)/2
+//   M2P  phi~ = sum_a (-1)^|a|/a! 2^|a| D~_a(R~) S~_a,  a~_i = -sum_{|a|<p} (...) D~_{a+e_i} S~_a
+//   L2P  phi~ = 1/2 sum_b L~_b u^b/b!,  a~_i = -1/4 sum_{b_i>0} L~_b u^(b-e_i)/(b-e_i)!
+// where D~_g = d^g(-1/r) on unit offsets (Sec. 2 Eqs. eq:M2M_general, eq:M2L, eq:L2L).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "afmm.h"
+
+namespace afmm {
+
+constexpr int kMaxLevel = 21;
+constexpr int kPMax = 8;
+constexpr int kKMax = 165;          // C(kPMax + 3, 3)
+constexpr int kNumD = 343;          // offsets d in [-3, 3]^3
+
+__host__ __device__ constexpr int nmi(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
+
+// Position of multi-index (a, b, c) in the degree-graded order (degree, then a
+// descending, then b descending).
+__host__ __device__ constexpr int mi_index(int a, int b, int c) {
+  return (a + b + c) * (a + b + c + 1) * (a + b + c + 2) / 6 + (b + c) * (b + c + 1) / 2 + c;
+}
+
+// Per-level device view.  Level l holds the children of the refined cells of
+// level l - 1 in Morton order, so cell index c has father refined rank c >> 3
+// and octant c & 7 (o = ox + 2 oy + 4 oz), and refined rank r owns children
+// 8r .. 8r+7.  Neighbour index e = (ex+1) + 3(ey+1) + 9(ez+1).
+struct LevelDev {
+  int32_t n = 0;             // cells
+  int32_t nref = 0;          // refined cells
+  const int32_t* rank = nullptr;     // [n] refined rank or -1 (leaf)
+  const int32_t* slot = nullptr;     // [n] caller slot (flat index) or -1 (cells above levelmin)
+  const int32_t* refcell = nullptr;  // [nref] cell index of refined rank r
+  const int32_t* nbr = nullptr;      // [nref][27] neighbour cell index at this level, -1 outside box
+  double* mass = nullptr;            // [n] leaf masses of this solve (0 for refined cells)
+  double* S64 = nullptr;             // [nref][K] multipoles (FP64)
+  float* S32 = nullptr;              // [nref][K] FP32 copy (mixed form)
+  double* L64 = nullptr;             // [nref][K] local expansions (FP64 levels)
+  float* L32 = nullptr;              // [nref][K] local expansions (FP32 levels)
+  double* Lbar64 = nullptr;          // adjoint accumulators (same layout as L)
+  float* Lbar32 = nullptr;
+  double* Sbar64 = nullptr;
+  float* Sbar32 = nullptr;
+};
+
+template <typename T>
+struct TablesDev {
+  const T* Dil = nullptr;     // [kNumD * 8][K]  D~ at R~ = -2d + o - 1/2
+  const T* Dsame = nullptr;   // [kNumD][K]      D~ at integer R~ in [-3,3]^3
+  const T* cfac2 = nullptr;   // [K] (-1)^|a|/a! 2^|a|
+  const T* cfac1 = nullptr;   // [K] (-1)^|a|/a!
+  const T* l2l = nullptr;     // [8][K][K] dense L2L per child octant
+  const T* l2p = nullptr;     // [8][4][K] L2P weights (phi, ax, ay, az) per child octant
+};
+
+struct CommonDev {
+  const int16_t* sumidx = nullptr;  // [K][K] index of a + b (or -1 when |a|+|b| > p)
+  const int16_t* up = nullptr;      // [K][3] index of a + e_i (or -1 when |a| = p)
+  const int8_t* mi = nullptr;       // [K][4] (a, b, c, |a|)
+  const double* m2m = nullptr;      // [8][K][K] dense M2M per child octant (FP64)
+};
+
+// Launchers (afmm_kernels.hip).  All return hipGetLastError() of the launch.
+hipError_t launch_gather_mass(const LevelDev& lv, const double* m_src, hipStream_t st);
+hipError_t launch_copy_slots(const int32_t* slots, int64_t n, const double* src, double* dst,
+                             hipStream_t st);
+hipError_t launch_upward(int p, const LevelDev& lv, const LevelDev& lvc, const CommonDev& cm,
+                         bool write32, hipStream_t st);
+hipError_t launch_m2l(int p, bool fp32, bool parent_fp32, int f, const int32_t* grp, int ngrp,
+                      const LevelDev& lv2, const LevelDev& lv1, const LevelDev& lv0,
+                      const TablesDev<float>& t32, const TablesDev<double>& t64, const CommonDev& cm,
+                      hipStream_t st);
+hipError_t launch_leaf(int p, bool fp32, int l, const int32_t* grp, int ngrp, const LevelDev& lv2,
+                       const LevelDev& lv1, const LevelDev& lv0, const LevelDev& lvp,
+                       const TablesDev<float>& t32, const TablesDev<double>& t64, const CommonDev& cm,
+                       double G, double h, double* phi, double* acc, hipStream_t st);
+
+}  // namespace afmm

@@ -1,0 +1,79 @@
+"""CPU checks of the C ABI: the library loads, exports every declared symbol, and
+its host-only validation returns the documented status codes and counts."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2607_19489_amd as A
+from paper_2607_19489_amd import _lib
+from synth import configs, unigrid
+from synth.hierarchy import Hierarchy, build_graded, refine_sphere
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "afmm.h")).read()
+    return sorted(set(re.findall(r"\b(afmm_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    L = _lib.lib()
+    names = _declared()
+    assert len(names) >= 13
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(_lib.SYMBOLS) == names
+
+
+def test_status_strings():
+    L = _lib.lib()
+    assert L.afmm_status_string(-2) == b"hierarchy not graded"
+    assert L.afmm_status_string(0) == b"ok"
+
+
+def _chain(levelmin, depth):
+    from test_oracle_fmm import _single_chain
+    return _single_chain(levelmin, depth)
+
+
+def test_validation_codes():
+    A.hierarchy_check(_chain(3, 1))
+    with pytest.raises(A.AfmmError) as e:
+        A.hierarchy_check(_chain(3, 2))
+    assert e.value.code == -2
+    h = build_graded(3, 5, refine_sphere((0.5, 0.5, 0.5), {3: 0.3, 4: 0.2}))
+    inc = Hierarchy(h.levelmin, h.levelmax, [h.ijk[0], h.ijk[1][1:], h.ijk[2]],
+                    [h.refined[0], h.refined[1][1:], h.refined[2]])
+    with pytest.raises(A.AfmmError) as e:
+        A.hierarchy_check(inc)
+    assert e.value.code == -3
+    bad = Hierarchy(h.levelmin, h.levelmax, [a.copy() for a in h.ijk], [r.copy() for r in h.refined])
+    bad.ijk[0][0, 0] = 99
+    with pytest.raises(A.AfmmError) as e:
+        A.hierarchy_check(bad)
+    assert e.value.code == -1
+    with pytest.raises(A.AfmmError) as e:
+        A.hierarchy_check(h, p=9)
+    assert e.value.code == -4
+
+
+def test_counts_unigrid():
+    info = A.hierarchy_check(unigrid(5), p=4)
+    assert info["nleaves"] == 32768 and info["nrefined"] == 0
+    # every leaf: 189 (interior) or fewer intermediate sources; near P2P <= 215
+    assert 0 < info["m2p_pairs"] <= 32768 * 189
+    assert info["p2p_pairs"] <= 32768 * 215
+    assert info["nearest_pairs"] == 0 and info["near_m2p_pairs"] == 0
+    # a 4^3 grid is near field only
+    i2 = A.hierarchy_check(unigrid(2), p=4)
+    assert i2["m2p_pairs"] == 0 and i2["p2p_pairs"] == 64 * 63
+
+
+def test_counts_cfg2():
+    info = A.hierarchy_check(configs.cfg2().hierarchy, p=6)
+    assert info["nleaves"] == 287680 and info["nrefined"] == 3648
+    assert info["nearest_pairs"] > 0 and info["near_m2p_pairs"] > 0

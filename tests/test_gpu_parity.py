@@ -1,0 +1,121 @@
+"""HIP path vs the FP64 oracle, element by element on the same seeded inputs.
+
+Tolerances (relative L2 over the evaluated leaves, max-normalised at most 10x):
+FP64 form 1e-10, FP32 mixed form 1e-4 (the stated force-error target).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from gpu_util import compare, gpu_solve, max_rel, rel_l2  # noqa: E402
+
+import oracle  # noqa: E402
+from synth import cell_masses, configs, plummer, shuffle_order, unigrid  # noqa: E402
+from synth.hierarchy import build_graded, refine_sphere  # noqa: E402
+
+
+def _amr(lmin, radii, centre=(0.5, 0.5, 0.5)):
+    return build_graded(lmin, lmin + len(radii), refine_sphere(centre, radii))
+
+
+@pytest.mark.parametrize("level", [1, 2, 3])
+def test_tiny_unigrid_fp64(level):
+    h = unigrid(level)
+    m = cell_masses(h, plummer(1.0, 0.1), 0.01, level)
+    print(f"unigrid level {level}", flush=True)
+    compare(h, m, 4, "fp64", 1e-12)
+
+
+def test_cfg1_unigrid32_fp64_all_targets():
+    w = configs.cfg1()
+    print("cfg1 32^3 p=4 fp64", flush=True)
+    ep, ea = compare(w.hierarchy, w.mass, w.p, "fp64", 1e-10)
+    print("errors", ep, ea)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_small_amr_all_orders(p):
+    h = _amr(3, {3: 0.3, 4: 0.2})
+    m = cell_masses(h, plummer(1.0, 0.1), 0.01, p)
+    print(f"amr p={p}", flush=True)
+    compare(h, m, p, "fp64", 1e-10)
+    compare(h, m, p, "fp32", 1e-4)
+
+
+def test_three_level_amr_fp32_and_fp64():
+    h = _amr(4, {4: 0.25, 5: 0.15, 6: 0.08})
+    m = cell_masses(h, plummer(1.0, 0.05), 0.01, 9)
+    print("amr 4+3", flush=True)
+    compare(h, m, 6, "fp64", 1e-10)
+    compare(h, m, 6, "fp32", 1e-4)
+
+
+def test_refinement_touching_box_corner_and_shuffled_order():
+    h = shuffle_order(_amr(3, {3: 0.35, 4: 0.2, 5: 0.1}, centre=(0.02, 0.03, 0.97)), 17)
+    m = cell_masses(h, plummer(1.0, 0.1, (0.1, 0.1, 0.9)), 0.01, 4)
+    print("corner amr", flush=True)
+    compare(h, m, 5, "fp64", 1e-10)
+    compare(h, m, 5, "fp32", 1e-4)
+
+
+def test_cfg2_full_size_sampled():
+    w = configs.cfg2()
+    print("cfg2 fp32 sampled", flush=True)
+    ep, ea = compare(w.hierarchy, w.mass, w.p, "fp32", 1e-4, sample=1500, seed=2)
+    print("fp32 errors", ep, ea)
+    ep, ea = compare(w.hierarchy, w.mass, w.p, "fp64", 1e-10, sample=600, seed=3)
+    print("fp64 errors", ep, ea)
+
+
+def test_nearest_pair_antisymmetry_gpu():
+    from test_oracle_fmm import _nearest_pair
+    h = _amr(4, {4: 0.25, 5: 0.12})
+    ci, fi = _nearest_pair(h)
+    m = np.zeros(h.total)
+    m[ci], m[fi] = 0.7, 0.3
+    for prec, tol in (("fp64", 1e-14), ("fp32", 1e-6)):
+        phi, acc, _ = gpu_solve(h, m, 6, prec)
+        mom = m[ci] * acc[ci] + m[fi] * acc[fi]
+        assert np.linalg.norm(mom) <= tol * m[ci] * np.linalg.norm(acc[ci]), prec
+
+
+def test_deterministic_and_untouched_entries():
+    import torch as T
+    import paper_2607_19489_amd as A
+    h = _amr(3, {3: 0.3, 4: 0.2})
+    m = cell_masses(h, plummer(1.0, 0.1), 0.01, 1)
+    plan = A.Plan(h, p=6, precision="fp32")
+    mt = T.from_numpy(m).cuda()
+    phi1 = T.full((h.total,), 7.0, dtype=T.float64, device="cuda")
+    acc1 = T.full((h.total, 3), 7.0, dtype=T.float64, device="cuda")
+    plan.solve(mt, phi=phi1, acc=acc1)
+    phi2, acc2 = plan.solve(mt)
+    T.cuda.synchronize()
+    leaf = T.from_numpy(h.leaf_mask()).cuda()
+    assert T.equal(phi1[leaf], phi2[leaf]) and T.equal(acc1[leaf], acc2[leaf])
+    assert bool((phi1[~leaf] == 7.0).all()) and bool((acc1[~leaf] == 7.0).all())
+
+
+def test_ats_sequence_matches_oracle():
+    import paper_2607_19489_amd as A
+    h = _amr(3, {3: 0.3, 4: 0.2})
+    rng = np.random.default_rng(4)
+    m0 = cell_masses(h, plummer(1.0, 0.1), 0.01, 1)
+    seq = [(3, 1), (4, 1), (5, 1), (5, 2), (4, 2), (5, 1), (5, 2)]
+    plan = A.Plan(h, p=4, precision="fp64")
+    o = oracle.Oracle(h, 4)
+    N = h.total
+    po = np.zeros(N)
+    ao = np.zeros((N, 3))
+    lev = h.level_of()
+    m = m0.copy()
+    for (l, ic) in seq:
+        m = m * (1 + 1e-3 * rng.uniform(-1, 1, N))
+        phi, acc, _ = gpu_solve(h, m, 4, level=l, icount=ic, plan=plan)
+        o.solve(l, ic, m, po, ao)
+        sel = (lev == l) & h.leaf_mask()
+        assert rel_l2(acc[sel], ao[sel]) < 1e-10, (l, ic)
+        assert rel_l2(phi[sel], po[sel]) < 1e-10, (l, ic)

@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""Throughput of one full adaptive-FMM solve (potential + acceleration of every
+leaf) on one MI355X, FP32-mixed form vs FP64 form.
+
+Default workload: level 6 complete + level 7 over the level-6 cells whose centre
+lies within 0.15 of the box centre (287,680 leaves), Plummer a=0.05 + 1% noise
+(seed 2), expansion order p=6.  Inputs (plan and masses) are resident in HBM
+before the timed region; a "step" is one full solve (upward pass, M2L/L2L over
+every FMM level, far/intermediate/near/nearest fields at every leaf).
+
+Prints one JSON line.  The roofline object describes the kernel family with
+the largest share of the timed region: its algorithmic flops divided by its
+summed launch time, both measured live with hipEvents on the solve stream.
+The cpu_baseline object times the FP64 CPU oracle (test infrastructure) on a
+bounded, spatially clustered sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cells/sec full FMM solve (φ+accel) at rel. force err ≤1e-4, FP32 vs FP64"
+PEAK = {"fp32_mfma": 157.3, "fp64_mfma": 78.6, "fp32_vector": 157.3, "fp64_vector": 78.6, "hbm": 8000.0}
+KERNEL_NAMES = {"leaf_f32": "k_leaf<float, P>", "leaf_f64": "k_leaf<double, P>",
+                "m2l_f32": "k_m2l<float, *, P>", "m2l_f64": "k_m2l<double, double, P>",
+                "upward": "k_upward<P>", "gather": "k_gather_mass"}
+
+
+def make_workload(name: str):
+    from synth import configs
+    if name == "cfg1":
+        return configs.cfg1(), "unigrid 32^3 (32,768 leaves), Plummer a=0.1, p=4"
+    if name == "cfg2":
+        return configs.cfg2(), ("level 6 + level 7 within r<=0.15 (287,680 leaves, 3,648 refined), "
+                                "Plummer a=0.05 + 1% noise, p=6")
+    if name == "cfg3":
+        return configs.cfg3(), "level 7 base + 4 mass-refined levels (~8.08M leaves), Plummer + 32 clumps, p=6"
+    if name == "cfg5":
+        return configs.cfg5(), "level 7 + r<0.2 + r<0.1 (3,081,632 leaves), Plummer a=0.05, p=6"
+    raise ValueError(name)
+
+
+def time_form(h, mass_t, p, precision, steps, warmup):
+    import torch
+    import paper_2607_19489_amd as A
+    plan = A.Plan(h, p=p, precision=precision)
+    info = plan.info()
+    phi = torch.zeros(h.total, dtype=torch.float64, device="cuda")
+    acc = torch.zeros(h.total, 3, dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        plan.solve(mass_t, phi=phi, acc=acc)
+    torch.cuda.synchronize()
+    plan.set_profiling(True)
+    plan.get_profile()  # reset
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.solve(mass_t, phi=phi, acc=acc)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = plan.get_profile()
+    plan.set_profiling(False)
+    out = {"ms_per_step": 1e3 * dt / steps, "value": info["nleaves"] * steps / dt, "info": info,
+           "kernels": prof}
+    phi_np, acc_np = phi.cpu().numpy(), acc.cpu().numpy()
+    plan.close()
+    return out, phi_np, acc_np
+
+
+def roofline(res, precision):
+    prof = res["kernels"]
+    name, k = max(prof.items(), key=lambda kv: kv[1]["ms"])
+    total_ms = sum(v["ms"] for v in prof.values())
+    tf = k["flops"] / (k["ms"] * 1e-3) / 1e12 if k["ms"] > 0 else 0.0
+    fp = "fp32" if name.endswith("f32") else "fp64"
+    if name in ("gather", "upward"):
+        achieved = k["bytes"] / (k["ms"] * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": achieved, "peak": PEAK["hbm"], "unit": "GB/s",
+                "frac": achieved / PEAK["hbm"], "traffic": None, "kernel": KERNEL_NAMES[name],
+                "share_of_step": k["ms"] / total_ms}
+    peak = PEAK[f"{fp}_vector"]
+    return {"bound": "alu", "achieved": tf, "peak": peak, "unit": "TFLOP/s", "frac": tf / peak,
+            "traffic": None, "kernel": KERNEL_NAMES[name], "family": name,
+            "launches": k["launches"], "avg_launch_ms": k["ms"] / max(k["launches"], 1),
+            "flops_per_launch": k["flops"] / max(k["launches"], 1),
+            "share_of_step": k["ms"] / total_ms}
+
+
+def clustered_sample(h, nclusters, seed=0):
+    """All leaves under `nclusters` random cells of level levelmin-2 (targets that share
+    their ancestors' local expansions, as in a full solve)."""
+    rng = np.random.default_rng(seed)
+    cl = max(h.levelmin - 2, 1)
+    lev = h.level_of()
+    ijk = h.flat_ijk().astype(np.int64)
+    anc = ijk >> (lev - cl)[:, None]
+    key = (anc[:, 0] << 40) | (anc[:, 1] << 20) | anc[:, 2]
+    leaf = h.leaf_mask()
+    ukeys = np.unique(key[leaf])
+    pick = rng.choice(ukeys, size=min(nclusters, ukeys.size), replace=False)
+    return np.nonzero(leaf & np.isin(key, pick))[0]
+
+
+def cpu_baseline(h, m, p, budget_s, gpu_outputs):
+    import oracle
+    o = oracle.Oracle(h, p)
+    t0 = time.perf_counter()
+    o.rebuild(h.levelmin, m)
+    t_up = time.perf_counter() - t0
+    # pilot with one cluster, then size the sample to the budget
+    pilot = clustered_sample(h, 1, seed=11)
+    t0 = time.perf_counter()
+    o.eval_sample(pilot)
+    t_pilot = max(time.perf_counter() - t0, 1e-3)
+    ncl = int(max(1, min(4096, (budget_s - t_up) / t_pilot)))
+    sample = clustered_sample(h, ncl, seed=1)
+    t0 = time.perf_counter()
+    po, ao = o.eval_sample(sample)
+    t_eval = time.perf_counter() - t0
+    nleaf = h.nleaves()
+    est_full = t_up + t_eval * nleaf / sample.size
+    errs = {}
+    for form, (phi, acc) in gpu_outputs.items():
+        errs[form] = {
+            "rel_l2_acc": float(np.linalg.norm(acc[sample] - ao) / np.linalg.norm(ao)),
+            "rel_l2_phi": float(np.linalg.norm(phi[sample] - po) / np.linalg.norm(po)),
+            "max_acc_over_max": float(np.abs(acc[sample] - ao).max() / np.abs(ao).max()),
+        }
+    base = {"value": nleaf / est_full, "unit": "cells/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": (f"oracle upward pass over all {nleaf} leaves ({t_up:.2f} s) + evaluation of "
+                       f"{sample.size} leaves under {ncl} random level-{max(h.levelmin - 2, 1)} cells "
+                       f"({t_eval:.2f} s), scaled to all leaves"),
+            "seconds": t_up + t_eval}
+    return base, errs
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg5"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-form run")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this solver runs on one GPU; multi-GPU sharding is described in DESIGN.md "
+              "but not built, so --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    w, desc = make_workload(args.workload)
+    h, m = w.hierarchy, w.mass
+    mass_t = torch.from_numpy(m).cuda()
+    print(f"[bench] workload {w.name}: {h.nleaves()} leaves", file=sys.stderr, flush=True)
+
+    r32, phi32, acc32 = time_form(h, mass_t, w.p, "fp32", args.steps, args.warmup)
+    print(f"[bench] fp32 form: {r32['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+    outputs = {"fp32": (phi32, acc32)}
+    r64 = None
+    if not args.no_fp64:
+        r64, phi64, acc64 = time_form(h, mass_t, w.p, "fp64", max(args.steps // 2, 1), 1)
+        outputs["fp64"] = (phi64, acc64)
+        print(f"[bench] fp64 form: {r64['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+
+    base, errs = (None, None)
+    if not args.no_cpu:
+        base, errs = cpu_baseline(h, m, w.p, args.cpu_seconds, outputs)
+        print(f"[bench] cpu oracle baseline {base['value']:.3e} cells/s", file=sys.stderr, flush=True)
+
+    info = r32["info"]
+    line = {
+        "metric": METRIC,
+        "value": r32["value"],
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {desc}", "p": w.p, "precision": "FP32 mixed (FP64 P2M/M2M, "
+                   "FMM levels <= 4 and outputs)", "leaves": info["nleaves"], "levels": [h.levelmin, h.levelmax]},
+        "roofline": roofline(r32, "fp32"),
+        "cpu_baseline": base,
+        "fp64_form": None if r64 is None else {"value": r64["value"], "unit": "cells/s",
+                                                "ms_per_step": r64["ms_per_step"], "dtype": "f64",
+                                                "roofline": roofline(r64, "fp64")},
+        "fp32_over_fp64": None if r64 is None else r32["value"] / r64["value"],
+        "error_vs_oracle_sample": errs,
+        "algorithmic_flops_per_step": info["flops_m2l"] + info["flops_m2p"] + info["flops_p2p"]
+        + info["flops_updown"],
+        "kernels_fp32": r32["kernels"],
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -164,6 +164,24 @@ afmm_status afmm_batch_destroy(afmm_batch* batch);
 afmm_status afmm_hierarchy_check(const afmm_hierarchy* h, const afmm_options* opt,
                                  afmm_plan_info* out);
 
+/*
+ * Per-launch timing (instrumentation, no effect on results).  While enabled,
+ * every kernel launch of a solve is bracketed by hipEvents recorded on the
+ * solve's stream.  afmm_plan_get_profile synchronises on those events, sums
+ * them per kernel family and resets the records; `out` receives up to `cap`
+ * families and *n_out their number.  flops/bytes are the algorithmic work of
+ * the timed launches (useful terms only, as in afmm_plan_info).
+ */
+typedef struct afmm_stage_time {
+  char name[24];      /* "gather", "upward", "m2l_f64", "m2l_f32", "leaf_f64", "leaf_f32" */
+  int32_t launches;
+  double ms;          /* summed event time */
+  double flops;       /* summed algorithmic flops */
+  double bytes;       /* summed algorithmic HBM bytes */
+} afmm_stage_time;
+afmm_status afmm_plan_set_profiling(afmm_plan* plan, int32_t enable);
+afmm_status afmm_plan_get_profile(afmm_plan* plan, afmm_stage_time* out, int32_t cap, int32_t* n_out);
+
 const char* afmm_status_string(afmm_status s);
 const char* afmm_last_error(void);
 

@@ -27,6 +27,7 @@ SYMBOLS = [
     "afmm_options_default", "afmm_plan_create", "afmm_plan_destroy", "afmm_plan_get_info", "afmm_solve",
     "afmm_solve_adjoint", "afmm_batch_create", "afmm_batch_solve", "afmm_batch_get_info",
     "afmm_batch_destroy", "afmm_hierarchy_check", "afmm_status_string", "afmm_last_error",
+    "afmm_plan_set_profiling", "afmm_plan_get_profile",
 ]
 
 
@@ -56,6 +57,11 @@ class PlanInfo(C.Structure):
             v = getattr(self, name)
             d[name] = list(v) if name == "leaves_per_level" else v
         return d
+
+
+class StageTime(C.Structure):
+    _fields_ = [("name", C.c_char * 24), ("launches", C.c_int32), ("ms", C.c_double), ("flops", C.c_double),
+                ("bytes", C.c_double)]
 
 
 class AfmmError(RuntimeError):
@@ -89,13 +95,16 @@ def lib():
     L.afmm_batch_get_info.argtypes = [vp, C.POINTER(PlanInfo)]
     L.afmm_batch_destroy.argtypes = [vp]
     L.afmm_hierarchy_check.argtypes = [C.POINTER(HierarchyC), C.POINTER(Options), C.POINTER(PlanInfo)]
+    L.afmm_plan_set_profiling.argtypes = [vp, C.c_int32]
+    L.afmm_plan_get_profile.argtypes = [vp, C.POINTER(StageTime), C.c_int32, C.POINTER(C.c_int32)]
     L.afmm_status_string.argtypes = [C.c_int32]
     L.afmm_status_string.restype = C.c_char_p
     L.afmm_last_error.argtypes = []
     L.afmm_last_error.restype = C.c_char_p
     for name in ("afmm_plan_create", "afmm_plan_destroy", "afmm_plan_get_info", "afmm_solve",
                  "afmm_solve_adjoint", "afmm_batch_create", "afmm_batch_solve", "afmm_batch_get_info",
-                 "afmm_batch_destroy", "afmm_hierarchy_check"):
+                 "afmm_batch_destroy", "afmm_hierarchy_check", "afmm_plan_set_profiling",
+                 "afmm_plan_get_profile"):
         getattr(L, name).restype = C.c_int32
     _lib = L
     return L

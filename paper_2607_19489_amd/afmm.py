@@ -12,7 +12,7 @@ import numpy as np
 import torch
 
 from ._lib import (AFMM_ALL_LEVELS, AFMM_CHECK_INPUT, AFMM_FP32_MIXED, AFMM_FP64, HierarchyC, Options,
-                   PlanInfo, check, lib)
+                   PlanInfo, StageTime, check, lib)
 
 PRECISIONS = {"fp64": AFMM_FP64, "fp32": AFMM_FP32_MIXED, "mixed": AFMM_FP32_MIXED}
 
@@ -101,6 +101,17 @@ class Plan:
         info = PlanInfo()
         check(lib().afmm_plan_get_info(self._ptr, C.byref(info)), "afmm_plan_get_info")
         return info.as_dict()
+
+    def set_profiling(self, enable: bool):
+        check(lib().afmm_plan_set_profiling(self._ptr, int(bool(enable))), "afmm_plan_set_profiling")
+
+    def get_profile(self) -> dict:
+        """Per kernel family: launches, summed event ms, algorithmic flops and bytes (resets)."""
+        buf = (StageTime * 16)()
+        n = C.c_int32()
+        check(lib().afmm_plan_get_profile(self._ptr, buf, 16, C.byref(n)), "afmm_plan_get_profile")
+        return {buf[i].name.decode(): {"launches": buf[i].launches, "ms": buf[i].ms, "flops": buf[i].flops,
+                                       "bytes": buf[i].bytes} for i in range(min(n.value, 16))}
 
     def _check_tensor(self, t: torch.Tensor, shape, name: str):
         if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():

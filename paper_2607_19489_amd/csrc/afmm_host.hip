@@ -231,10 +231,22 @@ static int64_t binom(int n, int k) {
   return r;
 }
 
-static void count_work(const Topology& T, int p, afmm_plan_info& info) {
+// Per-level algorithmic work of one synchronous solve (useful terms only).
+struct WorkCounts {
+  double m2l_flops[kMaxLevel] = {}, leaf_flops[kMaxLevel] = {}, up_flops[kMaxLevel] = {};
+  double m2l_bytes[kMaxLevel] = {}, leaf_bytes[kMaxLevel] = {}, up_bytes[kMaxLevel] = {};
+  int64_t m2l_targets = 0, m2l_pairs = 0, m2p = 0, p2p = 0, nm2p = 0, nst = 0, leaves = 0;
+  double flops_m2l = 0, flops_m2p = 0, flops_p2p = 0, flops_updown = 0;
+};
+
+static void count_work(const Topology& T, int p, bool mixed, int f64, WorkCounts& W) {
   const int K = nmi(p), K1 = nmi(p - 1);
-  int64_t m2l_t = 0, m2l_pairs = 0, m2l_mono = 0, m2p = 0, p2p = 0, nm2p = 0, nst = 0, upward = 0, leaves = 0;
-  for (int l = 0; l <= T.lmax; ++l) upward += T.lv[l].nref() * (l >= 2 ? 1 : 0);
+  const double tri = (double)binom(p + 6, 6);
+  const double fm2p = 2.0 * (K + 3.0 * K1), fp2p = 23.0, fl2p = 2.0 * (K + 3.0 * K1);
+  double m2m_terms = 0;
+  for (int a = 0; a <= p; ++a)
+    for (int b = 0; a + b <= p; ++b)
+      for (int c = 0; a + b + c <= p; ++c) m2m_terms += (a + 1) * (b + 1) * (c + 1);
   auto il_sources = [&](int l, int32_t F, std::vector<int32_t>& out) {
     out.clear();
     if (l < 2) return;
@@ -252,24 +264,46 @@ static void count_work(const Topology& T, int p, afmm_plan_info& info) {
       out.push_back(8 * L2.rank[Q] + op);
     }
   };
+  // upward: one M2M (or P2M) per child of every refined cell at levels >= 2
+  for (int f = 2; f < T.lmax; ++f) {
+    const double nr = T.lv[f].nref();
+    W.up_flops[f] = 2.0 * 8.0 * m2m_terms * nr;
+    W.up_bytes[f] = nr * K * 8.0 * (mixed && f >= f64 ? 1.5 : 1.0) + T.lv[f + 1].nref() * K * 8.0 +
+                    T.lv[f + 1].n() * (8.0 + 4.0);
+    W.flops_updown += W.up_flops[f];
+  }
   std::vector<int32_t> src;
   for (int f = 3; f <= T.lmax; ++f) {
     const HostLevel& L1 = T.lv[f - 1];
     const HostLevel& L0 = T.lv[f];
+    const double cs = (mixed && f > f64) ? 4.0 : 8.0;
+    int64_t pairs = 0, mono = 0, nt_all = 0;
     for (int32_t F : T.m2lgrp[f]) {
       int nt = 0;
       for (int o = 0; o < 8; ++o) nt += L0.rank[8 * F + o] >= 0;
       il_sources(f, F, src);
-      m2l_t += nt;
+      nt_all += nt;
       for (int32_t s : src) {
-        if (L1.rank[s] >= 0) m2l_pairs += nt;
-        else m2l_mono += nt;
+        if (L1.rank[s] >= 0) pairs += nt;
+        else mono += nt;
       }
     }
+    const double ng = (double)T.m2lgrp[f].size();
+    W.m2l_targets += nt_all;
+    W.m2l_pairs += pairs + mono;
+    W.m2l_flops[f] = 2.0 * tri * (double)pairs + 2.0 * K * (double)mono +
+                     (f - 1 >= 3 ? 2.0 * tri * (double)nt_all : 0.0);  // M2L + L2L of this launch
+    W.flops_m2l += 2.0 * tri * (double)pairs + 2.0 * K * (double)mono;
+    W.flops_updown += (f - 1 >= 3 ? 2.0 * tri * (double)nt_all : 0.0);
+    // unique data: source multipoles of level f-1, parent and output expansions, topology
+    W.m2l_bytes[f] = (double)L1.nref() * K * cs + ng * K * cs + (double)nt_all * K * cs + ng * 4.0 +
+                     (double)T.lv[f - 2].nref() * 27.0 * 4.0 + (double)L1.n() * (4.0 + 8.0);
   }
   for (int l = 1; l <= T.lmax; ++l) {
     const HostLevel& L1 = T.lv[l - 1];
     const HostLevel& L0 = T.lv[l];
+    const double cs = (mixed && (l - 1) > f64) ? 4.0 : 8.0;
+    int64_t m2p = 0, p2p = 0, nm2p = 0, nst = 0, leaves = 0;
     for (int32_t F : T.leafgrp[l]) {
       int nt = 0;
       bool tgt[8];
@@ -310,25 +344,22 @@ static void count_work(const Topology& T, int p, afmm_plan_info& info) {
         }
       }
     }
+    W.m2p += m2p;
+    W.p2p += p2p;
+    W.nm2p += nm2p;
+    W.nst += nst;
+    W.leaves += leaves;
+    const double far = (l - 1 >= 3) ? fl2p * (double)leaves : 0.0;
+    W.leaf_flops[l] = fm2p * (double)(m2p + nm2p) + fp2p * (double)p2p + far;
+    W.flops_m2p += fm2p * (double)(m2p + nm2p);
+    W.flops_p2p += fp2p * (double)p2p;
+    W.flops_updown += far;
+    const double ng = (double)T.leafgrp[l].size();
+    const double nnext = l + 1 <= T.lmax ? (double)T.lv[l + 1].n() : 0.0;
+    W.leaf_bytes[l] = (double)L1.nref() * K * cs + ng * K * cs + (double)L0.nref() * K * cs +
+                      8.0 * ((double)L1.n() + (double)L0.n() + nnext) + 32.0 * (double)leaves +
+                      4.0 * ((double)L1.n() + (double)L0.n()) + 108.0 * ((double)L1.nref() + ng);
   }
-  const double tri = (double)binom(p + 6, 6);
-  info.m2l_targets = m2l_t;
-  info.m2l_pairs = m2l_pairs + m2l_mono;
-  info.m2p_pairs = m2p;
-  info.p2p_pairs = p2p;
-  info.near_m2p_pairs = nm2p;
-  info.nearest_pairs = nst;
-  info.flops_m2l = 2.0 * tri * (double)m2l_pairs + 2.0 * K * (double)m2l_mono;
-  info.flops_m2p = 2.0 * (K + 3.0 * K1) * (double)(m2p + nm2p);
-  info.flops_p2p = 23.0 * (double)p2p;
-  // upward: 8 M2M per refined cell (useful triangle C(p+6,6)... of k <= a pairs), L2L per
-  // M2L target, L2P per leaf
-  double m2m_terms = 0;
-  for (int a = 0; a <= p; ++a)
-    for (int b = 0; a + b <= p; ++b)
-      for (int c = 0; a + b + c <= p; ++c) m2m_terms += (a + 1) * (b + 1) * (c + 1);
-  info.flops_updown = 2.0 * 8.0 * m2m_terms * (double)upward + 2.0 * tri * (double)m2l_t +
-                      2.0 * (K + 3.0 * K1) * (double)leaves;
 }
 
 // ---------------------------------------------------------------------------
@@ -507,6 +538,13 @@ struct afmm_plan {
   size_t bytes = 0;
   bool dead = false;              // sticky device error
   afmm_plan_info info{};
+  WorkCounts work;
+  // per-launch event timing (afmm_plan_set_profiling)
+  bool profiling = false;
+  struct Rec { int kind; int level; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> event_pool;
+  std::vector<afmm_stage_time> acc;
 };
 
 struct afmm_batch {
@@ -563,6 +601,13 @@ afmm_status upload_conv(afmm_plan* P, const std::vector<double>& v, const T** ou
 void free_plan(afmm_plan* P) {
   for (void* p : P->allocs) (void)hipFree(p);
   P->allocs.clear();
+  for (auto& r : P->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  P->recs.clear();
+  for (hipEvent_t e : P->event_pool) (void)hipEventDestroy(e);
+  P->event_pool.clear();
 }
 
 afmm_status check_options(const afmm_options* o) {
@@ -576,7 +621,7 @@ afmm_status check_options(const afmm_options* o) {
   return AFMM_OK;
 }
 
-void fill_info(afmm_plan_info& info, const Topology& T, const afmm_options& o) {
+void fill_info(afmm_plan_info& info, WorkCounts& W, const Topology& T, const afmm_options& o) {
   std::memset(&info, 0, sizeof info);
   info.levelmin = T.lmin_all;
   info.levelmax = T.lmax;
@@ -596,19 +641,22 @@ void fill_info(afmm_plan_info& info, const Topology& T, const afmm_options& o) {
         info.nrefined += L.rank[c] >= 0;
       }
   }
-  count_work(T, o.p, info);
-  // algorithmic HBM bytes: masses in, phi + acc out, multipoles and local
-  // expansions written once and read once, topology read once
-  double ref = 0, cells = 0;
-  for (int l = 0; l <= T.lmax; ++l) {
-    ref += T.lv[l].nref();
-    cells += T.lv[l].n();
-  }
-  const double K = nmi(o.p);
-  const double coef = o.precision == AFMM_FP64 ? 8.0 : 4.0;
-  info.bytes_min = 8.0 * info.nleaves + 32.0 * info.nleaves + ref * K * (8.0 + 8.0) +
-                   (o.precision == AFMM_FP64 ? 0.0 : ref * K * 8.0) + (double)info.m2l_targets * K * 2.0 * coef +
-                   cells * (4.0 + 4.0 + 8.0) + ref * 27.0 * 4.0;
+  const bool mixed = o.precision == AFMM_FP32_MIXED;
+  W = WorkCounts();
+  count_work(T, o.p, mixed, mixed ? o.fp64_levels : 1 << 20, W);
+  info.m2l_targets = W.m2l_targets;
+  info.m2l_pairs = W.m2l_pairs;
+  info.m2p_pairs = W.m2p;
+  info.p2p_pairs = W.p2p;
+  info.near_m2p_pairs = W.nm2p;
+  info.nearest_pairs = W.nst;
+  info.flops_m2l = W.flops_m2l;
+  info.flops_m2p = W.flops_m2p;
+  info.flops_p2p = W.flops_p2p;
+  info.flops_updown = W.flops_updown;
+  double b = 8.0 * info.nleaves;  // mass gather
+  for (int l = 0; l <= T.lmax; ++l) b += W.up_bytes[l] + W.m2l_bytes[l] + W.leaf_bytes[l];
+  info.bytes_min = b;
 }
 
 }  // namespace
@@ -655,7 +703,8 @@ afmm_status afmm_hierarchy_check(const afmm_hierarchy* h, const afmm_options* op
   s = append_hierarchy(T, *h, 0);
   if (s) return s;
   build_groups(T);
-  if (out) fill_info(*out, T, o);
+  WorkCounts W;
+  if (out) fill_info(*out, W, T, o);
   return AFMM_OK;
 }
 
@@ -668,7 +717,7 @@ static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
   const bool mixed = P->opt.precision == AFMM_FP32_MIXED;
   const int f64 = mixed ? P->opt.fp64_levels : 1 << 20;
   build_groups(T);
-  fill_info(P->info, T, P->opt);
+  fill_info(P->info, P->work, T, P->opt);
   build_tables(P->opt.p, P->tabs);
   afmm_status s;
   for (int l = 0; l <= T.lmax; ++l) {
@@ -787,6 +836,36 @@ static afmm_status dev_check(afmm_plan* P, hipError_t e, const char* what) {
   return fail(AFMM_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// ---- per-launch event timing ----
+enum { kGather = 0, kUpward, kM2L64, kM2L32, kLeaf64, kLeaf32, kNumKinds };
+static const char* kKindName[kNumKinds] = {"gather", "upward", "m2l_f64", "m2l_f32", "leaf_f64", "leaf_f32"};
+
+static hipEvent_t pool_get(afmm_plan* P) {
+  if (!P->event_pool.empty()) {
+    hipEvent_t e = P->event_pool.back();
+    P->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+static hipEvent_t prof_begin(afmm_plan* P, hipStream_t st) {
+  if (!P->profiling) return nullptr;
+  hipEvent_t a = pool_get(P);
+  if (a) (void)hipEventRecord(a, st);
+  return a;
+}
+
+static void prof_end(afmm_plan* P, hipEvent_t a, hipStream_t st, int kind, int level) {
+  if (!P->profiling || !a) return;
+  hipEvent_t b = pool_get(P);
+  if (!b) return;
+  (void)hipEventRecord(b, st);
+  P->recs.push_back({kind, level, a, b});
+}
+
 // Upward pass over every level, M2L over FMM levels 3..fmax, leaf evaluation
 // for the levels in [lo, hi].  Masses come from `msrc` (slot space).
 static afmm_status run_solve(afmm_plan* P, const double* msrc, int fmax, int lo, int hi, double* phi, double* acc,
@@ -796,18 +875,27 @@ static afmm_status run_solve(afmm_plan* P, const double* msrc, int fmax, int lo,
   const bool mixed = P->opt.precision == AFMM_FP32_MIXED;
   const int f64 = mixed ? P->opt.fp64_levels : 1 << 20;
   afmm_status s;
-  for (int l = T.lmin_all; l <= T.lmax; ++l)
+  for (int l = T.lmin_all; l <= T.lmax; ++l) {
+    hipEvent_t a = prof_begin(P, st);
     if ((s = dev_check(P, launch_gather_mass(P->lv[l], msrc, st), "gather"))) return s;
-  for (int f = T.lmax - 1; f >= 2; --f)
+    prof_end(P, a, st, kGather, l);
+  }
+  for (int f = T.lmax - 1; f >= 2; --f) {
+    hipEvent_t a = prof_begin(P, st);
     if ((s = dev_check(P, launch_upward(p, P->lv[f], P->lv[f + 1], P->cm, mixed && f >= f64, st), "upward")))
       return s;
+    prof_end(P, a, st, kUpward, f);
+  }
   for (int f = 3; f <= fmax; ++f) {
     const int ng = (int)T.m2lgrp[f].size();
+    if (ng == 0) continue;
+    hipEvent_t a = prof_begin(P, st);
     if ((s = dev_check(P,
                        launch_m2l(p, mixed && f > f64, mixed && (f - 1) > f64, f, P->d_m2lgrp[f], ng, P->lv[f - 2],
                                   P->lv[f - 1], P->lv[f], P->t32, P->t64, P->cm, st),
                        "m2l")))
       return s;
+    prof_end(P, a, st, (mixed && f > f64) ? kM2L32 : kM2L64, f);
   }
   for (int l = std::max(lo, 1); l <= hi; ++l) {
     const int ng = (int)T.leafgrp[l].size();
@@ -815,11 +903,14 @@ static afmm_status run_solve(afmm_plan* P, const double* msrc, int fmax, int lo,
     const LevelDev& lv2 = l >= 2 ? P->lv[l - 2] : empty;
     const LevelDev& lvp = l + 1 <= T.lmax ? P->lv[l + 1] : empty;
     const double h = P->opt.boxlen / (double)(1LL << l);
+    if (ng == 0) continue;
+    hipEvent_t a = prof_begin(P, st);
     if ((s = dev_check(P,
                        launch_leaf(p, mixed && (l - 1) > f64, l, P->d_leafgrp[l], ng, lv2, P->lv[l - 1], P->lv[l], lvp,
                                    P->t32, P->t64, P->cm, P->opt.G, h, phi, acc, st),
                        "leaf")))
       return s;
+    prof_end(P, a, st, (mixed && (l - 1) > f64) ? kLeaf32 : kLeaf64, l);
   }
   return AFMM_OK;
 }
@@ -868,6 +959,45 @@ extern "C" afmm_status afmm_solve(afmm_plan* P, int32_t level, int32_t icount, c
   }
   P->last_level = level;
   return run_solve(P, P->m_snap, level - 1, level, level, d_phi, d_acc, st);
+}
+
+extern "C" afmm_status afmm_plan_set_profiling(afmm_plan* P, int32_t enable) {
+  if (!P) return fail(AFMM_E_INVALID_ARG, "null plan");
+  P->profiling = enable != 0;
+  return AFMM_OK;
+}
+
+extern "C" afmm_status afmm_plan_get_profile(afmm_plan* P, afmm_stage_time* out, int32_t cap, int32_t* n_out) {
+  if (!P || !n_out || (cap > 0 && !out)) return fail(AFMM_E_INVALID_ARG, "null argument");
+  afmm_stage_time acc[kNumKinds];
+  std::memset(acc, 0, sizeof acc);
+  for (int k = 0; k < kNumKinds; ++k) std::snprintf(acc[k].name, sizeof acc[k].name, "%s", kKindName[k]);
+  for (auto& r : P->recs) {
+    if (hipEventSynchronize(r.b) != hipSuccess) return dev_check(P, hipGetLastError(), "profile sync");
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, r.a, r.b);
+    afmm_stage_time& t = acc[r.kind];
+    t.launches += 1;
+    t.ms += ms;
+    const WorkCounts& W = P->work;
+    switch (r.kind) {
+      case kUpward: t.flops += W.up_flops[r.level]; t.bytes += W.up_bytes[r.level]; break;
+      case kM2L64: case kM2L32: t.flops += W.m2l_flops[r.level]; t.bytes += W.m2l_bytes[r.level]; break;
+      case kLeaf64: case kLeaf32: t.flops += W.leaf_flops[r.level]; t.bytes += W.leaf_bytes[r.level]; break;
+      default: t.bytes += 12.0 * P->lv[r.level].n; break;
+    }
+    P->event_pool.push_back(r.a);
+    P->event_pool.push_back(r.b);
+  }
+  P->recs.clear();
+  int32_t n = 0;
+  for (int k = 0; k < kNumKinds; ++k)
+    if (acc[k].launches) {
+      if (n < cap) out[n] = acc[k];
+      ++n;
+    }
+  *n_out = n;
+  return AFMM_OK;
 }
 
 extern "C" afmm_status afmm_solve_adjoint(afmm_plan* P, int32_t level, const double* d_phi_bar,

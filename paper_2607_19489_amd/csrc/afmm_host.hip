@@ -235,6 +235,8 @@ static int64_t binom(int n, int k) {
 struct WorkCounts {
   double m2l_flops[kMaxLevel] = {}, leaf_flops[kMaxLevel] = {}, up_flops[kMaxLevel] = {};
   double m2l_bytes[kMaxLevel] = {}, leaf_bytes[kMaxLevel] = {}, up_bytes[kMaxLevel] = {};
+  double m2p_flops[kMaxLevel] = {}, m2p_bytes[kMaxLevel] = {};  // intermediate field (MFMA kernel)
+  double l2l_flops[kMaxLevel] = {}, l2l_bytes[kMaxLevel] = {};  // ShiftLocal chain step
   int64_t m2l_targets = 0, m2l_pairs = 0, m2p = 0, p2p = 0, nm2p = 0, nst = 0, leaves = 0;
   double flops_m2l = 0, flops_m2p = 0, flops_p2p = 0, flops_updown = 0;
 };
@@ -291,8 +293,9 @@ static void count_work(const Topology& T, int p, bool mixed, int f64, WorkCounts
     const double ng = (double)T.m2lgrp[f].size();
     W.m2l_targets += nt_all;
     W.m2l_pairs += pairs + mono;
-    W.m2l_flops[f] = 2.0 * tri * (double)pairs + 2.0 * K * (double)mono +
-                     (f - 1 >= 3 ? 2.0 * tri * (double)nt_all : 0.0);  // M2L + L2L of this launch
+    W.m2l_flops[f] = 2.0 * tri * (double)pairs + 2.0 * K * (double)mono;
+    W.l2l_flops[f] = f - 1 >= 3 ? 2.0 * tri * (double)nt_all : 0.0;
+    W.l2l_bytes[f] = f - 1 >= 3 ? ng * K * cs + 2.0 * (double)nt_all * K * cs : 0.0;
     W.flops_m2l += 2.0 * tri * (double)pairs + 2.0 * K * (double)mono;
     W.flops_updown += (f - 1 >= 3 ? 2.0 * tri * (double)nt_all : 0.0);
     // unique data: source multipoles of level f-1, parent and output expansions, topology
@@ -303,7 +306,7 @@ static void count_work(const Topology& T, int p, bool mixed, int f64, WorkCounts
     const HostLevel& L1 = T.lv[l - 1];
     const HostLevel& L0 = T.lv[l];
     const double cs = (mixed && (l - 1) > f64) ? 4.0 : 8.0;
-    int64_t m2p = 0, p2p = 0, nm2p = 0, nst = 0, leaves = 0;
+    int64_t m2p = 0, p2p = 0, p2p_il = 0, nm2p = 0, nst = 0, leaves = 0;
     for (int32_t F : T.leafgrp[l]) {
       int nt = 0;
       bool tgt[8];
@@ -312,7 +315,7 @@ static void count_work(const Topology& T, int p, bool mixed, int f64, WorkCounts
       il_sources(l, F, src);
       for (int32_t s : src) {
         if (L1.rank[s] >= 0) m2p += nt;
-        else p2p += nt;
+        else p2p_il += nt;
       }
       const int32_t* nb = &L1.nbr[(size_t)F * 27];
       for (int e = 0; e < 27; ++e) {
@@ -345,20 +348,24 @@ static void count_work(const Topology& T, int p, bool mixed, int f64, WorkCounts
       }
     }
     W.m2p += m2p;
-    W.p2p += p2p;
+    W.p2p += p2p + p2p_il;
     W.nm2p += nm2p;
     W.nst += nst;
     W.leaves += leaves;
     const double far = (l - 1 >= 3) ? fl2p * (double)leaves : 0.0;
-    W.leaf_flops[l] = fm2p * (double)(m2p + nm2p) + fp2p * (double)p2p + far;
+    W.m2p_flops[l] = fm2p * (double)m2p + fp2p * (double)p2p_il;
+    W.leaf_flops[l] = fm2p * (double)nm2p + fp2p * (double)p2p + far;
     W.flops_m2p += fm2p * (double)(m2p + nm2p);
-    W.flops_p2p += fp2p * (double)p2p;
+    W.flops_p2p += fp2p * (double)(p2p + p2p_il);
     W.flops_updown += far;
     const double ng = (double)T.leafgrp[l].size();
     const double nnext = l + 1 <= T.lmax ? (double)T.lv[l + 1].n() : 0.0;
-    W.leaf_bytes[l] = (double)L1.nref() * K * cs + ng * K * cs + (double)L0.nref() * K * cs +
+    // unique data touched: intermediate sources of level l-1 and the partials it writes
+    W.m2p_bytes[l] = (double)L1.nref() * K * cs + 8.0 * (double)L1.n() + 4.0 * (double)L1.n() + ng * 32.0 * cs +
+                     108.0 * (double)(l >= 2 ? T.lv[l - 2].nref() : 0);
+    W.leaf_bytes[l] = ng * K * cs + (double)L0.nref() * K * cs + ng * 32.0 * cs +
                       8.0 * ((double)L1.n() + (double)L0.n() + nnext) + 32.0 * (double)leaves +
-                      4.0 * ((double)L1.n() + (double)L0.n()) + 108.0 * ((double)L1.nref() + ng);
+                      4.0 * ((double)L1.n() + (double)L0.n()) + 108.0 * ng;
   }
 }
 
@@ -406,7 +413,11 @@ struct HostTables {
   std::vector<int> mi;          // [K][4]
   std::vector<int16_t> sumidx;  // [K][K]
   std::vector<int16_t> up;      // [K][3]
-  std::vector<double> Dil, Dsame, cfac2, cfac1, l2l, l2p, m2m;
+  std::vector<double> Dil, Dsame, cfac2, cfac1, l2lw, l2p, binom;
+  std::vector<int32_t> taps;        // [8][189]
+  std::vector<int16_t> m2p_off;     // [steps][64]
+  std::vector<int16_t> m2l_off;     // [steps][64]
+  std::vector<int32_t> m2l_tinfo;   // [NT][2]
 };
 
 static long double ipow(long double x, int n) {
@@ -472,22 +483,21 @@ static void build_tables(int p, HostTables& H) {
     H.cfac1[a] = (double)(sg / af);
     H.cfac2[a] = (double)(sg * ipow(2.0L, n) / af);
   }
-  // L2L: L~_b[y] = 2^(-1-|b|) sum_g u^g/g! L~_{b+g}[F], u = (o - 1/2)/2
-  H.l2l.assign((size_t)8 * K * K, 0.0);
+  // L2L weights: L~_b[y] = 2^(-1-|b|) sum_g u^g/g! L~_{b+g}[F], u = (o - 1/2)/2, stored per |b|
+  H.l2lw.assign((size_t)8 * (p + 1) * K, 0.0);
   H.l2p.assign((size_t)8 * 4 * K, 0.0);
-  H.m2m.assign((size_t)8 * K * K, 0.0);
   for (int o = 0; o < 8; ++o) {
     const long double u[3] = {((o & 1) - 0.5L) / 2, (((o >> 1) & 1) - 0.5L) / 2, (((o >> 2) & 1) - 0.5L) / 2};
+    for (int nb = 0; nb <= p; ++nb)
+      for (int g = 0; g < nmi(p - nb); ++g) {
+        const int* gg = &H.mi[4 * g];
+        H.l2lw[((size_t)o * (p + 1) + nb) * K + g] =
+            (double)(ipow(u[0], gg[0]) * ipow(u[1], gg[1]) * ipow(u[2], gg[2]) / (fact(gg[0]) * fact(gg[1]) * fact(gg[2])) /
+                     ipow(2.0L, 1 + nb));
+      }
+    // L2P: phi~ = 1/2 sum_b L~_b u^b/b!,  a~_i = -1/4 sum_{b_i>0} L~_b u^(b-e_i)/(b-e_i)!
     for (int b = 0; b < K; ++b) {
       const int* bb = &H.mi[4 * b];
-      for (int g = 0; g < K; ++g) {
-        const int* gg = &H.mi[4 * g];
-        if (bb[3] + gg[3] > p) continue;
-        const long double w = ipow(u[0], gg[0]) * ipow(u[1], gg[1]) * ipow(u[2], gg[2]) /
-                              (fact(gg[0]) * fact(gg[1]) * fact(gg[2])) / ipow(2.0L, 1 + bb[3]);
-        H.l2l[((size_t)o * K + b) * K + mi_index(bb[0] + gg[0], bb[1] + gg[1], bb[2] + gg[2])] = (double)w;
-      }
-      // L2P: phi~ = 1/2 sum_b L~_b u^b/b!,  a~_i = -1/4 sum_{b_i>0} L~_b u^(b-e_i)/(b-e_i)!
       const long double bf = fact(bb[0]) * fact(bb[1]) * fact(bb[2]);
       H.l2p[((size_t)o * 4 + 0) * K + b] = (double)(0.5L * ipow(u[0], bb[0]) * ipow(u[1], bb[1]) * ipow(u[2], bb[2]) / bf);
       for (int i = 0; i < 3; ++i) {
@@ -498,18 +508,62 @@ static void build_tables(int p, HostTables& H) {
             (double)(-0.25L * ipow(u[0], c[0]) * ipow(u[1], c[1]) * ipow(u[2], c[2]) / (fact(c[0]) * fact(c[1]) * fact(c[2])));
       }
     }
-    // M2M: S~_a[r] += C(a,k) d^(a-k) 2^-|k| S~_k[child],  d = (o - 1/2)/2
-    for (int a = 0; a < K; ++a) {
-      const int* aa = &H.mi[4 * a];
-      for (int k = 0; k <= a; ++k) {
-        const int* kk = &H.mi[4 * k];
-        if (kk[0] > aa[0] || kk[1] > aa[1] || kk[2] > aa[2]) continue;
-        const long double w = (long double)binom(aa[0], kk[0]) * binom(aa[1], kk[1]) * binom(aa[2], kk[2]) *
-                              ipow(u[0], aa[0] - kk[0]) * ipow(u[1], aa[1] - kk[1]) * ipow(u[2], aa[2] - kk[2]) /
-                              ipow(2.0L, kk[3]);
-        H.m2m[((size_t)o * K + a) * K + k] = (double)w;
+  }
+  H.binom.assign((kPMax + 1) * (kPMax + 1), 0.0);
+  for (int n = 0; n <= kPMax; ++n)
+    for (int k = 0; k <= n; ++k) H.binom[n * (kPMax + 1) + k] = (double)binom(n, k);
+  // taps of each parity class: neighbour e of G, child o' -> d = 2e + o' - o_F with |d|_inf >= 2
+  H.taps.clear();
+  for (int oF = 0; oF < 8; ++oF) {
+    int cnt = 0;
+    for (int e = 0; e < 27; ++e)
+      for (int op = 0; op < 8; ++op) {
+        int d[3], dm = 0;
+        for (int a = 0; a < 3; ++a) {
+          d[a] = 2 * ax_of(e, a) + ((op >> a) & 1) - ((oF >> a) & 1);
+          dm = std::max(dm, std::abs(d[a]));
+        }
+        if (dm <= 1) continue;
+        const int di = (d[0] + 3) + 7 * (d[1] + 3) + 49 * (d[2] + 3);
+        H.taps.push_back(e | (op << 5) | (di << 8));
+        ++cnt;
       }
-    }
+    (void)cnt;
+  }
+  // MFMA A-operand offsets into the staged D~ rows (sD[o][g], row stride KS, zero slot 8 KS)
+  const int KP = (K + 3) & ~3, KS = KP + 1, ZERO = 8 * KS, K1 = nmi(p - 1);
+  auto deg = [&](int idx) { return H.mi[4 * idx + 3]; };
+  H.m2p_off.clear();
+  for (int rt = 0; rt < 2; ++rt) {
+    const int steps = rt == 0 ? KP / 4 : (K1 + 3) / 4;
+    for (int kb = 0; kb < steps; ++kb)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int i = lane & 15, k = 4 * kb + (lane >> 4);
+        const int c = 2 * rt + (i >> 3), o = i & 7;  // c: 0 phi, 1..3 a_x..a_z
+        int v = ZERO;
+        if (c == 0 && k < K) v = o * KS + k;
+        if (c > 0 && k < K1) v = o * KS + H.up[3 * k + (c - 1)];
+        H.m2p_off.push_back((int16_t)v);
+      }
+  }
+  const int NT = (8 * K + 15) / 16;
+  H.m2l_tinfo.assign(2 * NT, 0);
+  H.m2l_off.clear();
+  int step = 0;
+  for (int T = 0; T < NT; ++T) {
+    const int ks = (nmi(p - deg(2 * T)) + 3) / 4;
+    H.m2l_tinfo[2 * T] = ks;
+    H.m2l_tinfo[2 * T + 1] = step;
+    step += ks;
+    for (int kb = 0; kb < ks; ++kb)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int R = 16 * T + (lane & 15), k = 4 * kb + (lane >> 4);
+        const int b = R >> 3, o = R & 7;
+        int v = ZERO;
+        if (b < K && k < K && deg(k) + deg(b) <= p)
+          v = o * KS + mi_index(H.mi[4 * k] + H.mi[4 * b], H.mi[4 * k + 1] + H.mi[4 * b + 1], H.mi[4 * k + 2] + H.mi[4 * b + 2]);
+        H.m2l_off.push_back((int16_t)v);
+      }
   }
 }
 
@@ -528,6 +582,13 @@ struct afmm_plan {
   LevelDev lv[kMaxLevel + 1];
   int32_t* d_leafgrp[kMaxLevel] = {};
   int32_t* d_m2lgrp[kMaxLevel] = {};
+  // MFMA tile records of every level, one array per precision (0 FP64, 1 FP32);
+  // range[l] = {precision, first tile, count}
+  MfmaTiles m2p_all[2], m2l_all[2];
+  int m2p_range[kMaxLevel][3] = {};
+  int m2l_range[kMaxLevel][3] = {};
+  LevelDev* d_lvs = nullptr;        // device copy of lv[]
+  MfmaTables mt;
   TablesDev<float> t32;
   TablesDev<double> t64;
   CommonDev cm;
@@ -541,7 +602,8 @@ struct afmm_plan {
   WorkCounts work;
   // per-launch event timing (afmm_plan_set_profiling)
   bool profiling = false;
-  struct Rec { int kind; int level; hipEvent_t a, b; };
+  double pending_flops = 0.0, pending_bytes = 0.0;  // work of a multi-level launch being timed
+  struct Rec { int kind; int level; hipEvent_t a, b; double flops, bytes; };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> event_pool;
   std::vector<afmm_stage_time> acc;
@@ -655,7 +717,7 @@ void fill_info(afmm_plan_info& info, WorkCounts& W, const Topology& T, const afm
   info.flops_p2p = W.flops_p2p;
   info.flops_updown = W.flops_updown;
   double b = 8.0 * info.nleaves;  // mass gather
-  for (int l = 0; l <= T.lmax; ++l) b += W.up_bytes[l] + W.m2l_bytes[l] + W.leaf_bytes[l];
+  for (int l = 0; l <= T.lmax; ++l) b += W.up_bytes[l] + W.m2l_bytes[l] + W.l2l_bytes[l] + W.m2p_bytes[l] + W.leaf_bytes[l];
   info.bytes_min = b;
 }
 
@@ -710,6 +772,30 @@ afmm_status afmm_hierarchy_check(const afmm_hierarchy* h, const afmm_options* op
 
 }  // extern "C"
 
+// Tile records (target level, then `nc` groups = refined ranks at level
+// target-1, -1 padded) of one parity class each, appended to `out`; the tiles
+// of the 8 classes are interleaved so that a contiguous range of tiles covers
+// one region for every class.  Returns the number of tiles appended.
+static int append_tiles(const Topology& T, int target, const std::vector<int32_t>& grp, int nc,
+                        std::vector<int32_t>& out) {
+  std::vector<int32_t> cls[8];
+  for (int32_t F : grp) cls[T.lv[target - 1].refcell[F] & 7].push_back(F);
+  size_t maxchunks = 0;
+  for (auto& c : cls) maxchunks = std::max(maxchunks, (c.size() + nc - 1) / nc);
+  int n = 0;
+  for (size_t ch = 0; ch < maxchunks; ++ch)
+    for (auto& c : cls) {
+      if (ch * nc >= c.size()) continue;
+      out.push_back(target);
+      for (int j = 0; j < nc; ++j) {
+        const size_t i = ch * nc + j;
+        out.push_back(i < c.size() ? c[i] : -1);
+      }
+      ++n;
+    }
+  return n;
+}
+
 // Allocate and upload everything of a plan whose topology is built.
 static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
   Topology& T = P->topo;
@@ -758,25 +844,70 @@ static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
   {
     std::vector<int8_t> mi8(H.mi.begin(), H.mi.end());
     int8_t* d_mi;
-    int16_t *d_sum, *d_up;
-    double* d_m2m;
+    int16_t *d_sum, *d_up, *d_m2p_off, *d_m2l_off;
+    double* d_binom;
+    int32_t *d_taps, *d_tinfo;
     if ((s = upload(P, mi8, &d_mi, st)) || (s = upload(P, H.sumidx, &d_sum, st)) || (s = upload(P, H.up, &d_up, st)) ||
-        (s = upload(P, H.m2m, &d_m2m, st)))
+        (s = upload(P, H.binom, &d_binom, st)) || (s = upload(P, H.taps, &d_taps, st)) ||
+        (s = upload(P, H.m2p_off, &d_m2p_off, st)) || (s = upload(P, H.m2l_off, &d_m2l_off, st)) ||
+        (s = upload(P, H.m2l_tinfo, &d_tinfo, st)))
       return s;
     P->cm.mi = d_mi;
     P->cm.sumidx = d_sum;
     P->cm.up = d_up;
-    P->cm.m2m = d_m2m;
+    P->cm.binom = d_binom;
+    P->mt.taps = d_taps;
+    P->mt.m2p_off = d_m2p_off;
+    P->mt.m2l_off = d_m2l_off;
+    P->mt.m2l_tinfo = d_tinfo;
   }
   if ((s = upload_conv<double>(P, H.Dil, &P->t64.Dil, st)) || (s = upload_conv<double>(P, H.Dsame, &P->t64.Dsame, st)) ||
       (s = upload_conv<double>(P, H.cfac2, &P->t64.cfac2, st)) || (s = upload_conv<double>(P, H.cfac1, &P->t64.cfac1, st)) ||
-      (s = upload_conv<double>(P, H.l2l, &P->t64.l2l, st)) || (s = upload_conv<double>(P, H.l2p, &P->t64.l2p, st)))
+      (s = upload_conv<double>(P, H.l2lw, &P->t64.l2lw, st)) || (s = upload_conv<double>(P, H.l2p, &P->t64.l2p, st)))
     return s;
   if (mixed) {
     if ((s = upload_conv<float>(P, H.Dil, &P->t32.Dil, st)) || (s = upload_conv<float>(P, H.Dsame, &P->t32.Dsame, st)) ||
         (s = upload_conv<float>(P, H.cfac2, &P->t32.cfac2, st)) || (s = upload_conv<float>(P, H.cfac1, &P->t32.cfac1, st)) ||
-        (s = upload_conv<float>(P, H.l2l, &P->t32.l2l, st)) || (s = upload_conv<float>(P, H.l2p, &P->t32.l2p, st)))
+        (s = upload_conv<float>(P, H.l2lw, &P->t32.l2lw, st)) || (s = upload_conv<float>(P, H.l2p, &P->t32.l2p, st)))
       return s;
+  }
+  // parity-class tiles of the MFMA kernels (all levels of one precision in one
+  // array) and the intermediate-field partials
+  {
+    std::vector<int32_t> m2p_rec[2], m2l_rec[2];
+    int m2p_nc[2] = {m2p_columns(P->opt.p, false), m2p_columns(P->opt.p, true)};
+    for (int l = 3; l <= T.lmax; ++l) {
+      const int pr = (mixed && (l - 1) > f64) ? 1 : 0;
+      const int n0 = (int)(m2p_rec[pr].size() / (m2p_nc[pr] + 1));
+      const int n = append_tiles(T, l, T.leafgrp[l], m2p_nc[pr], m2p_rec[pr]);
+      P->m2p_range[l][0] = pr;
+      P->m2p_range[l][1] = n0;
+      P->m2p_range[l][2] = n;
+      if (!T.leafgrp[l].empty()) {
+        void* q = nullptr;
+        if ((s = dev_alloc(P, &q, (size_t)T.lv[l - 1].nref() * 32 * (pr ? sizeof(float) : sizeof(double))))) return s;
+        P->lv[l - 1].part = q;
+      }
+      const int pm = (mixed && l > f64) ? 1 : 0;
+      if (l <= T.lmax - 1) {
+        const int m0 = (int)(m2l_rec[pm].size() / 17);
+        const int m = append_tiles(T, l, T.m2lgrp[l], 16, m2l_rec[pm]);
+        P->m2l_range[l][0] = pm;
+        P->m2l_range[l][1] = m0;
+        P->m2l_range[l][2] = m;
+      }
+    }
+    for (int pr = 0; pr < 2; ++pr) {
+      int32_t* d = nullptr;
+      if ((s = upload(P, m2p_rec[pr], &d, st))) return s;
+      P->m2p_all[pr] = {d, (int)(m2p_rec[pr].size() / (m2p_nc[pr] + 1)), m2p_nc[pr]};
+      if ((s = upload(P, m2l_rec[pr], &d, st))) return s;
+      P->m2l_all[pr] = {d, (int)(m2l_rec[pr].size() / 17), 16};
+    }
+  }
+  {
+    std::vector<LevelDev> lvh(P->lv, P->lv + kMaxLevel + 1);
+    if ((s = upload(P, lvh, &P->d_lvs, st))) return s;
   }
   void* p = nullptr;
   if ((s = dev_alloc(P, &p, (size_t)std::max<int64_t>(T.nslots, 1) * sizeof(double)))) return s;
@@ -837,8 +968,9 @@ static afmm_status dev_check(afmm_plan* P, hipError_t e, const char* what) {
 }
 
 // ---- per-launch event timing ----
-enum { kGather = 0, kUpward, kM2L64, kM2L32, kLeaf64, kLeaf32, kNumKinds };
-static const char* kKindName[kNumKinds] = {"gather", "upward", "m2l_f64", "m2l_f32", "leaf_f64", "leaf_f32"};
+enum { kGather = 0, kUpward, kM2L64, kM2L32, kL2L, kM2P64, kM2P32, kLeaf64, kLeaf32, kNumKinds };
+static const char* kKindName[kNumKinds] = {"gather", "upward", "m2l_f64", "m2l_f32", "l2l",
+                                           "m2p_f64", "m2p_f32", "near_f64", "near_f32"};
 
 static hipEvent_t pool_get(afmm_plan* P) {
   if (!P->event_pool.empty()) {
@@ -863,7 +995,8 @@ static void prof_end(afmm_plan* P, hipEvent_t a, hipStream_t st, int kind, int l
   hipEvent_t b = pool_get(P);
   if (!b) return;
   (void)hipEventRecord(b, st);
-  P->recs.push_back({kind, level, a, b});
+  P->recs.push_back({kind, level, a, b, P->pending_flops, P->pending_bytes});
+  P->pending_flops = P->pending_bytes = 0.0;
 }
 
 // Upward pass over every level, M2L over FMM levels 3..fmax, leaf evaluation
@@ -886,31 +1019,72 @@ static afmm_status run_solve(afmm_plan* P, const double* msrc, int fmax, int lo,
       return s;
     prof_end(P, a, st, kUpward, f);
   }
-  for (int f = 3; f <= fmax; ++f) {
+  // M2L tap sums of FMM levels 3..fmax: one launch per precision
+  for (int pr = 0; pr < 2; ++pr) {
+    int t0 = -1, n = 0;
+    for (int f = 3; f <= fmax; ++f)
+      if (P->m2l_range[f][0] == pr && P->m2l_range[f][2] > 0) {
+        if (t0 < 0) t0 = P->m2l_range[f][1];
+        n = P->m2l_range[f][1] + P->m2l_range[f][2] - t0;
+      }
+    if (n <= 0) continue;
+    hipEvent_t a = prof_begin(P, st);
+    if ((s = dev_check(P, launch_m2l_taps(p, pr == 1, P->m2l_all[pr], t0, n, P->mt, P->d_lvs, P->t32, P->t64, st),
+                       "m2l")))
+      return s;
+    for (int f = 3; f <= fmax; ++f)
+      if (P->m2l_range[f][0] == pr) {
+        P->pending_flops += P->work.m2l_flops[f];
+        P->pending_bytes += P->work.m2l_bytes[f];
+      }
+    prof_end(P, a, st, pr ? kM2L32 : kM2L64, -1);
+  }
+  // ShiftLocal chain (L2L) from FMM level 3 down
+  for (int f = 4; f <= fmax; ++f) {
     const int ng = (int)T.m2lgrp[f].size();
     if (ng == 0) continue;
     hipEvent_t a = prof_begin(P, st);
     if ((s = dev_check(P,
-                       launch_m2l(p, mixed && f > f64, mixed && (f - 1) > f64, f, P->d_m2lgrp[f], ng, P->lv[f - 2],
-                                  P->lv[f - 1], P->lv[f], P->t32, P->t64, P->cm, st),
-                       "m2l")))
+                       launch_l2l(p, mixed && f > f64, mixed && (f - 1) > f64, P->d_m2lgrp[f], ng, P->lv[f - 1],
+                                  P->lv[f], P->t32, P->t64, P->cm, st),
+                       "l2l")))
       return s;
-    prof_end(P, a, st, (mixed && f > f64) ? kM2L32 : kM2L64, f);
+    prof_end(P, a, st, kL2L, f);
   }
+  // intermediate field (M2P) of the leaf levels lo..hi: one launch per precision
+  for (int pr = 0; pr < 2; ++pr) {
+    int t0 = -1, n = 0;
+    for (int l = std::max(lo, 3); l <= hi; ++l)
+      if (P->m2p_range[l][0] == pr && P->m2p_range[l][2] > 0) {
+        if (t0 < 0) t0 = P->m2p_range[l][1];
+        n = P->m2p_range[l][1] + P->m2p_range[l][2] - t0;
+      }
+    if (n <= 0) continue;
+    hipEvent_t a = prof_begin(P, st);
+    if ((s = dev_check(P, launch_m2p(p, pr == 1, P->m2p_all[pr], t0, n, P->mt, P->d_lvs, P->t32, P->t64, st), "m2p")))
+      return s;
+    for (int l = std::max(lo, 3); l <= hi; ++l)
+      if (P->m2p_range[l][0] == pr) {
+        P->pending_flops += P->work.m2p_flops[l];
+        P->pending_bytes += P->work.m2p_bytes[l];
+      }
+    prof_end(P, a, st, pr ? kM2P32 : kM2P64, -1);
+  }
+  // far, near and nearest fields + output, per leaf level
   for (int l = std::max(lo, 1); l <= hi; ++l) {
     const int ng = (int)T.leafgrp[l].size();
+    if (ng == 0) continue;
     const LevelDev empty;
-    const LevelDev& lv2 = l >= 2 ? P->lv[l - 2] : empty;
     const LevelDev& lvp = l + 1 <= T.lmax ? P->lv[l + 1] : empty;
     const double h = P->opt.boxlen / (double)(1LL << l);
-    if (ng == 0) continue;
+    const bool fp32 = mixed && (l - 1) > f64;
     hipEvent_t a = prof_begin(P, st);
     if ((s = dev_check(P,
-                       launch_leaf(p, mixed && (l - 1) > f64, l, P->d_leafgrp[l], ng, lv2, P->lv[l - 1], P->lv[l], lvp,
-                                   P->t32, P->t64, P->cm, P->opt.G, h, phi, acc, st),
-                       "leaf")))
+                       launch_near(p, fp32, l, P->d_leafgrp[l], ng, P->lv[l - 1], P->lv[l], lvp, P->t32, P->t64, P->cm,
+                                   l >= 3 ? P->lv[l - 1].part : nullptr, P->opt.G, h, phi, acc, st),
+                       "near")))
       return s;
-    prof_end(P, a, st, (mixed && (l - 1) > f64) ? kLeaf32 : kLeaf64, l);
+    prof_end(P, a, st, fp32 ? kLeaf32 : kLeaf64, l);
   }
   return AFMM_OK;
 }
@@ -982,7 +1156,9 @@ extern "C" afmm_status afmm_plan_get_profile(afmm_plan* P, afmm_stage_time* out,
     const WorkCounts& W = P->work;
     switch (r.kind) {
       case kUpward: t.flops += W.up_flops[r.level]; t.bytes += W.up_bytes[r.level]; break;
-      case kM2L64: case kM2L32: t.flops += W.m2l_flops[r.level]; t.bytes += W.m2l_bytes[r.level]; break;
+      case kM2L64: case kM2L32: t.flops += r.flops; t.bytes += r.bytes; break;
+      case kL2L: t.flops += W.l2l_flops[r.level]; t.bytes += W.l2l_bytes[r.level]; break;
+      case kM2P64: case kM2P32: t.flops += r.flops; t.bytes += r.bytes; break;
       case kLeaf64: case kLeaf32: t.flops += W.leaf_flops[r.level]; t.bytes += W.leaf_bytes[r.level]; break;
       default: t.bytes += 12.0 * P->lv[r.level].n; break;
     }

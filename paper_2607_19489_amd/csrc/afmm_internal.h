@@ -50,6 +50,7 @@ struct LevelDev {
   float* S32 = nullptr;              // [nref][K] FP32 copy (mixed form)
   double* L64 = nullptr;             // [nref][K] local expansions (FP64 levels)
   float* L32 = nullptr;              // [nref][K] local expansions (FP32 levels)
+  void* part = nullptr;              // [nref][32] intermediate-field partials of the leaf children (T of the leaf level)
   double* Lbar64 = nullptr;          // adjoint accumulators (same layout as L)
   float* Lbar32 = nullptr;
   double* Sbar64 = nullptr;
@@ -62,7 +63,7 @@ struct TablesDev {
   const T* Dsame = nullptr;   // [kNumD][K]      D~ at integer R~ in [-3,3]^3
   const T* cfac2 = nullptr;   // [K] (-1)^|a|/a! 2^|a|
   const T* cfac1 = nullptr;   // [K] (-1)^|a|/a!
-  const T* l2l = nullptr;     // [8][K][K] dense L2L per child octant
+  const T* l2lw = nullptr;    // [8][p+1][K] L2L weights 2^(-1-|b|) u^g/g! per child octant and |b|
   const T* l2p = nullptr;     // [8][4][K] L2P weights (phi, ax, ay, az) per child octant
 };
 
@@ -70,7 +71,22 @@ struct CommonDev {
   const int16_t* sumidx = nullptr;  // [K][K] index of a + b (or -1 when |a|+|b| > p)
   const int16_t* up = nullptr;      // [K][3] index of a + e_i (or -1 when |a| = p)
   const int8_t* mi = nullptr;       // [K][4] (a, b, c, |a|)
-  const double* m2m = nullptr;      // [8][K][K] dense M2M per child octant (FP64)
+  const double* binom = nullptr;    // [(kPMax+1)^2] binomial coefficients C(n, k) at n*(kPMax+1)+k
+};
+
+// Group tiles of the MFMA kernels: NC refined ranks per tile (one parity class,
+// -1 padded), tiles of the 8 classes interleaved.
+struct MfmaTiles {
+  const int32_t* tiles = nullptr;
+  int ntiles = 0;
+  int nc = 0;
+};
+
+struct MfmaTables {
+  const int32_t* taps = nullptr;      // [8][189] per parity class: e | o' << 5 | d_index << 8
+  const int16_t* m2p_off = nullptr;   // [steps][64] sD offsets of the M2P A operand
+  const int16_t* m2l_off = nullptr;   // [steps][64] sD offsets of the M2L A operand
+  const int32_t* m2l_tinfo = nullptr; // [NT][2] k-steps and first step of each M2L row tile
 };
 
 // Launchers (afmm_kernels.hip).  All return hipGetLastError() of the launch.
@@ -79,13 +95,21 @@ hipError_t launch_copy_slots(const int32_t* slots, int64_t n, const double* src,
                              hipStream_t st);
 hipError_t launch_upward(int p, const LevelDev& lv, const LevelDev& lvc, const CommonDev& cm,
                          bool write32, hipStream_t st);
-hipError_t launch_m2l(int p, bool fp32, bool parent_fp32, int f, const int32_t* grp, int ngrp,
-                      const LevelDev& lv2, const LevelDev& lv1, const LevelDev& lv0,
-                      const TablesDev<float>& t32, const TablesDev<double>& t64, const CommonDev& cm,
+int m2p_columns(int p, bool fp32);
+// MFMA launches over a contiguous range [t0, t0 + n) of tile records; each
+// record is (target level, NC groups).  lvs is the device array of LevelDev.
+hipError_t launch_m2l_taps(int p, bool fp32, const MfmaTiles& mt, int t0, int n, const MfmaTables& tabs,
+                           const LevelDev* lvs, const TablesDev<float>& t32, const TablesDev<double>& t64,
+                           hipStream_t st);
+hipError_t launch_l2l(int p, bool fp32, bool parent_fp32, const int32_t* grp, int ngrp, const LevelDev& lv1,
+                      const LevelDev& lv0, const TablesDev<float>& t32, const TablesDev<double>& t64,
+                      const CommonDev& cm, hipStream_t st);
+hipError_t launch_m2p(int p, bool fp32, const MfmaTiles& mt, int t0, int n, const MfmaTables& tabs,
+                      const LevelDev* lvs, const TablesDev<float>& t32, const TablesDev<double>& t64,
                       hipStream_t st);
-hipError_t launch_leaf(int p, bool fp32, int l, const int32_t* grp, int ngrp, const LevelDev& lv2,
-                       const LevelDev& lv1, const LevelDev& lv0, const LevelDev& lvp,
-                       const TablesDev<float>& t32, const TablesDev<double>& t64, const CommonDev& cm,
-                       double G, double h, double* phi, double* acc, hipStream_t st);
+hipError_t launch_near(int p, bool fp32, int l, const int32_t* grp, int ngrp, const LevelDev& lv1,
+                       const LevelDev& lv0, const LevelDev& lvp, const TablesDev<float>& t32,
+                       const TablesDev<double>& t64, const CommonDev& cm, const void* part, double G, double h,
+                       double* phi, double* acc, hipStream_t st);
 
 }  // namespace afmm

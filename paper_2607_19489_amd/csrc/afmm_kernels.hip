@@ -1,11 +1,14 @@
-// HIP kernels of the adaptive FMM for gfx950 (first, VALU form).
+// HIP kernels of the adaptive FMM for gfx950.
 //
-// Work decomposition.  Targets are grouped by their father F (one "group" =
-// the 8 children of one refined cell).  The 8 siblings share one interaction
-// list (Sec. 2): the level-(f-1) cells of the 6^3 block around F's oct minus
-// the 27 cells touching F, i.e. the children of the 27 neighbours of F's father
-// G minus F's own neighbours.  Lists are therefore never stored: each block
-// rebuilds its 216 candidates from G's neighbour row and F's octant.
+// Group = the 8 children of one refined cell F.  The 8 siblings share F's
+// interaction list (Sec. 2): the level-(f-1) cells of the 6^3 block around
+// F's oct minus the 27 cells touching F, i.e. the children of the 27
+// neighbours of F's father G minus F's own neighbours.  Relative to F the
+// source offsets d = s - F form a fixed set of 189 "taps" that depends only on
+// F's octant (parity class), and the translation operator of a tap depends
+// only on d and the child octant.  Groups of one parity class therefore share
+// every operator: M2L and the intermediate-field M2P become, tap by tap, dense
+// products  OUT[rows x groups] += A_d[rows x K] * S[K x groups]  on MFMA.
 //
 // Deterministic: no atomics; every sum runs in a fixed order.
 #include <hip/hip_runtime.h>
@@ -17,10 +20,10 @@ namespace afmm {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kTaps = 189;
 
 inline int ceil_div_host(int a, int b) { return (a + b - 1) / b; }
 
-// Offsets of neighbour e and child octant o along each axis.
 __device__ inline int e_axis(int e, int d) { return (d == 0 ? e % 3 : (d == 1 ? (e / 3) % 3 : e / 9)) - 1; }
 __device__ inline int o_axis(int o, int d) { return (o >> d) & 1; }
 __device__ inline int d_index(int dx, int dy, int dz) { return (dx + 3) + 7 * (dy + 3) + 49 * (dz + 3); }
@@ -32,79 +35,52 @@ __device__ inline float rsqrt_t<float>(float x) { return rsqrtf(x); }
 template <>
 __device__ inline double rsqrt_t<double>(double x) { return 1.0 / sqrt(x); }
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+template <typename T> struct Acc4;
+template <> struct Acc4<float> { typedef f32x4 type; };
+template <> struct Acc4<double> { typedef f64x4 type; };
+
+// D[16x16] += A[16x4] B[4x16]; lane l holds A[l%16][l/16] and B[l/16][l%16].
+// Accumulator element r of lane l is D[acc_row(l/16, r)][l%16]: rows 4(l/16)+r
+// for FP32 and (l/16)+4r for FP64 (checked on gfx950 by a lane-layout probe).
+__device__ inline f32x4 mfma16(float a, float b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+__device__ inline f64x4 mfma16(double a, double b, f64x4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+template <typename T>
+__device__ inline int acc_row(int krow, int r) { return sizeof(T) == 4 ? 4 * krow + r : krow + 4 * r; }
+
 // P2P in target-level units: phi~ -= m/|R|, a~ -= m R/|R|^3.
 template <typename T>
 __device__ inline void p2p(T rx, T ry, T rz, T m, T* out) {
-  T r2 = rx * rx + ry * ry + rz * rz;
-  T inv = rsqrt_t<T>(r2);
-  T w = m * inv;
-  T w3 = w * inv * inv;
+  const T r2 = rx * rx + ry * ry + rz * rz;
+  const T inv = rsqrt_t<T>(r2);
+  const T w = m * inv;
+  const T w3 = w * inv * inv;
   out[0] -= w;
   out[1] -= w3 * rx;
   out[2] -= w3 * ry;
   out[3] -= w3 * rz;
 }
 
-// M2P of one source multipole with a precomputed D~ row (Taylor series of Sec. 2).
+// M2P of one multipole with a D~ row, for the near field (VALU).
 template <typename T, int P>
-__device__ inline void m2p(const T* __restrict__ D, const T* __restrict__ S, const T* __restrict__ cf,
-                           const int16_t* __restrict__ up, T* out) {
+__device__ inline void m2p_row(const T* __restrict__ D, const T* __restrict__ S, const T* __restrict__ cf,
+                               const int16_t* __restrict__ up, T* out) {
   constexpr int K = nmi(P);
   constexpr int K1 = nmi(P - 1);
   T phi = 0, ax = 0, ay = 0, az = 0;
-#pragma unroll 4
   for (int a = 0; a < K1; ++a) {
-    T w = cf[a] * S[a];
+    const T w = cf[a] * S[a];
     phi += w * D[a];
     ax += w * D[up[3 * a + 0]];
     ay += w * D[up[3 * a + 1]];
     az += w * D[up[3 * a + 2]];
   }
-#pragma unroll 4
   for (int a = K1; a < K; ++a) phi += cf[a] * S[a] * D[a];
   out[0] += phi;
   out[1] -= ax;
   out[2] -= ay;
   out[3] -= az;
-}
-
-// Block-wide compaction of the interaction-list candidates into s_cell/s_d.
-// Candidate t (< 216) = child o' = t & 7 of neighbour e = t >> 3 of G; kept if
-// inside the box and not touching F.  Returns the count (all threads).
-__device__ inline int build_il(const LevelDev& lv2, int G, int oF, int* s_cell, int* s_d, int* s_cnt) {
-  const int t = threadIdx.x;
-  int cell = -1, di = 0;
-  if (t < 216) {
-    const int e = t >> 3, op = t & 7;
-    const int Q = lv2.nbr[(size_t)G * 27 + e];
-    if (Q >= 0) {
-      const int rQ = lv2.rank[Q];
-      const int dx = 2 * e_axis(e, 0) + o_axis(op, 0) - o_axis(oF, 0);
-      const int dy = 2 * e_axis(e, 1) + o_axis(op, 1) - o_axis(oF, 1);
-      const int dz = 2 * e_axis(e, 2) + o_axis(op, 2) - o_axis(oF, 2);
-      const int dm = max(abs(dx), max(abs(dy), abs(dz)));
-      if (dm > 1 && rQ >= 0) {
-        cell = 8 * rQ + op;
-        di = d_index(dx, dy, dz);
-      }
-    }
-  }
-  // wave-level ballot compaction (wave64), then a block prefix over the waves
-  const unsigned long long mask = __ballot(cell >= 0);
-  const int lane = t & 63, wave = t >> 6;
-  const int before = __popcll(mask & ((1ull << lane) - 1ull));
-  if (lane == 0) s_cnt[wave] = __popcll(mask);
-  __syncthreads();
-  int base = 0;
-  for (int w = 0; w < wave; ++w) base += s_cnt[w];
-  int total = 0;
-  for (int w = 0; w < kBlock / 64; ++w) total += s_cnt[w];
-  if (cell >= 0) {
-    s_cell[base + before] = cell;
-    s_d[base + before] = di;
-  }
-  __syncthreads();
-  return total;
 }
 
 }  // namespace
@@ -127,165 +103,472 @@ hipError_t launch_gather_mass(const LevelDev& lv, const double* m_src, hipStream
 }
 
 // ---------------------------------------------------------------------------
-// Upward pass (Alg. 2 Upward + CenterShift): P2M of leaf children and M2M of
-// refined children into their father's centre, FP64.  One block per father.
+// Upward pass (Alg. 2 Upward + CenterShift), FP64.  With child offsets
+// d_o = (o - 1/2)/2 the M2M weight C(a,k) d_o^(a-k) 2^-|k| splits into
+// C(a,k) 4^-|a-k| 2^-|k| times a sign that depends only on the parity of
+// a - k, so the 8 children are first folded into 8 signed sums per
+// coefficient:  Y[k][q] = sum_o (prod_{i: q_i=1} sgn(o_i)) S_o[k].
 template <int P>
 __global__ __launch_bounds__(192) void k_upward(LevelDev lv, LevelDev lvc, CommonDev cm, int write32) {
   constexpr int K = nmi(P);
-  __shared__ double sc[8 * K];
+  __shared__ double sY[8][K];
+  __shared__ int8_t smi[K][4];
   const int r = blockIdx.x, t = threadIdx.x;
-  for (int i = t; i < 8 * K; i += blockDim.x) {
-    const int o = i / K, k = i - o * K;
-    const int c = 8 * r + o;
-    const int rc = lvc.rank[c];
-    sc[i] = rc >= 0 ? lvc.S64[(size_t)rc * K + k] : (k == 0 ? lvc.mass[c] : 0.0);
+  if (t < K) {
+    smi[t][0] = cm.mi[4 * t];
+    smi[t][1] = cm.mi[4 * t + 1];
+    smi[t][2] = cm.mi[4 * t + 2];
+    smi[t][3] = cm.mi[4 * t + 3];
+    double s[8];
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+      const int c = 8 * r + o;
+      const int rc = lvc.rank[c];
+      s[o] = rc >= 0 ? lvc.S64[(size_t)rc * K + t] : (t == 0 ? lvc.mass[c] : 0.0);
+    }
+    // fast Walsh-Hadamard over the 3 octant bits: sign +1 for o_i = 1, -1 for o_i = 0
+#pragma unroll
+    for (int bit = 0; bit < 3; ++bit) {
+      double u[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int qlo = q & ~(1 << bit);
+        if (q & (1 << bit)) u[q] = s[qlo | (1 << bit)] - s[qlo];
+        else u[q] = s[qlo] + s[qlo | (1 << bit)];
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s[q] = u[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sY[q][t] = s[q];
   }
   __syncthreads();
   if (t < K) {
-    double s = 0.0;
-    for (int o = 0; o < 8; ++o) {
-      const double* row = cm.m2m + ((size_t)o * K + t) * K;
-      for (int k = 0; k <= t; ++k) s += row[k] * sc[o * K + k];
-    }
-    lv.S64[(size_t)r * K + t] = s;
-    if (write32) lv.S32[(size_t)r * K + t] = (float)s;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// M2L at FMM level f (Alg. 3): targets are the children y of group F (level
-// f-1); sources are F's interaction list at level f-1.  L2L of L[F] is added.
-// Thread (o_y = t & 7, j = t >> 3) owns coefficients b = j, j+32, ...
-template <typename T, typename TL, int P>
-__global__ __launch_bounds__(kBlock) void k_m2l(const int32_t* __restrict__ grp, LevelDev lv2, LevelDev lv1,
-                                                LevelDev lv0, TablesDev<T> tb, const TL* __restrict__ Lpar,
-                                                const T* __restrict__ Ssrc, T* __restrict__ Lout, CommonDev cm) {
-  constexpr int K = nmi(P);
-  constexpr int NB = (K + 31) / 32;
-  // sources staged per round (LDS budget ~48 KB)
-  constexpr int NSRC = (49152 / (9 * K * (int)sizeof(T))) < 8 ? (49152 / (9 * K * (int)sizeof(T))) : 8;
-  __shared__ int s_cell[216], s_d[216], s_cnt[4];
-  __shared__ T s_S[NSRC][K];              // c_a 2^|a| S~_a
-  __shared__ T s_D[NSRC][8][K];           // D~ rows for the 8 child offsets
-  const int F = grp[blockIdx.x];
-  const int cF = lv1.refcell[F];
-  const int t = threadIdx.x;
-  const int n = build_il(lv2, cF >> 3, cF & 7, s_cell, s_d, s_cnt);
-  const int oy = t & 7, j = t >> 3;
-  T acc[NB];
-#pragma unroll
-  for (int i = 0; i < NB; ++i) acc[i] = 0;
-  if (Lpar) {
-    const TL* LF = Lpar + (size_t)F * K;
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const int b = j + 32 * i;
-      if (b < K) {
-        const T* row = tb.l2l + ((size_t)oy * K + b) * K;
-        T s = 0;
-        for (int k = b; k < K; ++k) s += row[k] * (T)LF[k];
-        acc[i] = s;
-      }
-    }
-  }
-  for (int s0 = 0; s0 < n; s0 += NSRC) {
-    const int ns = min(NSRC, n - s0);
-    for (int i = t; i < ns * K; i += kBlock) {
-      const int q = i / K, a = i - q * K;
-      const int cell = s_cell[s0 + q];
-      const int rs = lv1.rank[cell];
-      T v;
-      if (rs >= 0) v = Ssrc[(size_t)rs * K + a] * tb.cfac2[a];
-      else v = a == 0 ? (T)lv1.mass[cell] : (T)0;
-      s_S[q][a] = v;
-    }
-    for (int i = t; i < ns * 8 * K; i += kBlock) {
-      const int q = i / (8 * K), rem = i - q * 8 * K;
-      const int o = rem / K, g = rem - o * K;
-      s_D[q][o][g] = tb.Dil[((size_t)s_d[s0 + q] * 8 + o) * K + g];
-    }
-    __syncthreads();
-    for (int q = 0; q < ns; ++q) {
-#pragma unroll
-      for (int i = 0; i < NB; ++i) {
-        const int b = j + 32 * i;
-        if (b < K) {
-          const int16_t* si = cm.sumidx + (size_t)b * K;
-          const int na = nmi(P - cm.mi[4 * b + 3]);
-          T s = 0;
-          for (int a = 0; a < na; ++a) s += s_D[q][oy][si[a]] * s_S[q][a];
-          acc[i] += s;
+    const int a0 = smi[t][0], a1 = smi[t][1], a2 = smi[t][2];
+    const double* bin = cm.binom;
+    double acc = 0.0;
+    for (int k0 = 0; k0 <= a0; ++k0)
+      for (int k1 = 0; k1 <= a1; ++k1)
+        for (int k2 = 0; k2 <= a2; ++k2) {
+          const int v0 = a0 - k0, v1 = a1 - k1, v2 = a2 - k2;
+          const int q = (v0 & 1) | ((v1 & 1) << 1) | ((v2 & 1) << 2);
+          const double w = bin[a0 * (kPMax + 1) + k0] * bin[a1 * (kPMax + 1) + k1] * bin[a2 * (kPMax + 1) + k2] *
+                           ldexp(1.0, -2 * (v0 + v1 + v2) - (k0 + k1 + k2));
+          acc += w * sY[q][mi_index(k0, k1, k2)];
         }
+    lv.S64[(size_t)r * K + t] = acc;
+    if (write32) lv.S32[(size_t)r * K + t] = (float)acc;
+  }
+}
+
+hipError_t launch_upward(int p, const LevelDev& lv, const LevelDev& lvc, const CommonDev& cm, bool write32,
+                         hipStream_t st) {
+  if (lv.nref == 0) return hipSuccess;
+  const int K = nmi(p);
+  const dim3 grid(lv.nref), block(K <= 64 ? 64 : (K <= 128 ? 128 : 192));
+  switch (p) {
+#define AFMM_UP(PP) \
+  case PP: hipLaunchKernelGGL(k_upward<PP>, grid, block, 0, st, lv, lvc, cm, (int)write32); break;
+    AFMM_UP(1) AFMM_UP(2) AFMM_UP(3) AFMM_UP(4) AFMM_UP(5) AFMM_UP(6) AFMM_UP(7) AFMM_UP(8)
+#undef AFMM_UP
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// L2L (Eq. eq:L2L) chain step at FMM level f: the children y of every M2L group
+// F add L~_b[y] += sum_g w_o[|b|][g] L~_{b+g}[F] to the M2L sums already in
+// their slots.  One thread per (group, child octant, coefficient).
+template <typename T, typename TL, int P>
+__global__ void k_l2l(const int32_t* __restrict__ grp, int ngrp, const TL* __restrict__ Lpar,
+                      const int32_t* __restrict__ rank0, T* __restrict__ Lout, const T* __restrict__ w,
+                      const int16_t* __restrict__ sumidx, const int8_t* __restrict__ mi) {
+  constexpr int K = nmi(P);
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= (int64_t)ngrp * 8 * K) return;
+  const int g = (int)(i / (8 * K));
+  const int rem = (int)(i - (int64_t)g * 8 * K);
+  const int o = rem / K, b = rem - o * K;
+  const int F = grp[g];
+  const int ry = rank0[8 * F + o];
+  if (ry < 0) return;
+  const TL* LF = Lpar + (size_t)F * K;
+  const int nb = mi[4 * b + 3];
+  const T* wr = w + ((size_t)o * (P + 1) + nb) * K;
+  const int16_t* si = sumidx + (size_t)b * K;
+  T s = 0;
+  for (int gg = 0; gg < nmi(P - nb); ++gg) s += wr[gg] * (T)LF[si[gg]];
+  Lout[(size_t)ry * K + b] += s;
+}
+
+// ---------------------------------------------------------------------------
+// Shared tap pipeline of the MFMA kernels.  A block owns NC groups of one
+// parity class at one level.  For each of the 189 taps it stages, in LDS,
+//   sB[n][k]  = c_k 2^|k| S~_k of the tap's source of group n (monopole for a
+//               leaf source, 0 when there is none), k < K (zero padded to KP)
+//   sD[o][g]  = D~_g at the tap's child offset o (8 rows, then one zero slot)
+// while the MFMAs of the previous tap run.  A fragments are read from sD
+// through per-lane offsets that do not depend on the tap (kept in registers).
+template <typename T, int P, int NC>
+struct TapStage {
+  static constexpr int K = nmi(P);
+  static constexpr int KP = (K + 3) & ~3;
+  static constexpr int KS = KP + 1;          // sD row stride
+  static constexpr int KSB = KP + 1;         // sB row stride (odd: conflict-free column reads)
+  static constexpr int NB = (NC * KP + kBlock - 1) / kBlock;
+  static constexpr int ND = (8 * KS + 1 + kBlock - 1) / kBlock;
+};
+
+template <typename T> __device__ inline const T* level_S(const LevelDev& lv);
+template <> __device__ inline const float* level_S<float>(const LevelDev& lv) { return lv.S32; }
+template <> __device__ inline const double* level_S<double>(const LevelDev& lv) { return lv.S64; }
+template <typename T> __device__ inline T* level_L(const LevelDev& lv);
+template <> __device__ inline float* level_L<float>(const LevelDev& lv) { return lv.L32; }
+template <> __device__ inline double* level_L<double>(const LevelDev& lv) { return lv.L64; }
+
+template <typename T, int P, int NC>
+__device__ inline void tap_load(int code, const int* __restrict__ sCB, const int32_t* __restrict__ rank1,
+                                const double* __restrict__ mass1, const T* __restrict__ Dil,
+                                const T* __restrict__ cfac, const T* __restrict__ S1, T* vB, T* vD) {
+  using TS = TapStage<T, P, NC>;
+  const int t = threadIdx.x;
+  const int e = code & 31, op = (code >> 5) & 7, di = code >> 8;
+#pragma unroll
+  for (int j = 0; j < TS::NB; ++j) {
+    const int i = t + kBlock * j;
+    T v = 0;
+    if (i < NC * TS::KP) {
+      const int n = i / TS::KP;
+      const int a = i - n * TS::KP;
+      const int cb = sCB[n * 27 + e];
+      if (cb >= 0 && a < TS::K) {
+        const int s = cb + op;
+        const int rs = rank1[s];
+        if (rs >= 0) v = S1[(size_t)rs * TS::K + a] * cfac[a];
+        else if (a == 0) v = (T)mass1[s];
       }
     }
+    vB[j] = v;
+  }
+#pragma unroll
+  for (int j = 0; j < TS::ND; ++j) {
+    const int i = t + kBlock * j;
+    T v = 0;
+    if (i < 8 * TS::KS) {
+      const int o = i / TS::KS;
+      const int g = i - o * TS::KS;
+      if (g < TS::K) v = Dil[((size_t)di * 8 + o) * TS::K + g];
+    }
+    vD[j] = v;
+  }
+}
+
+template <typename T, int P, int NC>
+__device__ inline void tap_store(T* sB, T* sD, const T* vB, const T* vD) {
+  using TS = TapStage<T, P, NC>;
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < TS::NB; ++j) {
+    const int i = t + kBlock * j;
+    if (i < NC * TS::KP) {
+      const int n = i / TS::KP;
+      const int a = i - n * TS::KP;
+      sB[n * TS::KSB + a] = vB[j];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < TS::ND; ++j) {
+    const int i = t + kBlock * j;
+    if (i <= 8 * TS::KS) sD[i] = vD[j];
+  }
+}
+
+// Block-local setup: the tile record (level, then NC groups) and, per group,
+// the child base (8 x refined rank) of each of its father's 27 neighbours.
+__device__ inline void tile_setup(const int32_t* __restrict__ rec, int NC, const LevelDev& lv2,
+                                  const LevelDev& lv1, int* sF, int* sCB) {
+  const int t = threadIdx.x;
+  if (t < NC) sF[t] = rec[1 + t];
+  __syncthreads();
+  for (int i = t; i < NC * 27; i += kBlock) {
+    const int n = i / 27, e = i - n * 27;
+    const int F = sF[n];
+    int v = -1;
+    if (F >= 0) {
+      const int G = lv1.refcell[F] >> 3;
+      const int Q = lv2.nbr[(size_t)G * 27 + e];
+      if (Q >= 0) {
+        const int rQ = lv2.rank[Q];
+        if (rQ >= 0) v = 8 * rQ;
+      }
+    }
+    sCB[i] = v;
+  }
+}
+
+// XCD-aware tile order: consecutive blocks land on different XCDs, so block b
+// takes tile (b % 8) * ceil(n/8) + b / 8 and each XCD sweeps one contiguous
+// (spatially compact, all parity classes interleaved) range of tiles.
+__device__ inline int xcd_tile(int ntiles) {
+  const int per = (ntiles + 7) / 8;
+  return (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+}
+
+// ---------------------------------------------------------------------------
+// Intermediate-field M2P at the leaves (Alg. 4 / Sec. 3.2): rows = 8 children
+// x (phi, ax, ay, az) in two 16-row tiles, columns = NC groups, K = multipole
+// coefficients.  With NC = 64 wave w owns column tile w for both row tiles;
+// with NC = 32, column tile w & 1 and row tile w >> 1.  Output: part[F][c*8+o]
+// (accelerations already negated), in target-level units.  One launch covers
+// the tiles of every level of one precision.
+template <typename T, int P, int NC>
+__global__ __launch_bounds__(kBlock) void k_m2p(const int32_t* __restrict__ tiles, int ntiles,
+                                                const int32_t* __restrict__ taps, const int16_t* __restrict__ aoff,
+                                                const LevelDev* __restrict__ lvs, const T* __restrict__ Dil,
+                                                const T* __restrict__ cfac) {
+  using TS = TapStage<T, P, NC>;
+  static_assert(NC == 64 || NC == 32, "16-column tiles over 4 waves");
+  constexpr int NCT = NC / 16;
+  constexpr int K1 = nmi(P - 1);
+  constexpr int ST0 = TS::KP / 4, ST1 = ((K1 + 3) & ~3) / 4;
+  __shared__ T sB[2][NC * TS::KSB];
+  __shared__ T sD[2][8 * TS::KS + 1];
+  __shared__ int sF[NC];
+  __shared__ int sCB[NC * 27];
+  const int tile = xcd_tile(ntiles);
+  if (tile >= ntiles) return;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int32_t* rec = tiles + (size_t)tile * (NC + 1);
+  const int l = rec[0];
+  const LevelDev lv1 = lvs[l - 1];
+  const int32_t* rank1 = lv1.rank;
+  const double* mass1 = lv1.mass;
+  const T* S1 = level_S<T>(lv1);
+  T* part = (T*)lv1.part;
+  tile_setup(rec, NC, lvs[l - 2], lv1, sF, sCB);
+  int off0[ST0], off1[ST1];
+#pragma unroll
+  for (int kb = 0; kb < ST0; ++kb) off0[kb] = aoff[kb * 64 + lane];
+#pragma unroll
+  for (int kb = 0; kb < ST1; ++kb) off1[kb] = aoff[(ST0 + kb) * 64 + lane];
+  __syncthreads();
+  const int oF = lv1.refcell[sF[0]] & 7;
+  const int32_t* tp = taps + oF * kTaps;
+  T vB[TS::NB], vD[TS::ND];
+  tap_load<T, P, NC>(tp[0], sCB, rank1, mass1, Dil, cfac, S1, vB, vD);
+  tap_store<T, P, NC>(sB[0], sD[0], vB, vD);
+  __syncthreads();
+  typename Acc4<T>::type acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+  const int col = (NCT == 4 ? w : (w & 1)) * 16 + (lane & 15);
+  const bool do0 = NCT == 4 || (w >> 1) == 0;
+  const bool do1 = NCT == 4 || (w >> 1) == 1;
+  const int krow = lane >> 4;
+  for (int k = 0; k < kTaps; ++k) {
+    const int b = k & 1;
+    if (k + 1 < kTaps) tap_load<T, P, NC>(tp[k + 1], sCB, rank1, mass1, Dil, cfac, S1, vB, vD);
+    const T* B = sB[b] + col * TS::KSB + krow;
+    const T* D = sD[b];
+    T bv[ST0];
+#pragma unroll
+    for (int kb = 0; kb < ST0; ++kb) bv[kb] = B[4 * kb];
+#pragma unroll
+    for (int kb = 0; kb < ST0; ++kb) {
+      if (do0) acc0 = mfma16(D[off0[kb]], bv[kb], acc0);
+      if (kb < ST1 && do1) acc1 = mfma16(D[off1[kb]], bv[kb], acc1);
+    }
+    if (k + 1 < kTaps) tap_store<T, P, NC>(sB[b ^ 1], sD[b ^ 1], vB, vD);
     __syncthreads();
   }
-  const int y = 8 * F + oy;
-  const int ry = lv0.rank[y];
-  if (ry >= 0) {
+  const int F = sF[col];
+  if (F >= 0) {
+    T* out = part + (size_t)F * 32;
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const int b = j + 32 * i;
-      if (b < K) Lout[(size_t)ry * K + b] = acc[i];
+    for (int r = 0; r < 4; ++r) {
+      const int i = acc_row<T>(krow, r);
+      if (do0) out[i] = i < 8 ? acc0[r] : -acc0[r];
+      if (do1) out[16 + i] = -acc1[r];
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// Leaf evaluation at level l (Alg. 4 read through Sec. 3.2): for the leaf
-// children of group F, far (L2P of L[F]), intermediate (M2P / P2P over F's
-// interaction list at l-1), near (P2P from level-(l-1) and level-l leaves,
-// M2P from refined level-l cells not touching the target) and nearest (P2P
-// from the children of refined level-l cells touching the target).
-// Thread (o = t & 7, j = t >> 3): target child o, every 32nd source from j.
+// M2L tap sums at the FMM levels (Alg. 3 without the ShiftLocal term, which
+// the L2L chain adds afterwards): rows R = 8 b + o (local coefficient b, child
+// octant o; b in degree order, so 16-row tile T starts at coefficient 2T and
+// needs only the first ks(T)*4 multipole coefficients: the triangle
+// |a|+|b| <= p), columns = 16 groups.  The row tiles are split over the 4
+// waves by a compile-time greedy balance of their k-steps; each wave runs a
+// fully unrolled MFMA sequence with its A offsets in registers.
+constexpr int deg_of(int idx) {
+  int n = 0;
+  while (nmi(n) <= idx) ++n;
+  return n;
+}
+constexpr int m2l_ksteps(int P, int T) { return (nmi(P - deg_of(2 * T)) + 3) / 4; }
+
+template <int P>
+struct M2LPlan {
+  static constexpr int NT = (8 * nmi(P) + 15) / 16;
+  int n[4] = {0, 0, 0, 0};
+  int tile[4][NT] = {};
+  int steps[4] = {0, 0, 0, 0};
+  int kbmax[4] = {0, 0, 0, 0};
+  int base[NT] = {};   // first step of tile T in the natural-order offset table
+};
+
+template <int P>
+constexpr M2LPlan<P> make_m2l_plan() {
+  M2LPlan<P> pl{};
+  constexpr int NT = M2LPlan<P>::NT;
+  int s = 0;
+  for (int T = 0; T < NT; ++T) {
+    pl.base[T] = s;
+    s += m2l_ksteps(P, T);
+  }
+  // tiles in natural order have non-increasing k-steps: greedy to the lightest part
+  for (int T = 0; T < NT; ++T) {
+    int best = 0;
+    for (int q = 1; q < 4; ++q)
+      if (pl.steps[q] < pl.steps[best]) best = q;
+    pl.tile[best][pl.n[best]++] = T;
+    pl.steps[best] += m2l_ksteps(P, T);
+    if (m2l_ksteps(P, T) > pl.kbmax[best]) pl.kbmax[best] = m2l_ksteps(P, T);
+  }
+  return pl;
+}
+
+template <typename T, int P, int H>
+__device__ inline void m2l_part(const int32_t* __restrict__ tp, const int16_t* __restrict__ aoff, const int* sF,
+                                const int* sCB, T (*sB)[16 * TapStage<T, P, 16>::KSB],
+                                T (*sD)[8 * TapStage<T, P, 16>::KS + 1], const int32_t* __restrict__ rank1,
+                                const double* __restrict__ mass1, const T* __restrict__ Dil,
+                                const T* __restrict__ cfac, const T* __restrict__ S1, const int32_t* __restrict__ rank0,
+                                T* __restrict__ Lout) {
+  using TS = TapStage<T, P, 16>;
+  constexpr int K = TS::K;
+  constexpr M2LPlan<P> PL = make_m2l_plan<P>();
+  constexpr int NTH = PL.n[H];
+  constexpr int NS = PL.steps[H];
+  constexpr int KBH = PL.kbmax[H];
+  const int lane = threadIdx.x & 63, krow = lane >> 4;
+  int off[NS > 0 ? NS : 1];
+  {
+    int s = 0;
+#pragma unroll
+    for (int i = 0; i < NTH; ++i)
+#pragma unroll
+      for (int kb = 0; kb < m2l_ksteps(P, PL.tile[H][i]); ++kb) off[s++] = aoff[(PL.base[PL.tile[H][i]] + kb) * 64 + lane];
+  }
+  typename Acc4<T>::type acc[NTH > 0 ? NTH : 1];
+#pragma unroll
+  for (int i = 0; i < NTH; ++i) acc[i] = {0, 0, 0, 0};
+  T vB[TS::NB], vD[TS::ND];
+  for (int k = 0; k < kTaps; ++k) {
+    const int b = k & 1;
+    if (k + 1 < kTaps) tap_load<T, P, 16>(tp[k + 1], sCB, rank1, mass1, Dil, cfac, S1, vB, vD);
+    const T* B = sB[b] + (lane & 15) * TS::KSB + krow;
+    const T* D = sD[b];
+    T bv[KBH > 0 ? KBH : 1];
+#pragma unroll
+    for (int kb = 0; kb < KBH; ++kb) bv[kb] = B[4 * kb];
+    int s = 0;
+#pragma unroll
+    for (int i = 0; i < NTH; ++i)
+#pragma unroll
+      for (int kb = 0; kb < m2l_ksteps(P, PL.tile[H][i]); ++kb) {
+        acc[i] = mfma16(D[off[s]], bv[kb], acc[i]);
+        ++s;
+      }
+    if (k + 1 < kTaps) tap_store<T, P, 16>(sB[b ^ 1], sD[b ^ 1], vB, vD);
+    __syncthreads();
+  }
+  const int F = sF[lane & 15];
+  if (F < 0) return;
+#pragma unroll
+  for (int i = 0; i < NTH; ++i) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int R = 16 * PL.tile[H][i] + acc_row<T>(krow, r);
+      if ((R >> 3) >= K) continue;
+      const int ry = rank0[8 * F + (R & 7)];
+      if (ry >= 0) Lout[(size_t)ry * K + (R >> 3)] = acc[i][r];
+    }
+  }
+}
+
 template <typename T, int P>
-__global__ __launch_bounds__(kBlock) void k_leaf(const int32_t* __restrict__ grp, int l, LevelDev lv2,
-                                                 LevelDev lv1, LevelDev lv0, LevelDev lvp, TablesDev<T> tb,
-                                                 const T* __restrict__ Lpar, const T* __restrict__ S1,
-                                                 const T* __restrict__ S0, CommonDev cm, double G, double h,
-                                                 double* __restrict__ phi, double* __restrict__ acc) {
+__global__ __launch_bounds__(kBlock) void k_m2l_mfma(const int32_t* __restrict__ tiles, int ntiles,
+                                                     const int32_t* __restrict__ taps,
+                                                     const int16_t* __restrict__ aoff,
+                                                     const LevelDev* __restrict__ lvs, const T* __restrict__ Dil,
+                                                     const T* __restrict__ cfac) {
+  using TS = TapStage<T, P, 16>;
+  __shared__ T sB[2][16 * TS::KSB];
+  __shared__ T sD[2][8 * TS::KS + 1];
+  __shared__ int sF[16];
+  __shared__ int sCB[16 * 27];
+  const int tile = xcd_tile(ntiles);
+  if (tile >= ntiles) return;
+  const int t = threadIdx.x, w = t >> 6;
+  const int32_t* rec = tiles + (size_t)tile * 17;
+  const int f = rec[0];
+  const LevelDev lv1 = lvs[f - 1];
+  const LevelDev lv0 = lvs[f];
+  tile_setup(rec, 16, lvs[f - 2], lv1, sF, sCB);
+  __syncthreads();
+  const int oF = lv1.refcell[sF[0]] & 7;
+  const int32_t* tp = taps + oF * kTaps;
+  const T* S1 = level_S<T>(lv1);
+  T vB[TS::NB], vD[TS::ND];
+  tap_load<T, P, 16>(tp[0], sCB, lv1.rank, lv1.mass, Dil, cfac, S1, vB, vD);
+  tap_store<T, P, 16>(sB[0], sD[0], vB, vD);
+  __syncthreads();
+  T* Lout = level_L<T>(lv0);
+  // every wave runs the same number of barriers (one per tap)
+  switch (w) {
+    case 0: m2l_part<T, P, 0>(tp, aoff, sF, sCB, sB, sD, lv1.rank, lv1.mass, Dil, cfac, S1, lv0.rank, Lout); break;
+    case 1: m2l_part<T, P, 1>(tp, aoff, sF, sCB, sB, sD, lv1.rank, lv1.mass, Dil, cfac, S1, lv0.rank, Lout); break;
+    case 2: m2l_part<T, P, 2>(tp, aoff, sF, sCB, sB, sD, lv1.rank, lv1.mass, Dil, cfac, S1, lv0.rank, Lout); break;
+    default: m2l_part<T, P, 3>(tp, aoff, sF, sCB, sB, sD, lv1.rank, lv1.mass, Dil, cfac, S1, lv0.rank, Lout); break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Leaf evaluation at level l, VALU part: far field (L2P of L[F]), near field
+// (P2P from level-(l-1) and level-l leaves, M2P from refined level-l cells not
+// touching the target) and nearest field (P2P from the children of refined
+// level-l cells touching the target), plus the MFMA intermediate-field partial;
+// the four fields are summed in FP64 and scaled to physical units.
+// Thread (o = t & 7, j = t >> 3): target child o, every 32nd near cell from j.
+template <typename T, int P>
+__global__ __launch_bounds__(kBlock) void k_near(const int32_t* __restrict__ grp, LevelDev lv1, LevelDev lv0,
+                                                 LevelDev lvp, TablesDev<T> tb, const T* __restrict__ Lpar,
+                                                 const T* __restrict__ S0, const T* __restrict__ part,
+                                                 CommonDev cm, double G, double h, double* __restrict__ phi,
+                                                 double* __restrict__ acc) {
   constexpr int K = nmi(P);
-  __shared__ int s_cell[216], s_d[216], s_cnt[4], s_nb[27];
-  __shared__ T s_red[16][kBlock];
+  __shared__ int s_nb[27];
+  __shared__ T s_red[12][kBlock];
   const int F = grp[blockIdx.x];
-  const int cF = lv1.refcell[F];
   const int t = threadIdx.x;
   const int o = t & 7, j = t >> 3;
   if (t < 27) s_nb[t] = lv1.nbr[(size_t)F * 27 + t];
-  int n = 0;
-  if (l >= 2) n = build_il(lv2, cF >> 3, cF & 7, s_cell, s_d, s_cnt);
-  else __syncthreads();
+  __syncthreads();
   const int cell = 8 * F + o;
-  T far[4] = {0, 0, 0, 0}, mid[4] = {0, 0, 0, 0}, nea[4] = {0, 0, 0, 0}, nst[4] = {0, 0, 0, 0};
+  T far[4] = {0, 0, 0, 0}, nea[4] = {0, 0, 0, 0}, nst[4] = {0, 0, 0, 0};
   const T ox = (T)o_axis(o, 0), oy = (T)o_axis(o, 1), oz = (T)o_axis(o, 2);
-  // far field
   if (Lpar) {
     const T* LF = Lpar + (size_t)F * K;
-    const T* w = tb.l2p + (size_t)o * 4 * K;
+    const T* wl = tb.l2p + (size_t)o * 4 * K;
     for (int b = j; b < K; b += 32) {
       const T v = LF[b];
-      far[0] += w[b] * v;
-      far[1] += w[K + b] * v;
-      far[2] += w[2 * K + b] * v;
-      far[3] += w[3 * K + b] * v;
+      far[0] += wl[b] * v;
+      far[1] += wl[K + b] * v;
+      far[2] += wl[2 * K + b] * v;
+      far[3] += wl[3 * K + b] * v;
     }
   }
-  // intermediate field
-  for (int k = j; k < n; k += 32) {
-    const int s = s_cell[k];
-    const int rs = lv1.rank[s];
-    const T* D = tb.Dil + ((size_t)s_d[k] * 8 + o) * K;
-    if (rs < 0) {
-      const T m = (T)lv1.mass[s];
-      mid[0] += m * D[0];
-      mid[1] -= m * D[1];
-      mid[2] -= m * D[2];
-      mid[3] -= m * D[3];
-    } else {
-      m2p<T, P>(D, S1 + (size_t)rs * K, tb.cfac2, cm.up, mid);
-    }
-  }
-  // near and nearest fields
   for (int k = j; k < 216; k += 32) {
     const int e = k >> 3, op = k & 7;
     const int q = s_nb[e];
@@ -312,25 +595,26 @@ __global__ __launch_bounds__(kBlock) void k_leaf(const int32_t* __restrict__ grp
                (T)tz - ((T)o_axis(o2, 2) - (T)0.5) * (T)0.5, (T)lvp.mass[kc], nst);
       }
     } else {
-      const T* D = tb.Dsame + (size_t)d_index(tx, ty, tz) * K;
-      m2p<T, P>(D, S0 + (size_t)rn * K, tb.cfac1, cm.up, nea);
+      m2p_row<T, P>(tb.Dsame + (size_t)d_index(tx, ty, tz) * K, S0 + (size_t)rn * K, tb.cfac1, cm.up, nea);
     }
   }
-  // fixed-order reduction over the 32 threads of each target
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     s_red[c][t] = far[c];
-    s_red[4 + c][t] = mid[c];
-    s_red[8 + c][t] = nea[c];
-    s_red[12 + c][t] = nst[c];
+    s_red[4 + c][t] = nea[c];
+    s_red[8 + c][t] = nst[c];
   }
   __syncthreads();
   if (t < 8 && lv0.rank[8 * F + t] < 0) {
     double out[4] = {0, 0, 0, 0};
-    for (int c = 0; c < 16; ++c) {
+    for (int c = 0; c < 12; ++c) {
       T s = 0;
       for (int jj = 0; jj < 32; ++jj) s += s_red[c][t + 8 * jj];
       out[c & 3] += (double)s;
+    }
+    if (part) {
+      const T* pp = part + (size_t)F * 32;
+      for (int c = 0; c < 4; ++c) out[c] += (double)pp[c * 8 + t];
     }
     const int sl = lv0.slot[8 * F + t];
     const double sp = G / h, sa = G / (h * h);
@@ -344,30 +628,57 @@ __global__ __launch_bounds__(kBlock) void k_leaf(const int32_t* __restrict__ grp
 // ---------------------------------------------------------------------------
 // launchers
 
-hipError_t launch_upward(int p, const LevelDev& lv, const LevelDev& lvc, const CommonDev& cm, bool write32,
-                         hipStream_t st) {
-  if (lv.nref == 0) return hipSuccess;
-  const int K = nmi(p);
-  const dim3 grid(lv.nref), block(K <= 64 ? 64 : (K <= 128 ? 128 : 192));
+template <typename T, int P>
+static void m2p_launch(const MfmaTiles& mt, int t0, int n, const MfmaTables& tabs, const LevelDev* lvs, const T* Dil,
+                       const T* cfac, hipStream_t st) {
+  const dim3 grid(8 * ((n + 7) / 8)), block(kBlock);
+  if constexpr (sizeof(T) == 4 || P <= 7) {
+    if (mt.nc == 64) {
+      hipLaunchKernelGGL((k_m2p<T, P, 64>), grid, block, 0, st, mt.tiles + (size_t)t0 * 65, n, tabs.taps,
+                         tabs.m2p_off, lvs, Dil, cfac);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_m2p<T, P, 32>), grid, block, 0, st, mt.tiles + (size_t)t0 * 33, n, tabs.taps, tabs.m2p_off,
+                     lvs, Dil, cfac);
+}
+
+template <typename T>
+static hipError_t m2p_dispatch(int p, const MfmaTiles& mt, int t0, int n, const MfmaTables& tabs,
+                               const LevelDev* lvs, const T* Dil, const T* cfac, hipStream_t st) {
   switch (p) {
-#define AFMM_UP(PP) \
-  case PP: hipLaunchKernelGGL(k_upward<PP>, grid, block, 0, st, lv, lvc, cm, (int)write32); break;
-    AFMM_UP(1) AFMM_UP(2) AFMM_UP(3) AFMM_UP(4) AFMM_UP(5) AFMM_UP(6) AFMM_UP(7) AFMM_UP(8)
-#undef AFMM_UP
+    case 1: m2p_launch<T, 1>(mt, t0, n, tabs, lvs, Dil, cfac, st); break;
+    case 2: m2p_launch<T, 2>(mt, t0, n, tabs, lvs, Dil, cfac, st); break;
+    case 3: m2p_launch<T, 3>(mt, t0, n, tabs, lvs, Dil, cfac, st); break;
+    case 4: m2p_launch<T, 4>(mt, t0, n, tabs, lvs, Dil, cfac, st); break;
+    case 5: m2p_launch<T, 5>(mt, t0, n, tabs, lvs, Dil, cfac, st); break;
+    case 6: m2p_launch<T, 6>(mt, t0, n, tabs, lvs, Dil, cfac, st); break;
+    case 7: m2p_launch<T, 7>(mt, t0, n, tabs, lvs, Dil, cfac, st); break;
+    case 8: m2p_launch<T, 8>(mt, t0, n, tabs, lvs, Dil, cfac, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-template <typename T, typename TL>
-static hipError_t m2l_dispatch(int p, int ngrp, const int32_t* grp, const LevelDev& lv2, const LevelDev& lv1,
-                               const LevelDev& lv0, const TablesDev<T>& tb, const TL* Lpar, const T* S, T* Lout,
-                               const CommonDev& cm, hipStream_t st) {
-  const dim3 grid(ngrp), block(kBlock);
+hipError_t launch_m2p(int p, bool fp32, const MfmaTiles& mt, int t0, int n, const MfmaTables& tabs,
+                      const LevelDev* lvs, const TablesDev<float>& t32, const TablesDev<double>& t64,
+                      hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  if (fp32) return m2p_dispatch<float>(p, mt, t0, n, tabs, lvs, t32.Dil, t32.cfac2, st);
+  return m2p_dispatch<double>(p, mt, t0, n, tabs, lvs, t64.Dil, t64.cfac2, st);
+}
+
+int m2p_columns(int p, bool fp32) { return (fp32 || p <= 7) ? 64 : 32; }
+
+template <typename T>
+static hipError_t m2l_dispatch(int p, const MfmaTiles& mt, int t0, int n, const MfmaTables& tabs,
+                               const LevelDev* lvs, const T* Dil, const T* cfac, hipStream_t st) {
+  const dim3 grid(8 * ((n + 7) / 8)), block(kBlock);
+  const int32_t* tl = mt.tiles + (size_t)t0 * 17;
   switch (p) {
-#define AFMM_M2L(PP)                                                                                       \
-  case PP:                                                                                                 \
-    hipLaunchKernelGGL((k_m2l<T, TL, PP>), grid, block, 0, st, grp, lv2, lv1, lv0, tb, Lpar, S, Lout, cm); \
+#define AFMM_M2L(PP)                                                                                            \
+  case PP:                                                                                                      \
+    hipLaunchKernelGGL((k_m2l_mfma<T, PP>), grid, block, 0, st, tl, n, tabs.taps, tabs.m2l_off, lvs, Dil, cfac); \
     break;
     AFMM_M2L(1) AFMM_M2L(2) AFMM_M2L(3) AFMM_M2L(4) AFMM_M2L(5) AFMM_M2L(6) AFMM_M2L(7) AFMM_M2L(8)
 #undef AFMM_M2L
@@ -376,52 +687,72 @@ static hipError_t m2l_dispatch(int p, int ngrp, const int32_t* grp, const LevelD
   return hipGetLastError();
 }
 
-hipError_t launch_m2l(int p, bool fp32, bool parent_fp32, int f, const int32_t* grp, int ngrp, const LevelDev& lv2,
-                      const LevelDev& lv1, const LevelDev& lv0, const TablesDev<float>& t32,
-                      const TablesDev<double>& t64, const CommonDev& cm, hipStream_t st) {
-  if (ngrp == 0) return hipSuccess;
-  const bool has_parent = (f - 1) >= 3;
-  if (fp32) {
-    if (parent_fp32)
-      return m2l_dispatch<float, float>(p, ngrp, grp, lv2, lv1, lv0, t32, has_parent ? lv1.L32 : nullptr, lv1.S32,
-                                        lv0.L32, cm, st);
-    return m2l_dispatch<float, double>(p, ngrp, grp, lv2, lv1, lv0, t32, has_parent ? lv1.L64 : nullptr, lv1.S32,
-                                       lv0.L32, cm, st);
-  }
-  return m2l_dispatch<double, double>(p, ngrp, grp, lv2, lv1, lv0, t64, has_parent ? lv1.L64 : nullptr, lv1.S64,
-                                      lv0.L64, cm, st);
+hipError_t launch_m2l_taps(int p, bool fp32, const MfmaTiles& mt, int t0, int n, const MfmaTables& tabs,
+                           const LevelDev* lvs, const TablesDev<float>& t32, const TablesDev<double>& t64,
+                           hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  if (fp32) return m2l_dispatch<float>(p, mt, t0, n, tabs, lvs, t32.Dil, t32.cfac2, st);
+  return m2l_dispatch<double>(p, mt, t0, n, tabs, lvs, t64.Dil, t64.cfac2, st);
 }
 
-template <typename T>
-static hipError_t leaf_dispatch(int p, int l, int ngrp, const int32_t* grp, const LevelDev& lv2, const LevelDev& lv1,
-                                const LevelDev& lv0, const LevelDev& lvp, const TablesDev<T>& tb, const T* Lpar,
-                                const T* S1, const T* S0, const CommonDev& cm, double G, double h, double* phi,
-                                double* acc, hipStream_t st) {
-  const dim3 grid(ngrp), block(kBlock);
+template <typename T, typename TL>
+static hipError_t l2l_dispatch(int p, const int32_t* grp, int ngrp, const TL* Lpar, const int32_t* rank0, T* Lout,
+                               const T* w, const CommonDev& cm, hipStream_t st) {
+  const int64_t n = (int64_t)ngrp * 8 * nmi(p);
+  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
   switch (p) {
-#define AFMM_LEAF(PP)                                                                                          \
+#define AFMM_L2L(PP)                                                                                           \
   case PP:                                                                                                     \
-    hipLaunchKernelGGL((k_leaf<T, PP>), grid, block, 0, st, grp, l, lv2, lv1, lv0, lvp, tb, Lpar, S1, S0, cm, G, \
-                       h, phi, acc);                                                                           \
+    hipLaunchKernelGGL((k_l2l<T, TL, PP>), grid, block, 0, st, grp, ngrp, Lpar, rank0, Lout, w, cm.sumidx, cm.mi); \
     break;
-    AFMM_LEAF(1) AFMM_LEAF(2) AFMM_LEAF(3) AFMM_LEAF(4) AFMM_LEAF(5) AFMM_LEAF(6) AFMM_LEAF(7) AFMM_LEAF(8)
-#undef AFMM_LEAF
+    AFMM_L2L(1) AFMM_L2L(2) AFMM_L2L(3) AFMM_L2L(4) AFMM_L2L(5) AFMM_L2L(6) AFMM_L2L(7) AFMM_L2L(8)
+#undef AFMM_L2L
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_leaf(int p, bool fp32, int l, const int32_t* grp, int ngrp, const LevelDev& lv2,
-                       const LevelDev& lv1, const LevelDev& lv0, const LevelDev& lvp,
-                       const TablesDev<float>& t32, const TablesDev<double>& t64, const CommonDev& cm, double G,
-                       double h, double* phi, double* acc, hipStream_t st) {
+hipError_t launch_l2l(int p, bool fp32, bool parent_fp32, const int32_t* grp, int ngrp, const LevelDev& lv1,
+                      const LevelDev& lv0, const TablesDev<float>& t32, const TablesDev<double>& t64,
+                      const CommonDev& cm, hipStream_t st) {
+  if (ngrp == 0) return hipSuccess;
+  if (fp32) {
+    if (parent_fp32) return l2l_dispatch<float, float>(p, grp, ngrp, lv1.L32, lv0.rank, lv0.L32, t32.l2lw, cm, st);
+    return l2l_dispatch<float, double>(p, grp, ngrp, lv1.L64, lv0.rank, lv0.L32, t32.l2lw, cm, st);
+  }
+  return l2l_dispatch<double, double>(p, grp, ngrp, lv1.L64, lv0.rank, lv0.L64, t64.l2lw, cm, st);
+}
+
+template <typename T>
+static hipError_t near_dispatch(int p, int ngrp, const int32_t* grp, const LevelDev& lv1, const LevelDev& lv0,
+                                const LevelDev& lvp, const TablesDev<T>& tb, const T* Lpar, const T* S0,
+                                const T* part, const CommonDev& cm, double G, double h, double* phi, double* acc,
+                                hipStream_t st) {
+  const dim3 grid(ngrp), block(kBlock);
+  switch (p) {
+#define AFMM_NEAR(PP)                                                                                         \
+  case PP:                                                                                                    \
+    hipLaunchKernelGGL((k_near<T, PP>), grid, block, 0, st, grp, lv1, lv0, lvp, tb, Lpar, S0, part, cm, G, h, \
+                       phi, acc);                                                                             \
+    break;
+    AFMM_NEAR(1) AFMM_NEAR(2) AFMM_NEAR(3) AFMM_NEAR(4) AFMM_NEAR(5) AFMM_NEAR(6) AFMM_NEAR(7) AFMM_NEAR(8)
+#undef AFMM_NEAR
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_near(int p, bool fp32, int l, const int32_t* grp, int ngrp, const LevelDev& lv1,
+                       const LevelDev& lv0, const LevelDev& lvp, const TablesDev<float>& t32,
+                       const TablesDev<double>& t64, const CommonDev& cm, const void* part, double G, double h,
+                       double* phi, double* acc, hipStream_t st) {
   if (ngrp == 0) return hipSuccess;
   const bool has_far = (l - 1) >= 3;
   if (fp32)
-    return leaf_dispatch<float>(p, l, ngrp, grp, lv2, lv1, lv0, lvp, t32, has_far ? lv1.L32 : nullptr, lv1.S32,
-                                lv0.S32, cm, G, h, phi, acc, st);
-  return leaf_dispatch<double>(p, l, ngrp, grp, lv2, lv1, lv0, lvp, t64, has_far ? lv1.L64 : nullptr, lv1.S64,
-                               lv0.S64, cm, G, h, phi, acc, st);
+    return near_dispatch<float>(p, ngrp, grp, lv1, lv0, lvp, t32, has_far ? lv1.L32 : nullptr, lv0.S32,
+                                (const float*)part, cm, G, h, phi, acc, st);
+  return near_dispatch<double>(p, ngrp, grp, lv1, lv0, lvp, t64, has_far ? lv1.L64 : nullptr, lv0.S64,
+                               (const double*)part, cm, G, h, phi, acc, st);
 }
 
 }  // namespace afmm

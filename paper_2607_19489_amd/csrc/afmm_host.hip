@@ -413,10 +413,12 @@ struct HostTables {
   std::vector<int> mi;          // [K][4]
   std::vector<int16_t> sumidx;  // [K][K]
   std::vector<int16_t> up;      // [K][3]
-  std::vector<double> Dil, Dsame, cfac2, cfac1, l2lw, l2p, binom;
+  std::vector<double> Dil, Dsame, cfac2, cfacn, l2lw, l2p, binom;
   std::vector<int32_t> taps;        // [8][189]
   std::vector<int16_t> m2p_off;     // [steps][64]
   std::vector<int16_t> m2l_off;     // [steps][64]
+  std::vector<int32_t> m2m_start, m2m_list;
+  std::vector<double> m2m_w;
   std::vector<int32_t> m2l_tinfo;   // [NT][2]
 };
 
@@ -475,12 +477,12 @@ static void build_tables(int p, HostTables& H) {
         for (int g = 0; g < K; ++g) H.Dsame[(size_t)di * K + g] = (double)D[g];
       }
   H.cfac2.resize(K);
-  H.cfac1.resize(K);
+  H.cfacn.resize(K);
   for (int a = 0; a < K; ++a) {
     const int n = H.mi[4 * a + 3];
     const long double af = fact(H.mi[4 * a]) * fact(H.mi[4 * a + 1]) * fact(H.mi[4 * a + 2]);
     const long double sg = (n & 1) ? -1.0L : 1.0L;
-    H.cfac1[a] = (double)(sg / af);
+    H.cfacn[a] = (double)(1.0L / ipow(2.0L, n));
     H.cfac2[a] = (double)(sg * ipow(2.0L, n) / af);
   }
   // L2L weights: L~_b[y] = 2^(-1-|b|) sum_g u^g/g! L~_{b+g}[F], u = (o - 1/2)/2, stored per |b|
@@ -509,6 +511,25 @@ static void build_tables(int p, HostTables& H) {
       }
     }
   }
+  // M2M (upward) entries per coefficient a: k <= a, weight C(a,k) 4^-|a-k| 2^-|k|,
+  // sign pattern = parity of a - k (applied through the signed child sums)
+  H.m2m_start.assign(K + 1, 0);
+  H.m2m_list.clear();
+  H.m2m_w.clear();
+  for (int a = 0; a < K; ++a) {
+    H.m2m_start[a] = (int32_t)H.m2m_list.size();
+    const int* aa = &H.mi[4 * a];
+    for (int k0 = 0; k0 <= aa[0]; ++k0)
+      for (int k1 = 0; k1 <= aa[1]; ++k1)
+        for (int k2 = 0; k2 <= aa[2]; ++k2) {
+          const int v0 = aa[0] - k0, v1 = aa[1] - k1, v2 = aa[2] - k2;
+          const int q = (v0 & 1) | ((v1 & 1) << 1) | ((v2 & 1) << 2);
+          H.m2m_list.push_back(mi_index(k0, k1, k2) | (q << 12));
+          H.m2m_w.push_back((double)((long double)binom(aa[0], k0) * binom(aa[1], k1) * binom(aa[2], k2) /
+                                     ipow(2.0L, 2 * (v0 + v1 + v2) + k0 + k1 + k2)));
+        }
+  }
+  H.m2m_start[K] = (int32_t)H.m2m_list.size();
   H.binom.assign((kPMax + 1) * (kPMax + 1), 0.0);
   for (int n = 0; n <= kPMax; ++n)
     for (int k = 0; k <= n; ++k) H.binom[n * (kPMax + 1) + k] = (double)binom(n, k);
@@ -587,7 +608,12 @@ struct afmm_plan {
   MfmaTiles m2p_all[2], m2l_all[2];
   int m2p_range[kMaxLevel][3] = {};
   int m2l_range[kMaxLevel][3] = {};
+  int m2l_split[2] = {1, 1};        // tap ranges per M2L block, per precision
   LevelDev* d_lvs = nullptr;        // device copy of lv[]
+  // internal side stream: the downward M2L/L2L chain runs on it concurrently
+  // with the leaf-level M2P (they only share the multipoles of the upward pass)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   MfmaTables mt;
   TablesDev<float> t32;
   TablesDev<double> t64;
@@ -661,8 +687,14 @@ afmm_status upload_conv(afmm_plan* P, const std::vector<double>& v, const T** ou
 }
 
 void free_plan(afmm_plan* P) {
+  if (P->side) (void)hipStreamSynchronize(P->side);
   for (void* p : P->allocs) (void)hipFree(p);
   P->allocs.clear();
+  if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
+  if (P->ev_join) (void)hipEventDestroy(P->ev_join);
+  if (P->side) (void)hipStreamDestroy(P->side);
+  P->ev_fork = P->ev_join = nullptr;
+  P->side = nullptr;
   for (auto& r : P->recs) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
@@ -824,9 +856,17 @@ static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
     D.mass = (double*)p;
     if ((s = dev_alloc(P, &p, (size_t)D.nref * K * sizeof(double)))) return s;
     D.S64 = (double*)p;
+    // source copies: FP32 where an FP32 kernel reads this level (M2L of f = l+1 or
+    // M2P of l+1 when l >= f64; near-field M2P of l when l > f64+1), FP64 where an
+    // FP64 kernel does (l <= f64 + 1)
+    const int KP = (K + 3) & ~3;
     if (mixed && l >= f64) {
-      if ((s = dev_alloc(P, &p, (size_t)D.nref * K * sizeof(float)))) return s;
+      if ((s = dev_alloc(P, &p, (size_t)D.nref * KP * sizeof(float)))) return s;
       D.S32 = (float*)p;
+    }
+    if (!mixed || l <= f64 + 1) {
+      if ((s = dev_alloc(P, &p, (size_t)D.nref * KP * sizeof(double)))) return s;
+      D.Sc64 = (double*)p;
     }
     if (l <= f64) {
       if ((s = dev_alloc(P, &p, (size_t)D.nref * K * sizeof(double)))) return s;
@@ -856,18 +896,29 @@ static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
     P->cm.sumidx = d_sum;
     P->cm.up = d_up;
     P->cm.binom = d_binom;
+    const double* d_c2 = nullptr;
+    if ((s = upload_conv<double>(P, H.cfac2, &d_c2, st))) return s;
+    P->cm.cfac2 = d_c2;
+    int32_t *d_ms, *d_ml;
+    double* d_mw;
+    if ((s = upload(P, H.m2m_start, &d_ms, st)) || (s = upload(P, H.m2m_list, &d_ml, st)) ||
+        (s = upload(P, H.m2m_w, &d_mw, st)))
+      return s;
+    P->cm.m2m_start = d_ms;
+    P->cm.m2m_list = d_ml;
+    P->cm.m2m_w = d_mw;
     P->mt.taps = d_taps;
     P->mt.m2p_off = d_m2p_off;
     P->mt.m2l_off = d_m2l_off;
     P->mt.m2l_tinfo = d_tinfo;
   }
   if ((s = upload_conv<double>(P, H.Dil, &P->t64.Dil, st)) || (s = upload_conv<double>(P, H.Dsame, &P->t64.Dsame, st)) ||
-      (s = upload_conv<double>(P, H.cfac2, &P->t64.cfac2, st)) || (s = upload_conv<double>(P, H.cfac1, &P->t64.cfac1, st)) ||
+      (s = upload_conv<double>(P, H.cfac2, &P->t64.cfac2, st)) || (s = upload_conv<double>(P, H.cfacn, &P->t64.cfacn, st)) ||
       (s = upload_conv<double>(P, H.l2lw, &P->t64.l2lw, st)) || (s = upload_conv<double>(P, H.l2p, &P->t64.l2p, st)))
     return s;
   if (mixed) {
     if ((s = upload_conv<float>(P, H.Dil, &P->t32.Dil, st)) || (s = upload_conv<float>(P, H.Dsame, &P->t32.Dsame, st)) ||
-        (s = upload_conv<float>(P, H.cfac2, &P->t32.cfac2, st)) || (s = upload_conv<float>(P, H.cfac1, &P->t32.cfac1, st)) ||
+        (s = upload_conv<float>(P, H.cfac2, &P->t32.cfac2, st)) || (s = upload_conv<float>(P, H.cfacn, &P->t32.cfacn, st)) ||
         (s = upload_conv<float>(P, H.l2lw, &P->t32.l2lw, st)) || (s = upload_conv<float>(P, H.l2p, &P->t32.l2p, st)))
       return s;
   }
@@ -897,6 +948,26 @@ static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
         P->m2l_range[l][2] = m;
       }
     }
+    // M2L launches with few tiles split their 189 taps over several blocks
+    int ncu = 256;
+    {
+      int dev = 0;
+      if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+      if (ncu <= 0) ncu = 256;
+    }
+    for (int pr = 0; pr < 2; ++pr) {
+      const int nt = (int)(m2l_rec[pr].size() / 17);
+      P->m2l_split[pr] = nt > 0 ? std::max(1, std::min(21, (2 * ncu + nt - 1) / nt)) : 1;
+    }
+    for (int f = 3; f <= T.lmax - 1; ++f) {
+      const int pm = P->m2l_range[f][0];
+      if (P->m2l_split[pm] > 1 && P->m2l_range[f][2] > 0) {
+        void* q = nullptr;
+        if ((s = dev_alloc(P, &q, (size_t)P->m2l_split[pm] * T.lv[f].nref() * K * (pm ? sizeof(float) : sizeof(double)))))
+          return s;
+        P->lv[f].Lpart = q;
+      }
+    }
     for (int pr = 0; pr < 2; ++pr) {
       int32_t* d = nullptr;
       if ((s = upload(P, m2p_rec[pr], &d, st))) return s;
@@ -912,6 +983,10 @@ static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
   void* p = nullptr;
   if ((s = dev_alloc(P, &p, (size_t)std::max<int64_t>(T.nslots, 1) * sizeof(double)))) return s;
   P->m_snap = (double*)p;
+  if (hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming) != hipSuccess)
+    return fail(AFMM_E_DEVICE, "stream/event creation failed");
   if (hipStreamSynchronize(st) != hipSuccess) return fail(AFMM_E_DEVICE, "upload synchronisation failed");
   P->info.device_bytes = P->bytes;
   return AFMM_OK;
@@ -1015,10 +1090,15 @@ static afmm_status run_solve(afmm_plan* P, const double* msrc, int fmax, int lo,
   }
   for (int f = T.lmax - 1; f >= 2; --f) {
     hipEvent_t a = prof_begin(P, st);
-    if ((s = dev_check(P, launch_upward(p, P->lv[f], P->lv[f + 1], P->cm, mixed && f >= f64, st), "upward")))
+    if ((s = dev_check(P, launch_upward(p, P->lv[f], P->lv[f + 1], P->cm, st), "upward")))
       return s;
     prof_end(P, a, st, kUpward, f);
   }
+  // fork: the downward chain (M2L taps, then L2L) runs on the side stream
+  hipStream_t sd = P->side;
+  if ((s = dev_check(P, hipEventRecord(P->ev_fork, st), "fork")) ||
+      (s = dev_check(P, hipStreamWaitEvent(sd, P->ev_fork, 0), "fork")))
+    return s;
   // M2L tap sums of FMM levels 3..fmax: one launch per precision
   for (int pr = 0; pr < 2; ++pr) {
     int t0 = -1, n = 0;
@@ -1028,8 +1108,9 @@ static afmm_status run_solve(afmm_plan* P, const double* msrc, int fmax, int lo,
         n = P->m2l_range[f][1] + P->m2l_range[f][2] - t0;
       }
     if (n <= 0) continue;
-    hipEvent_t a = prof_begin(P, st);
-    if ((s = dev_check(P, launch_m2l_taps(p, pr == 1, P->m2l_all[pr], t0, n, P->mt, P->d_lvs, P->t32, P->t64, st),
+    hipEvent_t a = prof_begin(P, sd);
+    if ((s = dev_check(P, launch_m2l_taps(p, pr == 1, P->m2l_all[pr], t0, n, P->m2l_split[pr], P->mt, P->d_lvs,
+                                          P->t32, P->t64, sd),
                        "m2l")))
       return s;
     for (int f = 3; f <= fmax; ++f)
@@ -1037,20 +1118,22 @@ static afmm_status run_solve(afmm_plan* P, const double* msrc, int fmax, int lo,
         P->pending_flops += P->work.m2l_flops[f];
         P->pending_bytes += P->work.m2l_bytes[f];
       }
-    prof_end(P, a, st, pr ? kM2L32 : kM2L64, -1);
+    prof_end(P, a, sd, pr ? kM2L32 : kM2L64, -1);
   }
-  // ShiftLocal chain (L2L) from FMM level 3 down
-  for (int f = 4; f <= fmax; ++f) {
+  // completion of each FMM level: tap-range partials (if split) + ShiftLocal (L2L) of the father
+  for (int f = 3; f <= fmax; ++f) {
     const int ng = (int)T.m2lgrp[f].size();
-    if (ng == 0) continue;
-    hipEvent_t a = prof_begin(P, st);
+    const int ns = P->m2l_split[P->m2l_range[f][0]];
+    if (ng == 0 || (f - 1 < 3 && ns == 1)) continue;
+    hipEvent_t a = prof_begin(P, sd);
     if ((s = dev_check(P,
-                       launch_l2l(p, mixed && f > f64, mixed && (f - 1) > f64, P->d_m2lgrp[f], ng, P->lv[f - 1],
-                                  P->lv[f], P->t32, P->t64, P->cm, st),
+                       launch_l2l(p, mixed && f > f64, mixed && (f - 1) > f64, f - 1 >= 3, ns, P->d_m2lgrp[f], ng,
+                                  P->lv[f - 1], P->lv[f], P->t32, P->t64, P->cm, sd),
                        "l2l")))
       return s;
-    prof_end(P, a, st, kL2L, f);
+    prof_end(P, a, sd, kL2L, f);
   }
+  if ((s = dev_check(P, hipEventRecord(P->ev_join, sd), "join"))) return s;
   // intermediate field (M2P) of the leaf levels lo..hi: one launch per precision
   for (int pr = 0; pr < 2; ++pr) {
     int t0 = -1, n = 0;
@@ -1070,6 +1153,8 @@ static afmm_status run_solve(afmm_plan* P, const double* msrc, int fmax, int lo,
       }
     prof_end(P, a, st, pr ? kM2P32 : kM2P64, -1);
   }
+  // join: the far field needs the local expansions
+  if ((s = dev_check(P, hipStreamWaitEvent(st, P->ev_join, 0), "join"))) return s;
   // far, near and nearest fields + output, per leaf level
   for (int l = std::max(lo, 1); l <= hi; ++l) {
     const int ng = (int)T.leafgrp[l].size();

@@ -46,11 +46,14 @@ struct LevelDev {
   const int32_t* refcell = nullptr;  // [nref] cell index of refined rank r
   const int32_t* nbr = nullptr;      // [nref][27] neighbour cell index at this level, -1 outside box
   double* mass = nullptr;            // [n] leaf masses of this solve (0 for refined cells)
-  double* S64 = nullptr;             // [nref][K] multipoles (FP64)
-  float* S32 = nullptr;              // [nref][K] FP32 copy (mixed form)
+  double* S64 = nullptr;             // [nref][K] multipoles (FP64), used by the upward pass
+  float* S32 = nullptr;              // [nref][KP] source copy (-1)^|a|/a! 2^|a| S~_a, FP32 (mixed form);
+                                     // rows padded with zeros to KP = K rounded up to a multiple of 4
+  double* Sc64 = nullptr;            // [nref][KP] same source copy in FP64
   double* L64 = nullptr;             // [nref][K] local expansions (FP64 levels)
   float* L32 = nullptr;              // [nref][K] local expansions (FP32 levels)
   void* part = nullptr;              // [nref][32] intermediate-field partials of the leaf children (T of the leaf level)
+  void* Lpart = nullptr;             // [nsplit][nref][K] M2L tap-range partial sums (T of the level), if split
   double* Lbar64 = nullptr;          // adjoint accumulators (same layout as L)
   float* Lbar32 = nullptr;
   double* Sbar64 = nullptr;
@@ -62,7 +65,7 @@ struct TablesDev {
   const T* Dil = nullptr;     // [kNumD * 8][K]  D~ at R~ = -2d + o - 1/2
   const T* Dsame = nullptr;   // [kNumD][K]      D~ at integer R~ in [-3,3]^3
   const T* cfac2 = nullptr;   // [K] (-1)^|a|/a! 2^|a|
-  const T* cfac1 = nullptr;   // [K] (-1)^|a|/a!
+  const T* cfacn = nullptr;   // [K] 2^-|a|: same-level M2P from the source copies
   const T* l2lw = nullptr;    // [8][p+1][K] L2L weights 2^(-1-|b|) u^g/g! per child octant and |b|
   const T* l2p = nullptr;     // [8][4][K] L2P weights (phi, ax, ay, az) per child octant
 };
@@ -72,6 +75,10 @@ struct CommonDev {
   const int16_t* up = nullptr;      // [K][3] index of a + e_i (or -1 when |a| = p)
   const int8_t* mi = nullptr;       // [K][4] (a, b, c, |a|)
   const double* binom = nullptr;    // [(kPMax+1)^2] binomial coefficients C(n, k) at n*(kPMax+1)+k
+  const double* cfac2 = nullptr;    // [K] (-1)^|a|/a! 2^|a| (FP64), applied to the source copies
+  const int32_t* m2m_start = nullptr;  // [K+1] M2M entry range of each coefficient a
+  const int32_t* m2m_list = nullptr;   // entries: k | parity(a-k) << 12
+  const double* m2m_w = nullptr;       // entry weights C(a,k) 4^-|a-k| 2^-|k|
 };
 
 // Group tiles of the MFMA kernels: NC refined ranks per tile (one parity class,
@@ -93,17 +100,16 @@ struct MfmaTables {
 hipError_t launch_gather_mass(const LevelDev& lv, const double* m_src, hipStream_t st);
 hipError_t launch_copy_slots(const int32_t* slots, int64_t n, const double* src, double* dst,
                              hipStream_t st);
-hipError_t launch_upward(int p, const LevelDev& lv, const LevelDev& lvc, const CommonDev& cm,
-                         bool write32, hipStream_t st);
+hipError_t launch_upward(int p, const LevelDev& lv, const LevelDev& lvc, const CommonDev& cm, hipStream_t st);
 int m2p_columns(int p, bool fp32);
 // MFMA launches over a contiguous range [t0, t0 + n) of tile records; each
 // record is (target level, NC groups).  lvs is the device array of LevelDev.
-hipError_t launch_m2l_taps(int p, bool fp32, const MfmaTiles& mt, int t0, int n, const MfmaTables& tabs,
+hipError_t launch_m2l_taps(int p, bool fp32, const MfmaTiles& mt, int t0, int n, int nsplit, const MfmaTables& tabs,
                            const LevelDev* lvs, const TablesDev<float>& t32, const TablesDev<double>& t64,
                            hipStream_t st);
-hipError_t launch_l2l(int p, bool fp32, bool parent_fp32, const int32_t* grp, int ngrp, const LevelDev& lv1,
-                      const LevelDev& lv0, const TablesDev<float>& t32, const TablesDev<double>& t64,
-                      const CommonDev& cm, hipStream_t st);
+hipError_t launch_l2l(int p, bool fp32, bool parent_fp32, bool has_parent, int nsplit, const int32_t* grp, int ngrp,
+                      const LevelDev& lv1, const LevelDev& lv0, const TablesDev<float>& t32,
+                      const TablesDev<double>& t64, const CommonDev& cm, hipStream_t st);
 hipError_t launch_m2p(int p, bool fp32, const MfmaTiles& mt, int t0, int n, const MfmaTables& tabs,
                       const LevelDev* lvs, const TablesDev<float>& t32, const TablesDev<double>& t64,
                       hipStream_t st);

@@ -108,67 +108,72 @@ hipError_t launch_gather_mass(const LevelDev& lv, const double* m_src, hipStream
 // C(a,k) 4^-|a-k| 2^-|k| times a sign that depends only on the parity of
 // a - k, so the 8 children are first folded into 8 signed sums per
 // coefficient:  Y[k][q] = sum_o (prod_{i: q_i=1} sgn(o_i)) S_o[k].
+// The weights C(a,k) 4^-|a-k| 2^-|k| and signs are tabulated per coefficient a
+// (cm.m2m_list: for each a, its (k, parity) entries; cm.m2m_w the weights).
+// Thread = (cell, coefficient); a block holds CB cells and first stages the
+// 8 signed child sums Y of each in LDS.
 template <int P>
-__global__ __launch_bounds__(192) void k_upward(LevelDev lv, LevelDev lvc, CommonDev cm, int write32) {
-  constexpr int K = nmi(P);
-  __shared__ double sY[8][K];
-  __shared__ int8_t smi[K][4];
-  const int r = blockIdx.x, t = threadIdx.x;
-  if (t < K) {
-    smi[t][0] = cm.mi[4 * t];
-    smi[t][1] = cm.mi[4 * t + 1];
-    smi[t][2] = cm.mi[4 * t + 2];
-    smi[t][3] = cm.mi[4 * t + 3];
-    double s[8];
+__global__ __launch_bounds__(256) void k_upward(LevelDev lv, LevelDev lvc, CommonDev cm) {
+  constexpr int K = nmi(P), KP = (K + 3) & ~3;
+  constexpr int CB = 256 / KP;                // cells per block
+  __shared__ double sY[CB][8][K];
+  const int t = threadIdx.x;
+  const int c = t / KP, a = t - c * KP;
+  const int r0 = blockIdx.x * CB;
+  // phase 1: 8 child values per (cell, coefficient) -> signed sums over the octant bits
+  for (int i = t; i < CB * K; i += 256) {
+    const int cc = i / K, k = i - cc * K;
+    const int r = r0 + cc;
+    if (r >= lv.nref) continue;
+    double v[8];
 #pragma unroll
     for (int o = 0; o < 8; ++o) {
-      const int c = 8 * r + o;
-      const int rc = lvc.rank[c];
-      s[o] = rc >= 0 ? lvc.S64[(size_t)rc * K + t] : (t == 0 ? lvc.mass[c] : 0.0);
+      const int ch = 8 * r + o;
+      const int rc = lvc.rank[ch];
+      v[o] = rc >= 0 ? lvc.S64[(size_t)rc * K + k] : (k == 0 ? lvc.mass[ch] : 0.0);
     }
-    // fast Walsh-Hadamard over the 3 octant bits: sign +1 for o_i = 1, -1 for o_i = 0
 #pragma unroll
     for (int bit = 0; bit < 3; ++bit) {
       double u[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int qlo = q & ~(1 << bit);
-        if (q & (1 << bit)) u[q] = s[qlo | (1 << bit)] - s[qlo];
-        else u[q] = s[qlo] + s[qlo | (1 << bit)];
+        u[q] = (q & (1 << bit)) ? v[qlo | (1 << bit)] - v[qlo] : v[qlo] + v[qlo | (1 << bit)];
       }
 #pragma unroll
-      for (int q = 0; q < 8; ++q) s[q] = u[q];
+      for (int q = 0; q < 8; ++q) v[q] = u[q];
     }
 #pragma unroll
-    for (int q = 0; q < 8; ++q) sY[q][t] = s[q];
+    for (int q = 0; q < 8; ++q) sY[cc][q][k] = v[q];
   }
   __syncthreads();
-  if (t < K) {
-    const int a0 = smi[t][0], a1 = smi[t][1], a2 = smi[t][2];
-    const double* bin = cm.binom;
-    double acc = 0.0;
-    for (int k0 = 0; k0 <= a0; ++k0)
-      for (int k1 = 0; k1 <= a1; ++k1)
-        for (int k2 = 0; k2 <= a2; ++k2) {
-          const int v0 = a0 - k0, v1 = a1 - k1, v2 = a2 - k2;
-          const int q = (v0 & 1) | ((v1 & 1) << 1) | ((v2 & 1) << 2);
-          const double w = bin[a0 * (kPMax + 1) + k0] * bin[a1 * (kPMax + 1) + k1] * bin[a2 * (kPMax + 1) + k2] *
-                           ldexp(1.0, -2 * (v0 + v1 + v2) - (k0 + k1 + k2));
-          acc += w * sY[q][mi_index(k0, k1, k2)];
-        }
-    lv.S64[(size_t)r * K + t] = acc;
-    if (write32) lv.S32[(size_t)r * K + t] = (float)acc;
+  const int r = r0 + c;
+  if (c >= CB || r >= lv.nref) return;
+  if (a >= K) {  // zero padding of the source copies
+    if (lv.S32) lv.S32[(size_t)r * KP + a] = 0.f;
+    if (lv.Sc64) lv.Sc64[(size_t)r * KP + a] = 0.0;
+    return;
   }
+  const int b0 = cm.m2m_start[a], b1 = cm.m2m_start[a + 1];
+  double acc = 0.0;
+  for (int j = b0; j < b1; ++j) {
+    const int e = cm.m2m_list[j];
+    acc += cm.m2m_w[j] * sY[c][e >> 12][e & 4095];
+  }
+  lv.S64[(size_t)r * K + a] = acc;
+  // source copies for the translation kernels carry the factor (-1)^|a|/a! 2^|a|
+  const double sc = acc * cm.cfac2[a];
+  if (lv.S32) lv.S32[(size_t)r * KP + a] = (float)sc;
+  if (lv.Sc64) lv.Sc64[(size_t)r * KP + a] = sc;
 }
 
-hipError_t launch_upward(int p, const LevelDev& lv, const LevelDev& lvc, const CommonDev& cm, bool write32,
-                         hipStream_t st) {
+hipError_t launch_upward(int p, const LevelDev& lv, const LevelDev& lvc, const CommonDev& cm, hipStream_t st) {
   if (lv.nref == 0) return hipSuccess;
-  const int K = nmi(p);
-  const dim3 grid(lv.nref), block(K <= 64 ? 64 : (K <= 128 ? 128 : 192));
+  const int KP = (nmi(p) + 3) & ~3, CB = 256 / KP;
+  const dim3 grid((lv.nref + CB - 1) / CB), block(kBlock);
   switch (p) {
 #define AFMM_UP(PP) \
-  case PP: hipLaunchKernelGGL(k_upward<PP>, grid, block, 0, st, lv, lvc, cm, (int)write32); break;
+  case PP: hipLaunchKernelGGL(k_upward<PP>, grid, block, 0, st, lv, lvc, cm); break;
     AFMM_UP(1) AFMM_UP(2) AFMM_UP(3) AFMM_UP(4) AFMM_UP(5) AFMM_UP(6) AFMM_UP(7) AFMM_UP(8)
 #undef AFMM_UP
     default: return hipErrorInvalidValue;
@@ -177,29 +182,44 @@ hipError_t launch_upward(int p, const LevelDev& lv, const LevelDev& lvc, const C
 }
 
 // ---------------------------------------------------------------------------
-// L2L (Eq. eq:L2L) chain step at FMM level f: the children y of every M2L group
-// F add L~_b[y] += sum_g w_o[|b|][g] L~_{b+g}[F] to the M2L sums already in
-// their slots.  One thread per (group, child octant, coefficient).
+// Completion of the local expansions of FMM level f (one block per M2L group
+// F): L~_b[y] = sum_c Lpart[c][y]_b (the M2L tap sums, split over `nsplit`
+// tap ranges, added in fixed order; or the single sum already in L) + the
+// ShiftLocal term sum_g w_o[|b|][g] L~_{b+g}[F] (Eq. eq:L2L) when F has one.
 template <typename T, typename TL, int P>
-__global__ void k_l2l(const int32_t* __restrict__ grp, int ngrp, const TL* __restrict__ Lpar,
-                      const int32_t* __restrict__ rank0, T* __restrict__ Lout, const T* __restrict__ w,
-                      const int16_t* __restrict__ sumidx, const int8_t* __restrict__ mi) {
+__global__ __launch_bounds__(kBlock) void k_l2l(const int32_t* __restrict__ grp, const TL* __restrict__ Lpar,
+                                                const int32_t* __restrict__ rank0, T* __restrict__ Lout,
+                                                const T* __restrict__ Lpart, int nsplit, size_t split_stride,
+                                                const T* __restrict__ w, const int16_t* __restrict__ sumidx,
+                                                const int8_t* __restrict__ mi) {
   constexpr int K = nmi(P);
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= (int64_t)ngrp * 8 * K) return;
-  const int g = (int)(i / (8 * K));
-  const int rem = (int)(i - (int64_t)g * 8 * K);
-  const int o = rem / K, b = rem - o * K;
-  const int F = grp[g];
-  const int ry = rank0[8 * F + o];
-  if (ry < 0) return;
-  const TL* LF = Lpar + (size_t)F * K;
-  const int nb = mi[4 * b + 3];
-  const T* wr = w + ((size_t)o * (P + 1) + nb) * K;
-  const int16_t* si = sumidx + (size_t)b * K;
-  T s = 0;
-  for (int gg = 0; gg < nmi(P - nb); ++gg) s += wr[gg] * (T)LF[si[gg]];
-  Lout[(size_t)ry * K + b] += s;
+  __shared__ T sL[K];
+  __shared__ int sRy[8];
+  const int F = grp[blockIdx.x];
+  const int t = threadIdx.x;
+  if (t < K && Lpar) sL[t] = (T)Lpar[(size_t)F * K + t];
+  if (t < 8) sRy[t] = rank0[8 * F + t];
+  __syncthreads();
+  for (int i = t; i < 8 * K; i += kBlock) {
+    const int o = i / K, b = i - o * K;
+    const int ry = sRy[o];
+    if (ry < 0) continue;
+    const size_t at = (size_t)ry * K + b;
+    T v = 0;
+    if (nsplit > 1)
+      for (int c = 0; c < nsplit; ++c) v += Lpart[c * split_stride + at];
+    else
+      v = Lout[at];
+    if (Lpar) {
+      const int nb = mi[4 * b + 3];
+      const T* wr = w + ((size_t)o * (P + 1) + nb) * K;
+      const int16_t* si = sumidx + (size_t)b * K;
+      T sh = 0;
+      for (int g = 0; g < nmi(P - nb); ++g) sh += wr[g] * sL[si[g]];
+      v += sh;
+    }
+    Lout[at] = v;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -210,44 +230,60 @@ __global__ void k_l2l(const int32_t* __restrict__ grp, int ngrp, const TL* __res
 //   sD[o][g]  = D~_g at the tap's child offset o (8 rows, then one zero slot)
 // while the MFMAs of the previous tap run.  A fragments are read from sD
 // through per-lane offsets that do not depend on the tap (kept in registers).
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { typedef float type __attribute__((ext_vector_type(4))); };
+template <> struct Vec16<double> { typedef double type __attribute__((ext_vector_type(2))); };
+
 template <typename T, int P, int NC>
 struct TapStage {
   static constexpr int K = nmi(P);
-  static constexpr int KP = (K + 3) & ~3;
+  static constexpr int KP = (K + 3) & ~3;    // padded row length of the source copies
   static constexpr int KS = KP + 1;          // sD row stride
-  static constexpr int KSB = KP + 1;         // sB row stride (odd: conflict-free column reads)
-  static constexpr int NB = (NC * KP + kBlock - 1) / kBlock;
+  static constexpr int VW = 16 / (int)sizeof(T);
+  static constexpr int KV = KP / VW;         // 16-byte vectors per source row
+  static constexpr int NV = NC * KV;
+  static constexpr int NBV = (NV + kBlock - 1) / kBlock;
   static constexpr int ND = (8 * KS + 1 + kBlock - 1) / kBlock;
+  static constexpr int NCT = NC / 16;
+  static constexpr int SB = NC * KP;         // sB in MFMA fragment order [kb][ct][lane]
 };
 
+// scaled source copies c_a 2^|a| S~_a of a level
 template <typename T> __device__ inline const T* level_S(const LevelDev& lv);
 template <> __device__ inline const float* level_S<float>(const LevelDev& lv) { return lv.S32; }
-template <> __device__ inline const double* level_S<double>(const LevelDev& lv) { return lv.S64; }
+template <> __device__ inline const double* level_S<double>(const LevelDev& lv) { return lv.Sc64; }
 template <typename T> __device__ inline T* level_L(const LevelDev& lv);
 template <> __device__ inline float* level_L<float>(const LevelDev& lv) { return lv.L32; }
 template <> __device__ inline double* level_L<double>(const LevelDev& lv) { return lv.L64; }
 
+// Source of column n for tap `code`: refined rank (>= 0), -2 - cell for a leaf
+// (monopole), or -1 when there is none.  Resolved two taps ahead.
+__device__ inline int tap_src(int code, int n, const int* __restrict__ sCB, const int32_t* __restrict__ rank1) {
+  const int cb = sCB[n * 27 + (code & 31)];
+  if (cb < 0) return -1;
+  const int s = cb + ((code >> 5) & 7);
+  const int rs = rank1[s];
+  return rs >= 0 ? rs : -2 - s;
+}
+
 template <typename T, int P, int NC>
-__device__ inline void tap_load(int code, const int* __restrict__ sCB, const int32_t* __restrict__ rank1,
-                                const double* __restrict__ mass1, const T* __restrict__ Dil,
-                                const T* __restrict__ cfac, const T* __restrict__ S1, T* vB, T* vD) {
+__device__ inline void tap_load(int code, const int* __restrict__ src, const double* __restrict__ mass1,
+                                const T* __restrict__ Dil, const T* __restrict__ S1,
+                                typename Vec16<T>::type* vB, T* vD) {
   using TS = TapStage<T, P, NC>;
+  using V = typename Vec16<T>::type;
   const int t = threadIdx.x;
-  const int e = code & 31, op = (code >> 5) & 7, di = code >> 8;
+  const int di = code >> 8;
 #pragma unroll
-  for (int j = 0; j < TS::NB; ++j) {
-    const int i = t + kBlock * j;
-    T v = 0;
-    if (i < NC * TS::KP) {
-      const int n = i / TS::KP;
-      const int a = i - n * TS::KP;
-      const int cb = sCB[n * 27 + e];
-      if (cb >= 0 && a < TS::K) {
-        const int s = cb + op;
-        const int rs = rank1[s];
-        if (rs >= 0) v = S1[(size_t)rs * TS::K + a] * cfac[a];
-        else if (a == 0) v = (T)mass1[s];
-      }
+  for (int j = 0; j < TS::NBV; ++j) {
+    const int q = t + kBlock * j;
+    V v = {};
+    if (q < TS::NV) {
+      const int n = q / TS::KV;
+      const int a0 = (q - n * TS::KV) * TS::VW;
+      const int sr = src[n];
+      if (sr >= 0) v = *(const V*)(S1 + (size_t)sr * TS::KP + a0);
+      else if (sr <= -2 && a0 == 0) v[0] = (T)mass1[-2 - sr];
     }
     vB[j] = v;
   }
@@ -265,16 +301,21 @@ __device__ inline void tap_load(int code, const int* __restrict__ sCB, const int
 }
 
 template <typename T, int P, int NC>
-__device__ inline void tap_store(T* sB, T* sD, const T* vB, const T* vD) {
+__device__ inline void tap_store(T* sB, T* sD, const typename Vec16<T>::type* vB, const T* vD) {
   using TS = TapStage<T, P, NC>;
   const int t = threadIdx.x;
 #pragma unroll
-  for (int j = 0; j < TS::NB; ++j) {
-    const int i = t + kBlock * j;
-    if (i < NC * TS::KP) {
-      const int n = i / TS::KP;
-      const int a = i - n * TS::KP;
-      sB[n * TS::KSB + a] = vB[j];
+  for (int j = 0; j < TS::NBV; ++j) {
+    const int q = t + kBlock * j;
+    if (q < TS::NV) {
+      const int n = q / TS::KV;
+      const int a0 = (q - n * TS::KV) * TS::VW;
+      T* dst = sB + (n >> 4) * 64 + (n & 15);
+#pragma unroll
+      for (int e = 0; e < TS::VW; ++e) {
+        const int k = a0 + e;
+        dst[(k >> 2) * (TS::NCT * 64) + (k & 3) * 16] = vB[j][e];
+      }
     }
   }
 #pragma unroll
@@ -317,77 +358,148 @@ __device__ inline int xcd_tile(int ntiles) {
 
 // ---------------------------------------------------------------------------
 // Intermediate-field M2P at the leaves (Alg. 4 / Sec. 3.2): rows = 8 children
-// x (phi, ax, ay, az) in two 16-row tiles, columns = NC groups, K = multipole
-// coefficients.  With NC = 64 wave w owns column tile w for both row tiles;
-// with NC = 32, column tile w & 1 and row tile w >> 1.  Output: part[F][c*8+o]
-// (accelerations already negated), in target-level units.  One launch covers
-// the tiles of every level of one precision.
-template <typename T, int P, int NC>
-__global__ __launch_bounds__(kBlock) void k_m2p(const int32_t* __restrict__ tiles, int ntiles,
-                                                const int32_t* __restrict__ taps, const int16_t* __restrict__ aoff,
-                                                const LevelDev* __restrict__ lvs, const T* __restrict__ Dil,
-                                                const T* __restrict__ cfac) {
-  using TS = TapStage<T, P, NC>;
-  static_assert(NC == 64 || NC == 32, "16-column tiles over 4 waves");
-  constexpr int NCT = NC / 16;
+// x (phi, ax, ay, az) in two 16-row tiles (the acceleration rows only need
+// multipoles of order < p), columns = 16 groups of one parity class,
+// K = multipole coefficients.  One wave per block: the staged sources are not
+// shared with other waves, so blocks never wait on each other.  Output:
+// part[F][c*8+o] (accelerations already negated), in target-level units.
+// One launch covers the tiles of every level of one precision.
+template <typename T, int P>
+__global__ __launch_bounds__(64) void k_m2p(const int32_t* __restrict__ tiles, int ntiles,
+                                            const int32_t* __restrict__ taps, const int16_t* __restrict__ aoff,
+                                            const LevelDev* __restrict__ lvs, const T* __restrict__ Dil) {
+  using TS = TapStage<T, P, 16>;
+  using V = typename Vec16<T>::type;
   constexpr int K1 = nmi(P - 1);
   constexpr int ST0 = TS::KP / 4, ST1 = ((K1 + 3) & ~3) / 4;
-  __shared__ T sB[2][NC * TS::KSB];
-  __shared__ T sD[2][8 * TS::KS + 1];
-  __shared__ int sF[NC];
-  __shared__ int sCB[NC * 27];
+  constexpr int NBV = (TS::NV + 63) / 64;
+  constexpr int ND = (8 * TS::KS + 1 + 63) / 64;
+  __shared__ T sB[TS::SB];
+  __shared__ T sD[8 * TS::KS + 1];
+  __shared__ int sF[16];
+  __shared__ int sCB[16 * 27];
+  __shared__ int sSrc[2][16];
+  __shared__ int sTap[kTaps];
   const int tile = xcd_tile(ntiles);
   if (tile >= ntiles) return;
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int32_t* rec = tiles + (size_t)tile * (NC + 1);
+  const int lane = threadIdx.x;
+  const int32_t* rec = tiles + (size_t)tile * 17;
   const int l = rec[0];
   const LevelDev lv1 = lvs[l - 1];
+  const LevelDev lv2 = lvs[l - 2];
   const int32_t* rank1 = lv1.rank;
   const double* mass1 = lv1.mass;
   const T* S1 = level_S<T>(lv1);
   T* part = (T*)lv1.part;
-  tile_setup(rec, NC, lvs[l - 2], lv1, sF, sCB);
+  if (lane < 16) sF[lane] = rec[1 + lane];
+  __syncthreads();
+  for (int i = lane; i < 16 * 27; i += 64) {
+    const int n = i / 27, e = i - n * 27;
+    const int F = sF[n];
+    int v = -1;
+    if (F >= 0) {
+      const int Q = lv2.nbr[(size_t)(lv1.refcell[F] >> 3) * 27 + e];
+      if (Q >= 0) {
+        const int rQ = lv2.rank[Q];
+        if (rQ >= 0) v = 8 * rQ;
+      }
+    }
+    sCB[i] = v;
+  }
+  const int oF = lv1.refcell[sF[0]] & 7;
+  for (int i = lane; i < kTaps; i += 64) sTap[i] = taps[oF * kTaps + i];
   int off0[ST0], off1[ST1];
 #pragma unroll
   for (int kb = 0; kb < ST0; ++kb) off0[kb] = aoff[kb * 64 + lane];
 #pragma unroll
   for (int kb = 0; kb < ST1; ++kb) off1[kb] = aoff[(ST0 + kb) * 64 + lane];
   __syncthreads();
-  const int oF = lv1.refcell[sF[0]] & 7;
-  const int32_t* tp = taps + oF * kTaps;
-  T vB[TS::NB], vD[TS::ND];
-  tap_load<T, P, NC>(tp[0], sCB, rank1, mass1, Dil, cfac, S1, vB, vD);
-  tap_store<T, P, NC>(sB[0], sD[0], vB, vD);
+  if (lane < 16) {
+    sSrc[0][lane] = tap_src(sTap[0], lane, sCB, rank1);
+    sSrc[1][lane] = tap_src(sTap[1], lane, sCB, rank1);
+  }
+  __syncthreads();
+  V vB[NBV];
+  T vD[ND];
+  // stage tap `code` from registers / into registers (64 lanes)
+  auto load = [&](int code, const int* src) {
+    const int di = code >> 8;
+#pragma unroll
+    for (int j = 0; j < NBV; ++j) {
+      const int q = lane + 64 * j;
+      V v = {};
+      if (q < TS::NV) {
+        const int n = q / TS::KV;
+        const int a0 = (q - n * TS::KV) * TS::VW;
+        const int sr = src[n];
+        if (sr >= 0) v = *(const V*)(S1 + (size_t)sr * TS::KP + a0);
+        else if (sr <= -2 && a0 == 0) v[0] = (T)mass1[-2 - sr];
+      }
+      vB[j] = v;
+    }
+#pragma unroll
+    for (int j = 0; j < ND; ++j) {
+      const int i = lane + 64 * j;
+      T v = 0;
+      if (i < 8 * TS::KS) {
+        const int o = i / TS::KS;
+        const int g = i - o * TS::KS;
+        if (g < TS::K) v = Dil[((size_t)di * 8 + o) * TS::K + g];
+      }
+      vD[j] = v;
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int j = 0; j < NBV; ++j) {
+      const int q = lane + 64 * j;
+      if (q < TS::NV) {
+        const int n = q / TS::KV;
+        const int a0 = (q - n * TS::KV) * TS::VW;
+#pragma unroll
+        for (int e = 0; e < TS::VW; ++e) {
+          const int k = a0 + e;
+          sB[(k >> 2) * 64 + (k & 3) * 16 + n] = vB[j][e];
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < ND; ++j) {
+      const int i = lane + 64 * j;
+      if (i <= 8 * TS::KS) sD[i] = vD[j];
+    }
+  };
+  load(sTap[0], sSrc[0]);
+  store();
   __syncthreads();
   typename Acc4<T>::type acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-  const int col = (NCT == 4 ? w : (w & 1)) * 16 + (lane & 15);
-  const bool do0 = NCT == 4 || (w >> 1) == 0;
-  const bool do1 = NCT == 4 || (w >> 1) == 1;
   const int krow = lane >> 4;
   for (int k = 0; k < kTaps; ++k) {
     const int b = k & 1;
-    if (k + 1 < kTaps) tap_load<T, P, NC>(tp[k + 1], sCB, rank1, mass1, Dil, cfac, S1, vB, vD);
-    const T* B = sB[b] + col * TS::KSB + krow;
-    const T* D = sD[b];
+    if (k + 1 < kTaps) load(sTap[k + 1], sSrc[b ^ 1]);
+    int nsrc = 0;
+    if (k + 2 < kTaps && lane < 16) nsrc = tap_src(sTap[k + 2], lane, sCB, rank1);
     T bv[ST0];
 #pragma unroll
-    for (int kb = 0; kb < ST0; ++kb) bv[kb] = B[4 * kb];
+    for (int kb = 0; kb < ST0; ++kb) bv[kb] = sB[kb * 64 + lane];
 #pragma unroll
     for (int kb = 0; kb < ST0; ++kb) {
-      if (do0) acc0 = mfma16(D[off0[kb]], bv[kb], acc0);
-      if (kb < ST1 && do1) acc1 = mfma16(D[off1[kb]], bv[kb], acc1);
+      acc0 = mfma16(sD[off0[kb]], bv[kb], acc0);
+      if (kb < ST1) acc1 = mfma16(sD[off1[kb]], bv[kb], acc1);
     }
-    if (k + 1 < kTaps) tap_store<T, P, NC>(sB[b ^ 1], sD[b ^ 1], vB, vD);
+    __syncthreads();
+    if (k + 1 < kTaps) store();
+    if (k + 2 < kTaps && lane < 16) sSrc[b][lane] = nsrc;
     __syncthreads();
   }
-  const int F = sF[col];
+  const int F = sF[lane & 15];
   if (F >= 0) {
     T* out = part + (size_t)F * 32;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = acc_row<T>(krow, r);
-      if (do0) out[i] = i < 8 ? acc0[r] : -acc0[r];
-      if (do1) out[16 + i] = -acc1[r];
+      out[i] = i < 8 ? acc0[r] : -acc0[r];
+      out[16 + i] = -acc1[r];
     }
   }
 }
@@ -439,19 +551,18 @@ constexpr M2LPlan<P> make_m2l_plan() {
 }
 
 template <typename T, int P, int H>
-__device__ inline void m2l_part(const int32_t* __restrict__ tp, const int16_t* __restrict__ aoff, const int* sF,
-                                const int* sCB, T (*sB)[16 * TapStage<T, P, 16>::KSB],
+__device__ inline void m2l_part(const int32_t* __restrict__ tp, int nt, const int16_t* __restrict__ aoff,
+                                const int* sF, const int* sCB, int (*sSrc)[16], T (*sB)[TapStage<T, P, 16>::SB],
                                 T (*sD)[8 * TapStage<T, P, 16>::KS + 1], const int32_t* __restrict__ rank1,
                                 const double* __restrict__ mass1, const T* __restrict__ Dil,
-                                const T* __restrict__ cfac, const T* __restrict__ S1, const int32_t* __restrict__ rank0,
-                                T* __restrict__ Lout) {
+                                const T* __restrict__ S1, const int32_t* __restrict__ rank0, T* __restrict__ Lout) {
   using TS = TapStage<T, P, 16>;
   constexpr int K = TS::K;
   constexpr M2LPlan<P> PL = make_m2l_plan<P>();
   constexpr int NTH = PL.n[H];
   constexpr int NS = PL.steps[H];
   constexpr int KBH = PL.kbmax[H];
-  const int lane = threadIdx.x & 63, krow = lane >> 4;
+  const int t = threadIdx.x, lane = t & 63, krow = lane >> 4;
   int off[NS > 0 ? NS : 1];
   {
     int s = 0;
@@ -463,15 +574,18 @@ __device__ inline void m2l_part(const int32_t* __restrict__ tp, const int16_t* _
   typename Acc4<T>::type acc[NTH > 0 ? NTH : 1];
 #pragma unroll
   for (int i = 0; i < NTH; ++i) acc[i] = {0, 0, 0, 0};
-  T vB[TS::NB], vD[TS::ND];
-  for (int k = 0; k < kTaps; ++k) {
+  typename Vec16<T>::type vB[TS::NBV];
+  T vD[TS::ND];
+  for (int k = 0; k < nt; ++k) {
     const int b = k & 1;
-    if (k + 1 < kTaps) tap_load<T, P, 16>(tp[k + 1], sCB, rank1, mass1, Dil, cfac, S1, vB, vD);
-    const T* B = sB[b] + (lane & 15) * TS::KSB + krow;
+    if (k + 1 < nt) tap_load<T, P, 16>(tp[k + 1], sSrc[b ^ 1], mass1, Dil, S1, vB, vD);
+    int nsrc = 0;
+    if (k + 2 < nt && t < 16) nsrc = tap_src(tp[k + 2], t, sCB, rank1);
+    const T* B = sB[b] + lane;
     const T* D = sD[b];
     T bv[KBH > 0 ? KBH : 1];
 #pragma unroll
-    for (int kb = 0; kb < KBH; ++kb) bv[kb] = B[4 * kb];
+    for (int kb = 0; kb < KBH; ++kb) bv[kb] = B[kb * 64];
     int s = 0;
 #pragma unroll
     for (int i = 0; i < NTH; ++i)
@@ -480,7 +594,8 @@ __device__ inline void m2l_part(const int32_t* __restrict__ tp, const int16_t* _
         acc[i] = mfma16(D[off[s]], bv[kb], acc[i]);
         ++s;
       }
-    if (k + 1 < kTaps) tap_store<T, P, 16>(sB[b ^ 1], sD[b ^ 1], vB, vD);
+    if (k + 1 < nt) tap_store<T, P, 16>(sB[b ^ 1], sD[b ^ 1], vB, vD);
+    if (k + 2 < nt && t < 16) sSrc[b][t] = nsrc;
     __syncthreads();
   }
   const int F = sF[lane & 15];
@@ -497,19 +612,24 @@ __device__ inline void m2l_part(const int32_t* __restrict__ tp, const int16_t* _
   }
 }
 
+// One block = one tile (16 groups) and one of `nsplit` contiguous tap ranges.
+// With nsplit == 1 the sums go straight to L; otherwise to the level's
+// partial buffer [nsplit][nref][K], reduced in fixed order by k_l2l.
 template <typename T, int P>
-__global__ __launch_bounds__(kBlock) void k_m2l_mfma(const int32_t* __restrict__ tiles, int ntiles,
+__global__ __launch_bounds__(kBlock) void k_m2l_mfma(const int32_t* __restrict__ tiles, int ntiles, int nsplit,
                                                      const int32_t* __restrict__ taps,
                                                      const int16_t* __restrict__ aoff,
-                                                     const LevelDev* __restrict__ lvs, const T* __restrict__ Dil,
-                                                     const T* __restrict__ cfac) {
+                                                     const LevelDev* __restrict__ lvs, const T* __restrict__ Dil) {
   using TS = TapStage<T, P, 16>;
-  __shared__ T sB[2][16 * TS::KSB];
+  __shared__ T sB[2][TS::SB];
   __shared__ T sD[2][8 * TS::KS + 1];
   __shared__ int sF[16];
   __shared__ int sCB[16 * 27];
-  const int tile = xcd_tile(ntiles);
-  if (tile >= ntiles) return;
+  __shared__ int sSrc[2][16];
+  const int item = xcd_tile(ntiles * nsplit);
+  if (item >= ntiles * nsplit) return;
+  const int tile = item / nsplit, chunk = item - tile * nsplit;
+  const int tb = chunk * kTaps / nsplit, te = (chunk + 1) * kTaps / nsplit;
   const int t = threadIdx.x, w = t >> 6;
   const int32_t* rec = tiles + (size_t)tile * 17;
   const int f = rec[0];
@@ -518,19 +638,26 @@ __global__ __launch_bounds__(kBlock) void k_m2l_mfma(const int32_t* __restrict__
   tile_setup(rec, 16, lvs[f - 2], lv1, sF, sCB);
   __syncthreads();
   const int oF = lv1.refcell[sF[0]] & 7;
-  const int32_t* tp = taps + oF * kTaps;
+  const int32_t* tp = taps + oF * kTaps + tb;
+  const int nt = te - tb;
   const T* S1 = level_S<T>(lv1);
-  T vB[TS::NB], vD[TS::ND];
-  tap_load<T, P, 16>(tp[0], sCB, lv1.rank, lv1.mass, Dil, cfac, S1, vB, vD);
+  if (t < 16) {
+    sSrc[0][t] = tap_src(tp[0], t, sCB, lv1.rank);
+    if (nt > 1) sSrc[1][t] = tap_src(tp[1], t, sCB, lv1.rank);
+  }
+  __syncthreads();
+  typename Vec16<T>::type vB[TS::NBV];
+  T vD[TS::ND];
+  tap_load<T, P, 16>(tp[0], sSrc[0], lv1.mass, Dil, S1, vB, vD);
   tap_store<T, P, 16>(sB[0], sD[0], vB, vD);
   __syncthreads();
-  T* Lout = level_L<T>(lv0);
+  T* Lout = nsplit > 1 ? (T*)lv0.Lpart + (size_t)chunk * lv0.nref * TS::K : level_L<T>(lv0);
   // every wave runs the same number of barriers (one per tap)
   switch (w) {
-    case 0: m2l_part<T, P, 0>(tp, aoff, sF, sCB, sB, sD, lv1.rank, lv1.mass, Dil, cfac, S1, lv0.rank, Lout); break;
-    case 1: m2l_part<T, P, 1>(tp, aoff, sF, sCB, sB, sD, lv1.rank, lv1.mass, Dil, cfac, S1, lv0.rank, Lout); break;
-    case 2: m2l_part<T, P, 2>(tp, aoff, sF, sCB, sB, sD, lv1.rank, lv1.mass, Dil, cfac, S1, lv0.rank, Lout); break;
-    default: m2l_part<T, P, 3>(tp, aoff, sF, sCB, sB, sD, lv1.rank, lv1.mass, Dil, cfac, S1, lv0.rank, Lout); break;
+    case 0: m2l_part<T, P, 0>(tp, nt, aoff, sF, sCB, sSrc, sB, sD, lv1.rank, lv1.mass, Dil, S1, lv0.rank, Lout); break;
+    case 1: m2l_part<T, P, 1>(tp, nt, aoff, sF, sCB, sSrc, sB, sD, lv1.rank, lv1.mass, Dil, S1, lv0.rank, Lout); break;
+    case 2: m2l_part<T, P, 2>(tp, nt, aoff, sF, sCB, sSrc, sB, sD, lv1.rank, lv1.mass, Dil, S1, lv0.rank, Lout); break;
+    default: m2l_part<T, P, 3>(tp, nt, aoff, sF, sCB, sSrc, sB, sD, lv1.rank, lv1.mass, Dil, S1, lv0.rank, Lout); break;
   }
 }
 
@@ -595,7 +722,8 @@ __global__ __launch_bounds__(kBlock) void k_near(const int32_t* __restrict__ grp
                (T)tz - ((T)o_axis(o2, 2) - (T)0.5) * (T)0.5, (T)lvp.mass[kc], nst);
       }
     } else {
-      m2p_row<T, P>(tb.Dsame + (size_t)d_index(tx, ty, tz) * K, S0 + (size_t)rn * K, tb.cfac1, cm.up, nea);
+      m2p_row<T, P>(tb.Dsame + (size_t)d_index(tx, ty, tz) * K, S0 + (size_t)rn * ((K + 3) & ~3), tb.cfacn, cm.up,
+                    nea);
     }
   }
 #pragma unroll
@@ -628,33 +756,16 @@ __global__ __launch_bounds__(kBlock) void k_near(const int32_t* __restrict__ grp
 // ---------------------------------------------------------------------------
 // launchers
 
-template <typename T, int P>
-static void m2p_launch(const MfmaTiles& mt, int t0, int n, const MfmaTables& tabs, const LevelDev* lvs, const T* Dil,
-                       const T* cfac, hipStream_t st) {
-  const dim3 grid(8 * ((n + 7) / 8)), block(kBlock);
-  if constexpr (sizeof(T) == 4 || P <= 7) {
-    if (mt.nc == 64) {
-      hipLaunchKernelGGL((k_m2p<T, P, 64>), grid, block, 0, st, mt.tiles + (size_t)t0 * 65, n, tabs.taps,
-                         tabs.m2p_off, lvs, Dil, cfac);
-      return;
-    }
-  }
-  hipLaunchKernelGGL((k_m2p<T, P, 32>), grid, block, 0, st, mt.tiles + (size_t)t0 * 33, n, tabs.taps, tabs.m2p_off,
-                     lvs, Dil, cfac);
-}
-
 template <typename T>
 static hipError_t m2p_dispatch(int p, const MfmaTiles& mt, int t0, int n, const MfmaTables& tabs,
-                               const LevelDev* lvs, const T* Dil, const T* cfac, hipStream_t st) {
+                               const LevelDev* lvs, const T* Dil, hipStream_t st) {
+  const dim3 grid(8 * ((n + 7) / 8)), block(64);
+  const int32_t* tl = mt.tiles + (size_t)t0 * 17;
   switch (p) {
-    case 1: m2p_launch<T, 1>(mt, t0, n, tabs, lvs, Dil, cfac, st); break;
-    case 2: m2p_launch<T, 2>(mt, t0, n, tabs, lvs, Dil, cfac, st); break;
-    case 3: m2p_launch<T, 3>(mt, t0, n, tabs, lvs, Dil, cfac, st); break;
-    case 4: m2p_launch<T, 4>(mt, t0, n, tabs, lvs, Dil, cfac, st); break;
-    case 5: m2p_launch<T, 5>(mt, t0, n, tabs, lvs, Dil, cfac, st); break;
-    case 6: m2p_launch<T, 6>(mt, t0, n, tabs, lvs, Dil, cfac, st); break;
-    case 7: m2p_launch<T, 7>(mt, t0, n, tabs, lvs, Dil, cfac, st); break;
-    case 8: m2p_launch<T, 8>(mt, t0, n, tabs, lvs, Dil, cfac, st); break;
+#define AFMM_M2P(PP)                                                                                              \
+  case PP: hipLaunchKernelGGL((k_m2p<T, PP>), grid, block, 0, st, tl, n, tabs.taps, tabs.m2p_off, lvs, Dil); break;
+    AFMM_M2P(1) AFMM_M2P(2) AFMM_M2P(3) AFMM_M2P(4) AFMM_M2P(5) AFMM_M2P(6) AFMM_M2P(7) AFMM_M2P(8)
+#undef AFMM_M2P
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -664,21 +775,27 @@ hipError_t launch_m2p(int p, bool fp32, const MfmaTiles& mt, int t0, int n, cons
                       const LevelDev* lvs, const TablesDev<float>& t32, const TablesDev<double>& t64,
                       hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  if (fp32) return m2p_dispatch<float>(p, mt, t0, n, tabs, lvs, t32.Dil, t32.cfac2, st);
-  return m2p_dispatch<double>(p, mt, t0, n, tabs, lvs, t64.Dil, t64.cfac2, st);
+  if (fp32) return m2p_dispatch<float>(p, mt, t0, n, tabs, lvs, t32.Dil, st);
+  return m2p_dispatch<double>(p, mt, t0, n, tabs, lvs, t64.Dil, st);
 }
 
-int m2p_columns(int p, bool fp32) { return (fp32 || p <= 7) ? 64 : 32; }
+int m2p_columns(int p, bool fp32) {
+  (void)p;
+  (void)fp32;
+  return 16;
+}
 
 template <typename T>
-static hipError_t m2l_dispatch(int p, const MfmaTiles& mt, int t0, int n, const MfmaTables& tabs,
-                               const LevelDev* lvs, const T* Dil, const T* cfac, hipStream_t st) {
-  const dim3 grid(8 * ((n + 7) / 8)), block(kBlock);
+static hipError_t m2l_dispatch(int p, const MfmaTiles& mt, int t0, int n, int nsplit, const MfmaTables& tabs,
+                               const LevelDev* lvs, const T* Dil, hipStream_t st) {
+  const int items = n * nsplit;
+  const dim3 grid(8 * ((items + 7) / 8)), block(kBlock);
   const int32_t* tl = mt.tiles + (size_t)t0 * 17;
   switch (p) {
-#define AFMM_M2L(PP)                                                                                            \
-  case PP:                                                                                                      \
-    hipLaunchKernelGGL((k_m2l_mfma<T, PP>), grid, block, 0, st, tl, n, tabs.taps, tabs.m2l_off, lvs, Dil, cfac); \
+#define AFMM_M2L(PP)                                                                                          \
+  case PP:                                                                                                    \
+    hipLaunchKernelGGL((k_m2l_mfma<T, PP>), grid, block, 0, st, tl, n, nsplit, tabs.taps, tabs.m2l_off, lvs, \
+                       Dil);                                                                                  \
     break;
     AFMM_M2L(1) AFMM_M2L(2) AFMM_M2L(3) AFMM_M2L(4) AFMM_M2L(5) AFMM_M2L(6) AFMM_M2L(7) AFMM_M2L(8)
 #undef AFMM_M2L
@@ -687,23 +804,24 @@ static hipError_t m2l_dispatch(int p, const MfmaTiles& mt, int t0, int n, const 
   return hipGetLastError();
 }
 
-hipError_t launch_m2l_taps(int p, bool fp32, const MfmaTiles& mt, int t0, int n, const MfmaTables& tabs,
+hipError_t launch_m2l_taps(int p, bool fp32, const MfmaTiles& mt, int t0, int n, int nsplit, const MfmaTables& tabs,
                            const LevelDev* lvs, const TablesDev<float>& t32, const TablesDev<double>& t64,
                            hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  if (fp32) return m2l_dispatch<float>(p, mt, t0, n, tabs, lvs, t32.Dil, t32.cfac2, st);
-  return m2l_dispatch<double>(p, mt, t0, n, tabs, lvs, t64.Dil, t64.cfac2, st);
+  if (fp32) return m2l_dispatch<float>(p, mt, t0, n, nsplit, tabs, lvs, t32.Dil, st);
+  return m2l_dispatch<double>(p, mt, t0, n, nsplit, tabs, lvs, t64.Dil, st);
 }
 
 template <typename T, typename TL>
 static hipError_t l2l_dispatch(int p, const int32_t* grp, int ngrp, const TL* Lpar, const int32_t* rank0, T* Lout,
-                               const T* w, const CommonDev& cm, hipStream_t st) {
-  const int64_t n = (int64_t)ngrp * 8 * nmi(p);
-  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+                               const T* Lpart, int nsplit, size_t stride, const T* w, const CommonDev& cm,
+                               hipStream_t st) {
+  const dim3 grid(ngrp), block(kBlock);
   switch (p) {
-#define AFMM_L2L(PP)                                                                                           \
-  case PP:                                                                                                     \
-    hipLaunchKernelGGL((k_l2l<T, TL, PP>), grid, block, 0, st, grp, ngrp, Lpar, rank0, Lout, w, cm.sumidx, cm.mi); \
+#define AFMM_L2L(PP)                                                                                             \
+  case PP:                                                                                                       \
+    hipLaunchKernelGGL((k_l2l<T, TL, PP>), grid, block, 0, st, grp, Lpar, rank0, Lout, Lpart, nsplit, stride, w, \
+                       cm.sumidx, cm.mi);                                                                        \
     break;
     AFMM_L2L(1) AFMM_L2L(2) AFMM_L2L(3) AFMM_L2L(4) AFMM_L2L(5) AFMM_L2L(6) AFMM_L2L(7) AFMM_L2L(8)
 #undef AFMM_L2L
@@ -712,15 +830,20 @@ static hipError_t l2l_dispatch(int p, const int32_t* grp, int ngrp, const TL* Lp
   return hipGetLastError();
 }
 
-hipError_t launch_l2l(int p, bool fp32, bool parent_fp32, const int32_t* grp, int ngrp, const LevelDev& lv1,
-                      const LevelDev& lv0, const TablesDev<float>& t32, const TablesDev<double>& t64,
-                      const CommonDev& cm, hipStream_t st) {
+hipError_t launch_l2l(int p, bool fp32, bool parent_fp32, bool has_parent, int nsplit, const int32_t* grp, int ngrp,
+                      const LevelDev& lv1, const LevelDev& lv0, const TablesDev<float>& t32,
+                      const TablesDev<double>& t64, const CommonDev& cm, hipStream_t st) {
   if (ngrp == 0) return hipSuccess;
+  const size_t stride = (size_t)lv0.nref * nmi(p);
   if (fp32) {
-    if (parent_fp32) return l2l_dispatch<float, float>(p, grp, ngrp, lv1.L32, lv0.rank, lv0.L32, t32.l2lw, cm, st);
-    return l2l_dispatch<float, double>(p, grp, ngrp, lv1.L64, lv0.rank, lv0.L32, t32.l2lw, cm, st);
+    if (parent_fp32)
+      return l2l_dispatch<float, float>(p, grp, ngrp, has_parent ? lv1.L32 : nullptr, lv0.rank, lv0.L32,
+                                        (const float*)lv0.Lpart, nsplit, stride, t32.l2lw, cm, st);
+    return l2l_dispatch<float, double>(p, grp, ngrp, has_parent ? lv1.L64 : nullptr, lv0.rank, lv0.L32,
+                                       (const float*)lv0.Lpart, nsplit, stride, t32.l2lw, cm, st);
   }
-  return l2l_dispatch<double, double>(p, grp, ngrp, lv1.L64, lv0.rank, lv0.L64, t64.l2lw, cm, st);
+  return l2l_dispatch<double, double>(p, grp, ngrp, has_parent ? lv1.L64 : nullptr, lv0.rank, lv0.L64,
+                                      (const double*)lv0.Lpart, nsplit, stride, t64.l2lw, cm, st);
 }
 
 template <typename T>
@@ -751,7 +874,7 @@ hipError_t launch_near(int p, bool fp32, int l, const int32_t* grp, int ngrp, co
   if (fp32)
     return near_dispatch<float>(p, ngrp, grp, lv1, lv0, lvp, t32, has_far ? lv1.L32 : nullptr, lv0.S32,
                                 (const float*)part, cm, G, h, phi, acc, st);
-  return near_dispatch<double>(p, ngrp, grp, lv1, lv0, lvp, t64, has_far ? lv1.L64 : nullptr, lv0.S64,
+  return near_dispatch<double>(p, ngrp, grp, lv1, lv0, lvp, t64, has_far ? lv1.L64 : nullptr, lv0.Sc64,
                                (const double*)part, cm, G, h, phi, acc, st);
 }
 

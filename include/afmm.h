@@ -58,10 +58,15 @@ typedef struct afmm_options {
   double boxlen;             /* box side */
   uint32_t flags;            /* AFMM_CHECK_INPUT */
   int32_t fp64_levels;       /* mixed form: FMM levels <= this stay FP64 (default 4) */
+  int32_t tap_split;         /* M2L blocks per tile: the 189 source offsets of a tile are split
+                                over this many blocks and their partial sums reduced in a fixed
+                                order; 0 = automatic (enough blocks to fill the GPU), else 1..21.
+                                Results depend on it only through FP rounding order. */
   size_t max_device_bytes;   /* cap on the plan's device memory; 0 = no cap */
 } afmm_options;
 
-/* Defaults: p = 4, FP64, G = 1, boxlen = 1, no flags, fp64_levels = 4, no cap. */
+/* Defaults: p = 4, FP64, G = 1, boxlen = 1, no flags, fp64_levels = 4, tap_split = 0 (automatic),
+   no cap. */
 void afmm_options_default(afmm_options* opt);
 
 /*
@@ -145,10 +150,24 @@ afmm_status afmm_solve_adjoint(afmm_plan* plan, int32_t level, const double* d_p
                                const double* d_acc_bar, double* d_mass_bar, void* hip_stream);
 
 /*
- * Batch of independent hierarchies solved together (synchronous solves).  All
- * plans must share p, precision, G and boxlen; the batch copies their topology,
- * so the plans may be destroyed afterwards.  afmm_batch_solve takes host arrays
- * of n device pointers and runs the whole batch as one captured hipGraph launch.
+ * Batch of independent hierarchies of uneven size and depth, solved together
+ * (synchronous solves, Alg. 1 with every tree rebuilt).  The batch is one plan
+ * over the forest of all hierarchies: level l of the forest is the union of the
+ * level-l cells of every hierarchy (Morton order inside each), so every kernel
+ * of a solve runs once over all hierarchies.  The whole solve -- mass gather
+ * from the n caller arrays, upward pass, M2L/L2L chain, leaf fields and the
+ * scatter of the results -- is captured once into a hipGraph at creation and
+ * replayed by afmm_batch_solve as one graph launch.
+ *   plans[i]       plans built by afmm_plan_create (one hierarchy each); all must
+ *                  share p, precision, G, boxlen, fp64_levels and tap_split.  The
+ *                  batch copies their topology: they may be destroyed afterwards.
+ *   hip_stream     orders the uploads and the graph capture.
+ * afmm_batch_solve: d_mass[i], d_phi[i], d_acc[i] are device pointers laid out as
+ * for afmm_solve on plans[i] (host arrays of n pointers, read at the call).  Only
+ * leaf entries of the outputs are written.  A solve of the batch gives the same
+ * bits as afmm_solve on each plan (same tap_split, no atomics anywhere).
+ * Errors: AFMM_E_INVALID_ARG (null pointer, n < 1, an options mismatch),
+ * AFMM_E_DEVICE (capture or launch failure), AFMM_E_OUT_OF_MEMORY.
  */
 afmm_status afmm_batch_create(afmm_plan* const* plans, int32_t n, void* hip_stream, afmm_batch** out);
 afmm_status afmm_batch_solve(afmm_batch* batch, const double* const* d_mass, double* const* d_phi,

@@ -33,7 +33,8 @@ SYMBOLS = [
 
 class Options(C.Structure):
     _fields_ = [("p", C.c_int32), ("precision", C.c_int32), ("G", C.c_double), ("boxlen", C.c_double),
-                ("flags", C.c_uint32), ("fp64_levels", C.c_int32), ("max_device_bytes", C.c_size_t)]
+                ("flags", C.c_uint32), ("fp64_levels", C.c_int32), ("tap_split", C.c_int32),
+                ("max_device_bytes", C.c_size_t)]
 
 
 class HierarchyC(C.Structure):

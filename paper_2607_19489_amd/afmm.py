@@ -41,7 +41,8 @@ def _hier_struct(levelmin, levelmax, ncell, ijk, ref):
 
 
 def make_options(p: int = 4, precision: str = "fp64", G: float = 1.0, boxlen: float = 1.0,
-                 fp64_levels: int = 4, check_input: bool = False, max_device_bytes: int = 0) -> Options:
+                 fp64_levels: int = 4, check_input: bool = False, max_device_bytes: int = 0,
+                 tap_split: int = 0) -> Options:
     o = Options()
     lib().afmm_options_default(C.byref(o))
     o.p = p
@@ -49,6 +50,7 @@ def make_options(p: int = 4, precision: str = "fp64", G: float = 1.0, boxlen: fl
     o.G = G
     o.boxlen = boxlen
     o.fp64_levels = fp64_levels
+    o.tap_split = tap_split
     o.flags = AFMM_CHECK_INPUT if check_input else 0
     o.max_device_bytes = max_device_bytes
     return o
@@ -69,14 +71,14 @@ class Plan:
 
     def __init__(self, h, p: int = 4, precision: str = "fp64", G: float = 1.0,
                  boxlen: Optional[float] = None, fp64_levels: int = 4, check_input: bool = False,
-                 max_device_bytes: int = 0, stream: Optional[torch.cuda.Stream] = None):
+                 max_device_bytes: int = 0, tap_split: int = 0, stream: Optional[torch.cuda.Stream] = None):
         self._ptr = C.c_void_p()
         arrs = _hierarchy_arrays(h)
         self.levelmin, self.levelmax, self.ncell = arrs[0], arrs[1], arrs[2]
         self.N = int(self.ncell.sum())
         hc = _hier_struct(*arrs)
         bl = float(boxlen if boxlen is not None else getattr(h, "boxlen", 1.0))
-        self.options = make_options(p, precision, G, bl, fp64_levels, check_input, max_device_bytes)
+        self.options = make_options(p, precision, G, bl, fp64_levels, check_input, max_device_bytes, tap_split)
         check(lib().afmm_plan_create(C.byref(hc), C.byref(self.options), _stream_handle(stream),
                                      C.byref(self._ptr)), "afmm_plan_create")
         self.p = p
@@ -147,6 +149,60 @@ class Plan:
                                        C.c_void_p(acc_bar.data_ptr()), C.c_void_p(mass_bar.data_ptr()),
                                        _stream_handle(stream)), "afmm_solve_adjoint")
         return mass_bar
+
+
+def _check_f64(t: torch.Tensor, shape, name: str):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float64 CUDA tensor")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+class Batch:
+    """Independent hierarchies solved as one forest, replayed as one hipGraph (afmm_batch)."""
+
+    def __init__(self, plans: Sequence[Plan], stream: Optional[torch.cuda.Stream] = None):
+        self._ptr = C.c_void_p()
+        self.sizes = [pl.N for pl in plans]
+        arr = (C.c_void_p * len(plans))(*[pl.handle.value for pl in plans])
+        check(lib().afmm_batch_create(arr, len(plans), _stream_handle(stream), C.byref(self._ptr)),
+              "afmm_batch_create")
+
+    def close(self):
+        if self._ptr:
+            lib().afmm_batch_destroy(self._ptr)
+            self._ptr = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        info = PlanInfo()
+        check(lib().afmm_batch_get_info(self._ptr, C.byref(info)), "afmm_batch_get_info")
+        return info.as_dict()
+
+    def solve(self, masses: Sequence[torch.Tensor], phis: Optional[Sequence[torch.Tensor]] = None,
+              accs: Optional[Sequence[torch.Tensor]] = None, stream: Optional[torch.cuda.Stream] = None):
+        """afmm_batch_solve: returns the lists (phis, accs)."""
+        n = len(self.sizes)
+        if len(masses) != n:
+            raise ValueError(f"expected {n} mass tensors")
+        if phis is None:
+            phis = [torch.zeros(N, dtype=torch.float64, device=masses[0].device) for N in self.sizes]
+        if accs is None:
+            accs = [torch.zeros(N, 3, dtype=torch.float64, device=masses[0].device) for N in self.sizes]
+        for i, N in enumerate(self.sizes):
+            _check_f64(masses[i], (N,), f"masses[{i}]")
+            _check_f64(phis[i], (N,), f"phis[{i}]")
+            _check_f64(accs[i], (N, 3), f"accs[{i}]")
+        mp = (C.c_void_p * n)(*[t.data_ptr() for t in masses])
+        pp = (C.c_void_p * n)(*[t.data_ptr() for t in phis])
+        ap = (C.c_void_p * n)(*[t.data_ptr() for t in accs])
+        check(lib().afmm_batch_solve(self._ptr, mp, pp, ap, _stream_handle(stream)), "afmm_batch_solve")
+        return phis, accs
 
 
 class AFMMSolve(torch.autograd.Function):

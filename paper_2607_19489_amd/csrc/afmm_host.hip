@@ -636,15 +636,21 @@ struct afmm_plan {
 };
 
 struct afmm_batch {
-  afmm_plan* plan = nullptr;      // concatenated topology
+  afmm_plan* plan = nullptr;      // one plan over the forest of all hierarchies
   int32_t n = 0;
-  std::vector<int64_t> base, count;
-  double* d_mass = nullptr;
+  std::vector<int64_t> base;      // [n + 1] slot offset of each hierarchy in the forest
+  double* d_mass = nullptr;       // forest-wide slot arrays
   double* d_phi = nullptr;
   double* d_acc = nullptr;
+  int32_t* d_leafslot = nullptr;  // forest slot of every leaf
+  int32_t* d_leafhier = nullptr;  // its hierarchy
+  int64_t* d_base = nullptr;
+  void** d_ptrs = nullptr;        // [3][n] caller pointers (mass, phi, acc), refreshed per solve
+  std::vector<void*> h_ptrs;
+  int64_t nleaf = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  hipStream_t graph_stream = nullptr;
+  hipStream_t cap = nullptr;      // capture stream
 };
 
 namespace {
@@ -712,6 +718,7 @@ afmm_status check_options(const afmm_options* o) {
   if (o->flags & ~AFMM_CHECK_INPUT) return fail(AFMM_E_UNSUPPORTED, "unknown flag");
   if (!(o->boxlen > 0) || !std::isfinite(o->boxlen)) return fail(AFMM_E_INVALID_ARG, "boxlen must be > 0");
   if (!std::isfinite(o->G)) return fail(AFMM_E_INVALID_ARG, "G must be finite");
+  if (o->tap_split < 0 || o->tap_split > 21) return fail(AFMM_E_UNSUPPORTED, "tap_split must be in 0..21");
   return AFMM_OK;
 }
 
@@ -766,6 +773,7 @@ void afmm_options_default(afmm_options* o) {
   o->boxlen = 1.0;
   o->flags = 0;
   o->fp64_levels = 4;
+  o->tap_split = 0;
   o->max_device_bytes = 0;
 }
 
@@ -957,7 +965,9 @@ static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
     }
     for (int pr = 0; pr < 2; ++pr) {
       const int nt = (int)(m2l_rec[pr].size() / 17);
-      P->m2l_split[pr] = nt > 0 ? std::max(1, std::min(21, (2 * ncu + nt - 1) / nt)) : 1;
+      P->m2l_split[pr] = P->opt.tap_split > 0 ? P->opt.tap_split
+                         : nt > 0              ? std::max(1, std::min(21, (2 * ncu + nt - 1) / nt))
+                                               : 1;
     }
     for (int f = 3; f <= T.lmax - 1; ++f) {
       const int pm = P->m2l_range[f][0];
@@ -1272,28 +1282,167 @@ extern "C" afmm_status afmm_solve_adjoint(afmm_plan* P, int32_t level, const dou
   return fail(AFMM_E_UNSUPPORTED, "adjoint not built yet");
 }
 
+// Append topology S (one hierarchy) to the forest T, offsetting cells, refined
+// ranks and slots.  Level l of S holds 8 x (refined cells of level l-1) cells
+// like T, so the children of a shifted refined rank stay at 8r..8r+7.
+static void merge_topology(Topology& T, const Topology& S, int64_t slot_base) {
+  for (int l = 0; l <= S.lmax; ++l) {
+    HostLevel& D = T.lv[l];
+    const HostLevel& E = S.lv[l];
+    const int32_t base = D.n(), rbase = D.nref();
+    for (int32_t c = 0; c < E.n(); ++c) {
+      D.rank.push_back(E.rank[c] >= 0 ? E.rank[c] + rbase : -1);
+      D.slot.push_back(E.slot[c] >= 0 ? (int32_t)(E.slot[c] + slot_base) : -1);
+    }
+    for (int32_t r = 0; r < E.nref(); ++r) D.refcell.push_back(E.refcell[r] + base);
+    for (int32_t v : E.nbr) D.nbr.push_back(v >= 0 ? v + base : v);
+  }
+  T.lmax = std::max(T.lmax, S.lmax);
+  for (size_t i = 0; i < S.levelmin.size(); ++i) {
+    T.lmin_all = std::min(T.lmin_all, S.levelmin[i]);
+    T.levelmin.push_back(S.levelmin[i]);
+    T.levelmax.push_back(S.levelmax[i]);
+    T.slot_base.push_back(slot_base + S.slot_base[i]);
+    T.slot_count.push_back(S.slot_count[i]);
+    T.level_off.push_back(S.level_off[i]);
+  }
+  T.nslots = slot_base + S.nslots;
+}
+
+static void free_batch(afmm_batch* B) {
+  if (B->exec) (void)hipGraphExecDestroy(B->exec);
+  if (B->graph) (void)hipGraphDestroy(B->graph);
+  if (B->cap) (void)hipStreamDestroy(B->cap);
+  if (B->plan) {
+    free_plan(B->plan);
+    delete B->plan;
+  }
+  B->exec = nullptr;
+  B->graph = nullptr;
+  B->cap = nullptr;
+  B->plan = nullptr;
+}
+
 extern "C" afmm_status afmm_batch_create(afmm_plan* const* plans, int32_t n, void* hip_stream, afmm_batch** out) {
-  (void)plans;
-  (void)n;
-  (void)hip_stream;
-  if (out) *out = nullptr;
-  return fail(AFMM_E_UNSUPPORTED, "batching not built yet");
+  if (!plans || !out || n < 1) return fail(AFMM_E_INVALID_ARG, "null argument or n < 1");
+  *out = nullptr;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const afmm_options& o0 = plans[0] ? plans[0]->opt : afmm_options{};
+  for (int32_t i = 0; i < n; ++i) {
+    const afmm_plan* Q = plans[i];
+    if (!Q) return fail(AFMM_E_INVALID_ARG, "null plan in batch");
+    if (Q->dead) return fail(AFMM_E_DEVICE, "a plan of the batch is unusable after a device error");
+    if (Q->topo.levelmin.size() != 1) return fail(AFMM_E_INVALID_ARG, "a batch takes single-hierarchy plans");
+    const afmm_options& o = Q->opt;
+    if (o.p != o0.p || o.precision != o0.precision || o.G != o0.G || o.boxlen != o0.boxlen ||
+        o.fp64_levels != o0.fp64_levels || o.tap_split != o0.tap_split)
+      return fail(AFMM_E_INVALID_ARG, "plans of a batch must share p, precision, G, boxlen, fp64_levels, tap_split");
+  }
+  afmm_batch* B = new afmm_batch();
+  B->n = n;
+  B->plan = new afmm_plan();
+  afmm_plan* P = B->plan;
+  P->opt = o0;
+  P->opt.flags = 0;
+  P->K = nmi(o0.p);
+  B->base.assign(n + 1, 0);
+  for (int32_t i = 0; i < n; ++i) {
+    merge_topology(P->topo, plans[i]->topo, B->base[i]);
+    B->base[i + 1] = B->base[i] + plans[i]->topo.nslots;
+  }
+  afmm_status s = B->base[n] >= ((int64_t)1 << 31) ? fail(AFMM_E_INVALID_ARG, "batch has more than 2^31 cells")
+                                                    : plan_finish(P, st);
+  // leaf slots of the forest and their hierarchy
+  std::vector<int32_t> lslot, lhier;
+  if (!s) {
+    const Topology& T = P->topo;
+    for (int l = 0; l <= T.lmax; ++l)
+      for (int32_t c = 0; c < T.lv[l].n(); ++c) {
+        const int32_t sl = T.lv[l].slot[c];
+        if (T.lv[l].rank[c] >= 0 || sl < 0) continue;
+        lslot.push_back(sl);
+        lhier.push_back((int32_t)(std::upper_bound(B->base.begin(), B->base.end(), (int64_t)sl) - B->base.begin() - 1));
+      }
+    B->nleaf = (int64_t)lslot.size();
+    void* q = nullptr;
+    const size_t ns = (size_t)std::max<int64_t>(P->topo.nslots, 1);
+    if (!s) s = dev_alloc(P, &q, ns * sizeof(double)), B->d_mass = (double*)q;
+    if (!s) s = dev_alloc(P, &q, ns * sizeof(double)), B->d_phi = (double*)q;
+    if (!s) s = dev_alloc(P, &q, ns * 3 * sizeof(double)), B->d_acc = (double*)q;
+    if (!s) s = dev_alloc(P, &q, (size_t)3 * n * sizeof(void*)), B->d_ptrs = (void**)q;
+    if (!s) s = upload(P, lslot, &B->d_leafslot, st);
+    if (!s) s = upload(P, lhier, &B->d_leafhier, st);
+    if (!s) s = upload(P, B->base, &B->d_base, st);
+    B->h_ptrs.assign((size_t)3 * n, nullptr);
+  }
+  // capture: gather -> solve -> scatter, replayed by afmm_batch_solve
+  if (!s) {
+    if (hipStreamSynchronize(st) != hipSuccess ||
+        hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking) != hipSuccess)
+      s = fail(AFMM_E_DEVICE, "batch stream creation failed");
+  }
+  if (!s) {
+    const Topology& T = P->topo;
+    hipStream_t cs = B->cap;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      s = fail(AFMM_E_DEVICE, "graph capture could not start");
+    } else {
+      afmm_status sr = dev_check(P, launch_batch_in(B->nleaf, B->d_leafslot, B->d_leafhier, B->d_base,
+                                                    (const double* const*)B->d_ptrs, B->d_mass, cs),
+                                 "batch gather");
+      if (!sr) sr = run_solve(P, B->d_mass, T.lmax - 1, T.lmin_all, T.lmax, B->d_phi, B->d_acc, cs);
+      if (!sr)
+        sr = dev_check(P, launch_batch_out(B->nleaf, B->d_leafslot, B->d_leafhier, B->d_base, B->d_phi, B->d_acc,
+                                           (double* const*)(B->d_ptrs + n), (double* const*)(B->d_ptrs + 2 * n), cs),
+                       "batch scatter");
+      const hipError_t ee = hipStreamEndCapture(cs, &B->graph);
+      if (sr) s = sr;
+      else if (ee != hipSuccess || !B->graph) s = fail(AFMM_E_DEVICE, "graph capture failed");
+      else if (hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0) != hipSuccess)
+        s = fail(AFMM_E_DEVICE, "graph instantiation failed");
+    }
+  }
+  if (s) {
+    free_batch(B);
+    delete B;
+    return s;
+  }
+  *out = B;
+  return AFMM_OK;
 }
-extern "C" afmm_status afmm_batch_solve(afmm_batch* b, const double* const* d_mass, double* const* d_phi,
+
+extern "C" afmm_status afmm_batch_solve(afmm_batch* B, const double* const* d_mass, double* const* d_phi,
                                         double* const* d_acc, void* hip_stream) {
-  (void)b;
-  (void)d_mass;
-  (void)d_phi;
-  (void)d_acc;
-  (void)hip_stream;
-  return fail(AFMM_E_UNSUPPORTED, "batching not built yet");
+  if (!B || !d_mass || !d_phi || !d_acc) return fail(AFMM_E_INVALID_ARG, "null argument");
+  if (B->plan->dead) return fail(AFMM_E_DEVICE, "batch is unusable after an earlier device error");
+  const int32_t n = B->n;
+  for (int32_t i = 0; i < n; ++i) {
+    if (!d_mass[i] || !d_phi[i] || !d_acc[i]) return fail(AFMM_E_INVALID_ARG, "null array in batch");
+    B->h_ptrs[i] = (void*)d_mass[i];
+    B->h_ptrs[n + i] = (void*)d_phi[i];
+    B->h_ptrs[2 * n + i] = (void*)d_acc[i];
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  afmm_status s;
+  // pageable source: the runtime stages it before returning, so h_ptrs may be reused
+  if ((s = dev_check(B->plan, hipMemcpyAsync(B->d_ptrs, B->h_ptrs.data(), (size_t)3 * n * sizeof(void*),
+                                             hipMemcpyHostToDevice, st),
+                     "batch pointer table")))
+    return s;
+  return dev_check(B->plan, hipGraphLaunch(B->exec, st), "batch graph launch");
 }
-extern "C" afmm_status afmm_batch_get_info(const afmm_batch* b, afmm_plan_info* out) {
-  (void)b;
-  (void)out;
-  return fail(AFMM_E_UNSUPPORTED, "batching not built yet");
+
+extern "C" afmm_status afmm_batch_get_info(const afmm_batch* B, afmm_plan_info* out) {
+  if (!B || !out) return fail(AFMM_E_INVALID_ARG, "null argument");
+  *out = B->plan->info;
+  return AFMM_OK;
 }
-extern "C" afmm_status afmm_batch_destroy(afmm_batch* b) {
-  (void)b;
+
+extern "C" afmm_status afmm_batch_destroy(afmm_batch* B) {
+  if (!B) return AFMM_OK;
+  if (B->plan && B->plan->side) (void)hipStreamSynchronize(B->plan->side);
+  if (B->cap) (void)hipStreamSynchronize(B->cap);
+  free_batch(B);
+  delete B;
   return AFMM_OK;
 }

@@ -100,6 +100,13 @@ struct MfmaTables {
 hipError_t launch_gather_mass(const LevelDev& lv, const double* m_src, hipStream_t st);
 hipError_t launch_copy_slots(const int32_t* slots, int64_t n, const double* src, double* dst,
                              hipStream_t st);
+// Batches: forest slot <-> caller arrays.  leafslot/leafhier list every leaf of
+// the forest with its hierarchy; base[h] is the hierarchy's first forest slot.
+hipError_t launch_batch_in(int64_t nleaf, const int32_t* leafslot, const int32_t* leafhier, const int64_t* base,
+                           const double* const* mass, double* m_forest, hipStream_t st);
+hipError_t launch_batch_out(int64_t nleaf, const int32_t* leafslot, const int32_t* leafhier, const int64_t* base,
+                            const double* phi_forest, const double* acc_forest, double* const* phi,
+                            double* const* acc, hipStream_t st);
 hipError_t launch_upward(int p, const LevelDev& lv, const LevelDev& lvc, const CommonDev& cm, hipStream_t st);
 int m2p_columns(int p, bool fp32);
 // MFMA launches over a contiguous range [t0, t0 + n) of tile records; each

@@ -167,6 +167,46 @@ __global__ __launch_bounds__(256) void k_upward(LevelDev lv, LevelDev lvc, Commo
   if (lv.Sc64) lv.Sc64[(size_t)r * KP + a] = sc;
 }
 
+__global__ void k_batch_in(int64_t nleaf, const int32_t* __restrict__ leafslot, const int32_t* __restrict__ leafhier,
+                           const int64_t* __restrict__ base, const double* const* __restrict__ mass,
+                           double* __restrict__ m_forest) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nleaf) return;
+  const int32_t s = leafslot[i], h = leafhier[i];
+  m_forest[s] = mass[h][s - base[h]];
+}
+
+__global__ void k_batch_out(int64_t nleaf, const int32_t* __restrict__ leafslot, const int32_t* __restrict__ leafhier,
+                            const int64_t* __restrict__ base, const double* __restrict__ phi_forest,
+                            const double* __restrict__ acc_forest, double* const* __restrict__ phi,
+                            double* const* __restrict__ acc) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= nleaf) return;
+  const int32_t s = leafslot[i], h = leafhier[i];
+  const int64_t j = s - base[h];
+  phi[h][j] = phi_forest[s];
+  acc[h][3 * j + 0] = acc_forest[3 * (int64_t)s + 0];
+  acc[h][3 * j + 1] = acc_forest[3 * (int64_t)s + 1];
+  acc[h][3 * j + 2] = acc_forest[3 * (int64_t)s + 2];
+}
+
+hipError_t launch_batch_in(int64_t nleaf, const int32_t* leafslot, const int32_t* leafhier, const int64_t* base,
+                           const double* const* mass, double* m_forest, hipStream_t st) {
+  if (nleaf <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_in, dim3((unsigned)((nleaf + 255) / 256)), dim3(256), 0, st, nleaf, leafslot, leafhier,
+                     base, mass, m_forest);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_out(int64_t nleaf, const int32_t* leafslot, const int32_t* leafhier, const int64_t* base,
+                            const double* phi_forest, const double* acc_forest, double* const* phi,
+                            double* const* acc, hipStream_t st) {
+  if (nleaf <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_out, dim3((unsigned)((nleaf + 255) / 256)), dim3(256), 0, st, nleaf, leafslot,
+                     leafhier, base, phi_forest, acc_forest, phi, acc);
+  return hipGetLastError();
+}
+
 hipError_t launch_upward(int p, const LevelDev& lv, const LevelDev& lvc, const CommonDev& cm, hipStream_t st) {
   if (lv.nref == 0) return hipSuccess;
   const int KP = (nmi(p) + 3) & ~3, CB = 256 / KP;

@@ -419,6 +419,8 @@ struct HostTables {
   std::vector<int16_t> m2l_off;     // [steps][64]
   std::vector<int32_t> m2m_start, m2m_list;
   std::vector<double> m2m_w;
+  std::vector<int32_t> m2mT_start, m2mT_list, tapsT;
+  std::vector<double> m2mT_w;
   std::vector<int32_t> m2l_tinfo;   // [NT][2]
 };
 
@@ -530,6 +532,20 @@ static void build_tables(int p, HostTables& H) {
         }
   }
   H.m2m_start[K] = (int32_t)H.m2m_list.size();
+  // the same entries grouped by k, for the transposed M2M of the adjoint pass
+  H.m2mT_start.assign(K + 1, 0);
+  H.m2mT_list.clear();
+  H.m2mT_w.clear();
+  for (int k = 0; k < K; ++k) {
+    H.m2mT_start[k] = (int32_t)H.m2mT_list.size();
+    for (int a = 0; a < K; ++a)
+      for (int j = H.m2m_start[a]; j < H.m2m_start[a + 1]; ++j)
+        if ((H.m2m_list[j] & 4095) == k) {
+          H.m2mT_list.push_back(a | (H.m2m_list[j] >> 12) << 12);
+          H.m2mT_w.push_back(H.m2m_w[j]);
+        }
+  }
+  H.m2mT_start[K] = (int32_t)H.m2mT_list.size();
   H.binom.assign((kPMax + 1) * (kPMax + 1), 0.0);
   for (int n = 0; n <= kPMax; ++n)
     for (int k = 0; k <= n; ++k) H.binom[n * (kPMax + 1) + k] = (double)binom(n, k);
@@ -551,6 +567,21 @@ static void build_tables(int p, HostTables& H) {
       }
     (void)cnt;
   }
+  // transposed taps of each source octant os: groups F = child oF of the
+  // neighbour e of the source's father, d = s - F = os - oF - 2e, |d|_inf >= 2
+  H.tapsT.clear();
+  for (int os = 0; os < 8; ++os)
+    for (int e = 0; e < 27; ++e)
+      for (int oF = 0; oF < 8; ++oF) {
+        int d[3], dm = 0;
+        for (int a = 0; a < 3; ++a) {
+          d[a] = ((os >> a) & 1) - ((oF >> a) & 1) - 2 * ax_of(e, a);
+          dm = std::max(dm, std::abs(d[a]));
+        }
+        if (dm <= 1) continue;
+        const int di = (d[0] + 3) + 7 * (d[1] + 3) + 49 * (d[2] + 3);
+        H.tapsT.push_back(e | (oF << 5) | (di << 8));
+      }
   // MFMA A-operand offsets into the staged D~ rows (sD[o][g], row stride KS, zero slot 8 KS)
   const int KP = (K + 3) & ~3, KS = KP + 1, ZERO = 8 * KS, K1 = nmi(p - 1);
   auto deg = [&](int idx) { return H.mi[4 * idx + 3]; };
@@ -620,7 +651,10 @@ struct afmm_plan {
   CommonDev cm;
   double* m_snap = nullptr;       // adaptive-time-step snapshot of leaf masses (slot space)
   bool snap_valid = false;
+  bool solved = false;            // a solve has run (the adjoint transposes the last one)
   int last_level = AFMM_ALL_LEVELS;
+  int last_fresh = 0;             // levels >= this took their masses from the last call's d_mass
+  bool adj_ready = false;         // adjoint workspace allocated
   std::vector<void*> allocs;
   size_t bytes = 0;
   bool dead = false;              // sticky device error
@@ -915,6 +949,15 @@ static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
     P->cm.m2m_start = d_ms;
     P->cm.m2m_list = d_ml;
     P->cm.m2m_w = d_mw;
+    int32_t *d_ts, *d_tl, *d_tt;
+    double* d_tw;
+    if ((s = upload(P, H.m2mT_start, &d_ts, st)) || (s = upload(P, H.m2mT_list, &d_tl, st)) ||
+        (s = upload(P, H.m2mT_w, &d_tw, st)) || (s = upload(P, H.tapsT, &d_tt, st)))
+      return s;
+    P->cm.m2mT_start = d_ts;
+    P->cm.m2mT_list = d_tl;
+    P->cm.m2mT_w = d_tw;
+    P->cm.tapsT = d_tt;
     P->mt.taps = d_taps;
     P->mt.m2p_off = d_m2p_off;
     P->mt.m2l_off = d_m2l_off;
@@ -1210,7 +1253,9 @@ extern "C" afmm_status afmm_solve(afmm_plan* P, int32_t level, int32_t icount, c
   if (level == AFMM_ALL_LEVELS) {
     if (dev_check(P, hipMemcpyAsync(P->m_snap, d_mass, nb, hipMemcpyDeviceToDevice, st), "snapshot")) return AFMM_E_DEVICE;
     P->snap_valid = true;
+    P->solved = true;
     P->last_level = AFMM_ALL_LEVELS;
+    P->last_fresh = 0;
     return run_solve(P, d_mass, T.lmax - 1, lmin, lmax, d_phi, d_acc, st);
   }
   // Alg. 1: rebuild trees j >= level iff level == levelmin or icount > 1
@@ -1226,7 +1271,9 @@ extern "C" afmm_status afmm_solve(afmm_plan* P, int32_t level, int32_t icount, c
       return AFMM_E_DEVICE;
     P->snap_valid = true;
   }
+  P->solved = true;
   P->last_level = level;
+  P->last_fresh = rebuild ? level : T.lmax + 1;
   return run_solve(P, P->m_snap, level - 1, level, level, d_phi, d_acc, st);
 }
 
@@ -1271,15 +1318,99 @@ extern "C" afmm_status afmm_plan_get_profile(afmm_plan* P, afmm_stage_time* out,
   return AFMM_OK;
 }
 
+// Adjoint workspace: target bars and mass bars on every level, source-copy /
+// multipole bars on the multipole levels 2..lmax-1, local-expansion bars on
+// the FMM levels 3..lmax-1.
+static afmm_status adjoint_workspace(afmm_plan* P) {
+  if (P->adj_ready) return AFMM_OK;
+  const Topology& T = P->topo;
+  const int K = P->K;
+  afmm_status s;
+  for (int l = 0; l <= T.lmax; ++l) {
+    LevelDev& D = P->lv[l];
+    void* q = nullptr;
+    if ((s = dev_alloc(P, &q, (size_t)std::max(D.n, 1) * 4 * sizeof(double)))) return s;
+    D.tbar = (double*)q;
+    if ((s = dev_alloc(P, &q, (size_t)std::max(D.n, 1) * sizeof(double)))) return s;
+    D.mbar = (double*)q;
+    if (l >= 2 && l <= T.lmax - 1 && D.nref > 0) {
+      if ((s = dev_alloc(P, &q, (size_t)D.nref * K * sizeof(double)))) return s;
+      D.sbar = (double*)q;
+    }
+    if (l >= 3 && l <= T.lmax - 1 && D.nref > 0) {
+      if ((s = dev_alloc(P, &q, (size_t)D.nref * K * sizeof(double)))) return s;
+      D.lbar = (double*)q;
+    }
+  }
+  P->adj_ready = true;
+  return AFMM_OK;
+}
+
 extern "C" afmm_status afmm_solve_adjoint(afmm_plan* P, int32_t level, const double* d_phi_bar,
                                           const double* d_acc_bar, double* d_mass_bar, void* hip_stream) {
-  (void)P;
-  (void)level;
-  (void)d_phi_bar;
-  (void)d_acc_bar;
-  (void)d_mass_bar;
-  (void)hip_stream;
-  return fail(AFMM_E_UNSUPPORTED, "adjoint not built yet");
+  if (!P || !d_phi_bar || !d_acc_bar || !d_mass_bar) return fail(AFMM_E_INVALID_ARG, "null argument");
+  if (P->dead) return fail(AFMM_E_DEVICE, "plan is unusable after an earlier device error");
+  const Topology& T = P->topo;
+  if (T.levelmin.size() != 1) return fail(AFMM_E_INVALID_ARG, "batched plan: no adjoint");
+  if (!P->solved) return fail(AFMM_E_ATS_ORDER, "adjoint before any solve");
+  if (level != P->last_level) return fail(AFMM_E_INVALID_ARG, "adjoint level differs from the last solve's level");
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int p = P->opt.p, K = P->K;
+  const int lmin = T.levelmin[0], lmax = T.lmax;
+  const int lo = level == AFMM_ALL_LEVELS ? lmin : level, hi = level == AFMM_ALL_LEVELS ? lmax : level;
+  const int fmax = hi - 1;
+  afmm_status s;
+  if ((s = adjoint_workspace(P))) return s;
+  // 1. unit-form bars of the targets, zeroed accumulators
+  for (int l = 0; l <= lmax; ++l) {
+    const double h = P->opt.boxlen / (double)(1LL << l);
+    const bool tgt = l >= lo && l <= hi;
+    if ((s = dev_check(P, launch_adj_init(P->lv[l], tgt, d_phi_bar, d_acc_bar, P->opt.G / h, P->opt.G / (h * h), st),
+                       "adjoint init")))
+      return s;
+    if ((s = dev_check(P, launch_adj_zero(P->lv[l].sbar, P->lv[l].sbar ? (size_t)P->lv[l].nref * K : 0, st),
+                       "adjoint zero")) ||
+        (s = dev_check(P, launch_adj_zero(P->lv[l].lbar, P->lv[l].lbar ? (size_t)P->lv[l].nref * K : 0, st),
+                       "adjoint zero")))
+      return s;
+  }
+  // 2. leaf fields: P2P^T into the mass bars of every level next to a target
+  //    level, near M2P^T and L2P^T of the target levels
+  const LevelDev empty;
+  for (int l = std::max(1, lo - 1); l <= std::min(lmax, hi + 1); ++l) {
+    const LevelDev& lvp = l + 1 <= lmax ? P->lv[l + 1] : empty;
+    const bool tgt = l >= lo && l <= hi;
+    if ((s = dev_check(P, launch_adj_near(p, P->lv[l - 1], P->lv[l], lvp, tgt, P->t64, P->cm, st), "adjoint near")))
+      return s;
+    if (tgt && l - 1 >= 3 && P->lv[l - 1].lbar &&
+        (s = dev_check(P, launch_adj_l2p(p, P->lv[l - 1], P->lv[l], P->t64, st), "adjoint l2p")))
+      return s;
+  }
+  // 3. intermediate field: M2P^T into the level l-1 sources
+  for (int l = std::max(3, lo); l <= hi; ++l)
+    if ((s = dev_check(P, launch_adj_m2p(p, P->lv[l - 2], P->lv[l - 1], P->lv[l], P->cm.tapsT, P->t64, P->cm, st),
+                       "adjoint m2p")))
+      return s;
+  // 4. L2L^T, finest FMM level first
+  for (int f = fmax; f >= 4; --f)
+    if ((s = dev_check(P, launch_adj_l2l(p, P->lv[f - 1], P->lv[f], P->t64, P->cm, st), "adjoint l2l"))) return s;
+  // 5. M2L^T into the level f-1 sources
+  for (int f = 3; f <= fmax; ++f)
+    if ((s = dev_check(P, launch_adj_m2l(p, P->lv[f - 2], P->lv[f - 1], P->lv[f], P->cm.tapsT, P->t64, P->cm, st),
+                       "adjoint m2l")))
+      return s;
+  // 6. source-copy bars -> multipole bars, M2M^T coarse to fine
+  for (int f = 2; f <= lmax - 1; ++f)
+    if ((s = dev_check(P, launch_adj_down(p, P->lv[f - 1], P->lv[f], f >= 3, P->cm, st), "adjoint down"))) return s;
+  // 7. mass bars to the caller's slots (levels whose masses came from the last call)
+  for (int l = lmin; l <= lmax; ++l) {
+    const bool has_parent = l - 1 >= 2 && l - 1 <= lmax - 1;
+    const bool fresh = l >= P->last_fresh;
+    if ((s = dev_check(P, launch_adj_out(p, P->lv[l - 1], P->lv[l], has_parent, fresh, P->cm, d_mass_bar, st),
+                       "adjoint out")))
+      return s;
+  }
+  return AFMM_OK;
 }
 
 // Append topology S (one hierarchy) to the forest T, offsetting cells, refined

@@ -54,10 +54,11 @@ struct LevelDev {
   float* L32 = nullptr;              // [nref][K] local expansions (FP32 levels)
   void* part = nullptr;              // [nref][32] intermediate-field partials of the leaf children (T of the leaf level)
   void* Lpart = nullptr;             // [nsplit][nref][K] M2L tap-range partial sums (T of the level), if split
-  double* Lbar64 = nullptr;          // adjoint accumulators (same layout as L)
-  float* Lbar32 = nullptr;
-  double* Sbar64 = nullptr;
-  float* Sbar32 = nullptr;
+  // adjoint pass (FP64, allocated by the first adjoint call)
+  double* tbar = nullptr;            // [n][4] unit-form bars of the target leaves (phi, ax, ay, az)
+  double* mbar = nullptr;            // [n] mass bars of the leaves
+  double* sbar = nullptr;            // [nref][K] source-copy bar, then multipole bar
+  double* lbar = nullptr;            // [nref][K] local-expansion bar
 };
 
 template <typename T>
@@ -79,6 +80,10 @@ struct CommonDev {
   const int32_t* m2m_start = nullptr;  // [K+1] M2M entry range of each coefficient a
   const int32_t* m2m_list = nullptr;   // entries: k | parity(a-k) << 12
   const double* m2m_w = nullptr;       // entry weights C(a,k) 4^-|a-k| 2^-|k|
+  const int32_t* m2mT_start = nullptr; // [K+1] the same entries grouped by k (adjoint)
+  const int32_t* m2mT_list = nullptr;  // entries: a | parity(a-k) << 12
+  const double* m2mT_w = nullptr;
+  const int32_t* tapsT = nullptr;      // [8][189] per source octant: e | oF << 5 | d_index << 8 (adjoint)
 };
 
 // Group tiles of the MFMA kernels: NC refined ranks per tile (one parity class,
@@ -107,6 +112,24 @@ hipError_t launch_batch_in(int64_t nleaf, const int32_t* leafslot, const int32_t
 hipError_t launch_batch_out(int64_t nleaf, const int32_t* leafslot, const int32_t* leafhier, const int64_t* base,
                             const double* phi_forest, const double* acc_forest, double* const* phi,
                             double* const* acc, hipStream_t st);
+// Adjoint pass (afmm_adjoint.hip), FP64.
+hipError_t launch_adj_init(const LevelDev& lv, int target, const double* phib, const double* accb, double sp,
+                           double sa, hipStream_t st);
+hipError_t launch_adj_zero(double* p, size_t n, hipStream_t st);
+hipError_t launch_adj_near(int p, const LevelDev& lv1, const LevelDev& lv0, const LevelDev& lvp, int targets_here,
+                           const TablesDev<double>& t64, const CommonDev& cm, hipStream_t st);
+hipError_t launch_adj_l2p(int p, const LevelDev& lv1, const LevelDev& lv0, const TablesDev<double>& t64,
+                          hipStream_t st);
+hipError_t launch_adj_m2p(int p, const LevelDev& lv2, const LevelDev& lv1, const LevelDev& lv0,
+                          const int32_t* tapsT, const TablesDev<double>& t64, const CommonDev& cm, hipStream_t st);
+hipError_t launch_adj_l2l(int p, const LevelDev& lv1, const LevelDev& lv0, const TablesDev<double>& t64,
+                          const CommonDev& cm, hipStream_t st);
+hipError_t launch_adj_m2l(int p, const LevelDev& lv2, const LevelDev& lv1, const LevelDev& lv0,
+                          const int32_t* tapsT, const TablesDev<double>& t64, const CommonDev& cm, hipStream_t st);
+hipError_t launch_adj_down(int p, const LevelDev& lv1, const LevelDev& lv0, int has_parent, const CommonDev& cm,
+                           hipStream_t st);
+hipError_t launch_adj_out(int p, const LevelDev& lv1, const LevelDev& lv0, int has_parent, int rebuilt,
+                          const CommonDev& cm, double* mbar_out, hipStream_t st);
 hipError_t launch_upward(int p, const LevelDev& lv, const LevelDev& lvc, const CommonDev& cm, hipStream_t st);
 int m2p_columns(int p, bool fp32);
 // MFMA launches over a contiguous range [t0, t0 + n) of tile records; each

@@ -31,8 +31,10 @@ METRIC = "cells/sec full FMM solve (φ+accel) at rel. force err ≤1e-4, FP32 vs
 PEAK = {"fp32_mfma": 157.3, "fp64_mfma": 78.6, "fp32_vector": 157.3, "fp64_vector": 78.6, "hbm": 8000.0}
 KERNEL_NAMES = {"near_f32": "k_near<float, P>", "near_f64": "k_near<double, P>",
                 "m2l_f32": "k_m2l_mfma<float, P>", "m2l_f64": "k_m2l_mfma<double, P>",
-                "m2p_f32": "k_m2p<float, P, 64>", "m2p_f64": "k_m2p<double, P, NC>",
-                "l2l": "k_l2l<T, TL, P>", "upward": "k_upward<P>", "gather": "k_gather_mass"}
+                "m2p_f32": "k_m2p<float, P>", "m2p_f64": "k_m2p<double, P>",
+                "l2l": "k_l2l<T, TL, P>", "upward": "k_upward<P>", "gather": "k_gather_mass",
+                "adj_near": "k_adj_near_leaf + k_adj_near_m2p<P>", "adj_m2p": "k_adj_m2p<P>",
+                "adj_m2l": "k_adj_m2l<P>", "adj_tree": "k_adj_l2l/k_adj_down/k_adj_out"}
 MFMA_FAMILIES = ("m2l_f32", "m2l_f64", "m2p_f32", "m2p_f64")
 
 
@@ -50,24 +52,124 @@ def make_workload(name: str):
     raise ValueError(name)
 
 
-def time_form(h, mass_t, p, precision, steps, warmup):
+def time_adjoint(h, mass_t, p, precision, steps):
+    """Forward + adjoint of the full solve (the backward of AFMMSolve)."""
     import torch
     import paper_2607_19489_amd as A
     plan = A.Plan(h, p=p, precision=precision)
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    pb = torch.randn(h.total, dtype=torch.float64, device="cuda", generator=gen)
+    ab = torch.randn(h.total, 3, dtype=torch.float64, device="cuda", generator=gen)
+    mb = torch.zeros(h.total, dtype=torch.float64, device="cuda")
+    phi, acc = plan.solve(mass_t)
+    plan.solve_adjoint(pb, ab, mass_bar=mb)
+    torch.cuda.synchronize()
+    plan.set_profiling(True)
+    plan.get_profile()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.solve(mass_t, phi=phi, acc=acc)
+    torch.cuda.synchronize()
+    t_fwd = (time.perf_counter() - t0) / steps
+    fwd_prof = plan.get_profile()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.solve_adjoint(pb, ab, mass_bar=mb)
+    torch.cuda.synchronize()
+    t_adj = (time.perf_counter() - t0) / steps
+    prof = plan.get_profile()
+    plan.close()
+    adj = {k: v for k, v in prof.items() if k.startswith("adj_")}
+    return {"forward_ms": 1e3 * t_fwd, "adjoint_ms": 1e3 * t_adj, "adjoint_over_forward": t_adj / t_fwd,
+            "adjoint_precision": "f64", "kernels": kernel_table({"kernels": adj, "steps": steps}),
+            "forward_kernels": kernel_table({"kernels": fwd_prof, "steps": steps})}
+
+
+def run_batch(args):
+    """Batched workload: independent hierarchies of uneven size, one graph launch per solve."""
+    import torch
+    import paper_2607_19489_amd as A
+    from synth import configs
+    t0 = time.perf_counter()
+    ws = configs.cfg4(args.members, p=args.p)
+    nleaf = sum(w.hierarchy.nleaves() for w in ws)
+    print(f"[bench] batch of {len(ws)} hierarchies, {nleaf} leaves, generated in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    plans = [A.Plan(w.hierarchy, p=args.p, precision="fp32") for w in ws]
+    batch = A.Batch(plans)
+    for pl in plans:
+        pl.close()
+    masses = [torch.from_numpy(w.mass).cuda() for w in ws]
+    phis = [torch.zeros(w.hierarchy.total, dtype=torch.float64, device="cuda") for w in ws]
+    accs = [torch.zeros(w.hierarchy.total, 3, dtype=torch.float64, device="cuda") for w in ws]
+    for _ in range(args.warmup):
+        batch.solve(masses, phis, accs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        batch.solve(masses, phis, accs)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    # one eager profiled pass for the per-kernel roofline
+    batch.set_profiling(True)
+    batch.get_profile()
+    for _ in range(2):
+        batch.solve(masses, phis, accs)
+    torch.cuda.synchronize()
+    prof = batch.get_profile()
+    batch.set_profiling(False)
+    res = {"kernels": prof, "steps": 2}
+    info = batch.info()
+    base = None
+    if not args.no_cpu:
+        import oracle
+        t_used, done = 0.0, 0
+        for w in ws:
+            o = oracle.Oracle(w.hierarchy, args.p)
+            t1 = time.perf_counter()
+            o.solve_all(w.mass)
+            t_used += time.perf_counter() - t1
+            done += w.hierarchy.nleaves()
+            if t_used > args.cpu_seconds:
+                break
+        base = {"value": done / t_used, "unit": "cells/s", "cores": oracle.num_threads(), "kind": "oracle",
+                "sample": f"full oracle solves of the first hierarchies of the batch ({done} leaves, {t_used:.1f} s)"}
+    line = {
+        "metric": METRIC, "value": nleaf / dt, "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * dt, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": (f"cfg4: batch of {len(ws)} independent hierarchies (base level 4-6, 0-3 mass-refined "
+                                f"levels, Plummer or clumps), {nleaf} leaves, one hipGraph launch per solve"),
+                   "p": args.p, "precision": "FP32 mixed", "leaves": nleaf, "hierarchies": len(ws)},
+        "roofline": roofline(res, "fp32"), "cpu_baseline": base,
+        "algorithmic_flops_per_step": info["flops_m2l"] + info["flops_m2p"] + info["flops_p2p"] + info["flops_updown"],
+        "kernels_fp32": kernel_table(res),
+    }
+    print(json.dumps(line), flush=True)
+
+
+def time_form(h, mass_t, p, precision, steps, warmup, serial=False):
+    """Timed solves (no instrumentation), then the same number of profiled solves:
+    the profiled pass runs serially with hipEvents around every launch."""
+    import torch
+    import paper_2607_19489_amd as A
+    plan = A.Plan(h, p=p, precision=precision, serial=serial)
     info = plan.info()
     phi = torch.zeros(h.total, dtype=torch.float64, device="cuda")
     acc = torch.zeros(h.total, 3, dtype=torch.float64, device="cuda")
     for _ in range(warmup):
         plan.solve(mass_t, phi=phi, acc=acc)
     torch.cuda.synchronize()
-    plan.set_profiling(True)
-    plan.get_profile()  # reset
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         plan.solve(mass_t, phi=phi, acc=acc)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    plan.set_profiling(True)
+    plan.get_profile()  # reset
+    for _ in range(steps):
+        plan.solve(mass_t, phi=phi, acc=acc)
+    torch.cuda.synchronize()
     prof = plan.get_profile()
     plan.set_profiling(False)
     out = {"ms_per_step": 1e3 * dt / steps, "value": info["nleaves"] * steps / dt, "info": info,
@@ -164,7 +266,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg5"])
+    ap.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5"])
+    ap.add_argument("--p", type=int, default=4, help="expansion order of the batched workload (cfg4)")
+    ap.add_argument("--members", type=int, default=256, help="hierarchies in the batched workload (cfg4)")
+    ap.add_argument("--adjoint", action="store_true", help="also time the adjoint pass (default for cfg5)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-form run")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -177,6 +282,9 @@ def main():
 
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "cfg4":
+        run_batch(args)
+        return
     w, desc = make_workload(args.workload)
     h, m = w.hierarchy, w.mass
     mass_t = torch.from_numpy(m).cuda()
@@ -184,12 +292,20 @@ def main():
 
     r32, phi32, acc32 = time_form(h, mass_t, w.p, "fp32", args.steps, args.warmup)
     print(f"[bench] fp32 form: {r32['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+    r32s, _, _ = time_form(h, mass_t, w.p, "fp32", args.steps, 1, serial=True)
+    print(f"[bench] fp32 form, serial launches: {r32s['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     outputs = {"fp32": (phi32, acc32)}
     r64 = None
     if not args.no_fp64:
         r64, phi64, acc64 = time_form(h, mass_t, w.p, "fp64", max(args.steps // 2, 1), 1)
         outputs["fp64"] = (phi64, acc64)
         print(f"[bench] fp64 form: {r64['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+
+    adj = None
+    if args.adjoint or args.workload == "cfg5":
+        adj = time_adjoint(h, mass_t, w.p, "fp32", max(args.steps // 4, 2))
+        print(f"[bench] adjoint {adj['adjoint_ms']:.3f} ms vs forward {adj['forward_ms']:.3f} ms",
+              file=sys.stderr, flush=True)
 
     base, errs = (None, None)
     if not args.no_cpu:
@@ -218,11 +334,14 @@ def main():
                                                 "ms_per_step": r64["ms_per_step"], "dtype": "f64",
                                                 "roofline": roofline(r64, "fp64")},
         "fp32_over_fp64": None if r64 is None else r32["value"] / r64["value"],
+        "serial_ms_per_step": r32s["ms_per_step"],
+        "profiled_ms_per_step": sum(v["ms"] for v in r32["kernels"].values()) / r32["steps"],
         "error_vs_oracle_sample": errs,
         "algorithmic_flops_per_step": info["flops_m2l"] + info["flops_m2p"] + info["flops_p2p"]
         + info["flops_updown"],
         "kernels_fp32": kernel_table(r32),
         "kernels_fp64": None if r64 is None else kernel_table(r64),
+        "adjoint": adj,
     }
     print(json.dumps(line), flush=True)
 

@@ -48,6 +48,9 @@ typedef int32_t afmm_status;
                                 f <= fp64_levels and the per-cell output in FP64 */
 
 #define AFMM_CHECK_INPUT 1u  /* scan masses for NaN/Inf before a solve (one host sync) */
+#define AFMM_SERIAL 2u       /* run every launch of a solve on the caller's stream (by default the
+                                M2L/L2L chain runs on an internal second stream, concurrently with
+                                the intermediate-field M2P); results are identical either way */
 
 #define AFMM_ALL_LEVELS (-1) /* synchronous solve: all trees rebuilt, every leaf evaluated */
 
@@ -56,7 +59,7 @@ typedef struct afmm_options {
   int32_t precision;         /* AFMM_FP64 or AFMM_FP32_MIXED */
   double G;                  /* gravitational constant */
   double boxlen;             /* box side */
-  uint32_t flags;            /* AFMM_CHECK_INPUT */
+  uint32_t flags;            /* AFMM_CHECK_INPUT | AFMM_SERIAL */
   int32_t fp64_levels;       /* mixed form: FMM levels <= this stay FP64 (default 4) */
   int32_t tap_split;         /* M2L blocks per tile: the 189 source offsets of a tile are split
                                 over this many blocks and their partial sums reduced in a fixed
@@ -186,7 +189,8 @@ afmm_status afmm_hierarchy_check(const afmm_hierarchy* h, const afmm_options* op
 /*
  * Per-launch timing (instrumentation, no effect on results).  While enabled,
  * every kernel launch of a solve is bracketed by hipEvents recorded on the
- * solve's stream.  afmm_plan_get_profile synchronises on those events, sums
+ * solve's stream, and the solve runs serially (as with AFMM_SERIAL) so that
+ * each interval times one launch alone.  afmm_plan_get_profile synchronises on those events, sums
  * them per kernel family and resets the records; `out` receives up to `cap`
  * families and *n_out their number.  flops/bytes are the algorithmic work of
  * the timed launches (useful terms only, as in afmm_plan_info).
@@ -200,6 +204,10 @@ typedef struct afmm_stage_time {
 } afmm_stage_time;
 afmm_status afmm_plan_set_profiling(afmm_plan* plan, int32_t enable);
 afmm_status afmm_plan_get_profile(afmm_plan* plan, afmm_stage_time* out, int32_t cap, int32_t* n_out);
+/* The same for a batch.  While profiling is enabled, afmm_batch_solve runs the
+   captured launches eagerly (not as a graph) so that each can be timed. */
+afmm_status afmm_batch_set_profiling(afmm_batch* batch, int32_t enable);
+afmm_status afmm_batch_get_profile(afmm_batch* batch, afmm_stage_time* out, int32_t cap, int32_t* n_out);
 
 const char* afmm_status_string(afmm_status s);
 const char* afmm_last_error(void);

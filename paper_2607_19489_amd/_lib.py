@@ -14,6 +14,7 @@ AFMM_OK = 0
 AFMM_FP64 = 0
 AFMM_FP32_MIXED = 1
 AFMM_CHECK_INPUT = 1
+AFMM_SERIAL = 2
 AFMM_ALL_LEVELS = -1
 
 STATUS = {
@@ -27,7 +28,7 @@ SYMBOLS = [
     "afmm_options_default", "afmm_plan_create", "afmm_plan_destroy", "afmm_plan_get_info", "afmm_solve",
     "afmm_solve_adjoint", "afmm_batch_create", "afmm_batch_solve", "afmm_batch_get_info",
     "afmm_batch_destroy", "afmm_hierarchy_check", "afmm_status_string", "afmm_last_error",
-    "afmm_plan_set_profiling", "afmm_plan_get_profile",
+    "afmm_plan_set_profiling", "afmm_plan_get_profile", "afmm_batch_set_profiling", "afmm_batch_get_profile",
 ]
 
 
@@ -98,6 +99,8 @@ def lib():
     L.afmm_hierarchy_check.argtypes = [C.POINTER(HierarchyC), C.POINTER(Options), C.POINTER(PlanInfo)]
     L.afmm_plan_set_profiling.argtypes = [vp, C.c_int32]
     L.afmm_plan_get_profile.argtypes = [vp, C.POINTER(StageTime), C.c_int32, C.POINTER(C.c_int32)]
+    L.afmm_batch_set_profiling.argtypes = [vp, C.c_int32]
+    L.afmm_batch_get_profile.argtypes = [vp, C.POINTER(StageTime), C.c_int32, C.POINTER(C.c_int32)]
     L.afmm_status_string.argtypes = [C.c_int32]
     L.afmm_status_string.restype = C.c_char_p
     L.afmm_last_error.argtypes = []
@@ -105,7 +108,7 @@ def lib():
     for name in ("afmm_plan_create", "afmm_plan_destroy", "afmm_plan_get_info", "afmm_solve",
                  "afmm_solve_adjoint", "afmm_batch_create", "afmm_batch_solve", "afmm_batch_get_info",
                  "afmm_batch_destroy", "afmm_hierarchy_check", "afmm_plan_set_profiling",
-                 "afmm_plan_get_profile"):
+                 "afmm_plan_get_profile", "afmm_batch_set_profiling", "afmm_batch_get_profile"):
         getattr(L, name).restype = C.c_int32
     _lib = L
     return L

@@ -11,7 +11,7 @@ from typing import Optional, Sequence
 import numpy as np
 import torch
 
-from ._lib import (AFMM_ALL_LEVELS, AFMM_CHECK_INPUT, AFMM_FP32_MIXED, AFMM_FP64, HierarchyC, Options,
+from ._lib import (AFMM_ALL_LEVELS, AFMM_CHECK_INPUT, AFMM_FP32_MIXED, AFMM_FP64, AFMM_SERIAL, HierarchyC, Options,
                    PlanInfo, StageTime, check, lib)
 
 PRECISIONS = {"fp64": AFMM_FP64, "fp32": AFMM_FP32_MIXED, "mixed": AFMM_FP32_MIXED}
@@ -42,7 +42,7 @@ def _hier_struct(levelmin, levelmax, ncell, ijk, ref):
 
 def make_options(p: int = 4, precision: str = "fp64", G: float = 1.0, boxlen: float = 1.0,
                  fp64_levels: int = 4, check_input: bool = False, max_device_bytes: int = 0,
-                 tap_split: int = 0) -> Options:
+                 tap_split: int = 0, serial: bool = False) -> Options:
     o = Options()
     lib().afmm_options_default(C.byref(o))
     o.p = p
@@ -51,7 +51,7 @@ def make_options(p: int = 4, precision: str = "fp64", G: float = 1.0, boxlen: fl
     o.boxlen = boxlen
     o.fp64_levels = fp64_levels
     o.tap_split = tap_split
-    o.flags = AFMM_CHECK_INPUT if check_input else 0
+    o.flags = (AFMM_CHECK_INPUT if check_input else 0) | (AFMM_SERIAL if serial else 0)
     o.max_device_bytes = max_device_bytes
     return o
 
@@ -66,19 +66,29 @@ def hierarchy_check(h, p: int = 4, precision: str = "fp64") -> dict:
     return info.as_dict()
 
 
+def _profile(fn, handle, what) -> dict:
+    buf = (StageTime * 16)()
+    n = C.c_int32()
+    check(fn(handle, buf, 16, C.byref(n)), what)
+    return {buf[i].name.decode(): {"launches": buf[i].launches, "ms": buf[i].ms, "flops": buf[i].flops,
+                                   "bytes": buf[i].bytes} for i in range(min(n.value, 16))}
+
+
 class Plan:
     """A solver plan for one AMR hierarchy (afmm_plan)."""
 
     def __init__(self, h, p: int = 4, precision: str = "fp64", G: float = 1.0,
                  boxlen: Optional[float] = None, fp64_levels: int = 4, check_input: bool = False,
-                 max_device_bytes: int = 0, tap_split: int = 0, stream: Optional[torch.cuda.Stream] = None):
+                 max_device_bytes: int = 0, tap_split: int = 0, serial: bool = False,
+                 stream: Optional[torch.cuda.Stream] = None):
         self._ptr = C.c_void_p()
         arrs = _hierarchy_arrays(h)
         self.levelmin, self.levelmax, self.ncell = arrs[0], arrs[1], arrs[2]
         self.N = int(self.ncell.sum())
         hc = _hier_struct(*arrs)
         bl = float(boxlen if boxlen is not None else getattr(h, "boxlen", 1.0))
-        self.options = make_options(p, precision, G, bl, fp64_levels, check_input, max_device_bytes, tap_split)
+        self.options = make_options(p, precision, G, bl, fp64_levels, check_input, max_device_bytes, tap_split,
+                                    serial)
         check(lib().afmm_plan_create(C.byref(hc), C.byref(self.options), _stream_handle(stream),
                                      C.byref(self._ptr)), "afmm_plan_create")
         self.p = p
@@ -109,11 +119,7 @@ class Plan:
 
     def get_profile(self) -> dict:
         """Per kernel family: launches, summed event ms, algorithmic flops and bytes (resets)."""
-        buf = (StageTime * 16)()
-        n = C.c_int32()
-        check(lib().afmm_plan_get_profile(self._ptr, buf, 16, C.byref(n)), "afmm_plan_get_profile")
-        return {buf[i].name.decode(): {"launches": buf[i].launches, "ms": buf[i].ms, "flops": buf[i].flops,
-                                       "bytes": buf[i].bytes} for i in range(min(n.value, 16))}
+        return _profile(lib().afmm_plan_get_profile, self._ptr, "afmm_plan_get_profile")
 
     def _check_tensor(self, t: torch.Tensor, shape, name: str):
         if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
@@ -183,6 +189,13 @@ class Batch:
         info = PlanInfo()
         check(lib().afmm_batch_get_info(self._ptr, C.byref(info)), "afmm_batch_get_info")
         return info.as_dict()
+
+    def set_profiling(self, enable: bool):
+        """While enabled, solves run eagerly with per-launch events (no graph)."""
+        check(lib().afmm_batch_set_profiling(self._ptr, int(bool(enable))), "afmm_batch_set_profiling")
+
+    def get_profile(self) -> dict:
+        return _profile(lib().afmm_batch_get_profile, self._ptr, "afmm_batch_get_profile")
 
     def solve(self, masses: Sequence[torch.Tensor], phis: Optional[Sequence[torch.Tensor]] = None,
               accs: Optional[Sequence[torch.Tensor]] = None, stream: Optional[torch.cuda.Stream] = None):

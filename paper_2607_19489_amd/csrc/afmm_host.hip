@@ -749,7 +749,7 @@ afmm_status check_options(const afmm_options* o) {
   if (o->p < 1 || o->p > kPMax) return fail(AFMM_E_UNSUPPORTED, "p must be in 1..8");
   if (o->precision != AFMM_FP64 && o->precision != AFMM_FP32_MIXED)
     return fail(AFMM_E_UNSUPPORTED, "unknown precision");
-  if (o->flags & ~AFMM_CHECK_INPUT) return fail(AFMM_E_UNSUPPORTED, "unknown flag");
+  if (o->flags & ~(AFMM_CHECK_INPUT | AFMM_SERIAL)) return fail(AFMM_E_UNSUPPORTED, "unknown flag");
   if (!(o->boxlen > 0) || !std::isfinite(o->boxlen)) return fail(AFMM_E_INVALID_ARG, "boxlen must be > 0");
   if (!std::isfinite(o->G)) return fail(AFMM_E_INVALID_ARG, "G must be finite");
   if (o->tap_split < 0 || o->tap_split > 21) return fail(AFMM_E_UNSUPPORTED, "tap_split must be in 0..21");
@@ -1096,9 +1096,11 @@ static afmm_status dev_check(afmm_plan* P, hipError_t e, const char* what) {
 }
 
 // ---- per-launch event timing ----
-enum { kGather = 0, kUpward, kM2L64, kM2L32, kL2L, kM2P64, kM2P32, kLeaf64, kLeaf32, kNumKinds };
+enum { kGather = 0, kUpward, kM2L64, kM2L32, kL2L, kM2P64, kM2P32, kLeaf64, kLeaf32,
+       kAdjNear, kAdjM2P, kAdjM2L, kAdjTree, kNumKinds };
 static const char* kKindName[kNumKinds] = {"gather", "upward", "m2l_f64", "m2l_f32", "l2l",
-                                           "m2p_f64", "m2p_f32", "near_f64", "near_f32"};
+                                           "m2p_f64", "m2p_f32", "near_f64", "near_f32",
+                                           "adj_near", "adj_m2p", "adj_m2l", "adj_tree"};
 
 static hipEvent_t pool_get(afmm_plan* P) {
   if (!P->event_pool.empty()) {
@@ -1147,10 +1149,12 @@ static afmm_status run_solve(afmm_plan* P, const double* msrc, int fmax, int lo,
       return s;
     prof_end(P, a, st, kUpward, f);
   }
-  // fork: the downward chain (M2L taps, then L2L) runs on the side stream
-  hipStream_t sd = P->side;
-  if ((s = dev_check(P, hipEventRecord(P->ev_fork, st), "fork")) ||
-      (s = dev_check(P, hipStreamWaitEvent(sd, P->ev_fork, 0), "fork")))
+  // fork: the downward chain (M2L taps, then L2L) runs on the side stream,
+  // unless the plan is serial (or profiled: events then time one launch at a time)
+  const bool serial = (P->opt.flags & AFMM_SERIAL) || P->profiling;
+  hipStream_t sd = serial ? st : P->side;
+  if (!serial && ((s = dev_check(P, hipEventRecord(P->ev_fork, st), "fork")) ||
+                  (s = dev_check(P, hipStreamWaitEvent(sd, P->ev_fork, 0), "fork"))))
     return s;
   // M2L tap sums of FMM levels 3..fmax: one launch per precision
   for (int pr = 0; pr < 2; ++pr) {
@@ -1186,7 +1190,7 @@ static afmm_status run_solve(afmm_plan* P, const double* msrc, int fmax, int lo,
       return s;
     prof_end(P, a, sd, kL2L, f);
   }
-  if ((s = dev_check(P, hipEventRecord(P->ev_join, sd), "join"))) return s;
+  if (!serial && (s = dev_check(P, hipEventRecord(P->ev_join, sd), "join"))) return s;
   // intermediate field (M2P) of the leaf levels lo..hi: one launch per precision
   for (int pr = 0; pr < 2; ++pr) {
     int t0 = -1, n = 0;
@@ -1207,7 +1211,7 @@ static afmm_status run_solve(afmm_plan* P, const double* msrc, int fmax, int lo,
     prof_end(P, a, st, pr ? kM2P32 : kM2P64, -1);
   }
   // join: the far field needs the local expansions
-  if ((s = dev_check(P, hipStreamWaitEvent(st, P->ev_join, 0), "join"))) return s;
+  if (!serial && (s = dev_check(P, hipStreamWaitEvent(st, P->ev_join, 0), "join"))) return s;
   // far, near and nearest fields + output, per leaf level
   for (int l = std::max(lo, 1); l <= hi; ++l) {
     const int ng = (int)T.leafgrp[l].size();
@@ -1302,6 +1306,7 @@ extern "C" afmm_status afmm_plan_get_profile(afmm_plan* P, afmm_stage_time* out,
       case kL2L: t.flops += W.l2l_flops[r.level]; t.bytes += W.l2l_bytes[r.level]; break;
       case kM2P64: case kM2P32: t.flops += r.flops; t.bytes += r.bytes; break;
       case kLeaf64: case kLeaf32: t.flops += W.leaf_flops[r.level]; t.bytes += W.leaf_bytes[r.level]; break;
+      case kAdjNear: case kAdjM2P: case kAdjM2L: case kAdjTree: t.flops += r.flops; t.bytes += r.bytes; break;
       default: t.bytes += 12.0 * P->lv[r.level].n; break;
     }
     P->event_pool.push_back(r.a);
@@ -1361,7 +1366,9 @@ extern "C" afmm_status afmm_solve_adjoint(afmm_plan* P, int32_t level, const dou
   const int fmax = hi - 1;
   afmm_status s;
   if ((s = adjoint_workspace(P))) return s;
+  const WorkCounts& W = P->work;
   // 1. unit-form bars of the targets, zeroed accumulators
+  hipEvent_t ev = prof_begin(P, st);
   for (int l = 0; l <= lmax; ++l) {
     const double h = P->opt.boxlen / (double)(1LL << l);
     const bool tgt = l >= lo && l <= hi;
@@ -1374,9 +1381,15 @@ extern "C" afmm_status afmm_solve_adjoint(afmm_plan* P, int32_t level, const dou
                        "adjoint zero")))
       return s;
   }
+  prof_end(P, ev, st, kAdjTree, -1);
   // 2. leaf fields: P2P^T into the mass bars of every level next to a target
   //    level, near M2P^T and L2P^T of the target levels
   const LevelDev empty;
+  ev = prof_begin(P, st);
+  for (int l = lo; l <= hi; ++l) {
+    P->pending_flops += W.leaf_flops[l];
+    P->pending_bytes += W.leaf_bytes[l];
+  }
   for (int l = std::max(1, lo - 1); l <= std::min(lmax, hi + 1); ++l) {
     const LevelDev& lvp = l + 1 <= lmax ? P->lv[l + 1] : empty;
     const bool tgt = l >= lo && l <= hi;
@@ -1386,19 +1399,33 @@ extern "C" afmm_status afmm_solve_adjoint(afmm_plan* P, int32_t level, const dou
         (s = dev_check(P, launch_adj_l2p(p, P->lv[l - 1], P->lv[l], P->t64, st), "adjoint l2p")))
       return s;
   }
+  prof_end(P, ev, st, kAdjNear, -1);
   // 3. intermediate field: M2P^T into the level l-1 sources
-  for (int l = std::max(3, lo); l <= hi; ++l)
+  ev = prof_begin(P, st);
+  for (int l = std::max(3, lo); l <= hi; ++l) {
     if ((s = dev_check(P, launch_adj_m2p(p, P->lv[l - 2], P->lv[l - 1], P->lv[l], P->cm.tapsT, P->t64, P->cm, st),
                        "adjoint m2p")))
       return s;
+    P->pending_flops += W.m2p_flops[l];
+    P->pending_bytes += W.m2p_bytes[l];
+  }
+  prof_end(P, ev, st, kAdjM2P, -1);
   // 4. L2L^T, finest FMM level first
+  ev = prof_begin(P, st);
   for (int f = fmax; f >= 4; --f)
     if ((s = dev_check(P, launch_adj_l2l(p, P->lv[f - 1], P->lv[f], P->t64, P->cm, st), "adjoint l2l"))) return s;
+  prof_end(P, ev, st, kAdjTree, -1);
   // 5. M2L^T into the level f-1 sources
-  for (int f = 3; f <= fmax; ++f)
+  ev = prof_begin(P, st);
+  for (int f = 3; f <= fmax; ++f) {
     if ((s = dev_check(P, launch_adj_m2l(p, P->lv[f - 2], P->lv[f - 1], P->lv[f], P->cm.tapsT, P->t64, P->cm, st),
                        "adjoint m2l")))
       return s;
+    P->pending_flops += W.m2l_flops[f];
+    P->pending_bytes += W.m2l_bytes[f];
+  }
+  prof_end(P, ev, st, kAdjM2L, -1);
+  ev = prof_begin(P, st);
   // 6. source-copy bars -> multipole bars, M2M^T coarse to fine
   for (int f = 2; f <= lmax - 1; ++f)
     if ((s = dev_check(P, launch_adj_down(p, P->lv[f - 1], P->lv[f], f >= 3, P->cm, st), "adjoint down"))) return s;
@@ -1410,6 +1437,7 @@ extern "C" afmm_status afmm_solve_adjoint(afmm_plan* P, int32_t level, const dou
                        "adjoint out")))
       return s;
   }
+  prof_end(P, ev, st, kAdjTree, -1);
   return AFMM_OK;
 }
 
@@ -1560,7 +1588,28 @@ extern "C" afmm_status afmm_batch_solve(afmm_batch* B, const double* const* d_ma
                                              hipMemcpyHostToDevice, st),
                      "batch pointer table")))
     return s;
-  return dev_check(B->plan, hipGraphLaunch(B->exec, st), "batch graph launch");
+  afmm_plan* P = B->plan;
+  if (!P->profiling) return dev_check(P, hipGraphLaunch(B->exec, st), "batch graph launch");
+  // profiled solves run the same launches eagerly, each bracketed by events
+  const Topology& T = P->topo;
+  if ((s = dev_check(P, launch_batch_in(B->nleaf, B->d_leafslot, B->d_leafhier, B->d_base,
+                                        (const double* const*)B->d_ptrs, B->d_mass, st),
+                     "batch gather")) ||
+      (s = run_solve(P, B->d_mass, T.lmax - 1, T.lmin_all, T.lmax, B->d_phi, B->d_acc, st)))
+    return s;
+  return dev_check(P, launch_batch_out(B->nleaf, B->d_leafslot, B->d_leafhier, B->d_base, B->d_phi, B->d_acc,
+                                       (double* const*)(B->d_ptrs + n), (double* const*)(B->d_ptrs + 2 * n), st),
+                   "batch scatter");
+}
+
+extern "C" afmm_status afmm_batch_set_profiling(afmm_batch* B, int32_t enable) {
+  if (!B) return fail(AFMM_E_INVALID_ARG, "null batch");
+  return afmm_plan_set_profiling(B->plan, enable);
+}
+
+extern "C" afmm_status afmm_batch_get_profile(afmm_batch* B, afmm_stage_time* out, int32_t cap, int32_t* n_out) {
+  if (!B) return fail(AFMM_E_INVALID_ARG, "null batch");
+  return afmm_plan_get_profile(B->plan, out, cap, n_out);
 }
 
 extern "C" afmm_status afmm_batch_get_info(const afmm_batch* B, afmm_plan_info* out) {

@@ -97,6 +97,17 @@ def test_deterministic_and_untouched_entries():
     leaf = T.from_numpy(h.leaf_mask()).cuda()
     assert T.equal(phi1[leaf], phi2[leaf]) and T.equal(acc1[leaf], acc2[leaf])
     assert bool((phi1[~leaf] == 7.0).all()) and bool((acc1[~leaf] == 7.0).all())
+    # serial launches and profiled solves run the same arithmetic
+    plan_s = A.Plan(h, p=6, precision="fp32", serial=True)
+    phi3, acc3 = plan_s.solve(mt)
+    plan.set_profiling(True)
+    phi4, acc4 = plan.solve(mt)
+    T.cuda.synchronize()
+    prof = plan.get_profile()
+    assert T.equal(phi3[leaf], phi2[leaf]) and T.equal(acc3[leaf], acc2[leaf])
+    assert T.equal(phi4[leaf], phi2[leaf]) and T.equal(acc4[leaf], acc2[leaf])
+    assert prof["upward"]["launches"] >= 1 and sum(v["ms"] for v in prof.values()) > 0
+    assert any(k.startswith("near_") for k in prof) and any(k.startswith("m2p_") for k in prof)
 
 
 def test_ats_sequence_matches_oracle():

@@ -901,13 +901,12 @@ static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
     // source copies: FP32 where an FP32 kernel reads this level (M2L of f = l+1 or
     // M2P of l+1 when l >= f64; near-field M2P of l when l > f64+1), FP64 where an
     // FP64 kernel does (l <= f64 + 1)
-    const int KP = (K + 3) & ~3;
     if (mixed && l >= f64) {
-      if ((s = dev_alloc(P, &p, (size_t)D.nref * KP * sizeof(float)))) return s;
+      if ((s = dev_alloc(P, &p, (size_t)D.nref * src_row(P->opt.p, 4) * sizeof(float)))) return s;
       D.S32 = (float*)p;
     }
     if (!mixed || l <= f64 + 1) {
-      if ((s = dev_alloc(P, &p, (size_t)D.nref * KP * sizeof(double)))) return s;
+      if ((s = dev_alloc(P, &p, (size_t)D.nref * src_row(P->opt.p, 8) * sizeof(double)))) return s;
       D.Sc64 = (double*)p;
     }
     if (l <= f64) {

@@ -34,6 +34,17 @@ __host__ __device__ constexpr int mi_index(int a, int b, int c) {
   return (a + b + c) * (a + b + c + 1) * (a + b + c + 2) / 6 + (b + c) * (b + c + 1) / 2 + c;
 }
 
+// Layout of the scaled source copies (S32 / Sc64).  The MFMA kernels read the
+// B operand straight into registers: lane group g (lane >> 4) of a 16x16x4
+// step kb holds coefficient k = 4 kb + g, so coefficient k is stored at
+// (k & 3) * STP + (k >> 2) and each lane group loads one contiguous run of STP
+// values.  STP = ceil(K/4) rounded up to a 16-byte multiple; unused slots are 0.
+__host__ __device__ constexpr int src_stp(int p, int bytes) {
+  return (((nmi(p) + 3) / 4) + (16 / bytes) - 1) / (16 / bytes) * (16 / bytes);
+}
+__host__ __device__ constexpr int src_row(int p, int bytes) { return 4 * src_stp(p, bytes); }
+__host__ __device__ constexpr int src_pos(int k, int stp) { return (k & 3) * stp + (k >> 2); }
+
 // Per-level device view.  Level l holds the children of the refined cells of
 // level l - 1 in Morton order, so cell index c has father refined rank c >> 3
 // and octant c & 7 (o = ox + 2 oy + 4 oz), and refined rank r owns children
@@ -47,9 +58,9 @@ struct LevelDev {
   const int32_t* nbr = nullptr;      // [nref][27] neighbour cell index at this level, -1 outside box
   double* mass = nullptr;            // [n] leaf masses of this solve (0 for refined cells)
   double* S64 = nullptr;             // [nref][K] multipoles (FP64), used by the upward pass
-  float* S32 = nullptr;              // [nref][KP] source copy (-1)^|a|/a! 2^|a| S~_a, FP32 (mixed form);
-                                     // rows padded with zeros to KP = K rounded up to a multiple of 4
-  double* Sc64 = nullptr;            // [nref][KP] same source copy in FP64
+  float* S32 = nullptr;              // [nref][src_row(p, 4)] source copy (-1)^|a|/a! 2^|a| S~_a, FP32
+                                     // (mixed form), in the lane-group layout above
+  double* Sc64 = nullptr;            // [nref][src_row(p, 8)] same source copy in FP64
   double* L64 = nullptr;             // [nref][K] local expansions (FP64 levels)
   float* L32 = nullptr;              // [nref][K] local expansions (FP32 levels)
   void* part = nullptr;              // [nref][32] intermediate-field partials of the leaf children (T of the leaf level)

@@ -68,15 +68,16 @@ __device__ inline void m2p_row(const T* __restrict__ D, const T* __restrict__ S,
                                const int16_t* __restrict__ up, T* out) {
   constexpr int K = nmi(P);
   constexpr int K1 = nmi(P - 1);
+  constexpr int STP = src_stp(P, (int)sizeof(T));
   T phi = 0, ax = 0, ay = 0, az = 0;
   for (int a = 0; a < K1; ++a) {
-    const T w = cf[a] * S[a];
+    const T w = cf[a] * S[src_pos(a, STP)];
     phi += w * D[a];
     ax += w * D[up[3 * a + 0]];
     ay += w * D[up[3 * a + 1]];
     az += w * D[up[3 * a + 2]];
   }
-  for (int a = K1; a < K; ++a) phi += cf[a] * S[a] * D[a];
+  for (int a = K1; a < K; ++a) phi += cf[a] * S[src_pos(a, STP)] * D[a];
   out[0] += phi;
   out[1] -= ax;
   out[2] -= ay;
@@ -112,9 +113,13 @@ hipError_t launch_gather_mass(const LevelDev& lv, const double* m_src, hipStream
 // (cm.m2m_list: for each a, its (k, parity) entries; cm.m2m_w the weights).
 // Thread = (cell, coefficient); a block holds CB cells and first stages the
 // 8 signed child sums Y of each in LDS.
+// The source copies are written in the lane-group layout; thread a >= K of a
+// cell writes the zero of padding slot src_pos(a).
 template <int P>
 __global__ __launch_bounds__(256) void k_upward(LevelDev lv, LevelDev lvc, CommonDev cm) {
-  constexpr int K = nmi(P), KP = (K + 3) & ~3;
+  constexpr int K = nmi(P);
+  constexpr int STP32 = src_stp(P, 4), STP64 = src_stp(P, 8);
+  constexpr int KP = 4 * STP32;               // threads per cell (STP32 >= STP64)
   constexpr int CB = 256 / KP;                // cells per block
   __shared__ double sY[CB][8][K];
   const int t = threadIdx.x;
@@ -150,8 +155,8 @@ __global__ __launch_bounds__(256) void k_upward(LevelDev lv, LevelDev lvc, Commo
   const int r = r0 + c;
   if (c >= CB || r >= lv.nref) return;
   if (a >= K) {  // zero padding of the source copies
-    if (lv.S32) lv.S32[(size_t)r * KP + a] = 0.f;
-    if (lv.Sc64) lv.Sc64[(size_t)r * KP + a] = 0.0;
+    if (lv.S32) lv.S32[(size_t)r * 4 * STP32 + src_pos(a, STP32)] = 0.f;
+    if (lv.Sc64 && a < 4 * STP64) lv.Sc64[(size_t)r * 4 * STP64 + src_pos(a, STP64)] = 0.0;
     return;
   }
   const int b0 = cm.m2m_start[a], b1 = cm.m2m_start[a + 1];
@@ -163,8 +168,8 @@ __global__ __launch_bounds__(256) void k_upward(LevelDev lv, LevelDev lvc, Commo
   lv.S64[(size_t)r * K + a] = acc;
   // source copies for the translation kernels carry the factor (-1)^|a|/a! 2^|a|
   const double sc = acc * cm.cfac2[a];
-  if (lv.S32) lv.S32[(size_t)r * KP + a] = (float)sc;
-  if (lv.Sc64) lv.Sc64[(size_t)r * KP + a] = sc;
+  if (lv.S32) lv.S32[(size_t)r * 4 * STP32 + src_pos(a, STP32)] = (float)sc;
+  if (lv.Sc64) lv.Sc64[(size_t)r * 4 * STP64 + src_pos(a, STP64)] = sc;
 }
 
 __global__ void k_batch_in(int64_t nleaf, const int32_t* __restrict__ leafslot, const int32_t* __restrict__ leafhier,
@@ -209,7 +214,7 @@ hipError_t launch_batch_out(int64_t nleaf, const int32_t* leafslot, const int32_
 
 hipError_t launch_upward(int p, const LevelDev& lv, const LevelDev& lvc, const CommonDev& cm, hipStream_t st) {
   if (lv.nref == 0) return hipSuccess;
-  const int KP = (nmi(p) + 3) & ~3, CB = 256 / KP;
+  const int KP = src_row(p, 4), CB = 256 / KP;
   const dim3 grid((lv.nref + CB - 1) / CB), block(kBlock);
   switch (p) {
 #define AFMM_UP(PP) \
@@ -263,29 +268,30 @@ __global__ __launch_bounds__(kBlock) void k_l2l(const int32_t* __restrict__ grp,
 }
 
 // ---------------------------------------------------------------------------
-// Shared tap pipeline of the MFMA kernels.  A block owns NC groups of one
-// parity class at one level.  For each of the 189 taps it stages, in LDS,
-//   sB[n][k]  = c_k 2^|k| S~_k of the tap's source of group n (monopole for a
-//               leaf source, 0 when there is none), k < K (zero padded to KP)
-//   sD[o][g]  = D~_g at the tap's child offset o (8 rows, then one zero slot)
-// while the MFMAs of the previous tap run.  A fragments are read from sD
-// through per-lane offsets that do not depend on the tap (kept in registers).
+// Shared tap pipeline of the MFMA kernels.  A block owns 16 groups of one
+// parity class at one level.  For each of the 189 taps:
+//   B[k][n] = c_k 2^|k| S~_k of the tap's source of group n (monopole for a
+//             leaf source, 0 when there is none) is loaded by lane (n, g)
+//             straight into registers: its STP coefficients k = 4 kb + g are
+//             one contiguous run of the source copy (lane-group layout);
+//   sD[o][g] = D~_g at the tap's child offset o (8 rows, then one zero slot)
+//             is staged in LDS while the MFMAs of the previous tap run.
+// A fragments are read from sD through per-lane offsets that do not depend on
+// the tap (kept in registers).
 template <typename T> struct Vec16;
 template <> struct Vec16<float> { typedef float type __attribute__((ext_vector_type(4))); };
 template <> struct Vec16<double> { typedef double type __attribute__((ext_vector_type(2))); };
 
-template <typename T, int P, int NC>
+template <typename T, int P>
 struct TapStage {
   static constexpr int K = nmi(P);
-  static constexpr int KP = (K + 3) & ~3;    // padded row length of the source copies
+  static constexpr int KP = (K + 3) & ~3;    // coefficients covered by the k-steps
   static constexpr int KS = KP + 1;          // sD row stride
   static constexpr int VW = 16 / (int)sizeof(T);
-  static constexpr int KV = KP / VW;         // 16-byte vectors per source row
-  static constexpr int NV = NC * KV;
-  static constexpr int NBV = (NV + kBlock - 1) / kBlock;
-  static constexpr int ND = (8 * KS + 1 + kBlock - 1) / kBlock;
-  static constexpr int NCT = NC / 16;
-  static constexpr int SB = NC * KP;         // sB in MFMA fragment order [kb][ct][lane]
+  static constexpr int STP = src_stp(P, (int)sizeof(T));  // per-lane run of the source copy
+  static constexpr int ROW = 4 * STP;        // source-copy row length
+  static constexpr int NVB = STP / VW;       // 16-byte vectors per lane and tap
+  static constexpr int SD = 8 * KS + 1;      // sD size (8 rows + zero slot)
 };
 
 // scaled source copies c_a 2^|a| S~_a of a level
@@ -306,30 +312,33 @@ __device__ inline int tap_src(int code, int n, const int* __restrict__ sCB, cons
   return rs >= 0 ? rs : -2 - s;
 }
 
-template <typename T, int P, int NC>
-__device__ inline void tap_load(int code, const int* __restrict__ src, const double* __restrict__ mass1,
-                                const T* __restrict__ Dil, const T* __restrict__ S1,
-                                typename Vec16<T>::type* vB, T* vD) {
-  using TS = TapStage<T, P, NC>;
+// B fragments of one tap for lane (n = lane & 15, g = lane >> 4): the first NV
+// 16-byte vectors of the lane's run (vector j holds steps kb = VW j .. VW j + VW-1).
+template <typename T, int P, int NV>
+__device__ inline void load_bfrag(int sr, int lane, const double* __restrict__ mass1, const T* __restrict__ S1,
+                                  typename Vec16<T>::type* vb) {
+  using TS = TapStage<T, P>;
   using V = typename Vec16<T>::type;
+  if (sr >= 0) {
+    const V* src = (const V*)(S1 + (size_t)sr * TS::ROW + (lane >> 4) * TS::STP);
+#pragma unroll
+    for (int j = 0; j < NV; ++j) vb[j] = src[j];
+  } else {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) vb[j] = V{};
+    if (sr <= -2 && (lane >> 4) == 0) vb[0][0] = (T)mass1[-2 - sr];
+  }
+}
+
+template <typename T, int P, int NTH>
+__device__ inline void load_drows(int code, const T* __restrict__ Dil, T* vD) {
+  using TS = TapStage<T, P>;
+  constexpr int ND = (TS::SD + NTH - 1) / NTH;
   const int t = threadIdx.x;
   const int di = code >> 8;
 #pragma unroll
-  for (int j = 0; j < TS::NBV; ++j) {
-    const int q = t + kBlock * j;
-    V v = {};
-    if (q < TS::NV) {
-      const int n = q / TS::KV;
-      const int a0 = (q - n * TS::KV) * TS::VW;
-      const int sr = src[n];
-      if (sr >= 0) v = *(const V*)(S1 + (size_t)sr * TS::KP + a0);
-      else if (sr <= -2 && a0 == 0) v[0] = (T)mass1[-2 - sr];
-    }
-    vB[j] = v;
-  }
-#pragma unroll
-  for (int j = 0; j < TS::ND; ++j) {
-    const int i = t + kBlock * j;
+  for (int j = 0; j < ND; ++j) {
+    const int i = t + NTH * j;
     T v = 0;
     if (i < 8 * TS::KS) {
       const int o = i / TS::KS;
@@ -340,28 +349,15 @@ __device__ inline void tap_load(int code, const int* __restrict__ src, const dou
   }
 }
 
-template <typename T, int P, int NC>
-__device__ inline void tap_store(T* sB, T* sD, const typename Vec16<T>::type* vB, const T* vD) {
-  using TS = TapStage<T, P, NC>;
+template <typename T, int P, int NTH>
+__device__ inline void store_drows(T* sD, const T* vD) {
+  using TS = TapStage<T, P>;
+  constexpr int ND = (TS::SD + NTH - 1) / NTH;
   const int t = threadIdx.x;
 #pragma unroll
-  for (int j = 0; j < TS::NBV; ++j) {
-    const int q = t + kBlock * j;
-    if (q < TS::NV) {
-      const int n = q / TS::KV;
-      const int a0 = (q - n * TS::KV) * TS::VW;
-      T* dst = sB + (n >> 4) * 64 + (n & 15);
-#pragma unroll
-      for (int e = 0; e < TS::VW; ++e) {
-        const int k = a0 + e;
-        dst[(k >> 2) * (TS::NCT * 64) + (k & 3) * 16] = vB[j][e];
-      }
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < TS::ND; ++j) {
-    const int i = t + kBlock * j;
-    if (i <= 8 * TS::KS) sD[i] = vD[j];
+  for (int j = 0; j < ND; ++j) {
+    const int i = t + NTH * j;
+    if (i < TS::SD) sD[i] = vD[j];
   }
 }
 
@@ -400,22 +396,22 @@ __device__ inline int xcd_tile(int ntiles) {
 // Intermediate-field M2P at the leaves (Alg. 4 / Sec. 3.2): rows = 8 children
 // x (phi, ax, ay, az) in two 16-row tiles (the acceleration rows only need
 // multipoles of order < p), columns = 16 groups of one parity class,
-// K = multipole coefficients.  One wave per block: the staged sources are not
-// shared with other waves, so blocks never wait on each other.  Output:
-// part[F][c*8+o] (accelerations already negated), in target-level units.
-// One launch covers the tiles of every level of one precision.
+// K = multipole coefficients.  One wave per block: B comes straight from the
+// source copies into registers (the next tap's while the current tap's MFMAs
+// run), only the D~ rows go through LDS.  Output: part[F][c*8+o]
+// (accelerations already negated), in target-level units.  One launch covers
+// the tiles of every level of one precision.
 template <typename T, int P>
 __global__ __launch_bounds__(64) void k_m2p(const int32_t* __restrict__ tiles, int ntiles,
                                             const int32_t* __restrict__ taps, const int16_t* __restrict__ aoff,
                                             const LevelDev* __restrict__ lvs, const T* __restrict__ Dil) {
-  using TS = TapStage<T, P, 16>;
+  using TS = TapStage<T, P>;
   using V = typename Vec16<T>::type;
   constexpr int K1 = nmi(P - 1);
   constexpr int ST0 = TS::KP / 4, ST1 = ((K1 + 3) & ~3) / 4;
-  constexpr int NBV = (TS::NV + 63) / 64;
-  constexpr int ND = (8 * TS::KS + 1 + 63) / 64;
-  __shared__ T sB[TS::SB];
-  __shared__ T sD[8 * TS::KS + 1];
+  constexpr int NV = (ST0 + TS::VW - 1) / TS::VW;
+  constexpr int ND = (TS::SD + 63) / 64;
+  __shared__ T sD[2][TS::SD];
   __shared__ int sF[16];
   __shared__ int sCB[16 * 27];
   __shared__ int sSrc[2][16];
@@ -423,6 +419,7 @@ __global__ __launch_bounds__(64) void k_m2p(const int32_t* __restrict__ tiles, i
   const int tile = xcd_tile(ntiles);
   if (tile >= ntiles) return;
   const int lane = threadIdx.x;
+  const int n = lane & 15;
   const int32_t* rec = tiles + (size_t)tile * 17;
   const int l = rec[0];
   const LevelDev lv1 = lvs[l - 1];
@@ -434,8 +431,8 @@ __global__ __launch_bounds__(64) void k_m2p(const int32_t* __restrict__ tiles, i
   if (lane < 16) sF[lane] = rec[1 + lane];
   __syncthreads();
   for (int i = lane; i < 16 * 27; i += 64) {
-    const int n = i / 27, e = i - n * 27;
-    const int F = sF[n];
+    const int c = i / 27, e = i - c * 27;
+    const int F = sF[c];
     int v = -1;
     if (F >= 0) {
       const int Q = lv2.nbr[(size_t)(lv1.refcell[F] >> 3) * 27 + e];
@@ -459,82 +456,41 @@ __global__ __launch_bounds__(64) void k_m2p(const int32_t* __restrict__ tiles, i
     sSrc[1][lane] = tap_src(sTap[1], lane, sCB, rank1);
   }
   __syncthreads();
-  V vB[NBV];
+  V bA[NV], bB[NV];
   T vD[ND];
-  // stage tap `code` from registers / into registers (64 lanes)
-  auto load = [&](int code, const int* src) {
-    const int di = code >> 8;
-#pragma unroll
-    for (int j = 0; j < NBV; ++j) {
-      const int q = lane + 64 * j;
-      V v = {};
-      if (q < TS::NV) {
-        const int n = q / TS::KV;
-        const int a0 = (q - n * TS::KV) * TS::VW;
-        const int sr = src[n];
-        if (sr >= 0) v = *(const V*)(S1 + (size_t)sr * TS::KP + a0);
-        else if (sr <= -2 && a0 == 0) v[0] = (T)mass1[-2 - sr];
-      }
-      vB[j] = v;
-    }
-#pragma unroll
-    for (int j = 0; j < ND; ++j) {
-      const int i = lane + 64 * j;
-      T v = 0;
-      if (i < 8 * TS::KS) {
-        const int o = i / TS::KS;
-        const int g = i - o * TS::KS;
-        if (g < TS::K) v = Dil[((size_t)di * 8 + o) * TS::K + g];
-      }
-      vD[j] = v;
-    }
-  };
-  auto store = [&]() {
-#pragma unroll
-    for (int j = 0; j < NBV; ++j) {
-      const int q = lane + 64 * j;
-      if (q < TS::NV) {
-        const int n = q / TS::KV;
-        const int a0 = (q - n * TS::KV) * TS::VW;
-#pragma unroll
-        for (int e = 0; e < TS::VW; ++e) {
-          const int k = a0 + e;
-          sB[(k >> 2) * 64 + (k & 3) * 16 + n] = vB[j][e];
-        }
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < ND; ++j) {
-      const int i = lane + 64 * j;
-      if (i <= 8 * TS::KS) sD[i] = vD[j];
-    }
-  };
-  load(sTap[0], sSrc[0]);
-  store();
+  load_bfrag<T, P, NV>(sSrc[0][n], lane, mass1, S1, bA);
+  load_drows<T, P, 64>(sTap[0], Dil, vD);
+  store_drows<T, P, 64>(sD[0], vD);
   __syncthreads();
   typename Acc4<T>::type acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-  const int krow = lane >> 4;
-  for (int k = 0; k < kTaps; ++k) {
+  // one tap: prefetch tap k+1 (B into bn, D rows into vD), MFMAs of tap k from bc / sD[k & 1]
+  auto step = [&](int k, const V* bc, V* bn) {
     const int b = k & 1;
-    if (k + 1 < kTaps) load(sTap[k + 1], sSrc[b ^ 1]);
+    if (k + 1 < kTaps) {
+      load_bfrag<T, P, NV>(sSrc[b ^ 1][n], lane, mass1, S1, bn);
+      load_drows<T, P, 64>(sTap[k + 1], Dil, vD);
+    }
     int nsrc = 0;
     if (k + 2 < kTaps && lane < 16) nsrc = tap_src(sTap[k + 2], lane, sCB, rank1);
-    T bv[ST0];
-#pragma unroll
-    for (int kb = 0; kb < ST0; ++kb) bv[kb] = sB[kb * 64 + lane];
+    const T* D = sD[b];
 #pragma unroll
     for (int kb = 0; kb < ST0; ++kb) {
-      acc0 = mfma16(sD[off0[kb]], bv[kb], acc0);
-      if (kb < ST1) acc1 = mfma16(sD[off1[kb]], bv[kb], acc1);
+      const T bv = bc[kb / TS::VW][kb % TS::VW];
+      acc0 = mfma16(D[off0[kb]], bv, acc0);
+      if (kb < ST1) acc1 = mfma16(D[off1[kb]], bv, acc1);
     }
-    __syncthreads();
-    if (k + 1 < kTaps) store();
+    if (k + 1 < kTaps) store_drows<T, P, 64>(sD[b ^ 1], vD);
     if (k + 2 < kTaps && lane < 16) sSrc[b][lane] = nsrc;
     __syncthreads();
+  };
+  for (int k = 0; k < kTaps; k += 2) {
+    step(k, bA, bB);
+    if (k + 1 < kTaps) step(k + 1, bB, bA);
   }
-  const int F = sF[lane & 15];
+  const int F = sF[n];
   if (F >= 0) {
     T* out = part + (size_t)F * 32;
+    const int krow = lane >> 4;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = acc_row<T>(krow, r);
@@ -590,19 +546,27 @@ constexpr M2LPlan<P> make_m2l_plan() {
   return pl;
 }
 
+// One wave's share of an M2L tile: its row tiles (compile-time plan H), B from
+// the source copies into registers (next tap prefetched when the registers
+// allow), D~ rows from the block's LDS stage.
 template <typename T, int P, int H>
 __device__ inline void m2l_part(const int32_t* __restrict__ tp, int nt, const int16_t* __restrict__ aoff,
-                                const int* sF, const int* sCB, int (*sSrc)[16], T (*sB)[TapStage<T, P, 16>::SB],
-                                T (*sD)[8 * TapStage<T, P, 16>::KS + 1], const int32_t* __restrict__ rank1,
-                                const double* __restrict__ mass1, const T* __restrict__ Dil,
-                                const T* __restrict__ S1, const int32_t* __restrict__ rank0, T* __restrict__ Lout) {
-  using TS = TapStage<T, P, 16>;
+                                const int* sF, const int* sCB, int (*sSrc)[16], T (*sD)[TapStage<T, P>::SD],
+                                const int32_t* __restrict__ rank1, const double* __restrict__ mass1,
+                                const T* __restrict__ Dil, const T* __restrict__ S1,
+                                const int32_t* __restrict__ rank0, T* __restrict__ Lout) {
+  using TS = TapStage<T, P>;
+  using V = typename Vec16<T>::type;
   constexpr int K = TS::K;
   constexpr M2LPlan<P> PL = make_m2l_plan<P>();
   constexpr int NTH = PL.n[H];
   constexpr int NS = PL.steps[H];
   constexpr int KBH = PL.kbmax[H];
-  const int t = threadIdx.x, lane = t & 63, krow = lane >> 4;
+  constexpr int NV = KBH > 0 ? (KBH + TS::VW - 1) / TS::VW : 1;
+  constexpr int ND = (TS::SD + kBlock - 1) / kBlock;
+  // prefetch the next tap's B when both buffers fit next to the A offsets
+  constexpr bool PF = (2 * NV * 4 + NS) <= 160;
+  const int t = threadIdx.x, lane = t & 63, krow = lane >> 4, n = lane & 15;
   int off[NS > 0 ? NS : 1];
   {
     int s = 0;
@@ -614,29 +578,37 @@ __device__ inline void m2l_part(const int32_t* __restrict__ tp, int nt, const in
   typename Acc4<T>::type acc[NTH > 0 ? NTH : 1];
 #pragma unroll
   for (int i = 0; i < NTH; ++i) acc[i] = {0, 0, 0, 0};
-  typename Vec16<T>::type vB[TS::NBV];
-  T vD[TS::ND];
-  for (int k = 0; k < nt; ++k) {
+  T vD[ND];
+  V bA[NV], bB[PF ? NV : 1];
+  if (PF && KBH > 0) load_bfrag<T, P, NV>(sSrc[0][n], lane, mass1, S1, bA);
+  auto step = [&](int k, V* bc, V* bn) {
     const int b = k & 1;
-    if (k + 1 < nt) tap_load<T, P, 16>(tp[k + 1], sSrc[b ^ 1], mass1, Dil, S1, vB, vD);
+    if (k + 1 < nt) load_drows<T, P, kBlock>(tp[k + 1], Dil, vD);
+    if (KBH > 0) {
+      if (PF) {
+        if (k + 1 < nt) load_bfrag<T, P, NV>(sSrc[b ^ 1][n], lane, mass1, S1, bn);
+      } else {
+        load_bfrag<T, P, NV>(sSrc[b][n], lane, mass1, S1, bc);
+      }
+    }
     int nsrc = 0;
     if (k + 2 < nt && t < 16) nsrc = tap_src(tp[k + 2], t, sCB, rank1);
-    const T* B = sB[b] + lane;
     const T* D = sD[b];
-    T bv[KBH > 0 ? KBH : 1];
-#pragma unroll
-    for (int kb = 0; kb < KBH; ++kb) bv[kb] = B[kb * 64];
     int s = 0;
 #pragma unroll
     for (int i = 0; i < NTH; ++i)
 #pragma unroll
       for (int kb = 0; kb < m2l_ksteps(P, PL.tile[H][i]); ++kb) {
-        acc[i] = mfma16(D[off[s]], bv[kb], acc[i]);
+        acc[i] = mfma16(D[off[s]], bc[kb / TS::VW][kb % TS::VW], acc[i]);
         ++s;
       }
-    if (k + 1 < nt) tap_store<T, P, 16>(sB[b ^ 1], sD[b ^ 1], vB, vD);
+    if (k + 1 < nt) store_drows<T, P, kBlock>(sD[b ^ 1], vD);
     if (k + 2 < nt && t < 16) sSrc[b][t] = nsrc;
     __syncthreads();
+  };
+  for (int k = 0; k < nt; k += 2) {
+    step(k, bA, PF ? bB : bA);
+    if (k + 1 < nt) step(k + 1, PF ? bB : bA, bA);
   }
   const int F = sF[lane & 15];
   if (F < 0) return;
@@ -660,9 +632,9 @@ __global__ __launch_bounds__(kBlock) void k_m2l_mfma(const int32_t* __restrict__
                                                      const int32_t* __restrict__ taps,
                                                      const int16_t* __restrict__ aoff,
                                                      const LevelDev* __restrict__ lvs, const T* __restrict__ Dil) {
-  using TS = TapStage<T, P, 16>;
-  __shared__ T sB[2][TS::SB];
-  __shared__ T sD[2][8 * TS::KS + 1];
+  using TS = TapStage<T, P>;
+  constexpr int ND = (TS::SD + kBlock - 1) / kBlock;
+  __shared__ T sD[2][TS::SD];
   __shared__ int sF[16];
   __shared__ int sCB[16 * 27];
   __shared__ int sSrc[2][16];
@@ -685,19 +657,19 @@ __global__ __launch_bounds__(kBlock) void k_m2l_mfma(const int32_t* __restrict__
     sSrc[0][t] = tap_src(tp[0], t, sCB, lv1.rank);
     if (nt > 1) sSrc[1][t] = tap_src(tp[1], t, sCB, lv1.rank);
   }
-  __syncthreads();
-  typename Vec16<T>::type vB[TS::NBV];
-  T vD[TS::ND];
-  tap_load<T, P, 16>(tp[0], sSrc[0], lv1.mass, Dil, S1, vB, vD);
-  tap_store<T, P, 16>(sB[0], sD[0], vB, vD);
+  {
+    T vD[ND];
+    load_drows<T, P, kBlock>(tp[0], Dil, vD);
+    store_drows<T, P, kBlock>(sD[0], vD);
+  }
   __syncthreads();
   T* Lout = nsplit > 1 ? (T*)lv0.Lpart + (size_t)chunk * lv0.nref * TS::K : level_L<T>(lv0);
   // every wave runs the same number of barriers (one per tap)
   switch (w) {
-    case 0: m2l_part<T, P, 0>(tp, nt, aoff, sF, sCB, sSrc, sB, sD, lv1.rank, lv1.mass, Dil, S1, lv0.rank, Lout); break;
-    case 1: m2l_part<T, P, 1>(tp, nt, aoff, sF, sCB, sSrc, sB, sD, lv1.rank, lv1.mass, Dil, S1, lv0.rank, Lout); break;
-    case 2: m2l_part<T, P, 2>(tp, nt, aoff, sF, sCB, sSrc, sB, sD, lv1.rank, lv1.mass, Dil, S1, lv0.rank, Lout); break;
-    default: m2l_part<T, P, 3>(tp, nt, aoff, sF, sCB, sSrc, sB, sD, lv1.rank, lv1.mass, Dil, S1, lv0.rank, Lout); break;
+    case 0: m2l_part<T, P, 0>(tp, nt, aoff, sF, sCB, sSrc, sD, lv1.rank, lv1.mass, Dil, S1, lv0.rank, Lout); break;
+    case 1: m2l_part<T, P, 1>(tp, nt, aoff, sF, sCB, sSrc, sD, lv1.rank, lv1.mass, Dil, S1, lv0.rank, Lout); break;
+    case 2: m2l_part<T, P, 2>(tp, nt, aoff, sF, sCB, sSrc, sD, lv1.rank, lv1.mass, Dil, S1, lv0.rank, Lout); break;
+    default: m2l_part<T, P, 3>(tp, nt, aoff, sF, sCB, sSrc, sD, lv1.rank, lv1.mass, Dil, S1, lv0.rank, Lout); break;
   }
 }
 
@@ -762,8 +734,8 @@ __global__ __launch_bounds__(kBlock) void k_near(const int32_t* __restrict__ grp
                (T)tz - ((T)o_axis(o2, 2) - (T)0.5) * (T)0.5, (T)lvp.mass[kc], nst);
       }
     } else {
-      m2p_row<T, P>(tb.Dsame + (size_t)d_index(tx, ty, tz) * K, S0 + (size_t)rn * ((K + 3) & ~3), tb.cfacn, cm.up,
-                    nea);
+      m2p_row<T, P>(tb.Dsame + (size_t)d_index(tx, ty, tz) * K, S0 + (size_t)rn * src_row(P, (int)sizeof(T)),
+                    tb.cfacn, cm.up, nea);
     }
   }
 #pragma unroll

@@ -546,27 +546,67 @@ constexpr M2LPlan<P> make_m2l_plan() {
   return pl;
 }
 
-// One wave's share of an M2L tile: its row tiles (compile-time plan H), B from
-// the source copies into registers (next tap prefetched when the registers
-// allow), D~ rows from the block's LDS stage.
+// B of one M2L tap in LDS, fragment order sB[kb][lane]: wave w loads vectors
+// j in [w NVW, (w+1) NVW) of every lane's run (16-byte loads) and writes
+// element e of vector j to sB[(VW j + e) * 64 + lane] (consecutive lanes,
+// consecutive banks).
+template <typename T, int P>
+struct M2LStage {
+  static constexpr int NVB = TapStage<T, P>::STP / TapStage<T, P>::VW;  // vectors per lane run
+  static constexpr int NVW = (NVB + 3) / 4;                            // per wave
+};
+
+template <typename T, int P>
+__device__ inline void load_bshare(int sr, int lane, int w, const double* __restrict__ mass1,
+                                   const T* __restrict__ S1, typename Vec16<T>::type* vb) {
+  using TS = TapStage<T, P>;
+  using MS = M2LStage<T, P>;
+  using V = typename Vec16<T>::type;
+#pragma unroll
+  for (int i = 0; i < MS::NVW; ++i) {
+    const int j = w * MS::NVW + i;
+    V v = {};
+    if (j < MS::NVB) {
+      if (sr >= 0) v = *(const V*)(S1 + (size_t)sr * TS::ROW + (lane >> 4) * TS::STP + j * TS::VW);
+      else if (sr <= -2 && j == 0 && (lane >> 4) == 0) v[0] = (T)mass1[-2 - sr];
+    }
+    vb[i] = v;
+  }
+}
+
+template <typename T, int P>
+__device__ inline void store_bshare(T* sB, int lane, int w, const typename Vec16<T>::type* vb) {
+  using TS = TapStage<T, P>;
+  using MS = M2LStage<T, P>;
+#pragma unroll
+  for (int i = 0; i < MS::NVW; ++i) {
+    const int j = w * MS::NVW + i;
+    if (j < MS::NVB) {
+#pragma unroll
+      for (int e = 0; e < TS::VW; ++e) sB[(j * TS::VW + e) * 64 + lane] = vb[i][e];
+    }
+  }
+}
+
+// One wave's share of an M2L tile: its row tiles (compile-time plan H) over
+// the block's LDS stage of B and of the D~ rows; the wave also loads its share
+// of the next tap's stage while its MFMAs run.
 template <typename T, int P, int H>
 __device__ inline void m2l_part(const int32_t* __restrict__ tp, int nt, const int16_t* __restrict__ aoff,
-                                const int* sF, const int* sCB, int (*sSrc)[16], T (*sD)[TapStage<T, P>::SD],
-                                const int32_t* __restrict__ rank1, const double* __restrict__ mass1,
-                                const T* __restrict__ Dil, const T* __restrict__ S1,
-                                const int32_t* __restrict__ rank0, T* __restrict__ Lout) {
+                                const int* sF, const int* sCB, int (*sSrc)[16], T (*sB)[TapStage<T, P>::STP * 64],
+                                T (*sD)[TapStage<T, P>::SD], const int32_t* __restrict__ rank1,
+                                const double* __restrict__ mass1, const T* __restrict__ Dil,
+                                const T* __restrict__ S1, const int32_t* __restrict__ rank0, T* __restrict__ Lout) {
   using TS = TapStage<T, P>;
+  using MS = M2LStage<T, P>;
   using V = typename Vec16<T>::type;
   constexpr int K = TS::K;
   constexpr M2LPlan<P> PL = make_m2l_plan<P>();
   constexpr int NTH = PL.n[H];
   constexpr int NS = PL.steps[H];
   constexpr int KBH = PL.kbmax[H];
-  constexpr int NV = KBH > 0 ? (KBH + TS::VW - 1) / TS::VW : 1;
   constexpr int ND = (TS::SD + kBlock - 1) / kBlock;
-  // prefetch the next tap's B when both buffers fit next to the A offsets
-  constexpr bool PF = (2 * NV * 4 + NS) <= 160;
-  const int t = threadIdx.x, lane = t & 63, krow = lane >> 4, n = lane & 15;
+  const int t = threadIdx.x, lane = t & 63, krow = lane >> 4;
   int off[NS > 0 ? NS : 1];
   {
     int s = 0;
@@ -579,36 +619,34 @@ __device__ inline void m2l_part(const int32_t* __restrict__ tp, int nt, const in
 #pragma unroll
   for (int i = 0; i < NTH; ++i) acc[i] = {0, 0, 0, 0};
   T vD[ND];
-  V bA[NV], bB[PF ? NV : 1];
-  if (PF && KBH > 0) load_bfrag<T, P, NV>(sSrc[0][n], lane, mass1, S1, bA);
-  auto step = [&](int k, V* bc, V* bn) {
+  V vB[MS::NVW];
+  for (int k = 0; k < nt; ++k) {
     const int b = k & 1;
-    if (k + 1 < nt) load_drows<T, P, kBlock>(tp[k + 1], Dil, vD);
-    if (KBH > 0) {
-      if (PF) {
-        if (k + 1 < nt) load_bfrag<T, P, NV>(sSrc[b ^ 1][n], lane, mass1, S1, bn);
-      } else {
-        load_bfrag<T, P, NV>(sSrc[b][n], lane, mass1, S1, bc);
-      }
+    if (k + 1 < nt) {
+      load_drows<T, P, kBlock>(tp[k + 1], Dil, vD);
+      load_bshare<T, P>(sSrc[b ^ 1][lane & 15], lane, H, mass1, S1, vB);
     }
     int nsrc = 0;
     if (k + 2 < nt && t < 16) nsrc = tap_src(tp[k + 2], t, sCB, rank1);
+    const T* B = sB[b] + lane;
     const T* D = sD[b];
+    T bv[KBH > 0 ? KBH : 1];
+#pragma unroll
+    for (int kb = 0; kb < KBH; ++kb) bv[kb] = B[kb * 64];
     int s = 0;
 #pragma unroll
     for (int i = 0; i < NTH; ++i)
 #pragma unroll
       for (int kb = 0; kb < m2l_ksteps(P, PL.tile[H][i]); ++kb) {
-        acc[i] = mfma16(D[off[s]], bc[kb / TS::VW][kb % TS::VW], acc[i]);
+        acc[i] = mfma16(D[off[s]], bv[kb], acc[i]);
         ++s;
       }
-    if (k + 1 < nt) store_drows<T, P, kBlock>(sD[b ^ 1], vD);
+    if (k + 1 < nt) {
+      store_drows<T, P, kBlock>(sD[b ^ 1], vD);
+      store_bshare<T, P>(sB[b ^ 1], lane, H, vB);
+    }
     if (k + 2 < nt && t < 16) sSrc[b][t] = nsrc;
     __syncthreads();
-  };
-  for (int k = 0; k < nt; k += 2) {
-    step(k, bA, PF ? bB : bA);
-    if (k + 1 < nt) step(k + 1, PF ? bB : bA, bA);
   }
   const int F = sF[lane & 15];
   if (F < 0) return;
@@ -633,7 +671,9 @@ __global__ __launch_bounds__(kBlock) void k_m2l_mfma(const int32_t* __restrict__
                                                      const int16_t* __restrict__ aoff,
                                                      const LevelDev* __restrict__ lvs, const T* __restrict__ Dil) {
   using TS = TapStage<T, P>;
+  using MS = M2LStage<T, P>;
   constexpr int ND = (TS::SD + kBlock - 1) / kBlock;
+  __shared__ T sB[2][TS::STP * 64];
   __shared__ T sD[2][TS::SD];
   __shared__ int sF[16];
   __shared__ int sCB[16 * 27];
@@ -642,7 +682,7 @@ __global__ __launch_bounds__(kBlock) void k_m2l_mfma(const int32_t* __restrict__
   if (item >= ntiles * nsplit) return;
   const int tile = item / nsplit, chunk = item - tile * nsplit;
   const int tb = chunk * kTaps / nsplit, te = (chunk + 1) * kTaps / nsplit;
-  const int t = threadIdx.x, w = t >> 6;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const int32_t* rec = tiles + (size_t)tile * 17;
   const int f = rec[0];
   const LevelDev lv1 = lvs[f - 1];
@@ -657,19 +697,23 @@ __global__ __launch_bounds__(kBlock) void k_m2l_mfma(const int32_t* __restrict__
     sSrc[0][t] = tap_src(tp[0], t, sCB, lv1.rank);
     if (nt > 1) sSrc[1][t] = tap_src(tp[1], t, sCB, lv1.rank);
   }
+  __syncthreads();
   {
     T vD[ND];
+    typename Vec16<T>::type vB[MS::NVW];
     load_drows<T, P, kBlock>(tp[0], Dil, vD);
+    load_bshare<T, P>(sSrc[0][lane & 15], lane, w, lv1.mass, S1, vB);
     store_drows<T, P, kBlock>(sD[0], vD);
+    store_bshare<T, P>(sB[0], lane, w, vB);
   }
   __syncthreads();
   T* Lout = nsplit > 1 ? (T*)lv0.Lpart + (size_t)chunk * lv0.nref * TS::K : level_L<T>(lv0);
   // every wave runs the same number of barriers (one per tap)
   switch (w) {
-    case 0: m2l_part<T, P, 0>(tp, nt, aoff, sF, sCB, sSrc, sD, lv1.rank, lv1.mass, Dil, S1, lv0.rank, Lout); break;
-    case 1: m2l_part<T, P, 1>(tp, nt, aoff, sF, sCB, sSrc, sD, lv1.rank, lv1.mass, Dil, S1, lv0.rank, Lout); break;
-    case 2: m2l_part<T, P, 2>(tp, nt, aoff, sF, sCB, sSrc, sD, lv1.rank, lv1.mass, Dil, S1, lv0.rank, Lout); break;
-    default: m2l_part<T, P, 3>(tp, nt, aoff, sF, sCB, sSrc, sD, lv1.rank, lv1.mass, Dil, S1, lv0.rank, Lout); break;
+    case 0: m2l_part<T, P, 0>(tp, nt, aoff, sF, sCB, sSrc, sB, sD, lv1.rank, lv1.mass, Dil, S1, lv0.rank, Lout); break;
+    case 1: m2l_part<T, P, 1>(tp, nt, aoff, sF, sCB, sSrc, sB, sD, lv1.rank, lv1.mass, Dil, S1, lv0.rank, Lout); break;
+    case 2: m2l_part<T, P, 2>(tp, nt, aoff, sF, sCB, sSrc, sB, sD, lv1.rank, lv1.mass, Dil, S1, lv0.rank, Lout); break;
+    default: m2l_part<T, P, 3>(tp, nt, aoff, sF, sCB, sSrc, sB, sD, lv1.rank, lv1.mass, Dil, S1, lv0.rank, Lout); break;
   }
 }
 

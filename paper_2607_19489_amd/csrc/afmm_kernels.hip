@@ -723,7 +723,10 @@ __global__ __launch_bounds__(kBlock) void k_m2l_mfma(const int32_t* __restrict__
 // touching the target) and nearest field (P2P from the children of refined
 // level-l cells touching the target), plus the MFMA intermediate-field partial;
 // the four fields are summed in FP64 and scaled to physical units.
-// Thread (o = t & 7, j = t >> 3): target child o, every 32nd near cell from j.
+// The 8 targets of a group share their 216 candidate near cells (children of
+// F's 27 neighbours, or the neighbour itself when it is a leaf): they are
+// resolved once per block into LDS (kind, mass, refined rank), then thread
+// (o = t & 7, j = t >> 3) takes target child o and every 32nd candidate from j.
 template <typename T, int P>
 __global__ __launch_bounds__(kBlock) void k_near(const int32_t* __restrict__ grp, LevelDev lv1, LevelDev lv0,
                                                  LevelDev lvp, TablesDev<T> tb, const T* __restrict__ Lpar,
@@ -731,21 +734,53 @@ __global__ __launch_bounds__(kBlock) void k_near(const int32_t* __restrict__ grp
                                                  CommonDev cm, double G, double h, double* __restrict__ phi,
                                                  double* __restrict__ acc) {
   constexpr int K = nmi(P);
-  __shared__ int s_nb[27];
+  enum { kNone = 0, kCoarse = 1, kLeaf = 2, kRefined = 3 };
+  __shared__ int s_kind[216];
+  __shared__ int s_rn[216];
+  __shared__ T s_m[216];
+  __shared__ T s_L[K];
   __shared__ T s_red[12][kBlock];
   const int F = grp[blockIdx.x];
   const int t = threadIdx.x;
   const int o = t & 7, j = t >> 3;
-  if (t < 27) s_nb[t] = lv1.nbr[(size_t)F * 27 + t];
+  if (t < 216) {
+    const int e = t >> 3, op = t & 7;
+    const int q = lv1.nbr[(size_t)F * 27 + e];
+    int kind = kNone, rn = -1;
+    T m = 0;
+    if (q >= 0) {
+      const int rq = lv1.rank[q];
+      if (rq < 0) {
+        if (op == 0) {
+          kind = kCoarse;
+          m = (T)lv1.mass[q];
+        }
+      } else {
+        const int n = 8 * rq + op;
+        rn = lv0.rank[n];
+        if (rn < 0) {
+          kind = kLeaf;  // a target skips itself (s_rn holds the cell index)
+          m = (T)lv0.mass[n];
+          rn = n;
+        } else {
+          kind = kRefined;
+        }
+      }
+    }
+    s_kind[t] = kind;
+    s_rn[t] = rn;
+    s_m[t] = m;
+  }
+  if (Lpar)
+    for (int b = t; b < K; b += kBlock) s_L[b] = Lpar[(size_t)F * K + b];
   __syncthreads();
   const int cell = 8 * F + o;
   T far[4] = {0, 0, 0, 0}, nea[4] = {0, 0, 0, 0}, nst[4] = {0, 0, 0, 0};
   const T ox = (T)o_axis(o, 0), oy = (T)o_axis(o, 1), oz = (T)o_axis(o, 2);
   if (Lpar) {
-    const T* LF = Lpar + (size_t)F * K;
     const T* wl = tb.l2p + (size_t)o * 4 * K;
     for (int b = j; b < K; b += 32) {
-      const T v = LF[b];
+      const T v = s_L[b];
       far[0] += wl[b] * v;
       far[1] += wl[K + b] * v;
       far[2] += wl[2 * K + b] * v;
@@ -753,25 +788,23 @@ __global__ __launch_bounds__(kBlock) void k_near(const int32_t* __restrict__ grp
     }
   }
   for (int k = j; k < 216; k += 32) {
+    const int kind = s_kind[k];
+    if (kind == kNone) continue;
     const int e = k >> 3, op = k & 7;
-    const int q = s_nb[e];
-    if (q < 0) continue;
     const int ex = e_axis(e, 0), ey = e_axis(e, 1), ez = e_axis(e, 2);
-    const int rq = lv1.rank[q];
-    if (rq < 0) {
-      if (op == 0)
-        p2p<T>(ox - (T)0.5 - (T)(2 * ex), oy - (T)0.5 - (T)(2 * ey), oz - (T)0.5 - (T)(2 * ez), (T)lv1.mass[q], nea);
+    if (kind == kCoarse) {
+      p2p<T>(ox - (T)0.5 - (T)(2 * ex), oy - (T)0.5 - (T)(2 * ey), oz - (T)0.5 - (T)(2 * ez), s_m[k], nea);
       continue;
     }
-    const int nc = 8 * rq + op;
-    if (nc == cell) continue;
     const int tx = o_axis(o, 0) - 2 * ex - o_axis(op, 0);
     const int ty = o_axis(o, 1) - 2 * ey - o_axis(op, 1);
     const int tz = o_axis(o, 2) - 2 * ez - o_axis(op, 2);
-    const int rn = lv0.rank[nc];
-    if (rn < 0) {
-      p2p<T>((T)tx, (T)ty, (T)tz, (T)lv0.mass[nc], nea);
-    } else if (max(abs(tx), max(abs(ty), abs(tz))) <= 1) {
+    if (kind == kLeaf) {
+      if (s_rn[k] != cell) p2p<T>((T)tx, (T)ty, (T)tz, s_m[k], nea);
+      continue;
+    }
+    const int rn = s_rn[k];
+    if (max(abs(tx), max(abs(ty), abs(tz))) <= 1) {
       for (int o2 = 0; o2 < 8; ++o2) {
         const int kc = 8 * rn + o2;
         p2p<T>((T)tx - ((T)o_axis(o2, 0) - (T)0.5) * (T)0.5, (T)ty - ((T)o_axis(o2, 1) - (T)0.5) * (T)0.5,

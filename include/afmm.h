@@ -61,10 +61,10 @@ typedef struct afmm_options {
   double boxlen;             /* box side */
   uint32_t flags;            /* AFMM_CHECK_INPUT | AFMM_SERIAL */
   int32_t fp64_levels;       /* mixed form: FMM levels <= this stay FP64 (default 4) */
-  int32_t tap_split;         /* M2L blocks per tile: the 189 source offsets of a tile are split
-                                over this many blocks and their partial sums reduced in a fixed
-                                order; 0 = automatic (enough blocks to fill the GPU), else 1..21.
-                                Results depend on it only through FP rounding order. */
+  int32_t tap_split;         /* M2L and M2P blocks per tile: the 189 source offsets of a tile are
+                                split over this many blocks and their partial sums reduced in a
+                                fixed order; 0 = automatic (enough blocks to fill the GPU), else
+                                1..21.  Results depend on it only through FP rounding order. */
   size_t max_device_bytes;   /* cap on the plan's device memory; 0 = no cap */
 } afmm_options;
 

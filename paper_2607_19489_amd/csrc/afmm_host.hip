@@ -639,7 +639,8 @@ struct afmm_plan {
   MfmaTiles m2p_all[2], m2l_all[2];
   int m2p_range[kMaxLevel][3] = {};
   int m2l_range[kMaxLevel][3] = {};
-  int m2l_split[2] = {1, 1};        // tap ranges per M2L block, per precision
+  int m2l_split[2] = {1, 1};        // tap ranges per M2L tile, per precision
+  int m2p_split[2] = {1, 1};        // tap ranges per M2P tile, per precision
   LevelDev* d_lvs = nullptr;        // device copy of lv[]
   // internal side stream: the downward M2L/L2L chain runs on it concurrently
   // with the leaf-level M2P (they only share the multipoles of the upward pass)
@@ -984,11 +985,6 @@ static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
       P->m2p_range[l][0] = pr;
       P->m2p_range[l][1] = n0;
       P->m2p_range[l][2] = n;
-      if (!T.leafgrp[l].empty()) {
-        void* q = nullptr;
-        if ((s = dev_alloc(P, &q, (size_t)T.lv[l - 1].nref() * 32 * (pr ? sizeof(float) : sizeof(double))))) return s;
-        P->lv[l - 1].part = q;
-      }
       const int pm = (mixed && l > f64) ? 1 : 0;
       if (l <= T.lmax - 1) {
         const int m0 = (int)(m2l_rec[pm].size() / 17);
@@ -1010,6 +1006,24 @@ static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
       P->m2l_split[pr] = P->opt.tap_split > 0 ? P->opt.tap_split
                          : nt > 0              ? std::max(1, std::min(21, (2 * ncu + nt - 1) / nt))
                                                : 1;
+    }
+    // M2P likewise, aiming at 12 waves per CU; each tap range writes its own
+    // partial set, summed in order by the leaf kernel
+    for (int pr = 0; pr < 2; ++pr) {
+      const int nt = (int)(m2p_rec[pr].size() / (m2p_nc[pr] + 1));
+      P->m2p_split[pr] = P->opt.tap_split > 0 ? P->opt.tap_split
+                         : nt > 0              ? std::max(1, std::min(8, (12 * ncu + nt - 1) / nt))
+                                               : 1;
+    }
+    for (int l = 3; l <= T.lmax; ++l) {
+      if (T.leafgrp[l].empty()) continue;
+      const int pr = P->m2p_range[l][0];
+      void* q = nullptr;
+      if ((s = dev_alloc(P, &q, (size_t)P->m2p_split[pr] * T.lv[l - 1].nref() * 32 *
+                                    (pr ? sizeof(float) : sizeof(double)))))
+        return s;
+      P->lv[l - 1].part = q;
+      P->lv[l - 1].npart = P->m2p_split[pr];
     }
     for (int f = 3; f <= T.lmax - 1; ++f) {
       const int pm = P->m2l_range[f][0];
@@ -1200,7 +1214,7 @@ static afmm_status run_solve(afmm_plan* P, const double* msrc, int fmax, int lo,
       }
     if (n <= 0) continue;
     hipEvent_t a = prof_begin(P, st);
-    if ((s = dev_check(P, launch_m2p(p, pr == 1, P->m2p_all[pr], t0, n, P->mt, P->d_lvs, P->t32, P->t64, st), "m2p")))
+    if ((s = dev_check(P, launch_m2p(p, pr == 1, P->m2p_all[pr], t0, n, P->m2p_split[pr], P->mt, P->d_lvs, P->t32, P->t64, st), "m2p")))
       return s;
     for (int l = std::max(lo, 3); l <= hi; ++l)
       if (P->m2p_range[l][0] == pr) {

@@ -63,7 +63,9 @@ struct LevelDev {
   double* Sc64 = nullptr;            // [nref][src_row(p, 8)] same source copy in FP64
   double* L64 = nullptr;             // [nref][K] local expansions (FP64 levels)
   float* L32 = nullptr;              // [nref][K] local expansions (FP32 levels)
-  void* part = nullptr;              // [nref][32] intermediate-field partials of the leaf children (T of the leaf level)
+  void* part = nullptr;              // [npart][nref][32] intermediate-field partials of the leaf children (T of the
+                                     // leaf level), one set per M2P tap range
+  int32_t npart = 0;
   void* Lpart = nullptr;             // [nsplit][nref][K] M2L tap-range partial sums (T of the level), if split
   // adjoint pass (FP64, allocated by the first adjoint call)
   double* tbar = nullptr;            // [n][4] unit-form bars of the target leaves (phi, ax, ay, az)
@@ -151,7 +153,7 @@ hipError_t launch_m2l_taps(int p, bool fp32, const MfmaTiles& mt, int t0, int n,
 hipError_t launch_l2l(int p, bool fp32, bool parent_fp32, bool has_parent, int nsplit, const int32_t* grp, int ngrp,
                       const LevelDev& lv1, const LevelDev& lv0, const TablesDev<float>& t32,
                       const TablesDev<double>& t64, const CommonDev& cm, hipStream_t st);
-hipError_t launch_m2p(int p, bool fp32, const MfmaTiles& mt, int t0, int n, const MfmaTables& tabs,
+hipError_t launch_m2p(int p, bool fp32, const MfmaTiles& mt, int t0, int n, int nsplit, const MfmaTables& tabs,
                       const LevelDev* lvs, const TablesDev<float>& t32, const TablesDev<double>& t64,
                       hipStream_t st);
 hipError_t launch_near(int p, bool fp32, int l, const int32_t* grp, int ngrp, const LevelDev& lv1,

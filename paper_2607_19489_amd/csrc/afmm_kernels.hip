@@ -400,9 +400,11 @@ __device__ inline int xcd_tile(int ntiles) {
 // source copies into registers (the next tap's while the current tap's MFMAs
 // run), only the D~ rows go through LDS.  Output: part[F][c*8+o]
 // (accelerations already negated), in target-level units.  One launch covers
-// the tiles of every level of one precision.
+// the tiles of every level of one precision.  One block takes one of `nsplit`
+// contiguous tap ranges of its tile and writes its own partial set
+// part[chunk][F][...], summed in order by the leaf kernel.
 template <typename T, int P>
-__global__ __launch_bounds__(64) void k_m2p(const int32_t* __restrict__ tiles, int ntiles,
+__global__ __launch_bounds__(64) void k_m2p(const int32_t* __restrict__ tiles, int ntiles, int nsplit,
                                             const int32_t* __restrict__ taps, const int16_t* __restrict__ aoff,
                                             const LevelDev* __restrict__ lvs, const T* __restrict__ Dil) {
   using TS = TapStage<T, P>;
@@ -416,8 +418,10 @@ __global__ __launch_bounds__(64) void k_m2p(const int32_t* __restrict__ tiles, i
   __shared__ int sCB[16 * 27];
   __shared__ int sSrc[2][16];
   __shared__ int sTap[kTaps];
-  const int tile = xcd_tile(ntiles);
-  if (tile >= ntiles) return;
+  const int item = xcd_tile(ntiles * nsplit);
+  if (item >= ntiles * nsplit) return;
+  const int tile = item / nsplit, chunk = item - tile * nsplit;
+  const int tb = chunk * kTaps / nsplit, te = (chunk + 1) * kTaps / nsplit;
   const int lane = threadIdx.x;
   const int n = lane & 15;
   const int32_t* rec = tiles + (size_t)tile * 17;
@@ -427,7 +431,7 @@ __global__ __launch_bounds__(64) void k_m2p(const int32_t* __restrict__ tiles, i
   const int32_t* rank1 = lv1.rank;
   const double* mass1 = lv1.mass;
   const T* S1 = level_S<T>(lv1);
-  T* part = (T*)lv1.part;
+  T* part = (T*)lv1.part + (size_t)chunk * lv1.nref * 32;
   if (lane < 16) sF[lane] = rec[1 + lane];
   __syncthreads();
   for (int i = lane; i < 16 * 27; i += 64) {
@@ -452,26 +456,26 @@ __global__ __launch_bounds__(64) void k_m2p(const int32_t* __restrict__ tiles, i
   for (int kb = 0; kb < ST1; ++kb) off1[kb] = aoff[(ST0 + kb) * 64 + lane];
   __syncthreads();
   if (lane < 16) {
-    sSrc[0][lane] = tap_src(sTap[0], lane, sCB, rank1);
-    sSrc[1][lane] = tap_src(sTap[1], lane, sCB, rank1);
+    sSrc[0][lane] = tap_src(sTap[tb], lane, sCB, rank1);
+    if (tb + 1 < te) sSrc[1][lane] = tap_src(sTap[tb + 1], lane, sCB, rank1);
   }
   __syncthreads();
   V bA[NV], bB[NV];
   T vD[ND];
   load_bfrag<T, P, NV>(sSrc[0][n], lane, mass1, S1, bA);
-  load_drows<T, P, 64>(sTap[0], Dil, vD);
+  load_drows<T, P, 64>(sTap[tb], Dil, vD);
   store_drows<T, P, 64>(sD[0], vD);
   __syncthreads();
   typename Acc4<T>::type acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
   // one tap: prefetch tap k+1 (B into bn, D rows into vD), MFMAs of tap k from bc / sD[k & 1]
   auto step = [&](int k, const V* bc, V* bn) {
-    const int b = k & 1;
-    if (k + 1 < kTaps) {
+    const int b = (k - tb) & 1;
+    if (k + 1 < te) {
       load_bfrag<T, P, NV>(sSrc[b ^ 1][n], lane, mass1, S1, bn);
       load_drows<T, P, 64>(sTap[k + 1], Dil, vD);
     }
     int nsrc = 0;
-    if (k + 2 < kTaps && lane < 16) nsrc = tap_src(sTap[k + 2], lane, sCB, rank1);
+    if (k + 2 < te && lane < 16) nsrc = tap_src(sTap[k + 2], lane, sCB, rank1);
     const T* D = sD[b];
 #pragma unroll
     for (int kb = 0; kb < ST0; ++kb) {
@@ -479,13 +483,13 @@ __global__ __launch_bounds__(64) void k_m2p(const int32_t* __restrict__ tiles, i
       acc0 = mfma16(D[off0[kb]], bv, acc0);
       if (kb < ST1) acc1 = mfma16(D[off1[kb]], bv, acc1);
     }
-    if (k + 1 < kTaps) store_drows<T, P, 64>(sD[b ^ 1], vD);
-    if (k + 2 < kTaps && lane < 16) sSrc[b][lane] = nsrc;
+    if (k + 1 < te) store_drows<T, P, 64>(sD[b ^ 1], vD);
+    if (k + 2 < te && lane < 16) sSrc[b][lane] = nsrc;
     __syncthreads();
   };
-  for (int k = 0; k < kTaps; k += 2) {
+  for (int k = tb; k < te; k += 2) {
     step(k, bA, bB);
-    if (k + 1 < kTaps) step(k + 1, bB, bA);
+    if (k + 1 < te) step(k + 1, bB, bA);
   }
   const int F = sF[n];
   if (F >= 0) {
@@ -829,10 +833,11 @@ __global__ __launch_bounds__(kBlock) void k_near(const int32_t* __restrict__ grp
       for (int jj = 0; jj < 32; ++jj) s += s_red[c][t + 8 * jj];
       out[c & 3] += (double)s;
     }
-    if (part) {
-      const T* pp = part + (size_t)F * 32;
-      for (int c = 0; c < 4; ++c) out[c] += (double)pp[c * 8 + t];
-    }
+    if (part)
+      for (int sp = 0; sp < lv1.npart; ++sp) {
+        const T* pp = part + ((size_t)sp * lv1.nref + F) * 32;
+        for (int c = 0; c < 4; ++c) out[c] += (double)pp[c * 8 + t];
+      }
     const int sl = lv0.slot[8 * F + t];
     const double sp = G / h, sa = G / (h * h);
     phi[sl] = sp * out[0];
@@ -846,13 +851,16 @@ __global__ __launch_bounds__(kBlock) void k_near(const int32_t* __restrict__ grp
 // launchers
 
 template <typename T>
-static hipError_t m2p_dispatch(int p, const MfmaTiles& mt, int t0, int n, const MfmaTables& tabs,
+static hipError_t m2p_dispatch(int p, const MfmaTiles& mt, int t0, int n, int nsplit, const MfmaTables& tabs,
                                const LevelDev* lvs, const T* Dil, hipStream_t st) {
-  const dim3 grid(8 * ((n + 7) / 8)), block(64);
+  const int items = n * nsplit;
+  const dim3 grid(8 * ((items + 7) / 8)), block(64);
   const int32_t* tl = mt.tiles + (size_t)t0 * 17;
   switch (p) {
 #define AFMM_M2P(PP)                                                                                              \
-  case PP: hipLaunchKernelGGL((k_m2p<T, PP>), grid, block, 0, st, tl, n, tabs.taps, tabs.m2p_off, lvs, Dil); break;
+  case PP:                                                                                                  \
+    hipLaunchKernelGGL((k_m2p<T, PP>), grid, block, 0, st, tl, n, nsplit, tabs.taps, tabs.m2p_off, lvs, Dil);  \
+    break;
     AFMM_M2P(1) AFMM_M2P(2) AFMM_M2P(3) AFMM_M2P(4) AFMM_M2P(5) AFMM_M2P(6) AFMM_M2P(7) AFMM_M2P(8)
 #undef AFMM_M2P
     default: return hipErrorInvalidValue;
@@ -860,12 +868,12 @@ static hipError_t m2p_dispatch(int p, const MfmaTiles& mt, int t0, int n, const 
   return hipGetLastError();
 }
 
-hipError_t launch_m2p(int p, bool fp32, const MfmaTiles& mt, int t0, int n, const MfmaTables& tabs,
+hipError_t launch_m2p(int p, bool fp32, const MfmaTiles& mt, int t0, int n, int nsplit, const MfmaTables& tabs,
                       const LevelDev* lvs, const TablesDev<float>& t32, const TablesDev<double>& t64,
                       hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  if (fp32) return m2p_dispatch<float>(p, mt, t0, n, tabs, lvs, t32.Dil, st);
-  return m2p_dispatch<double>(p, mt, t0, n, tabs, lvs, t64.Dil, st);
+  if (fp32) return m2p_dispatch<float>(p, mt, t0, n, nsplit, tabs, lvs, t32.Dil, st);
+  return m2p_dispatch<double>(p, mt, t0, n, nsplit, tabs, lvs, t64.Dil, st);
 }
 
 int m2p_columns(int p, bool fp32) {

@@ -102,6 +102,7 @@ def run_batch(args):
     masses = [torch.from_numpy(w.mass).cuda() for w in ws]
     phis = [torch.zeros(w.hierarchy.total, dtype=torch.float64, device="cuda") for w in ws]
     accs = [torch.zeros(w.hierarchy.total, 3, dtype=torch.float64, device="cuda") for w in ws]
+    tune = None if args.no_autotune else batch.autotune(masses)
     for _ in range(args.warmup):
         batch.solve(masses, phis, accs)
     torch.cuda.synchronize()
@@ -141,22 +142,24 @@ def run_batch(args):
         "config": {"workload": (f"cfg4: batch of {len(ws)} independent hierarchies (base level 4-6, 0-3 mass-refined "
                                 f"levels, Plummer or clumps), {nleaf} leaves, one hipGraph launch per solve"),
                    "p": args.p, "precision": "FP32 mixed", "leaves": nleaf, "hierarchies": len(ws)},
-        "roofline": roofline(res, "fp32"), "cpu_baseline": base,
+        "roofline": roofline(res, "fp32"), "cpu_baseline": base, "autotune": tune,
         "algorithmic_flops_per_step": info["flops_m2l"] + info["flops_m2p"] + info["flops_p2p"] + info["flops_updown"],
         "kernels_fp32": kernel_table(res),
     }
     print(json.dumps(line), flush=True)
 
 
-def time_form(h, mass_t, p, precision, steps, warmup, serial=False):
-    """Timed solves (no instrumentation), then the same number of profiled solves:
-    the profiled pass runs serially with hipEvents around every launch."""
+def time_form(h, mass_t, p, precision, steps, warmup, serial=False, autotune=True):
+    """Autotuned plan (tap splits), timed solves (no instrumentation), then the same
+    number of profiled solves: the profiled pass runs serially with hipEvents
+    around every launch."""
     import torch
     import paper_2607_19489_amd as A
     plan = A.Plan(h, p=p, precision=precision, serial=serial)
     info = plan.info()
     phi = torch.zeros(h.total, dtype=torch.float64, device="cuda")
     acc = torch.zeros(h.total, 3, dtype=torch.float64, device="cuda")
+    tune = plan.autotune(mass_t, phi, acc) if autotune else None
     for _ in range(warmup):
         plan.solve(mass_t, phi=phi, acc=acc)
     torch.cuda.synchronize()
@@ -173,7 +176,7 @@ def time_form(h, mass_t, p, precision, steps, warmup, serial=False):
     prof = plan.get_profile()
     plan.set_profiling(False)
     out = {"ms_per_step": 1e3 * dt / steps, "value": info["nleaves"] * steps / dt, "info": info,
-           "kernels": prof, "steps": steps}
+           "kernels": prof, "steps": steps, "autotune": tune}
     phi_np, acc_np = phi.cpu().numpy(), acc.cpu().numpy()
     plan.close()
     return out, phi_np, acc_np
@@ -273,6 +276,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-form run")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default tap splits")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -290,14 +294,15 @@ def main():
     mass_t = torch.from_numpy(m).cuda()
     print(f"[bench] workload {w.name}: {h.nleaves()} leaves", file=sys.stderr, flush=True)
 
-    r32, phi32, acc32 = time_form(h, mass_t, w.p, "fp32", args.steps, args.warmup)
+    r32, phi32, acc32 = time_form(h, mass_t, w.p, "fp32", args.steps, args.warmup, autotune=not args.no_autotune)
     print(f"[bench] fp32 form: {r32['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
-    r32s, _, _ = time_form(h, mass_t, w.p, "fp32", args.steps, 1, serial=True)
+    r32s, _, _ = time_form(h, mass_t, w.p, "fp32", args.steps, 1, serial=True, autotune=not args.no_autotune)
     print(f"[bench] fp32 form, serial launches: {r32s['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     outputs = {"fp32": (phi32, acc32)}
     r64 = None
     if not args.no_fp64:
-        r64, phi64, acc64 = time_form(h, mass_t, w.p, "fp64", max(args.steps // 2, 1), 1)
+        r64, phi64, acc64 = time_form(h, mass_t, w.p, "fp64", max(args.steps // 2, 1), 1,
+                                      autotune=not args.no_autotune)
         outputs["fp64"] = (phi64, acc64)
         print(f"[bench] fp64 form: {r64['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
 
@@ -335,6 +340,7 @@ def main():
                                                 "roofline": roofline(r64, "fp64")},
         "fp32_over_fp64": None if r64 is None else r32["value"] / r64["value"],
         "serial_ms_per_step": r32s["ms_per_step"],
+        "autotune_fp32": r32["autotune"], "autotune_fp64": None if r64 is None else r64["autotune"],
         "profiled_ms_per_step": sum(v["ms"] for v in r32["kernels"].values()) / r32["steps"],
         "error_vs_oracle_sample": errs,
         "algorithmic_flops_per_step": info["flops_m2l"] + info["flops_m2p"] + info["flops_p2p"]

@@ -209,6 +209,30 @@ afmm_status afmm_plan_get_profile(afmm_plan* plan, afmm_stage_time* out, int32_t
 afmm_status afmm_batch_set_profiling(afmm_batch* batch, int32_t enable);
 afmm_status afmm_batch_get_profile(afmm_batch* batch, afmm_stage_time* out, int32_t cap, int32_t* n_out);
 
+/*
+ * Autotuner of the work granularity.  The tap split of M2L and of M2P (how
+ * many blocks share the 189 source offsets of one tile, see tap_split) trades
+ * parallelism against partial-sum traffic and per-block setup; the best value
+ * depends on the hierarchy's shape.  afmm_plan_autotune times candidate splits
+ * (per-launch events, serial launches) on full solves of the caller's data and
+ * keeps, per precision, the fastest M2L split and the fastest M2P split; it
+ * leaves phi/acc holding a full solve and counts as one (AFMM_ALL_LEVELS).
+ * afmm_batch_autotune does the same on a batch and re-captures its graph.
+ * Results of later solves change only through FP rounding order.  Takes a few
+ * dozen solves; no host-visible allocation beyond the partial-sum buffers.
+ */
+typedef struct afmm_tune_result {
+  int32_t m2l_split[2];   /* chosen splits, [0] FP64 kernels, [1] FP32 kernels */
+  int32_t m2p_split[2];
+  double ms_before;       /* summed launch time of one solve before / after */
+  double ms_after;
+  int32_t candidates;     /* candidate configurations timed */
+} afmm_tune_result;
+afmm_status afmm_plan_autotune(afmm_plan* plan, const double* d_mass, double* d_phi, double* d_acc,
+                               void* hip_stream, afmm_tune_result* out);
+afmm_status afmm_batch_autotune(afmm_batch* batch, const double* const* d_mass, double* const* d_phi,
+                                double* const* d_acc, void* hip_stream, afmm_tune_result* out);
+
 const char* afmm_status_string(afmm_status s);
 const char* afmm_last_error(void);
 

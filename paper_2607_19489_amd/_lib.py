@@ -29,6 +29,7 @@ SYMBOLS = [
     "afmm_solve_adjoint", "afmm_batch_create", "afmm_batch_solve", "afmm_batch_get_info",
     "afmm_batch_destroy", "afmm_hierarchy_check", "afmm_status_string", "afmm_last_error",
     "afmm_plan_set_profiling", "afmm_plan_get_profile", "afmm_batch_set_profiling", "afmm_batch_get_profile",
+    "afmm_plan_autotune", "afmm_batch_autotune",
 ]
 
 
@@ -66,6 +67,15 @@ class StageTime(C.Structure):
                 ("bytes", C.c_double)]
 
 
+class TuneResult(C.Structure):
+    _fields_ = [("m2l_split", C.c_int32 * 2), ("m2p_split", C.c_int32 * 2), ("ms_before", C.c_double),
+                ("ms_after", C.c_double), ("candidates", C.c_int32)]
+
+    def as_dict(self):
+        return {"m2l_split": list(self.m2l_split), "m2p_split": list(self.m2p_split),
+                "ms_before": self.ms_before, "ms_after": self.ms_after, "candidates": self.candidates}
+
+
 class AfmmError(RuntimeError):
     def __init__(self, code: int, what: str, detail: str):
         super().__init__(f"{what}: {STATUS.get(code, code)} ({detail})")
@@ -101,6 +111,8 @@ def lib():
     L.afmm_plan_get_profile.argtypes = [vp, C.POINTER(StageTime), C.c_int32, C.POINTER(C.c_int32)]
     L.afmm_batch_set_profiling.argtypes = [vp, C.c_int32]
     L.afmm_batch_get_profile.argtypes = [vp, C.POINTER(StageTime), C.c_int32, C.POINTER(C.c_int32)]
+    L.afmm_plan_autotune.argtypes = [vp, vp, vp, vp, vp, C.POINTER(TuneResult)]
+    L.afmm_batch_autotune.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), vp, C.POINTER(TuneResult)]
     L.afmm_status_string.argtypes = [C.c_int32]
     L.afmm_status_string.restype = C.c_char_p
     L.afmm_last_error.argtypes = []
@@ -108,7 +120,8 @@ def lib():
     for name in ("afmm_plan_create", "afmm_plan_destroy", "afmm_plan_get_info", "afmm_solve",
                  "afmm_solve_adjoint", "afmm_batch_create", "afmm_batch_solve", "afmm_batch_get_info",
                  "afmm_batch_destroy", "afmm_hierarchy_check", "afmm_plan_set_profiling",
-                 "afmm_plan_get_profile", "afmm_batch_set_profiling", "afmm_batch_get_profile"):
+                 "afmm_plan_get_profile", "afmm_batch_set_profiling", "afmm_batch_get_profile",
+                 "afmm_plan_autotune", "afmm_batch_autotune"):
         getattr(L, name).restype = C.c_int32
     _lib = L
     return L

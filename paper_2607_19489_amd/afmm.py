@@ -12,7 +12,7 @@ import numpy as np
 import torch
 
 from ._lib import (AFMM_ALL_LEVELS, AFMM_CHECK_INPUT, AFMM_FP32_MIXED, AFMM_FP64, AFMM_SERIAL, HierarchyC, Options,
-                   PlanInfo, StageTime, check, lib)
+                   PlanInfo, StageTime, TuneResult, check, lib)
 
 PRECISIONS = {"fp64": AFMM_FP64, "fp32": AFMM_FP32_MIXED, "mixed": AFMM_FP32_MIXED}
 
@@ -143,6 +143,20 @@ class Plan:
               "afmm_solve")
         return phi, acc
 
+    def autotune(self, mass: torch.Tensor, phi: Optional[torch.Tensor] = None, acc: Optional[torch.Tensor] = None,
+                 stream: Optional[torch.cuda.Stream] = None) -> dict:
+        """afmm_plan_autotune: pick the M2L / M2P tap splits by timing; leaves a full solve in phi/acc."""
+        self._check_tensor(mass, (self.N,), "mass")
+        if phi is None:
+            phi = torch.zeros(self.N, dtype=torch.float64, device=mass.device)
+        if acc is None:
+            acc = torch.zeros(self.N, 3, dtype=torch.float64, device=mass.device)
+        res = TuneResult()
+        check(lib().afmm_plan_autotune(self._ptr, C.c_void_p(mass.data_ptr()), C.c_void_p(phi.data_ptr()),
+                                       C.c_void_p(acc.data_ptr()), _stream_handle(stream), C.byref(res)),
+              "afmm_plan_autotune")
+        return res.as_dict()
+
     def solve_adjoint(self, phi_bar: torch.Tensor, acc_bar: torch.Tensor, level: int = AFMM_ALL_LEVELS,
                       mass_bar: Optional[torch.Tensor] = None, stream: Optional[torch.cuda.Stream] = None):
         """afmm_solve_adjoint: returns mass_bar[N] = A^T (phi_bar, acc_bar)."""
@@ -197,9 +211,7 @@ class Batch:
     def get_profile(self) -> dict:
         return _profile(lib().afmm_batch_get_profile, self._ptr, "afmm_batch_get_profile")
 
-    def solve(self, masses: Sequence[torch.Tensor], phis: Optional[Sequence[torch.Tensor]] = None,
-              accs: Optional[Sequence[torch.Tensor]] = None, stream: Optional[torch.cuda.Stream] = None):
-        """afmm_batch_solve: returns the lists (phis, accs)."""
+    def _arrays(self, masses, phis, accs):
         n = len(self.sizes)
         if len(masses) != n:
             raise ValueError(f"expected {n} mass tensors")
@@ -214,6 +226,20 @@ class Batch:
         mp = (C.c_void_p * n)(*[t.data_ptr() for t in masses])
         pp = (C.c_void_p * n)(*[t.data_ptr() for t in phis])
         ap = (C.c_void_p * n)(*[t.data_ptr() for t in accs])
+        return phis, accs, mp, pp, ap
+
+    def autotune(self, masses: Sequence[torch.Tensor], stream: Optional[torch.cuda.Stream] = None) -> dict:
+        """afmm_batch_autotune: pick the tap splits by timing and capture the graph again."""
+        _, _, mp, pp, ap = self._arrays(masses, None, None)
+        res = TuneResult()
+        check(lib().afmm_batch_autotune(self._ptr, mp, pp, ap, _stream_handle(stream), C.byref(res)),
+              "afmm_batch_autotune")
+        return res.as_dict()
+
+    def solve(self, masses: Sequence[torch.Tensor], phis: Optional[Sequence[torch.Tensor]] = None,
+              accs: Optional[Sequence[torch.Tensor]] = None, stream: Optional[torch.cuda.Stream] = None):
+        """afmm_batch_solve: returns the lists (phis, accs)."""
+        phis, accs, mp, pp, ap = self._arrays(masses, phis, accs)
         check(lib().afmm_batch_solve(self._ptr, mp, pp, ap, _stream_handle(stream)), "afmm_batch_solve")
         return phis, accs
 

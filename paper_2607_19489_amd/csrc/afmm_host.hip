@@ -871,6 +871,59 @@ static int append_tiles(const Topology& T, int target, const std::vector<int32_t
   return n;
 }
 
+static void dev_free(afmm_plan* P, void* ptr, size_t bytes) {
+  if (!ptr) return;
+  for (size_t i = 0; i < P->allocs.size(); ++i)
+    if (P->allocs[i] == ptr) {
+      P->allocs.erase(P->allocs.begin() + (long)i);
+      break;
+    }
+  (void)hipFree(ptr);
+  P->bytes -= bytes;
+}
+
+// Partial-sum buffers of the tap splits: M2P partial sets per leaf level and
+// M2L tap-range partials per FMM level, for the plan's current splits.  Frees
+// earlier ones (after a device sync) and refreshes the device copy of lv[].
+static afmm_status alloc_split_buffers(afmm_plan* P) {
+  const Topology& T = P->topo;
+  const int K = P->K;
+  afmm_status s;
+  const bool had = P->d_lvs != nullptr;
+  if (had && hipDeviceSynchronize() != hipSuccess) return fail(AFMM_E_DEVICE, "sync before reallocation");
+  for (int l = 0; l <= T.lmax; ++l) {
+    LevelDev& D = P->lv[l];
+    dev_free(P, D.part, D.part_bytes);
+    dev_free(P, D.Lpart, D.Lpart_bytes);
+    D.part = D.Lpart = nullptr;
+    D.part_bytes = D.Lpart_bytes = 0;
+    D.npart = 0;
+  }
+  for (int l = 3; l <= T.lmax; ++l) {
+    if (T.leafgrp[l].empty()) continue;
+    const int pr = P->m2p_range[l][0];
+    const size_t b = (size_t)P->m2p_split[pr] * T.lv[l - 1].nref() * 32 * (pr ? sizeof(float) : sizeof(double));
+    void* q = nullptr;
+    if ((s = dev_alloc(P, &q, b))) return s;
+    P->lv[l - 1].part = q;
+    P->lv[l - 1].part_bytes = b;
+    P->lv[l - 1].npart = P->m2p_split[pr];
+  }
+  for (int f = 3; f <= T.lmax - 1; ++f) {
+    const int pm = P->m2l_range[f][0];
+    if (P->m2l_split[pm] > 1 && P->m2l_range[f][2] > 0) {
+      const size_t b = (size_t)P->m2l_split[pm] * T.lv[f].nref() * K * (pm ? sizeof(float) : sizeof(double));
+      void* q = nullptr;
+      if ((s = dev_alloc(P, &q, b))) return s;
+      P->lv[f].Lpart = q;
+      P->lv[f].Lpart_bytes = b;
+    }
+  }
+  if (had && hipMemcpy(P->d_lvs, P->lv, sizeof(LevelDev) * (kMaxLevel + 1), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(AFMM_E_DEVICE, "level table refresh failed");
+  return AFMM_OK;
+}
+
 // Allocate and upload everything of a plan whose topology is built.
 static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
   Topology& T = P->topo;
@@ -1015,25 +1068,7 @@ static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
                          : nt > 0              ? std::max(1, std::min(8, (12 * ncu + nt - 1) / nt))
                                                : 1;
     }
-    for (int l = 3; l <= T.lmax; ++l) {
-      if (T.leafgrp[l].empty()) continue;
-      const int pr = P->m2p_range[l][0];
-      void* q = nullptr;
-      if ((s = dev_alloc(P, &q, (size_t)P->m2p_split[pr] * T.lv[l - 1].nref() * 32 *
-                                    (pr ? sizeof(float) : sizeof(double)))))
-        return s;
-      P->lv[l - 1].part = q;
-      P->lv[l - 1].npart = P->m2p_split[pr];
-    }
-    for (int f = 3; f <= T.lmax - 1; ++f) {
-      const int pm = P->m2l_range[f][0];
-      if (P->m2l_split[pm] > 1 && P->m2l_range[f][2] > 0) {
-        void* q = nullptr;
-        if ((s = dev_alloc(P, &q, (size_t)P->m2l_split[pm] * T.lv[f].nref() * K * (pm ? sizeof(float) : sizeof(double)))))
-          return s;
-        P->lv[f].Lpart = q;
-      }
-    }
+    if ((s = alloc_split_buffers(P))) return s;
     for (int pr = 0; pr < 2; ++pr) {
       int32_t* d = nullptr;
       if ((s = upload(P, m2p_rec[pr], &d, st))) return s;
@@ -1336,6 +1371,152 @@ extern "C" afmm_status afmm_plan_get_profile(afmm_plan* P, afmm_stage_time* out,
   return AFMM_OK;
 }
 
+static afmm_status capture_batch(afmm_batch* B);
+
+// ---------------------------------------------------------------------------
+// Autotuner: the tap splits of M2L and M2P set the work per block (how many of
+// a tile's 189 source offsets one block sums).  Each candidate is timed with
+// per-launch events over a few solves of the caller's data; per precision the
+// split with the smallest time of its kernel family plus the family that sums
+// its partials (L2L for M2L, the leaf kernel for M2P) is kept.
+namespace {
+template <typename SolveFn>
+afmm_status autotune_core(afmm_plan* P, SolveFn solve, hipStream_t st, afmm_tune_result* out) {
+  const bool prof = P->profiling;
+  P->profiling = true;
+  const int m2l0[2] = {P->m2l_split[0], P->m2l_split[1]};
+  const int m2p0[2] = {P->m2p_split[0], P->m2p_split[1]};
+  auto measure = [&](double* kind_ms) -> afmm_status {
+    afmm_status s;
+    for (int r = 0; r < 4; ++r)
+      if ((s = solve())) return s;
+    if (hipStreamSynchronize(st) != hipSuccess) return fail(AFMM_E_DEVICE, "autotune sync");
+    std::memset(kind_ms, 0, sizeof(double) * kNumKinds);
+    // drop the first solve of the four (warm-up), average the rest
+    size_t per = P->recs.size() / 4;
+    for (size_t i = 0; i < P->recs.size(); ++i) {
+      auto& r = P->recs[i];
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, r.a, r.b);
+      if (i >= per) kind_ms[r.kind] += ms / 3.0;
+      P->event_pool.push_back(r.a);
+      P->event_pool.push_back(r.b);
+    }
+    P->recs.clear();
+    return AFMM_OK;
+  };
+  afmm_status s;
+  double k0[kNumKinds];
+  // baseline with the current splits
+  for (auto& r : P->recs) {
+    P->event_pool.push_back(r.a);
+    P->event_pool.push_back(r.b);
+  }
+  P->recs.clear();
+  if ((s = measure(k0))) return s;
+  double before = 0;
+  for (int k = 0; k < kNumKinds; ++k) before += k0[k];
+  static const int cand_m2l[] = {1, 2, 3, 4, 6, 8, 12, 16, 21};
+  static const int cand_m2p[] = {1, 2, 3, 4, 6, 8};
+  double best_l[2] = {1e300, 1e300}, best_p[2] = {1e300, 1e300};
+  int arg_l[2] = {m2l0[0], m2l0[1]}, arg_p[2] = {m2p0[0], m2p0[1]};
+  for (int c : cand_m2l) {
+    P->m2l_split[0] = P->m2l_split[1] = c;
+    if ((s = alloc_split_buffers(P))) return s;
+    double km[kNumKinds];
+    if ((s = measure(km))) return s;
+    for (int pr = 0; pr < 2; ++pr) {
+      const double t = km[pr ? kM2L32 : kM2L64] + km[kL2L];
+      if (t < best_l[pr]) best_l[pr] = t, arg_l[pr] = c;
+    }
+  }
+  P->m2l_split[0] = arg_l[0];
+  P->m2l_split[1] = arg_l[1];
+  for (int c : cand_m2p) {
+    P->m2p_split[0] = P->m2p_split[1] = c;
+    if ((s = alloc_split_buffers(P))) return s;
+    double km[kNumKinds];
+    if ((s = measure(km))) return s;
+    for (int pr = 0; pr < 2; ++pr) {
+      const double t = km[pr ? kM2P32 : kM2P64] + km[pr ? kLeaf32 : kLeaf64];
+      if (t < best_p[pr]) best_p[pr] = t, arg_p[pr] = c;
+    }
+  }
+  P->m2p_split[0] = arg_p[0];
+  P->m2p_split[1] = arg_p[1];
+  if ((s = alloc_split_buffers(P))) return s;
+  double k1[kNumKinds];
+  if ((s = measure(k1))) return s;
+  double after = 0;
+  for (int k = 0; k < kNumKinds; ++k) after += k1[k];
+  P->profiling = prof;
+  if (out) {
+    for (int pr = 0; pr < 2; ++pr) {
+      out->m2l_split[pr] = P->m2l_split[pr];
+      out->m2p_split[pr] = P->m2p_split[pr];
+    }
+    out->ms_before = before;
+    out->ms_after = after;
+    out->candidates = (int32_t)(sizeof(cand_m2l) / sizeof(int) + sizeof(cand_m2p) / sizeof(int));
+  }
+  return AFMM_OK;
+}
+}  // namespace
+
+extern "C" afmm_status afmm_plan_autotune(afmm_plan* P, const double* d_mass, double* d_phi, double* d_acc,
+                                          void* hip_stream, afmm_tune_result* out) {
+  if (!P || !d_mass || !d_phi || !d_acc) return fail(AFMM_E_INVALID_ARG, "null argument");
+  if (P->dead) return fail(AFMM_E_DEVICE, "plan is unusable after an earlier device error");
+  const Topology& T = P->topo;
+  if (T.levelmin.size() != 1) return fail(AFMM_E_INVALID_ARG, "batched plan: use afmm_batch_autotune");
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int lmin = T.levelmin[0], lmax = T.levelmax[0];
+  auto solve = [&]() { return run_solve(P, d_mass, T.lmax - 1, lmin, lmax, d_phi, d_acc, st); };
+  afmm_status s = autotune_core(P, solve, st, out);
+  if (s) return s;
+  // the autotune solves were synchronous full solves: they also rebuilt every tree
+  if (hipMemcpyAsync(P->m_snap, d_mass, (size_t)T.nslots * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return dev_check(P, hipGetLastError(), "snapshot");
+  P->snap_valid = true;
+  P->solved = true;
+  P->last_level = AFMM_ALL_LEVELS;
+  P->last_fresh = 0;
+  return AFMM_OK;
+}
+
+extern "C" afmm_status afmm_batch_autotune(afmm_batch* B, const double* const* d_mass, double* const* d_phi,
+                                           double* const* d_acc, void* hip_stream, afmm_tune_result* out) {
+  if (!B || !d_mass || !d_phi || !d_acc) return fail(AFMM_E_INVALID_ARG, "null argument");
+  afmm_plan* P = B->plan;
+  if (P->dead) return fail(AFMM_E_DEVICE, "batch is unusable after an earlier device error");
+  const int32_t n = B->n;
+  for (int32_t i = 0; i < n; ++i) {
+    if (!d_mass[i] || !d_phi[i] || !d_acc[i]) return fail(AFMM_E_INVALID_ARG, "null array in batch");
+    B->h_ptrs[i] = (void*)d_mass[i];
+    B->h_ptrs[n + i] = (void*)d_phi[i];
+    B->h_ptrs[2 * n + i] = (void*)d_acc[i];
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  afmm_status s;
+  if ((s = dev_check(P, hipMemcpyAsync(B->d_ptrs, B->h_ptrs.data(), (size_t)3 * n * sizeof(void*),
+                                       hipMemcpyHostToDevice, st),
+                     "batch pointer table")))
+    return s;
+  const Topology& T = P->topo;
+  auto solve = [&]() -> afmm_status {
+    afmm_status r;
+    if ((r = dev_check(P, launch_batch_in(B->nleaf, B->d_leafslot, B->d_leafhier, B->d_base,
+                                          (const double* const*)B->d_ptrs, B->d_mass, st),
+                       "batch gather")))
+      return r;
+    return run_solve(P, B->d_mass, T.lmax - 1, T.lmin_all, T.lmax, B->d_phi, B->d_acc, st);
+  };
+  if ((s = autotune_core(P, solve, st, out))) return s;
+  if (hipStreamSynchronize(st) != hipSuccess) return fail(AFMM_E_DEVICE, "autotune sync");
+  // kernel arguments and grids changed: capture the graph again
+  return capture_batch(B);
+}
+
 // Adjoint workspace: target bars and mass bars on every level, source-copy /
 // multipole bars on the multipole levels 2..lmax-1, local-expansion bars on
 // the FMM levels 3..lmax-1.
@@ -1495,6 +1676,41 @@ static void free_batch(afmm_batch* B) {
   B->plan = nullptr;
 }
 
+// Capture gather -> solve -> scatter of a batch into its graph (replacing an
+// earlier one).
+static afmm_status capture_batch(afmm_batch* B) {
+  afmm_plan* P = B->plan;
+  const Topology& T = P->topo;
+  const int n = B->n;
+  if (B->exec) (void)hipGraphExecDestroy(B->exec);
+  if (B->graph) (void)hipGraphDestroy(B->graph);
+  B->exec = nullptr;
+  B->graph = nullptr;
+  const bool prof = P->profiling;
+  P->profiling = false;
+  hipStream_t cs = B->cap;
+  afmm_status s = AFMM_OK;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    s = fail(AFMM_E_DEVICE, "graph capture could not start");
+  } else {
+    afmm_status sr = dev_check(P, launch_batch_in(B->nleaf, B->d_leafslot, B->d_leafhier, B->d_base,
+                                                  (const double* const*)B->d_ptrs, B->d_mass, cs),
+                               "batch gather");
+    if (!sr) sr = run_solve(P, B->d_mass, T.lmax - 1, T.lmin_all, T.lmax, B->d_phi, B->d_acc, cs);
+    if (!sr)
+      sr = dev_check(P, launch_batch_out(B->nleaf, B->d_leafslot, B->d_leafhier, B->d_base, B->d_phi, B->d_acc,
+                                         (double* const*)(B->d_ptrs + n), (double* const*)(B->d_ptrs + 2 * n), cs),
+                     "batch scatter");
+    const hipError_t ee = hipStreamEndCapture(cs, &B->graph);
+    if (sr) s = sr;
+    else if (ee != hipSuccess || !B->graph) s = fail(AFMM_E_DEVICE, "graph capture failed");
+    else if (hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0) != hipSuccess)
+      s = fail(AFMM_E_DEVICE, "graph instantiation failed");
+  }
+  P->profiling = prof;
+  return s;
+}
+
 extern "C" afmm_status afmm_batch_create(afmm_plan* const* plans, int32_t n, void* hip_stream, afmm_batch** out) {
   if (!plans || !out || n < 1) return fail(AFMM_E_INVALID_ARG, "null argument or n < 1");
   *out = nullptr;
@@ -1553,27 +1769,7 @@ extern "C" afmm_status afmm_batch_create(afmm_plan* const* plans, int32_t n, voi
         hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking) != hipSuccess)
       s = fail(AFMM_E_DEVICE, "batch stream creation failed");
   }
-  if (!s) {
-    const Topology& T = P->topo;
-    hipStream_t cs = B->cap;
-    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-      s = fail(AFMM_E_DEVICE, "graph capture could not start");
-    } else {
-      afmm_status sr = dev_check(P, launch_batch_in(B->nleaf, B->d_leafslot, B->d_leafhier, B->d_base,
-                                                    (const double* const*)B->d_ptrs, B->d_mass, cs),
-                                 "batch gather");
-      if (!sr) sr = run_solve(P, B->d_mass, T.lmax - 1, T.lmin_all, T.lmax, B->d_phi, B->d_acc, cs);
-      if (!sr)
-        sr = dev_check(P, launch_batch_out(B->nleaf, B->d_leafslot, B->d_leafhier, B->d_base, B->d_phi, B->d_acc,
-                                           (double* const*)(B->d_ptrs + n), (double* const*)(B->d_ptrs + 2 * n), cs),
-                       "batch scatter");
-      const hipError_t ee = hipStreamEndCapture(cs, &B->graph);
-      if (sr) s = sr;
-      else if (ee != hipSuccess || !B->graph) s = fail(AFMM_E_DEVICE, "graph capture failed");
-      else if (hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0) != hipSuccess)
-        s = fail(AFMM_E_DEVICE, "graph instantiation failed");
-    }
-  }
+  if (!s) s = capture_batch(B);
   if (s) {
     free_batch(B);
     delete B;

@@ -66,6 +66,7 @@ struct LevelDev {
   void* part = nullptr;              // [npart][nref][32] intermediate-field partials of the leaf children (T of the
                                      // leaf level), one set per M2P tap range
   int32_t npart = 0;
+  size_t part_bytes = 0, Lpart_bytes = 0;
   void* Lpart = nullptr;             // [nsplit][nref][K] M2L tap-range partial sums (T of the level), if split
   // adjoint pass (FP64, allocated by the first adjoint call)
   double* tbar = nullptr;            // [n][4] unit-form bars of the target leaves (phi, ax, ay, az)

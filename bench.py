@@ -182,28 +182,52 @@ def time_form(h, mass_t, p, precision, steps, warmup, serial=False, autotune=Tru
     return out, phi_np, acc_np
 
 
-def roofline(res, precision):
+SYMBOLS = {"m2p_f32": "k_m2p<float, {p}>", "m2p_f64": "k_m2p<double, {p}>",
+           "m2l_f32": "k_m2l_mfma<float, {p}>", "m2l_f64": "k_m2l_mfma<double, {p}>",
+           "near_f32": "k_near<float, {p}>", "near_f64": "k_near<double, {p}>", "upward": "k_upward<{p}>"}
+
+
+def measured_traffic(family, p, workload):
+    """HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE summary of this
+    kernel and workload, or None (none taken, or the kernels changed since)."""
+    import glob
+    sys.path.insert(0, ROOT)
+    from bench_profile import source_hash
+    want = SYMBOLS.get(family, "").format(p=p)
+    for f in glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json")):
+        try:
+            t = json.load(open(f))
+        except (OSError, ValueError):
+            continue
+        if t.get("kernel") == want and t.get("workload") == workload and t.get("source_sha256") == source_hash():
+            return t["traffic_bytes_per_launch"], os.path.relpath(f, ROOT)
+    return None, None
+
+
+def roofline(res, precision, p=None, workload=None):
     """Roofline of the kernel family with the largest summed time in the timed region."""
     prof = res["kernels"]
     name, k = max(prof.items(), key=lambda kv: kv[1]["ms"])
     total_ms = sum(v["ms"] for v in prof.values())
+    traffic, tsrc = measured_traffic(name, p, workload) if p is not None else (None, None)
     common = {"kernel": KERNEL_NAMES.get(name, name), "family": name, "launches": k["launches"],
+              "traffic_source": tsrc,
               "avg_launch_ms": k["ms"] / max(k["launches"], 1),
               "flops_per_launch": k["flops"] / max(k["launches"], 1),
               "bytes_per_launch": k["bytes"] / max(k["launches"], 1), "share_of_step": k["ms"] / total_ms}
     if name in ("gather", "upward", "l2l"):
         achieved = k["bytes"] / (k["ms"] * 1e-3) / 1e9
         return {"bound": "hbm", "achieved": achieved, "peak": PEAK["hbm"], "unit": "GB/s",
-                "frac": achieved / PEAK["hbm"], "traffic": None, **common}
+                "frac": achieved / PEAK["hbm"], "traffic": traffic, **common}
     tf = k["flops"] / (k["ms"] * 1e-3) / 1e12 if k["ms"] > 0 else 0.0
     fp = "fp32" if name.endswith("f32") else "fp64"
     if name in MFMA_FAMILIES:
         peak = PEAK[f"{fp}_mfma"]
         return {"bound": "mfma", "achieved": tf, "peak": peak, "unit": "TFLOP/s", "frac": tf / peak,
-                "traffic": None, **common}
+                "traffic": traffic, **common}
     peak = PEAK[f"{fp}_vector"]
     return {"bound": "alu", "achieved": tf, "peak": peak, "unit": "TFLOP/s", "frac": tf / peak,
-            "traffic": None, **common}
+            "traffic": traffic, **common}
 
 
 def kernel_table(res):
@@ -277,6 +301,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-form run")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tap splits")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 256 MiB device copy (reference for the FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -286,6 +312,13 @@ def main():
 
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration:
+        src = torch.ones(256 * 1024 * 1024 // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.workload == "cfg4":
         run_batch(args)
         return
@@ -333,11 +366,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{w.name}: {desc}", "p": w.p, "precision": "FP32 mixed (FP64 P2M/M2M, "
                    "FMM levels <= 4 and outputs)", "leaves": info["nleaves"], "levels": [h.levelmin, h.levelmax]},
-        "roofline": roofline(r32, "fp32"),
+        "roofline": roofline(r32, "fp32", w.p, w.name),
         "cpu_baseline": base,
         "fp64_form": None if r64 is None else {"value": r64["value"], "unit": "cells/s",
                                                 "ms_per_step": r64["ms_per_step"], "dtype": "f64",
-                                                "roofline": roofline(r64, "fp64")},
+                                                "roofline": roofline(r64, "fp64", w.p, w.name)},
         "fp32_over_fp64": None if r64 is None else r32["value"] / r64["value"],
         "serial_ms_per_step": r32s["ms_per_step"],
         "autotune_fp32": r32["autotune"], "autotune_fp64": None if r64 is None else r64["autotune"],

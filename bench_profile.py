@@ -1,0 +1,141 @@
+#!/usr/bin/env python3
+"""Summaries of rocprofv3 output for bench.py (text/JSON under profiles/).
+
+  stats:   kernel trace (--kernel-trace --stats) of a bench.py run -> a Markdown
+           table: rocprofv3's own per-kernel statistics over every dispatch, and
+           the per-dispatch statistics of the last N dispatches of each kernel
+           (the timed, autotuned launches; the autotuner's candidates come first).
+  traffic: two --pmc runs of the same command (FETCH_SIZE, then WRITE_SIZE) ->
+           HBM bytes per launch of one kernel, each counter scaled by the reading
+           of the same counter for a plain device copy of known size (the
+           bench's --copy-calibration copy), plus the sha256 of the kernel
+           source, so that bench.py drops the figure once the kernels change.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import re
+import statistics
+import sys
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2607_19489_amd", "csrc", "afmm_kernels.hip")
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+
+
+def source_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+
+
+def short(name: str) -> str:
+    name = re.sub(r"^void ", "", name)
+    name = re.sub(r"\(.*$", "", name)
+    return name.replace("afmm::", "")
+
+
+def _find(d: str, suffix: str):
+    hits = glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True)
+    if not hits:
+        sys.exit(f"no *{suffix} under {d}")
+    return hits[0]
+
+
+def cmd_stats(a):
+    stats = list(csv.DictReader(open(_find(a.trace, "kernel_stats.csv"))))
+    trace = list(csv.DictReader(open(_find(a.trace, "kernel_trace.csv"))))
+    per = {}
+    for r in trace:
+        k = short(r["Kernel_Name"])
+        per.setdefault(k, []).append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    out = [f"# rocprofv3 kernel statistics: {a.title}", "", "Command (repository root on the MI355X box):", "",
+           "```", a.command, "```", "",
+           "## All dispatches (rocprofv3 --stats)", "",
+           "| kernel | calls | total ms | avg us | min us | max us | % |", "|---|---|---|---|---|---|---|"]
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:a.top]:
+        out.append(f"| `{short(r['Name'])}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                   f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
+                   f"{float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
+    out += ["", f"## Last {a.last} dispatches of each kernel (the timed launches after autotuning)", "",
+            "| kernel | dispatches | avg us | median us | min us | max us |", "|---|---|---|---|---|---|"]
+    rows = []
+    for k, v in per.items():
+        v.sort()
+        d = [x[1] / 1e3 for x in v[-a.last:]]
+        rows.append((sum(d), k, d))
+    for tot, k, d in sorted(rows, reverse=True)[:a.top]:
+        out.append(f"| `{k}` | {len(d)} | {statistics.mean(d):.1f} | {statistics.median(d):.1f} | "
+                   f"{min(d):.1f} | {max(d):.1f} |")
+    open(a.out, "w").write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+
+def _pmc(d: str, counter: str):
+    rows = list(csv.DictReader(open(_find(d, "counter_collection.csv"))))
+    per = {}
+    for r in rows:
+        if r["Counter_Name"] != counter:
+            continue
+        key = (short(r["Kernel_Name"]), r.get("Dispatch_Id", ""))
+        per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+    byk = {}
+    for (k, did), v in per.items():
+        byk.setdefault(k, []).append((int(did) if did.isdigit() else 0, v))
+    for v in byk.values():
+        v.sort()
+    return byk
+
+
+def cmd_traffic(a):
+    fetch = _pmc(a.fetch, "FETCH_SIZE")
+    write = _pmc(a.write, "WRITE_SIZE")
+    copy_bytes = a.copy_mib * 1024 * 1024
+    cf = max(v for _, v in fetch[COPY_KERNEL])   # KiB per dispatch of the calibration copy
+    cw = max(v for _, v in write[COPY_KERNEL])
+    f_factor = copy_bytes / (cf * 1024.0)
+    w_factor = copy_bytes / (cw * 1024.0)
+    k = a.kernel
+    fk = [v for _, v in fetch[k][-a.last:]]
+    wk = [v for _, v in write[k][-a.last:]]
+    fb = statistics.median(fk) * 1024.0 * f_factor
+    wb = statistics.median(wk) * 1024.0 * w_factor
+    res = {"kernel": k, "workload": a.workload, "source_sha256": source_hash(), "command_fetch": a.command_fetch,
+           "command_write": a.command_write, "dispatches_used": len(fk),
+           "fetch_kib_per_dispatch": statistics.median(fk), "write_kib_per_dispatch": statistics.median(wk),
+           "calibration": {"copy_bytes": copy_bytes, "copy_fetch_kib": cf, "copy_write_kib": cw,
+                           "fetch_factor": f_factor, "write_factor": w_factor},
+           "traffic_bytes_per_launch": fb + wb, "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb}
+    json.dump(res, open(a.out, "w"), indent=1)
+    print(json.dumps(res, indent=1))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="mode", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("--trace", required=True)
+    s.add_argument("--last", type=int, default=20)
+    s.add_argument("--top", type=int, default=14)
+    s.add_argument("--title", required=True)
+    s.add_argument("--command", required=True)
+    s.add_argument("--out", required=True)
+    t = sub.add_parser("traffic")
+    t.add_argument("--fetch", required=True)
+    t.add_argument("--write", required=True)
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--workload", required=True)
+    t.add_argument("--last", type=int, default=20)
+    t.add_argument("--copy-mib", type=int, default=256)
+    t.add_argument("--command-fetch", required=True)
+    t.add_argument("--command-write", required=True)
+    t.add_argument("--out", required=True)
+    a = ap.parse_args()
+    cmd_stats(a) if a.mode == "stats" else cmd_traffic(a)
+
+
+if __name__ == "__main__":
+    main()

@@ -46,10 +46,71 @@ def make_workload(name: str):
         return configs.cfg2(), ("level 6 + level 7 within r<=0.15 (287,680 leaves, 3,648 refined), "
                                 "Plummer a=0.05 + 1% noise, p=6")
     if name == "cfg3":
-        return configs.cfg3(), "level 7 base + 4 mass-refined levels (~8.08M leaves), Plummer + 32 clumps, p=6"
+        return configs.cfg3(), ("level 7 base + 4 mass-refined levels (8,083,818 leaves), Plummer a=0.05 + 32 "
+                                "Gaussian clumps, p=6")
     if name == "cfg5":
         return configs.cfg5(), "level 7 + r<0.2 + r<0.1 (3,081,632 leaves), Plummer a=0.05, p=6"
     raise ValueError(name)
+
+
+def ats_sequence(lmin, lmax):
+    """Adaptive-time-step solve order (Alg. 1): a level-l step solves l, then runs two
+    steps of level l+1 (icount 1 and 2): 1 + 2 + 4 + ... solves."""
+    seq = []
+
+    def rec(l, icount):
+        seq.append((l, icount))
+        if l < lmax:
+            rec(l + 1, 1)
+            rec(l + 1, 2)
+
+    rec(lmin, 1)
+    return seq
+
+
+def time_ats(h, mass_t, p, precision, reps=2):
+    """One coarse step of the adaptive-time-step sequence, masses of the active
+    levels perturbed by 1e-3 seeded noise before every solve."""
+    import torch
+    import paper_2607_19489_amd as A
+    plan = A.Plan(h, p=p, precision=precision)
+    plan.autotune(mass_t)
+    seq = ats_sequence(h.levelmin, h.levelmax)
+    lev = torch.from_numpy(h.level_of()).cuda()
+    gen = torch.Generator(device="cuda").manual_seed(3)
+    noise = [1.0 + 1e-3 * (2 * torch.rand(h.total, dtype=torch.float64, device="cuda", generator=gen) - 1)
+             for _ in range(len(seq))]
+    masses = []
+    m = mass_t.clone()
+    for (l, _), u in zip(seq, noise):
+        m = torch.where(lev >= l, m * u, m)
+        masses.append(m)
+    phi = torch.zeros(h.total, dtype=torch.float64, device="cuda")
+    acc = torch.zeros(h.total, 3, dtype=torch.float64, device="cuda")
+    per_level = {}
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in seq]
+    best = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for (l, ic), mm, (a, b) in zip(seq, masses, ev):
+            a.record()
+            plan.solve(mm, level=l, icount=ic, phi=phi, acc=acc)
+            b.record()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if best is None or dt < best:
+            best = dt
+            per_level = {}
+            for (l, ic), (a, b) in zip(seq, ev):
+                per_level.setdefault(str(l), []).append(a.elapsed_time(b))
+    info = plan.info()
+    leaf_updates = sum(info["leaves_per_level"][l] for l, _ in seq)
+    plan.close()
+    return {"solves": len(seq), "sequence_ms": 1e3 * best, "leaf_updates": leaf_updates,
+            "leaf_updates_per_s": leaf_updates / best,
+            "mean_ms_per_solve_by_level": {k: sum(v) / len(v) for k, v in per_level.items()},
+            "solves_by_level": {k: len(v) for k, v in per_level.items()}}
 
 
 def time_adjoint(h, mass_t, p, precision, steps):
@@ -297,6 +358,7 @@ def main():
     ap.add_argument("--p", type=int, default=4, help="expansion order of the batched workload (cfg4)")
     ap.add_argument("--members", type=int, default=256, help="hierarchies in the batched workload (cfg4)")
     ap.add_argument("--adjoint", action="store_true", help="also time the adjoint pass (default for cfg5)")
+    ap.add_argument("--ats", action="store_true", help="also time one adaptive-time-step cycle (default for cfg3)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-form run")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -338,6 +400,11 @@ def main():
                                       autotune=not args.no_autotune)
         outputs["fp64"] = (phi64, acc64)
         print(f"[bench] fp64 form: {r64['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+
+    ats = None
+    if args.ats or args.workload == "cfg3":
+        ats = time_ats(h, mass_t, w.p, "fp32")
+        print(f"[bench] ATS step: {ats['solves']} solves in {ats['sequence_ms']:.2f} ms", file=sys.stderr, flush=True)
 
     adj = None
     if args.adjoint or args.workload == "cfg5":
@@ -381,6 +448,7 @@ def main():
         "kernels_fp32": kernel_table(r32),
         "kernels_fp64": None if r64 is None else kernel_table(r64),
         "adjoint": adj,
+        "ats_step": ats,
     }
     print(json.dumps(line), flush=True)
 

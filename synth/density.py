@@ -19,7 +19,13 @@ def plummer(total_mass: float = 1.0, a: float = 0.1, centre=(0.5, 0.5, 0.5)) -> 
     rho0 = 3.0 * total_mass / (4.0 * np.pi * a ** 3)
 
     def rho(x):
-        r2 = np.sum((np.asarray(x, dtype=np.float64) - c) ** 2, axis=-1)
+        x = np.asarray(x, dtype=np.float64)
+        d = x[..., 0] - c[0]
+        r2 = d * d
+        d = x[..., 1] - c[1]
+        r2 += d * d
+        d = x[..., 2] - c[2]
+        r2 += d * d
         return rho0 * (1.0 + r2 / (a * a)) ** (-2.5)
 
     return rho
@@ -34,9 +40,15 @@ def gaussian_clumps(centres: np.ndarray, sigmas: Sequence[float], masses: Sequen
 
     def rho(x):
         x = np.asarray(x, dtype=np.float64)
+        x0, x1, x2 = x[..., 0], x[..., 1], x[..., 2]
         out = np.zeros(x.shape[:-1], dtype=np.float64)
         for c, s, n in zip(centres, sig, norm):
-            r2 = np.sum((x - c) ** 2, axis=-1)
+            d = x0 - c[0]
+            r2 = d * d
+            d = x1 - c[1]
+            r2 += d * d
+            d = x2 - c[2]
+            r2 += d * d
             out += n * np.exp(-0.5 * r2 / (s * s))
         return out
 

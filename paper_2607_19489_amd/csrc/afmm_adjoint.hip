@@ -1,4 +1,6 @@
-// Adjoint (transposed) pass of the adaptive FMM, FP64.
+// Adjoint (transposed) pass of the adaptive FMM.  The translation products
+// (M2P^T, M2L^T) run on MFMA in the precision of the forward kernel of the same
+// level; bars are accumulated in FP64.
 //
 // A solve is a linear map m -> (phi, a).  These kernels apply its transpose:
 // given bars (phi_bar, a_bar) on the target leaves they return m_bar, running
@@ -9,11 +11,11 @@
 //   near P2P / nearest P2P (Sec. 3.2)          P2P^T gathered per source leaf     k_adj_near_leaf
 //   near M2P from refined level-l cells        M2P^T into the level-l source bar  k_adj_near_m2p
 //   L2P (far field)                            L2P^T into the father's L bar      k_adj_l2p
-//   M2P, intermediate field                    M2P^T per source cell              k_adj_m2p
+//   M2P, intermediate field                    M2P^T per source cell (MFMA)       k_adj_m2p_mfma
 //   L2L (Eq. eq:L2L), top-down                 L2L^T, bottom-up                   k_adj_l2l
-//   M2L (Eq. eq:M2L), 189-cell list            M2L^T per source cell              k_adj_m2l
+//   M2L (Eq. eq:M2L), 189-cell list            M2L^T per source cell (MFMA)       k_adj_m2l_mfma
 //   source copy c_a 2^|a| S~_a                 scale of the source bar            k_adj_down
-//   M2M (Eq. eq:M2M_general), bottom-up        M2M^T, top-down                    k_adj_down
+//   M2M (Eq. eq:M2M_general), bottom-up        M2M^T, top-down                    k_adj_down, k_adj_leafup
 //   mass gather (slot -> cell)                 scatter (cell -> slot)             k_adj_out
 //
 // Every relation is gathered from the receiving side, so no atomics are needed
@@ -24,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include "afmm_internal.h"
+#include "afmm_mfma.h"
 
 namespace afmm {
 
@@ -46,7 +49,6 @@ __device__ inline double p2p_adj(double rx, double ry, double rz, const double* 
 // sign of child octant o in the signed child sum of parity class q
 __device__ inline double parity_sign(int q, int o) { return (__popc(q & ~o) & 1) ? -1.0 : 1.0; }
 
-constexpr int threads_for(int K) { return ((K + 63) / 64) * 64; }
 
 }  // namespace
 
@@ -190,72 +192,12 @@ __global__ __launch_bounds__(256) void k_adj_l2p(LevelDev lv1, LevelDev lv0, con
   }
 }
 
-// Transposed-tap resolution for source cell s = 8 P + os at level l-1: the
-// group F (refined rank at level l-1) and offset index of each tap, or -1.
-__device__ inline void resolve_taps(int s, const LevelDev& lv2, const LevelDev& lv1, const int32_t* __restrict__ tapsT,
-                                    int* sF, int* sDi) {
-  const int os = s & 7, P = s >> 3;
-  for (int i = threadIdx.x; i < kTapsT; i += blockDim.x) {
-    const int code = tapsT[os * kTapsT + i];
-    const int e = code & 31, oF = (code >> 5) & 7;
-    int rF = -1;
-    const int Q = lv2.nbr[(size_t)P * 27 + e];
-    if (Q >= 0) {
-      const int rQ = lv2.rank[Q];
-      if (rQ >= 0) rF = lv1.rank[8 * rQ + oF];
-    }
-    sF[i] = rF;
-    sDi[i] = code >> 8;
-  }
-}
-
-// Intermediate-field M2P^T (block = one source cell s of level l-1): the leaf
-// children c of every group F whose list holds s read c_a 2^|a| S~_a[s] (or
-// the mass of a leaf s) with D~ at R~ = c - s.
-template <int P>
-__global__ __launch_bounds__(threads_for(nmi(P))) void k_adj_m2p(LevelDev lv2, LevelDev lv1, LevelDev lv0,
-                                                                  const int32_t* __restrict__ tapsT,
-                                                                  const double* __restrict__ Dil,
-                                                                  const int16_t* __restrict__ up) {
-  constexpr int K = nmi(P), K1 = nmi(P - 1), NT = threads_for(K);
-  __shared__ int sF[kTapsT], sDi[kTapsT];
-  __shared__ double sD[8 * K];
-  __shared__ double sT[32];
-  const int s = blockIdx.x;
-  const int t = threadIdx.x;
-  resolve_taps(s, lv2, lv1, tapsT, sF, sDi);
-  const int rs = lv1.rank[s];
-  double acc = 0.0;
-  for (int i = 0; i < kTapsT; ++i) {
-    __syncthreads();
-    const int rF = sF[i];
-    if (rF < 0) continue;
-    const double* Dr = Dil + (size_t)sDi[i] * 8 * K;
-    for (int k = t; k < 8 * K; k += NT) sD[k] = Dr[k];
-    if (t < 32) sT[t] = lv0.tbar[4 * (size_t)(8 * rF) + t];
-    __syncthreads();
-    if (t < K && (rs >= 0 || t == 0)) {
-      for (int o = 0; o < 8; ++o) {
-        const double* D = sD + o * K;
-        double v = D[t] * sT[4 * o];
-        if (t < K1) v -= D[up[3 * t + 0]] * sT[4 * o + 1] + D[up[3 * t + 1]] * sT[4 * o + 2] +
-                         D[up[3 * t + 2]] * sT[4 * o + 3];
-        acc += v;
-      }
-    }
-  }
-  if (rs >= 0) {
-    if (t < K) lv1.sbar[(size_t)rs * K + t] += acc;
-  } else if (t == 0) {
-    lv1.mbar[s] += acc;
-  }
-}
-
 // L2L^T (block = one refined cell F of level f-1): L_bar[F]_c += sum over the
-// refined children y and b <= c of 2^(-1-|b|) u^(c-b)/(c-b)! L_bar[y]_b.
+// refined children y of 2^(-1-|b|) u^(c-b)/(c-b)! L_bar[y]_b, b <= c; the
+// (b, c - b) pairs of each c come from a host table (cm.l2lT_*).
 template <int P>
 __global__ __launch_bounds__(256) void k_adj_l2l(LevelDev lv1, LevelDev lv0, const double* __restrict__ l2lw,
-                                                 const int8_t* __restrict__ mi) {
+                                                 CommonDev cm) {
   constexpr int K = nmi(P);
   __shared__ double sL[8 * K];
   __shared__ int sR[8];
@@ -269,65 +211,38 @@ __global__ __launch_bounds__(256) void k_adj_l2l(LevelDev lv1, LevelDev lv0, con
   }
   __syncthreads();
   for (int c = t; c < K; c += 256) {
-    const int c0 = mi[4 * c], c1 = mi[4 * c + 1], c2 = mi[4 * c + 2];
     double acc = 0.0;
-    for (int b = 0; b <= c; ++b) {
-      const int g0 = c0 - mi[4 * b], g1 = c1 - mi[4 * b + 1], g2 = c2 - mi[4 * b + 2];
-      if (g0 < 0 || g1 < 0 || g2 < 0) continue;
-      const int g = mi_index(g0, g1, g2), nb = mi[4 * b + 3];
+    for (int j = cm.l2lT_start[c]; j < cm.l2lT_start[c + 1]; ++j) {
+      const int code = cm.l2lT_list[j];
+      const int b = code & 255, g = (code >> 8) & 255, nb = code >> 16;
+#pragma unroll
       for (int o = 0; o < 8; ++o) acc += l2lw[((size_t)o * (P + 1) + nb) * K + g] * sL[o * K + b];
     }
     lv1.lbar[(size_t)F * K + c] += acc;
   }
 }
 
-// M2L^T (block = one source cell s of level f-1): every refined child y of a
-// group F whose list holds s reads c_a 2^|a| S~_a[s] through D~_(a+b)(R~),
-// R~ = y - s, |a| + |b| <= p.
+// M2M^T into the leaf children of the refined cells of level l-1: the
+// monopole entry of every coefficient, folded per parity class first
+// (Y_q = sum over a of parity q of w_a S_bar_a), then m_bar(o) += sum_q sign_q(o) Y_q.
 template <int P>
-__global__ __launch_bounds__(threads_for(nmi(P))) void k_adj_m2l(LevelDev lv2, LevelDev lv1, LevelDev lv0,
-                                                                  const int32_t* __restrict__ tapsT,
-                                                                  const double* __restrict__ Dil,
-                                                                  const int16_t* __restrict__ sumidx,
-                                                                  const int8_t* __restrict__ mi) {
-  constexpr int K = nmi(P), NT = threads_for(K);
-  __shared__ int sF[kTapsT], sDi[kTapsT];
-  __shared__ double sD[8 * K];
-  __shared__ double sL[8 * K];
-  __shared__ int sR[8];
-  const int s = blockIdx.x;
-  const int t = threadIdx.x;
-  resolve_taps(s, lv2, lv1, tapsT, sF, sDi);
-  const int rs = lv1.rank[s];
-  const int na = t < K ? nmi(P - mi[4 * t + 3]) : 0;  // b range of row a = t
-  double acc = 0.0;
-  for (int i = 0; i < kTapsT; ++i) {
-    __syncthreads();
-    const int rF = sF[i];
-    if (rF < 0) continue;
-    if (t < 8) sR[t] = lv0.rank[8 * rF + t];
-    const double* Dr = Dil + (size_t)sDi[i] * 8 * K;
-    for (int k = t; k < 8 * K; k += NT) sD[k] = Dr[k];
-    __syncthreads();
-    for (int k = t; k < 8 * K; k += NT) {
-      const int o = k / K, b = k - o * K;
-      sL[k] = sR[o] >= 0 ? lv0.lbar[(size_t)sR[o] * K + b] : 0.0;
-    }
-    __syncthreads();
-    if (t < K && (rs >= 0 || t == 0)) {
-      const int16_t* si = sumidx + (size_t)t * K;
-      for (int o = 0; o < 8; ++o) {
-        if (sR[o] < 0) continue;
-        const double* D = sD + o * K;
-        const double* L = sL + o * K;
-        for (int b = 0; b < na; ++b) acc += D[si[b]] * L[b];
-      }
-    }
+__global__ void k_adj_leafup(LevelDev lv1, LevelDev lv0, CommonDev cm) {
+  constexpr int K = nmi(P);
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= lv1.nref) return;
+  double Y[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const double* Sp = lv1.sbar + (size_t)r * K;
+  for (int j = cm.m2mT_start[0]; j < cm.m2mT_start[1]; ++j) {
+    const int code = cm.m2mT_list[j];
+    Y[code >> 12] += cm.m2mT_w[j] * Sp[code & 4095];
   }
-  if (rs >= 0) {
-    if (t < K) lv1.sbar[(size_t)rs * K + t] += acc;
-  } else if (t == 0) {
-    lv1.mbar[s] += acc;
+  for (int o = 0; o < 8; ++o) {
+    const int c = 8 * r + o;
+    if (lv0.rank[c] >= 0) continue;
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v += parity_sign(q, o) * Y[q];
+    lv0.mbar[c] += v;
   }
 }
 
@@ -353,29 +268,269 @@ __global__ __launch_bounds__(256) void k_adj_down(LevelDev lv1, LevelDev lv0, in
   lv0.sbar[i] = v;
 }
 
-// Mass bars to the caller's slots: leaf cells of rebuilt levels get their own
-// bar plus the M2M^T term of their father's multipole bar (monopole entry);
+// Mass bars to the caller's slots: leaf cells of rebuilt levels get their bar,
 // every other slot of the level gets 0.
-template <int P>
-__global__ void k_adj_out(LevelDev lv1, LevelDev lv0, int has_parent, int rebuilt, CommonDev cm,
-                          double* __restrict__ mbar_out) {
+__global__ void k_adj_out(LevelDev lv0, int rebuilt, double* __restrict__ mbar_out) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= lv0.n) return;
   const int s = lv0.slot[c];
   if (s < 0) return;
-  double v = 0.0;
-  if (rebuilt && lv0.rank[c] < 0) {
-    v = lv0.mbar[c];
-    if (has_parent) {
-      const int o = c & 7;
-      const double* Sp = lv1.sbar + (size_t)(c >> 3) * nmi(P);
-      for (int j = cm.m2mT_start[0]; j < cm.m2mT_start[1]; ++j) {
-        const int code = cm.m2mT_list[j];
-        v += cm.m2mT_w[j] * parity_sign(code >> 12, o) * Sp[code & 4095];
+  mbar_out[s] = (rebuilt && lv0.rank[c] < 0) ? lv0.mbar[c] : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// MFMA forms of the transposed M2P and M2L.  A tile = 16 source cells of one
+// octant class at level ls; for each of the 189 transposed taps the tap's
+// group F of every column is found through the column's parent neighbours,
+// and the contribution of F's 8 children (targets) is a dense product
+//   OUT[K rows a x 16 columns] += A[K x k] * B[k x 16]
+// with the D~ rows of the tap's offset staged in LDS (A read through per-lane
+// offsets) and B loaded straight into registers.  One wave per block; each
+// source cell belongs to one tile, so its bars have one writer.
+
+// Unit-form target bars of the leaf children of every group at level ls, as
+// the B operand of the transposed M2P: tbT[F][4 o + q] = T_(8F+o) with the
+// acceleration bars negated (the forward M2P stores -acc), in T.
+template <typename T>
+__global__ void k_adj_tbT(LevelDev lvs, LevelDev lvt, T* __restrict__ tbT) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= lvs.nref * 32) return;
+  const int F = i >> 5, j = i & 31;
+  const double v = lvt.tbar[4 * (size_t)(8 * F) + j];
+  tbT[i] = (T)((j & 3) == 0 ? v : -v);
+}
+
+// Local-expansion bars of level f in T and in the lane-group layout of the
+// source copies (coefficient b at (b & 3) STP + (b >> 2), zero padded).
+template <typename T, int P>
+__global__ void k_adj_lbarT(LevelDev lv, T* __restrict__ lT) {
+  constexpr int K = nmi(P), STP = src_stp(P, (int)sizeof(T)), ROW = 4 * STP;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= lv.nref * ROW) return;
+  const int r = i / ROW, b = i - r * ROW;   // b runs over coefficient indices 0 .. ROW-1
+  lT[(size_t)r * ROW + src_pos(b, STP)] = b < K ? (T)lv.lbar[(size_t)r * K + b] : (T)0;
+}
+
+// Per-block setup shared by both kernels: the 16 source cells, the child base
+// (8 x refined rank, level ls) of each column's parent neighbours, the class
+// taps.  Returns the octant class.
+__device__ inline void adj_tile_setup(const int32_t* __restrict__ rec, const LevelDev& lvp, int* sS, int* sCB,
+                                      int* sTap, const int32_t* __restrict__ tapsT) {
+  const int lane = threadIdx.x;
+  if (lane < 16) sS[lane] = rec[1 + lane];
+  __syncthreads();
+  for (int i = lane; i < 16 * 27; i += 64) {
+    const int n = i / 27, e = i - n * 27;
+    const int c = sS[n];
+    int v = -1;
+    if (c >= 0) {
+      const int Q = lvp.nbr[(size_t)(c >> 3) * 27 + e];
+      if (Q >= 0) {
+        const int rQ = lvp.rank[Q];
+        if (rQ >= 0) v = 8 * rQ;
       }
     }
+    sCB[i] = v;
   }
-  mbar_out[s] = v;
+  const int os = sS[0] & 7;
+  for (int i = lane; i < kTapsT; i += 64) sTap[i] = tapsT[os * kTapsT + i];
+}
+
+// group (refined rank at level ls) of column n for transposed tap `code`, or -1
+__device__ inline int adj_group(int code, int n, const int* sCB, const int32_t* __restrict__ rank_s) {
+  const int cb = sCB[n * 27 + (code & 31)];
+  return cb < 0 ? -1 : rank_s[cb + ((code >> 5) & 7)];
+}
+
+// Output rows of one 16-row tile: multipole-source bars of refined sources,
+// the monopole row of leaf sources into their mass bars.
+template <typename T, int K>
+__device__ inline void adj_write(const typename Acc4<T>::type& acc, int rt, int lane, int s, const LevelDev& lvs) {
+  if (s < 0) return;
+  const int rs = lvs.rank[s];
+  const int krow = lane >> 4;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int a = 16 * rt + acc_row<T>(krow, r);
+    if (rs >= 0) {
+      if (a < K) lvs.sbar[(size_t)rs * K + a] += (double)acc[r];
+    } else if (a == 0) {
+      lvs.mbar[s] += (double)acc[r];
+    }
+  }
+}
+
+// Transposed intermediate-field M2P: targets = leaf children (level ls + 1) of
+// the groups reading the source; k = (child o, quantity q) with lane group g
+// holding j = 8 g + kb, so its B fragments are 8 consecutive values of tbT.
+template <typename T, int P>
+__global__ __launch_bounds__(64) void k_adj_m2p_mfma(const int32_t* __restrict__ tiles, int ntiles,
+                                                     const int32_t* __restrict__ tapsT,
+                                                     const int16_t* __restrict__ aoff, LevelDev lvp, LevelDev lvs,
+                                                     const T* __restrict__ tbT, const T* __restrict__ Dil) {
+  constexpr int K = nmi(P), KS = ((K + 3) & ~3) + 1, SD = 8 * KS + 1, RT = (K + 15) / 16;
+  constexpr int VW = 16 / (int)sizeof(T), NVB = 8 / VW, ND = (SD + 63) / 64;
+  using V = typename Vec16<T>::type;
+  __shared__ T sD[2][SD];
+  __shared__ int sS[16];
+  __shared__ int sCB[16 * 27];
+  __shared__ int sTap[kTapsT];
+  const int tile = xcd_tile(ntiles);
+  if (tile >= ntiles) return;
+  const int lane = threadIdx.x, n = lane & 15, g = lane >> 4;
+  adj_tile_setup(tiles + (size_t)tile * 17, lvp, sS, sCB, sTap, tapsT);
+  int off[RT][8];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb) off[rt][kb] = aoff[(rt * 8 + kb) * 64 + lane];
+  __syncthreads();
+  auto loadB = [&](int rF, V* b) {
+    if (rF >= 0) {
+      const V* src = (const V*)(tbT + (size_t)rF * 32 + 8 * g);
+#pragma unroll
+      for (int j = 0; j < NVB; ++j) b[j] = src[j];
+    } else {
+#pragma unroll
+      for (int j = 0; j < NVB; ++j) b[j] = V{};
+    }
+  };
+  typename Acc4<T>::type acc[RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) acc[rt] = {0, 0, 0, 0};
+  V bA[NVB], bB[NVB];
+  T vD[ND];
+  int gn = adj_group(sTap[0], n, sCB, lvs.rank);
+  loadB(gn, bA);
+  load_drows_t<T, K, KS, 64>(sTap[0] >> 8, Dil, vD);
+  store_drows_t<T, K, KS, 64>(sD[0], vD);
+  gn = adj_group(sTap[1], n, sCB, lvs.rank);
+  __syncthreads();
+  auto step = [&](int k, const V* bc, V* bn) {
+    const int b = k & 1;
+    if (k + 1 < kTapsT) {
+      loadB(gn, bn);
+      load_drows_t<T, K, KS, 64>(sTap[k + 1] >> 8, Dil, vD);
+    }
+    if (k + 2 < kTapsT) gn = adj_group(sTap[k + 2], n, sCB, lvs.rank);
+    const T* D = sD[b];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int kb = 0; kb < 8; ++kb) acc[rt] = mfma16(D[off[rt][kb]], bc[kb / VW][kb % VW], acc[rt]);
+    if (k + 1 < kTapsT) store_drows_t<T, K, KS, 64>(sD[b ^ 1], vD);
+    __syncthreads();
+  };
+  for (int k = 0; k < kTapsT; k += 2) {
+    step(k, bA, bB);
+    if (k + 1 < kTapsT) step(k + 1, bB, bA);
+  }
+  const int s = sS[n];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) adj_write<T, K>(acc[rt], rt, lane, s, lvs);
+}
+
+// Transposed M2L: targets = refined children y (level ls + 1) of the groups
+// reading the source; for each tap and child octant o, A = D~_(a+b)(R~_o)
+// (triangle |a| + |b| <= p skipped at k-step granularity) and B = the local-
+// expansion bars of child o, b = 4 kb + g from the lane-group layout.
+template <int P>
+struct AdjM2LPlan {
+  static constexpr int RT = (nmi(P) + 15) / 16;
+  int ks[RT] = {};
+  int base[RT] = {};
+  int total = 0;
+  int kbmax = 0;
+};
+template <int P>
+constexpr AdjM2LPlan<P> make_adj_m2l_plan() {
+  AdjM2LPlan<P> pl{};
+  for (int rt = 0; rt < AdjM2LPlan<P>::RT; ++rt) {
+    int d = 0;
+    while (nmi(d) <= 16 * rt) ++d;  // degree of the tile's first row
+    pl.ks[rt] = (nmi(P - d) + 3) / 4;
+    pl.base[rt] = pl.total;
+    pl.total += pl.ks[rt];
+    if (pl.ks[rt] > pl.kbmax) pl.kbmax = pl.ks[rt];
+  }
+  return pl;
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(64) void k_adj_m2l_mfma(const int32_t* __restrict__ tiles, int ntiles,
+                                                     const int32_t* __restrict__ tapsT,
+                                                     const int16_t* __restrict__ aoff, LevelDev lvp, LevelDev lvs,
+                                                     LevelDev lvt, const T* __restrict__ lT,
+                                                     const T* __restrict__ Dil) {
+  constexpr int K = nmi(P), KS = ((K + 3) & ~3) + 1, SD = 8 * KS + 1;
+  constexpr AdjM2LPlan<P> PL = make_adj_m2l_plan<P>();
+  constexpr int RT = AdjM2LPlan<P>::RT;
+  constexpr int VW = 16 / (int)sizeof(T), STP = src_stp(P, (int)sizeof(T)), ROW = 4 * STP;
+  constexpr int NVB = (PL.kbmax + VW - 1) / VW, ND = (SD + 63) / 64;
+  using V = typename Vec16<T>::type;
+  __shared__ T sD[2][SD];
+  __shared__ int sS[16];
+  __shared__ int sCB[16 * 27];
+  __shared__ int sTap[kTapsT];
+  const int tile = xcd_tile(ntiles);
+  if (tile >= ntiles) return;
+  const int lane = threadIdx.x, n = lane & 15, g = lane >> 4;
+  adj_tile_setup(tiles + (size_t)tile * 17, lvp, sS, sCB, sTap, tapsT);
+  int off[PL.total];
+#pragma unroll
+  for (int i = 0; i < PL.total; ++i) off[i] = aoff[i * 64 + lane];
+  __syncthreads();
+  // local-expansion-bar row of child o of group rF (refined rank at level ls + 1), or -1
+  auto child = [&](int rF, int o) { return rF >= 0 ? lvt.rank[8 * rF + o] : -1; };
+  auto loadB = [&](int ry, V* b) {
+    if (ry >= 0) {
+      const V* src = (const V*)(lT + (size_t)ry * ROW + g * STP);
+#pragma unroll
+      for (int j = 0; j < NVB; ++j) b[j] = src[j];
+    } else {
+#pragma unroll
+      for (int j = 0; j < NVB; ++j) b[j] = V{};
+    }
+  };
+  typename Acc4<T>::type acc[RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) acc[rt] = {0, 0, 0, 0};
+  V bA[NVB], bB[NVB];
+  T vD[ND];
+  int gcur = adj_group(sTap[0], n, sCB, lvs.rank);
+  int gnext = adj_group(sTap[1], n, sCB, lvs.rank);
+  loadB(child(gcur, 0), bA);
+  load_drows_t<T, K, KS, 64>(sTap[0] >> 8, Dil, vD);
+  store_drows_t<T, K, KS, 64>(sD[0], vD);
+  __syncthreads();
+  // sub-step (tap k, octant o): B of (k, o) in bc; prefetch (k, o+1) or (k+1, 0) into bn
+  auto sub = [&](int k, int o, const V* bc, V* bn) {
+    const int b = k & 1;
+    if (o < 7) loadB(child(gcur, o + 1), bn);
+    else if (k + 1 < kTapsT) loadB(child(gnext, 0), bn);
+    const T* D = sD[b] + o * KS;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int kb = 0; kb < PL.ks[rt]; ++kb)
+        acc[rt] = mfma16(D[off[PL.base[rt] + kb]], bc[kb / VW][kb % VW], acc[rt]);
+  };
+  for (int k = 0; k < kTapsT; ++k) {
+    const int b = k & 1;
+    if (k + 1 < kTapsT) load_drows_t<T, K, KS, 64>(sTap[k + 1] >> 8, Dil, vD);
+#pragma unroll
+    for (int o = 0; o < 8; o += 2) {
+      sub(k, o, bA, bB);
+      sub(k, o + 1, bB, bA);
+    }
+    if (k + 1 < kTapsT) store_drows_t<T, K, KS, 64>(sD[b ^ 1], vD);
+    gcur = gnext;
+    if (k + 2 < kTapsT) gnext = adj_group(sTap[k + 2], n, sCB, lvs.rank);
+    __syncthreads();
+  }
+  const int s = sS[n];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) adj_write<T, K>(acc[rt], rt, lane, s, lvs);
 }
 
 // ---------------------------------------------------------------------------
@@ -423,31 +578,11 @@ hipError_t launch_adj_l2p(int p, const LevelDev& lv1, const LevelDev& lv0, const
   return hipGetLastError();
 }
 
-hipError_t launch_adj_m2p(int p, const LevelDev& lv2, const LevelDev& lv1, const LevelDev& lv0,
-                          const int32_t* tapsT, const TablesDev<double>& t64, const CommonDev& cm, hipStream_t st) {
-  if (lv1.n == 0) return hipSuccess;
-#define X(PP) \
-  case PP: hipLaunchKernelGGL((k_adj_m2p<PP>), dim3(lv1.n), dim3(threads_for(nmi(PP))), 0, st, lv2, lv1, lv0, tapsT, t64.Dil, cm.up); break;
-  AFMM_P_SWITCH(p, X)
-#undef X
-  return hipGetLastError();
-}
-
 hipError_t launch_adj_l2l(int p, const LevelDev& lv1, const LevelDev& lv0, const TablesDev<double>& t64,
                           const CommonDev& cm, hipStream_t st) {
   if (lv1.nref == 0) return hipSuccess;
 #define X(PP) \
-  case PP: hipLaunchKernelGGL((k_adj_l2l<PP>), dim3(lv1.nref), dim3(256), 0, st, lv1, lv0, t64.l2lw, cm.mi); break;
-  AFMM_P_SWITCH(p, X)
-#undef X
-  return hipGetLastError();
-}
-
-hipError_t launch_adj_m2l(int p, const LevelDev& lv2, const LevelDev& lv1, const LevelDev& lv0,
-                          const int32_t* tapsT, const TablesDev<double>& t64, const CommonDev& cm, hipStream_t st) {
-  if (lv1.n == 0) return hipSuccess;
-#define X(PP) \
-  case PP: hipLaunchKernelGGL((k_adj_m2l<PP>), dim3(lv1.n), dim3(threads_for(nmi(PP))), 0, st, lv2, lv1, lv0, tapsT, t64.Dil, cm.sumidx, cm.mi); break;
+  case PP: hipLaunchKernelGGL((k_adj_l2l<PP>), dim3(lv1.nref), dim3(256), 0, st, lv1, lv0, t64.l2lw, cm); break;
   AFMM_P_SWITCH(p, X)
 #undef X
   return hipGetLastError();
@@ -467,11 +602,62 @@ hipError_t launch_adj_down(int p, const LevelDev& lv1, const LevelDev& lv0, int 
 hipError_t launch_adj_out(int p, const LevelDev& lv1, const LevelDev& lv0, int has_parent, int rebuilt,
                           const CommonDev& cm, double* mbar_out, hipStream_t st) {
   if (lv0.n == 0) return hipSuccess;
+  if (has_parent && lv1.nref > 0) {
 #define X(PP) \
-  case PP: hipLaunchKernelGGL((k_adj_out<PP>), dim3((lv0.n + 255) / 256), dim3(256), 0, st, lv1, lv0, has_parent, rebuilt, cm, mbar_out); break;
+  case PP: hipLaunchKernelGGL((k_adj_leafup<PP>), dim3((lv1.nref + 255) / 256), dim3(256), 0, st, lv1, lv0, cm); break;
+    AFMM_P_SWITCH(p, X)
+#undef X
+  }
+  hipLaunchKernelGGL(k_adj_out, dim3((lv0.n + 255) / 256), dim3(256), 0, st, lv0, rebuilt, mbar_out);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t adj_m2p_t(int p, const int32_t* tiles, int ntiles, const int32_t* tapsT, const int16_t* aoff,
+                            const LevelDev& lvp, const LevelDev& lvs, const LevelDev& lvt, const T* Dil,
+                            hipStream_t st) {
+  T* tbT = (T*)lvs.tbT;
+  hipLaunchKernelGGL((k_adj_tbT<T>), dim3((lvs.nref * 32 + 255) / 256), dim3(256), 0, st, lvs, lvt, tbT);
+  const dim3 grid(8 * ((ntiles + 7) / 8)), block(64);
+#define X(PP) \
+  case PP: hipLaunchKernelGGL((k_adj_m2p_mfma<T, PP>), grid, block, 0, st, tiles, ntiles, tapsT, aoff, lvp, lvs, (const T*)tbT, Dil); break;
   AFMM_P_SWITCH(p, X)
 #undef X
   return hipGetLastError();
+}
+
+hipError_t launch_adj_m2p_mfma(int p, bool fp32, const int32_t* tiles, int ntiles, const int32_t* tapsT,
+                               const int16_t* aoff, const LevelDev& lvp, const LevelDev& lvs, const LevelDev& lvt,
+                               const TablesDev<float>& t32, const TablesDev<double>& t64, hipStream_t st) {
+  if (ntiles <= 0 || lvs.nref == 0) return hipSuccess;
+  if (fp32) return adj_m2p_t<float>(p, tiles, ntiles, tapsT, aoff, lvp, lvs, lvt, t32.Dil, st);
+  return adj_m2p_t<double>(p, tiles, ntiles, tapsT, aoff, lvp, lvs, lvt, t64.Dil, st);
+}
+
+template <typename T>
+static hipError_t adj_m2l_t(int p, const int32_t* tiles, int ntiles, const int32_t* tapsT, const int16_t* aoff,
+                            const LevelDev& lvp, const LevelDev& lvs, const LevelDev& lvt, const T* Dil,
+                            hipStream_t st) {
+  T* lT = (T*)lvt.lbarT;
+  const int rows = lvt.nref * src_row(p, (int)sizeof(T));
+#define X(PP) \
+  case PP: hipLaunchKernelGGL((k_adj_lbarT<T, PP>), dim3((rows + 255) / 256), dim3(256), 0, st, lvt, lT); break;
+  AFMM_P_SWITCH(p, X)
+#undef X
+  const dim3 grid(8 * ((ntiles + 7) / 8)), block(64);
+#define X(PP) \
+  case PP: hipLaunchKernelGGL((k_adj_m2l_mfma<T, PP>), grid, block, 0, st, tiles, ntiles, tapsT, aoff, lvp, lvs, lvt, (const T*)lT, Dil); break;
+  AFMM_P_SWITCH(p, X)
+#undef X
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_m2l_mfma(int p, bool fp32, const int32_t* tiles, int ntiles, const int32_t* tapsT,
+                               const int16_t* aoff, const LevelDev& lvp, const LevelDev& lvs, const LevelDev& lvt,
+                               const TablesDev<float>& t32, const TablesDev<double>& t64, hipStream_t st) {
+  if (ntiles <= 0 || lvt.nref == 0) return hipSuccess;
+  if (fp32) return adj_m2l_t<float>(p, tiles, ntiles, tapsT, aoff, lvp, lvs, lvt, t32.Dil, st);
+  return adj_m2l_t<double>(p, tiles, ntiles, tapsT, aoff, lvp, lvs, lvt, t64.Dil, st);
 }
 
 #undef AFMM_P_SWITCH

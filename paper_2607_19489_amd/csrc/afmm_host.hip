@@ -422,6 +422,8 @@ struct HostTables {
   std::vector<int32_t> m2mT_start, m2mT_list, tapsT;
   std::vector<double> m2mT_w;
   std::vector<int32_t> m2l_tinfo;   // [NT][2]
+  std::vector<int16_t> adj_m2p_off, adj_m2l_off;
+  std::vector<int32_t> l2lT_start, l2lT_list;
 };
 
 static long double ipow(long double x, int n) {
@@ -598,6 +600,47 @@ static void build_tables(int p, HostTables& H) {
         H.m2p_off.push_back((int16_t)v);
       }
   }
+  // adjoint: transposed L2L pairs (b <= c componentwise, g = c - b) per c
+  H.l2lT_start.assign(K + 1, 0);
+  H.l2lT_list.clear();
+  for (int c = 0; c < K; ++c) {
+    H.l2lT_start[c] = (int32_t)H.l2lT_list.size();
+    for (int b = 0; b < K; ++b) {
+      const int g0 = H.mi[4 * c] - H.mi[4 * b], g1 = H.mi[4 * c + 1] - H.mi[4 * b + 1], g2 = H.mi[4 * c + 2] - H.mi[4 * b + 2];
+      if (g0 < 0 || g1 < 0 || g2 < 0) continue;
+      H.l2lT_list.push_back(b | (mi_index(g0, g1, g2) << 8) | (H.mi[4 * b + 3] << 16));
+    }
+  }
+  H.l2lT_start[K] = (int32_t)H.l2lT_list.size();
+  // adjoint: transposed M2P, rows a (tiles of 16), k = 8 g + kb -> (child o, quantity q)
+  {
+    const int RT = (K + 15) / 16;
+    H.adj_m2p_off.clear();
+    for (int rt = 0; rt < RT; ++rt)
+      for (int kb = 0; kb < 8; ++kb)
+        for (int lane = 0; lane < 64; ++lane) {
+          const int a = 16 * rt + (lane & 15), j = 8 * (lane >> 4) + kb, o = j >> 2, q = j & 3;
+          int v = ZERO;
+          if (a < K && q == 0) v = o * KS + a;
+          if (a < K1 && q > 0) v = o * KS + H.up[3 * a + (q - 1)];
+          H.adj_m2p_off.push_back((int16_t)v);
+        }
+    // transposed M2L, rows a, k = b = 4 kb + g, offsets within one D~ row (K = its zero)
+    H.adj_m2l_off.clear();
+    for (int rt = 0; rt < RT; ++rt) {
+      int d = 0;
+      while (nmi(d) <= 16 * rt) ++d;
+      const int ks = (nmi(p - d) + 3) / 4;
+      for (int kb = 0; kb < ks; ++kb)
+        for (int lane = 0; lane < 64; ++lane) {
+          const int a = 16 * rt + (lane & 15), b = 4 * kb + (lane >> 4);
+          int v = K;
+          if (a < K && b < K && deg(a) + deg(b) <= p)
+            v = mi_index(H.mi[4 * a] + H.mi[4 * b], H.mi[4 * a + 1] + H.mi[4 * b + 1], H.mi[4 * a + 2] + H.mi[4 * b + 2]);
+          H.adj_m2l_off.push_back((int16_t)v);
+        }
+    }
+  }
   const int NT = (8 * K + 15) / 16;
   H.m2l_tinfo.assign(2 * NT, 0);
   H.m2l_off.clear();
@@ -656,6 +699,10 @@ struct afmm_plan {
   int last_level = AFMM_ALL_LEVELS;
   int last_fresh = 0;             // levels >= this took their masses from the last call's d_mass
   bool adj_ready = false;         // adjoint workspace allocated
+  // source tiles of the transposed M2P (index: leaf level l) and M2L (index: FMM level f)
+  int32_t* d_adjp[kMaxLevel] = {};
+  int32_t* d_adjl[kMaxLevel] = {};
+  int n_adjp[kMaxLevel] = {}, n_adjl[kMaxLevel] = {};
   std::vector<void*> allocs;
   size_t bytes = 0;
   bool dead = false;              // sticky device error
@@ -1011,6 +1058,14 @@ static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
     P->cm.m2mT_list = d_tl;
     P->cm.m2mT_w = d_tw;
     P->cm.tapsT = d_tt;
+    int16_t *d_ap, *d_al;
+    if ((s = upload(P, H.adj_m2p_off, &d_ap, st)) || (s = upload(P, H.adj_m2l_off, &d_al, st))) return s;
+    P->cm.adj_m2p_off = d_ap;
+    P->cm.adj_m2l_off = d_al;
+    int32_t *d_lts, *d_ltl;
+    if ((s = upload(P, H.l2lT_start, &d_lts, st)) || (s = upload(P, H.l2lT_list, &d_ltl, st))) return s;
+    P->cm.l2lT_start = d_lts;
+    P->cm.l2lT_list = d_ltl;
     P->mt.taps = d_taps;
     P->mt.m2p_off = d_m2p_off;
     P->mt.m2l_off = d_m2l_off;
@@ -1541,6 +1596,62 @@ static afmm_status adjoint_workspace(afmm_plan* P) {
       D.lbar = (double*)q;
     }
   }
+  // source tiles: the level-ls cells read by some group of `grp` (refined ranks
+  // at ls), 16 per tile, one octant class per tile
+  const bool mixed = P->opt.precision == AFMM_FP32_MIXED;
+  const int f64 = mixed ? P->opt.fp64_levels : 1 << 20;
+  auto src_tiles = [&](int target, const std::vector<int32_t>& grp, int32_t** dst, int* nt) -> afmm_status {
+    *nt = 0;
+    if (grp.empty() || target < 3) return AFMM_OK;
+    const int ls = target - 1;
+    const HostLevel& LS = T.lv[ls];
+    const HostLevel& LP = T.lv[ls - 1];
+    std::vector<uint8_t> mark(LS.n(), 0);
+    for (int32_t F : grp) {
+      const int32_t cF = LS.refcell[F];
+      const int32_t G = cF >> 3, oF = cF & 7;
+      for (int i = 0; i < 189; ++i) {
+        const int code = P->tabs.taps[oF * 189 + i];
+        const int32_t Q = LP.nbr[(size_t)G * 27 + (code & 31)];
+        if (Q < 0 || LP.rank[Q] < 0) continue;
+        mark[8 * LP.rank[Q] + ((code >> 5) & 7)] = 1;
+      }
+    }
+    std::vector<int32_t> cls[8], rec;
+    for (int32_t c = 0; c < LS.n(); ++c)
+      if (mark[c]) cls[c & 7].push_back(c);
+    size_t chunks = 0;
+    for (auto& c : cls) chunks = std::max(chunks, (c.size() + 15) / 16);
+    for (size_t ch = 0; ch < chunks; ++ch)
+      for (auto& c : cls) {
+        if (ch * 16 >= c.size()) continue;
+        rec.push_back(target);
+        for (int j = 0; j < 16; ++j) rec.push_back(ch * 16 + j < c.size() ? c[ch * 16 + j] : -1);
+        ++*nt;
+      }
+    return upload(P, rec, dst, nullptr);
+  };
+  for (int l = 3; l <= T.lmax; ++l) {
+    if ((s = src_tiles(l, T.leafgrp[l], &P->d_adjp[l], &P->n_adjp[l]))) return s;
+    if (P->n_adjp[l] > 0) {
+      void* q = nullptr;
+      const size_t es = (mixed && (l - 1) > f64) ? sizeof(float) : sizeof(double);
+      if ((s = dev_alloc(P, &q, (size_t)T.lv[l - 1].nref() * 32 * es))) return s;
+      P->lv[l - 1].tbT = q;
+    }
+  }
+  for (int f = 3; f <= T.lmax - 1; ++f) {
+    if ((s = src_tiles(f, T.m2lgrp[f], &P->d_adjl[f], &P->n_adjl[f]))) return s;
+    if (P->n_adjl[f] > 0) {
+      void* q = nullptr;
+      const bool f32 = mixed && f > f64;
+      const size_t b = (size_t)T.lv[f].nref() * (f32 ? src_row(P->opt.p, 4) * sizeof(float)
+                                                       : src_row(P->opt.p, 8) * sizeof(double));
+      if ((s = dev_alloc(P, &q, b))) return s;
+      P->lv[f].lbarT = q;
+    }
+  }
+  if (hipDeviceSynchronize() != hipSuccess) return fail(AFMM_E_DEVICE, "adjoint workspace upload");
   P->adj_ready = true;
   return AFMM_OK;
 }
@@ -1596,8 +1707,13 @@ extern "C" afmm_status afmm_solve_adjoint(afmm_plan* P, int32_t level, const dou
   prof_end(P, ev, st, kAdjNear, -1);
   // 3. intermediate field: M2P^T into the level l-1 sources
   ev = prof_begin(P, st);
+  const bool mixed = P->opt.precision == AFMM_FP32_MIXED;
+  const int f64 = mixed ? P->opt.fp64_levels : 1 << 20;
   for (int l = std::max(3, lo); l <= hi; ++l) {
-    if ((s = dev_check(P, launch_adj_m2p(p, P->lv[l - 2], P->lv[l - 1], P->lv[l], P->cm.tapsT, P->t64, P->cm, st),
+    if ((s = dev_check(P,
+                       launch_adj_m2p_mfma(p, mixed && (l - 1) > f64, P->d_adjp[l], P->n_adjp[l], P->cm.tapsT,
+                                           P->cm.adj_m2p_off, P->lv[l - 2], P->lv[l - 1], P->lv[l], P->t32, P->t64,
+                                           st),
                        "adjoint m2p")))
       return s;
     P->pending_flops += W.m2p_flops[l];
@@ -1612,7 +1728,10 @@ extern "C" afmm_status afmm_solve_adjoint(afmm_plan* P, int32_t level, const dou
   // 5. M2L^T into the level f-1 sources
   ev = prof_begin(P, st);
   for (int f = 3; f <= fmax; ++f) {
-    if ((s = dev_check(P, launch_adj_m2l(p, P->lv[f - 2], P->lv[f - 1], P->lv[f], P->cm.tapsT, P->t64, P->cm, st),
+    if ((s = dev_check(P,
+                       launch_adj_m2l_mfma(p, mixed && f > f64, P->d_adjl[f], P->n_adjl[f], P->cm.tapsT,
+                                           P->cm.adj_m2l_off, P->lv[f - 2], P->lv[f - 1], P->lv[f], P->t32, P->t64,
+                                           st),
                        "adjoint m2l")))
       return s;
     P->pending_flops += W.m2l_flops[f];

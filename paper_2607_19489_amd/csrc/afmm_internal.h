@@ -73,6 +73,8 @@ struct LevelDev {
   double* mbar = nullptr;            // [n] mass bars of the leaves
   double* sbar = nullptr;            // [nref][K] source-copy bar, then multipole bar
   double* lbar = nullptr;            // [nref][K] local-expansion bar
+  void* tbT = nullptr;               // [nref][32] target bars of the leaf children, B of the transposed M2P (T)
+  void* lbarT = nullptr;             // [nref][src_row] local-expansion bar, B of the transposed M2L (T, lane-group layout)
 };
 
 template <typename T>
@@ -98,6 +100,10 @@ struct CommonDev {
   const int32_t* m2mT_list = nullptr;  // entries: a | parity(a-k) << 12
   const double* m2mT_w = nullptr;
   const int32_t* tapsT = nullptr;      // [8][189] per source octant: e | oF << 5 | d_index << 8 (adjoint)
+  const int16_t* adj_m2p_off = nullptr; // [RT * 8][64] A offsets of the transposed M2P
+  const int16_t* adj_m2l_off = nullptr; // [steps][64] A offsets (within one D~ row) of the transposed M2L
+  const int32_t* l2lT_start = nullptr;  // [K+1] transposed L2L pairs of each coefficient c
+  const int32_t* l2lT_list = nullptr;   // b | (c - b) << 8 | |b| << 16
 };
 
 // Group tiles of the MFMA kernels: NC refined ranks per tile (one parity class,
@@ -126,7 +132,7 @@ hipError_t launch_batch_in(int64_t nleaf, const int32_t* leafslot, const int32_t
 hipError_t launch_batch_out(int64_t nleaf, const int32_t* leafslot, const int32_t* leafhier, const int64_t* base,
                             const double* phi_forest, const double* acc_forest, double* const* phi,
                             double* const* acc, hipStream_t st);
-// Adjoint pass (afmm_adjoint.hip), FP64.
+// Adjoint pass (afmm_adjoint.hip).
 hipError_t launch_adj_init(const LevelDev& lv, int target, const double* phib, const double* accb, double sp,
                            double sa, hipStream_t st);
 hipError_t launch_adj_zero(double* p, size_t n, hipStream_t st);
@@ -134,12 +140,15 @@ hipError_t launch_adj_near(int p, const LevelDev& lv1, const LevelDev& lv0, cons
                            const TablesDev<double>& t64, const CommonDev& cm, hipStream_t st);
 hipError_t launch_adj_l2p(int p, const LevelDev& lv1, const LevelDev& lv0, const TablesDev<double>& t64,
                           hipStream_t st);
-hipError_t launch_adj_m2p(int p, const LevelDev& lv2, const LevelDev& lv1, const LevelDev& lv0,
-                          const int32_t* tapsT, const TablesDev<double>& t64, const CommonDev& cm, hipStream_t st);
+// MFMA forms: tiles of 16 source cells (records: target level, 16 cells).
+hipError_t launch_adj_m2p_mfma(int p, bool fp32, const int32_t* tiles, int ntiles, const int32_t* tapsT,
+                               const int16_t* aoff, const LevelDev& lvp, const LevelDev& lvs, const LevelDev& lvt,
+                               const TablesDev<float>& t32, const TablesDev<double>& t64, hipStream_t st);
+hipError_t launch_adj_m2l_mfma(int p, bool fp32, const int32_t* tiles, int ntiles, const int32_t* tapsT,
+                               const int16_t* aoff, const LevelDev& lvp, const LevelDev& lvs, const LevelDev& lvt,
+                               const TablesDev<float>& t32, const TablesDev<double>& t64, hipStream_t st);
 hipError_t launch_adj_l2l(int p, const LevelDev& lv1, const LevelDev& lv0, const TablesDev<double>& t64,
                           const CommonDev& cm, hipStream_t st);
-hipError_t launch_adj_m2l(int p, const LevelDev& lv2, const LevelDev& lv1, const LevelDev& lv0,
-                          const int32_t* tapsT, const TablesDev<double>& t64, const CommonDev& cm, hipStream_t st);
 hipError_t launch_adj_down(int p, const LevelDev& lv1, const LevelDev& lv0, int has_parent, const CommonDev& cm,
                            hipStream_t st);
 hipError_t launch_adj_out(int p, const LevelDev& lv1, const LevelDev& lv0, int has_parent, int rebuilt,

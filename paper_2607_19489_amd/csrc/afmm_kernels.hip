@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include "afmm_internal.h"
+#include "afmm_mfma.h"
 
 namespace afmm {
 
@@ -34,20 +35,6 @@ template <>
 __device__ inline float rsqrt_t<float>(float x) { return rsqrtf(x); }
 template <>
 __device__ inline double rsqrt_t<double>(double x) { return 1.0 / sqrt(x); }
-
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-template <typename T> struct Acc4;
-template <> struct Acc4<float> { typedef f32x4 type; };
-template <> struct Acc4<double> { typedef f64x4 type; };
-
-// D[16x16] += A[16x4] B[4x16]; lane l holds A[l%16][l/16] and B[l/16][l%16].
-// Accumulator element r of lane l is D[acc_row(l/16, r)][l%16]: rows 4(l/16)+r
-// for FP32 and (l/16)+4r for FP64 (checked on gfx950 by a lane-layout probe).
-__device__ inline f32x4 mfma16(float a, float b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
-__device__ inline f64x4 mfma16(double a, double b, f64x4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
-template <typename T>
-__device__ inline int acc_row(int krow, int r) { return sizeof(T) == 4 ? 4 * krow + r : krow + 4 * r; }
 
 // P2P in target-level units: phi~ -= m/|R|, a~ -= m R/|R|^3.
 template <typename T>
@@ -278,10 +265,6 @@ __global__ __launch_bounds__(kBlock) void k_l2l(const int32_t* __restrict__ grp,
 //             is staged in LDS while the MFMAs of the previous tap run.
 // A fragments are read from sD through per-lane offsets that do not depend on
 // the tap (kept in registers).
-template <typename T> struct Vec16;
-template <> struct Vec16<float> { typedef float type __attribute__((ext_vector_type(4))); };
-template <> struct Vec16<double> { typedef double type __attribute__((ext_vector_type(2))); };
-
 template <typename T, int P>
 struct TapStage {
   static constexpr int K = nmi(P);
@@ -384,13 +367,6 @@ __device__ inline void tile_setup(const int32_t* __restrict__ rec, int NC, const
   }
 }
 
-// XCD-aware tile order: consecutive blocks land on different XCDs, so block b
-// takes tile (b % 8) * ceil(n/8) + b / 8 and each XCD sweeps one contiguous
-// (spatially compact, all parity classes interleaved) range of tiles.
-__device__ inline int xcd_tile(int ntiles) {
-  const int per = (ntiles + 7) / 8;
-  return (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-}
 
 // ---------------------------------------------------------------------------
 // Intermediate-field M2P at the leaves (Alg. 4 / Sec. 3.2): rows = 8 children

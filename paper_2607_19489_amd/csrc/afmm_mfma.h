@@ -1,0 +1,67 @@
+// MFMA helpers shared by the forward and adjoint kernels (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace afmm {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+template <typename T> struct Acc4;
+template <> struct Acc4<float> { typedef f32x4 type; };
+template <> struct Acc4<double> { typedef f64x4 type; };
+
+// D[16x16] += A[16x4] B[4x16]; lane l holds A[l%16][l/16] and B[l/16][l%16].
+// Accumulator element r of lane l is D[acc_row(l/16, r)][l%16]: rows 4(l/16)+r
+// for FP32 and (l/16)+4r for FP64 (checked on gfx950 by a lane-layout probe).
+__device__ inline f32x4 mfma16(float a, float b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+__device__ inline f64x4 mfma16(double a, double b, f64x4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+template <typename T>
+__device__ inline int acc_row(int krow, int r) { return sizeof(T) == 4 ? 4 * krow + r : krow + 4 * r; }
+
+// 16-byte vectors
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { typedef float type __attribute__((ext_vector_type(4))); };
+template <> struct Vec16<double> { typedef double type __attribute__((ext_vector_type(2))); };
+
+// XCD-aware tile order: consecutive blocks land on different XCDs, so block b
+// takes tile (b % 8) * ceil(n/8) + b / 8 and each XCD sweeps one contiguous
+// (spatially compact) range of tiles.
+__device__ inline int xcd_tile(int ntiles) {
+  const int per = (ntiles + 7) / 8;
+  return (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+}
+
+// D~ rows of one source offset staged in LDS: sD[o * KS + g] = D~_g at child
+// offset o (g < K; zeros up to KS), then one zero slot at 8 KS.  NTH threads.
+template <typename T, int K, int KS, int NTH>
+__device__ inline void load_drows_t(int di, const T* __restrict__ Dil, T* vD) {
+  constexpr int SD = 8 * KS + 1;
+  constexpr int ND = (SD + NTH - 1) / NTH;
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < ND; ++j) {
+    const int i = t + NTH * j;
+    T v = 0;
+    if (i < 8 * KS) {
+      const int o = i / KS;
+      const int g = i - o * KS;
+      if (g < K) v = Dil[((size_t)di * 8 + o) * K + g];
+    }
+    vD[j] = v;
+  }
+}
+
+template <typename T, int K, int KS, int NTH>
+__device__ inline void store_drows_t(T* sD, const T* vD) {
+  constexpr int SD = 8 * KS + 1;
+  constexpr int ND = (SD + NTH - 1) / NTH;
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < ND; ++j) {
+    const int i = t + NTH * j;
+    if (i < SD) sD[i] = vD[j];
+  }
+}
+
+}  // namespace afmm

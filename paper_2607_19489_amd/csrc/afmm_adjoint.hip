@@ -194,7 +194,8 @@ __global__ __launch_bounds__(256) void k_adj_l2p(LevelDev lv1, LevelDev lv0, con
 
 // L2L^T (block = one refined cell F of level f-1): L_bar[F]_c += sum over the
 // refined children y of 2^(-1-|b|) u^(c-b)/(c-b)! L_bar[y]_b, b <= c; the
-// (b, c - b) pairs of each c come from a host table (cm.l2lT_*).
+// (b, c - b) pairs of each c and their 8 octant weights come from a host
+// table (cm.l2lT_*).
 template <int P>
 __global__ __launch_bounds__(256) void k_adj_l2l(LevelDev lv1, LevelDev lv0, const double* __restrict__ l2lw,
                                                  CommonDev cm) {
@@ -213,10 +214,10 @@ __global__ __launch_bounds__(256) void k_adj_l2l(LevelDev lv1, LevelDev lv0, con
   for (int c = t; c < K; c += 256) {
     double acc = 0.0;
     for (int j = cm.l2lT_start[c]; j < cm.l2lT_start[c + 1]; ++j) {
-      const int code = cm.l2lT_list[j];
-      const int b = code & 255, g = (code >> 8) & 255, nb = code >> 16;
+      const int b = cm.l2lT_list[j] & 255;
+      const double* w8 = cm.l2lT_w + 8 * (size_t)j;
 #pragma unroll
-      for (int o = 0; o < 8; ++o) acc += l2lw[((size_t)o * (P + 1) + nb) * K + g] * sL[o * K + b];
+      for (int o = 0; o < 8; ++o) acc += w8[o] * sL[o * K + b];
     }
     lv1.lbar[(size_t)F * K + c] += acc;
   }
@@ -249,23 +250,46 @@ __global__ void k_adj_leafup(LevelDev lv1, LevelDev lv0, CommonDev cm) {
 // Source-copy bars -> multipole bars, and M2M^T from the parent (levels
 // processed coarse to fine): S_bar[r]_k = c_k 2^|k| Sc_bar[r]_k
 //   + sum over the M2M entries (a, k, parity q) of w sign_q(o_r) S_bar[parent]_a.
+// Block = one refined parent at level f-1 (its row and the entry lists in LDS),
+// thread = (child octant, k); without a parent (f = 2) only the scaling.
 template <int P>
-__global__ __launch_bounds__(256) void k_adj_down(LevelDev lv1, LevelDev lv0, int has_parent, CommonDev cm) {
+__global__ __launch_bounds__(256) void k_adj_down(LevelDev lv1, LevelDev lv0, CommonDev cm) {
+  constexpr int K = nmi(P);
+  constexpr int NE = nmi_entries(P);
+  __shared__ double sP[K];
+  __shared__ int sR[8];
+  __shared__ int sStart[K + 1];
+  __shared__ int sList[NE];
+  __shared__ double sW[NE];
+  const int rp = blockIdx.x;
+  const int t = threadIdx.x;
+  for (int i = t; i < K; i += 256) sP[i] = lv1.sbar[(size_t)rp * K + i];
+  for (int i = t; i <= K; i += 256) sStart[i] = cm.m2mT_start[i];
+  for (int i = t; i < NE; i += 256) {
+    sList[i] = cm.m2mT_list[i];
+    sW[i] = cm.m2mT_w[i];
+  }
+  if (t < 8) sR[t] = lv0.rank[8 * rp + t];
+  __syncthreads();
+  for (int i = t; i < 8 * K; i += 256) {
+    const int o = i / K, k = i - o * K;
+    const int rc = sR[o];
+    if (rc < 0) continue;
+    double v = cm.cfac2[k] * lv0.sbar[(size_t)rc * K + k];
+    for (int j = sStart[k]; j < sStart[k + 1]; ++j) {
+      const int code = sList[j];
+      v += sW[j] * parity_sign(code >> 12, o) * sP[code & 4095];
+    }
+    lv0.sbar[(size_t)rc * K + k] = v;
+  }
+}
+
+template <int P>
+__global__ void k_adj_scale(LevelDev lv0, CommonDev cm) {
   constexpr int K = nmi(P);
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= lv0.nref * K) return;
-  const int r = i / K, k = i - r * K;
-  double v = cm.cfac2[k] * lv0.sbar[i];
-  if (has_parent) {
-    const int c = lv0.refcell[r];
-    const int pr = c >> 3, o = c & 7;
-    const double* Sp = lv1.sbar + (size_t)pr * K;
-    for (int j = cm.m2mT_start[k]; j < cm.m2mT_start[k + 1]; ++j) {
-      const int code = cm.m2mT_list[j];
-      v += cm.m2mT_w[j] * parity_sign(code >> 12, o) * Sp[code & 4095];
-    }
-  }
-  lv0.sbar[i] = v;
+  lv0.sbar[i] *= cm.cfac2[i % K];
 }
 
 // Mass bars to the caller's slots: leaf cells of rebuilt levels get their bar,
@@ -343,10 +367,22 @@ __device__ inline int adj_group(int code, int n, const int* sCB, const int32_t* 
 }
 
 // Output rows of one 16-row tile: multipole-source bars of refined sources,
-// the monopole row of leaf sources into their mass bars.
+// the monopole row of leaf sources into their mass bars; with a tap split,
+// the rows go to the block's partial set part[(chunk * ntiles + tile) * 16 + n][K]
+// instead, summed in order by k_adj_reduce.
 template <typename T, int K>
-__device__ inline void adj_write(const typename Acc4<T>::type& acc, int rt, int lane, int s, const LevelDev& lvs) {
+__device__ inline void adj_write(const typename Acc4<T>::type& acc, int rt, int lane, int s, const LevelDev& lvs,
+                                 double* part) {
   if (s < 0) return;
+  if (part) {
+    const int krow = lane >> 4;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int a = 16 * rt + acc_row<T>(krow, r);
+      if (a < K) part[(size_t)(lane & 15) * K + a] = (double)acc[r];
+    }
+    return;
+  }
   const int rs = lvs.rank[s];
   const int krow = lane >> 4;
 #pragma unroll
@@ -364,8 +400,8 @@ __device__ inline void adj_write(const typename Acc4<T>::type& acc, int rt, int 
 // the groups reading the source; k = (child o, quantity q) with lane group g
 // holding j = 8 g + kb, so its B fragments are 8 consecutive values of tbT.
 template <typename T, int P>
-__global__ __launch_bounds__(64) void k_adj_m2p_mfma(const int32_t* __restrict__ tiles, int ntiles,
-                                                     const int32_t* __restrict__ tapsT,
+__global__ __launch_bounds__(64) void k_adj_m2p_mfma(const int32_t* __restrict__ tiles, int ntiles, int nsplit,
+                                                     double* __restrict__ part, const int32_t* __restrict__ tapsT,
                                                      const int16_t* __restrict__ aoff, LevelDev lvp, LevelDev lvs,
                                                      const T* __restrict__ tbT, const T* __restrict__ Dil) {
   constexpr int K = nmi(P), KS = ((K + 3) & ~3) + 1, SD = 8 * KS + 1, RT = (K + 15) / 16;
@@ -375,8 +411,10 @@ __global__ __launch_bounds__(64) void k_adj_m2p_mfma(const int32_t* __restrict__
   __shared__ int sS[16];
   __shared__ int sCB[16 * 27];
   __shared__ int sTap[kTapsT];
-  const int tile = xcd_tile(ntiles);
-  if (tile >= ntiles) return;
+  const int item = xcd_tile(ntiles * nsplit);
+  if (item >= ntiles * nsplit) return;
+  const int tile = item / nsplit, chunk = item - tile * nsplit;
+  const int tb = chunk * kTapsT / nsplit, te = (chunk + 1) * kTapsT / nsplit;
   const int lane = threadIdx.x, n = lane & 15, g = lane >> 4;
   adj_tile_setup(tiles + (size_t)tile * 17, lvp, sS, sCB, sTap, tapsT);
   int off[RT][8];
@@ -400,34 +438,35 @@ __global__ __launch_bounds__(64) void k_adj_m2p_mfma(const int32_t* __restrict__
   for (int rt = 0; rt < RT; ++rt) acc[rt] = {0, 0, 0, 0};
   V bA[NVB], bB[NVB];
   T vD[ND];
-  int gn = adj_group(sTap[0], n, sCB, lvs.rank);
+  int gn = adj_group(sTap[tb], n, sCB, lvs.rank);
   loadB(gn, bA);
-  load_drows_t<T, K, KS, 64>(sTap[0] >> 8, Dil, vD);
+  load_drows_t<T, K, KS, 64>(sTap[tb] >> 8, Dil, vD);
   store_drows_t<T, K, KS, 64>(sD[0], vD);
-  gn = adj_group(sTap[1], n, sCB, lvs.rank);
+  if (tb + 1 < te) gn = adj_group(sTap[tb + 1], n, sCB, lvs.rank);
   __syncthreads();
   auto step = [&](int k, const V* bc, V* bn) {
-    const int b = k & 1;
-    if (k + 1 < kTapsT) {
+    const int b = (k - tb) & 1;
+    if (k + 1 < te) {
       loadB(gn, bn);
       load_drows_t<T, K, KS, 64>(sTap[k + 1] >> 8, Dil, vD);
     }
-    if (k + 2 < kTapsT) gn = adj_group(sTap[k + 2], n, sCB, lvs.rank);
+    if (k + 2 < te) gn = adj_group(sTap[k + 2], n, sCB, lvs.rank);
     const T* D = sD[b];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
       for (int kb = 0; kb < 8; ++kb) acc[rt] = mfma16(D[off[rt][kb]], bc[kb / VW][kb % VW], acc[rt]);
-    if (k + 1 < kTapsT) store_drows_t<T, K, KS, 64>(sD[b ^ 1], vD);
+    if (k + 1 < te) store_drows_t<T, K, KS, 64>(sD[b ^ 1], vD);
     __syncthreads();
   };
-  for (int k = 0; k < kTapsT; k += 2) {
+  for (int k = tb; k < te; k += 2) {
     step(k, bA, bB);
-    if (k + 1 < kTapsT) step(k + 1, bB, bA);
+    if (k + 1 < te) step(k + 1, bB, bA);
   }
   const int s = sS[n];
+  double* pp = nsplit > 1 ? part + ((size_t)chunk * ntiles + tile) * 16 * K : nullptr;
 #pragma unroll
-  for (int rt = 0; rt < RT; ++rt) adj_write<T, K>(acc[rt], rt, lane, s, lvs);
+  for (int rt = 0; rt < RT; ++rt) adj_write<T, K>(acc[rt], rt, lane, s, lvs, pp);
 }
 
 // Transposed M2L: targets = refined children y (level ls + 1) of the groups
@@ -457,8 +496,8 @@ constexpr AdjM2LPlan<P> make_adj_m2l_plan() {
 }
 
 template <typename T, int P>
-__global__ __launch_bounds__(64) void k_adj_m2l_mfma(const int32_t* __restrict__ tiles, int ntiles,
-                                                     const int32_t* __restrict__ tapsT,
+__global__ __launch_bounds__(64) void k_adj_m2l_mfma(const int32_t* __restrict__ tiles, int ntiles, int nsplit,
+                                                     double* __restrict__ part, const int32_t* __restrict__ tapsT,
                                                      const int16_t* __restrict__ aoff, LevelDev lvp, LevelDev lvs,
                                                      LevelDev lvt, const T* __restrict__ lT,
                                                      const T* __restrict__ Dil) {
@@ -472,8 +511,10 @@ __global__ __launch_bounds__(64) void k_adj_m2l_mfma(const int32_t* __restrict__
   __shared__ int sS[16];
   __shared__ int sCB[16 * 27];
   __shared__ int sTap[kTapsT];
-  const int tile = xcd_tile(ntiles);
-  if (tile >= ntiles) return;
+  const int item = xcd_tile(ntiles * nsplit);
+  if (item >= ntiles * nsplit) return;
+  const int tile = item / nsplit, chunk = item - tile * nsplit;
+  const int tb = chunk * kTapsT / nsplit, te = (chunk + 1) * kTapsT / nsplit;
   const int lane = threadIdx.x, n = lane & 15, g = lane >> 4;
   adj_tile_setup(tiles + (size_t)tile * 17, lvp, sS, sCB, sTap, tapsT);
   int off[PL.total];
@@ -497,17 +538,17 @@ __global__ __launch_bounds__(64) void k_adj_m2l_mfma(const int32_t* __restrict__
   for (int rt = 0; rt < RT; ++rt) acc[rt] = {0, 0, 0, 0};
   V bA[NVB], bB[NVB];
   T vD[ND];
-  int gcur = adj_group(sTap[0], n, sCB, lvs.rank);
-  int gnext = adj_group(sTap[1], n, sCB, lvs.rank);
+  int gcur = adj_group(sTap[tb], n, sCB, lvs.rank);
+  int gnext = tb + 1 < te ? adj_group(sTap[tb + 1], n, sCB, lvs.rank) : -1;
   loadB(child(gcur, 0), bA);
-  load_drows_t<T, K, KS, 64>(sTap[0] >> 8, Dil, vD);
+  load_drows_t<T, K, KS, 64>(sTap[tb] >> 8, Dil, vD);
   store_drows_t<T, K, KS, 64>(sD[0], vD);
   __syncthreads();
   // sub-step (tap k, octant o): B of (k, o) in bc; prefetch (k, o+1) or (k+1, 0) into bn
   auto sub = [&](int k, int o, const V* bc, V* bn) {
-    const int b = k & 1;
+    const int b = (k - tb) & 1;
     if (o < 7) loadB(child(gcur, o + 1), bn);
-    else if (k + 1 < kTapsT) loadB(child(gnext, 0), bn);
+    else if (k + 1 < te) loadB(child(gnext, 0), bn);
     const T* D = sD[b] + o * KS;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
@@ -515,22 +556,42 @@ __global__ __launch_bounds__(64) void k_adj_m2l_mfma(const int32_t* __restrict__
       for (int kb = 0; kb < PL.ks[rt]; ++kb)
         acc[rt] = mfma16(D[off[PL.base[rt] + kb]], bc[kb / VW][kb % VW], acc[rt]);
   };
-  for (int k = 0; k < kTapsT; ++k) {
-    const int b = k & 1;
-    if (k + 1 < kTapsT) load_drows_t<T, K, KS, 64>(sTap[k + 1] >> 8, Dil, vD);
+  for (int k = tb; k < te; ++k) {
+    const int b = (k - tb) & 1;
+    if (k + 1 < te) load_drows_t<T, K, KS, 64>(sTap[k + 1] >> 8, Dil, vD);
 #pragma unroll
     for (int o = 0; o < 8; o += 2) {
       sub(k, o, bA, bB);
       sub(k, o + 1, bB, bA);
     }
-    if (k + 1 < kTapsT) store_drows_t<T, K, KS, 64>(sD[b ^ 1], vD);
+    if (k + 1 < te) store_drows_t<T, K, KS, 64>(sD[b ^ 1], vD);
     gcur = gnext;
-    if (k + 2 < kTapsT) gnext = adj_group(sTap[k + 2], n, sCB, lvs.rank);
+    if (k + 2 < te) gnext = adj_group(sTap[k + 2], n, sCB, lvs.rank);
     __syncthreads();
   }
   const int s = sS[n];
+  double* pp = nsplit > 1 ? part + ((size_t)chunk * ntiles + tile) * 16 * K : nullptr;
 #pragma unroll
-  for (int rt = 0; rt < RT; ++rt) adj_write<T, K>(acc[rt], rt, lane, s, lvs);
+  for (int rt = 0; rt < RT; ++rt) adj_write<T, K>(acc[rt], rt, lane, s, lvs, pp);
+}
+
+// Ordered sum of the tap-split partial sets of a transposed translation into
+// the source bars (thread = tile column x coefficient).
+template <int P>
+__global__ void k_adj_reduce(const int32_t* __restrict__ tiles, int ntiles, int nsplit,
+                             const double* __restrict__ part, LevelDev lvs) {
+  constexpr int K = nmi(P);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ntiles * 16 * K) return;
+  const int col = i / K, a = i - col * K;
+  const int s = tiles[(size_t)(col >> 4) * 17 + 1 + (col & 15)];
+  if (s < 0) return;
+  const int rs = lvs.rank[s];
+  if (rs < 0 && a != 0) return;
+  double v = 0.0;
+  for (int c = 0; c < nsplit; ++c) v += part[((size_t)c * ntiles * 16 + col) * K + a];
+  if (rs >= 0) lvs.sbar[(size_t)rs * K + a] += v;
+  else lvs.mbar[s] += v;
 }
 
 // ---------------------------------------------------------------------------
@@ -592,10 +653,17 @@ hipError_t launch_adj_down(int p, const LevelDev& lv1, const LevelDev& lv0, int 
                            hipStream_t st) {
   const int n = lv0.nref * nmi(p);
   if (n == 0) return hipSuccess;
+  if (has_parent) {
 #define X(PP) \
-  case PP: hipLaunchKernelGGL((k_adj_down<PP>), dim3((n + 255) / 256), dim3(256), 0, st, lv1, lv0, has_parent, cm); break;
-  AFMM_P_SWITCH(p, X)
+  case PP: hipLaunchKernelGGL((k_adj_down<PP>), dim3(lv1.nref), dim3(256), 0, st, lv1, lv0, cm); break;
+    AFMM_P_SWITCH(p, X)
 #undef X
+  } else {
+#define X(PP) \
+  case PP: hipLaunchKernelGGL((k_adj_scale<PP>), dim3((n + 255) / 256), dim3(256), 0, st, lv0, cm); break;
+    AFMM_P_SWITCH(p, X)
+#undef X
+  }
   return hipGetLastError();
 }
 
@@ -612,52 +680,67 @@ hipError_t launch_adj_out(int p, const LevelDev& lv1, const LevelDev& lv0, int h
   return hipGetLastError();
 }
 
-template <typename T>
-static hipError_t adj_m2p_t(int p, const int32_t* tiles, int ntiles, const int32_t* tapsT, const int16_t* aoff,
-                            const LevelDev& lvp, const LevelDev& lvs, const LevelDev& lvt, const T* Dil,
-                            hipStream_t st) {
-  T* tbT = (T*)lvs.tbT;
-  hipLaunchKernelGGL((k_adj_tbT<T>), dim3((lvs.nref * 32 + 255) / 256), dim3(256), 0, st, lvs, lvt, tbT);
-  const dim3 grid(8 * ((ntiles + 7) / 8)), block(64);
+static hipError_t adj_reduce(int p, const int32_t* tiles, int ntiles, int nsplit, const double* part,
+                             const LevelDev& lvs, hipStream_t st) {
+  if (nsplit <= 1) return hipGetLastError();
+  const int n = ntiles * 16 * nmi(p);
 #define X(PP) \
-  case PP: hipLaunchKernelGGL((k_adj_m2p_mfma<T, PP>), grid, block, 0, st, tiles, ntiles, tapsT, aoff, lvp, lvs, (const T*)tbT, Dil); break;
+  case PP: hipLaunchKernelGGL((k_adj_reduce<PP>), dim3((n + 255) / 256), dim3(256), 0, st, tiles, ntiles, nsplit, part, lvs); break;
   AFMM_P_SWITCH(p, X)
 #undef X
   return hipGetLastError();
 }
 
-hipError_t launch_adj_m2p_mfma(int p, bool fp32, const int32_t* tiles, int ntiles, const int32_t* tapsT,
-                               const int16_t* aoff, const LevelDev& lvp, const LevelDev& lvs, const LevelDev& lvt,
-                               const TablesDev<float>& t32, const TablesDev<double>& t64, hipStream_t st) {
+template <typename T>
+static hipError_t adj_m2p_t(int p, const int32_t* tiles, int ntiles, int nsplit, double* part, const int32_t* tapsT,
+                            const int16_t* aoff, const LevelDev& lvp, const LevelDev& lvs, const LevelDev& lvt,
+                            const T* Dil, hipStream_t st) {
+  T* tbT = (T*)lvs.tbT;
+  hipLaunchKernelGGL((k_adj_tbT<T>), dim3((lvs.nref * 32 + 255) / 256), dim3(256), 0, st, lvs, lvt, tbT);
+  const int items = ntiles * nsplit;
+  const dim3 grid(8 * ((items + 7) / 8)), block(64);
+#define X(PP) \
+  case PP: hipLaunchKernelGGL((k_adj_m2p_mfma<T, PP>), grid, block, 0, st, tiles, ntiles, nsplit, part, tapsT, aoff, lvp, lvs, (const T*)tbT, Dil); break;
+  AFMM_P_SWITCH(p, X)
+#undef X
+  return adj_reduce(p, tiles, ntiles, nsplit, part, lvs, st);
+}
+
+hipError_t launch_adj_m2p_mfma(int p, bool fp32, const int32_t* tiles, int ntiles, int nsplit, double* part,
+                               const int32_t* tapsT, const int16_t* aoff, const LevelDev& lvp, const LevelDev& lvs,
+                               const LevelDev& lvt, const TablesDev<float>& t32, const TablesDev<double>& t64,
+                               hipStream_t st) {
   if (ntiles <= 0 || lvs.nref == 0) return hipSuccess;
-  if (fp32) return adj_m2p_t<float>(p, tiles, ntiles, tapsT, aoff, lvp, lvs, lvt, t32.Dil, st);
-  return adj_m2p_t<double>(p, tiles, ntiles, tapsT, aoff, lvp, lvs, lvt, t64.Dil, st);
+  if (fp32) return adj_m2p_t<float>(p, tiles, ntiles, nsplit, part, tapsT, aoff, lvp, lvs, lvt, t32.Dil, st);
+  return adj_m2p_t<double>(p, tiles, ntiles, nsplit, part, tapsT, aoff, lvp, lvs, lvt, t64.Dil, st);
 }
 
 template <typename T>
-static hipError_t adj_m2l_t(int p, const int32_t* tiles, int ntiles, const int32_t* tapsT, const int16_t* aoff,
-                            const LevelDev& lvp, const LevelDev& lvs, const LevelDev& lvt, const T* Dil,
-                            hipStream_t st) {
+static hipError_t adj_m2l_t(int p, const int32_t* tiles, int ntiles, int nsplit, double* part, const int32_t* tapsT,
+                            const int16_t* aoff, const LevelDev& lvp, const LevelDev& lvs, const LevelDev& lvt,
+                            const T* Dil, hipStream_t st) {
   T* lT = (T*)lvt.lbarT;
   const int rows = lvt.nref * src_row(p, (int)sizeof(T));
 #define X(PP) \
   case PP: hipLaunchKernelGGL((k_adj_lbarT<T, PP>), dim3((rows + 255) / 256), dim3(256), 0, st, lvt, lT); break;
   AFMM_P_SWITCH(p, X)
 #undef X
-  const dim3 grid(8 * ((ntiles + 7) / 8)), block(64);
+  const int items = ntiles * nsplit;
+  const dim3 grid(8 * ((items + 7) / 8)), block(64);
 #define X(PP) \
-  case PP: hipLaunchKernelGGL((k_adj_m2l_mfma<T, PP>), grid, block, 0, st, tiles, ntiles, tapsT, aoff, lvp, lvs, lvt, (const T*)lT, Dil); break;
+  case PP: hipLaunchKernelGGL((k_adj_m2l_mfma<T, PP>), grid, block, 0, st, tiles, ntiles, nsplit, part, tapsT, aoff, lvp, lvs, lvt, (const T*)lT, Dil); break;
   AFMM_P_SWITCH(p, X)
 #undef X
-  return hipGetLastError();
+  return adj_reduce(p, tiles, ntiles, nsplit, part, lvs, st);
 }
 
-hipError_t launch_adj_m2l_mfma(int p, bool fp32, const int32_t* tiles, int ntiles, const int32_t* tapsT,
-                               const int16_t* aoff, const LevelDev& lvp, const LevelDev& lvs, const LevelDev& lvt,
-                               const TablesDev<float>& t32, const TablesDev<double>& t64, hipStream_t st) {
+hipError_t launch_adj_m2l_mfma(int p, bool fp32, const int32_t* tiles, int ntiles, int nsplit, double* part,
+                               const int32_t* tapsT, const int16_t* aoff, const LevelDev& lvp, const LevelDev& lvs,
+                               const LevelDev& lvt, const TablesDev<float>& t32, const TablesDev<double>& t64,
+                               hipStream_t st) {
   if (ntiles <= 0 || lvt.nref == 0) return hipSuccess;
-  if (fp32) return adj_m2l_t<float>(p, tiles, ntiles, tapsT, aoff, lvp, lvs, lvt, t32.Dil, st);
-  return adj_m2l_t<double>(p, tiles, ntiles, tapsT, aoff, lvp, lvs, lvt, t64.Dil, st);
+  if (fp32) return adj_m2l_t<float>(p, tiles, ntiles, nsplit, part, tapsT, aoff, lvp, lvs, lvt, t32.Dil, st);
+  return adj_m2l_t<double>(p, tiles, ntiles, nsplit, part, tapsT, aoff, lvp, lvs, lvt, t64.Dil, st);
 }
 
 #undef AFMM_P_SWITCH

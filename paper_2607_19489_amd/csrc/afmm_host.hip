@@ -424,6 +424,7 @@ struct HostTables {
   std::vector<int32_t> m2l_tinfo;   // [NT][2]
   std::vector<int16_t> adj_m2p_off, adj_m2l_off;
   std::vector<int32_t> l2lT_start, l2lT_list;
+  std::vector<double> l2lT_w;
 };
 
 static long double ipow(long double x, int n) {
@@ -612,6 +613,11 @@ static void build_tables(int p, HostTables& H) {
     }
   }
   H.l2lT_start[K] = (int32_t)H.l2lT_list.size();
+  H.l2lT_w.assign(H.l2lT_list.size() * 8, 0.0);
+  for (size_t j = 0; j < H.l2lT_list.size(); ++j) {
+    const int g = (H.l2lT_list[j] >> 8) & 255, nb = H.l2lT_list[j] >> 16;
+    for (int o = 0; o < 8; ++o) H.l2lT_w[8 * j + o] = H.l2lw[((size_t)o * (p + 1) + nb) * K + g];
+  }
   // adjoint: transposed M2P, rows a (tiles of 16), k = 8 g + kb -> (child o, quantity q)
   {
     const int RT = (K + 15) / 16;
@@ -703,6 +709,8 @@ struct afmm_plan {
   int32_t* d_adjp[kMaxLevel] = {};
   int32_t* d_adjl[kMaxLevel] = {};
   int n_adjp[kMaxLevel] = {}, n_adjl[kMaxLevel] = {};
+  int s_adjp[kMaxLevel] = {}, s_adjl[kMaxLevel] = {};  // their tap splits
+  double* adj_part = nullptr;     // partial sets of the split transposed translations
   std::vector<void*> allocs;
   size_t bytes = 0;
   bool dead = false;              // sticky device error
@@ -1063,9 +1071,13 @@ static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
     P->cm.adj_m2p_off = d_ap;
     P->cm.adj_m2l_off = d_al;
     int32_t *d_lts, *d_ltl;
-    if ((s = upload(P, H.l2lT_start, &d_lts, st)) || (s = upload(P, H.l2lT_list, &d_ltl, st))) return s;
+    double* d_ltw;
+    if ((s = upload(P, H.l2lT_start, &d_lts, st)) || (s = upload(P, H.l2lT_list, &d_ltl, st)) ||
+        (s = upload(P, H.l2lT_w, &d_ltw, st)))
+      return s;
     P->cm.l2lT_start = d_lts;
     P->cm.l2lT_list = d_ltl;
+    P->cm.l2lT_w = d_ltw;
     P->mt.taps = d_taps;
     P->mt.m2p_off = d_m2p_off;
     P->mt.m2l_off = d_m2l_off;
@@ -1651,6 +1663,26 @@ static afmm_status adjoint_workspace(afmm_plan* P) {
       P->lv[f].lbarT = q;
     }
   }
+  // tap splits of the transposed translations: about 12 waves per CU
+  int ncu = 256;
+  {
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (ncu <= 0) ncu = 256;
+  }
+  size_t part_max = 0;
+  auto split_of = [&](int nt) { return nt > 0 ? std::max(1, std::min(16, (12 * ncu + nt - 1) / nt)) : 1; };
+  for (int l = 0; l < kMaxLevel; ++l) {
+    P->s_adjp[l] = split_of(P->n_adjp[l]);
+    P->s_adjl[l] = split_of(P->n_adjl[l]);
+    if (P->s_adjp[l] > 1) part_max = std::max(part_max, (size_t)P->s_adjp[l] * P->n_adjp[l] * 16 * K);
+    if (P->s_adjl[l] > 1) part_max = std::max(part_max, (size_t)P->s_adjl[l] * P->n_adjl[l] * 16 * K);
+  }
+  if (part_max > 0) {
+    void* q = nullptr;
+    if ((s = dev_alloc(P, &q, part_max * sizeof(double)))) return s;
+    P->adj_part = (double*)q;
+  }
   if (hipDeviceSynchronize() != hipSuccess) return fail(AFMM_E_DEVICE, "adjoint workspace upload");
   P->adj_ready = true;
   return AFMM_OK;
@@ -1711,9 +1743,9 @@ extern "C" afmm_status afmm_solve_adjoint(afmm_plan* P, int32_t level, const dou
   const int f64 = mixed ? P->opt.fp64_levels : 1 << 20;
   for (int l = std::max(3, lo); l <= hi; ++l) {
     if ((s = dev_check(P,
-                       launch_adj_m2p_mfma(p, mixed && (l - 1) > f64, P->d_adjp[l], P->n_adjp[l], P->cm.tapsT,
-                                           P->cm.adj_m2p_off, P->lv[l - 2], P->lv[l - 1], P->lv[l], P->t32, P->t64,
-                                           st),
+                       launch_adj_m2p_mfma(p, mixed && (l - 1) > f64, P->d_adjp[l], P->n_adjp[l], P->s_adjp[l],
+                                           P->adj_part, P->cm.tapsT, P->cm.adj_m2p_off, P->lv[l - 2], P->lv[l - 1],
+                                           P->lv[l], P->t32, P->t64, st),
                        "adjoint m2p")))
       return s;
     P->pending_flops += W.m2p_flops[l];
@@ -1729,9 +1761,9 @@ extern "C" afmm_status afmm_solve_adjoint(afmm_plan* P, int32_t level, const dou
   ev = prof_begin(P, st);
   for (int f = 3; f <= fmax; ++f) {
     if ((s = dev_check(P,
-                       launch_adj_m2l_mfma(p, mixed && f > f64, P->d_adjl[f], P->n_adjl[f], P->cm.tapsT,
-                                           P->cm.adj_m2l_off, P->lv[f - 2], P->lv[f - 1], P->lv[f], P->t32, P->t64,
-                                           st),
+                       launch_adj_m2l_mfma(p, mixed && f > f64, P->d_adjl[f], P->n_adjl[f], P->s_adjl[f],
+                                           P->adj_part, P->cm.tapsT, P->cm.adj_m2l_off, P->lv[f - 2], P->lv[f - 1],
+                                           P->lv[f], P->t32, P->t64, st),
                        "adjoint m2l")))
       return s;
     P->pending_flops += W.m2l_flops[f];

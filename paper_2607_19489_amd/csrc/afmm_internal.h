@@ -27,6 +27,10 @@ constexpr int kKMax = 165;          // C(kPMax + 3, 3)
 constexpr int kNumD = 343;          // offsets d in [-3, 3]^3
 
 __host__ __device__ constexpr int nmi(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
+// number of pairs (a, k) with k <= a componentwise and |a| <= p: C(p + 6, 6)
+__host__ __device__ constexpr int nmi_entries(int p) {
+  return (p + 1) * (p + 2) * (p + 3) * (p + 4) * (p + 5) * (p + 6) / 720;
+}
 
 // Position of multi-index (a, b, c) in the degree-graded order (degree, then a
 // descending, then b descending).
@@ -104,6 +108,7 @@ struct CommonDev {
   const int16_t* adj_m2l_off = nullptr; // [steps][64] A offsets (within one D~ row) of the transposed M2L
   const int32_t* l2lT_start = nullptr;  // [K+1] transposed L2L pairs of each coefficient c
   const int32_t* l2lT_list = nullptr;   // b | (c - b) << 8 | |b| << 16
+  const double* l2lT_w = nullptr;       // [entries][8] weights 2^(-1-|b|) u_o^(c-b)/(c-b)! per octant o
 };
 
 // Group tiles of the MFMA kernels: NC refined ranks per tile (one parity class,
@@ -140,13 +145,17 @@ hipError_t launch_adj_near(int p, const LevelDev& lv1, const LevelDev& lv0, cons
                            const TablesDev<double>& t64, const CommonDev& cm, hipStream_t st);
 hipError_t launch_adj_l2p(int p, const LevelDev& lv1, const LevelDev& lv0, const TablesDev<double>& t64,
                           hipStream_t st);
-// MFMA forms: tiles of 16 source cells (records: target level, 16 cells).
-hipError_t launch_adj_m2p_mfma(int p, bool fp32, const int32_t* tiles, int ntiles, const int32_t* tapsT,
-                               const int16_t* aoff, const LevelDev& lvp, const LevelDev& lvs, const LevelDev& lvt,
-                               const TablesDev<float>& t32, const TablesDev<double>& t64, hipStream_t st);
-hipError_t launch_adj_m2l_mfma(int p, bool fp32, const int32_t* tiles, int ntiles, const int32_t* tapsT,
-                               const int16_t* aoff, const LevelDev& lvp, const LevelDev& lvs, const LevelDev& lvt,
-                               const TablesDev<float>& t32, const TablesDev<double>& t64, hipStream_t st);
+// MFMA forms: tiles of 16 source cells (records: target level, 16 cells); with
+// nsplit > 1 the 189 taps of a tile are split over blocks writing partial sets
+// into `part` ([nsplit][ntiles * 16][K] FP64), summed in order afterwards.
+hipError_t launch_adj_m2p_mfma(int p, bool fp32, const int32_t* tiles, int ntiles, int nsplit, double* part,
+                               const int32_t* tapsT, const int16_t* aoff, const LevelDev& lvp, const LevelDev& lvs,
+                               const LevelDev& lvt, const TablesDev<float>& t32, const TablesDev<double>& t64,
+                               hipStream_t st);
+hipError_t launch_adj_m2l_mfma(int p, bool fp32, const int32_t* tiles, int ntiles, int nsplit, double* part,
+                               const int32_t* tapsT, const int16_t* aoff, const LevelDev& lvp, const LevelDev& lvs,
+                               const LevelDev& lvt, const TablesDev<float>& t32, const TablesDev<double>& t64,
+                               hipStream_t st);
 hipError_t launch_adj_l2l(int p, const LevelDev& lv1, const LevelDev& lv0, const TablesDev<double>& t64,
                           const CommonDev& cm, hipStream_t st);
 hipError_t launch_adj_down(int p, const LevelDev& lv1, const LevelDev& lv0, int has_parent, const CommonDev& cm,

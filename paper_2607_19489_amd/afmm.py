@@ -230,10 +230,12 @@ class Batch:
 
     def autotune(self, masses: Sequence[torch.Tensor], stream: Optional[torch.cuda.Stream] = None) -> dict:
         """afmm_batch_autotune: pick the tap splits by timing and capture the graph again."""
-        _, _, mp, pp, ap = self._arrays(masses, None, None)
+        # phis/accs stay referenced until the call returns: the table holds their addresses
+        phis, accs, mp, pp, ap = self._arrays(masses, None, None)
         res = TuneResult()
         check(lib().afmm_batch_autotune(self._ptr, mp, pp, ap, _stream_handle(stream), C.byref(res)),
               "afmm_batch_autotune")
+        del phis, accs
         return res.as_dict()
 
     def solve(self, masses: Sequence[torch.Tensor], phis: Optional[Sequence[torch.Tensor]] = None,

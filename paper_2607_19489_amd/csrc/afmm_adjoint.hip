@@ -73,14 +73,15 @@ __global__ void k_adj_zero(size_t n, double* __restrict__ p) {
 }
 
 // P2P^T for the leaves s of level l (block = one refined cell F of level l-1,
-// s = its child o).  Targets that read s through a P2P:
+// s = its child o = t & 7; partial sums reduced by shuffles within a wave and
+// through LDS across waves).  Targets that read s through a P2P:
 //   level l leaves n among the children of F's 27 neighbours (near field),
 //   level l+1 children of a refined level-l n touching s (s is in their near
 //     field as a coarse leaf),
 //   level l-1 leaves q touching F (s is in q's nearest field).
 __global__ __launch_bounds__(256) void k_adj_near_leaf(LevelDev lv1, LevelDev lv0, LevelDev lvp) {
   __shared__ int s_nb[27];
-  __shared__ double s_red[256];
+  __shared__ double s_red[4][8];
   const int F = blockIdx.x;
   const int t = threadIdx.x, o = t & 7, j = t >> 3;
   if (t < 27) s_nb[t] = lv1.nbr[(size_t)F * 27 + t];
@@ -115,13 +116,11 @@ __global__ __launch_bounds__(256) void k_adj_near_leaf(LevelDev lv1, LevelDev lv
       }
     }
   }
-  s_red[t] = acc;
+#pragma unroll
+  for (int w = 8; w <= 32; w <<= 1) acc += __shfl_xor(acc, w, 64);
+  if ((t & 63) < 8) s_red[t >> 6][o] = acc;
   __syncthreads();
-  if (t < 8 && lv0.rank[8 * F + t] < 0) {
-    double sum = 0.0;
-    for (int jj = 0; jj < 32; ++jj) sum += s_red[t + 8 * jj];
-    lv0.mbar[8 * F + t] += sum;
-  }
+  if (t < 8 && lv0.rank[s] < 0) lv0.mbar[s] += s_red[0][o] + s_red[1][o] + s_red[2][o] + s_red[3][o];
 }
 
 // Near-field M2P^T: a refined level-l cell s is read, through 2^-|a| times its

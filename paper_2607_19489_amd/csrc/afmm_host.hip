@@ -736,7 +736,8 @@ struct afmm_batch {
   int32_t* d_leafhier = nullptr;  // its hierarchy
   int64_t* d_base = nullptr;
   void** d_ptrs = nullptr;        // [3][n] caller pointers (mass, phi, acc), refreshed per solve
-  std::vector<void*> h_ptrs;
+  void** h_stage = nullptr;       // pinned [3][n] caller pointers, read by the asynchronous table upload
+  hipEvent_t ev_stage = nullptr;  // recorded after that upload: h_stage may be rewritten once it completes
   int64_t nleaf = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -767,7 +768,9 @@ afmm_status upload(afmm_plan* P, const std::vector<V>& v, V** out, hipStream_t s
   void* p = nullptr;
   afmm_status s = dev_alloc(P, &p, v.size() * sizeof(V));
   if (s) return s;
-  if (hipMemcpyAsync(p, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice, st) != hipSuccess)
+  // the source is often a temporary: wait for the copy before it can go away
+  if (hipMemcpyAsync(p, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
     return fail(AFMM_E_DEVICE, "upload failed");
   *out = (V*)p;
   return AFMM_OK;
@@ -1439,6 +1442,8 @@ extern "C" afmm_status afmm_plan_get_profile(afmm_plan* P, afmm_stage_time* out,
 }
 
 static afmm_status capture_batch(afmm_batch* B);
+static afmm_status batch_pointer_table(afmm_batch* B, const double* const* d_mass, double* const* d_phi,
+                                       double* const* d_acc, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Autotuner: the tap splits of M2L and M2P set the work per block (how many of
@@ -1556,19 +1561,9 @@ extern "C" afmm_status afmm_batch_autotune(afmm_batch* B, const double* const* d
   if (!B || !d_mass || !d_phi || !d_acc) return fail(AFMM_E_INVALID_ARG, "null argument");
   afmm_plan* P = B->plan;
   if (P->dead) return fail(AFMM_E_DEVICE, "batch is unusable after an earlier device error");
-  const int32_t n = B->n;
-  for (int32_t i = 0; i < n; ++i) {
-    if (!d_mass[i] || !d_phi[i] || !d_acc[i]) return fail(AFMM_E_INVALID_ARG, "null array in batch");
-    B->h_ptrs[i] = (void*)d_mass[i];
-    B->h_ptrs[n + i] = (void*)d_phi[i];
-    B->h_ptrs[2 * n + i] = (void*)d_acc[i];
-  }
   hipStream_t st = (hipStream_t)hip_stream;
   afmm_status s;
-  if ((s = dev_check(P, hipMemcpyAsync(B->d_ptrs, B->h_ptrs.data(), (size_t)3 * n * sizeof(void*),
-                                       hipMemcpyHostToDevice, st),
-                     "batch pointer table")))
-    return s;
+  if ((s = batch_pointer_table(B, d_mass, d_phi, d_acc, st))) return s;
   const Topology& T = P->topo;
   auto solve = [&]() -> afmm_status {
     afmm_status r;
@@ -1813,10 +1808,38 @@ static void merge_topology(Topology& T, const Topology& S, int64_t slot_base) {
   T.nslots = slot_base + S.nslots;
 }
 
+// Refresh the device table of caller pointers (stream-ordered, no host sync
+// unless the previous refresh is still pending).
+static afmm_status batch_pointer_table(afmm_batch* B, const double* const* d_mass, double* const* d_phi,
+                                       double* const* d_acc, hipStream_t st) {
+  const int32_t n = B->n;
+  for (int32_t i = 0; i < n; ++i)
+    if (!d_mass[i] || !d_phi[i] || !d_acc[i]) return fail(AFMM_E_INVALID_ARG, "null array in batch");
+  if (hipEventSynchronize(B->ev_stage) != hipSuccess) return dev_check(B->plan, hipGetLastError(), "table event");
+  for (int32_t i = 0; i < n; ++i) {
+    B->h_stage[i] = (void*)d_mass[i];
+    B->h_stage[n + i] = (void*)d_phi[i];
+    B->h_stage[2 * n + i] = (void*)d_acc[i];
+  }
+  afmm_status s;
+  if ((s = dev_check(B->plan, hipMemcpyAsync(B->d_ptrs, B->h_stage, (size_t)3 * n * sizeof(void*),
+                                             hipMemcpyHostToDevice, st),
+                     "batch pointer table")))
+    return s;
+  return dev_check(B->plan, hipEventRecord(B->ev_stage, st), "table event");
+}
+
 static void free_batch(afmm_batch* B) {
   if (B->exec) (void)hipGraphExecDestroy(B->exec);
   if (B->graph) (void)hipGraphDestroy(B->graph);
   if (B->cap) (void)hipStreamDestroy(B->cap);
+  if (B->ev_stage) {
+    (void)hipEventSynchronize(B->ev_stage);
+    (void)hipEventDestroy(B->ev_stage);
+  }
+  if (B->h_stage) (void)hipHostFree(B->h_stage);
+  B->ev_stage = nullptr;
+  B->h_stage = nullptr;
   if (B->plan) {
     free_plan(B->plan);
     delete B->plan;
@@ -1912,7 +1935,10 @@ extern "C" afmm_status afmm_batch_create(afmm_plan* const* plans, int32_t n, voi
     if (!s) s = upload(P, lslot, &B->d_leafslot, st);
     if (!s) s = upload(P, lhier, &B->d_leafhier, st);
     if (!s) s = upload(P, B->base, &B->d_base, st);
-    B->h_ptrs.assign((size_t)3 * n, nullptr);
+    if (!s && (hipHostMalloc((void**)&B->h_stage, (size_t)3 * n * sizeof(void*), hipHostMallocDefault) != hipSuccess ||
+               hipEventCreateWithFlags(&B->ev_stage, hipEventDisableTiming) != hipSuccess ||
+               hipEventRecord(B->ev_stage, st) != hipSuccess))
+      s = fail(AFMM_E_DEVICE, "batch pointer staging");
   }
   // capture: gather -> solve -> scatter, replayed by afmm_batch_solve
   if (!s) {
@@ -1935,19 +1961,9 @@ extern "C" afmm_status afmm_batch_solve(afmm_batch* B, const double* const* d_ma
   if (!B || !d_mass || !d_phi || !d_acc) return fail(AFMM_E_INVALID_ARG, "null argument");
   if (B->plan->dead) return fail(AFMM_E_DEVICE, "batch is unusable after an earlier device error");
   const int32_t n = B->n;
-  for (int32_t i = 0; i < n; ++i) {
-    if (!d_mass[i] || !d_phi[i] || !d_acc[i]) return fail(AFMM_E_INVALID_ARG, "null array in batch");
-    B->h_ptrs[i] = (void*)d_mass[i];
-    B->h_ptrs[n + i] = (void*)d_phi[i];
-    B->h_ptrs[2 * n + i] = (void*)d_acc[i];
-  }
   hipStream_t st = (hipStream_t)hip_stream;
   afmm_status s;
-  // pageable source: the runtime stages it before returning, so h_ptrs may be reused
-  if ((s = dev_check(B->plan, hipMemcpyAsync(B->d_ptrs, B->h_ptrs.data(), (size_t)3 * n * sizeof(void*),
-                                             hipMemcpyHostToDevice, st),
-                     "batch pointer table")))
-    return s;
+  if ((s = batch_pointer_table(B, d_mass, d_phi, d_acc, st))) return s;
   afmm_plan* P = B->plan;
   if (!P->profiling) return dev_check(P, hipGraphLaunch(B->exec, st), "batch graph launch");
   // profiled solves run the same launches eagerly, each bracketed by events

@@ -706,7 +706,10 @@ __global__ __launch_bounds__(kBlock) void k_m2l_mfma(const int32_t* __restrict__
 // The 8 targets of a group share their 216 candidate near cells (children of
 // F's 27 neighbours, or the neighbour itself when it is a leaf): they are
 // resolved once per block into LDS (kind, mass, refined rank), then thread
-// (o = t & 7, j = t >> 3) takes target child o and every 32nd candidate from j.
+// (o = t & 7, j = t >> 3) takes target child o and every 32nd candidate from
+// j (the lanes of a wave share candidates, so the branches on the candidate
+// kind rarely diverge); partial sums are reduced by shuffles within a wave
+// and through LDS across the 4 waves.
 template <typename T, int P>
 __global__ __launch_bounds__(kBlock) void k_near(const int32_t* __restrict__ grp, LevelDev lv1, LevelDev lv0,
                                                  LevelDev lvp, TablesDev<T> tb, const T* __restrict__ Lpar,
@@ -719,7 +722,7 @@ __global__ __launch_bounds__(kBlock) void k_near(const int32_t* __restrict__ grp
   __shared__ int s_rn[216];
   __shared__ T s_m[216];
   __shared__ T s_L[K];
-  __shared__ T s_red[12][kBlock];
+  __shared__ T s_red[kBlock / 64][12][8];
   const int F = grp[blockIdx.x];
   const int t = threadIdx.x;
   const int o = t & 7, j = t >> 3;
@@ -795,26 +798,36 @@ __global__ __launch_bounds__(kBlock) void k_near(const int32_t* __restrict__ grp
                     tb.cfacn, cm.up, nea);
     }
   }
+  T red[12];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    s_red[c][t] = far[c];
-    s_red[4 + c][t] = nea[c];
-    s_red[8 + c][t] = nst[c];
+    red[c] = far[c];
+    red[4 + c] = nea[c];
+    red[8 + c] = nst[c];
   }
+#pragma unroll
+  for (int w = 8; w <= 32; w <<= 1)
+#pragma unroll
+    for (int c = 0; c < 12; ++c) red[c] += __shfl_xor(red[c], w, 64);
+  if ((t & 63) < 8)
+#pragma unroll
+    for (int c = 0; c < 12; ++c) s_red[t >> 6][c][o] = red[c];
   __syncthreads();
-  if (t < 8 && lv0.rank[8 * F + t] < 0) {
+  if (t < 8 && lv0.rank[cell] < 0) {
     double out[4] = {0, 0, 0, 0};
+#pragma unroll
     for (int c = 0; c < 12; ++c) {
-      T s = 0;
-      for (int jj = 0; jj < 32; ++jj) s += s_red[c][t + 8 * jj];
-      out[c & 3] += (double)s;
+      T v = 0;
+#pragma unroll
+      for (int w = 0; w < kBlock / 64; ++w) v += s_red[w][c][o];
+      out[c & 3] += (double)v;
     }
     if (part)
       for (int sp = 0; sp < lv1.npart; ++sp) {
         const T* pp = part + ((size_t)sp * lv1.nref + F) * 32;
-        for (int c = 0; c < 4; ++c) out[c] += (double)pp[c * 8 + t];
+        for (int c = 0; c < 4; ++c) out[c] += (double)pp[c * 8 + o];
       }
-    const int sl = lv0.slot[8 * F + t];
+    const int sl = lv0.slot[cell];
     const double sp = G / h, sa = G / (h * h);
     phi[sl] = sp * out[0];
     acc[3 * (size_t)sl + 0] = sa * out[1];

@@ -18,3 +18,16 @@ def _oracle_built():
     import oracle
     oracle.build(force=False)
     yield
+
+
+# GPU modules run core parity first; the autotuner (which times dozens of
+# candidate launches) runs after everything that checks results.
+_MODULE_ORDER = {"test_gpu_parity.py": 1, "test_gpu_adjoint.py": 2, "test_gpu_batch.py": 3,
+                 "test_gpu_autotune.py": 4}
+
+
+def pytest_collection_modifyitems(config, items):
+    def rank(item):
+        name = os.path.basename(str(item.fspath))
+        return 9 if name.startswith("test_zz") else _MODULE_ORDER.get(name, 0)
+    items.sort(key=rank)

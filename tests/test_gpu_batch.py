@@ -29,6 +29,27 @@ def _members(p):
     return hs, ms
 
 
+def _plans(hs, p, **kw):
+    """Plans of the members; if one is refused, report how its input differs
+    from a fresh generation of the same member (the generators are seeded)."""
+    out = []
+    for i, h in enumerate(hs):
+        try:
+            out.append(A.Plan(h, p=p, **kw))
+        except A.AfmmError:
+            fresh = _members(p)[0][i]
+            for lv, (a, b) in enumerate(zip(h.ijk, fresh.ijk)):
+                bad = np.nonzero(np.any(a != b, axis=1))[0] if a.shape == b.shape else np.arange(len(a))
+                if bad.size:
+                    print(f"member {i} level {h.levelmin + lv}: {bad.size} cells differ, first {bad[:8]}, "
+                          f"got {a[bad[:4]].tolist()} want {b[bad[:4]].tolist()}, "
+                          f"array at {a.__array_interface__['data'][0]:#x} ({a.dtype}, {a.nbytes} B)", flush=True)
+            same = all(np.array_equal(a, b) for a, b in zip(h.ijk + h.refined, fresh.ijk + fresh.refined))
+            print(f"member {i}: stored arrays {'match' if same else 'differ from'} a fresh generation", flush=True)
+            raise
+    return out
+
+
 def _individual(plans, masses):
     out = []
     for pl, m in zip(plans, masses):
@@ -44,7 +65,7 @@ def _individual(plans, masses):
 def test_batch_equals_individual_bitwise(precision, p):
     hs, ms = _members(p)
     print(f"batch {precision} p={p}: {[h.nleaves() for h in hs]} leaves", flush=True)
-    plans = [A.Plan(h, p=p, precision=precision, tap_split=3) for h in hs]
+    plans = _plans(hs, p, precision=precision, tap_split=3)
     batch = A.Batch(plans)
     info = batch.info()
     assert info["nhier"] == len(hs)

@@ -1086,6 +1086,18 @@ static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
     P->mt.m2l_off = d_m2l_off;
     P->mt.m2l_tinfo = d_tinfo;
   }
+  // D~ rows in the LDS stage layout of the MFMA kernels (per element type: the
+  // padding is to whole 16-byte vectors)
+  auto dstage = [&](int bytes) {
+    const int p = P->opt.p, ks = dstage_ks(p), len = dstage_len(p, bytes);
+    std::vector<double> v((size_t)kNumD * len, 0.0);
+    for (int di = 0; di < kNumD; ++di)
+      for (int o = 0; o < 8; ++o)
+        for (int g = 0; g < K; ++g) v[(size_t)di * len + o * ks + g] = H.Dil[((size_t)di * 8 + o) * K + g];
+    return v;
+  };
+  if ((s = upload_conv<double>(P, dstage(8), &P->t64.Dstage, st))) return s;
+  if (mixed && (s = upload_conv<float>(P, dstage(4), &P->t32.Dstage, st))) return s;
   if ((s = upload_conv<double>(P, H.Dil, &P->t64.Dil, st)) || (s = upload_conv<double>(P, H.Dsame, &P->t64.Dsame, st)) ||
       (s = upload_conv<double>(P, H.cfac2, &P->t64.cfac2, st)) || (s = upload_conv<double>(P, H.cfacn, &P->t64.cfacn, st)) ||
       (s = upload_conv<double>(P, H.l2lw, &P->t64.l2lw, st)) || (s = upload_conv<double>(P, H.l2p, &P->t64.l2p, st)))

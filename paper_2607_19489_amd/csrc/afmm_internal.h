@@ -49,6 +49,15 @@ __host__ __device__ constexpr int src_stp(int p, int bytes) {
 __host__ __device__ constexpr int src_row(int p, int bytes) { return 4 * src_stp(p, bytes); }
 __host__ __device__ constexpr int src_pos(int k, int stp) { return (k & 3) * stp + (k >> 2); }
 
+// D~ rows of one source offset in the layout the MFMA kernels stage in LDS:
+// row o (child octant) at o * dstage_ks(p), coefficients g < K then zeros up
+// to the stride, one zero slot at 8 * dstage_ks(p), zero padding to whole
+// 16-byte vectors for every lane of a wave.  Copied to LDS as is.
+__host__ __device__ constexpr int dstage_ks(int p) { return ((nmi(p) + 3) & ~3) + 1; }
+__host__ __device__ constexpr int dstage_len(int p, int bytes) {
+  return (8 * dstage_ks(p) + 1 + 64 * (16 / bytes) - 1) / (64 * (16 / bytes)) * (64 * (16 / bytes));
+}
+
 // Per-level device view.  Level l holds the children of the refined cells of
 // level l - 1 in Morton order, so cell index c has father refined rank c >> 3
 // and octant c & 7 (o = ox + 2 oy + 4 oz), and refined rank r owns children
@@ -84,6 +93,7 @@ struct LevelDev {
 template <typename T>
 struct TablesDev {
   const T* Dil = nullptr;     // [kNumD * 8][K]  D~ at R~ = -2d + o - 1/2
+  const T* Dstage = nullptr;  // [kNumD][dstage_len(p, sizeof(T))] the same rows in LDS stage layout
   const T* Dsame = nullptr;   // [kNumD][K]      D~ at integer R~ in [-3,3]^3
   const T* cfac2 = nullptr;   // [K] (-1)^|a|/a! 2^|a|
   const T* cfacn = nullptr;   // [K] 2^-|a|: same-level M2P from the source copies

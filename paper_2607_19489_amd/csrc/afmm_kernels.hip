@@ -275,6 +275,9 @@ struct TapStage {
   static constexpr int ROW = 4 * STP;        // source-copy row length
   static constexpr int NVB = STP / VW;       // 16-byte vectors per lane and tap
   static constexpr int SD = 8 * KS + 1;      // sD size (8 rows + zero slot)
+  static constexpr int SDP = dstage_len(P, (int)sizeof(T));  // staged length (16-byte padded)
+  static constexpr int NDV = SDP / VW;       // 16-byte vectors of one stage
+  static_assert(KS == dstage_ks(P), "stage stride");
 };
 
 // scaled source copies c_a 2^|a| S~_a of a level
@@ -286,24 +289,28 @@ template <> __device__ inline float* level_L<float>(const LevelDev& lv) { return
 template <> __device__ inline double* level_L<double>(const LevelDev& lv) { return lv.L64; }
 
 // Source of column n for tap `code`: refined rank (>= 0), -2 - cell for a leaf
-// (monopole), or -1 when there is none.  Resolved two taps ahead.
-__device__ inline int tap_src(int code, int n, const int* __restrict__ sCB, const int32_t* __restrict__ rank1) {
+// (monopole), or -1 when there is none.  Resolved two taps ahead, in two
+// halves inside the tap loop: the level-(l-1) cell and the load of its rank
+// before the tap's MFMAs, the combination after them, so that the rank load
+// has the MFMA phase to land.
+__device__ inline int tap_cell(int code, int n, const int* __restrict__ sCB) {
   const int cb = sCB[n * 27 + (code & 31)];
-  if (cb < 0) return -1;
-  const int s = cb + ((code >> 5) & 7);
-  const int rs = rank1[s];
-  return rs >= 0 ? rs : -2 - s;
+  return cb < 0 ? -1 : cb + ((code >> 5) & 7);
+}
+__device__ inline int tap_code(int s, int rs) { return s < 0 ? -1 : (rs >= 0 ? rs : -2 - s); }
+__device__ inline int tap_src(int code, int n, const int* __restrict__ sCB, gptr<int32_t> rank1) {
+  const int s = tap_cell(code, n, sCB);
+  return tap_code(s, s < 0 ? -1 : rank1[s]);
 }
 
 // B fragments of one tap for lane (n = lane & 15, g = lane >> 4): the first NV
 // 16-byte vectors of the lane's run (vector j holds steps kb = VW j .. VW j + VW-1).
 template <typename T, int P, int NV>
-__device__ inline void load_bfrag(int sr, int lane, const double* __restrict__ mass1, const T* __restrict__ S1,
-                                  typename Vec16<T>::type* vb) {
+__device__ inline void load_bfrag(int sr, int lane, gptr<double> mass1, gptr<T> S1, typename Vec16<T>::type* vb) {
   using TS = TapStage<T, P>;
   using V = typename Vec16<T>::type;
   if (sr >= 0) {
-    const V* src = (const V*)(S1 + (size_t)sr * TS::ROW + (lane >> 4) * TS::STP);
+    gptr<V> src = (gptr<V>)(S1 + (size_t)sr * TS::ROW + (lane >> 4) * TS::STP);
 #pragma unroll
     for (int j = 0; j < NV; ++j) vb[j] = src[j];
   } else {
@@ -313,35 +320,29 @@ __device__ inline void load_bfrag(int sr, int lane, const double* __restrict__ m
   }
 }
 
+// D~ stage of tap `code` (rows already in the LDS layout): NTH threads copy
+// its NDV 16-byte vectors, thread t taking vectors t, t + NTH, ...
 template <typename T, int P, int NTH>
-__device__ inline void load_drows(int code, const T* __restrict__ Dil, T* vD) {
+__device__ inline void load_dstage(int code, const T* __restrict__ Dst, typename Vec16<T>::type* vD) {
   using TS = TapStage<T, P>;
-  constexpr int ND = (TS::SD + NTH - 1) / NTH;
+  using V = typename Vec16<T>::type;
+  constexpr int NJ = (TS::NDV + NTH - 1) / NTH;
   const int t = threadIdx.x;
-  const int di = code >> 8;
+  const V* src = (const V*)(Dst + (size_t)(code >> 8) * TS::SDP);
 #pragma unroll
-  for (int j = 0; j < ND; ++j) {
-    const int i = t + NTH * j;
-    T v = 0;
-    if (i < 8 * TS::KS) {
-      const int o = i / TS::KS;
-      const int g = i - o * TS::KS;
-      if (g < TS::K) v = Dil[((size_t)di * 8 + o) * TS::K + g];
-    }
-    vD[j] = v;
-  }
+  for (int j = 0; j < NJ; ++j)
+    if (TS::NDV % NTH == 0 || t + NTH * j < TS::NDV) vD[j] = src[t + NTH * j];
 }
 
 template <typename T, int P, int NTH>
-__device__ inline void store_drows(T* sD, const T* vD) {
+__device__ inline void store_dstage(T* sD, const typename Vec16<T>::type* vD) {
   using TS = TapStage<T, P>;
-  constexpr int ND = (TS::SD + NTH - 1) / NTH;
+  using V = typename Vec16<T>::type;
+  constexpr int NJ = (TS::NDV + NTH - 1) / NTH;
   const int t = threadIdx.x;
 #pragma unroll
-  for (int j = 0; j < ND; ++j) {
-    const int i = t + NTH * j;
-    if (i < TS::SD) sD[i] = vD[j];
-  }
+  for (int j = 0; j < NJ; ++j)
+    if (TS::NDV % NTH == 0 || t + NTH * j < TS::NDV) ((V*)sD)[t + NTH * j] = vD[j];
 }
 
 // Block-local setup: the tile record (level, then NC groups) and, per group,
@@ -356,10 +357,10 @@ __device__ inline void tile_setup(const int32_t* __restrict__ rec, int NC, const
     const int F = sF[n];
     int v = -1;
     if (F >= 0) {
-      const int G = lv1.refcell[F] >> 3;
-      const int Q = lv2.nbr[(size_t)G * 27 + e];
+      const int G = as_global(lv1.refcell)[F] >> 3;
+      const int Q = as_global(lv2.nbr)[(size_t)G * 27 + e];
       if (Q >= 0) {
-        const int rQ = lv2.rank[Q];
+        const int rQ = as_global(lv2.rank)[Q];
         if (rQ >= 0) v = 8 * rQ;
       }
     }
@@ -382,14 +383,14 @@ __device__ inline void tile_setup(const int32_t* __restrict__ rec, int NC, const
 template <typename T, int P>
 __global__ __launch_bounds__(64) void k_m2p(const int32_t* __restrict__ tiles, int ntiles, int nsplit,
                                             const int32_t* __restrict__ taps, const int16_t* __restrict__ aoff,
-                                            const LevelDev* __restrict__ lvs, const T* __restrict__ Dil) {
+                                            const LevelDev* __restrict__ lvs, const T* __restrict__ Dst) {
   using TS = TapStage<T, P>;
   using V = typename Vec16<T>::type;
   constexpr int K1 = nmi(P - 1);
   constexpr int ST0 = TS::KP / 4, ST1 = ((K1 + 3) & ~3) / 4;
   constexpr int NV = (ST0 + TS::VW - 1) / TS::VW;
-  constexpr int ND = (TS::SD + 63) / 64;
-  __shared__ T sD[2][TS::SD];
+  constexpr int ND = (TS::NDV + 63) / 64;
+  __shared__ __align__(16) T sD[2][TS::SDP];
   __shared__ int sF[16];
   __shared__ int sCB[16 * 27];
   __shared__ int sSrc[2][16];
@@ -404,26 +405,29 @@ __global__ __launch_bounds__(64) void k_m2p(const int32_t* __restrict__ tiles, i
   const int l = rec[0];
   const LevelDev lv1 = lvs[l - 1];
   const LevelDev lv2 = lvs[l - 2];
-  const int32_t* rank1 = lv1.rank;
-  const double* mass1 = lv1.mass;
-  const T* S1 = level_S<T>(lv1);
-  T* part = (T*)lv1.part + (size_t)chunk * lv1.nref * 32;
+  gptr<int32_t> rank1 = as_global(lv1.rank);
+  gptr<double> mass1 = as_global(lv1.mass);
+  gptr<T> S1 = as_global(level_S<T>(lv1));
+  gmut<T> part = as_global_mut((T*)lv1.part) + (size_t)chunk * lv1.nref * 32;
   if (lane < 16) sF[lane] = rec[1 + lane];
   __syncthreads();
+  gptr<int32_t> refcell1 = as_global(lv1.refcell);
+  gptr<int32_t> nbr2 = as_global(lv2.nbr);
+  gptr<int32_t> rank2 = as_global(lv2.rank);
   for (int i = lane; i < 16 * 27; i += 64) {
     const int c = i / 27, e = i - c * 27;
     const int F = sF[c];
     int v = -1;
     if (F >= 0) {
-      const int Q = lv2.nbr[(size_t)(lv1.refcell[F] >> 3) * 27 + e];
+      const int Q = nbr2[(size_t)(refcell1[F] >> 3) * 27 + e];
       if (Q >= 0) {
-        const int rQ = lv2.rank[Q];
+        const int rQ = rank2[Q];
         if (rQ >= 0) v = 8 * rQ;
       }
     }
     sCB[i] = v;
   }
-  const int oF = lv1.refcell[sF[0]] & 7;
+  const int oF = refcell1[sF[0]] & 7;
   for (int i = lane; i < kTaps; i += 64) sTap[i] = taps[oF * kTaps + i];
   int off0[ST0], off1[ST1];
 #pragma unroll
@@ -437,21 +441,24 @@ __global__ __launch_bounds__(64) void k_m2p(const int32_t* __restrict__ tiles, i
   }
   __syncthreads();
   V bA[NV], bB[NV];
-  T vD[ND];
+  V vD[ND];
   load_bfrag<T, P, NV>(sSrc[0][n], lane, mass1, S1, bA);
-  load_drows<T, P, 64>(sTap[tb], Dil, vD);
-  store_drows<T, P, 64>(sD[0], vD);
+  load_dstage<T, P, 64>(sTap[tb], Dst, vD);
+  store_dstage<T, P, 64>(sD[0], vD);
   __syncthreads();
   typename Acc4<T>::type acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
   // one tap: prefetch tap k+1 (B into bn, D rows into vD), MFMAs of tap k from bc / sD[k & 1]
   auto step = [&](int k, const V* bc, V* bn) {
     const int b = (k - tb) & 1;
+    int ncell = -1, nrank = -1;
+    if (k + 2 < te && lane < 16) {
+      ncell = tap_cell(sTap[k + 2], lane, sCB);
+      if (ncell >= 0) nrank = rank1[ncell];
+    }
     if (k + 1 < te) {
       load_bfrag<T, P, NV>(sSrc[b ^ 1][n], lane, mass1, S1, bn);
-      load_drows<T, P, 64>(sTap[k + 1], Dil, vD);
+      load_dstage<T, P, 64>(sTap[k + 1], Dst, vD);
     }
-    int nsrc = 0;
-    if (k + 2 < te && lane < 16) nsrc = tap_src(sTap[k + 2], lane, sCB, rank1);
     const T* D = sD[b];
 #pragma unroll
     for (int kb = 0; kb < ST0; ++kb) {
@@ -459,8 +466,8 @@ __global__ __launch_bounds__(64) void k_m2p(const int32_t* __restrict__ tiles, i
       acc0 = mfma16(D[off0[kb]], bv, acc0);
       if (kb < ST1) acc1 = mfma16(D[off1[kb]], bv, acc1);
     }
-    if (k + 1 < te) store_drows<T, P, 64>(sD[b ^ 1], vD);
-    if (k + 2 < te && lane < 16) sSrc[b][lane] = nsrc;
+    if (k + 1 < te) store_dstage<T, P, 64>(sD[b ^ 1], vD);
+    if (k + 2 < te && lane < 16) sSrc[b][lane] = tap_code(ncell, nrank);
     __syncthreads();
   };
   for (int k = tb; k < te; k += 2) {
@@ -469,7 +476,7 @@ __global__ __launch_bounds__(64) void k_m2p(const int32_t* __restrict__ tiles, i
   }
   const int F = sF[n];
   if (F >= 0) {
-    T* out = part + (size_t)F * 32;
+    gmut<T> out = part + (size_t)F * 32;
     const int krow = lane >> 4;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -537,8 +544,8 @@ struct M2LStage {
 };
 
 template <typename T, int P>
-__device__ inline void load_bshare(int sr, int lane, int w, const double* __restrict__ mass1,
-                                   const T* __restrict__ S1, typename Vec16<T>::type* vb) {
+__device__ inline void load_bshare(int sr, int lane, int w, gptr<double> mass1, gptr<T> S1,
+                                   typename Vec16<T>::type* vb) {
   using TS = TapStage<T, P>;
   using MS = M2LStage<T, P>;
   using V = typename Vec16<T>::type;
@@ -547,7 +554,7 @@ __device__ inline void load_bshare(int sr, int lane, int w, const double* __rest
     const int j = w * MS::NVW + i;
     V v = {};
     if (j < MS::NVB) {
-      if (sr >= 0) v = *(const V*)(S1 + (size_t)sr * TS::ROW + (lane >> 4) * TS::STP + j * TS::VW);
+      if (sr >= 0) v = *(gptr<V>)(S1 + (size_t)sr * TS::ROW + (lane >> 4) * TS::STP + j * TS::VW);
       else if (sr <= -2 && j == 0 && (lane >> 4) == 0) v[0] = (T)mass1[-2 - sr];
     }
     vb[i] = v;
@@ -574,9 +581,8 @@ __device__ inline void store_bshare(T* sB, int lane, int w, const typename Vec16
 template <typename T, int P, int H>
 __device__ inline void m2l_part(const int32_t* __restrict__ tp, int nt, const int16_t* __restrict__ aoff,
                                 const int* sF, const int* sCB, int (*sSrc)[16], T (*sB)[TapStage<T, P>::STP * 64],
-                                T (*sD)[TapStage<T, P>::SD], const int32_t* __restrict__ rank1,
-                                const double* __restrict__ mass1, const T* __restrict__ Dil,
-                                const T* __restrict__ S1, const int32_t* __restrict__ rank0, T* __restrict__ Lout) {
+                                T (*sD)[TapStage<T, P>::SDP], gptr<int32_t> rank1, gptr<double> mass1,
+                                const T* __restrict__ Dst, gptr<T> S1, gptr<int32_t> rank0, gmut<T> Lout) {
   using TS = TapStage<T, P>;
   using MS = M2LStage<T, P>;
   using V = typename Vec16<T>::type;
@@ -585,7 +591,7 @@ __device__ inline void m2l_part(const int32_t* __restrict__ tp, int nt, const in
   constexpr int NTH = PL.n[H];
   constexpr int NS = PL.steps[H];
   constexpr int KBH = PL.kbmax[H];
-  constexpr int ND = (TS::SD + kBlock - 1) / kBlock;
+  constexpr int ND = (TS::NDV + kBlock - 1) / kBlock;
   const int t = threadIdx.x, lane = t & 63, krow = lane >> 4;
   int off[NS > 0 ? NS : 1];
   {
@@ -598,16 +604,19 @@ __device__ inline void m2l_part(const int32_t* __restrict__ tp, int nt, const in
   typename Acc4<T>::type acc[NTH > 0 ? NTH : 1];
 #pragma unroll
   for (int i = 0; i < NTH; ++i) acc[i] = {0, 0, 0, 0};
-  T vD[ND];
+  V vD[ND];
   V vB[MS::NVW];
   for (int k = 0; k < nt; ++k) {
     const int b = k & 1;
+    int ncell = -1, nrank = -1;
+    if (k + 2 < nt && t < 16) {
+      ncell = tap_cell(tp[k + 2], t, sCB);
+      if (ncell >= 0) nrank = rank1[ncell];
+    }
     if (k + 1 < nt) {
-      load_drows<T, P, kBlock>(tp[k + 1], Dil, vD);
+      load_dstage<T, P, kBlock>(tp[k + 1], Dst, vD);
       load_bshare<T, P>(sSrc[b ^ 1][lane & 15], lane, H, mass1, S1, vB);
     }
-    int nsrc = 0;
-    if (k + 2 < nt && t < 16) nsrc = tap_src(tp[k + 2], t, sCB, rank1);
     const T* B = sB[b] + lane;
     const T* D = sD[b];
     T bv[KBH > 0 ? KBH : 1];
@@ -622,10 +631,10 @@ __device__ inline void m2l_part(const int32_t* __restrict__ tp, int nt, const in
         ++s;
       }
     if (k + 1 < nt) {
-      store_drows<T, P, kBlock>(sD[b ^ 1], vD);
+      store_dstage<T, P, kBlock>(sD[b ^ 1], vD);
       store_bshare<T, P>(sB[b ^ 1], lane, H, vB);
     }
-    if (k + 2 < nt && t < 16) sSrc[b][t] = nsrc;
+    if (k + 2 < nt && t < 16) sSrc[b][t] = tap_code(ncell, nrank);
     __syncthreads();
   }
   const int F = sF[lane & 15];
@@ -649,12 +658,12 @@ template <typename T, int P>
 __global__ __launch_bounds__(kBlock) void k_m2l_mfma(const int32_t* __restrict__ tiles, int ntiles, int nsplit,
                                                      const int32_t* __restrict__ taps,
                                                      const int16_t* __restrict__ aoff,
-                                                     const LevelDev* __restrict__ lvs, const T* __restrict__ Dil) {
+                                                     const LevelDev* __restrict__ lvs, const T* __restrict__ Dst) {
   using TS = TapStage<T, P>;
   using MS = M2LStage<T, P>;
-  constexpr int ND = (TS::SD + kBlock - 1) / kBlock;
+  constexpr int ND = (TS::NDV + kBlock - 1) / kBlock;
   __shared__ T sB[2][TS::STP * 64];
-  __shared__ T sD[2][TS::SD];
+  __shared__ __align__(16) T sD[2][TS::SDP];
   __shared__ int sF[16];
   __shared__ int sCB[16 * 27];
   __shared__ int sSrc[2][16];
@@ -669,31 +678,34 @@ __global__ __launch_bounds__(kBlock) void k_m2l_mfma(const int32_t* __restrict__
   const LevelDev lv0 = lvs[f];
   tile_setup(rec, 16, lvs[f - 2], lv1, sF, sCB);
   __syncthreads();
-  const int oF = lv1.refcell[sF[0]] & 7;
+  const int oF = as_global(lv1.refcell)[sF[0]] & 7;
   const int32_t* tp = taps + oF * kTaps + tb;
   const int nt = te - tb;
-  const T* S1 = level_S<T>(lv1);
+  gptr<T> S1 = as_global(level_S<T>(lv1));
+  gptr<int32_t> rank1 = as_global(lv1.rank);
+  gptr<double> mass1 = as_global(lv1.mass);
   if (t < 16) {
-    sSrc[0][t] = tap_src(tp[0], t, sCB, lv1.rank);
-    if (nt > 1) sSrc[1][t] = tap_src(tp[1], t, sCB, lv1.rank);
+    sSrc[0][t] = tap_src(tp[0], t, sCB, rank1);
+    if (nt > 1) sSrc[1][t] = tap_src(tp[1], t, sCB, rank1);
   }
   __syncthreads();
   {
-    T vD[ND];
+    typename Vec16<T>::type vD[ND];
     typename Vec16<T>::type vB[MS::NVW];
-    load_drows<T, P, kBlock>(tp[0], Dil, vD);
-    load_bshare<T, P>(sSrc[0][lane & 15], lane, w, lv1.mass, S1, vB);
-    store_drows<T, P, kBlock>(sD[0], vD);
+    load_dstage<T, P, kBlock>(tp[0], Dst, vD);
+    load_bshare<T, P>(sSrc[0][lane & 15], lane, w, mass1, S1, vB);
+    store_dstage<T, P, kBlock>(sD[0], vD);
     store_bshare<T, P>(sB[0], lane, w, vB);
   }
   __syncthreads();
-  T* Lout = nsplit > 1 ? (T*)lv0.Lpart + (size_t)chunk * lv0.nref * TS::K : level_L<T>(lv0);
+  gmut<T> Lout = as_global_mut(nsplit > 1 ? (T*)lv0.Lpart + (size_t)chunk * lv0.nref * TS::K : level_L<T>(lv0));
+  gptr<int32_t> rank0 = as_global(lv0.rank);
   // every wave runs the same number of barriers (one per tap)
   switch (w) {
-    case 0: m2l_part<T, P, 0>(tp, nt, aoff, sF, sCB, sSrc, sB, sD, lv1.rank, lv1.mass, Dil, S1, lv0.rank, Lout); break;
-    case 1: m2l_part<T, P, 1>(tp, nt, aoff, sF, sCB, sSrc, sB, sD, lv1.rank, lv1.mass, Dil, S1, lv0.rank, Lout); break;
-    case 2: m2l_part<T, P, 2>(tp, nt, aoff, sF, sCB, sSrc, sB, sD, lv1.rank, lv1.mass, Dil, S1, lv0.rank, Lout); break;
-    default: m2l_part<T, P, 3>(tp, nt, aoff, sF, sCB, sSrc, sB, sD, lv1.rank, lv1.mass, Dil, S1, lv0.rank, Lout); break;
+    case 0: m2l_part<T, P, 0>(tp, nt, aoff, sF, sCB, sSrc, sB, sD, rank1, mass1, Dst, S1, rank0, Lout); break;
+    case 1: m2l_part<T, P, 1>(tp, nt, aoff, sF, sCB, sSrc, sB, sD, rank1, mass1, Dst, S1, rank0, Lout); break;
+    case 2: m2l_part<T, P, 2>(tp, nt, aoff, sF, sCB, sSrc, sB, sD, rank1, mass1, Dst, S1, rank0, Lout); break;
+    default: m2l_part<T, P, 3>(tp, nt, aoff, sF, sCB, sSrc, sB, sD, rank1, mass1, Dst, S1, rank0, Lout); break;
   }
 }
 
@@ -861,8 +873,8 @@ hipError_t launch_m2p(int p, bool fp32, const MfmaTiles& mt, int t0, int n, int 
                       const LevelDev* lvs, const TablesDev<float>& t32, const TablesDev<double>& t64,
                       hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  if (fp32) return m2p_dispatch<float>(p, mt, t0, n, nsplit, tabs, lvs, t32.Dil, st);
-  return m2p_dispatch<double>(p, mt, t0, n, nsplit, tabs, lvs, t64.Dil, st);
+  if (fp32) return m2p_dispatch<float>(p, mt, t0, n, nsplit, tabs, lvs, t32.Dstage, st);
+  return m2p_dispatch<double>(p, mt, t0, n, nsplit, tabs, lvs, t64.Dstage, st);
 }
 
 int m2p_columns(int p, bool fp32) {
@@ -894,8 +906,8 @@ hipError_t launch_m2l_taps(int p, bool fp32, const MfmaTiles& mt, int t0, int n,
                            const LevelDev* lvs, const TablesDev<float>& t32, const TablesDev<double>& t64,
                            hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  if (fp32) return m2l_dispatch<float>(p, mt, t0, n, nsplit, tabs, lvs, t32.Dil, st);
-  return m2l_dispatch<double>(p, mt, t0, n, nsplit, tabs, lvs, t64.Dil, st);
+  if (fp32) return m2l_dispatch<float>(p, mt, t0, n, nsplit, tabs, lvs, t32.Dstage, st);
+  return m2l_dispatch<double>(p, mt, t0, n, nsplit, tabs, lvs, t64.Dstage, st);
 }
 
 template <typename T, typename TL>

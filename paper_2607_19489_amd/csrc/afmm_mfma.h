@@ -19,6 +19,16 @@ __device__ inline f64x4 mfma16(double a, double b, f64x4 c) { return __builtin_a
 template <typename T>
 __device__ inline int acc_row(int krow, int r) { return sizeof(T) == 4 ? 4 * krow + r : krow + 4 * r; }
 
+// Device pointers read out of tables in memory reach the compiler as generic
+// pointers, and loads through them become flat loads, which count against the
+// LDS wait counter as well: every wait for an LDS read would then also wait
+// for all global loads in flight (the next tap's prefetch).  Such pointers
+// always address global memory; the kernels load and store through these.
+template <typename T> using gptr = const __attribute__((address_space(1))) T*;
+template <typename T> using gmut = __attribute__((address_space(1))) T*;
+template <typename T> __device__ inline gptr<T> as_global(const T* p) { return (gptr<T>)p; }
+template <typename T> __device__ inline gmut<T> as_global_mut(T* p) { return (gmut<T>)p; }
+
 // 16-byte vectors
 template <typename T> struct Vec16;
 template <> struct Vec16<float> { typedef float type __attribute__((ext_vector_type(4))); };

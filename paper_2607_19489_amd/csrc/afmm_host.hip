@@ -41,6 +41,7 @@ struct Topology {
   int64_t nslots = 0;
   std::vector<int32_t> leafgrp[kMaxLevel];  // index l: refined ranks at l-1 with a leaf child
   std::vector<int32_t> m2lgrp[kMaxLevel];   // index f: refined ranks at f-1 with a refined child
+  std::vector<int32_t> nmgrp[kMaxLevel];    // index l: leafgrp entries with a refined level-l near candidate
   // per hierarchy
   std::vector<int32_t> levelmin, levelmax;
   std::vector<int64_t> slot_base, slot_count;
@@ -215,6 +216,20 @@ static void build_groups(Topology& T) {
       }
       if (leaf) lg.push_back(r);
       if (refd && l >= 3) mg.push_back(r);
+    }
+    // groups whose near candidates (children of the 27 neighbours of F)
+    // include a refined level-l cell: their near-field M2P runs apart
+    auto& nm = T.nmgrp[l];
+    nm.clear();
+    for (int32_t r : lg) {
+      bool any = false;
+      const int32_t* nb = &P.nbr[(size_t)r * 27];
+      for (int e = 0; e < 27 && !any; ++e) {
+        const int32_t q = nb[e];
+        if (q < 0 || P.rank[q] < 0) continue;
+        for (int op = 0; op < 8 && !any; ++op) any = C.rank[8 * P.rank[q] + op] >= 0;
+      }
+      if (any) nm.push_back(r);
     }
   }
 }
@@ -683,6 +698,8 @@ struct afmm_plan {
   LevelDev lv[kMaxLevel + 1];
   int32_t* d_leafgrp[kMaxLevel] = {};
   int32_t* d_m2lgrp[kMaxLevel] = {};
+  int32_t* d_nmgrp[kMaxLevel] = {};
+  void* d_nmp[kMaxLevel] = {};   // near-field M2P partials of level l (leaf-kernel precision)
   // MFMA tile records of every level, one array per precision (0 FP64, 1 FP32);
   // range[l] = {precision, first tile, count}
   MfmaTiles m2p_all[2], m2l_all[2];
@@ -1032,6 +1049,11 @@ static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
   for (int l = 0; l <= T.lmax; ++l) {
     if ((s = upload(P, T.leafgrp[l], &P->d_leafgrp[l], st))) return s;
     if ((s = upload(P, T.m2lgrp[l], &P->d_m2lgrp[l], st))) return s;
+    if ((s = upload(P, T.nmgrp[l], &P->d_nmgrp[l], st))) return s;
+    if (!T.nmgrp[l].empty()) {
+      const size_t es = (mixed && (l - 1) > f64) ? sizeof(float) : sizeof(double);
+      if ((s = dev_alloc(P, &P->d_nmp[l], (size_t)T.lv[l - 1].nref() * 32 * es))) return s;
+    }
   }
   HostTables& H = P->tabs;
   {
@@ -1351,9 +1373,16 @@ static afmm_status run_solve(afmm_plan* P, const double* msrc, int fmax, int lo,
     const double h = P->opt.boxlen / (double)(1LL << l);
     const bool fp32 = mixed && (l - 1) > f64;
     hipEvent_t a = prof_begin(P, st);
+    const int nm = (int)T.nmgrp[l].size();
+    if (nm > 0 && (s = dev_check(P,
+                                 launch_near_m2p(p, fp32, P->d_nmgrp[l], nm, P->lv[l - 1], P->lv[l], P->t32, P->t64,
+                                                 P->d_nmp[l], st),
+                                 "near m2p")))
+      return s;
     if ((s = dev_check(P,
                        launch_near(p, fp32, l, P->d_leafgrp[l], ng, P->lv[l - 1], P->lv[l], lvp, P->t32, P->t64, P->cm,
-                                   l >= 3 ? P->lv[l - 1].part : nullptr, P->opt.G, h, phi, acc, st),
+                                   l >= 3 ? P->lv[l - 1].part : nullptr, nm > 0 ? P->d_nmp[l] : nullptr, P->opt.G,
+                                   h, phi, acc, st),
                        "near")))
       return s;
     prof_end(P, a, st, fp32 ? kLeaf32 : kLeaf64, l);

@@ -187,7 +187,11 @@ hipError_t launch_m2p(int p, bool fp32, const MfmaTiles& mt, int t0, int n, int 
                       hipStream_t st);
 hipError_t launch_near(int p, bool fp32, int l, const int32_t* grp, int ngrp, const LevelDev& lv1,
                        const LevelDev& lv0, const LevelDev& lvp, const TablesDev<float>& t32,
-                       const TablesDev<double>& t64, const CommonDev& cm, const void* part, double G, double h,
-                       double* phi, double* acc, hipStream_t st);
+                       const TablesDev<double>& t64, const CommonDev& cm, const void* part, const void* nmp,
+                       double G, double h, double* phi, double* acc, hipStream_t st);
+// Near-field M2P from the refined level-l cells among the near candidates of
+// the groups `grp` (those that have any): partial [nref(l-1)][c * 8 + o].
+hipError_t launch_near_m2p(int p, bool fp32, const int32_t* grp, int ngrp, const LevelDev& lv1, const LevelDev& lv0,
+                           const TablesDev<float>& t32, const TablesDev<double>& t64, void* nmp, hipStream_t st);
 
 }  // namespace afmm

@@ -49,22 +49,44 @@ __device__ inline void p2p(T rx, T ry, T rz, T m, T* out) {
   out[3] -= w3 * rz;
 }
 
-// M2P of one multipole with a D~ row, for the near field (VALU).
+// Compile-time multi-index tables of order P: degree |a| and the position of
+// a + e_i (or -1 when |a| = P) for every degree-ordered position a.
+template <int P>
+struct MiTab {
+  int deg[nmi(P)];
+  int up[nmi(P)][3];
+  constexpr MiTab() : deg(), up() {
+    for (int n = 0; n <= P; ++n)
+      for (int a = n; a >= 0; --a)
+        for (int b = n - a; b >= 0; --b) {
+          const int c = n - a - b, g = mi_index(a, b, c);
+          deg[g] = n;
+          for (int i = 0; i < 3; ++i)
+            up[g][i] = n < P ? mi_index(a + (i == 0), b + (i == 1), c + (i == 2)) : -1;
+        }
+  }
+};
+
+// M2P of one multipole with a D~ row, for the near field (VALU): fully
+// unrolled over the coefficients, so every D~ and source index (and the
+// weight 2^-|a| of the same-level source copy) is a compile-time constant.
 template <typename T, int P>
-__device__ inline void m2p_row(const T* __restrict__ D, const T* __restrict__ S, const T* __restrict__ cf,
-                               const int16_t* __restrict__ up, T* out) {
+__device__ inline void m2p_row(const T* __restrict__ D, const T* __restrict__ S, T* out) {
   constexpr int K = nmi(P);
   constexpr int K1 = nmi(P - 1);
   constexpr int STP = src_stp(P, (int)sizeof(T));
+  constexpr MiTab<P> mt{};
   T phi = 0, ax = 0, ay = 0, az = 0;
+#pragma unroll
   for (int a = 0; a < K1; ++a) {
-    const T w = cf[a] * S[src_pos(a, STP)];
+    const T w = (T)(1.0 / (double)(1 << mt.deg[a])) * S[src_pos(a, STP)];
     phi += w * D[a];
-    ax += w * D[up[3 * a + 0]];
-    ay += w * D[up[3 * a + 1]];
-    az += w * D[up[3 * a + 2]];
+    ax += w * D[mt.up[a][0]];
+    ay += w * D[mt.up[a][1]];
+    az += w * D[mt.up[a][2]];
   }
-  for (int a = K1; a < K; ++a) phi += cf[a] * S[src_pos(a, STP)] * D[a];
+#pragma unroll
+  for (int a = K1; a < K; ++a) phi += (T)(1.0 / (double)(1 << mt.deg[a])) * S[src_pos(a, STP)] * D[a];
   out[0] += phi;
   out[1] -= ax;
   out[2] -= ay;
@@ -711,10 +733,11 @@ __global__ __launch_bounds__(kBlock) void k_m2l_mfma(const int32_t* __restrict__
 
 // ---------------------------------------------------------------------------
 // Leaf evaluation at level l, VALU part: far field (L2P of L[F]), near field
-// (P2P from level-(l-1) and level-l leaves, M2P from refined level-l cells not
-// touching the target) and nearest field (P2P from the children of refined
-// level-l cells touching the target), plus the MFMA intermediate-field partial;
-// the four fields are summed in FP64 and scaled to physical units.
+// (P2P from level-(l-1) and level-l leaves) and nearest field (P2P from the
+// children of refined level-l cells touching the target), plus the partials of
+// the MFMA intermediate field and of the near-field M2P from refined level-l
+// cells not touching the target (k_near_m2p, for the groups that have such
+// candidates); the fields are summed in FP64 and scaled to physical units.
 // The 8 targets of a group share their 216 candidate near cells (children of
 // F's 27 neighbours, or the neighbour itself when it is a leaf): they are
 // resolved once per block into LDS (kind, mass, refined rank), then thread
@@ -725,11 +748,12 @@ __global__ __launch_bounds__(kBlock) void k_m2l_mfma(const int32_t* __restrict__
 template <typename T, int P>
 __global__ __launch_bounds__(kBlock) void k_near(const int32_t* __restrict__ grp, LevelDev lv1, LevelDev lv0,
                                                  LevelDev lvp, TablesDev<T> tb, const T* __restrict__ Lpar,
-                                                 const T* __restrict__ S0, const T* __restrict__ part,
-                                                 CommonDev cm, double G, double h, double* __restrict__ phi,
+                                                 const T* __restrict__ part, const T* __restrict__ nmp,
+                                                 double G, double h, double* __restrict__ phi,
                                                  double* __restrict__ acc) {
   constexpr int K = nmi(P);
   enum { kNone = 0, kCoarse = 1, kLeaf = 2, kRefined = 3 };
+  __shared__ int s_hasref;
   __shared__ int s_kind[216];
   __shared__ int s_rn[216];
   __shared__ T s_m[216];
@@ -738,6 +762,8 @@ __global__ __launch_bounds__(kBlock) void k_near(const int32_t* __restrict__ grp
   const int F = grp[blockIdx.x];
   const int t = threadIdx.x;
   const int o = t & 7, j = t >> 3;
+  if (t == 0) s_hasref = 0;
+  __syncthreads();
   if (t < 216) {
     const int e = t >> 3, op = t & 7;
     const int q = lv1.nbr[(size_t)F * 27 + e];
@@ -759,6 +785,7 @@ __global__ __launch_bounds__(kBlock) void k_near(const int32_t* __restrict__ grp
           rn = n;
         } else {
           kind = kRefined;
+          s_hasref = 1;
         }
       }
     }
@@ -805,9 +832,6 @@ __global__ __launch_bounds__(kBlock) void k_near(const int32_t* __restrict__ grp
         p2p<T>((T)tx - ((T)o_axis(o2, 0) - (T)0.5) * (T)0.5, (T)ty - ((T)o_axis(o2, 1) - (T)0.5) * (T)0.5,
                (T)tz - ((T)o_axis(o2, 2) - (T)0.5) * (T)0.5, (T)lvp.mass[kc], nst);
       }
-    } else {
-      m2p_row<T, P>(tb.Dsame + (size_t)d_index(tx, ty, tz) * K, S0 + (size_t)rn * src_row(P, (int)sizeof(T)),
-                    tb.cfacn, cm.up, nea);
     }
   }
   T red[12];
@@ -839,6 +863,8 @@ __global__ __launch_bounds__(kBlock) void k_near(const int32_t* __restrict__ grp
         const T* pp = part + ((size_t)sp * lv1.nref + F) * 32;
         for (int c = 0; c < 4; ++c) out[c] += (double)pp[c * 8 + o];
       }
+    if (s_hasref)
+      for (int c = 0; c < 4; ++c) out[c] += (double)nmp[(size_t)F * 32 + c * 8 + o];
     const int sl = lv0.slot[cell];
     const double sp = G / h, sa = G / (h * h);
     phi[sl] = sp * out[0];
@@ -846,6 +872,66 @@ __global__ __launch_bounds__(kBlock) void k_near(const int32_t* __restrict__ grp
     acc[3 * (size_t)sl + 1] = sa * out[2];
     acc[3 * (size_t)sl + 2] = sa * out[3];
   }
+}
+
+// Near-field M2P from the refined level-l cells among the near candidates of
+// a group (the children of F's 27 neighbours that are refined and do not
+// touch the target): one wave per group, four groups per block.  The wave
+// compacts its refined candidates into LDS; lane (o = lane & 7, j = lane >> 3)
+// takes target o and every 8th candidate, partial sums are reduced by
+// shuffles and lanes 0..7 write nmp[F][c * 8 + o] (target-level units), read
+// by k_near.  Every child o is evaluated (refined ones are not read).
+template <typename T, int P>
+__global__ __launch_bounds__(kBlock) void k_near_m2p(const int32_t* __restrict__ grp, int ngrp, LevelDev lv1,
+                                                     LevelDev lv0, const T* __restrict__ Dsame,
+                                                     const T* __restrict__ S0, T* __restrict__ nmp) {
+  constexpr int K = nmi(P);
+  constexpr int NW = kBlock / 64;
+  __shared__ int s_c[NW][216];
+  __shared__ int s_rn[NW][216];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int gi = blockIdx.x * NW + w;
+  if (gi >= ngrp) return;
+  const int F = grp[gi];
+  int nlist = 0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int t = lane + 64 * r;
+    int rn = -1;
+    if (t < 216) {
+      const int q = lv1.nbr[(size_t)F * 27 + (t >> 3)];
+      if (q >= 0) {
+        const int rq = lv1.rank[q];
+        if (rq >= 0) rn = lv0.rank[8 * rq + (t & 7)];
+      }
+    }
+    const uint64_t m = __ballot(rn >= 0);
+    if (rn >= 0) {
+      const int pos = nlist + __popcll(m & ((1ull << lane) - 1ull));
+      s_c[w][pos] = t;
+      s_rn[w][pos] = rn;
+    }
+    nlist += __popcll(m);
+  }
+  wave_sync();
+  const int o = lane & 7, j = lane >> 3;
+  T sum[4] = {0, 0, 0, 0};
+  for (int i = j; i < nlist; i += 8) {
+    const int t = s_c[w][i], e = t >> 3, op = t & 7;
+    const int tx = o_axis(o, 0) - 2 * e_axis(e, 0) - o_axis(op, 0);
+    const int ty = o_axis(o, 1) - 2 * e_axis(e, 1) - o_axis(op, 1);
+    const int tz = o_axis(o, 2) - 2 * e_axis(e, 2) - o_axis(op, 2);
+    if (max(abs(tx), max(abs(ty), abs(tz))) <= 1) continue;
+    m2p_row<T, P>(Dsame + (size_t)d_index(tx, ty, tz) * K, S0 + (size_t)s_rn[w][i] * src_row(P, (int)sizeof(T)),
+                  sum);
+  }
+#pragma unroll
+  for (int d = 8; d <= 32; d <<= 1)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) sum[c] += __shfl_xor(sum[c], d, 64);
+  if (lane < 8)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) nmp[(size_t)F * 32 + c * 8 + o] = sum[c];
 }
 
 // ---------------------------------------------------------------------------
@@ -946,14 +1032,13 @@ hipError_t launch_l2l(int p, bool fp32, bool parent_fp32, bool has_parent, int n
 
 template <typename T>
 static hipError_t near_dispatch(int p, int ngrp, const int32_t* grp, const LevelDev& lv1, const LevelDev& lv0,
-                                const LevelDev& lvp, const TablesDev<T>& tb, const T* Lpar, const T* S0,
-                                const T* part, const CommonDev& cm, double G, double h, double* phi, double* acc,
-                                hipStream_t st) {
+                                const LevelDev& lvp, const TablesDev<T>& tb, const T* Lpar, const T* part,
+                                const T* nmp, double G, double h, double* phi, double* acc, hipStream_t st) {
   const dim3 grid(ngrp), block(kBlock);
   switch (p) {
 #define AFMM_NEAR(PP)                                                                                         \
   case PP:                                                                                                    \
-    hipLaunchKernelGGL((k_near<T, PP>), grid, block, 0, st, grp, lv1, lv0, lvp, tb, Lpar, S0, part, cm, G, h, \
+    hipLaunchKernelGGL((k_near<T, PP>), grid, block, 0, st, grp, lv1, lv0, lvp, tb, Lpar, part, nmp, G, h,   \
                        phi, acc);                                                                             \
     break;
     AFMM_NEAR(1) AFMM_NEAR(2) AFMM_NEAR(3) AFMM_NEAR(4) AFMM_NEAR(5) AFMM_NEAR(6) AFMM_NEAR(7) AFMM_NEAR(8)
@@ -965,15 +1050,39 @@ static hipError_t near_dispatch(int p, int ngrp, const int32_t* grp, const Level
 
 hipError_t launch_near(int p, bool fp32, int l, const int32_t* grp, int ngrp, const LevelDev& lv1,
                        const LevelDev& lv0, const LevelDev& lvp, const TablesDev<float>& t32,
-                       const TablesDev<double>& t64, const CommonDev& cm, const void* part, double G, double h,
-                       double* phi, double* acc, hipStream_t st) {
+                       const TablesDev<double>& t64, const CommonDev& cm, const void* part, const void* nmp,
+                       double G, double h, double* phi, double* acc, hipStream_t st) {
+  (void)cm;
   if (ngrp == 0) return hipSuccess;
   const bool has_far = (l - 1) >= 3;
   if (fp32)
-    return near_dispatch<float>(p, ngrp, grp, lv1, lv0, lvp, t32, has_far ? lv1.L32 : nullptr, lv0.S32,
-                                (const float*)part, cm, G, h, phi, acc, st);
-  return near_dispatch<double>(p, ngrp, grp, lv1, lv0, lvp, t64, has_far ? lv1.L64 : nullptr, lv0.Sc64,
-                               (const double*)part, cm, G, h, phi, acc, st);
+    return near_dispatch<float>(p, ngrp, grp, lv1, lv0, lvp, t32, has_far ? lv1.L32 : nullptr, (const float*)part,
+                                (const float*)nmp, G, h, phi, acc, st);
+  return near_dispatch<double>(p, ngrp, grp, lv1, lv0, lvp, t64, has_far ? lv1.L64 : nullptr, (const double*)part,
+                               (const double*)nmp, G, h, phi, acc, st);
+}
+
+template <typename T>
+static hipError_t near_m2p_dispatch(int p, const int32_t* grp, int ngrp, const LevelDev& lv1, const LevelDev& lv0,
+                                    const T* Dsame, const T* S0, T* nmp, hipStream_t st) {
+  const dim3 grid((ngrp + kBlock / 64 - 1) / (kBlock / 64)), block(kBlock);
+  switch (p) {
+#define AFMM_NM2P(PP)                                                                                          \
+  case PP:                                                                                                     \
+    hipLaunchKernelGGL((k_near_m2p<T, PP>), grid, block, 0, st, grp, ngrp, lv1, lv0, Dsame, S0, nmp);          \
+    break;
+    AFMM_NM2P(1) AFMM_NM2P(2) AFMM_NM2P(3) AFMM_NM2P(4) AFMM_NM2P(5) AFMM_NM2P(6) AFMM_NM2P(7) AFMM_NM2P(8)
+#undef AFMM_NM2P
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_near_m2p(int p, bool fp32, const int32_t* grp, int ngrp, const LevelDev& lv1, const LevelDev& lv0,
+                           const TablesDev<float>& t32, const TablesDev<double>& t64, void* nmp, hipStream_t st) {
+  if (ngrp == 0) return hipSuccess;
+  if (fp32) return near_m2p_dispatch<float>(p, grp, ngrp, lv1, lv0, t32.Dsame, lv0.S32, (float*)nmp, st);
+  return near_m2p_dispatch<double>(p, grp, ngrp, lv1, lv0, t64.Dsame, lv0.Sc64, (double*)nmp, st);
 }
 
 }  // namespace afmm

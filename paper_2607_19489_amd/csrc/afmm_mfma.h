@@ -29,6 +29,15 @@ template <typename T> using gmut = __attribute__((address_space(1))) T*;
 template <typename T> __device__ inline gptr<T> as_global(const T* p) { return (gptr<T>)p; }
 template <typename T> __device__ inline gmut<T> as_global_mut(T* p) { return (gmut<T>)p; }
 
+// Orders the LDS accesses of one wave: writes before the call are visible to
+// every lane of the same wave after it (no block barrier needed when each
+// wave only touches its own LDS slice).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // 16-byte vectors
 template <typename T> struct Vec16;
 template <> struct Vec16<float> { typedef float type __attribute__((ext_vector_type(4))); };

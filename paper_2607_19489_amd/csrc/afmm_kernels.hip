@@ -120,65 +120,91 @@ hipError_t launch_gather_mass(const LevelDev& lv, const double* m_src, hipStream
 // coefficient:  Y[k][q] = sum_o (prod_{i: q_i=1} sgn(o_i)) S_o[k].
 // The weights C(a,k) 4^-|a-k| 2^-|k| and signs are tabulated per coefficient a
 // (cm.m2m_list: for each a, its (k, parity) entries; cm.m2m_w the weights).
-// Thread = (cell, coefficient); a block holds CB cells and first stages the
-// 8 signed child sums Y of each in LDS.
+// Thread = (cell, coefficient) over chunks of CB cells; a block is persistent:
+// it stages the entry tables in LDS once, then for each chunk loads the
+// children's ranks and masses, forms the 8 signed child sums Y of each cell in
+// LDS and sums the entries of each coefficient.
 // The source copies are written in the lane-group layout; thread a >= K of a
 // cell writes the zero of padding slot src_pos(a).
 template <int P>
 __global__ __launch_bounds__(256) void k_upward(LevelDev lv, LevelDev lvc, CommonDev cm) {
   constexpr int K = nmi(P);
+  constexpr int NE = nmi_entries(P);
   constexpr int STP32 = src_stp(P, 4), STP64 = src_stp(P, 8);
   constexpr int KP = 4 * STP32;               // threads per cell (STP32 >= STP64)
-  constexpr int CB = 256 / KP;                // cells per block
+  constexpr int CB = 256 / KP;                // cells per chunk
   __shared__ double sY[CB][8][K];
+  __shared__ double sW[NE];
+  __shared__ int sE[NE];
+  __shared__ int sB[K + 1];
+  __shared__ int sRc[CB][8];
+  __shared__ double sM[CB][8];
   const int t = threadIdx.x;
+  for (int i = t; i < NE; i += 256) {
+    sW[i] = cm.m2m_w[i];
+    sE[i] = cm.m2m_list[i];
+  }
+  for (int i = t; i <= K; i += 256) sB[i] = cm.m2m_start[i];
   const int c = t / KP, a = t - c * KP;
-  const int r0 = blockIdx.x * CB;
-  // phase 1: 8 child values per (cell, coefficient) -> signed sums over the octant bits
-  for (int i = t; i < CB * K; i += 256) {
-    const int cc = i / K, k = i - cc * K;
-    const int r = r0 + cc;
-    if (r >= lv.nref) continue;
-    double v[8];
-#pragma unroll
-    for (int o = 0; o < 8; ++o) {
-      const int ch = 8 * r + o;
-      const int rc = lvc.rank[ch];
-      v[o] = rc >= 0 ? lvc.S64[(size_t)rc * K + k] : (k == 0 ? lvc.mass[ch] : 0.0);
+  for (int r0 = blockIdx.x * CB; r0 < lv.nref; r0 += gridDim.x * CB) {
+    // children of the chunk: refined rank, or the mass of a leaf child
+    if (t < CB * 8) {
+      const int r = r0 + (t >> 3);
+      int rc = -1;
+      double m = 0.0;
+      if (r < lv.nref) {
+        const int ch = 8 * r + (t & 7);
+        rc = lvc.rank[ch];
+        if (rc < 0) m = lvc.mass[ch];
+      }
+      sRc[t >> 3][t & 7] = rc;
+      sM[t >> 3][t & 7] = m;
     }
+    __syncthreads();
+    // 8 child values per (cell, coefficient) -> signed sums over the octant bits
+    for (int i = t; i < CB * K; i += 256) {
+      const int cc = i / K, k = i - cc * K;
+      double v[8];
 #pragma unroll
-    for (int bit = 0; bit < 3; ++bit) {
-      double u[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int qlo = q & ~(1 << bit);
-        u[q] = (q & (1 << bit)) ? v[qlo | (1 << bit)] - v[qlo] : v[qlo] + v[qlo | (1 << bit)];
+      for (int o = 0; o < 8; ++o) {
+        const int rc = sRc[cc][o];
+        v[o] = rc >= 0 ? lvc.S64[(size_t)rc * K + k] : (k == 0 ? sM[cc][o] : 0.0);
       }
 #pragma unroll
-      for (int q = 0; q < 8; ++q) v[q] = u[q];
-    }
+      for (int bit = 0; bit < 3; ++bit) {
+        double u[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) sY[cc][q][k] = v[q];
+        for (int q = 0; q < 8; ++q) {
+          const int qlo = q & ~(1 << bit);
+          u[q] = (q & (1 << bit)) ? v[qlo | (1 << bit)] - v[qlo] : v[qlo] + v[qlo | (1 << bit)];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = u[q];
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) sY[cc][q][k] = v[q];
+    }
+    __syncthreads();
+    const int r = r0 + c;
+    if (c < CB && r < lv.nref) {
+      if (a >= K) {  // zero padding of the source copies
+        if (lv.S32) lv.S32[(size_t)r * 4 * STP32 + src_pos(a, STP32)] = 0.f;
+        if (lv.Sc64 && a < 4 * STP64) lv.Sc64[(size_t)r * 4 * STP64 + src_pos(a, STP64)] = 0.0;
+      } else {
+        double acc = 0.0;
+        for (int j = sB[a]; j < sB[a + 1]; ++j) {
+          const int e = sE[j];
+          acc += sW[j] * sY[c][e >> 12][e & 4095];
+        }
+        lv.S64[(size_t)r * K + a] = acc;
+        // source copies for the translation kernels carry the factor (-1)^|a|/a! 2^|a|
+        const double sc = acc * cm.cfac2[a];
+        if (lv.S32) lv.S32[(size_t)r * 4 * STP32 + src_pos(a, STP32)] = (float)sc;
+        if (lv.Sc64) lv.Sc64[(size_t)r * 4 * STP64 + src_pos(a, STP64)] = sc;
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  const int r = r0 + c;
-  if (c >= CB || r >= lv.nref) return;
-  if (a >= K) {  // zero padding of the source copies
-    if (lv.S32) lv.S32[(size_t)r * 4 * STP32 + src_pos(a, STP32)] = 0.f;
-    if (lv.Sc64 && a < 4 * STP64) lv.Sc64[(size_t)r * 4 * STP64 + src_pos(a, STP64)] = 0.0;
-    return;
-  }
-  const int b0 = cm.m2m_start[a], b1 = cm.m2m_start[a + 1];
-  double acc = 0.0;
-  for (int j = b0; j < b1; ++j) {
-    const int e = cm.m2m_list[j];
-    acc += cm.m2m_w[j] * sY[c][e >> 12][e & 4095];
-  }
-  lv.S64[(size_t)r * K + a] = acc;
-  // source copies for the translation kernels carry the factor (-1)^|a|/a! 2^|a|
-  const double sc = acc * cm.cfac2[a];
-  if (lv.S32) lv.S32[(size_t)r * 4 * STP32 + src_pos(a, STP32)] = (float)sc;
-  if (lv.Sc64) lv.Sc64[(size_t)r * 4 * STP64 + src_pos(a, STP64)] = sc;
 }
 
 __global__ void k_batch_in(int64_t nleaf, const int32_t* __restrict__ leafslot, const int32_t* __restrict__ leafhier,
@@ -224,7 +250,8 @@ hipError_t launch_batch_out(int64_t nleaf, const int32_t* leafslot, const int32_
 hipError_t launch_upward(int p, const LevelDev& lv, const LevelDev& lvc, const CommonDev& cm, hipStream_t st) {
   if (lv.nref == 0) return hipSuccess;
   const int KP = src_row(p, 4), CB = 256 / KP;
-  const dim3 grid((lv.nref + CB - 1) / CB), block(kBlock);
+  // persistent blocks: a few per CU, each looping over chunks of CB cells
+  const dim3 grid(std::min((lv.nref + CB - 1) / CB, 8 * 256)), block(kBlock);
   switch (p) {
 #define AFMM_UP(PP) \
   case PP: hipLaunchKernelGGL(k_upward<PP>, grid, block, 0, st, lv, lvc, cm); break;

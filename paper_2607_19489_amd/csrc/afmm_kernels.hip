@@ -281,8 +281,10 @@ __global__ __launch_bounds__(kBlock) void k_l2l(const int32_t* __restrict__ grp,
   if (t < K && Lpar) sL[t] = (T)Lpar[(size_t)F * K + t];
   if (t < 8) sRy[t] = rank0[8 * F + t];
   __syncthreads();
+  // child o fastest: the lanes of a wave share few coefficients b, all of
+  // nearly the same degree, so their shift sums have nearly equal lengths
   for (int i = t; i < 8 * K; i += kBlock) {
-    const int o = i / K, b = i - o * K;
+    const int o = i & 7, b = i >> 3;
     const int ry = sRy[o];
     if (ry < 0) continue;
     const size_t at = (size_t)ry * K + b;

@@ -324,14 +324,14 @@ __global__ void k_adj_tbT(LevelDev lvs, LevelDev lvt, T* __restrict__ tbT) {
 }
 
 // Local-expansion bars of level f in T and in the lane-group layout of the
-// source copies (coefficient b at (b & 3) STP + (b >> 2), zero padded).
+// source copies (coefficient b at src_pos(b), zero padded).
 template <typename T, int P>
 __global__ void k_adj_lbarT(LevelDev lv, T* __restrict__ lT) {
   constexpr int K = nmi(P), STP = src_stp(P, (int)sizeof(T)), ROW = 4 * STP;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= lv.nref * ROW) return;
   const int r = i / ROW, b = i - r * ROW;   // b runs over coefficient indices 0 .. ROW-1
-  lT[(size_t)r * ROW + src_pos(b, STP)] = b < K ? (T)lv.lbar[(size_t)r * K + b] : (T)0;
+  lT[(size_t)r * ROW + src_pos(b, (int)sizeof(T))] = b < K ? (T)lv.lbar[(size_t)r * K + b] : (T)0;
 }
 
 // Per-block setup shared by both kernels: the 16 source cells, the child base
@@ -524,9 +524,9 @@ __global__ __launch_bounds__(64) void k_adj_m2l_mfma(const int32_t* __restrict__
   auto child = [&](int rF, int o) { return rF >= 0 ? lvt.rank[8 * rF + o] : -1; };
   auto loadB = [&](int ry, V* b) {
     if (ry >= 0) {
-      const V* src = (const V*)(lT + (size_t)ry * ROW + g * STP);
+      const T* src = lT + (size_t)ry * ROW;
 #pragma unroll
-      for (int j = 0; j < NVB; ++j) b[j] = src[j];
+      for (int j = 0; j < NVB; ++j) b[j] = *(const V*)(src + src_vec(j, g, (int)sizeof(T)));
     } else {
 #pragma unroll
       for (int j = 0; j < NVB; ++j) b[j] = V{};

@@ -40,14 +40,22 @@ __host__ __device__ constexpr int mi_index(int a, int b, int c) {
 
 // Layout of the scaled source copies (S32 / Sc64).  The MFMA kernels read the
 // B operand straight into registers: lane group g (lane >> 4) of a 16x16x4
-// step kb holds coefficient k = 4 kb + g, so coefficient k is stored at
-// (k & 3) * STP + (k >> 2) and each lane group loads one contiguous run of STP
-// values.  STP = ceil(K/4) rounded up to a 16-byte multiple; unused slots are 0.
+// step kb holds coefficient k = 4 kb + g.  A lane group needs STP steps
+// (STP = ceil(K/4) rounded up to whole 16-byte vectors of VW = 16/bytes
+// values); its vector j holds steps VW j .. VW j + VW - 1.  The row stores the
+// vectors j-major: vector j of lane group g at (4 j + g) VW, so one 16-byte
+// load per lane (vector j for all 4 lane groups of a source) reads 64
+// contiguous bytes of each source row.  Coefficient k therefore sits at
+// ((k >> 2) / VW) 4 VW + (k & 3) VW + (k >> 2) % VW; unused slots are 0.
 __host__ __device__ constexpr int src_stp(int p, int bytes) {
   return (((nmi(p) + 3) / 4) + (16 / bytes) - 1) / (16 / bytes) * (16 / bytes);
 }
 __host__ __device__ constexpr int src_row(int p, int bytes) { return 4 * src_stp(p, bytes); }
-__host__ __device__ constexpr int src_pos(int k, int stp) { return (k & 3) * stp + (k >> 2); }
+__host__ __device__ constexpr int src_pos(int k, int bytes) {
+  return ((k >> 2) / (16 / bytes)) * 4 * (16 / bytes) + (k & 3) * (16 / bytes) + (k >> 2) % (16 / bytes);
+}
+// element offset of vector j of lane group g in a source row
+__host__ __device__ constexpr int src_vec(int j, int g, int bytes) { return (4 * j + g) * (16 / bytes); }
 
 // D~ rows of one source offset in the layout the MFMA kernels stage in LDS:
 // row o (child octant) at o * dstage_ks(p), coefficients g < K then zeros up

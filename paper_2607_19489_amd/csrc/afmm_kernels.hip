@@ -79,14 +79,14 @@ __device__ inline void m2p_row(const T* __restrict__ D, const T* __restrict__ S,
   T phi = 0, ax = 0, ay = 0, az = 0;
 #pragma unroll
   for (int a = 0; a < K1; ++a) {
-    const T w = (T)(1.0 / (double)(1 << mt.deg[a])) * S[src_pos(a, STP)];
+    const T w = (T)(1.0 / (double)(1 << mt.deg[a])) * S[src_pos(a, (int)sizeof(T))];
     phi += w * D[a];
     ax += w * D[mt.up[a][0]];
     ay += w * D[mt.up[a][1]];
     az += w * D[mt.up[a][2]];
   }
 #pragma unroll
-  for (int a = K1; a < K; ++a) phi += (T)(1.0 / (double)(1 << mt.deg[a])) * S[src_pos(a, STP)] * D[a];
+  for (int a = K1; a < K; ++a) phi += (T)(1.0 / (double)(1 << mt.deg[a])) * S[src_pos(a, (int)sizeof(T))] * D[a];
   out[0] += phi;
   out[1] -= ax;
   out[2] -= ay;
@@ -188,8 +188,8 @@ __global__ __launch_bounds__(256) void k_upward(LevelDev lv, LevelDev lvc, Commo
     const int r = r0 + c;
     if (c < CB && r < lv.nref) {
       if (a >= K) {  // zero padding of the source copies
-        if (lv.S32) lv.S32[(size_t)r * 4 * STP32 + src_pos(a, STP32)] = 0.f;
-        if (lv.Sc64 && a < 4 * STP64) lv.Sc64[(size_t)r * 4 * STP64 + src_pos(a, STP64)] = 0.0;
+        if (lv.S32) lv.S32[(size_t)r * 4 * STP32 + src_pos(a, 4)] = 0.f;
+        if (lv.Sc64 && a < 4 * STP64) lv.Sc64[(size_t)r * 4 * STP64 + src_pos(a, 8)] = 0.0;
       } else {
         double acc = 0.0;
         for (int j = sB[a]; j < sB[a + 1]; ++j) {
@@ -199,8 +199,8 @@ __global__ __launch_bounds__(256) void k_upward(LevelDev lv, LevelDev lvc, Commo
         lv.S64[(size_t)r * K + a] = acc;
         // source copies for the translation kernels carry the factor (-1)^|a|/a! 2^|a|
         const double sc = acc * cm.cfac2[a];
-        if (lv.S32) lv.S32[(size_t)r * 4 * STP32 + src_pos(a, STP32)] = (float)sc;
-        if (lv.Sc64) lv.Sc64[(size_t)r * 4 * STP64 + src_pos(a, STP64)] = sc;
+        if (lv.S32) lv.S32[(size_t)r * 4 * STP32 + src_pos(a, 4)] = (float)sc;
+        if (lv.Sc64) lv.Sc64[(size_t)r * 4 * STP64 + src_pos(a, 8)] = sc;
       }
     }
     __syncthreads();
@@ -311,7 +311,8 @@ __global__ __launch_bounds__(kBlock) void k_l2l(const int32_t* __restrict__ grp,
 //   B[k][n] = c_k 2^|k| S~_k of the tap's source of group n (monopole for a
 //             leaf source, 0 when there is none) is loaded by lane (n, g)
 //             straight into registers: its STP coefficients k = 4 kb + g are
-//             one contiguous run of the source copy (lane-group layout);
+//             runs of the source copy (lane-group layout: 16-byte vector j of
+//             the 4 lane groups adjacent, so a load reads 64 B of each row);
 //   sD[o][g] = D~_g at the tap's child offset o (8 rows, then one zero slot)
 //             is staged in LDS while the MFMAs of the previous tap run.
 // A fragments are read from sD through per-lane offsets that do not depend on
@@ -361,9 +362,9 @@ __device__ inline void load_bfrag(int sr, int lane, gptr<double> mass1, gptr<T> 
   using TS = TapStage<T, P>;
   using V = typename Vec16<T>::type;
   if (sr >= 0) {
-    gptr<V> src = (gptr<V>)(S1 + (size_t)sr * TS::ROW + (lane >> 4) * TS::STP);
+    gptr<T> src = S1 + (size_t)sr * TS::ROW;
 #pragma unroll
-    for (int j = 0; j < NV; ++j) vb[j] = src[j];
+    for (int j = 0; j < NV; ++j) vb[j] = *(gptr<V>)(src + src_vec(j, lane >> 4, (int)sizeof(T)));
   } else {
 #pragma unroll
     for (int j = 0; j < NV; ++j) vb[j] = V{};
@@ -605,7 +606,7 @@ __device__ inline void load_bshare(int sr, int lane, int w, gptr<double> mass1, 
     const int j = w * MS::NVW + i;
     V v = {};
     if (j < MS::NVB) {
-      if (sr >= 0) v = *(gptr<V>)(S1 + (size_t)sr * TS::ROW + (lane >> 4) * TS::STP + j * TS::VW);
+      if (sr >= 0) v = *(gptr<V>)(S1 + (size_t)sr * TS::ROW + src_vec(j, lane >> 4, (int)sizeof(T)));
       else if (sr <= -2 && j == 0 && (lane >> 4) == 0) v[0] = (T)mass1[-2 - sr];
     }
     vb[i] = v;

@@ -703,6 +703,15 @@ struct afmm_plan {
   // MFMA tile records of every level, one array per precision (0 FP64, 1 FP32);
   // range[l] = {precision, first tile, count}
   MfmaTiles m2p_all[2], m2l_all[2];
+  // Level solves (ATS, Alg. 2): the M2L / L2L work restricted to the FMM cells
+  // that are ancestors of the leaves of target level l (per target level l)
+  struct AtsChain {
+    bool on = false;
+    MfmaTiles m2l_all[2];
+    int m2l_range[kMaxLevel][3] = {};
+    int32_t* d_grp[kMaxLevel] = {};
+    int ngrp[kMaxLevel] = {};
+  } ats[kMaxLevel];
   int m2p_range[kMaxLevel][3] = {};
   int m2l_range[kMaxLevel][3] = {};
   int m2l_split[2] = {1, 1};        // tap ranges per M2L tile, per precision
@@ -1180,6 +1189,48 @@ static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
       if ((s = upload(P, m2l_rec[pr], &d, st))) return s;
       P->m2l_all[pr] = {d, (int)(m2l_rec[pr].size() / 17), 16};
     }
+    // ATS chains: walking up from the groups of target level l, the needed
+    // cells of FMM level f are the refined ancestors of level-l leaves; the
+    // M2L group of f-1 is needed when one of its children is
+    for (int l = 4; l <= T.lmax; ++l) {
+      if (T.leafgrp[l].empty()) continue;
+      auto& A = P->ats[l];
+      std::vector<char> need(T.lv[l - 1].nref(), 0);
+      for (int32_t F : T.leafgrp[l]) need[F] = 1;
+      std::vector<int32_t> grp[kMaxLevel];
+      for (int f = l - 1; f >= 3; --f) {
+        std::vector<char> up(T.lv[f - 1].nref(), 0);
+        for (int32_t G : T.m2lgrp[f]) {
+          bool any = false;
+          for (int o = 0; o < 8 && !any; ++o) {
+            const int32_t rc = T.lv[f].rank[8 * G + o];
+            any = rc >= 0 && need[rc];
+          }
+          if (any) {
+            grp[f].push_back(G);
+            up[G] = 1;
+          }
+        }
+        need.swap(up);
+      }
+      std::vector<int32_t> rec[2];
+      for (int f = 3; f <= l - 1; ++f) {
+        const int pm = P->m2l_range[f][0];
+        const int m0 = (int)(rec[pm].size() / 17);
+        const int m = append_tiles(T, f, grp[f], 16, rec[pm]);
+        A.m2l_range[f][0] = pm;
+        A.m2l_range[f][1] = m0;
+        A.m2l_range[f][2] = m;
+        A.ngrp[f] = (int)grp[f].size();
+        if ((s = upload(P, grp[f], &A.d_grp[f], st))) return s;
+      }
+      for (int pr = 0; pr < 2; ++pr) {
+        int32_t* d = nullptr;
+        if ((s = upload(P, rec[pr], &d, st))) return s;
+        A.m2l_all[pr] = {d, (int)(rec[pr].size() / 17), 16};
+      }
+      A.on = true;
+    }
   }
   {
     std::vector<LevelDev> lvh(P->lv, P->lv + kMaxLevel + 1);
@@ -1308,35 +1359,41 @@ static afmm_status run_solve(afmm_plan* P, const double* msrc, int fmax, int lo,
   if (!serial && ((s = dev_check(P, hipEventRecord(P->ev_fork, st), "fork")) ||
                   (s = dev_check(P, hipStreamWaitEvent(sd, P->ev_fork, 0), "fork"))))
     return s;
-  // M2L tap sums of FMM levels 3..fmax: one launch per precision
+  // M2L tap sums of FMM levels 3..fmax: one launch per precision.  A solve of
+  // one target level takes its ATS chain (ancestors of the level's leaves only).
+  const afmm_plan::AtsChain* chain = (lo == hi && P->ats[lo].on) ? &P->ats[lo] : nullptr;
+  const MfmaTiles* m2l_all = chain ? chain->m2l_all : P->m2l_all;
+  const int(*m2l_range)[3] = chain ? chain->m2l_range : P->m2l_range;
   for (int pr = 0; pr < 2; ++pr) {
     int t0 = -1, n = 0;
     for (int f = 3; f <= fmax; ++f)
-      if (P->m2l_range[f][0] == pr && P->m2l_range[f][2] > 0) {
-        if (t0 < 0) t0 = P->m2l_range[f][1];
-        n = P->m2l_range[f][1] + P->m2l_range[f][2] - t0;
+      if (m2l_range[f][0] == pr && m2l_range[f][2] > 0) {
+        if (t0 < 0) t0 = m2l_range[f][1];
+        n = m2l_range[f][1] + m2l_range[f][2] - t0;
       }
     if (n <= 0) continue;
     hipEvent_t a = prof_begin(P, sd);
-    if ((s = dev_check(P, launch_m2l_taps(p, pr == 1, P->m2l_all[pr], t0, n, P->m2l_split[pr], P->mt, P->d_lvs,
+    if ((s = dev_check(P, launch_m2l_taps(p, pr == 1, m2l_all[pr], t0, n, P->m2l_split[pr], P->mt, P->d_lvs,
                                           P->t32, P->t64, sd),
                        "m2l")))
       return s;
     for (int f = 3; f <= fmax; ++f)
-      if (P->m2l_range[f][0] == pr) {
-        P->pending_flops += P->work.m2l_flops[f];
-        P->pending_bytes += P->work.m2l_bytes[f];
+      if (m2l_range[f][0] == pr && m2l_range[f][2] > 0) {
+        const double frac = chain ? (double)chain->ngrp[f] / (double)std::max<size_t>(T.m2lgrp[f].size(), 1) : 1.0;
+        P->pending_flops += frac * P->work.m2l_flops[f];
+        P->pending_bytes += frac * P->work.m2l_bytes[f];
       }
     prof_end(P, a, sd, pr ? kM2L32 : kM2L64, -1);
   }
   // completion of each FMM level: tap-range partials (if split) + ShiftLocal (L2L) of the father
   for (int f = 3; f <= fmax; ++f) {
-    const int ng = (int)T.m2lgrp[f].size();
+    const int ng = chain ? chain->ngrp[f] : (int)T.m2lgrp[f].size();
+    const int32_t* grp = chain ? chain->d_grp[f] : P->d_m2lgrp[f];
     const int ns = P->m2l_split[P->m2l_range[f][0]];
     if (ng == 0 || (f - 1 < 3 && ns == 1)) continue;
     hipEvent_t a = prof_begin(P, sd);
     if ((s = dev_check(P,
-                       launch_l2l(p, mixed && f > f64, mixed && (f - 1) > f64, f - 1 >= 3, ns, P->d_m2lgrp[f], ng,
+                       launch_l2l(p, mixed && f > f64, mixed && (f - 1) > f64, f - 1 >= 3, ns, grp, ng,
                                   P->lv[f - 1], P->lv[f], P->t32, P->t64, P->cm, sd),
                        "l2l")))
       return s;

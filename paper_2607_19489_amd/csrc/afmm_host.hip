@@ -727,6 +727,9 @@ struct afmm_plan {
   CommonDev cm;
   double* m_snap = nullptr;       // adaptive-time-step snapshot of leaf masses (slot space)
   bool snap_valid = false;
+  // the per-level masses and merged multipoles on the device were computed from
+  // the current snapshot m_snap (a solve that rebuilds no tree can skip them)
+  bool tree_fresh = false;
   bool solved = false;            // a solve has run (the adjoint transposes the last one)
   int last_level = AFMM_ALL_LEVELS;
   int last_fresh = 0;             // levels >= this took their masses from the last call's d_mass
@@ -1335,18 +1338,19 @@ static void prof_end(afmm_plan* P, hipEvent_t a, hipStream_t st, int kind, int l
 // Upward pass over every level, M2L over FMM levels 3..fmax, leaf evaluation
 // for the levels in [lo, hi].  Masses come from `msrc` (slot space).
 static afmm_status run_solve(afmm_plan* P, const double* msrc, int fmax, int lo, int hi, double* phi, double* acc,
-                             hipStream_t st) {
+                             hipStream_t st, bool keep_trees = false) {
   Topology& T = P->topo;
   const int p = P->opt.p;
   const bool mixed = P->opt.precision == AFMM_FP32_MIXED;
   const int f64 = mixed ? P->opt.fp64_levels : 1 << 20;
   afmm_status s;
-  for (int l = T.lmin_all; l <= T.lmax; ++l) {
+  // keep_trees: the level masses and multipoles on the device already belong to msrc
+  for (int l = T.lmin_all; l <= T.lmax && !keep_trees; ++l) {
     hipEvent_t a = prof_begin(P, st);
     if ((s = dev_check(P, launch_gather_mass(P->lv[l], msrc, st), "gather"))) return s;
     prof_end(P, a, st, kGather, l);
   }
-  for (int f = T.lmax - 1; f >= 2; --f) {
+  for (int f = T.lmax - 1; f >= 2 && !keep_trees; --f) {
     hipEvent_t a = prof_begin(P, st);
     if ((s = dev_check(P, launch_upward(p, P->lv[f], P->lv[f + 1], P->cm, st), "upward")))
       return s;
@@ -1476,7 +1480,10 @@ extern "C" afmm_status afmm_solve(afmm_plan* P, int32_t level, int32_t icount, c
     P->solved = true;
     P->last_level = AFMM_ALL_LEVELS;
     P->last_fresh = 0;
-    return run_solve(P, d_mass, T.lmax - 1, lmin, lmax, d_phi, d_acc, st);
+    P->tree_fresh = false;
+    afmm_status r = run_solve(P, d_mass, T.lmax - 1, lmin, lmax, d_phi, d_acc, st);
+    P->tree_fresh = r == AFMM_OK;
+    return r;
   }
   // Alg. 1: rebuild trees j >= level iff level == levelmin or icount > 1
   const bool rebuild = (level == lmin) || (icount > 1);
@@ -1494,7 +1501,13 @@ extern "C" afmm_status afmm_solve(afmm_plan* P, int32_t level, int32_t icount, c
   P->solved = true;
   P->last_level = level;
   P->last_fresh = rebuild ? level : T.lmax + 1;
-  return run_solve(P, P->m_snap, level - 1, level, level, d_phi, d_acc, st);
+  // Alg. 1 without a rebuild leaves every tree as it was: the snapshot, hence
+  // the level masses and merged multipoles of the previous solve, still hold
+  const bool keep = !rebuild && P->tree_fresh;
+  P->tree_fresh = false;
+  afmm_status r = run_solve(P, P->m_snap, level - 1, level, level, d_phi, d_acc, st, keep);
+  P->tree_fresh = r == AFMM_OK;
+  return r;
 }
 
 extern "C" afmm_status afmm_plan_set_profiling(afmm_plan* P, int32_t enable) {
@@ -1642,12 +1655,14 @@ extern "C" afmm_status afmm_plan_autotune(afmm_plan* P, const double* d_mass, do
   hipStream_t st = (hipStream_t)hip_stream;
   const int lmin = T.levelmin[0], lmax = T.levelmax[0];
   auto solve = [&]() { return run_solve(P, d_mass, T.lmax - 1, lmin, lmax, d_phi, d_acc, st); };
+  P->tree_fresh = false;  // the candidates' solves rebuild the trees from d_mass
   afmm_status s = autotune_core(P, solve, st, out);
   if (s) return s;
   // the autotune solves were synchronous full solves: they also rebuilt every tree
   if (hipMemcpyAsync(P->m_snap, d_mass, (size_t)T.nslots * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess)
     return dev_check(P, hipGetLastError(), "snapshot");
   P->snap_valid = true;
+  P->tree_fresh = true;
   P->solved = true;
   P->last_level = AFMM_ALL_LEVELS;
   P->last_fresh = 0;

@@ -191,35 +191,59 @@ __global__ __launch_bounds__(256) void k_adj_l2p(LevelDev lv1, LevelDev lv0, con
   }
 }
 
-// L2L^T (block = one refined cell F of level f-1): L_bar[F]_c += sum over the
-// refined children y of 2^(-1-|b|) u^(c-b)/(c-b)! L_bar[y]_b, b <= c; the
-// (b, c - b) pairs of each c and their 8 octant weights come from a host
-// table (cm.l2lT_*).
+// L2L^T over the M2L groups F of level f-1 (refined cells with a refined
+// child): L_bar[F]_c += sum over the refined children y_o of
+// 2^(-1-|b|) u_o^(c-b)/(c-b)! L_bar[y_o]_b, b <= c.  The child offsets u_o
+// have components +-1/4, so the weight of child o is that of child 7 times
+// (-1)^popcount(~o & q), q the parity of c - b: thread (group, b) first folds
+// the 8 children's bars into Z_q[b] = sum_o (-1)^popcount(~o & q) L_bar[y_o]_b
+// (a Walsh-Hadamard butterfly), then thread (group, c) sums the (b, c - b)
+// entries of c (cm.l2lT_*, one weight each) against Z.  GB groups per block.
 template <int P>
-__global__ __launch_bounds__(256) void k_adj_l2l(LevelDev lv1, LevelDev lv0, const double* __restrict__ l2lw,
-                                                 CommonDev cm) {
+__global__ __launch_bounds__(256) void k_adj_l2l(const int32_t* __restrict__ grp, int ngrp, LevelDev lv1,
+                                                 LevelDev lv0, CommonDev cm) {
   constexpr int K = nmi(P);
-  __shared__ double sL[8 * K];
-  __shared__ int sR[8];
-  const int F = blockIdx.x;
+  constexpr int GB = 256 / K;
+  __shared__ double sZ[GB][8][K];
+  __shared__ int sR[GB][8];
   const int t = threadIdx.x;
-  if (t < 8) sR[t] = lv0.rank[8 * F + t];
-  __syncthreads();
-  for (int i = t; i < 8 * K; i += 256) {
-    const int o = i / K, b = i - o * K;
-    sL[i] = sR[o] >= 0 ? lv0.lbar[(size_t)sR[o] * K + b] : 0.0;
+  for (int i = t; i < GB * 8; i += 256) {
+    const int gj = blockIdx.x * GB + (i >> 3);
+    sR[i >> 3][i & 7] = gj < ngrp ? lv0.rank[8 * grp[gj] + (i & 7)] : -1;
   }
   __syncthreads();
-  for (int c = t; c < K; c += 256) {
-    double acc = 0.0;
-    for (int j = cm.l2lT_start[c]; j < cm.l2lT_start[c + 1]; ++j) {
-      const int b = cm.l2lT_list[j] & 255;
-      const double* w8 = cm.l2lT_w + 8 * (size_t)j;
+  const int gl = t / K, b = t - gl * K;
+  const int gi = blockIdx.x * GB + gl;
+  const bool active = gl < GB && gi < ngrp;
+  if (active) {
+    // w[x] = bar of child 7 - x; after the butterfly w[q] = sum_x (-1)^popcount(x & q) w[x]
+    double w[8];
 #pragma unroll
-      for (int o = 0; o < 8; ++o) acc += w8[o] * sL[o * K + b];
+    for (int x = 0; x < 8; ++x) {
+      const int r = sR[gl][7 - x];
+      w[x] = r >= 0 ? lv0.lbar[(size_t)r * K + b] : 0.0;
     }
-    lv1.lbar[(size_t)F * K + c] += acc;
+#pragma unroll
+    for (int bit = 1; bit < 8; bit <<= 1)
+#pragma unroll
+      for (int x = 0; x < 8; ++x)
+        if (!(x & bit)) {
+          const double u = w[x], v = w[x | bit];
+          w[x] = u + v;
+          w[x | bit] = u - v;
+        }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sZ[gl][q][b] = w[q];
   }
+  __syncthreads();
+  if (!active) return;
+  const int c = b;
+  double acc = 0.0;
+  for (int j = cm.l2lT_start[c]; j < cm.l2lT_start[c + 1]; ++j) {
+    const int code = cm.l2lT_list[j];
+    acc += cm.l2lT_w[j] * sZ[gl][(code >> 24) & 7][code & 255];
+  }
+  lv1.lbar[(size_t)grp[gi] * K + c] += acc;
 }
 
 // M2M^T into the leaf children of the refined cells of level l-1: the
@@ -638,11 +662,15 @@ hipError_t launch_adj_l2p(int p, const LevelDev& lv1, const LevelDev& lv0, const
   return hipGetLastError();
 }
 
-hipError_t launch_adj_l2l(int p, const LevelDev& lv1, const LevelDev& lv0, const TablesDev<double>& t64,
-                          const CommonDev& cm, hipStream_t st) {
-  if (lv1.nref == 0) return hipSuccess;
-#define X(PP) \
-  case PP: hipLaunchKernelGGL((k_adj_l2l<PP>), dim3(lv1.nref), dim3(256), 0, st, lv1, lv0, t64.l2lw, cm); break;
+hipError_t launch_adj_l2l(int p, const int32_t* grp, int ngrp, const LevelDev& lv1, const LevelDev& lv0,
+                          const TablesDev<double>& t64, const CommonDev& cm, hipStream_t st) {
+  (void)t64;
+  if (ngrp == 0) return hipSuccess;
+  const int gb = 256 / nmi(p);
+#define X(PP)                                                                                                  \
+  case PP:                                                                                                     \
+    hipLaunchKernelGGL((k_adj_l2l<PP>), dim3((ngrp + gb - 1) / gb), dim3(256), 0, st, grp, ngrp, lv1, lv0, cm); \
+    break;
   AFMM_P_SWITCH(p, X)
 #undef X
   return hipGetLastError();

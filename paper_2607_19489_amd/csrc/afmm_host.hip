@@ -624,14 +624,17 @@ static void build_tables(int p, HostTables& H) {
     for (int b = 0; b < K; ++b) {
       const int g0 = H.mi[4 * c] - H.mi[4 * b], g1 = H.mi[4 * c + 1] - H.mi[4 * b + 1], g2 = H.mi[4 * c + 2] - H.mi[4 * b + 2];
       if (g0 < 0 || g1 < 0 || g2 < 0) continue;
-      H.l2lT_list.push_back(b | (mi_index(g0, g1, g2) << 8) | (H.mi[4 * b + 3] << 16));
+      H.l2lT_list.push_back(b | (mi_index(g0, g1, g2) << 8) | (H.mi[4 * b + 3] << 16) |
+                            (((g0 & 1) | (g1 & 1) << 1 | (g2 & 1) << 2) << 24));
     }
   }
   H.l2lT_start[K] = (int32_t)H.l2lT_list.size();
-  H.l2lT_w.assign(H.l2lT_list.size() * 8, 0.0);
+  // weight of child 7 (offset components all +1/4); child o differs by the sign
+  // (-1)^popcount(~o & parity(c - b)), applied to the children's bars on the device
+  H.l2lT_w.assign(H.l2lT_list.size(), 0.0);
   for (size_t j = 0; j < H.l2lT_list.size(); ++j) {
-    const int g = (H.l2lT_list[j] >> 8) & 255, nb = H.l2lT_list[j] >> 16;
-    for (int o = 0; o < 8; ++o) H.l2lT_w[8 * j + o] = H.l2lw[((size_t)o * (p + 1) + nb) * K + g];
+    const int g = (H.l2lT_list[j] >> 8) & 255, nb = (H.l2lT_list[j] >> 16) & 255;
+    H.l2lT_w[j] = H.l2lw[((size_t)7 * (p + 1) + nb) * K + g];
   }
   // adjoint: transposed M2P, rows a (tiles of 16), k = 8 g + kb -> (child o, quantity q)
   {
@@ -1863,7 +1866,11 @@ extern "C" afmm_status afmm_solve_adjoint(afmm_plan* P, int32_t level, const dou
   // 4. L2L^T, finest FMM level first
   ev = prof_begin(P, st);
   for (int f = fmax; f >= 4; --f)
-    if ((s = dev_check(P, launch_adj_l2l(p, P->lv[f - 1], P->lv[f], P->t64, P->cm, st), "adjoint l2l"))) return s;
+    if ((s = dev_check(P,
+                       launch_adj_l2l(p, P->d_m2lgrp[f], (int)T.m2lgrp[f].size(), P->lv[f - 1], P->lv[f], P->t64,
+                                      P->cm, st),
+                       "adjoint l2l")))
+      return s;
   prof_end(P, ev, st, kAdjTree, -1);
   // 5. M2L^T into the level f-1 sources
   ev = prof_begin(P, st);

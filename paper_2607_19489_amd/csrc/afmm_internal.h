@@ -125,8 +125,8 @@ struct CommonDev {
   const int16_t* adj_m2p_off = nullptr; // [RT * 8][64] A offsets of the transposed M2P
   const int16_t* adj_m2l_off = nullptr; // [steps][64] A offsets (within one D~ row) of the transposed M2L
   const int32_t* l2lT_start = nullptr;  // [K+1] transposed L2L pairs of each coefficient c
-  const int32_t* l2lT_list = nullptr;   // b | (c - b) << 8 | |b| << 16
-  const double* l2lT_w = nullptr;       // [entries][8] weights 2^(-1-|b|) u_o^(c-b)/(c-b)! per octant o
+  const int32_t* l2lT_list = nullptr;   // b | (c - b) << 8 | |b| << 16 | parity(c - b) << 24
+  const double* l2lT_w = nullptr;       // [entries] weight 2^(-1-|b|) u_7^(c-b)/(c-b)! of child 7 (u_7 = +1/4)
 };
 
 // Group tiles of the MFMA kernels: NC refined ranks per tile (one parity class,
@@ -174,8 +174,8 @@ hipError_t launch_adj_m2l_mfma(int p, bool fp32, const int32_t* tiles, int ntile
                                const int32_t* tapsT, const int16_t* aoff, const LevelDev& lvp, const LevelDev& lvs,
                                const LevelDev& lvt, const TablesDev<float>& t32, const TablesDev<double>& t64,
                                hipStream_t st);
-hipError_t launch_adj_l2l(int p, const LevelDev& lv1, const LevelDev& lv0, const TablesDev<double>& t64,
-                          const CommonDev& cm, hipStream_t st);
+hipError_t launch_adj_l2l(int p, const int32_t* grp, int ngrp, const LevelDev& lv1, const LevelDev& lv0,
+                          const TablesDev<double>& t64, const CommonDev& cm, hipStream_t st);
 hipError_t launch_adj_down(int p, const LevelDev& lv1, const LevelDev& lv0, int has_parent, const CommonDev& cm,
                            hipStream_t st);
 hipError_t launch_adj_out(int p, const LevelDev& lv1, const LevelDev& lv0, int has_parent, int rebuilt,

@@ -72,47 +72,64 @@ __global__ void k_adj_zero(size_t n, double* __restrict__ p) {
     p[i] = 0.0;
 }
 
-// P2P^T for the leaves s of level l (block = one refined cell F of level l-1,
-// s = its child o = t & 7; partial sums reduced by shuffles within a wave and
-// through LDS across waves).  Targets that read s through a P2P:
+// P2P^T for the leaves s of level l (block = one group F of level l-1 with a
+// leaf child; s = its child o = t & 7).  The 216 candidates (children of F's
+// 27 neighbours, or the neighbour itself when it is a leaf) are resolved once
+// into LDS; partial sums are reduced by shuffles within a wave and through LDS
+// across waves.  Targets that read s through a P2P:
 //   level l leaves n among the children of F's 27 neighbours (near field),
 //   level l+1 children of a refined level-l n touching s (s is in their near
 //     field as a coarse leaf),
 //   level l-1 leaves q touching F (s is in q's nearest field).
-__global__ __launch_bounds__(256) void k_adj_near_leaf(LevelDev lv1, LevelDev lv0, LevelDev lvp) {
-  __shared__ int s_nb[27];
+__global__ __launch_bounds__(256) void k_adj_near_leaf(const int32_t* __restrict__ grp, LevelDev lv1, LevelDev lv0,
+                                                       LevelDev lvp) {
+  enum { kNone = 0, kCoarse = 1, kLeaf = 2, kRefined = 3 };
+  __shared__ int s_kind[216];
+  __shared__ int s_idx[216];
   __shared__ double s_red[4][8];
-  const int F = blockIdx.x;
+  const int F = grp ? grp[blockIdx.x] : (int)blockIdx.x;
   const int t = threadIdx.x, o = t & 7, j = t >> 3;
-  if (t < 27) s_nb[t] = lv1.nbr[(size_t)F * 27 + t];
+  if (t < 216) {
+    const int e = t >> 3, op = t & 7;
+    const int q = lv1.nbr[(size_t)F * 27 + e];
+    int kind = kNone, idx = -1;
+    if (q >= 0) {
+      const int rq = lv1.rank[q];
+      if (rq < 0) {
+        if (op == 0) kind = kCoarse, idx = q;
+      } else {
+        const int n = 8 * rq + op;
+        const int rn = lv0.rank[n];
+        if (rn < 0) kind = kLeaf, idx = n;
+        else kind = kRefined, idx = rn;
+      }
+    }
+    s_kind[t] = kind;
+    s_idx[t] = idx;
+  }
   __syncthreads();
   const int s = 8 * F + o;
   double acc = 0.0;
   if (lv0.rank[s] < 0) {
     const int sx = ax_o(o, 0), sy = ax_o(o, 1), sz = ax_o(o, 2);
     for (int k = j; k < 216; k += 32) {
+      const int kind = s_kind[k];
+      if (kind == kNone) continue;
       const int e = k >> 3, op = k & 7;
-      const int q = s_nb[e];
-      if (q < 0) continue;
       const int ex = ax_e(e, 0), ey = ax_e(e, 1), ez = ax_e(e, 2);
-      const int rq = lv1.rank[q];
-      if (rq < 0) {
+      const int idx = s_idx[k];
+      if (kind == kCoarse) {
         // nearest field of the coarse leaf q = F + e: r = e - (o - 1/2)/2 in h_(l-1) units
-        if (op == 0)
-          acc += p2p_adj(ex - (sx - 0.5) * 0.5, ey - (sy - 0.5) * 0.5, ez - (sz - 0.5) * 0.5,
-                         lv1.tbar + 4 * (size_t)q);
+        acc += p2p_adj(ex - (sx - 0.5) * 0.5, ey - (sy - 0.5) * 0.5, ez - (sz - 0.5) * 0.5, lv1.tbar + 4 * (size_t)idx);
         continue;
       }
-      const int n = 8 * rq + op;
-      if (n == s) continue;
       const int tx = sx - 2 * ex - ax_o(op, 0), ty = sy - 2 * ey - ax_o(op, 1), tz = sz - 2 * ez - ax_o(op, 2);
-      const int rn = lv0.rank[n];
-      if (rn < 0) {
-        acc += p2p_adj(-tx, -ty, -tz, lv0.tbar + 4 * (size_t)n);
+      if (kind == kLeaf) {
+        if (idx != s) acc += p2p_adj(-tx, -ty, -tz, lv0.tbar + 4 * (size_t)idx);
       } else if (max(abs(tx), max(abs(ty), abs(tz))) <= 1) {
         for (int o2 = 0; o2 < 8; ++o2)
           acc += p2p_adj(ax_o(o2, 0) - 0.5 - 2.0 * tx, ax_o(o2, 1) - 0.5 - 2.0 * ty, ax_o(o2, 2) - 0.5 - 2.0 * tz,
-                         lvp.tbar + 4 * (size_t)(8 * rn + o2));
+                         lvp.tbar + 4 * (size_t)(8 * idx + o2));
       }
     }
   }
@@ -128,13 +145,14 @@ __global__ __launch_bounds__(256) void k_adj_near_leaf(LevelDev lv1, LevelDev lv
 // that do not touch s.  Source-copy bar of s += cfacn_a (D_a T_phi - sum_i
 // D_(a+e_i) T_i) with D = D~ at n - s.
 template <int P>
-__global__ __launch_bounds__(256) void k_adj_near_m2p(LevelDev lv1, LevelDev lv0, const double* __restrict__ Dsame,
+__global__ __launch_bounds__(256) void k_adj_near_m2p(const int32_t* __restrict__ grp, LevelDev lv1, LevelDev lv0,
+                                                      const double* __restrict__ Dsame,
                                                       const double* __restrict__ cfacn,
                                                       const int16_t* __restrict__ up) {
   constexpr int K = nmi(P), K1 = nmi(P - 1);
   __shared__ int s_cand[216];
   __shared__ int s_ref[8];
-  const int F = blockIdx.x;
+  const int F = grp ? grp[blockIdx.x] : (int)blockIdx.x;
   const int t = threadIdx.x;
   if (t < 8) s_ref[t] = lv0.rank[8 * F + t];
   if (t < 216) {
@@ -174,19 +192,34 @@ __global__ __launch_bounds__(256) void k_adj_near_m2p(LevelDev lv1, LevelDev lv0
   }
 }
 
-// L2P^T: the far field of the leaf children of F reads L~[F] (level l-1).
+// L2P^T: the far field of the leaf children of F (a group with a leaf child)
+// reads L~[F] (level l-1).  The child offsets have components +-1/4, so the
+// weight of child o for quantity q (phi, a_x, a_y, a_z) at coefficient b is
+// that of child 7 times (-1)^popcount(~o & pi), pi the parity of b (phi) or
+// of b - e_i (a_i): the 8 children's target bars are folded per quantity into
+// Y_q[pi] = sum_o (-1)^popcount(~o & pi) T_o[q] first.
 template <int P>
-__global__ __launch_bounds__(256) void k_adj_l2p(LevelDev lv1, LevelDev lv0, const double* __restrict__ l2p) {
+__global__ __launch_bounds__(256) void k_adj_l2p(const int32_t* __restrict__ grp, LevelDev lv1, LevelDev lv0,
+                                                 const double* __restrict__ l2p, const int8_t* __restrict__ mi) {
   constexpr int K = nmi(P);
   __shared__ double s_t[32];
-  const int F = blockIdx.x;
+  __shared__ double sY[4][8];
+  const int F = grp ? grp[blockIdx.x] : (int)blockIdx.x;
   const int t = threadIdx.x;
   if (t < 32) s_t[t] = lv0.tbar[4 * (size_t)(8 * F) + t];
   __syncthreads();
+  if (t < 32) {
+    const int q = t >> 3, pi = t & 7;
+    double y = 0.0;
+    for (int o = 0; o < 8; ++o) y += parity_sign(pi, o) * s_t[4 * o + q];
+    sY[q][pi] = y;
+  }
+  __syncthreads();
+  const double* w7 = l2p + (size_t)7 * 4 * K;
   for (int b = t; b < K; b += 256) {
-    double acc = 0.0;
-    for (int o = 0; o < 8; ++o)
-      for (int q = 0; q < 4; ++q) acc += l2p[((size_t)o * 4 + q) * K + b] * s_t[4 * o + q];
+    const int par = (mi[4 * b] & 1) | (mi[4 * b + 1] & 1) << 1 | (mi[4 * b + 2] & 1) << 2;
+    double acc = w7[b] * sY[0][par];
+    for (int i = 0; i < 3; ++i) acc += w7[(size_t)(1 + i) * K + b] * sY[1 + i][par ^ (1 << i)];
     lv1.lbar[(size_t)F * K + b] += acc;
   }
 }
@@ -427,10 +460,11 @@ __global__ __launch_bounds__(64) void k_adj_m2p_mfma(const int32_t* __restrict__
                                                      double* __restrict__ part, const int32_t* __restrict__ tapsT,
                                                      const int16_t* __restrict__ aoff, LevelDev lvp, LevelDev lvs,
                                                      const T* __restrict__ tbT, const T* __restrict__ Dil) {
-  constexpr int K = nmi(P), KS = ((K + 3) & ~3) + 1, SD = 8 * KS + 1, RT = (K + 15) / 16;
-  constexpr int VW = 16 / (int)sizeof(T), NVB = 8 / VW, ND = (SD + 63) / 64;
+  constexpr int K = nmi(P), RT = (K + 15) / 16;
+  constexpr int SDP = dstage_len(P, (int)sizeof(T));
+  constexpr int VW = 16 / (int)sizeof(T), NVB = 8 / VW, ND = (SDP / VW + 63) / 64;
   using V = typename Vec16<T>::type;
-  __shared__ T sD[2][SD];
+  __shared__ __align__(16) T sD[2][SDP];
   __shared__ int sS[16];
   __shared__ int sCB[16 * 27];
   __shared__ int sTap[kTapsT];
@@ -460,18 +494,18 @@ __global__ __launch_bounds__(64) void k_adj_m2p_mfma(const int32_t* __restrict__
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt) acc[rt] = {0, 0, 0, 0};
   V bA[NVB], bB[NVB];
-  T vD[ND];
+  V vD[ND];
   int gn = adj_group(sTap[tb], n, sCB, lvs.rank);
   loadB(gn, bA);
-  load_drows_t<T, K, KS, 64>(sTap[tb] >> 8, Dil, vD);
-  store_drows_t<T, K, KS, 64>(sD[0], vD);
+  load_dstage_t<T, SDP, 64>(sTap[tb] >> 8, Dil, vD);
+  store_dstage_t<T, SDP, 64>(sD[0], vD);
   if (tb + 1 < te) gn = adj_group(sTap[tb + 1], n, sCB, lvs.rank);
   __syncthreads();
   auto step = [&](int k, const V* bc, V* bn) {
     const int b = (k - tb) & 1;
     if (k + 1 < te) {
       loadB(gn, bn);
-      load_drows_t<T, K, KS, 64>(sTap[k + 1] >> 8, Dil, vD);
+      load_dstage_t<T, SDP, 64>(sTap[k + 1] >> 8, Dil, vD);
     }
     if (k + 2 < te) gn = adj_group(sTap[k + 2], n, sCB, lvs.rank);
     const T* D = sD[b];
@@ -479,7 +513,7 @@ __global__ __launch_bounds__(64) void k_adj_m2p_mfma(const int32_t* __restrict__
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
       for (int kb = 0; kb < 8; ++kb) acc[rt] = mfma16(D[off[rt][kb]], bc[kb / VW][kb % VW], acc[rt]);
-    if (k + 1 < te) store_drows_t<T, K, KS, 64>(sD[b ^ 1], vD);
+    if (k + 1 < te) store_dstage_t<T, SDP, 64>(sD[b ^ 1], vD);
     __syncthreads();
   };
   for (int k = tb; k < te; k += 2) {
@@ -524,13 +558,13 @@ __global__ __launch_bounds__(64) void k_adj_m2l_mfma(const int32_t* __restrict__
                                                      const int16_t* __restrict__ aoff, LevelDev lvp, LevelDev lvs,
                                                      LevelDev lvt, const T* __restrict__ lT,
                                                      const T* __restrict__ Dil) {
-  constexpr int K = nmi(P), KS = ((K + 3) & ~3) + 1, SD = 8 * KS + 1;
+  constexpr int K = nmi(P), KS = dstage_ks(P), SDP = dstage_len(P, (int)sizeof(T));
   constexpr AdjM2LPlan<P> PL = make_adj_m2l_plan<P>();
   constexpr int RT = AdjM2LPlan<P>::RT;
   constexpr int VW = 16 / (int)sizeof(T), STP = src_stp(P, (int)sizeof(T)), ROW = 4 * STP;
-  constexpr int NVB = (PL.kbmax + VW - 1) / VW, ND = (SD + 63) / 64;
+  constexpr int NVB = (PL.kbmax + VW - 1) / VW, ND = (SDP / VW + 63) / 64;
   using V = typename Vec16<T>::type;
-  __shared__ T sD[2][SD];
+  __shared__ __align__(16) T sD[2][SDP];
   __shared__ int sS[16];
   __shared__ int sCB[16 * 27];
   __shared__ int sTap[kTapsT];
@@ -560,12 +594,12 @@ __global__ __launch_bounds__(64) void k_adj_m2l_mfma(const int32_t* __restrict__
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt) acc[rt] = {0, 0, 0, 0};
   V bA[NVB], bB[NVB];
-  T vD[ND];
+  V vD[ND];
   int gcur = adj_group(sTap[tb], n, sCB, lvs.rank);
   int gnext = tb + 1 < te ? adj_group(sTap[tb + 1], n, sCB, lvs.rank) : -1;
   loadB(child(gcur, 0), bA);
-  load_drows_t<T, K, KS, 64>(sTap[tb] >> 8, Dil, vD);
-  store_drows_t<T, K, KS, 64>(sD[0], vD);
+  load_dstage_t<T, SDP, 64>(sTap[tb] >> 8, Dil, vD);
+  store_dstage_t<T, SDP, 64>(sD[0], vD);
   __syncthreads();
   // sub-step (tap k, octant o): B of (k, o) in bc; prefetch (k, o+1) or (k+1, 0) into bn
   auto sub = [&](int k, int o, const V* bc, V* bn) {
@@ -581,13 +615,13 @@ __global__ __launch_bounds__(64) void k_adj_m2l_mfma(const int32_t* __restrict__
   };
   for (int k = tb; k < te; ++k) {
     const int b = (k - tb) & 1;
-    if (k + 1 < te) load_drows_t<T, K, KS, 64>(sTap[k + 1] >> 8, Dil, vD);
+    if (k + 1 < te) load_dstage_t<T, SDP, 64>(sTap[k + 1] >> 8, Dil, vD);
 #pragma unroll
     for (int o = 0; o < 8; o += 2) {
       sub(k, o, bA, bB);
       sub(k, o + 1, bB, bA);
     }
-    if (k + 1 < te) store_drows_t<T, K, KS, 64>(sD[b ^ 1], vD);
+    if (k + 1 < te) store_dstage_t<T, SDP, 64>(sD[b ^ 1], vD);
     gcur = gnext;
     if (k + 2 < te) gnext = adj_group(sTap[k + 2], n, sCB, lvs.rank);
     __syncthreads();
@@ -640,23 +674,29 @@ hipError_t launch_adj_zero(double* p, size_t n, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_adj_near(int p, const LevelDev& lv1, const LevelDev& lv0, const LevelDev& lvp, int targets_here,
+hipError_t launch_adj_near(int p, const int32_t* leafgrp, int nleafgrp, const int32_t* refgrp, int nrefgrp,
+                           const LevelDev& lv1, const LevelDev& lv0, const LevelDev& lvp, int targets_here,
                            const TablesDev<double>& t64, const CommonDev& cm, hipStream_t st) {
   if (lv1.nref == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_adj_near_leaf, dim3(lv1.nref), dim3(256), 0, st, lv1, lv0, lvp);
-  if (!targets_here || !lv0.sbar) return hipGetLastError();
-#define X(PP) \
-  case PP: hipLaunchKernelGGL((k_adj_near_m2p<PP>), dim3(lv1.nref), dim3(256), 0, st, lv1, lv0, t64.Dsame, t64.cfacn, cm.up); break;
+  if (nleafgrp > 0) hipLaunchKernelGGL(k_adj_near_leaf, dim3(nleafgrp), dim3(256), 0, st, leafgrp, lv1, lv0, lvp);
+  if (!targets_here || !lv0.sbar || nrefgrp == 0) return hipGetLastError();
+  // refgrp == nullptr: every refined cell of level l-1
+  const int nb = refgrp ? nrefgrp : lv1.nref;
+#define X(PP)                                                                                                  \
+  case PP:                                                                                                     \
+    hipLaunchKernelGGL((k_adj_near_m2p<PP>), dim3(nb), dim3(256), 0, st, refgrp, lv1, lv0, t64.Dsame, t64.cfacn, \
+                       cm.up);                                                                                 \
+    break;
   AFMM_P_SWITCH(p, X)
 #undef X
   return hipGetLastError();
 }
 
-hipError_t launch_adj_l2p(int p, const LevelDev& lv1, const LevelDev& lv0, const TablesDev<double>& t64,
-                          hipStream_t st) {
-  if (lv1.nref == 0) return hipSuccess;
-#define X(PP) \
-  case PP: hipLaunchKernelGGL((k_adj_l2p<PP>), dim3(lv1.nref), dim3(256), 0, st, lv1, lv0, t64.l2p); break;
+hipError_t launch_adj_l2p(int p, const int32_t* grp, int ngrp, const LevelDev& lv1, const LevelDev& lv0,
+                          const TablesDev<double>& t64, const CommonDev& cm, hipStream_t st) {
+  if (ngrp == 0) return hipSuccess;
+#define X(PP)                                                                                                         \
+  case PP: hipLaunchKernelGGL((k_adj_l2p<PP>), dim3(ngrp), dim3(256), 0, st, grp, lv1, lv0, t64.l2p, cm.mi); break;
   AFMM_P_SWITCH(p, X)
 #undef X
   return hipGetLastError();
@@ -738,8 +778,8 @@ hipError_t launch_adj_m2p_mfma(int p, bool fp32, const int32_t* tiles, int ntile
                                const LevelDev& lvt, const TablesDev<float>& t32, const TablesDev<double>& t64,
                                hipStream_t st) {
   if (ntiles <= 0 || lvs.nref == 0) return hipSuccess;
-  if (fp32) return adj_m2p_t<float>(p, tiles, ntiles, nsplit, part, tapsT, aoff, lvp, lvs, lvt, t32.Dil, st);
-  return adj_m2p_t<double>(p, tiles, ntiles, nsplit, part, tapsT, aoff, lvp, lvs, lvt, t64.Dil, st);
+  if (fp32) return adj_m2p_t<float>(p, tiles, ntiles, nsplit, part, tapsT, aoff, lvp, lvs, lvt, t32.Dstage, st);
+  return adj_m2p_t<double>(p, tiles, ntiles, nsplit, part, tapsT, aoff, lvp, lvs, lvt, t64.Dstage, st);
 }
 
 template <typename T>
@@ -766,8 +806,8 @@ hipError_t launch_adj_m2l_mfma(int p, bool fp32, const int32_t* tiles, int ntile
                                const LevelDev& lvt, const TablesDev<float>& t32, const TablesDev<double>& t64,
                                hipStream_t st) {
   if (ntiles <= 0 || lvt.nref == 0) return hipSuccess;
-  if (fp32) return adj_m2l_t<float>(p, tiles, ntiles, nsplit, part, tapsT, aoff, lvp, lvs, lvt, t32.Dil, st);
-  return adj_m2l_t<double>(p, tiles, ntiles, nsplit, part, tapsT, aoff, lvp, lvs, lvt, t64.Dil, st);
+  if (fp32) return adj_m2l_t<float>(p, tiles, ntiles, nsplit, part, tapsT, aoff, lvp, lvs, lvt, t32.Dstage, st);
+  return adj_m2l_t<double>(p, tiles, ntiles, nsplit, part, tapsT, aoff, lvp, lvs, lvt, t64.Dstage, st);
 }
 
 #undef AFMM_P_SWITCH

@@ -1841,10 +1841,18 @@ extern "C" afmm_status afmm_solve_adjoint(afmm_plan* P, int32_t level, const dou
   for (int l = std::max(1, lo - 1); l <= std::min(lmax, hi + 1); ++l) {
     const LevelDev& lvp = l + 1 <= lmax ? P->lv[l + 1] : empty;
     const bool tgt = l >= lo && l <= hi;
-    if ((s = dev_check(P, launch_adj_near(p, P->lv[l - 1], P->lv[l], lvp, tgt, P->t64, P->cm, st), "adjoint near")))
+    // P2P^T over the groups with a leaf child; near M2P^T over the groups with a
+    // refined child (the M2L group list from level 3 on, every refined cell below)
+    const int nlg = (int)T.leafgrp[l].size();
+    const int nrg = l >= 3 ? (int)T.m2lgrp[l].size() : P->lv[l - 1].nref;
+    if ((s = dev_check(P,
+                       launch_adj_near(p, P->d_leafgrp[l], nlg, l >= 3 ? P->d_m2lgrp[l] : nullptr, nrg, P->lv[l - 1],
+                                       P->lv[l], lvp, tgt, P->t64, P->cm, st),
+                       "adjoint near")))
       return s;
     if (tgt && l - 1 >= 3 && P->lv[l - 1].lbar &&
-        (s = dev_check(P, launch_adj_l2p(p, P->lv[l - 1], P->lv[l], P->t64, st), "adjoint l2p")))
+        (s = dev_check(P, launch_adj_l2p(p, P->d_leafgrp[l], nlg, P->lv[l - 1], P->lv[l], P->t64, P->cm, st),
+                       "adjoint l2p")))
       return s;
   }
   prof_end(P, ev, st, kAdjNear, -1);

@@ -159,10 +159,11 @@ hipError_t launch_batch_out(int64_t nleaf, const int32_t* leafslot, const int32_
 hipError_t launch_adj_init(const LevelDev& lv, int target, const double* phib, const double* accb, double sp,
                            double sa, hipStream_t st);
 hipError_t launch_adj_zero(double* p, size_t n, hipStream_t st);
-hipError_t launch_adj_near(int p, const LevelDev& lv1, const LevelDev& lv0, const LevelDev& lvp, int targets_here,
+hipError_t launch_adj_near(int p, const int32_t* leafgrp, int nleafgrp, const int32_t* refgrp, int nrefgrp,
+                           const LevelDev& lv1, const LevelDev& lv0, const LevelDev& lvp, int targets_here,
                            const TablesDev<double>& t64, const CommonDev& cm, hipStream_t st);
-hipError_t launch_adj_l2p(int p, const LevelDev& lv1, const LevelDev& lv0, const TablesDev<double>& t64,
-                          hipStream_t st);
+hipError_t launch_adj_l2p(int p, const int32_t* grp, int ngrp, const LevelDev& lv1, const LevelDev& lv0,
+                          const TablesDev<double>& t64, const CommonDev& cm, hipStream_t st);
 // MFMA forms: tiles of 16 source cells (records: target level, 16 cells); with
 // nsplit > 1 the 189 taps of a tile are split over blocks writing partial sets
 // into `part` ([nsplit][ntiles * 16][K] FP64), summed in order afterwards.

@@ -52,35 +52,28 @@ __device__ inline int xcd_tile(int ntiles) {
 }
 
 // D~ rows of one source offset staged in LDS: sD[o * KS + g] = D~_g at child
-// offset o (g < K; zeros up to KS), then one zero slot at 8 KS.  NTH threads.
-template <typename T, int K, int KS, int NTH>
-__device__ inline void load_drows_t(int di, const T* __restrict__ Dil, T* vD) {
-  constexpr int SD = 8 * KS + 1;
-  constexpr int ND = (SD + NTH - 1) / NTH;
+// offset o (g < K; zeros up to KS), then one zero slot at 8 KS, copied from
+// rows already in that layout and padded to whole 16-byte vectors (SDP values
+// per offset): NTH threads, thread t takes vectors t, t + NTH, ...
+template <typename T, int SDP, int NTH>
+__device__ inline void load_dstage_t(int di, const T* __restrict__ Dst, typename Vec16<T>::type* vD) {
+  using V = typename Vec16<T>::type;
+  constexpr int NV = SDP / (16 / (int)sizeof(T)), NJ = (NV + NTH - 1) / NTH;
+  const V* src = (const V*)(Dst + (size_t)di * SDP);
   const int t = threadIdx.x;
 #pragma unroll
-  for (int j = 0; j < ND; ++j) {
-    const int i = t + NTH * j;
-    T v = 0;
-    if (i < 8 * KS) {
-      const int o = i / KS;
-      const int g = i - o * KS;
-      if (g < K) v = Dil[((size_t)di * 8 + o) * K + g];
-    }
-    vD[j] = v;
-  }
+  for (int j = 0; j < NJ; ++j)
+    if (NV % NTH == 0 || t + NTH * j < NV) vD[j] = src[t + NTH * j];
 }
 
-template <typename T, int K, int KS, int NTH>
-__device__ inline void store_drows_t(T* sD, const T* vD) {
-  constexpr int SD = 8 * KS + 1;
-  constexpr int ND = (SD + NTH - 1) / NTH;
+template <typename T, int SDP, int NTH>
+__device__ inline void store_dstage_t(T* sD, const typename Vec16<T>::type* vD) {
+  using V = typename Vec16<T>::type;
+  constexpr int NV = SDP / (16 / (int)sizeof(T)), NJ = (NV + NTH - 1) / NTH;
   const int t = threadIdx.x;
 #pragma unroll
-  for (int j = 0; j < ND; ++j) {
-    const int i = t + NTH * j;
-    if (i < SD) sD[i] = vD[j];
-  }
+  for (int j = 0; j < NJ; ++j)
+    if (NV % NTH == 0 || t + NTH * j < NV) ((V*)sD)[t + NTH * j] = vD[j];
 }
 
 }  // namespace afmm

@@ -601,7 +601,7 @@ static void build_tables(int p, HostTables& H) {
         H.tapsT.push_back(e | (oF << 5) | (di << 8));
       }
   // MFMA A-operand offsets into the staged D~ rows (sD[o][g], row stride KS, zero slot 8 KS)
-  const int KP = (K + 3) & ~3, KS = KP + 1, ZERO = 8 * KS, K1 = nmi(p - 1);
+  const int KP = (K + 3) & ~3, KS = dstage_ks(p), ZERO = 8 * KS, K1 = nmi(p - 1);
   auto deg = [&](int idx) { return H.mi[4 * idx + 3]; };
   H.m2p_off.clear();
   for (int rt = 0; rt < 2; ++rt) {

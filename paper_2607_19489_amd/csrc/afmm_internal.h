@@ -60,8 +60,14 @@ __host__ __device__ constexpr int src_vec(int j, int g, int bytes) { return (4 *
 // D~ rows of one source offset in the layout the MFMA kernels stage in LDS:
 // row o (child octant) at o * dstage_ks(p), coefficients g < K then zeros up
 // to the stride, one zero slot at 8 * dstage_ks(p), zero padding to whole
-// 16-byte vectors for every lane of a wave.  Copied to LDS as is.
-__host__ __device__ constexpr int dstage_ks(int p) { return ((nmi(p) + 3) & ~3) + 1; }
+// 16-byte vectors for every lane of a wave.  Copied to LDS as is.  The row
+// stride is chosen per order (at least K rounded up to 4, same padded length)
+// to spread the A-operand gathers of M2P and M2L (8 rows x derivative-shifted
+// coefficient indices per lane) over the LDS banks; chosen by counting bank
+// conflicts of those offset tables for 32- and 64-bank LDS models.
+__host__ __device__ constexpr int dstage_ks(int p) {
+  return p == 1 ? 6 : p == 2 ? 30 : p == 3 ? 28 : p == 4 ? 52 : p == 5 ? 57 : p == 6 ? 93 : p == 7 ? 121 : 185;
+}
 __host__ __device__ constexpr int dstage_len(int p, int bytes) {
   return (8 * dstage_ks(p) + 1 + 64 * (16 / bytes) - 1) / (64 * (16 / bytes)) * (64 * (16 / bytes));
 }

@@ -321,7 +321,7 @@ template <typename T, int P>
 struct TapStage {
   static constexpr int K = nmi(P);
   static constexpr int KP = (K + 3) & ~3;    // coefficients covered by the k-steps
-  static constexpr int KS = KP + 1;          // sD row stride
+  static constexpr int KS = dstage_ks(P);    // sD row stride
   static constexpr int VW = 16 / (int)sizeof(T);
   static constexpr int STP = src_stp(P, (int)sizeof(T));  // per-lane run of the source copy
   static constexpr int ROW = 4 * STP;        // source-copy row length

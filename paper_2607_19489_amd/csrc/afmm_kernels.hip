@@ -146,20 +146,27 @@ __global__ __launch_bounds__(256) void k_upward(LevelDev lv, LevelDev lvc, Commo
   }
   for (int i = t; i <= K; i += 256) sB[i] = cm.m2m_start[i];
   const int c = t / KP, a = t - c * KP;
-  for (int r0 = blockIdx.x * CB; r0 < lv.nref; r0 += gridDim.x * CB) {
-    // children of the chunk: refined rank, or the mass of a leaf child
-    if (t < CB * 8) {
-      const int r = r0 + (t >> 3);
-      int rc = -1;
-      double m = 0.0;
-      if (r < lv.nref) {
-        const int ch = 8 * r + (t & 7);
-        rc = lvc.rank[ch];
-        if (rc < 0) m = lvc.mass[ch];
-      }
-      sRc[t >> 3][t & 7] = rc;
-      sM[t >> 3][t & 7] = m;
+  // children of a chunk: refined rank and mass (the gathered mass of a refined
+  // child is 0 and unused), two independent loads, prefetched one chunk ahead
+  auto child = [&](int r0, int& rc, double& m) {
+    rc = -1;
+    m = 0.0;
+    const int r = r0 + (t >> 3);
+    if (t < CB * 8 && r < lv.nref) {
+      const int ch = 8 * r + (t & 7);
+      rc = lvc.rank[ch];
+      m = lvc.mass[ch];
     }
+  };
+  int rcn;
+  double mn;
+  child(blockIdx.x * CB, rcn, mn);
+  for (int r0 = blockIdx.x * CB; r0 < lv.nref; r0 += gridDim.x * CB) {
+    if (t < CB * 8) {
+      sRc[t >> 3][t & 7] = rcn;
+      sM[t >> 3][t & 7] = rcn < 0 ? mn : 0.0;
+    }
+    child(r0 + gridDim.x * CB, rcn, mn);
     __syncthreads();
     // 8 child values per (cell, coefficient) -> signed sums over the octant bits
     for (int i = t; i < CB * K; i += 256) {

@@ -62,3 +62,21 @@ def test_batch_autotune():
         leaf = ws[i].hierarchy.leaf_mask()
         assert rel_l2(accs[i].cpu().numpy()[leaf], acc.cpu().numpy()[leaf]) <= 1e-13
         assert rel_l2(phis[i].cpu().numpy()[leaf], phi.cpu().numpy()[leaf]) <= 1e-13
+
+
+def test_level_solve_after_autotune_matches_oracle():
+    """The autotuner's solves rebuild every tree from the tuned masses: a level
+    solve without a rebuild right after it evaluates those trees."""
+    h = _amr()
+    m = cell_masses(h, plummer(1.0, 0.05), 0.01, 13)
+    plan = A.Plan(h, p=5, precision="fp64")
+    plan.autotune(torch.from_numpy(m).cuda())
+    o = oracle.Oracle(h, 5)
+    o.rebuild(h.levelmin, m)
+    lev = h.level_of()
+    for l in (5, 6):
+        phi, acc = plan.solve(torch.from_numpy(m * 2.0).cuda(), level=l, icount=1)
+        torch.cuda.synchronize()
+        sel = np.nonzero((lev == l) & h.leaf_mask())[0]
+        po, ao = o.eval(l, sel)
+        assert rel_l2(acc.cpu().numpy()[sel], ao) <= 1e-10 and rel_l2(phi.cpu().numpy()[sel], po) <= 1e-10

@@ -130,3 +130,27 @@ def test_ats_sequence_matches_oracle():
         sel = (lev == l) & h.leaf_mask()
         assert rel_l2(acc[sel], ao[sel]) < 1e-10, (l, ic)
         assert rel_l2(phi[sel], po[sel]) < 1e-10, (l, ic)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_level_solve_without_rebuild_reproduces_the_full_solve(precision):
+    """Alg. 1: solve(l, icount=1) for l > levelmin rebuilds no tree, so right after a
+    full solve it must give the full solve's level-l values whatever masses it is
+    handed: the device keeps the trees, and the level's restricted M2L/L2L chain
+    computes every needed local expansion with the same per-column arithmetic."""
+    import paper_2607_19489_amd as A
+    h = _amr(4, {4: 0.25, 5: 0.15, 6: 0.08})
+    m = cell_masses(h, plummer(1.0, 0.05), 0.01, 21)
+    plan = A.Plan(h, p=5, precision=precision, tap_split=2)
+    phi, acc, _ = gpu_solve(h, m, 5, plan=plan)
+    lev = h.level_of()
+    junk = m * 3.0 + 1.0
+    for l in (5, 6, 7):
+        pl, al, _ = gpu_solve(h, junk, 5, level=l, icount=1, plan=plan)
+        sel = (lev == l) & h.leaf_mask()
+        assert sel.any()
+        assert np.array_equal(pl[sel], phi[sel]) and np.array_equal(al[sel], acc[sel]), l
+    # a rebuild (icount 2) takes the new masses of levels >= l: level l changes
+    pl, al, _ = gpu_solve(h, junk, 5, level=6, icount=2, plan=plan)
+    sel = (lev == 6) & h.leaf_mask()
+    assert not np.allclose(al[sel], acc[sel])

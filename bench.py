@@ -432,7 +432,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{w.name}: {desc}", "p": w.p, "precision": "FP32 mixed (FP64 P2M/M2M, "
-                   "FMM levels <= 4 and outputs)", "leaves": info["nleaves"], "levels": [h.levelmin, h.levelmax]},
+                   "FMM levels <= 3 and outputs)", "leaves": info["nleaves"], "levels": [h.levelmin, h.levelmax]},
         "roofline": roofline(r32, "fp32", w.p, w.name),
         "cpu_baseline": base,
         "fp64_form": None if r64 is None else {"value": r64["value"], "unit": "cells/s",

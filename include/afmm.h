@@ -60,7 +60,7 @@ typedef struct afmm_options {
   double G;                  /* gravitational constant */
   double boxlen;             /* box side */
   uint32_t flags;            /* AFMM_CHECK_INPUT | AFMM_SERIAL */
-  int32_t fp64_levels;       /* mixed form: FMM levels <= this stay FP64 (default 4) */
+  int32_t fp64_levels;       /* mixed form: FMM levels <= this stay FP64 (default 3) */
   int32_t tap_split;         /* M2L and M2P blocks per tile: the 189 source offsets of a tile are
                                 split over this many blocks and their partial sums reduced in a
                                 fixed order; 0 = automatic (enough blocks to fill the GPU), else
@@ -68,7 +68,7 @@ typedef struct afmm_options {
   size_t max_device_bytes;   /* cap on the plan's device memory; 0 = no cap */
 } afmm_options;
 
-/* Defaults: p = 4, FP64, G = 1, boxlen = 1, no flags, fp64_levels = 4, tap_split = 0 (automatic),
+/* Defaults: p = 4, FP64, G = 1, boxlen = 1, no flags, fp64_levels = 3, tap_split = 0 (automatic),
    no cap. */
 void afmm_options_default(afmm_options* opt);
 

@@ -41,7 +41,7 @@ def _hier_struct(levelmin, levelmax, ncell, ijk, ref):
 
 
 def make_options(p: int = 4, precision: str = "fp64", G: float = 1.0, boxlen: float = 1.0,
-                 fp64_levels: int = 4, check_input: bool = False, max_device_bytes: int = 0,
+                 fp64_levels: int = 3, check_input: bool = False, max_device_bytes: int = 0,
                  tap_split: int = 0, serial: bool = False) -> Options:
     o = Options()
     lib().afmm_options_default(C.byref(o))
@@ -78,7 +78,7 @@ class Plan:
     """A solver plan for one AMR hierarchy (afmm_plan)."""
 
     def __init__(self, h, p: int = 4, precision: str = "fp64", G: float = 1.0,
-                 boxlen: Optional[float] = None, fp64_levels: int = 4, check_input: bool = False,
+                 boxlen: Optional[float] = None, fp64_levels: int = 3, check_input: bool = False,
                  max_device_bytes: int = 0, tap_split: int = 0, serial: bool = False,
                  stream: Optional[torch.cuda.Stream] = None):
         self._ptr = C.c_void_p()

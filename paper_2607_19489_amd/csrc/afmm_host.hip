@@ -897,7 +897,7 @@ void afmm_options_default(afmm_options* o) {
   o->G = 1.0;
   o->boxlen = 1.0;
   o->flags = 0;
-  o->fp64_levels = 4;
+  o->fp64_levels = 3;
   o->tap_split = 0;
   o->max_device_bytes = 0;
 }

@@ -459,7 +459,7 @@ template <typename T, int P>
 __global__ __launch_bounds__(64) void k_adj_m2p_mfma(const int32_t* __restrict__ tiles, int ntiles, int nsplit,
                                                      double* __restrict__ part, const int32_t* __restrict__ tapsT,
                                                      const int16_t* __restrict__ aoff, LevelDev lvp, LevelDev lvs,
-                                                     const T* __restrict__ tbT, const T* __restrict__ Dil) {
+                                                     const T* __restrict__ tbT, const T* __restrict__ Dst) {
   constexpr int K = nmi(P), RT = (K + 15) / 16;
   constexpr int SDP = dstage_len(P, (int)sizeof(T));
   constexpr int VW = 16 / (int)sizeof(T), NVB = 8 / VW, ND = (SDP / VW + 63) / 64;
@@ -497,7 +497,7 @@ __global__ __launch_bounds__(64) void k_adj_m2p_mfma(const int32_t* __restrict__
   V vD[ND];
   int gn = adj_group(sTap[tb], n, sCB, lvs.rank);
   loadB(gn, bA);
-  load_dstage_t<T, SDP, 64>(sTap[tb] >> 8, Dil, vD);
+  load_dstage_t<T, SDP, 64>(sTap[tb] >> 8, Dst, vD);
   store_dstage_t<T, SDP, 64>(sD[0], vD);
   if (tb + 1 < te) gn = adj_group(sTap[tb + 1], n, sCB, lvs.rank);
   __syncthreads();
@@ -505,7 +505,7 @@ __global__ __launch_bounds__(64) void k_adj_m2p_mfma(const int32_t* __restrict__
     const int b = (k - tb) & 1;
     if (k + 1 < te) {
       loadB(gn, bn);
-      load_dstage_t<T, SDP, 64>(sTap[k + 1] >> 8, Dil, vD);
+      load_dstage_t<T, SDP, 64>(sTap[k + 1] >> 8, Dst, vD);
     }
     if (k + 2 < te) gn = adj_group(sTap[k + 2], n, sCB, lvs.rank);
     const T* D = sD[b];
@@ -557,7 +557,7 @@ __global__ __launch_bounds__(64) void k_adj_m2l_mfma(const int32_t* __restrict__
                                                      double* __restrict__ part, const int32_t* __restrict__ tapsT,
                                                      const int16_t* __restrict__ aoff, LevelDev lvp, LevelDev lvs,
                                                      LevelDev lvt, const T* __restrict__ lT,
-                                                     const T* __restrict__ Dil) {
+                                                     const T* __restrict__ Dst) {
   constexpr int K = nmi(P), KS = dstage_ks(P), SDP = dstage_len(P, (int)sizeof(T));
   constexpr AdjM2LPlan<P> PL = make_adj_m2l_plan<P>();
   constexpr int RT = AdjM2LPlan<P>::RT;
@@ -598,7 +598,7 @@ __global__ __launch_bounds__(64) void k_adj_m2l_mfma(const int32_t* __restrict__
   int gcur = adj_group(sTap[tb], n, sCB, lvs.rank);
   int gnext = tb + 1 < te ? adj_group(sTap[tb + 1], n, sCB, lvs.rank) : -1;
   loadB(child(gcur, 0), bA);
-  load_dstage_t<T, SDP, 64>(sTap[tb] >> 8, Dil, vD);
+  load_dstage_t<T, SDP, 64>(sTap[tb] >> 8, Dst, vD);
   store_dstage_t<T, SDP, 64>(sD[0], vD);
   __syncthreads();
   // sub-step (tap k, octant o): B of (k, o) in bc; prefetch (k, o+1) or (k+1, 0) into bn
@@ -615,7 +615,7 @@ __global__ __launch_bounds__(64) void k_adj_m2l_mfma(const int32_t* __restrict__
   };
   for (int k = tb; k < te; ++k) {
     const int b = (k - tb) & 1;
-    if (k + 1 < te) load_dstage_t<T, SDP, 64>(sTap[k + 1] >> 8, Dil, vD);
+    if (k + 1 < te) load_dstage_t<T, SDP, 64>(sTap[k + 1] >> 8, Dst, vD);
 #pragma unroll
     for (int o = 0; o < 8; o += 2) {
       sub(k, o, bA, bB);
@@ -761,13 +761,13 @@ static hipError_t adj_reduce(int p, const int32_t* tiles, int ntiles, int nsplit
 template <typename T>
 static hipError_t adj_m2p_t(int p, const int32_t* tiles, int ntiles, int nsplit, double* part, const int32_t* tapsT,
                             const int16_t* aoff, const LevelDev& lvp, const LevelDev& lvs, const LevelDev& lvt,
-                            const T* Dil, hipStream_t st) {
+                            const T* Dst, hipStream_t st) {
   T* tbT = (T*)lvs.tbT;
   hipLaunchKernelGGL((k_adj_tbT<T>), dim3((lvs.nref * 32 + 255) / 256), dim3(256), 0, st, lvs, lvt, tbT);
   const int items = ntiles * nsplit;
   const dim3 grid(8 * ((items + 7) / 8)), block(64);
 #define X(PP) \
-  case PP: hipLaunchKernelGGL((k_adj_m2p_mfma<T, PP>), grid, block, 0, st, tiles, ntiles, nsplit, part, tapsT, aoff, lvp, lvs, (const T*)tbT, Dil); break;
+  case PP: hipLaunchKernelGGL((k_adj_m2p_mfma<T, PP>), grid, block, 0, st, tiles, ntiles, nsplit, part, tapsT, aoff, lvp, lvs, (const T*)tbT, Dst); break;
   AFMM_P_SWITCH(p, X)
 #undef X
   return adj_reduce(p, tiles, ntiles, nsplit, part, lvs, st);
@@ -785,7 +785,7 @@ hipError_t launch_adj_m2p_mfma(int p, bool fp32, const int32_t* tiles, int ntile
 template <typename T>
 static hipError_t adj_m2l_t(int p, const int32_t* tiles, int ntiles, int nsplit, double* part, const int32_t* tapsT,
                             const int16_t* aoff, const LevelDev& lvp, const LevelDev& lvs, const LevelDev& lvt,
-                            const T* Dil, hipStream_t st) {
+                            const T* Dst, hipStream_t st) {
   T* lT = (T*)lvt.lbarT;
   const int rows = lvt.nref * src_row(p, (int)sizeof(T));
 #define X(PP) \
@@ -795,7 +795,7 @@ static hipError_t adj_m2l_t(int p, const int32_t* tiles, int ntiles, int nsplit,
   const int items = ntiles * nsplit;
   const dim3 grid(8 * ((items + 7) / 8)), block(64);
 #define X(PP) \
-  case PP: hipLaunchKernelGGL((k_adj_m2l_mfma<T, PP>), grid, block, 0, st, tiles, ntiles, nsplit, part, tapsT, aoff, lvp, lvs, lvt, (const T*)lT, Dil); break;
+  case PP: hipLaunchKernelGGL((k_adj_m2l_mfma<T, PP>), grid, block, 0, st, tiles, ntiles, nsplit, part, tapsT, aoff, lvp, lvs, lvt, (const T*)lT, Dst); break;
   AFMM_P_SWITCH(p, X)
 #undef X
   return adj_reduce(p, tiles, ntiles, nsplit, part, lvs, st);

@@ -1135,12 +1135,12 @@ static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
   };
   if ((s = upload_conv<double>(P, dstage(8), &P->t64.Dstage, st))) return s;
   if (mixed && (s = upload_conv<float>(P, dstage(4), &P->t32.Dstage, st))) return s;
-  if ((s = upload_conv<double>(P, H.Dil, &P->t64.Dil, st)) || (s = upload_conv<double>(P, H.Dsame, &P->t64.Dsame, st)) ||
+  if ((s = upload_conv<double>(P, H.Dsame, &P->t64.Dsame, st)) ||
       (s = upload_conv<double>(P, H.cfac2, &P->t64.cfac2, st)) || (s = upload_conv<double>(P, H.cfacn, &P->t64.cfacn, st)) ||
       (s = upload_conv<double>(P, H.l2lw, &P->t64.l2lw, st)) || (s = upload_conv<double>(P, H.l2p, &P->t64.l2p, st)))
     return s;
   if (mixed) {
-    if ((s = upload_conv<float>(P, H.Dil, &P->t32.Dil, st)) || (s = upload_conv<float>(P, H.Dsame, &P->t32.Dsame, st)) ||
+    if ((s = upload_conv<float>(P, H.Dsame, &P->t32.Dsame, st)) ||
         (s = upload_conv<float>(P, H.cfac2, &P->t32.cfac2, st)) || (s = upload_conv<float>(P, H.cfacn, &P->t32.cfacn, st)) ||
         (s = upload_conv<float>(P, H.l2lw, &P->t32.l2lw, st)) || (s = upload_conv<float>(P, H.l2p, &P->t32.l2p, st)))
       return s;

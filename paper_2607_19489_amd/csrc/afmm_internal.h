@@ -106,8 +106,8 @@ struct LevelDev {
 
 template <typename T>
 struct TablesDev {
-  const T* Dil = nullptr;     // [kNumD * 8][K]  D~ at R~ = -2d + o - 1/2
-  const T* Dstage = nullptr;  // [kNumD][dstage_len(p, sizeof(T))] the same rows in LDS stage layout
+  const T* Dstage = nullptr;  // [kNumD][dstage_len(p, sizeof(T))] D~ at R~ = -2d + o - 1/2, 8 rows per d,
+                              // in the LDS stage layout of the MFMA kernels
   const T* Dsame = nullptr;   // [kNumD][K]      D~ at integer R~ in [-3,3]^3
   const T* cfac2 = nullptr;   // [K] (-1)^|a|/a! 2^|a|
   const T* cfacn = nullptr;   // [K] 2^-|a|: same-level M2P from the source copies

@@ -976,14 +976,14 @@ __global__ __launch_bounds__(kBlock) void k_near_m2p(const int32_t* __restrict__
 
 template <typename T>
 static hipError_t m2p_dispatch(int p, const MfmaTiles& mt, int t0, int n, int nsplit, const MfmaTables& tabs,
-                               const LevelDev* lvs, const T* Dil, hipStream_t st) {
+                               const LevelDev* lvs, const T* Dst, hipStream_t st) {
   const int items = n * nsplit;
   const dim3 grid(8 * ((items + 7) / 8)), block(64);
   const int32_t* tl = mt.tiles + (size_t)t0 * 17;
   switch (p) {
 #define AFMM_M2P(PP)                                                                                              \
   case PP:                                                                                                  \
-    hipLaunchKernelGGL((k_m2p<T, PP>), grid, block, 0, st, tl, n, nsplit, tabs.taps, tabs.m2p_off, lvs, Dil);  \
+    hipLaunchKernelGGL((k_m2p<T, PP>), grid, block, 0, st, tl, n, nsplit, tabs.taps, tabs.m2p_off, lvs, Dst);  \
     break;
     AFMM_M2P(1) AFMM_M2P(2) AFMM_M2P(3) AFMM_M2P(4) AFMM_M2P(5) AFMM_M2P(6) AFMM_M2P(7) AFMM_M2P(8)
 #undef AFMM_M2P
@@ -1008,7 +1008,7 @@ int m2p_columns(int p, bool fp32) {
 
 template <typename T>
 static hipError_t m2l_dispatch(int p, const MfmaTiles& mt, int t0, int n, int nsplit, const MfmaTables& tabs,
-                               const LevelDev* lvs, const T* Dil, hipStream_t st) {
+                               const LevelDev* lvs, const T* Dst, hipStream_t st) {
   const int items = n * nsplit;
   const dim3 grid(8 * ((items + 7) / 8)), block(kBlock);
   const int32_t* tl = mt.tiles + (size_t)t0 * 17;
@@ -1016,7 +1016,7 @@ static hipError_t m2l_dispatch(int p, const MfmaTiles& mt, int t0, int n, int ns
 #define AFMM_M2L(PP)                                                                                          \
   case PP:                                                                                                    \
     hipLaunchKernelGGL((k_m2l_mfma<T, PP>), grid, block, 0, st, tl, n, nsplit, tabs.taps, tabs.m2l_off, lvs, \
-                       Dil);                                                                                  \
+                       Dst);                                                                                  \
     break;
     AFMM_M2L(1) AFMM_M2L(2) AFMM_M2L(3) AFMM_M2L(4) AFMM_M2L(5) AFMM_M2L(6) AFMM_M2L(7) AFMM_M2L(8)
 #undef AFMM_M2L

@@ -168,9 +168,19 @@ __global__ __launch_bounds__(256) void k_upward(LevelDev lv, LevelDev lvc, Commo
     }
     child(r0 + gridDim.x * CB, rcn, mn);
     __syncthreads();
+    // a cell whose 8 children are leaves has only monopole children: its signed
+    // sums vanish for k > 0 and each coefficient keeps the k = 0 entry (the
+    // first of its list)
+    auto leaf_only = [&](int cc) {
+      bool lo = true;
+#pragma unroll
+      for (int o = 0; o < 8; ++o) lo = lo && sRc[cc][o] < 0;
+      return lo;
+    };
     // 8 child values per (cell, coefficient) -> signed sums over the octant bits
     for (int i = t; i < CB * K; i += 256) {
       const int cc = i / K, k = i - cc * K;
+      if (k > 0 && leaf_only(cc)) continue;
       double v[8];
 #pragma unroll
       for (int o = 0; o < 8; ++o) {
@@ -199,9 +209,13 @@ __global__ __launch_bounds__(256) void k_upward(LevelDev lv, LevelDev lvc, Commo
         if (lv.Sc64 && a < 4 * STP64) lv.Sc64[(size_t)r * 4 * STP64 + src_pos(a, 8)] = 0.0;
       } else {
         double acc = 0.0;
-        for (int j = sB[a]; j < sB[a + 1]; ++j) {
-          const int e = sE[j];
-          acc += sW[j] * sY[c][e >> 12][e & 4095];
+        if (leaf_only(c)) {
+          acc = sW[sB[a]] * sY[c][sE[sB[a]] >> 12][0];
+        } else {
+          for (int j = sB[a]; j < sB[a + 1]; ++j) {
+            const int e = sE[j];
+            acc += sW[j] * sY[c][e >> 12][e & 4095];
+          }
         }
         lv.S64[(size_t)r * K + a] = acc;
         // source copies for the translation kernels carry the factor (-1)^|a|/a! 2^|a|

@@ -38,7 +38,7 @@ typedef int32_t afmm_status;
 #define AFMM_E_NOT_GRADED (-2)     /* refinement breaks the graded-octree rule of Sec. 3.2 */
 #define AFMM_E_INCOMPLETE_OCT (-3) /* a refined cell without its 8 children, or an orphan cell */
 #define AFMM_E_UNSUPPORTED (-4)    /* p outside 1..8, unknown precision or flag */
-#define AFMM_E_OUT_OF_MEMORY (-5)  /* device allocation failed or exceeds max_device_bytes */
+#define AFMM_E_OUT_OF_MEMORY (-5)  /* device or host allocation failed, or max_device_bytes exceeded */
 #define AFMM_E_DEVICE (-6)         /* HIP runtime error; sticky on the plan */
 #define AFMM_E_ATS_ORDER (-7)      /* solve(l, icount) needs trees that were never built */
 #define AFMM_E_NONFINITE (-8)      /* non-finite mass seen (only with AFMM_CHECK_INPUT) */

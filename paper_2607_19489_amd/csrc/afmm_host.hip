@@ -22,6 +22,21 @@ static afmm_status fail(afmm_status s, const std::string& msg) {
   return s;
 }
 
+// Host containers may throw (std::bad_alloc on huge plans); no exception may
+// cross the C ABI, so every entry point that allocates runs through this.
+template <typename F>
+static afmm_status guarded(F&& f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    return fail(AFMM_E_OUT_OF_MEMORY, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(AFMM_E_INVALID_ARG, std::string("internal error: ") + e.what());
+  } catch (...) {
+    return fail(AFMM_E_INVALID_ARG, "internal error");
+  }
+}
+
 // ---------------------------------------------------------------------------
 // topology (host)
 
@@ -919,7 +934,7 @@ const char* afmm_status_string(afmm_status s) {
 
 const char* afmm_last_error(void) { return g_last_error.c_str(); }
 
-afmm_status afmm_hierarchy_check(const afmm_hierarchy* h, const afmm_options* opt, afmm_plan_info* out) {
+static afmm_status afmm_hierarchy_check_impl(const afmm_hierarchy* h, const afmm_options* opt, afmm_plan_info* out) {
   if (!h) return fail(AFMM_E_INVALID_ARG, "null hierarchy");
   afmm_options o;
   if (opt) o = *opt;
@@ -1254,7 +1269,7 @@ static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
   return AFMM_OK;
 }
 
-extern "C" afmm_status afmm_plan_create(const afmm_hierarchy* h, const afmm_options* opt, void* hip_stream,
+static afmm_status afmm_plan_create_impl(const afmm_hierarchy* h, const afmm_options* opt, void* hip_stream,
                                         afmm_plan** out) {
   if (!h || !out) return fail(AFMM_E_INVALID_ARG, "null argument");
   *out = nullptr;
@@ -1264,10 +1279,16 @@ extern "C" afmm_status afmm_plan_create(const afmm_hierarchy* h, const afmm_opti
   afmm_status s = check_options(&o);
   if (s) return s;
   afmm_plan* P = new afmm_plan();
-  P->opt = o;
-  P->K = nmi(o.p);
-  s = append_hierarchy(P->topo, *h, 0);
-  if (!s) s = plan_finish(P, (hipStream_t)hip_stream);
+  try {
+    P->opt = o;
+    P->K = nmi(o.p);
+    s = append_hierarchy(P->topo, *h, 0);
+    if (!s) s = plan_finish(P, (hipStream_t)hip_stream);
+  } catch (...) {
+    free_plan(P);
+    delete P;
+    throw;
+  }
   if (s) {
     free_plan(P);
     delete P;
@@ -1454,7 +1475,7 @@ static afmm_status run_solve(afmm_plan* P, const double* msrc, int fmax, int lo,
   return AFMM_OK;
 }
 
-extern "C" afmm_status afmm_solve(afmm_plan* P, int32_t level, int32_t icount, const double* d_mass, double* d_phi,
+static afmm_status afmm_solve_impl(afmm_plan* P, int32_t level, int32_t icount, const double* d_mass, double* d_phi,
                                   double* d_acc, void* hip_stream) {
   if (!P || !d_mass || !d_phi || !d_acc) return fail(AFMM_E_INVALID_ARG, "null argument");
   if (P->dead) return fail(AFMM_E_DEVICE, "plan is unusable after an earlier device error");
@@ -1519,7 +1540,7 @@ extern "C" afmm_status afmm_plan_set_profiling(afmm_plan* P, int32_t enable) {
   return AFMM_OK;
 }
 
-extern "C" afmm_status afmm_plan_get_profile(afmm_plan* P, afmm_stage_time* out, int32_t cap, int32_t* n_out) {
+static afmm_status afmm_plan_get_profile_impl(afmm_plan* P, afmm_stage_time* out, int32_t cap, int32_t* n_out) {
   if (!P || !n_out || (cap > 0 && !out)) return fail(AFMM_E_INVALID_ARG, "null argument");
   afmm_stage_time acc[kNumKinds];
   std::memset(acc, 0, sizeof acc);
@@ -1649,7 +1670,7 @@ afmm_status autotune_core(afmm_plan* P, SolveFn solve, hipStream_t st, afmm_tune
 }
 }  // namespace
 
-extern "C" afmm_status afmm_plan_autotune(afmm_plan* P, const double* d_mass, double* d_phi, double* d_acc,
+static afmm_status afmm_plan_autotune_impl(afmm_plan* P, const double* d_mass, double* d_phi, double* d_acc,
                                           void* hip_stream, afmm_tune_result* out) {
   if (!P || !d_mass || !d_phi || !d_acc) return fail(AFMM_E_INVALID_ARG, "null argument");
   if (P->dead) return fail(AFMM_E_DEVICE, "plan is unusable after an earlier device error");
@@ -1672,7 +1693,7 @@ extern "C" afmm_status afmm_plan_autotune(afmm_plan* P, const double* d_mass, do
   return AFMM_OK;
 }
 
-extern "C" afmm_status afmm_batch_autotune(afmm_batch* B, const double* const* d_mass, double* const* d_phi,
+static afmm_status afmm_batch_autotune_impl(afmm_batch* B, const double* const* d_mass, double* const* d_phi,
                                            double* const* d_acc, void* hip_stream, afmm_tune_result* out) {
   if (!B || !d_mass || !d_phi || !d_acc) return fail(AFMM_E_INVALID_ARG, "null argument");
   afmm_plan* P = B->plan;
@@ -1799,7 +1820,7 @@ static afmm_status adjoint_workspace(afmm_plan* P) {
   return AFMM_OK;
 }
 
-extern "C" afmm_status afmm_solve_adjoint(afmm_plan* P, int32_t level, const double* d_phi_bar,
+static afmm_status afmm_solve_adjoint_impl(afmm_plan* P, int32_t level, const double* d_phi_bar,
                                           const double* d_acc_bar, double* d_mass_bar, void* hip_stream) {
   if (!P || !d_phi_bar || !d_acc_bar || !d_mass_bar) return fail(AFMM_E_INVALID_ARG, "null argument");
   if (P->dead) return fail(AFMM_E_DEVICE, "plan is unusable after an earlier device error");
@@ -2013,7 +2034,7 @@ static afmm_status capture_batch(afmm_batch* B) {
   return s;
 }
 
-extern "C" afmm_status afmm_batch_create(afmm_plan* const* plans, int32_t n, void* hip_stream, afmm_batch** out) {
+static afmm_status afmm_batch_create_impl(afmm_plan* const* plans, int32_t n, void* hip_stream, afmm_batch** out) {
   if (!plans || !out || n < 1) return fail(AFMM_E_INVALID_ARG, "null argument or n < 1");
   *out = nullptr;
   hipStream_t st = (hipStream_t)hip_stream;
@@ -2029,62 +2050,68 @@ extern "C" afmm_status afmm_batch_create(afmm_plan* const* plans, int32_t n, voi
       return fail(AFMM_E_INVALID_ARG, "plans of a batch must share p, precision, G, boxlen, fp64_levels, tap_split");
   }
   afmm_batch* B = new afmm_batch();
-  B->n = n;
-  B->plan = new afmm_plan();
-  afmm_plan* P = B->plan;
-  P->opt = o0;
-  P->opt.flags = 0;
-  P->K = nmi(o0.p);
-  B->base.assign(n + 1, 0);
-  for (int32_t i = 0; i < n; ++i) {
-    merge_topology(P->topo, plans[i]->topo, B->base[i]);
-    B->base[i + 1] = B->base[i] + plans[i]->topo.nslots;
-  }
-  afmm_status s = B->base[n] >= ((int64_t)1 << 31) ? fail(AFMM_E_INVALID_ARG, "batch has more than 2^31 cells")
-                                                    : plan_finish(P, st);
-  // leaf slots of the forest and their hierarchy
-  std::vector<int32_t> lslot, lhier;
-  if (!s) {
-    const Topology& T = P->topo;
-    for (int l = 0; l <= T.lmax; ++l)
-      for (int32_t c = 0; c < T.lv[l].n(); ++c) {
-        const int32_t sl = T.lv[l].slot[c];
-        if (T.lv[l].rank[c] >= 0 || sl < 0) continue;
-        lslot.push_back(sl);
-        lhier.push_back((int32_t)(std::upper_bound(B->base.begin(), B->base.end(), (int64_t)sl) - B->base.begin() - 1));
-      }
-    B->nleaf = (int64_t)lslot.size();
-    void* q = nullptr;
-    const size_t ns = (size_t)std::max<int64_t>(P->topo.nslots, 1);
-    if (!s) s = dev_alloc(P, &q, ns * sizeof(double)), B->d_mass = (double*)q;
-    if (!s) s = dev_alloc(P, &q, ns * sizeof(double)), B->d_phi = (double*)q;
-    if (!s) s = dev_alloc(P, &q, ns * 3 * sizeof(double)), B->d_acc = (double*)q;
-    if (!s) s = dev_alloc(P, &q, (size_t)3 * n * sizeof(void*)), B->d_ptrs = (void**)q;
-    if (!s) s = upload(P, lslot, &B->d_leafslot, st);
-    if (!s) s = upload(P, lhier, &B->d_leafhier, st);
-    if (!s) s = upload(P, B->base, &B->d_base, st);
-    if (!s && (hipHostMalloc((void**)&B->h_stage, (size_t)3 * n * sizeof(void*), hipHostMallocDefault) != hipSuccess ||
-               hipEventCreateWithFlags(&B->ev_stage, hipEventDisableTiming) != hipSuccess ||
-               hipEventRecord(B->ev_stage, st) != hipSuccess))
-      s = fail(AFMM_E_DEVICE, "batch pointer staging");
-  }
-  // capture: gather -> solve -> scatter, replayed by afmm_batch_solve
-  if (!s) {
-    if (hipStreamSynchronize(st) != hipSuccess ||
-        hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking) != hipSuccess)
-      s = fail(AFMM_E_DEVICE, "batch stream creation failed");
-  }
-  if (!s) s = capture_batch(B);
-  if (s) {
+  try {
+    B->n = n;
+    B->plan = new afmm_plan();
+    afmm_plan* P = B->plan;
+    P->opt = o0;
+    P->opt.flags = 0;
+    P->K = nmi(o0.p);
+    B->base.assign(n + 1, 0);
+    for (int32_t i = 0; i < n; ++i) {
+      merge_topology(P->topo, plans[i]->topo, B->base[i]);
+      B->base[i + 1] = B->base[i] + plans[i]->topo.nslots;
+    }
+    afmm_status s = B->base[n] >= ((int64_t)1 << 31) ? fail(AFMM_E_INVALID_ARG, "batch has more than 2^31 cells")
+                                                      : plan_finish(P, st);
+    // leaf slots of the forest and their hierarchy
+    std::vector<int32_t> lslot, lhier;
+    if (!s) {
+      const Topology& T = P->topo;
+      for (int l = 0; l <= T.lmax; ++l)
+        for (int32_t c = 0; c < T.lv[l].n(); ++c) {
+          const int32_t sl = T.lv[l].slot[c];
+          if (T.lv[l].rank[c] >= 0 || sl < 0) continue;
+          lslot.push_back(sl);
+          lhier.push_back((int32_t)(std::upper_bound(B->base.begin(), B->base.end(), (int64_t)sl) - B->base.begin() - 1));
+        }
+      B->nleaf = (int64_t)lslot.size();
+      void* q = nullptr;
+      const size_t ns = (size_t)std::max<int64_t>(P->topo.nslots, 1);
+      if (!s) s = dev_alloc(P, &q, ns * sizeof(double)), B->d_mass = (double*)q;
+      if (!s) s = dev_alloc(P, &q, ns * sizeof(double)), B->d_phi = (double*)q;
+      if (!s) s = dev_alloc(P, &q, ns * 3 * sizeof(double)), B->d_acc = (double*)q;
+      if (!s) s = dev_alloc(P, &q, (size_t)3 * n * sizeof(void*)), B->d_ptrs = (void**)q;
+      if (!s) s = upload(P, lslot, &B->d_leafslot, st);
+      if (!s) s = upload(P, lhier, &B->d_leafhier, st);
+      if (!s) s = upload(P, B->base, &B->d_base, st);
+      if (!s && (hipHostMalloc((void**)&B->h_stage, (size_t)3 * n * sizeof(void*), hipHostMallocDefault) != hipSuccess ||
+                 hipEventCreateWithFlags(&B->ev_stage, hipEventDisableTiming) != hipSuccess ||
+                 hipEventRecord(B->ev_stage, st) != hipSuccess))
+        s = fail(AFMM_E_DEVICE, "batch pointer staging");
+    }
+    // capture: gather -> solve -> scatter, replayed by afmm_batch_solve
+    if (!s) {
+      if (hipStreamSynchronize(st) != hipSuccess ||
+          hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking) != hipSuccess)
+        s = fail(AFMM_E_DEVICE, "batch stream creation failed");
+    }
+    if (!s) s = capture_batch(B);
+    if (s) {
+      free_batch(B);
+      delete B;
+      return s;
+    }
+  } catch (...) {
     free_batch(B);
     delete B;
-    return s;
+    throw;
   }
   *out = B;
   return AFMM_OK;
 }
 
-extern "C" afmm_status afmm_batch_solve(afmm_batch* B, const double* const* d_mass, double* const* d_phi,
+static afmm_status afmm_batch_solve_impl(afmm_batch* B, const double* const* d_mass, double* const* d_phi,
                                         double* const* d_acc, void* hip_stream) {
   if (!B || !d_mass || !d_phi || !d_acc) return fail(AFMM_E_INVALID_ARG, "null argument");
   if (B->plan->dead) return fail(AFMM_E_DEVICE, "batch is unusable after an earlier device error");
@@ -2111,7 +2138,7 @@ extern "C" afmm_status afmm_batch_set_profiling(afmm_batch* B, int32_t enable) {
   return afmm_plan_set_profiling(B->plan, enable);
 }
 
-extern "C" afmm_status afmm_batch_get_profile(afmm_batch* B, afmm_stage_time* out, int32_t cap, int32_t* n_out) {
+static afmm_status afmm_batch_get_profile_impl(afmm_batch* B, afmm_stage_time* out, int32_t cap, int32_t* n_out) {
   if (!B) return fail(AFMM_E_INVALID_ARG, "null batch");
   return afmm_plan_get_profile(B->plan, out, cap, n_out);
 }
@@ -2129,4 +2156,53 @@ extern "C" afmm_status afmm_batch_destroy(afmm_batch* B) {
   free_batch(B);
   delete B;
   return AFMM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI entry points that allocate: exceptions become status codes.
+
+extern "C" afmm_status afmm_plan_create(const afmm_hierarchy* h, const afmm_options* opt, void* hip_stream,
+                                        afmm_plan** out) {
+  return guarded([&] { return afmm_plan_create_impl(h, opt, hip_stream, out); });
+}
+
+extern "C" afmm_status afmm_solve(afmm_plan* P, int32_t level, int32_t icount, const double* d_mass, double* d_phi,
+                                  double* d_acc, void* hip_stream) {
+  return guarded([&] { return afmm_solve_impl(P, level, icount, d_mass, d_phi, d_acc, hip_stream); });
+}
+
+extern "C" afmm_status afmm_plan_get_profile(afmm_plan* P, afmm_stage_time* out, int32_t cap, int32_t* n_out) {
+  return guarded([&] { return afmm_plan_get_profile_impl(P, out, cap, n_out); });
+}
+
+extern "C" afmm_status afmm_plan_autotune(afmm_plan* P, const double* d_mass, double* d_phi, double* d_acc,
+                                          void* hip_stream, afmm_tune_result* out) {
+  return guarded([&] { return afmm_plan_autotune_impl(P, d_mass, d_phi, d_acc, hip_stream, out); });
+}
+
+extern "C" afmm_status afmm_batch_autotune(afmm_batch* B, const double* const* d_mass, double* const* d_phi,
+                                           double* const* d_acc, void* hip_stream, afmm_tune_result* out) {
+  return guarded([&] { return afmm_batch_autotune_impl(B, d_mass, d_phi, d_acc, hip_stream, out); });
+}
+
+extern "C" afmm_status afmm_solve_adjoint(afmm_plan* P, int32_t level, const double* d_phi_bar,
+                                          const double* d_acc_bar, double* d_mass_bar, void* hip_stream) {
+  return guarded([&] { return afmm_solve_adjoint_impl(P, level, d_phi_bar, d_acc_bar, d_mass_bar, hip_stream); });
+}
+
+extern "C" afmm_status afmm_batch_create(afmm_plan* const* plans, int32_t n, void* hip_stream, afmm_batch** out) {
+  return guarded([&] { return afmm_batch_create_impl(plans, n, hip_stream, out); });
+}
+
+extern "C" afmm_status afmm_batch_solve(afmm_batch* B, const double* const* d_mass, double* const* d_phi,
+                                        double* const* d_acc, void* hip_stream) {
+  return guarded([&] { return afmm_batch_solve_impl(B, d_mass, d_phi, d_acc, hip_stream); });
+}
+
+extern "C" afmm_status afmm_batch_get_profile(afmm_batch* B, afmm_stage_time* out, int32_t cap, int32_t* n_out) {
+  return guarded([&] { return afmm_batch_get_profile_impl(B, out, cap, n_out); });
+}
+
+extern "C" afmm_status afmm_hierarchy_check(const afmm_hierarchy* h, const afmm_options* opt, afmm_plan_info* out) {
+  return guarded([&] { return afmm_hierarchy_check_impl(h, opt, out); });
 }

@@ -130,11 +130,16 @@ afmm_status afmm_plan_get_info(const afmm_plan* plan, afmm_plan_info* out);
  * entries are left untouched.  Stream-ordered and asynchronous (no host sync
  * unless AFMM_CHECK_INPUT).
  *   level == AFMM_ALL_LEVELS: synchronous solve, every tree rebuilt from d_mass.
- *   level == l, icount:       Alg. 1 Solve(l, icount): trees j >= l are rebuilt
+ *   level == l, icount >= 1:  Alg. 1 Solve(l, icount): trees j >= l are rebuilt
  *                             from d_mass iff l == levelmin or icount > 1; stale
  *                             trees keep their multipoles and leaf masses; only
- *                             level-l leaves are written.  Returns
- *                             AFMM_E_ATS_ORDER if no tree snapshot exists yet.
+ *                             level-l leaves are written, and only the local
+ *                             expansions of their ancestors are computed (Alg. 2).
+ *                             A solve that rebuilds no tree reuses the device
+ *                             multipoles of the previous solve.  Returns
+ *                             AFMM_E_ATS_ORDER if no tree snapshot exists yet,
+ *                             AFMM_E_INVALID_ARG for icount < 1 or a level
+ *                             outside [levelmin, levelmax].
  * Plans are not thread-safe; one plan per stream.
  */
 afmm_status afmm_solve(afmm_plan* plan, int32_t level, int32_t icount, const double* d_mass,

@@ -1485,6 +1485,7 @@ static afmm_status afmm_solve_impl(afmm_plan* P, int32_t level, int32_t icount, 
   const int lmin = T.levelmin[0], lmax = T.levelmax[0];
   if (level != AFMM_ALL_LEVELS && (level < lmin || level > lmax))
     return fail(AFMM_E_INVALID_ARG, "level outside [levelmin, levelmax]");
+  if (level != AFMM_ALL_LEVELS && icount < 1) return fail(AFMM_E_INVALID_ARG, "icount must be >= 1");
   if (P->opt.flags & AFMM_CHECK_INPUT) {
     void* fl = nullptr;
     if (hipMalloc(&fl, sizeof(int)) != hipSuccess) return fail(AFMM_E_OUT_OF_MEMORY, "flag alloc");

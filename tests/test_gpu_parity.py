@@ -130,6 +130,10 @@ def test_ats_sequence_matches_oracle():
         sel = (lev == l) & h.leaf_mask()
         assert rel_l2(acc[sel], ao[sel]) < 1e-10, (l, ic)
         assert rel_l2(phi[sel], po[sel]) < 1e-10, (l, ic)
+    mt = torch.from_numpy(m).cuda()
+    for bad in ((4, 0), (2, 1), (6, 1)):
+        with pytest.raises(A.AfmmError):
+            plan.solve(mt, level=bad[0], icount=bad[1])
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])

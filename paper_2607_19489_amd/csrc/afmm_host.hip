@@ -1592,8 +1592,6 @@ template <typename SolveFn>
 afmm_status autotune_core(afmm_plan* P, SolveFn solve, hipStream_t st, afmm_tune_result* out) {
   const bool prof = P->profiling;
   P->profiling = true;
-  const int m2l0[2] = {P->m2l_split[0], P->m2l_split[1]};
-  const int m2p0[2] = {P->m2p_split[0], P->m2p_split[1]};
   auto measure = [&](double* kind_ms) -> afmm_status {
     afmm_status s;
     for (int r = 0; r < 4; ++r)
@@ -1626,32 +1624,40 @@ afmm_status autotune_core(afmm_plan* P, SolveFn solve, hipStream_t st, afmm_tune
   for (int k = 0; k < kNumKinds; ++k) before += k0[k];
   static const int cand_m2l[] = {1, 2, 3, 4, 6, 8, 12, 16, 21};
   static const int cand_m2p[] = {1, 2, 3, 4, 6, 8};
-  double best_l[2] = {1e300, 1e300}, best_p[2] = {1e300, 1e300};
-  int arg_l[2] = {m2l0[0], m2l0[1]}, arg_p[2] = {m2p0[0], m2p0[1]};
-  for (int c : cand_m2l) {
-    P->m2l_split[0] = P->m2l_split[1] = c;
-    if ((s = alloc_split_buffers(P))) return s;
-    double km[kNumKinds];
-    if ((s = measure(km))) return s;
-    for (int pr = 0; pr < 2; ++pr) {
+  // One precision at a time (FP32 first), the other held at its current
+  // split: the L2L and leaf kernels sum the partials of both precisions, so a
+  // joint sweep would let the larger launch decide the smaller one's split.
+  int ncand = 0;
+  for (int pr = 1; pr >= 0; --pr) {
+    if (P->m2l_all[pr].ntiles == 0) continue;
+    double best = 1e300;
+    int arg = P->m2l_split[pr];
+    for (int c : cand_m2l) {
+      P->m2l_split[pr] = c;
+      if ((s = alloc_split_buffers(P))) return s;
+      double km[kNumKinds];
+      if ((s = measure(km))) return s;
+      ++ncand;
       const double t = km[pr ? kM2L32 : kM2L64] + km[kL2L];
-      if (t < best_l[pr]) best_l[pr] = t, arg_l[pr] = c;
+      if (t < best) best = t, arg = c;
     }
+    P->m2l_split[pr] = arg;
   }
-  P->m2l_split[0] = arg_l[0];
-  P->m2l_split[1] = arg_l[1];
-  for (int c : cand_m2p) {
-    P->m2p_split[0] = P->m2p_split[1] = c;
-    if ((s = alloc_split_buffers(P))) return s;
-    double km[kNumKinds];
-    if ((s = measure(km))) return s;
-    for (int pr = 0; pr < 2; ++pr) {
+  for (int pr = 1; pr >= 0; --pr) {
+    if (P->m2p_all[pr].ntiles == 0) continue;
+    double best = 1e300;
+    int arg = P->m2p_split[pr];
+    for (int c : cand_m2p) {
+      P->m2p_split[pr] = c;
+      if ((s = alloc_split_buffers(P))) return s;
+      double km[kNumKinds];
+      if ((s = measure(km))) return s;
+      ++ncand;
       const double t = km[pr ? kM2P32 : kM2P64] + km[pr ? kLeaf32 : kLeaf64];
-      if (t < best_p[pr]) best_p[pr] = t, arg_p[pr] = c;
+      if (t < best) best = t, arg = c;
     }
+    P->m2p_split[pr] = arg;
   }
-  P->m2p_split[0] = arg_p[0];
-  P->m2p_split[1] = arg_p[1];
   if ((s = alloc_split_buffers(P))) return s;
   double k1[kNumKinds];
   if ((s = measure(k1))) return s;
@@ -1665,7 +1671,7 @@ afmm_status autotune_core(afmm_plan* P, SolveFn solve, hipStream_t st, afmm_tune
     }
     out->ms_before = before;
     out->ms_after = after;
-    out->candidates = (int32_t)(sizeof(cand_m2l) / sizeof(int) + sizeof(cand_m2p) / sizeof(int));
+    out->candidates = ncand;
   }
   return AFMM_OK;
 }

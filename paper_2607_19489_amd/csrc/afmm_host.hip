@@ -455,6 +455,7 @@ struct HostTables {
   std::vector<int16_t> adj_m2p_off, adj_m2l_off;
   std::vector<int32_t> l2lT_start, l2lT_list;
   std::vector<double> l2lT_w;
+  std::vector<double> nearA;        // [2][near_ksteps][64] near-field operator (A lane order)
 };
 
 static long double ipow(long double x, int n) {
@@ -545,6 +546,48 @@ static void build_tables(int p, HostTables& H) {
             (double)(-0.25L * ipow(u[0], c[0]) * ipow(u[1], c[1]) * ipow(u[2], c[2]) / (fact(c[0]) * fact(c[1]) * fact(c[2])));
       }
     }
+  }
+  // Near-field operator of a group (target-level units): P2P kernel values
+  // phi~ = -1/|R|, a~ = -R/|R|^3 at R = target - source for the 216 same-level
+  // candidates (the target itself excluded) and the 27 coarse neighbours, then
+  // the L2P weights.  Row 16 t + (lane & 15), column 4 kb + (lane >> 4).
+  {
+    const int NKB = near_ksteps(p);
+    H.nearA.assign((size_t)2 * NKB * 64, 0.0);
+    for (int t = 0; t < 2; ++t)
+      for (int kb = 0; kb < NKB; ++kb)
+        for (int lane = 0; lane < 64; ++lane) {
+          const int R = 16 * t + (lane & 15), k = 4 * kb + (lane >> 4);
+          const int c = R >> 3, o = R & 7;
+          double v = 0.0;
+          long double r[3];
+          bool pair = false;
+          if (k < kNearLeafCols) {
+            const int e = k >> 3, op = k & 7;
+            if (!(e == 13 && op == o)) {
+              for (int d = 0; d < 3; ++d) {
+                const int ed = (d == 0 ? e % 3 : d == 1 ? (e / 3) % 3 : e / 9) - 1;
+                r[d] = (long double)(((o >> d) & 1) - 2 * ed - ((op >> d) & 1));
+              }
+              pair = true;
+            }
+          } else if (k < kNearLeafCols + kNearCoarseCols) {
+            const int e = k - kNearLeafCols;
+            for (int d = 0; d < 3; ++d) {
+              const int ed = (d == 0 ? e % 3 : d == 1 ? (e / 3) % 3 : e / 9) - 1;
+              r[d] = (long double)((o >> d) & 1) - 0.5L - 2.0L * ed;
+            }
+            pair = true;
+          } else if (k < kNearLeafCols + kNearCoarseCols + K) {
+            v = H.l2p[((size_t)o * 4 + c) * K + (k - kNearLeafCols - kNearCoarseCols)];
+          }
+          if (pair) {
+            const long double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+            const long double inv = 1.0L / std::sqrt(r2);
+            v = (double)(c == 0 ? -inv : -r[c - 1] * inv * inv * inv);
+          }
+          H.nearA[((size_t)t * NKB + kb) * 64 + lane] = v;
+        }
   }
   // M2M (upward) entries per coefficient a: k <= a, weight C(a,k) 4^-|a-k| 2^-|k|,
   // sign pattern = parity of a - k (applied through the signed child sums)
@@ -1082,7 +1125,10 @@ static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
     if ((s = upload(P, T.nmgrp[l], &P->d_nmgrp[l], st))) return s;
     if (!T.nmgrp[l].empty()) {
       const size_t es = (mixed && (l - 1) > f64) ? sizeof(float) : sizeof(double);
-      if ((s = dev_alloc(P, &P->d_nmp[l], (size_t)T.lv[l - 1].nref() * 32 * es))) return s;
+      // groups without refined near candidates are never written: zero once
+      const size_t bytes = (size_t)T.lv[l - 1].nref() * 32 * es;
+      if ((s = dev_alloc(P, &P->d_nmp[l], bytes))) return s;
+      if (hipMemsetAsync(P->d_nmp[l], 0, bytes, st) != hipSuccess) return fail(AFMM_E_DEVICE, "near partial clear");
     }
   }
   HostTables& H = P->tabs;
@@ -1150,6 +1196,19 @@ static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
   };
   if ((s = upload_conv<double>(P, dstage(8), &P->t64.Dstage, st))) return s;
   if (mixed && (s = upload_conv<float>(P, dstage(4), &P->t32.Dstage, st))) return s;
+  // near-field operator regrouped into 16-byte vectors of consecutive MFMA
+  // steps per lane: [t][kb / VW][lane][kb % VW]
+  auto near_vec = [&](int bytes) {
+    const int NKB = near_ksteps(P->opt.p), vw = 16 / bytes;
+    std::vector<double> v(H.nearA.size());
+    for (int t = 0; t < 2; ++t)
+      for (int kb = 0; kb < NKB; ++kb)
+        for (int lane = 0; lane < 64; ++lane)
+          v[(((size_t)t * (NKB / vw) + kb / vw) * 64 + lane) * vw + kb % vw] = H.nearA[((size_t)t * NKB + kb) * 64 + lane];
+    return v;
+  };
+  if ((s = upload_conv<double>(P, near_vec(8), &P->t64.nearA, st))) return s;
+  if (mixed && (s = upload_conv<float>(P, near_vec(4), &P->t32.nearA, st))) return s;
   if ((s = upload_conv<double>(P, H.Dsame, &P->t64.Dsame, st)) ||
       (s = upload_conv<double>(P, H.cfac2, &P->t64.cfac2, st)) || (s = upload_conv<double>(P, H.cfacn, &P->t64.cfacn, st)) ||
       (s = upload_conv<double>(P, H.l2lw, &P->t64.l2lw, st)) || (s = upload_conv<double>(P, H.l2p, &P->t64.l2p, st)))
@@ -1460,8 +1519,8 @@ static afmm_status run_solve(afmm_plan* P, const double* msrc, int fmax, int lo,
     hipEvent_t a = prof_begin(P, st);
     const int nm = (int)T.nmgrp[l].size();
     if (nm > 0 && (s = dev_check(P,
-                                 launch_near_m2p(p, fp32, P->d_nmgrp[l], nm, P->lv[l - 1], P->lv[l], P->t32, P->t64,
-                                                 P->d_nmp[l], st),
+                                 launch_near_m2p(p, fp32, P->d_nmgrp[l], nm, P->lv[l - 1], P->lv[l], lvp, P->t32,
+                                                 P->t64, P->d_nmp[l], st),
                                  "near m2p")))
       return s;
     if ((s = dev_check(P,

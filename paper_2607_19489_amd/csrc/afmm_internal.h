@@ -72,6 +72,20 @@ __host__ __device__ constexpr int dstage_len(int p, int bytes) {
   return (8 * dstage_ks(p) + 1 + 64 * (16 / bytes) - 1) / (64 * (16 / bytes)) * (64 * (16 / bytes));
 }
 
+// Near field of one group as a fixed linear map (Sec. 3.2, Alg. 4): the 8
+// targets (rows c * 8 + o, c = phi, ax, ay, az) take P2P from the 216 children
+// of the father's 27 neighbours (columns 8 e + o'), P2P from the 27
+// neighbours themselves when they are leaves one level coarser (columns
+// 216 + e), and L2P from the father's local expansion (columns 243 + b).
+// Columns are padded to whole 16-byte vectors of MFMA steps for both
+// precisions; the operator is stored per lane of the 16x16x4 A operand:
+// element [t][kb / VW][lane][kb % VW] is row 16 t + (lane & 15), column
+// 4 kb + (lane >> 4), VW = 16 / bytes.
+constexpr int kNearLeafCols = 216;
+constexpr int kNearCoarseCols = 27;
+__host__ __device__ constexpr int near_cols(int p) { return (kNearLeafCols + kNearCoarseCols + nmi(p) + 15) / 16 * 16; }
+__host__ __device__ constexpr int near_ksteps(int p) { return near_cols(p) / 4; }
+
 // Per-level device view.  Level l holds the children of the refined cells of
 // level l - 1 in Morton order, so cell index c has father refined rank c >> 3
 // and octant c & 7 (o = ox + 2 oy + 4 oz), and refined rank r owns children
@@ -113,6 +127,7 @@ struct TablesDev {
   const T* cfacn = nullptr;   // [K] 2^-|a|: same-level M2P from the source copies
   const T* l2lw = nullptr;    // [8][p+1][K] L2L weights 2^(-1-|b|) u^g/g! per child octant and |b|
   const T* l2p = nullptr;     // [8][4][K] L2P weights (phi, ax, ay, az) per child octant
+  const T* nearA = nullptr;   // [2][near_ksteps / VW][64][VW] near-field operator, MFMA A layout
 };
 
 struct CommonDev {
@@ -207,6 +222,7 @@ hipError_t launch_near(int p, bool fp32, int l, const int32_t* grp, int ngrp, co
 // Near-field M2P from the refined level-l cells among the near candidates of
 // the groups `grp` (those that have any): partial [nref(l-1)][c * 8 + o].
 hipError_t launch_near_m2p(int p, bool fp32, const int32_t* grp, int ngrp, const LevelDev& lv1, const LevelDev& lv0,
-                           const TablesDev<float>& t32, const TablesDev<double>& t64, void* nmp, hipStream_t st);
+                           const LevelDev& lvp, const TablesDev<float>& t32, const TablesDev<double>& t64, void* nmp,
+                           hipStream_t st);
 
 }  // namespace afmm

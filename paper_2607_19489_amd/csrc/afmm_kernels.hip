@@ -783,198 +783,220 @@ __global__ __launch_bounds__(kBlock) void k_m2l_mfma(const int32_t* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Leaf evaluation at level l, VALU part: far field (L2P of L[F]), near field
-// (P2P from level-(l-1) and level-l leaves) and nearest field (P2P from the
-// children of refined level-l cells touching the target), plus the partials of
-// the MFMA intermediate field and of the near-field M2P from refined level-l
-// cells not touching the target (k_near_m2p, for the groups that have such
-// candidates); the fields are summed in FP64 and scaled to physical units.
-// The 8 targets of a group share their 216 candidate near cells (children of
-// F's 27 neighbours, or the neighbour itself when it is a leaf): they are
-// resolved once per block into LDS (kind, mass, refined rank), then thread
-// (o = t & 7, j = t >> 3) takes target child o and every 32nd candidate from
-// j (the lanes of a wave share candidates, so the branches on the candidate
-// kind rarely diverge); partial sums are reduced by shuffles within a wave
-// and through LDS across the 4 waves.
-template <typename T, int P>
-__global__ __launch_bounds__(kBlock) void k_near(const int32_t* __restrict__ grp, LevelDev lv1, LevelDev lv0,
-                                                 LevelDev lvp, TablesDev<T> tb, const T* __restrict__ Lpar,
-                                                 const T* __restrict__ part, const T* __restrict__ nmp,
-                                                 double G, double h, double* __restrict__ phi,
-                                                 double* __restrict__ acc) {
+// Leaf evaluation at level l (Alg. 4): far field (L2P of L[F]) and near field
+// (P2P from the level-l leaves among the children of F's 27 neighbours and
+// from the neighbours that are leaves one level coarser).  For every group
+// these are one fixed linear map of the same gathered inputs (the candidates'
+// masses, L[F]), so 16 groups are one product [32 x near_cols] . [near_cols x
+// 16] on 16x16x4 MFMA: rows c * 8 + o (phi, ax, ay, az of child o), columns
+// in the order of the operator table nearA.  Lane (n = lane & 15, g = lane >>
+// 4) gathers column n's inputs for steps 4 kb + g straight into registers.
+// The intermediate-field partials (k_m2p) and the partial of the refined near
+// cells (near M2P and nearest-field P2P, k_near_m2p; zero for groups without
+// such cells) are added in FP64 and the sums scaled to physical units.  One
+// block per 16 groups of the level's group list; its 4 waves take a quarter
+// of the operator columns each (more loads in flight per tile), and wave 0
+// adds the other waves' accumulators in order.
+template <typename T, int P, int W>
+__device__ inline void near_part(int lane, int F, const int* __restrict__ sCB, gptr<double> mass0,
+                                 gptr<double> mass1, const T* __restrict__ Lpar, const T* __restrict__ nearA,
+                                 typename Acc4<T>::type& acc0, typename Acc4<T>::type& acc1) {
+  using V = typename Vec16<T>::type;
   constexpr int K = nmi(P);
-  enum { kNone = 0, kCoarse = 1, kLeaf = 2, kRefined = 3 };
-  __shared__ int s_hasref;
-  __shared__ int s_kind[216];
-  __shared__ int s_rn[216];
-  __shared__ T s_m[216];
-  __shared__ T s_L[K];
-  __shared__ T s_red[kBlock / 64][12][8];
-  const int F = grp[blockIdx.x];
-  const int t = threadIdx.x;
-  const int o = t & 7, j = t >> 3;
-  if (t == 0) s_hasref = 0;
-  __syncthreads();
-  if (t < 216) {
-    const int e = t >> 3, op = t & 7;
-    const int q = lv1.nbr[(size_t)F * 27 + e];
-    int kind = kNone, rn = -1;
-    T m = 0;
-    if (q >= 0) {
-      const int rq = lv1.rank[q];
-      if (rq < 0) {
-        if (op == 0) {
-          kind = kCoarse;
-          m = (T)lv1.mass[q];
-        }
-      } else {
-        const int n = 8 * rq + op;
-        rn = lv0.rank[n];
-        if (rn < 0) {
-          kind = kLeaf;  // a target skips itself (s_rn holds the cell index)
-          m = (T)lv0.mass[n];
-          rn = n;
-        } else {
-          kind = kRefined;
-          s_hasref = 1;
-        }
+  constexpr int VW = 16 / (int)sizeof(T);
+  constexpr int NQ = near_ksteps(P) / VW;
+  constexpr int Q0 = W * NQ / 4, Q1 = (W + 1) * NQ / 4;
+  constexpr int C0 = kNearLeafCols, C1 = kNearLeafCols + kNearCoarseCols;
+  const int n = lane & 15, g = lane >> 4;
+  // B: column n's inputs for steps 4 kb + g (refined cells hold mass 0; every
+  // load has a valid address, the value is selected afterwards)
+  T bv[(Q1 - Q0) * VW + 1];
+#pragma unroll
+  for (int i = 0; i < (Q1 - Q0) * VW; ++i) {
+    const int k = 4 * (Q0 * VW + i) + g;
+    T v = 0;
+    if (k < C0) {
+      const int cb = sCB[n * 27 + (k >> 3)];
+      const double m = mass0[cb >= 0 ? cb + (k & 7) : 0];
+      v = cb >= 0 ? (T)m : (T)0;
+    } else if (k < C1) {
+      const int cb = sCB[n * 27 + (k - C0)];
+      const double m = mass1[cb <= -2 ? -2 - cb : 0];
+      v = cb <= -2 ? (T)m : (T)0;
+    } else if (k < C1 + K) {
+      if (Lpar) {
+        const T l = as_global(Lpar)[(size_t)(F >= 0 ? F : 0) * K + (k - C1)];
+        v = F >= 0 ? l : (T)0;
       }
     }
-    s_kind[t] = kind;
-    s_rn[t] = rn;
-    s_m[t] = m;
+    bv[i] = v;
   }
-  if (Lpar)
-    for (int b = t; b < K; b += kBlock) s_L[b] = Lpar[(size_t)F * K + b];
-  __syncthreads();
-  const int cell = 8 * F + o;
-  T far[4] = {0, 0, 0, 0}, nea[4] = {0, 0, 0, 0}, nst[4] = {0, 0, 0, 0};
-  const T ox = (T)o_axis(o, 0), oy = (T)o_axis(o, 1), oz = (T)o_axis(o, 2);
-  if (Lpar) {
-    const T* wl = tb.l2p + (size_t)o * 4 * K;
-    for (int b = j; b < K; b += 32) {
-      const T v = s_L[b];
-      far[0] += wl[b] * v;
-      far[1] += wl[K + b] * v;
-      far[2] += wl[2 * K + b] * v;
-      far[3] += wl[3 * K + b] * v;
+  gptr<V> A = (gptr<V>)as_global(nearA);
+#pragma unroll
+  for (int q = Q0; q < Q1; ++q) {
+    const V a0 = A[(size_t)q * 64 + lane];
+    const V a1 = A[(size_t)(NQ + q) * 64 + lane];
+#pragma unroll
+    for (int j = 0; j < VW; ++j) {
+      acc0 = mfma16(a0[j], bv[(q - Q0) * VW + j], acc0);
+      acc1 = mfma16(a1[j], bv[(q - Q0) * VW + j], acc1);
     }
-  }
-  for (int k = j; k < 216; k += 32) {
-    const int kind = s_kind[k];
-    if (kind == kNone) continue;
-    const int e = k >> 3, op = k & 7;
-    const int ex = e_axis(e, 0), ey = e_axis(e, 1), ez = e_axis(e, 2);
-    if (kind == kCoarse) {
-      p2p<T>(ox - (T)0.5 - (T)(2 * ex), oy - (T)0.5 - (T)(2 * ey), oz - (T)0.5 - (T)(2 * ez), s_m[k], nea);
-      continue;
-    }
-    const int tx = o_axis(o, 0) - 2 * ex - o_axis(op, 0);
-    const int ty = o_axis(o, 1) - 2 * ey - o_axis(op, 1);
-    const int tz = o_axis(o, 2) - 2 * ez - o_axis(op, 2);
-    if (kind == kLeaf) {
-      if (s_rn[k] != cell) p2p<T>((T)tx, (T)ty, (T)tz, s_m[k], nea);
-      continue;
-    }
-    const int rn = s_rn[k];
-    if (max(abs(tx), max(abs(ty), abs(tz))) <= 1) {
-      for (int o2 = 0; o2 < 8; ++o2) {
-        const int kc = 8 * rn + o2;
-        p2p<T>((T)tx - ((T)o_axis(o2, 0) - (T)0.5) * (T)0.5, (T)ty - ((T)o_axis(o2, 1) - (T)0.5) * (T)0.5,
-               (T)tz - ((T)o_axis(o2, 2) - (T)0.5) * (T)0.5, (T)lvp.mass[kc], nst);
-      }
-    }
-  }
-  T red[12];
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    red[c] = far[c];
-    red[4 + c] = nea[c];
-    red[8 + c] = nst[c];
-  }
-#pragma unroll
-  for (int w = 8; w <= 32; w <<= 1)
-#pragma unroll
-    for (int c = 0; c < 12; ++c) red[c] += __shfl_xor(red[c], w, 64);
-  if ((t & 63) < 8)
-#pragma unroll
-    for (int c = 0; c < 12; ++c) s_red[t >> 6][c][o] = red[c];
-  __syncthreads();
-  if (t < 8 && lv0.rank[cell] < 0) {
-    double out[4] = {0, 0, 0, 0};
-#pragma unroll
-    for (int c = 0; c < 12; ++c) {
-      T v = 0;
-#pragma unroll
-      for (int w = 0; w < kBlock / 64; ++w) v += s_red[w][c][o];
-      out[c & 3] += (double)v;
-    }
-    if (part)
-      for (int sp = 0; sp < lv1.npart; ++sp) {
-        const T* pp = part + ((size_t)sp * lv1.nref + F) * 32;
-        for (int c = 0; c < 4; ++c) out[c] += (double)pp[c * 8 + o];
-      }
-    if (s_hasref)
-      for (int c = 0; c < 4; ++c) out[c] += (double)nmp[(size_t)F * 32 + c * 8 + o];
-    const int sl = lv0.slot[cell];
-    const double sp = G / h, sa = G / (h * h);
-    phi[sl] = sp * out[0];
-    acc[3 * (size_t)sl + 0] = sa * out[1];
-    acc[3 * (size_t)sl + 1] = sa * out[2];
-    acc[3 * (size_t)sl + 2] = sa * out[3];
   }
 }
 
-// Near-field M2P from the refined level-l cells among the near candidates of
-// a group (the children of F's 27 neighbours that are refined and do not
-// touch the target): one wave per group, four groups per block.  The wave
-// compacts its refined candidates into LDS; lane (o = lane & 7, j = lane >> 3)
-// takes target o and every 8th candidate, partial sums are reduced by
-// shuffles and lanes 0..7 write nmp[F][c * 8 + o] (target-level units), read
-// by k_near.  Every child o is evaluated (refined ones are not read).
 template <typename T, int P>
-__global__ __launch_bounds__(kBlock) void k_near_m2p(const int32_t* __restrict__ grp, int ngrp, LevelDev lv1,
-                                                     LevelDev lv0, const T* __restrict__ Dsame,
-                                                     const T* __restrict__ S0, T* __restrict__ nmp) {
-  constexpr int K = nmi(P);
-  constexpr int NW = kBlock / 64;
-  __shared__ int s_c[NW][216];
-  __shared__ int s_rn[NW][216];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int gi = blockIdx.x * NW + w;
-  if (gi >= ngrp) return;
-  const int F = grp[gi];
-  int nlist = 0;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int t = lane + 64 * r;
-    int rn = -1;
-    if (t < 216) {
-      const int q = lv1.nbr[(size_t)F * 27 + (t >> 3)];
+__global__ __launch_bounds__(kBlock) void k_near(const int32_t* __restrict__ grp, int ngrp, LevelDev lv1, LevelDev lv0,
+                                                 const T* __restrict__ nearA, const T* __restrict__ Lpar,
+                                                 const T* __restrict__ part, const T* __restrict__ nmp, double G,
+                                                 double h, double* __restrict__ phi, double* __restrict__ acc) {
+  static_assert(kBlock == 256, "four waves split the operator columns");
+  static_assert(near_ksteps(P) % (16 / (int)sizeof(T)) == 0, "near operator vectors");
+  __shared__ int sF[16];
+  __shared__ int sCB[16 * 27];
+  __shared__ T sAcc[3][8][64];
+  const int ntiles = (ngrp + 15) / 16;
+  const int tile = xcd_tile(ntiles);
+  if (tile >= ntiles) return;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  if (t < 16) sF[t] = 16 * tile + t < ngrp ? grp[16 * tile + t] : -1;
+  __syncthreads();
+  // per group and neighbour e: child base 8 rq (refined neighbour), -2 - q
+  // (leaf neighbour q), or -1 (outside the box)
+  gptr<int32_t> nbr1 = as_global(lv1.nbr), rank1 = as_global(lv1.rank);
+  for (int i = t; i < 16 * 27; i += kBlock) {
+    const int c = i / 27, e = i - 27 * c;
+    const int F = sF[c];
+    int v = -1;
+    if (F >= 0) {
+      const int q = nbr1[(size_t)F * 27 + e];
       if (q >= 0) {
-        const int rq = lv1.rank[q];
-        if (rq >= 0) rn = lv0.rank[8 * rq + (t & 7)];
+        const int rq = rank1[q];
+        v = rq >= 0 ? 8 * rq : -2 - q;
       }
     }
-    const uint64_t m = __ballot(rn >= 0);
-    if (rn >= 0) {
-      const int pos = nlist + __popcll(m & ((1ull << lane) - 1ull));
-      s_c[w][pos] = t;
-      s_rn[w][pos] = rn;
-    }
-    nlist += __popcll(m);
+    sCB[i] = v;
   }
-  wave_sync();
-  const int o = lane & 7, j = lane >> 3;
+  __syncthreads();
+  const int n = lane & 15, g = lane >> 4;
+  const int F = sF[n];
+  gptr<double> mass0 = as_global(lv0.mass), mass1 = as_global(lv1.mass);
+  typename Acc4<T>::type acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+  switch (w) {
+    case 0: near_part<T, P, 0>(lane, F, sCB, mass0, mass1, Lpar, nearA, acc0, acc1); break;
+    case 1: near_part<T, P, 1>(lane, F, sCB, mass0, mass1, Lpar, nearA, acc0, acc1); break;
+    case 2: near_part<T, P, 2>(lane, F, sCB, mass0, mass1, Lpar, nearA, acc0, acc1); break;
+    default: near_part<T, P, 3>(lane, F, sCB, mass0, mass1, Lpar, nearA, acc0, acc1); break;
+  }
+  if (w > 0)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      sAcc[w - 1][r][lane] = acc0[r];
+      sAcc[w - 1][4 + r][lane] = acc1[r];
+    }
+  __syncthreads();
+  if (w > 0 || F < 0) return;
+#pragma unroll
+  for (int v = 0; v < 3; ++v)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      acc0[r] += sAcc[v][r][lane];
+      acc1[r] += sAcc[v][4 + r][lane];
+    }
+  gptr<int32_t> rank0 = as_global(lv0.rank), slot0 = as_global(lv0.slot);
+  const double sp = G / h, sa = G / (h * h);
+#pragma unroll
+  for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int R = 16 * tt + acc_row<T>(g, r);
+      const int c = R >> 3, cell = 8 * F + (R & 7);
+      if (rank0[cell] >= 0) continue;  // refined child: not a target
+      double v = (double)(tt ? acc1[r] : acc0[r]);
+      if (part)
+        for (int s = 0; s < lv1.npart; ++s) v += (double)as_global(part)[((size_t)s * lv1.nref + F) * 32 + R];
+      if (nmp) v += (double)as_global(nmp)[(size_t)F * 32 + R];
+      const int sl = slot0[cell];
+      if (c == 0)
+        phi[sl] = sp * v;
+      else
+        acc[3 * (size_t)sl + c - 1] = sa * v;
+    }
+}
+
+// Refined level-l cells among the near candidates of a group (children of
+// F's 27 neighbours): M2P from those that do not touch the target (Alg. 4) and
+// P2P from the 8 children of those that do (nearest field, Sec. 3.2; the
+// children are leaves by the grading rule).  One block per group: the refined
+// candidates are compacted into LDS (ballot per wave, in candidate order),
+// thread (o = t & 7, j = t >> 3) takes target o and every 32nd candidate from
+// j, first for the M2P and then, in a separate loop, for the nearest field
+// (so that threads on one path do not wait for the other); partial sums are
+// reduced by shuffles within a wave and in order across the waves, and
+// threads 0..7 write nmp[F][c * 8 + o] (target-level units), read by k_near.
+// Every child o is evaluated (refined ones are not read).
+template <typename T, int P>
+__global__ __launch_bounds__(kBlock) void k_near_m2p(const int32_t* __restrict__ grp, int ngrp, LevelDev lv1,
+                                                     LevelDev lv0, LevelDev lvp, const T* __restrict__ Dsame,
+                                                     const T* __restrict__ S0, T* __restrict__ nmp) {
+  static_assert(kBlock == 256, "one candidate per thread in the compaction");
+  constexpr int K = nmi(P);
+  constexpr int NW = kBlock / 64;
+  constexpr int NJ = kBlock / 8;
+  __shared__ int s_c[216];
+  __shared__ int s_rn[216];
+  __shared__ int s_cnt[NW];
+  __shared__ T s_red[NW][4][8];
+  const int gi = blockIdx.x;
+  if (gi >= ngrp) return;
+  const int F = grp[gi];
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  int rn = -1;
+  if (t < 216) {
+    const int q = lv1.nbr[(size_t)F * 27 + (t >> 3)];
+    if (q >= 0) {
+      const int rq = lv1.rank[q];
+      if (rq >= 0) rn = lv0.rank[8 * rq + (t & 7)];
+    }
+  }
+  const uint64_t m = __ballot(rn >= 0);
+  if (lane == 0) s_cnt[w] = __popcll(m);
+  __syncthreads();
+  int base = 0, nlist = 0;
+#pragma unroll
+  for (int v = 0; v < NW; ++v) {
+    base += v < w ? s_cnt[v] : 0;
+    nlist += s_cnt[v];
+  }
+  if (rn >= 0) {
+    const int pos = base + __popcll(m & ((1ull << lane) - 1ull));
+    s_c[pos] = t;
+    s_rn[pos] = rn;
+  }
+  __syncthreads();
+  const int o = t & 7, j = t >> 3;
   T sum[4] = {0, 0, 0, 0};
-  for (int i = j; i < nlist; i += 8) {
-    const int t = s_c[w][i], e = t >> 3, op = t & 7;
+  for (int i = j; i < nlist; i += NJ) {
+    const int c = s_c[i], e = c >> 3, op = c & 7;
     const int tx = o_axis(o, 0) - 2 * e_axis(e, 0) - o_axis(op, 0);
     const int ty = o_axis(o, 1) - 2 * e_axis(e, 1) - o_axis(op, 1);
     const int tz = o_axis(o, 2) - 2 * e_axis(e, 2) - o_axis(op, 2);
     if (max(abs(tx), max(abs(ty), abs(tz))) <= 1) continue;
-    m2p_row<T, P>(Dsame + (size_t)d_index(tx, ty, tz) * K, S0 + (size_t)s_rn[w][i] * src_row(P, (int)sizeof(T)),
-                  sum);
+    m2p_row<T, P>(Dsame + (size_t)d_index(tx, ty, tz) * K, S0 + (size_t)s_rn[i] * src_row(P, (int)sizeof(T)), sum);
+  }
+  gptr<double> massp = as_global(lvp.mass);
+  for (int i = j; i < nlist; i += NJ) {
+    const int c = s_c[i], e = c >> 3, op = c & 7;
+    const int tx = o_axis(o, 0) - 2 * e_axis(e, 0) - o_axis(op, 0);
+    const int ty = o_axis(o, 1) - 2 * e_axis(e, 1) - o_axis(op, 1);
+    const int tz = o_axis(o, 2) - 2 * e_axis(e, 2) - o_axis(op, 2);
+    if (max(abs(tx), max(abs(ty), abs(tz))) > 1) continue;
+    double mc[8];
+#pragma unroll
+    for (int o2 = 0; o2 < 8; ++o2) mc[o2] = massp[8 * s_rn[i] + o2];
+#pragma unroll
+    for (int o2 = 0; o2 < 8; ++o2)
+      p2p<T>((T)tx - ((T)o_axis(o2, 0) - (T)0.5) * (T)0.5, (T)ty - ((T)o_axis(o2, 1) - (T)0.5) * (T)0.5,
+             (T)tz - ((T)o_axis(o2, 2) - (T)0.5) * (T)0.5, (T)mc[o2], sum);
   }
 #pragma unroll
   for (int d = 8; d <= 32; d <<= 1)
@@ -982,7 +1004,16 @@ __global__ __launch_bounds__(kBlock) void k_near_m2p(const int32_t* __restrict__
     for (int c = 0; c < 4; ++c) sum[c] += __shfl_xor(sum[c], d, 64);
   if (lane < 8)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) nmp[(size_t)F * 32 + c * 8 + o] = sum[c];
+    for (int c = 0; c < 4; ++c) s_red[w][c][o] = sum[c];
+  __syncthreads();
+  if (t < 8)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      T v = 0;
+#pragma unroll
+      for (int u = 0; u < NW; ++u) v += s_red[u][c][o];
+      nmp[(size_t)F * 32 + c * 8 + o] = v;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1083,14 +1114,15 @@ hipError_t launch_l2l(int p, bool fp32, bool parent_fp32, bool has_parent, int n
 
 template <typename T>
 static hipError_t near_dispatch(int p, int ngrp, const int32_t* grp, const LevelDev& lv1, const LevelDev& lv0,
-                                const LevelDev& lvp, const TablesDev<T>& tb, const T* Lpar, const T* part,
-                                const T* nmp, double G, double h, double* phi, double* acc, hipStream_t st) {
-  const dim3 grid(ngrp), block(kBlock);
+                                const TablesDev<T>& tb, const T* Lpar, const T* part, const T* nmp, double G,
+                                double h, double* phi, double* acc, hipStream_t st) {
+  const int ntiles = (ngrp + 15) / 16;
+  const dim3 grid(8 * ((ntiles + 7) / 8)), block(kBlock);
   switch (p) {
 #define AFMM_NEAR(PP)                                                                                         \
   case PP:                                                                                                    \
-    hipLaunchKernelGGL((k_near<T, PP>), grid, block, 0, st, grp, lv1, lv0, lvp, tb, Lpar, part, nmp, G, h,   \
-                       phi, acc);                                                                             \
+    hipLaunchKernelGGL((k_near<T, PP>), grid, block, 0, st, grp, ngrp, lv1, lv0, tb.nearA, Lpar, part, nmp,  \
+                       G, h, phi, acc);                                                                       \
     break;
     AFMM_NEAR(1) AFMM_NEAR(2) AFMM_NEAR(3) AFMM_NEAR(4) AFMM_NEAR(5) AFMM_NEAR(6) AFMM_NEAR(7) AFMM_NEAR(8)
 #undef AFMM_NEAR
@@ -1104,23 +1136,24 @@ hipError_t launch_near(int p, bool fp32, int l, const int32_t* grp, int ngrp, co
                        const TablesDev<double>& t64, const CommonDev& cm, const void* part, const void* nmp,
                        double G, double h, double* phi, double* acc, hipStream_t st) {
   (void)cm;
+  (void)lvp;
   if (ngrp == 0) return hipSuccess;
   const bool has_far = (l - 1) >= 3;
   if (fp32)
-    return near_dispatch<float>(p, ngrp, grp, lv1, lv0, lvp, t32, has_far ? lv1.L32 : nullptr, (const float*)part,
+    return near_dispatch<float>(p, ngrp, grp, lv1, lv0, t32, has_far ? lv1.L32 : nullptr, (const float*)part,
                                 (const float*)nmp, G, h, phi, acc, st);
-  return near_dispatch<double>(p, ngrp, grp, lv1, lv0, lvp, t64, has_far ? lv1.L64 : nullptr, (const double*)part,
+  return near_dispatch<double>(p, ngrp, grp, lv1, lv0, t64, has_far ? lv1.L64 : nullptr, (const double*)part,
                                (const double*)nmp, G, h, phi, acc, st);
 }
 
 template <typename T>
 static hipError_t near_m2p_dispatch(int p, const int32_t* grp, int ngrp, const LevelDev& lv1, const LevelDev& lv0,
-                                    const T* Dsame, const T* S0, T* nmp, hipStream_t st) {
-  const dim3 grid((ngrp + kBlock / 64 - 1) / (kBlock / 64)), block(kBlock);
+                                    const LevelDev& lvp, const T* Dsame, const T* S0, T* nmp, hipStream_t st) {
+  const dim3 grid(ngrp), block(kBlock);
   switch (p) {
 #define AFMM_NM2P(PP)                                                                                          \
   case PP:                                                                                                     \
-    hipLaunchKernelGGL((k_near_m2p<T, PP>), grid, block, 0, st, grp, ngrp, lv1, lv0, Dsame, S0, nmp);          \
+    hipLaunchKernelGGL((k_near_m2p<T, PP>), grid, block, 0, st, grp, ngrp, lv1, lv0, lvp, Dsame, S0, nmp);     \
     break;
     AFMM_NM2P(1) AFMM_NM2P(2) AFMM_NM2P(3) AFMM_NM2P(4) AFMM_NM2P(5) AFMM_NM2P(6) AFMM_NM2P(7) AFMM_NM2P(8)
 #undef AFMM_NM2P
@@ -1130,10 +1163,11 @@ static hipError_t near_m2p_dispatch(int p, const int32_t* grp, int ngrp, const L
 }
 
 hipError_t launch_near_m2p(int p, bool fp32, const int32_t* grp, int ngrp, const LevelDev& lv1, const LevelDev& lv0,
-                           const TablesDev<float>& t32, const TablesDev<double>& t64, void* nmp, hipStream_t st) {
+                           const LevelDev& lvp, const TablesDev<float>& t32, const TablesDev<double>& t64, void* nmp,
+                           hipStream_t st) {
   if (ngrp == 0) return hipSuccess;
-  if (fp32) return near_m2p_dispatch<float>(p, grp, ngrp, lv1, lv0, t32.Dsame, lv0.S32, (float*)nmp, st);
-  return near_m2p_dispatch<double>(p, grp, ngrp, lv1, lv0, t64.Dsame, lv0.Sc64, (double*)nmp, st);
+  if (fp32) return near_m2p_dispatch<float>(p, grp, ngrp, lv1, lv0, lvp, t32.Dsame, lv0.S32, (float*)nmp, st);
+  return near_m2p_dispatch<double>(p, grp, ngrp, lv1, lv0, lvp, t64.Dsame, lv0.Sc64, (double*)nmp, st);
 }
 
 }  // namespace afmm

@@ -1103,12 +1103,21 @@ static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
     // source copies: FP32 where an FP32 kernel reads this level (M2L of f = l+1 or
     // M2P of l+1 when l >= f64; near-field M2P of l when l > f64+1), FP64 where an
     // FP64 kernel does (l <= f64 + 1)
+    // Each copy has one extra row of zeros after the nref rows: the MFMA tap
+    // loops read it for a missing or leaf source, so that their loads need no
+    // branch.
     if (mixed && l >= f64) {
-      if ((s = dev_alloc(P, &p, (size_t)D.nref * src_row(P->opt.p, 4) * sizeof(float)))) return s;
+      const size_t row = (size_t)src_row(P->opt.p, 4) * sizeof(float);
+      if ((s = dev_alloc(P, &p, (size_t)(D.nref + 1) * row))) return s;
+      if (hipMemsetAsync((char*)p + (size_t)D.nref * row, 0, row, st) != hipSuccess)
+        return fail(AFMM_E_DEVICE, "zero row of the source copy");
       D.S32 = (float*)p;
     }
     if (!mixed || l <= f64 + 1) {
-      if ((s = dev_alloc(P, &p, (size_t)D.nref * src_row(P->opt.p, 8) * sizeof(double)))) return s;
+      const size_t row = (size_t)src_row(P->opt.p, 8) * sizeof(double);
+      if ((s = dev_alloc(P, &p, (size_t)(D.nref + 1) * row))) return s;
+      if (hipMemsetAsync((char*)p + (size_t)D.nref * row, 0, row, st) != hipSuccess)
+        return fail(AFMM_E_DEVICE, "zero row of the source copy");
       D.Sc64 = (double*)p;
     }
     if (l <= f64) {

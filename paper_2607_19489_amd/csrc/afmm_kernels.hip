@@ -616,31 +616,33 @@ struct M2LStage {
   static constexpr int NVW = (NVB + 3) / 4;                            // per wave
 };
 
-template <typename T, int P>
-__device__ inline void load_bshare(int sr, int lane, int w, gptr<double> mass1, gptr<T> S1,
-                                   typename Vec16<T>::type* vb) {
+// Wave w's share of the B stage of a tap (vectors j in [w NVW, (w+1) NVW) of
+// every lane's run).  Branch-free: a missing or leaf source reads the zero
+// row zrow of the source copy, and wave 0 also loads a mass (cell 0 when the
+// source is no leaf) that store_bshare puts into the monopole slot.
+template <typename T, int P, int W>
+__device__ inline void load_bshare(int sr, int zrow, int lane, gptr<double> mass1, gptr<T> S1,
+                                   typename Vec16<T>::type* vb, double& vm) {
   using TS = TapStage<T, P>;
   using MS = M2LStage<T, P>;
   using V = typename Vec16<T>::type;
+  gptr<T> src = S1 + (size_t)(sr >= 0 ? sr : zrow) * TS::ROW;
 #pragma unroll
   for (int i = 0; i < MS::NVW; ++i) {
-    const int j = w * MS::NVW + i;
-    V v = {};
-    if (j < MS::NVB) {
-      if (sr >= 0) v = *(gptr<V>)(S1 + (size_t)sr * TS::ROW + src_vec(j, lane >> 4, (int)sizeof(T)));
-      else if (sr <= -2 && j == 0 && (lane >> 4) == 0) v[0] = (T)mass1[-2 - sr];
-    }
-    vb[i] = v;
+    constexpr int j0 = W * MS::NVW;
+    if (j0 + i < MS::NVB) vb[i] = *(gptr<V>)(src + src_vec(j0 + i, lane >> 4, (int)sizeof(T)));
   }
+  if (W == 0) vm = mass1[sr <= -2 ? -2 - sr : 0];
 }
 
-template <typename T, int P>
-__device__ inline void store_bshare(T* sB, int lane, int w, const typename Vec16<T>::type* vb) {
+template <typename T, int P, int W>
+__device__ inline void store_bshare(T* sB, int sr, int lane, typename Vec16<T>::type* vb, double vm) {
   using TS = TapStage<T, P>;
   using MS = M2LStage<T, P>;
+  if (W == 0 && sr <= -2 && (lane >> 4) == 0) vb[0][0] = (T)vm;
 #pragma unroll
   for (int i = 0; i < MS::NVW; ++i) {
-    const int j = w * MS::NVW + i;
+    const int j = W * MS::NVW + i;
     if (j < MS::NVB) {
 #pragma unroll
       for (int e = 0; e < TS::VW; ++e) sB[(j * TS::VW + e) * 64 + lane] = vb[i][e];
@@ -648,13 +650,29 @@ __device__ inline void store_bshare(T* sB, int lane, int w, const typename Vec16
   }
 }
 
+// D~ stage copy without a branch around the loads: thread t loads vectors
+// t, t + NTH, ... clamped to the last one (stores skip the extra ones).
+template <typename T, int P, int NTH>
+__device__ inline void load_dstage_nb(int code, const T* __restrict__ Dst, typename Vec16<T>::type* vD) {
+  using TS = TapStage<T, P>;
+  using V = typename Vec16<T>::type;
+  constexpr int NJ = (TS::NDV + NTH - 1) / NTH;
+  const int t = threadIdx.x;
+  gptr<V> src = (gptr<V>)as_global(Dst + (size_t)(code >> 8) * TS::SDP);
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) vD[j] = src[min(t + NTH * j, TS::NDV - 1)];
+}
+
 // One wave's share of an M2L tile: its row tiles (compile-time plan H) over
-// the block's LDS stage of B and of the D~ rows; the wave also loads its share
-// of the next tap's stage while its MFMAs run.
+// the block's LDS stage of B and of the D~ rows.  The stage of tap k + 2 is
+// loaded into registers while the MFMAs of tap k run and stored to LDS after
+// those of tap k + 1 (two register sets, two LDS buffers), so a load has two
+// taps to land; the sources of every tap of the range were resolved into LDS
+// (sSrcT) before the loop.
 template <typename T, int P, int H>
 __device__ inline void m2l_part(const int32_t* __restrict__ tp, int nt, const int16_t* __restrict__ aoff,
-                                const int* sF, const int* sCB, int (*sSrc)[16], T (*sB)[TapStage<T, P>::STP * 64],
-                                T (*sD)[TapStage<T, P>::SDP], gptr<int32_t> rank1, gptr<double> mass1,
+                                const int* sF, const int* sSrcT, T (*sB)[TapStage<T, P>::STP * 64],
+                                T (*sD)[TapStage<T, P>::SDP], int zrow, gptr<double> mass1,
                                 const T* __restrict__ Dst, gptr<T> S1, gptr<int32_t> rank0, gmut<T> Lout) {
   using TS = TapStage<T, P>;
   using MS = M2LStage<T, P>;
@@ -665,7 +683,7 @@ __device__ inline void m2l_part(const int32_t* __restrict__ tp, int nt, const in
   constexpr int NS = PL.steps[H];
   constexpr int KBH = PL.kbmax[H];
   constexpr int ND = (TS::NDV + kBlock - 1) / kBlock;
-  const int t = threadIdx.x, lane = t & 63, krow = lane >> 4;
+  const int t = threadIdx.x, lane = t & 63, krow = lane >> 4, n = lane & 15;
   int off[NS > 0 ? NS : 1];
   {
     int s = 0;
@@ -677,19 +695,28 @@ __device__ inline void m2l_part(const int32_t* __restrict__ tp, int nt, const in
   typename Acc4<T>::type acc[NTH > 0 ? NTH : 1];
 #pragma unroll
   for (int i = 0; i < NTH; ++i) acc[i] = {0, 0, 0, 0};
-  V vD[ND];
-  V vB[MS::NVW];
-  for (int k = 0; k < nt; ++k) {
-    const int b = k & 1;
-    int ncell = -1, nrank = -1;
-    if (k + 2 < nt && t < 16) {
-      ncell = tap_cell(tp[k + 2], t, sCB);
-      if (ncell >= 0) nrank = rank1[ncell];
-    }
-    if (k + 1 < nt) {
-      load_dstage<T, P, kBlock>(tp[k + 1], Dst, vD);
-      load_bshare<T, P>(sSrc[b ^ 1][lane & 15], lane, H, mass1, S1, vB);
-    }
+  // register sets X (odd taps ahead) and Y; tap 1 goes to X first
+  V vDX[ND], vDY[ND], vBX[MS::NVW], vBY[MS::NVW];
+  double vmX = 0, vmY = 0;
+  int srX = -1, srY = -1;
+  // Taps run in pairs; an odd range ends with one empty tap (no source, so B
+  // is zero; its D~ stage repeats the last tap's finite rows), so that both
+  // steps of a pair and every load run unconditionally.
+  const int nt2 = (nt + 1) & ~1;
+  {
+    const int k1 = nt > 1 ? 1 : 0;
+    srX = nt > 1 ? sSrcT[16 + n] : -1;
+    load_dstage_nb<T, P, kBlock>(tp[k1], Dst, vDX);
+    load_bshare<T, P, H>(srX, zrow, lane, mass1, S1, vBX, vmX);
+  }
+  // one tap: load tap k + 2 into (vDn, vBn), MFMAs of tap k from LDS buffer
+  // b, store tap k + 1 from (vDc, vBc) into buffer b ^ 1
+  auto step = [&](int k, int b, V* vDc, V* vBc, double vmc, int src, V* vDn, V* vBn, double& vmn, int& srn) {
+    const int k2 = k + 2 < nt ? k + 2 : nt - 1;
+    srn = k + 2 < nt ? sSrcT[k2 * 16 + n] : -1;
+    load_dstage_nb<T, P, kBlock>(tp[k2], Dst, vDn);
+    load_bshare<T, P, H>(srn, zrow, lane, mass1, S1, vBn, vmn);
+    __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the MFMAs
     const T* B = sB[b] + lane;
     const T* D = sD[b];
     T bv[KBH > 0 ? KBH : 1];
@@ -703,12 +730,15 @@ __device__ inline void m2l_part(const int32_t* __restrict__ tp, int nt, const in
         acc[i] = mfma16(D[off[s]], bv[kb], acc[i]);
         ++s;
       }
-    if (k + 1 < nt) {
-      store_dstage<T, P, kBlock>(sD[b ^ 1], vD);
-      store_bshare<T, P>(sB[b ^ 1], lane, H, vB);
+    if (k + 1 < nt2) {
+      store_dstage<T, P, kBlock>(sD[b ^ 1], vDc);
+      store_bshare<T, P, H>(sB[b ^ 1], src, lane, vBc, vmc);
     }
-    if (k + 2 < nt && t < 16) sSrc[b][t] = tap_code(ncell, nrank);
     __syncthreads();
+  };
+  for (int k = 0; k < nt2; k += 2) {
+    step(k, 0, vDX, vBX, vmX, srX, vDY, vBY, vmY, srY);
+    step(k + 1, 1, vDY, vBY, vmY, srY, vDX, vBX, vmX, srX);
   }
   const int F = sF[lane & 15];
   if (F < 0) return;
@@ -739,7 +769,7 @@ __global__ __launch_bounds__(kBlock) void k_m2l_mfma(const int32_t* __restrict__
   __shared__ __align__(16) T sD[2][TS::SDP];
   __shared__ int sF[16];
   __shared__ int sCB[16 * 27];
-  __shared__ int sSrc[2][16];
+  __shared__ int sSrcT[kTaps * 16];
   const int item = xcd_tile(ntiles * nsplit);
   if (item >= ntiles * nsplit) return;
   const int tile = item / nsplit, chunk = item - tile * nsplit;
@@ -757,28 +787,33 @@ __global__ __launch_bounds__(kBlock) void k_m2l_mfma(const int32_t* __restrict__
   gptr<T> S1 = as_global(level_S<T>(lv1));
   gptr<int32_t> rank1 = as_global(lv1.rank);
   gptr<double> mass1 = as_global(lv1.mass);
-  if (t < 16) {
-    sSrc[0][t] = tap_src(tp[0], t, sCB, rank1);
-    if (nt > 1) sSrc[1][t] = tap_src(tp[1], t, sCB, rank1);
-  }
+  // sources of every tap of the range
+  for (int i = t; i < nt * 16; i += kBlock) sSrcT[i] = tap_src(tp[i >> 4], i & 15, sCB, rank1);
   __syncthreads();
+  const int zrow = lv1.nref;
   {
     typename Vec16<T>::type vD[ND];
     typename Vec16<T>::type vB[MS::NVW];
-    load_dstage<T, P, kBlock>(tp[0], Dst, vD);
-    load_bshare<T, P>(sSrc[0][lane & 15], lane, w, mass1, S1, vB);
+    double vm = 0;
+    const int sr = sSrcT[lane & 15];
+    load_dstage_nb<T, P, kBlock>(tp[0], Dst, vD);
+    switch (w) {
+      case 0: load_bshare<T, P, 0>(sr, zrow, lane, mass1, S1, vB, vm); store_bshare<T, P, 0>(sB[0], sr, lane, vB, vm); break;
+      case 1: load_bshare<T, P, 1>(sr, zrow, lane, mass1, S1, vB, vm); store_bshare<T, P, 1>(sB[0], sr, lane, vB, vm); break;
+      case 2: load_bshare<T, P, 2>(sr, zrow, lane, mass1, S1, vB, vm); store_bshare<T, P, 2>(sB[0], sr, lane, vB, vm); break;
+      default: load_bshare<T, P, 3>(sr, zrow, lane, mass1, S1, vB, vm); store_bshare<T, P, 3>(sB[0], sr, lane, vB, vm); break;
+    }
     store_dstage<T, P, kBlock>(sD[0], vD);
-    store_bshare<T, P>(sB[0], lane, w, vB);
   }
   __syncthreads();
   gmut<T> Lout = as_global_mut(nsplit > 1 ? (T*)lv0.Lpart + (size_t)chunk * lv0.nref * TS::K : level_L<T>(lv0));
   gptr<int32_t> rank0 = as_global(lv0.rank);
   // every wave runs the same number of barriers (one per tap)
   switch (w) {
-    case 0: m2l_part<T, P, 0>(tp, nt, aoff, sF, sCB, sSrc, sB, sD, rank1, mass1, Dst, S1, rank0, Lout); break;
-    case 1: m2l_part<T, P, 1>(tp, nt, aoff, sF, sCB, sSrc, sB, sD, rank1, mass1, Dst, S1, rank0, Lout); break;
-    case 2: m2l_part<T, P, 2>(tp, nt, aoff, sF, sCB, sSrc, sB, sD, rank1, mass1, Dst, S1, rank0, Lout); break;
-    default: m2l_part<T, P, 3>(tp, nt, aoff, sF, sCB, sSrc, sB, sD, rank1, mass1, Dst, S1, rank0, Lout); break;
+    case 0: m2l_part<T, P, 0>(tp, nt, aoff, sF, sSrcT, sB, sD, zrow, mass1, Dst, S1, rank0, Lout); break;
+    case 1: m2l_part<T, P, 1>(tp, nt, aoff, sF, sSrcT, sB, sD, zrow, mass1, Dst, S1, rank0, Lout); break;
+    case 2: m2l_part<T, P, 2>(tp, nt, aoff, sF, sSrcT, sB, sD, zrow, mass1, Dst, S1, rank0, Lout); break;
+    default: m2l_part<T, P, 3>(tp, nt, aoff, sF, sSrcT, sB, sD, zrow, mass1, Dst, S1, rank0, Lout); break;
   }
 }
 

@@ -361,6 +361,15 @@ template <typename T> __device__ inline T* level_L(const LevelDev& lv);
 template <> __device__ inline float* level_L<float>(const LevelDev& lv) { return lv.L32; }
 template <> __device__ inline double* level_L<double>(const LevelDev& lv) { return lv.L64; }
 
+// Tap range of chunk c of nsplit: whole pairs of taps (the tap loops run in
+// pairs), so that only the last chunk has an odd count and runs one empty tap.
+// The host keeps nsplit <= 21, so every range holds at least 8 taps.
+__device__ inline void tap_range(int c, int nsplit, int& tb, int& te) {
+  constexpr int kPairs = (kTaps + 1) / 2;
+  tb = 2 * (c * kPairs / nsplit);
+  te = min(kTaps, 2 * ((c + 1) * kPairs / nsplit));
+}
+
 // Source of column n for tap `code`: refined rank (>= 0), -2 - cell for a leaf
 // (monopole), or -1 when there is none.  Resolved two taps ahead, in two
 // halves inside the tap loop: the level-(l-1) cell and the load of its rank
@@ -391,6 +400,31 @@ __device__ inline void load_bfrag(int sr, int lane, gptr<double> mass1, gptr<T> 
     for (int j = 0; j < NV; ++j) vb[j] = V{};
     if (sr <= -2 && (lane >> 4) == 0) vb[0][0] = (T)mass1[-2 - sr];
   }
+}
+
+// Branch-free form for the M2P tap loop: a missing or leaf source reads the
+// zero row zrow after the level's nref rows, and every lane loads a mass (cell
+// 0 when the source is no leaf), put into the monopole slot when the tap is
+// used (bfrag_m0).  Only the NS steps used are loaded (a partial last vector
+// element by element): an element loaded but never read would leave a
+// register that the compiler reuses while the load is still in flight.
+template <typename T, int P, int NS>
+__device__ inline void load_bfrag_nb(int sr, int zrow, gptr<double> mass1, gptr<T> S1,
+                                     typename Vec16<T>::type* vb, double& vm) {
+  using TS = TapStage<T, P>;
+  using V = typename Vec16<T>::type;
+  constexpr int NF = NS / TS::VW, R = NS % TS::VW;
+  gptr<T> src = S1 + (size_t)(sr >= 0 ? sr : zrow) * TS::ROW;
+  const int g = (threadIdx.x & 63) >> 4;
+#pragma unroll
+  for (int j = 0; j < NF; ++j) vb[j] = *(gptr<V>)(src + src_vec(j, g, (int)sizeof(T)));
+#pragma unroll
+  for (int r = 0; r < R; ++r) vb[NF][r] = src[src_vec(NF, g, (int)sizeof(T)) + r];
+  vm = mass1[sr <= -2 ? -2 - sr : 0];
+}
+template <typename T>
+__device__ inline T bfrag_m0(int sr, double vm, T b0) {
+  return (sr <= -2 && ((threadIdx.x & 63) >> 4) == 0) ? (T)vm : b0;
 }
 
 // D~ stage of tap `code` (rows already in the LDS layout): NTH threads copy
@@ -466,12 +500,12 @@ __global__ __launch_bounds__(64) void k_m2p(const int32_t* __restrict__ tiles, i
   __shared__ __align__(16) T sD[2][TS::SDP];
   __shared__ int sF[16];
   __shared__ int sCB[16 * 27];
-  __shared__ int sSrc[2][16];
-  __shared__ int sTap[kTaps];
+  __shared__ int sSrcT[kTaps * 16];
   const int item = xcd_tile(ntiles * nsplit);
   if (item >= ntiles * nsplit) return;
   const int tile = item / nsplit, chunk = item - tile * nsplit;
-  const int tb = chunk * kTaps / nsplit, te = (chunk + 1) * kTaps / nsplit;
+  int tb, te;
+  tap_range(chunk, nsplit, tb, te);
   const int lane = threadIdx.x;
   const int n = lane & 15;
   const int32_t* rec = tiles + (size_t)tile * 17;
@@ -501,51 +535,52 @@ __global__ __launch_bounds__(64) void k_m2p(const int32_t* __restrict__ tiles, i
     sCB[i] = v;
   }
   const int oF = refcell1[sF[0]] & 7;
-  for (int i = lane; i < kTaps; i += 64) sTap[i] = taps[oF * kTaps + i];
+  const int nt = te - tb;
+  const int32_t* tp = taps + oF * kTaps + tb;
   int off0[ST0], off1[ST1];
 #pragma unroll
   for (int kb = 0; kb < ST0; ++kb) off0[kb] = aoff[kb * 64 + lane];
 #pragma unroll
   for (int kb = 0; kb < ST1; ++kb) off1[kb] = aoff[(ST0 + kb) * 64 + lane];
   __syncthreads();
-  if (lane < 16) {
-    sSrc[0][lane] = tap_src(sTap[tb], lane, sCB, rank1);
-    if (tb + 1 < te) sSrc[1][lane] = tap_src(sTap[tb + 1], lane, sCB, rank1);
-  }
+  // sources of every tap of the range
+  for (int i = lane; i < nt * 16; i += 64) sSrcT[i] = tap_src(tp[i >> 4], i & 15, sCB, rank1);
   __syncthreads();
+  const int zrow = lv1.nref;
   V bA[NV], bB[NV];
   V vD[ND];
-  load_bfrag<T, P, NV>(sSrc[0][n], lane, mass1, S1, bA);
-  load_dstage<T, P, 64>(sTap[tb], Dst, vD);
+  double vmA = 0, vmB = 0;
+  int srA = sSrcT[n], srB = -1;
+  load_bfrag_nb<T, P, ST0>(srA, zrow, mass1, S1, bA, vmA);
+  load_dstage<T, P, 64>(tp[0], Dst, vD);
   store_dstage<T, P, 64>(sD[0], vD);
   __syncthreads();
   typename Acc4<T>::type acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-  // one tap: prefetch tap k+1 (B into bn, D rows into vD), MFMAs of tap k from bc / sD[k & 1]
-  auto step = [&](int k, const V* bc, V* bn) {
-    const int b = (k - tb) & 1;
-    int ncell = -1, nrank = -1;
-    if (k + 2 < te && lane < 16) {
-      ncell = tap_cell(sTap[k + 2], lane, sCB);
-      if (ncell >= 0) nrank = rank1[ncell];
-    }
-    if (k + 1 < te) {
-      load_bfrag<T, P, NV>(sSrc[b ^ 1][n], lane, mass1, S1, bn);
-      load_dstage<T, P, 64>(sTap[k + 1], Dst, vD);
-    }
+  // Taps run in pairs; an odd range ends with one empty tap (no source, so B
+  // is zero; the D~ stage repeats the last tap's finite rows), so that both
+  // halves of a pair and every load run unconditionally.
+  const int nt2 = (nt + 1) & ~1;
+  // one tap: prefetch tap k + 1 (D~ rows into vD, B into bn), MFMAs of tap k
+  // from bc and the LDS stage sD[b]
+  auto step = [&](int k, int b, const V* bc, int src, double vmc, V* bn, int& srn, double& vmn) {
+    const int k1 = k + 1 < nt ? k + 1 : nt - 1;
+    load_dstage<T, P, 64>(tp[k1], Dst, vD);
+    srn = k + 1 < nt ? sSrcT[k1 * 16 + n] : -1;
+    load_bfrag_nb<T, P, ST0>(srn, zrow, mass1, S1, bn, vmn);
+    __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the MFMAs
     const T* D = sD[b];
 #pragma unroll
     for (int kb = 0; kb < ST0; ++kb) {
-      const T bv = bc[kb / TS::VW][kb % TS::VW];
+      const T bv = kb == 0 ? bfrag_m0<T>(src, vmc, bc[0][0]) : bc[kb / TS::VW][kb % TS::VW];
       acc0 = mfma16(D[off0[kb]], bv, acc0);
       if (kb < ST1) acc1 = mfma16(D[off1[kb]], bv, acc1);
     }
-    if (k + 1 < te) store_dstage<T, P, 64>(sD[b ^ 1], vD);
-    if (k + 2 < te && lane < 16) sSrc[b][lane] = tap_code(ncell, nrank);
+    store_dstage<T, P, 64>(sD[b ^ 1], vD);
     __syncthreads();
   };
-  for (int k = tb; k < te; k += 2) {
-    step(k, bA, bB);
-    if (k + 1 < te) step(k + 1, bB, bA);
+  for (int k = 0; k < nt2; k += 2) {
+    step(k, 0, bA, srA, vmA, bB, srB, vmB);
+    step(k + 1, 1, bB, srB, vmB, bA, srA, vmA);
   }
   const int F = sF[n];
   if (F >= 0) {
@@ -773,7 +808,8 @@ __global__ __launch_bounds__(kBlock) void k_m2l_mfma(const int32_t* __restrict__
   const int item = xcd_tile(ntiles * nsplit);
   if (item >= ntiles * nsplit) return;
   const int tile = item / nsplit, chunk = item - tile * nsplit;
-  const int tb = chunk * kTaps / nsplit, te = (chunk + 1) * kTaps / nsplit;
+  int tb, te;
+  tap_range(chunk, nsplit, tb, te);
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   const int32_t* rec = tiles + (size_t)tile * 17;
   const int f = rec[0];

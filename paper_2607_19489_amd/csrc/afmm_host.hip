@@ -57,6 +57,8 @@ struct Topology {
   std::vector<int32_t> leafgrp[kMaxLevel];  // index l: refined ranks at l-1 with a leaf child
   std::vector<int32_t> m2lgrp[kMaxLevel];   // index f: refined ranks at f-1 with a refined child
   std::vector<int32_t> nmgrp[kMaxLevel];    // index l: leafgrp entries with a refined level-l near candidate
+  std::vector<int32_t> upleaf[kMaxLevel];   // index f: refined ranks at f whose 8 children are leaves
+  std::vector<int32_t> upmix[kMaxLevel];    // index f: refined ranks at f with a refined child
   // per hierarchy
   std::vector<int32_t> levelmin, levelmax;
   std::vector<int64_t> slot_base, slot_count;
@@ -221,8 +223,12 @@ static void build_groups(Topology& T) {
     const HostLevel& C = T.lv[l];
     auto& lg = T.leafgrp[l];
     auto& mg = T.m2lgrp[l];
+    auto& ul = T.upleaf[l - 1];
+    auto& um = T.upmix[l - 1];
     lg.clear();
     mg.clear();
+    ul.clear();
+    um.clear();
     for (int32_t r = 0; r < P.nref(); ++r) {
       bool leaf = false, refd = false;
       for (int o = 0; o < 8; ++o) {
@@ -231,6 +237,7 @@ static void build_groups(Topology& T) {
       }
       if (leaf) lg.push_back(r);
       if (refd && l >= 3) mg.push_back(r);
+      (refd ? um : ul).push_back(r);
     }
     // groups whose near candidates (children of the 27 neighbours of F)
     // include a refined level-l cell: their near-field M2P runs apart
@@ -760,6 +767,8 @@ struct afmm_plan {
   int32_t* d_leafgrp[kMaxLevel] = {};
   int32_t* d_m2lgrp[kMaxLevel] = {};
   int32_t* d_nmgrp[kMaxLevel] = {};
+  int32_t* d_upleaf[kMaxLevel] = {};  // upward lists (Topology::upleaf / upmix)
+  int32_t* d_upmix[kMaxLevel] = {};
   void* d_nmp[kMaxLevel] = {};   // near-field M2P partials of level l (leaf-kernel precision)
   // MFMA tile records of every level, one array per precision (0 FP64, 1 FP32);
   // range[l] = {precision, first tile, count}
@@ -1132,6 +1141,8 @@ static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
     if ((s = upload(P, T.leafgrp[l], &P->d_leafgrp[l], st))) return s;
     if ((s = upload(P, T.m2lgrp[l], &P->d_m2lgrp[l], st))) return s;
     if ((s = upload(P, T.nmgrp[l], &P->d_nmgrp[l], st))) return s;
+    if ((s = upload(P, T.upleaf[l], &P->d_upleaf[l], st))) return s;
+    if ((s = upload(P, T.upmix[l], &P->d_upmix[l], st))) return s;
     if (!T.nmgrp[l].empty()) {
       const size_t es = (mixed && (l - 1) > f64) ? sizeof(float) : sizeof(double);
       // groups without refined near candidates are never written: zero once
@@ -1444,7 +1455,10 @@ static afmm_status run_solve(afmm_plan* P, const double* msrc, int fmax, int lo,
   }
   for (int f = T.lmax - 1; f >= 2 && !keep_trees; --f) {
     hipEvent_t a = prof_begin(P, st);
-    if ((s = dev_check(P, launch_upward(p, P->lv[f], P->lv[f + 1], P->cm, st), "upward")))
+    if ((s = dev_check(P,
+                       launch_upward(p, P->d_upleaf[f], (int)T.upleaf[f].size(), P->d_upmix[f],
+                                     (int)T.upmix[f].size(), P->lv[f], P->lv[f + 1], P->cm, st),
+                       "upward")))
       return s;
     prof_end(P, a, st, kUpward, f);
   }

@@ -202,7 +202,10 @@ hipError_t launch_adj_down(int p, const LevelDev& lv1, const LevelDev& lv0, int 
                            hipStream_t st);
 hipError_t launch_adj_out(int p, const LevelDev& lv1, const LevelDev& lv0, int has_parent, int rebuilt,
                           const CommonDev& cm, double* mbar_out, hipStream_t st);
-hipError_t launch_upward(int p, const LevelDev& lv, const LevelDev& lvc, const CommonDev& cm, hipStream_t st);
+// Upward pass of FMM level f: the refined cells whose children are all leaves
+// (list leaf, P2M only) and the others (list mix, M2M of refined children).
+hipError_t launch_upward(int p, const int32_t* leaf, int nleaf, const int32_t* mix, int nmix, const LevelDev& lv,
+                         const LevelDev& lvc, const CommonDev& cm, hipStream_t st);
 int m2p_columns(int p, bool fp32);
 // MFMA launches over a contiguous range [t0, t0 + n) of tile records; each
 // record is (target level, NC groups).  lvs is the device array of LevelDev.

@@ -125,9 +125,12 @@ hipError_t launch_gather_mass(const LevelDev& lv, const double* m_src, hipStream
 // children's ranks and masses, forms the 8 signed child sums Y of each cell in
 // LDS and sums the entries of each coefficient.
 // The source copies are written in the lane-group layout; thread a >= K of a
-// cell writes the zero of padding slot src_pos(a).
+// cell writes the zero of padding slot src_pos(a).  Runs over a list of the
+// level's refined ranks (those with a refined child; k_p2m_leaf takes the
+// others).
 template <int P>
-__global__ __launch_bounds__(256) void k_upward(LevelDev lv, LevelDev lvc, CommonDev cm) {
+__global__ __launch_bounds__(256) void k_upward(const int32_t* __restrict__ list, int nlist, LevelDev lv,
+                                                LevelDev lvc, CommonDev cm) {
   constexpr int K = nmi(P);
   constexpr int NE = nmi_entries(P);
   constexpr int STP32 = src_stp(P, 4), STP64 = src_stp(P, 8);
@@ -148,12 +151,12 @@ __global__ __launch_bounds__(256) void k_upward(LevelDev lv, LevelDev lvc, Commo
   const int c = t / KP, a = t - c * KP;
   // children of a chunk: refined rank and mass (the gathered mass of a refined
   // child is 0 and unused), two independent loads, prefetched one chunk ahead
-  auto child = [&](int r0, int& rc, double& m) {
+  auto child = [&](int i0, int& rc, double& m) {
     rc = -1;
     m = 0.0;
-    const int r = r0 + (t >> 3);
-    if (t < CB * 8 && r < lv.nref) {
-      const int ch = 8 * r + (t & 7);
+    const int i = i0 + (t >> 3);
+    if (t < CB * 8 && i < nlist) {
+      const int ch = 8 * list[i] + (t & 7);
       rc = lvc.rank[ch];
       m = lvc.mass[ch];
     }
@@ -161,12 +164,12 @@ __global__ __launch_bounds__(256) void k_upward(LevelDev lv, LevelDev lvc, Commo
   int rcn;
   double mn;
   child(blockIdx.x * CB, rcn, mn);
-  for (int r0 = blockIdx.x * CB; r0 < lv.nref; r0 += gridDim.x * CB) {
+  for (int i0 = blockIdx.x * CB; i0 < nlist; i0 += gridDim.x * CB) {
     if (t < CB * 8) {
       sRc[t >> 3][t & 7] = rcn;
       sM[t >> 3][t & 7] = rcn < 0 ? mn : 0.0;
     }
-    child(r0 + gridDim.x * CB, rcn, mn);
+    child(i0 + gridDim.x * CB, rcn, mn);
     __syncthreads();
     // a cell whose 8 children are leaves has only monopole children: its signed
     // sums vanish for k > 0 and each coefficient keeps the k = 0 entry (the
@@ -202,8 +205,8 @@ __global__ __launch_bounds__(256) void k_upward(LevelDev lv, LevelDev lvc, Commo
       for (int q = 0; q < 8; ++q) sY[cc][q][k] = v[q];
     }
     __syncthreads();
-    const int r = r0 + c;
-    if (c < CB && r < lv.nref) {
+    const int r = i0 + c < nlist ? list[i0 + c] : -1;
+    if (c < CB && r >= 0) {
       if (a >= K) {  // zero padding of the source copies
         if (lv.S32) lv.S32[(size_t)r * 4 * STP32 + src_pos(a, 4)] = 0.f;
         if (lv.Sc64 && a < 4 * STP64) lv.Sc64[(size_t)r * 4 * STP64 + src_pos(a, 8)] = 0.0;
@@ -226,6 +229,50 @@ __global__ __launch_bounds__(256) void k_upward(LevelDev lv, LevelDev lvc, Commo
     }
     __syncthreads();
   }
+}
+
+// Upward pass for the refined cells whose 8 children are leaves (P2M, Eq.
+// eq:P2M): the signed child sums vanish for k > 0, so coefficient a is the
+// k = 0 entry of its M2M list times one signed sum of the 8 masses (signs by
+// the parity of a).  Thread = (cell of the list, slot a of the source-copy
+// run), no synchronisation; the 8 masses of a cell are one 64-byte run.
+template <int P>
+__global__ __launch_bounds__(256) void k_p2m_leaf(const int32_t* __restrict__ list, int nlist, LevelDev lv,
+                                                  LevelDev lvc, CommonDev cm) {
+  constexpr int K = nmi(P);
+  constexpr int STP32 = src_stp(P, 4), STP64 = src_stp(P, 8);
+  constexpr int KP = 4 * STP32;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= (int64_t)nlist * KP) return;
+  const int r = list[i / KP], a = (int)(i % KP);
+  if (a >= K) {  // zero padding of the source copies
+    if (lv.S32) lv.S32[(size_t)r * 4 * STP32 + src_pos(a, 4)] = 0.f;
+    if (lv.Sc64 && a < 4 * STP64) lv.Sc64[(size_t)r * 4 * STP64 + src_pos(a, 8)] = 0.0;
+    return;
+  }
+  gptr<double> m = as_global(lvc.mass) + 8 * (size_t)r;
+  double v[8];
+#pragma unroll
+  for (int o = 0; o < 8; ++o) v[o] = m[o];
+  const int e0 = cm.m2m_start[a];
+  const int q = cm.m2m_list[e0] >> 12;
+  // signed sum over the octant bits of q (the butterfly of k_upward, one output)
+#pragma unroll
+  for (int bit = 0; bit < 3; ++bit) {
+    double u[8];
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+      const int lo = o & ~(1 << bit);
+      u[o] = (q & (1 << bit)) ? v[lo | (1 << bit)] - v[lo] : v[lo] + v[lo | (1 << bit)];
+    }
+#pragma unroll
+    for (int o = 0; o < 8; ++o) v[o] = u[o];
+  }
+  const double acc = cm.m2m_w[e0] * v[q];
+  lv.S64[(size_t)r * K + a] = acc;
+  const double sc = acc * cm.cfac2[a];
+  if (lv.S32) lv.S32[(size_t)r * 4 * STP32 + src_pos(a, 4)] = (float)sc;
+  if (lv.Sc64) lv.Sc64[(size_t)r * 4 * STP64 + src_pos(a, 8)] = sc;
 }
 
 __global__ void k_batch_in(int64_t nleaf, const int32_t* __restrict__ leafslot, const int32_t* __restrict__ leafhier,
@@ -268,17 +315,31 @@ hipError_t launch_batch_out(int64_t nleaf, const int32_t* leafslot, const int32_
   return hipGetLastError();
 }
 
-hipError_t launch_upward(int p, const LevelDev& lv, const LevelDev& lvc, const CommonDev& cm, hipStream_t st) {
-  if (lv.nref == 0) return hipSuccess;
+hipError_t launch_upward(int p, const int32_t* leaf, int nleaf, const int32_t* mix, int nmix, const LevelDev& lv,
+                         const LevelDev& lvc, const CommonDev& cm, hipStream_t st) {
   const int KP = src_row(p, 4), CB = 256 / KP;
-  // persistent blocks: a few per CU, each looping over chunks of CB cells
-  const dim3 grid(std::min((lv.nref + CB - 1) / CB, 8 * 256)), block(kBlock);
-  switch (p) {
+  if (nleaf > 0) {
+    const dim3 grid((unsigned)(((int64_t)nleaf * KP + 255) / 256)), block(256);
+    switch (p) {
+#define AFMM_P2M(PP) \
+  case PP: hipLaunchKernelGGL(k_p2m_leaf<PP>, grid, block, 0, st, leaf, nleaf, lv, lvc, cm); break;
+      AFMM_P2M(1) AFMM_P2M(2) AFMM_P2M(3) AFMM_P2M(4) AFMM_P2M(5) AFMM_P2M(6) AFMM_P2M(7) AFMM_P2M(8)
+#undef AFMM_P2M
+      default: return hipErrorInvalidValue;
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (nmix > 0) {
+    // persistent blocks: a few per CU, each looping over chunks of CB cells
+    const dim3 grid(std::min((nmix + CB - 1) / CB, 8 * 256)), block(kBlock);
+    switch (p) {
 #define AFMM_UP(PP) \
-  case PP: hipLaunchKernelGGL(k_upward<PP>, grid, block, 0, st, lv, lvc, cm); break;
-    AFMM_UP(1) AFMM_UP(2) AFMM_UP(3) AFMM_UP(4) AFMM_UP(5) AFMM_UP(6) AFMM_UP(7) AFMM_UP(8)
+  case PP: hipLaunchKernelGGL(k_upward<PP>, grid, block, 0, st, mix, nmix, lv, lvc, cm); break;
+      AFMM_UP(1) AFMM_UP(2) AFMM_UP(3) AFMM_UP(4) AFMM_UP(5) AFMM_UP(6) AFMM_UP(7) AFMM_UP(8)
 #undef AFMM_UP
-    default: return hipErrorInvalidValue;
+      default: return hipErrorInvalidValue;
+    }
   }
   return hipGetLastError();
 }

@@ -1439,9 +1439,10 @@ static void prof_end(afmm_plan* P, hipEvent_t a, hipStream_t st, int kind, int l
 }
 
 // Upward pass over every level, M2L over FMM levels 3..fmax, leaf evaluation
-// for the levels in [lo, hi].  Masses come from `msrc` (slot space).
+// for the levels in [lo, hi].  Masses come from `msrc` (slot space); with
+// `snap`, the mass gather also copies every slot there.
 static afmm_status run_solve(afmm_plan* P, const double* msrc, int fmax, int lo, int hi, double* phi, double* acc,
-                             hipStream_t st, bool keep_trees = false) {
+                             hipStream_t st, bool keep_trees = false, double* snap = nullptr) {
   Topology& T = P->topo;
   const int p = P->opt.p;
   const bool mixed = P->opt.precision == AFMM_FP32_MIXED;
@@ -1450,7 +1451,7 @@ static afmm_status run_solve(afmm_plan* P, const double* msrc, int fmax, int lo,
   // keep_trees: the level masses and multipoles on the device already belong to msrc
   for (int l = T.lmin_all; l <= T.lmax && !keep_trees; ++l) {
     hipEvent_t a = prof_begin(P, st);
-    if ((s = dev_check(P, launch_gather_mass(P->lv[l], msrc, st), "gather"))) return s;
+    if ((s = dev_check(P, launch_gather_mass(P->lv[l], msrc, snap, st), "gather"))) return s;
     prof_end(P, a, st, kGather, l);
   }
   for (int f = T.lmax - 1; f >= 2 && !keep_trees; --f) {
@@ -1580,15 +1581,14 @@ static afmm_status afmm_solve_impl(afmm_plan* P, int32_t level, int32_t icount, 
     if (e != hipSuccess) return dev_check(P, e, "input check");
     if (hostflag) return fail(AFMM_E_NONFINITE, "non-finite mass");
   }
-  const size_t nb = (size_t)T.nslots * sizeof(double);
   if (level == AFMM_ALL_LEVELS) {
-    if (dev_check(P, hipMemcpyAsync(P->m_snap, d_mass, nb, hipMemcpyDeviceToDevice, st), "snapshot")) return AFMM_E_DEVICE;
+    // the snapshot is written by the mass gather of this solve
     P->snap_valid = true;
     P->solved = true;
     P->last_level = AFMM_ALL_LEVELS;
     P->last_fresh = 0;
     P->tree_fresh = false;
-    afmm_status r = run_solve(P, d_mass, T.lmax - 1, lmin, lmax, d_phi, d_acc, st);
+    afmm_status r = run_solve(P, d_mass, T.lmax - 1, lmin, lmax, d_phi, d_acc, st, false, P->m_snap);
     P->tree_fresh = r == AFMM_OK;
     return r;
   }

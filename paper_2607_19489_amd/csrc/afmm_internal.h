@@ -166,7 +166,9 @@ struct MfmaTables {
 };
 
 // Launchers (afmm_kernels.hip).  All return hipGetLastError() of the launch.
-hipError_t launch_gather_mass(const LevelDev& lv, const double* m_src, hipStream_t st);
+// Leaf masses of one level from the caller's slot array; with `snap`, every
+// cell's slot value is also copied there (the adaptive-time-step snapshot).
+hipError_t launch_gather_mass(const LevelDev& lv, const double* m_src, double* snap, hipStream_t st);
 hipError_t launch_copy_slots(const int32_t* slots, int64_t n, const double* src, double* dst,
                              hipStream_t st);
 // Batches: forest slot <-> caller arrays.  leafslot/leafhier list every leaf of

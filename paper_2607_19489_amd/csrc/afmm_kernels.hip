@@ -98,17 +98,19 @@ __device__ inline void m2p_row(const T* __restrict__ D, const T* __restrict__ S,
 // ---------------------------------------------------------------------------
 // leaf masses of one level (slot gather); refined cells get 0
 __global__ void k_gather_mass(int n, const int32_t* __restrict__ rank, const int32_t* __restrict__ slot,
-                              const double* __restrict__ m, double* __restrict__ out) {
+                              const double* __restrict__ m, double* __restrict__ out, double* __restrict__ snap) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int s = slot[i];
-  out[i] = (rank[i] < 0 && s >= 0) ? m[s] : 0.0;
+  const double v = s >= 0 ? m[s] : 0.0;
+  out[i] = rank[i] < 0 ? v : 0.0;
+  if (snap && s >= 0) snap[s] = v;
 }
 
-hipError_t launch_gather_mass(const LevelDev& lv, const double* m_src, hipStream_t st) {
+hipError_t launch_gather_mass(const LevelDev& lv, const double* m_src, double* snap, hipStream_t st) {
   if (lv.n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_gather_mass, dim3(ceil_div_host(lv.n, 256)), dim3(256), 0, st, lv.n, lv.rank, lv.slot,
-                     m_src, lv.mass);
+                     m_src, lv.mass, snap);
   return hipGetLastError();
 }
 
@@ -371,10 +373,19 @@ __global__ __launch_bounds__(kBlock) void k_l2l(const int32_t* __restrict__ grp,
     if (ry < 0) continue;
     const size_t at = (size_t)ry * K + b;
     T v = 0;
-    if (nsplit > 1)
-      for (int c = 0; c < nsplit; ++c) v += Lpart[c * split_stride + at];
-    else
+    if (nsplit > 1) {
+      // in order, four loads in flight at a time (the trip count is a runtime value)
+      for (int c0 = 0; c0 < nsplit; c0 += 4) {
+        T x[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[j] = Lpart[min(c0 + j, nsplit - 1) * split_stride + at];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (c0 + j < nsplit) v += x[j];
+      }
+    } else {
       v = Lout[at];
+    }
     if (Lpar) {
       const int nb = mi[4 * b + 3];
       const T* wr = w + ((size_t)o * (P + 1) + nb) * K;

@@ -5,6 +5,10 @@
            table: rocprofv3's own per-kernel statistics over every dispatch, and
            the per-dispatch statistics of the last N dispatches of each kernel
            (the timed, autotuned launches; the autotuner's candidates come first).
+  mfma:    one --pmc run counting MFMA operations (SQ_INSTS_VALU_MFMA_MOPS_F32 /
+           _F64, 512 flops each) and a kernel trace of the same command ->
+           issued MFMA flops per dispatch of each MFMA kernel over its average
+           traced duration, against the dense MFMA peak of its precision.
   traffic: two --pmc runs of the same command (FETCH_SIZE, then WRITE_SIZE) ->
            HBM bytes per launch of one kernel, each counter scaled by the reading
            of the same counter for a plain device copy of known size (the
@@ -90,6 +94,40 @@ def _pmc(d: str, counter: str):
     return byk
 
 
+PEAK_TFLOPS = {"SQ_INSTS_VALU_MFMA_MOPS_F32": 157.3, "SQ_INSTS_VALU_MFMA_MOPS_F64": 78.6}
+
+
+def cmd_mfma(a):
+    trace = list(csv.DictReader(open(_find(a.trace, "kernel_trace.csv"))))
+    dur = {}
+    for r in trace:
+        dur.setdefault(short(r["Kernel_Name"]), []).append(
+            (int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    out = [f"# Issued MFMA throughput: {a.title}", "",
+           "Operation counts (rocprofv3 --pmc, SQ_INSTS_VALU_MFMA_MOPS_*: multiply and add operations / 512,",
+           "summed over the shader engines) per dispatch, over the average duration of the same kernel's",
+           "dispatches in a kernel trace of the same command (last N of each).  Issued operations include the",
+           "zero padding of the MFMA tiles; the useful-flop rate is the bench's own figure.  The M2L chain",
+           "runs on a second stream beside M2P here, so a traced duration can include time shared with the",
+           "other stream (the small FP64 M2L of the top FMM levels is such a case).", "",
+           "Commands (repository root on the MI355X box):", "", "```", a.command_pmc, a.command_trace, "```", "",
+           "| kernel | counter | dispatches | issued GFLOP / dispatch | avg us (trace) | issued TFLOP/s | of peak |",
+           "|---|---|---|---|---|---|---|"]
+    for counter, peak in PEAK_TFLOPS.items():
+        per = _pmc(a.pmc, counter)
+        for k, v in sorted(per.items()):
+            ops = [x for _, x in v[-a.last:]]
+            if not ops or max(ops) == 0 or k not in dur:
+                continue
+            d = sorted(dur[k])[-a.last:]
+            us = statistics.mean(x[1] for x in d) / 1e3
+            gf = statistics.median(ops) * 512 / 1e9
+            tf = gf / us * 1e3
+            out.append(f"| `{k}` | {counter[-3:]} | {len(ops)} | {gf:.2f} | {us:.1f} | {tf:.1f} | {tf / peak:.1%} |")
+    open(a.out, "w").write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+
 def cmd_traffic(a):
     fetch = _pmc(a.fetch, "FETCH_SIZE")
     write = _pmc(a.write, "WRITE_SIZE")
@@ -123,6 +161,14 @@ def main():
     s.add_argument("--title", required=True)
     s.add_argument("--command", required=True)
     s.add_argument("--out", required=True)
+    m = sub.add_parser("mfma")
+    m.add_argument("--pmc", required=True)
+    m.add_argument("--trace", required=True)
+    m.add_argument("--last", type=int, default=8)
+    m.add_argument("--title", required=True)
+    m.add_argument("--command-pmc", required=True)
+    m.add_argument("--command-trace", required=True)
+    m.add_argument("--out", required=True)
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -134,7 +180,7 @@ def main():
     t.add_argument("--command-write", required=True)
     t.add_argument("--out", required=True)
     a = ap.parse_args()
-    cmd_stats(a) if a.mode == "stats" else cmd_traffic(a)
+    {"stats": cmd_stats, "mfma": cmd_mfma, "traffic": cmd_traffic}[a.mode](a)
 
 
 if __name__ == "__main__":

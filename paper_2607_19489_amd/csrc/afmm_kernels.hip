@@ -433,6 +433,44 @@ template <typename T> __device__ inline T* level_L(const LevelDev& lv);
 template <> __device__ inline float* level_L<float>(const LevelDev& lv) { return lv.L32; }
 template <> __device__ inline double* level_L<double>(const LevelDev& lv) { return lv.L64; }
 
+// Drops the taps of a range that have no source in any of the 16 columns
+// (they add nothing; common near the box faces), keeping the order: run by
+// one whole wave, in place on the source table src[tap][16], with the taps'
+// codes copied to code[].  Returns the number kept (at least 1: an empty
+// range keeps its first tap, whose B is zero).
+__device__ inline int compact_taps(int nt, const int32_t* __restrict__ tp, int* src, int* code) {
+  const int lane = threadIdx.x & 63;
+  int cnt = 0;
+  for (int i0 = 0; i0 < nt; i0 += 64) {
+    const int i = i0 + lane;
+    int v[16];
+    bool any = false;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      v[c] = i < nt ? src[i * 16 + c] : -1;
+      any = any || v[c] != -1;
+    }
+    const int cd = i < nt ? tp[i] : 0;
+    const uint64_t m = __ballot(any);
+    wave_sync();
+    if (any) {
+      const int j = cnt + __popcll(m & ((1ull << lane) - 1ull));
+#pragma unroll
+      for (int c = 0; c < 16; ++c) src[j * 16 + c] = v[c];
+      code[j] = cd;
+    }
+    cnt += __popcll(m);
+    wave_sync();
+  }
+  if (cnt == 0) {
+    if (lane < 16) src[lane] = -1;
+    if (lane == 0) code[0] = tp[0];
+    cnt = 1;
+  }
+  wave_sync();
+  return cnt;
+}
+
 // Tap range of chunk c of nsplit: whole pairs of taps (the tap loops run in
 // pairs), so that only the last chunk has an odd count and runs one empty tap.
 // The host keeps nsplit <= 21, so every range holds at least 8 taps.
@@ -607,8 +645,7 @@ __global__ __launch_bounds__(64) void k_m2p(const int32_t* __restrict__ tiles, i
     sCB[i] = v;
   }
   const int oF = refcell1[sF[0]] & 7;
-  const int nt = te - tb;
-  const int32_t* tp = taps + oF * kTaps + tb;
+  const int32_t* tpg = taps + oF * kTaps + tb;
   int off0[ST0], off1[ST1];
 #pragma unroll
   for (int kb = 0; kb < ST0; ++kb) off0[kb] = aoff[kb * 64 + lane];
@@ -616,6 +653,8 @@ __global__ __launch_bounds__(64) void k_m2p(const int32_t* __restrict__ tiles, i
   for (int kb = 0; kb < ST1; ++kb) off1[kb] = aoff[(ST0 + kb) * 64 + lane];
   __syncthreads();
   // sources of every tap of the range
+  const int nt = te - tb;
+  const int32_t* tp = tpg;
   for (int i = lane; i < nt * 16; i += 64) sSrcT[i] = tap_src(tp[i >> 4], i & 15, sCB, rank1);
   __syncthreads();
   const int zrow = lv1.nref;
@@ -877,6 +916,8 @@ __global__ __launch_bounds__(kBlock) void k_m2l_mfma(const int32_t* __restrict__
   __shared__ int sF[16];
   __shared__ int sCB[16 * 27];
   __shared__ int sSrcT[kTaps * 16];
+  __shared__ int sCode[kTaps];
+  __shared__ int sNt;
   const int item = xcd_tile(ntiles * nsplit);
   if (item >= ntiles * nsplit) return;
   const int tile = item / nsplit, chunk = item - tile * nsplit;
@@ -890,14 +931,20 @@ __global__ __launch_bounds__(kBlock) void k_m2l_mfma(const int32_t* __restrict__
   tile_setup(rec, 16, lvs[f - 2], lv1, sF, sCB);
   __syncthreads();
   const int oF = as_global(lv1.refcell)[sF[0]] & 7;
-  const int32_t* tp = taps + oF * kTaps + tb;
-  const int nt = te - tb;
+  const int32_t* tpg = taps + oF * kTaps + tb;
   gptr<T> S1 = as_global(level_S<T>(lv1));
   gptr<int32_t> rank1 = as_global(lv1.rank);
   gptr<double> mass1 = as_global(lv1.mass);
-  // sources of every tap of the range
-  for (int i = t; i < nt * 16; i += kBlock) sSrcT[i] = tap_src(tp[i >> 4], i & 15, sCB, rank1);
+  // sources of every tap of the range, then the taps with a source (wave 0)
+  for (int i = t; i < (te - tb) * 16; i += kBlock) sSrcT[i] = tap_src(tpg[i >> 4], i & 15, sCB, rank1);
   __syncthreads();
+  if (w == 0) {
+    const int c = compact_taps(te - tb, tpg, sSrcT, sCode);
+    if (lane == 0) sNt = c;
+  }
+  __syncthreads();
+  const int nt = sNt;
+  const int* tp = sCode;
   const int zrow = lv1.nref;
   {
     typename Vec16<T>::type vD[ND];

@@ -1463,13 +1463,37 @@ static afmm_status run_solve(afmm_plan* P, const double* msrc, int fmax, int lo,
       return s;
     prof_end(P, a, st, kUpward, f);
   }
-  // fork: the downward chain (M2L taps, then L2L) runs on the side stream,
-  // unless the plan is serial (or profiled: events then time one launch at a time)
+  // fork: the intermediate field (M2P, one large launch) runs on the side
+  // stream while the downward chain (M2L taps, then the latency-bound L2L
+  // levels) runs on this one; the chain is enqueued without a wait, so its
+  // small first launches get the CUs first and M2P fills the rest.  Serial
+  // plans (and profiled solves: events then time one launch at a time) use
+  // one stream.
   const bool serial = (P->opt.flags & AFMM_SERIAL) || P->profiling;
-  hipStream_t sd = serial ? st : P->side;
+  hipStream_t sm = serial ? st : P->side;
   if (!serial && ((s = dev_check(P, hipEventRecord(P->ev_fork, st), "fork")) ||
-                  (s = dev_check(P, hipStreamWaitEvent(sd, P->ev_fork, 0), "fork"))))
+                  (s = dev_check(P, hipStreamWaitEvent(sm, P->ev_fork, 0), "fork"))))
     return s;
+  // intermediate field (M2P) of the leaf levels lo..hi: one launch per precision
+  for (int pr = 0; pr < 2; ++pr) {
+    int t0 = -1, n = 0;
+    for (int l = std::max(lo, 3); l <= hi; ++l)
+      if (P->m2p_range[l][0] == pr && P->m2p_range[l][2] > 0) {
+        if (t0 < 0) t0 = P->m2p_range[l][1];
+        n = P->m2p_range[l][1] + P->m2p_range[l][2] - t0;
+      }
+    if (n <= 0) continue;
+    hipEvent_t a = prof_begin(P, sm);
+    if ((s = dev_check(P, launch_m2p(p, pr == 1, P->m2p_all[pr], t0, n, P->m2p_split[pr], P->mt, P->d_lvs, P->t32, P->t64, sm), "m2p")))
+      return s;
+    for (int l = std::max(lo, 3); l <= hi; ++l)
+      if (P->m2p_range[l][0] == pr) {
+        P->pending_flops += P->work.m2p_flops[l];
+        P->pending_bytes += P->work.m2p_bytes[l];
+      }
+    prof_end(P, a, sm, pr ? kM2P32 : kM2P64, -1);
+  }
+  if (!serial && (s = dev_check(P, hipEventRecord(P->ev_join, sm), "join"))) return s;
   // M2L tap sums of FMM levels 3..fmax: one launch per precision.  A solve of
   // one target level takes its ATS chain (ancestors of the level's leaves only).
   const afmm_plan::AtsChain* chain = (lo == hi && P->ats[lo].on) ? &P->ats[lo] : nullptr;
@@ -1483,9 +1507,9 @@ static afmm_status run_solve(afmm_plan* P, const double* msrc, int fmax, int lo,
         n = m2l_range[f][1] + m2l_range[f][2] - t0;
       }
     if (n <= 0) continue;
-    hipEvent_t a = prof_begin(P, sd);
+    hipEvent_t a = prof_begin(P, st);
     if ((s = dev_check(P, launch_m2l_taps(p, pr == 1, m2l_all[pr], t0, n, P->m2l_split[pr], P->mt, P->d_lvs,
-                                          P->t32, P->t64, sd),
+                                          P->t32, P->t64, st),
                        "m2l")))
       return s;
     for (int f = 3; f <= fmax; ++f)
@@ -1494,7 +1518,7 @@ static afmm_status run_solve(afmm_plan* P, const double* msrc, int fmax, int lo,
         P->pending_flops += frac * P->work.m2l_flops[f];
         P->pending_bytes += frac * P->work.m2l_bytes[f];
       }
-    prof_end(P, a, sd, pr ? kM2L32 : kM2L64, -1);
+    prof_end(P, a, st, pr ? kM2L32 : kM2L64, -1);
   }
   // completion of each FMM level: tap-range partials (if split) + ShiftLocal (L2L) of the father
   for (int f = 3; f <= fmax; ++f) {
@@ -1502,35 +1526,15 @@ static afmm_status run_solve(afmm_plan* P, const double* msrc, int fmax, int lo,
     const int32_t* grp = chain ? chain->d_grp[f] : P->d_m2lgrp[f];
     const int ns = P->m2l_split[P->m2l_range[f][0]];
     if (ng == 0 || (f - 1 < 3 && ns == 1)) continue;
-    hipEvent_t a = prof_begin(P, sd);
+    hipEvent_t a = prof_begin(P, st);
     if ((s = dev_check(P,
                        launch_l2l(p, mixed && f > f64, mixed && (f - 1) > f64, f - 1 >= 3, ns, grp, ng,
-                                  P->lv[f - 1], P->lv[f], P->t32, P->t64, P->cm, sd),
+                                  P->lv[f - 1], P->lv[f], P->t32, P->t64, P->cm, st),
                        "l2l")))
       return s;
-    prof_end(P, a, sd, kL2L, f);
+    prof_end(P, a, st, kL2L, f);
   }
-  if (!serial && (s = dev_check(P, hipEventRecord(P->ev_join, sd), "join"))) return s;
-  // intermediate field (M2P) of the leaf levels lo..hi: one launch per precision
-  for (int pr = 0; pr < 2; ++pr) {
-    int t0 = -1, n = 0;
-    for (int l = std::max(lo, 3); l <= hi; ++l)
-      if (P->m2p_range[l][0] == pr && P->m2p_range[l][2] > 0) {
-        if (t0 < 0) t0 = P->m2p_range[l][1];
-        n = P->m2p_range[l][1] + P->m2p_range[l][2] - t0;
-      }
-    if (n <= 0) continue;
-    hipEvent_t a = prof_begin(P, st);
-    if ((s = dev_check(P, launch_m2p(p, pr == 1, P->m2p_all[pr], t0, n, P->m2p_split[pr], P->mt, P->d_lvs, P->t32, P->t64, st), "m2p")))
-      return s;
-    for (int l = std::max(lo, 3); l <= hi; ++l)
-      if (P->m2p_range[l][0] == pr) {
-        P->pending_flops += P->work.m2p_flops[l];
-        P->pending_bytes += P->work.m2p_bytes[l];
-      }
-    prof_end(P, a, st, pr ? kM2P32 : kM2P64, -1);
-  }
-  // join: the far field needs the local expansions
+  // join: the leaf kernel needs the intermediate-field partials
   if (!serial && (s = dev_check(P, hipStreamWaitEvent(st, P->ev_join, 0), "join"))) return s;
   // far, near and nearest fields + output, per leaf level
   for (int l = std::max(lo, 1); l <= hi; ++l) {

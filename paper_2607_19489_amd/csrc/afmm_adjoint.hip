@@ -155,17 +155,19 @@ __global__ __launch_bounds__(256) void k_adj_near_m2p(const int32_t* __restrict_
   const int F = grp ? grp[blockIdx.x] : (int)blockIdx.x;
   const int t = threadIdx.x;
   if (t < 8) s_ref[t] = lv0.rank[8 * F + t];
+  int v = -1;
   if (t < 216) {
     const int e = t >> 3, op = t & 7;
     const int q = lv1.nbr[(size_t)F * 27 + e];
-    int v = -1;
     if (q >= 0) {
       const int rq = lv1.rank[q];
       if (rq >= 0 && lv0.rank[8 * rq + op] < 0) v = 8 * rq + op;
     }
     s_cand[t] = v;
   }
-  __syncthreads();
+  // no leaf among the candidates (inside a refined region): nothing reads the
+  // group's refined children here
+  if (!__syncthreads_or(v >= 0)) return;
   bool any = false;
   for (int o = 0; o < 8; ++o) any |= s_ref[o] >= 0;
   if (!any) return;

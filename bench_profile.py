@@ -101,29 +101,39 @@ def cmd_mfma(a):
     trace = list(csv.DictReader(open(_find(a.trace, "kernel_trace.csv"))))
     dur = {}
     for r in trace:
-        dur.setdefault(short(r["Kernel_Name"]), []).append(
-            (int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+        key = (short(r["Kernel_Name"]), r.get("Grid_Size_X") or r.get("Grid_Size"))
+        dur.setdefault(key, []).append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    rows = list(csv.DictReader(open(_find(a.pmc, "counter_collection.csv"))))
     out = [f"# Issued MFMA throughput: {a.title}", "",
            "Operation counts (rocprofv3 --pmc, SQ_INSTS_VALU_MFMA_MOPS_*: multiply and add operations / 512,",
-           "summed over the shader engines) per dispatch, over the average duration of the same kernel's",
-           "dispatches in a kernel trace of the same command (last N of each).  Issued operations include the",
-           "zero padding of the MFMA tiles; the useful-flop rate is the bench's own figure.  The M2L chain",
-           "runs on a second stream beside M2P here, so a traced duration can include time shared with the",
-           "other stream (the small FP64 M2L of the top FMM levels is such a case).", "",
+           "summed over the shader engines) per dispatch, over the median duration of the dispatches of the",
+           "same kernel and grid in a kernel trace of the same command (last N of each).  Issued operations",
+           "include the zero padding of the MFMA tiles; the useful-flop rate is the bench's own figure.  The",
+           "M2L chain runs on the caller's stream beside M2P on a second one, so a traced duration can",
+           "include time shared with the other stream; the median keeps such a dispatch out.", "",
            "Commands (repository root on the MI355X box):", "", "```", a.command_pmc, a.command_trace, "```", "",
-           "| kernel | counter | dispatches | issued GFLOP / dispatch | avg us (trace) | issued TFLOP/s | of peak |",
-           "|---|---|---|---|---|---|---|"]
+           "| kernel | grid | counter | dispatches | issued GFLOP / dispatch | median us (trace) | issued TFLOP/s | of peak |",
+           "|---|---|---|---|---|---|---|---|"]
     for counter, peak in PEAK_TFLOPS.items():
-        per = _pmc(a.pmc, counter)
-        for k, v in sorted(per.items()):
-            ops = [x for _, x in v[-a.last:]]
-            if not ops or max(ops) == 0 or k not in dur:
+        per = {}
+        for r in rows:
+            if r["Counter_Name"] != counter:
                 continue
-            d = sorted(dur[k])[-a.last:]
-            us = statistics.mean(x[1] for x in d) / 1e3
+            key = (short(r["Kernel_Name"]), r["Grid_Size"], r.get("Dispatch_Id", ""))
+            per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+        byk = {}
+        for (k, g, did), v in per.items():
+            byk.setdefault((k, g), []).append((int(did) if did.isdigit() else 0, v))
+        for (k, g), v in sorted(byk.items()):
+            v.sort()
+            ops = [x for _, x in v[-a.last:]]
+            if not ops or max(ops) == 0 or (k, g) not in dur:
+                continue
+            d = sorted(dur[(k, g)])[-a.last:]
+            us = statistics.median(x[1] for x in d) / 1e3
             gf = statistics.median(ops) * 512 / 1e9
             tf = gf / us * 1e3
-            out.append(f"| `{k}` | {counter[-3:]} | {len(ops)} | {gf:.2f} | {us:.1f} | {tf:.1f} | {tf / peak:.1%} |")
+            out.append(f"| `{k}` | {g} | {counter[-3:]} | {len(ops)} | {gf:.2f} | {us:.1f} | {tf:.1f} | {tf / peak:.1%} |")
     open(a.out, "w").write("\n".join(out) + "\n")
     print("\n".join(out))
 

@@ -74,7 +74,6 @@ template <typename T, int P>
 __device__ inline void m2p_row(const T* __restrict__ D, const T* __restrict__ S, T* out) {
   constexpr int K = nmi(P);
   constexpr int K1 = nmi(P - 1);
-  constexpr int STP = src_stp(P, (int)sizeof(T));
   constexpr MiTab<P> mt{};
   T phi = 0, ax = 0, ay = 0, az = 0;
 #pragma unroll
@@ -481,43 +480,24 @@ __device__ inline void tap_range(int c, int nsplit, int& tb, int& te) {
 }
 
 // Source of column n for tap `code`: refined rank (>= 0), -2 - cell for a leaf
-// (monopole), or -1 when there is none.  Resolved two taps ahead, in two
-// halves inside the tap loop: the level-(l-1) cell and the load of its rank
-// before the tap's MFMAs, the combination after them, so that the rank load
-// has the MFMA phase to land.
-__device__ inline int tap_cell(int code, int n, const int* __restrict__ sCB) {
-  const int cb = sCB[n * 27 + (code & 31)];
-  return cb < 0 ? -1 : cb + ((code >> 5) & 7);
-}
-__device__ inline int tap_code(int s, int rs) { return s < 0 ? -1 : (rs >= 0 ? rs : -2 - s); }
+// (monopole), or -1 when there is none.  The tap loops resolve the sources of
+// all their taps into LDS before the loop.
 __device__ inline int tap_src(int code, int n, const int* __restrict__ sCB, gptr<int32_t> rank1) {
-  const int s = tap_cell(code, n, sCB);
-  return tap_code(s, s < 0 ? -1 : rank1[s]);
+  const int cb = sCB[n * 27 + (code & 31)];
+  const int s = cb < 0 ? -1 : cb + ((code >> 5) & 7);
+  if (s < 0) return -1;
+  const int rs = rank1[s];
+  return rs >= 0 ? rs : -2 - s;
 }
 
-// B fragments of one tap for lane (n = lane & 15, g = lane >> 4): the first NV
-// 16-byte vectors of the lane's run (vector j holds steps kb = VW j .. VW j + VW-1).
-template <typename T, int P, int NV>
-__device__ inline void load_bfrag(int sr, int lane, gptr<double> mass1, gptr<T> S1, typename Vec16<T>::type* vb) {
-  using TS = TapStage<T, P>;
-  using V = typename Vec16<T>::type;
-  if (sr >= 0) {
-    gptr<T> src = S1 + (size_t)sr * TS::ROW;
-#pragma unroll
-    for (int j = 0; j < NV; ++j) vb[j] = *(gptr<V>)(src + src_vec(j, lane >> 4, (int)sizeof(T)));
-  } else {
-#pragma unroll
-    for (int j = 0; j < NV; ++j) vb[j] = V{};
-    if (sr <= -2 && (lane >> 4) == 0) vb[0][0] = (T)mass1[-2 - sr];
-  }
-}
-
-// Branch-free form for the M2P tap loop: a missing or leaf source reads the
-// zero row zrow after the level's nref rows, and every lane loads a mass (cell
-// 0 when the source is no leaf), put into the monopole slot when the tap is
-// used (bfrag_m0).  Only the NS steps used are loaded (a partial last vector
-// element by element): an element loaded but never read would leave a
-// register that the compiler reuses while the load is still in flight.
+// B fragments of one tap for lane (n = lane & 15, g = lane >> 4): the lane's
+// run of steps (16-byte vector j holds steps VW j .. VW j + VW - 1), without a
+// branch: a missing or leaf source reads the zero row zrow after the level's
+// nref rows, and every lane loads a mass (cell 0 when the source is no leaf),
+// put into the monopole slot when the tap is used (bfrag_m0).  Only the NS
+// steps used are loaded (a partial last vector element by element): an
+// element loaded but never read would leave a register that the compiler
+// reuses while the load is still in flight.
 template <typename T, int P, int NS>
 __device__ inline void load_bfrag_nb(int sr, int zrow, gptr<double> mass1, gptr<T> S1,
                                      typename Vec16<T>::type* vb, double& vm) {

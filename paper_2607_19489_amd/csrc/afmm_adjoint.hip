@@ -580,13 +580,23 @@ __global__ __launch_bounds__(64) void k_adj_m2l_mfma(const int32_t* __restrict__
 #pragma unroll
   for (int i = 0; i < PL.total; ++i) off[i] = aoff[i * 64 + lane];
   __syncthreads();
-  // local-expansion-bar row of child o of group rF (refined rank at level ls + 1), or -1
-  auto child = [&](int rF, int o) { return rF >= 0 ? lvt.rank[8 * rF + o] : -1; };
+  // Local-expansion-bar rows (refined ranks at level ls + 1) of the 8 children
+  // of a tap's group: loaded together one tap ahead, so that the B loads of a
+  // sub-step never wait for a rank.  Loads go through global-address pointers
+  // (flat loads would also count against the wait for the LDS A reads).
+  gptr<int32_t> rankt = as_global(lvt.rank);
+  gptr<T> lTg = as_global(lT);
+  auto children = [&](int rF, int* ry) {
+#pragma unroll
+    for (int o = 0; o < 8; ++o) ry[o] = rankt[8 * (rF >= 0 ? rF : 0) + o];
+#pragma unroll
+    for (int o = 0; o < 8; ++o) ry[o] = rF >= 0 ? ry[o] : -1;
+  };
   auto loadB = [&](int ry, V* b) {
     if (ry >= 0) {
-      const T* src = lT + (size_t)ry * ROW;
+      gptr<T> src = lTg + (size_t)ry * ROW;
 #pragma unroll
-      for (int j = 0; j < NVB; ++j) b[j] = *(const V*)(src + src_vec(j, g, (int)sizeof(T)));
+      for (int j = 0; j < NVB; ++j) b[j] = *(gptr<V>)(src + src_vec(j, g, (int)sizeof(T)));
     } else {
 #pragma unroll
       for (int j = 0; j < NVB; ++j) b[j] = V{};
@@ -597,17 +607,19 @@ __global__ __launch_bounds__(64) void k_adj_m2l_mfma(const int32_t* __restrict__
   for (int rt = 0; rt < RT; ++rt) acc[rt] = {0, 0, 0, 0};
   V bA[NVB], bB[NVB];
   V vD[ND];
-  int gcur = adj_group(sTap[tb], n, sCB, lvs.rank);
+  int ryc[8], ryn[8];
   int gnext = tb + 1 < te ? adj_group(sTap[tb + 1], n, sCB, lvs.rank) : -1;
-  loadB(child(gcur, 0), bA);
+  children(adj_group(sTap[tb], n, sCB, lvs.rank), ryc);
+  children(gnext, ryn);
+  loadB(ryc[0], bA);
   load_dstage_t<T, SDP, 64>(sTap[tb] >> 8, Dst, vD);
   store_dstage_t<T, SDP, 64>(sD[0], vD);
   __syncthreads();
   // sub-step (tap k, octant o): B of (k, o) in bc; prefetch (k, o+1) or (k+1, 0) into bn
   auto sub = [&](int k, int o, const V* bc, V* bn) {
     const int b = (k - tb) & 1;
-    if (o < 7) loadB(child(gcur, o + 1), bn);
-    else if (k + 1 < te) loadB(child(gnext, 0), bn);
+    if (o < 7) loadB(ryc[o + 1], bn);
+    else if (k + 1 < te) loadB(ryn[0], bn);
     const T* D = sD[b] + o * KS;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
@@ -624,8 +636,12 @@ __global__ __launch_bounds__(64) void k_adj_m2l_mfma(const int32_t* __restrict__
       sub(k, o + 1, bB, bA);
     }
     if (k + 1 < te) store_dstage_t<T, SDP, 64>(sD[b ^ 1], vD);
-    gcur = gnext;
-    if (k + 2 < te) gnext = adj_group(sTap[k + 2], n, sCB, lvs.rank);
+#pragma unroll
+    for (int o = 0; o < 8; ++o) ryc[o] = ryn[o];
+    if (k + 2 < te) {
+      gnext = adj_group(sTap[k + 2], n, sCB, lvs.rank);
+      children(gnext, ryn);
+    }
     __syncthreads();
   }
   const int s = sS[n];

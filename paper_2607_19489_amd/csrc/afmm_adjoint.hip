@@ -482,9 +482,10 @@ __global__ __launch_bounds__(64) void k_adj_m2p_mfma(const int32_t* __restrict__
 #pragma unroll
     for (int kb = 0; kb < 8; ++kb) off[rt][kb] = aoff[(rt * 8 + kb) * 64 + lane];
   __syncthreads();
+  gptr<T> tbTg = as_global(tbT);
   auto loadB = [&](int rF, V* b) {
     if (rF >= 0) {
-      const V* src = (const V*)(tbT + (size_t)rF * 32 + 8 * g);
+      gptr<V> src = (gptr<V>)(tbTg + (size_t)rF * 32 + 8 * g);
 #pragma unroll
       for (int j = 0; j < NVB; ++j) b[j] = src[j];
     } else {
@@ -500,27 +501,31 @@ __global__ __launch_bounds__(64) void k_adj_m2p_mfma(const int32_t* __restrict__
   int gn = adj_group(sTap[tb], n, sCB, lvs.rank);
   loadB(gn, bA);
   load_dstage_t<T, SDP, 64>(sTap[tb] >> 8, Dst, vD);
+  // both buffers hold finite rows from the start (the empty tap below reads one)
   store_dstage_t<T, SDP, 64>(sD[0], vD);
-  if (tb + 1 < te) gn = adj_group(sTap[tb + 1], n, sCB, lvs.rank);
+  store_dstage_t<T, SDP, 64>(sD[1], vD);
+  gn = adj_group(sTap[tb + 1 < te ? tb + 1 : tb], n, sCB, lvs.rank);
   __syncthreads();
-  auto step = [&](int k, const V* bc, V* bn) {
-    const int b = (k - tb) & 1;
-    if (k + 1 < te) {
-      loadB(gn, bn);
-      load_dstage_t<T, SDP, 64>(sTap[k + 1] >> 8, Dst, vD);
-    }
-    if (k + 2 < te) gn = adj_group(sTap[k + 2], n, sCB, lvs.rank);
+  // Taps run in pairs; an odd range ends with one empty tap (B zero), so that
+  // both steps of a pair run unconditionally (no accumulator moves between
+  // them).
+  const int te2 = tb + ((te - tb + 1) & ~1);
+  auto step = [&](int k, int b, const V* bc, V* bn) {
+    const int k1 = k + 1 < te ? k + 1 : te - 1;
+    loadB(k + 1 < te ? gn : -1, bn);
+    load_dstage_t<T, SDP, 64>(sTap[k1] >> 8, Dst, vD);
+    gn = adj_group(sTap[k + 2 < te ? k + 2 : te - 1], n, sCB, lvs.rank);
     const T* D = sD[b];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
       for (int kb = 0; kb < 8; ++kb) acc[rt] = mfma16(D[off[rt][kb]], bc[kb / VW][kb % VW], acc[rt]);
-    if (k + 1 < te) store_dstage_t<T, SDP, 64>(sD[b ^ 1], vD);
+    store_dstage_t<T, SDP, 64>(sD[b ^ 1], vD);
     __syncthreads();
   };
-  for (int k = tb; k < te; k += 2) {
-    step(k, bA, bB);
-    if (k + 1 < te) step(k + 1, bB, bA);
+  for (int k = tb; k < te2; k += 2) {
+    step(k, 0, bA, bB);
+    step(k + 1, 1, bB, bA);
   }
   const int s = sS[n];
   double* pp = nsplit > 1 ? part + ((size_t)chunk * ntiles + tile) * 16 * K : nullptr;

@@ -59,7 +59,7 @@ template <typename T, int SDP, int NTH>
 __device__ inline void load_dstage_t(int di, const T* __restrict__ Dst, typename Vec16<T>::type* vD) {
   using V = typename Vec16<T>::type;
   constexpr int NV = SDP / (16 / (int)sizeof(T)), NJ = (NV + NTH - 1) / NTH;
-  const V* src = (const V*)(Dst + (size_t)di * SDP);
+  gptr<V> src = (gptr<V>)as_global(Dst + (size_t)di * SDP);
   const int t = threadIdx.x;
 #pragma unroll
   for (int j = 0; j < NJ; ++j)

@@ -48,9 +48,12 @@ typedef int32_t afmm_status;
                                 f <= fp64_levels and the per-cell output in FP64 */
 
 #define AFMM_CHECK_INPUT 1u  /* scan masses for NaN/Inf before a solve (one host sync) */
-#define AFMM_SERIAL 2u       /* run every launch of a solve on the caller's stream (by default the
-                                M2L/L2L chain runs on an internal second stream, concurrently with
-                                the intermediate-field M2P); results are identical either way */
+#define AFMM_SERIAL 2u       /* every launch of a solve on the caller's stream (the default; wins
+                                over AFMM_OVERLAP) */
+#define AFMM_OVERLAP 4u      /* run the intermediate-field M2P on an internal second stream,
+                                concurrently with the M2L/L2L chain on the caller's stream.
+                                Results are identical either way; measured on MI355X the overlap
+                                does not pay (both launches fill the GPU), so it is off by default */
 
 #define AFMM_ALL_LEVELS (-1) /* synchronous solve: all trees rebuilt, every leaf evaluated */
 
@@ -59,7 +62,7 @@ typedef struct afmm_options {
   int32_t precision;         /* AFMM_FP64 or AFMM_FP32_MIXED */
   double G;                  /* gravitational constant */
   double boxlen;             /* box side */
-  uint32_t flags;            /* AFMM_CHECK_INPUT | AFMM_SERIAL */
+  uint32_t flags;            /* AFMM_CHECK_INPUT | AFMM_SERIAL | AFMM_OVERLAP */
   int32_t fp64_levels;       /* mixed form: FMM levels <= this stay FP64 (default 3) */
   int32_t tap_split;         /* M2L and M2P blocks per tile: the 189 source offsets of a tile are
                                 split over this many blocks and their partial sums reduced in a

@@ -15,6 +15,7 @@ AFMM_FP64 = 0
 AFMM_FP32_MIXED = 1
 AFMM_CHECK_INPUT = 1
 AFMM_SERIAL = 2
+AFMM_OVERLAP = 4
 AFMM_ALL_LEVELS = -1
 
 STATUS = {

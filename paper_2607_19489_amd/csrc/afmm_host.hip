@@ -907,7 +907,7 @@ afmm_status check_options(const afmm_options* o) {
   if (o->p < 1 || o->p > kPMax) return fail(AFMM_E_UNSUPPORTED, "p must be in 1..8");
   if (o->precision != AFMM_FP64 && o->precision != AFMM_FP32_MIXED)
     return fail(AFMM_E_UNSUPPORTED, "unknown precision");
-  if (o->flags & ~(AFMM_CHECK_INPUT | AFMM_SERIAL)) return fail(AFMM_E_UNSUPPORTED, "unknown flag");
+  if (o->flags & ~(AFMM_CHECK_INPUT | AFMM_SERIAL | AFMM_OVERLAP)) return fail(AFMM_E_UNSUPPORTED, "unknown flag");
   if (!(o->boxlen > 0) || !std::isfinite(o->boxlen)) return fail(AFMM_E_INVALID_ARG, "boxlen must be > 0");
   if (!std::isfinite(o->G)) return fail(AFMM_E_INVALID_ARG, "G must be finite");
   if (o->tap_split < 0 || o->tap_split > 21) return fail(AFMM_E_UNSUPPORTED, "tap_split must be in 0..21");
@@ -1469,7 +1469,7 @@ static afmm_status run_solve(afmm_plan* P, const double* msrc, int fmax, int lo,
   // small first launches get the CUs first and M2P fills the rest.  Serial
   // plans (and profiled solves: events then time one launch at a time) use
   // one stream.
-  const bool serial = (P->opt.flags & AFMM_SERIAL) || P->profiling;
+  const bool serial = !(P->opt.flags & AFMM_OVERLAP) || (P->opt.flags & AFMM_SERIAL) || P->profiling;
   hipStream_t sm = serial ? st : P->side;
   if (!serial && ((s = dev_check(P, hipEventRecord(P->ev_fork, st), "fork")) ||
                   (s = dev_check(P, hipStreamWaitEvent(sm, P->ev_fork, 0), "fork"))))

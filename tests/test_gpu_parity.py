@@ -97,9 +97,13 @@ def test_deterministic_and_untouched_entries():
     leaf = T.from_numpy(h.leaf_mask()).cuda()
     assert T.equal(phi1[leaf], phi2[leaf]) and T.equal(acc1[leaf], acc2[leaf])
     assert bool((phi1[~leaf] == 7.0).all()) and bool((acc1[~leaf] == 7.0).all())
-    # serial launches and profiled solves run the same arithmetic
+    # the two-stream schedule, serial launches and profiled solves run the same arithmetic
     plan_s = A.Plan(h, p=6, precision="fp32", serial=True)
     phi3, acc3 = plan_s.solve(mt)
+    plan_o = A.Plan(h, p=6, precision="fp32", overlap=True)
+    phi5, acc5 = plan_o.solve(mt)
+    T.cuda.synchronize()
+    assert T.equal(phi5[leaf], phi2[leaf]) and T.equal(acc5[leaf], acc2[leaf])
     plan.set_profiling(True)
     phi4, acc4 = plan.solve(mt)
     T.cuda.synchronize()

@@ -72,15 +72,17 @@ __global__ void k_adj_zero(size_t n, double* __restrict__ p) {
     p[i] = 0.0;
 }
 
-// P2P^T for the leaves s of level l (block = one group F of level l-1 with a
-// leaf child; s = its child o = t & 7).  The 216 candidates (children of F's
-// 27 neighbours, or the neighbour itself when it is a leaf) are resolved once
-// into LDS; partial sums are reduced by shuffles within a wave and through LDS
-// across waves.  Targets that read s through a P2P:
-//   level l leaves n among the children of F's 27 neighbours (near field),
+// P2P^T for the leaves s of level l from targets one level finer or coarser
+// (block = one group F of level l-1 with a leaf child; s = its child o = t &
+// 7).  The 216 candidates (children of F's 27 neighbours, or the neighbour
+// itself when it is a leaf) are resolved once into LDS; partial sums are
+// reduced by shuffles within a wave and through LDS across waves.  Targets
+// that read s through a P2P:
 //   level l+1 children of a refined level-l n touching s (s is in their near
 //     field as a coarse leaf),
 //   level l-1 leaves q touching F (s is in q's nearest field).
+// The same-level near field (level l leaves among the children of F's
+// neighbours) is k_adj_near_mfma.
 __global__ __launch_bounds__(256) void k_adj_near_leaf(const int32_t* __restrict__ grp, LevelDev lv1, LevelDev lv0,
                                                        LevelDev lvp) {
   enum { kNone = 0, kCoarse = 1, kLeaf = 2, kRefined = 3 };
@@ -124,9 +126,7 @@ __global__ __launch_bounds__(256) void k_adj_near_leaf(const int32_t* __restrict
         continue;
       }
       const int tx = sx - 2 * ex - ax_o(op, 0), ty = sy - 2 * ey - ax_o(op, 1), tz = sz - 2 * ez - ax_o(op, 2);
-      if (kind == kLeaf) {
-        if (idx != s) acc += p2p_adj(-tx, -ty, -tz, lv0.tbar + 4 * (size_t)idx);
-      } else if (max(abs(tx), max(abs(ty), abs(tz))) <= 1) {
+      if (kind == kRefined && max(abs(tx), max(abs(ty), abs(tz))) <= 1) {
         for (int o2 = 0; o2 < 8; ++o2)
           acc += p2p_adj(ax_o(o2, 0) - 0.5 - 2.0 * tx, ax_o(o2, 1) - 0.5 - 2.0 * ty, ax_o(o2, 2) - 0.5 - 2.0 * tz,
                          lvp.tbar + 4 * (size_t)(8 * idx + o2));
@@ -138,6 +138,66 @@ __global__ __launch_bounds__(256) void k_adj_near_leaf(const int32_t* __restrict
   if ((t & 63) < 8) s_red[t >> 6][o] = acc;
   __syncthreads();
   if (t < 8 && lv0.rank[s] < 0) lv0.mbar[s] += s_red[0][o] + s_red[1][o] + s_red[2][o] + s_red[3][o];
+}
+
+// Same-level near field transposed (the P2P^T of the forward near operator's
+// leaf columns): for a source group F (level l-1) its children receive
+//   m_bar[8F + op] += sum_{e', o, q} W[op][32 e' + 4 o + q] T[8 F' + o][q],
+// F' = F's neighbour e' (a refined cell, else no term), T the unit-form target
+// bars, W = adjNearA (the forward weights of slot 8 (26 - e') + op).  As an
+// FP64 MFMA product [16 x 864] . [864 x 16 groups] with rows 8..15 zero; the
+// 4 waves of a block take a quarter of the 216 steps each and wave 0 adds
+// the others' accumulators in order.
+__global__ __launch_bounds__(256) void k_adj_near_mfma(const int32_t* __restrict__ grp, int ngrp, LevelDev lv1,
+                                                       LevelDev lv0, const double* __restrict__ W) {
+  constexpr int NKB = 216, KW = NKB / 4;
+  __shared__ int sF[16];
+  __shared__ int sRF[16 * 27];
+  __shared__ double sAcc[3][4][64];
+  const int ntiles = (ngrp + 15) / 16;
+  const int tile = xcd_tile(ntiles);
+  if (tile >= ntiles) return;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63, n = lane & 15, g = lane >> 4;
+  if (t < 16) sF[t] = 16 * tile + t < ngrp ? grp[16 * tile + t] : -1;
+  __syncthreads();
+  for (int i = t; i < 16 * 27; i += 256) {
+    const int c = i / 27, e = i - 27 * c;
+    const int F = sF[c];
+    int v = -1;
+    if (F >= 0) {
+      const int q = lv1.nbr[(size_t)F * 27 + e];
+      if (q >= 0) v = lv1.rank[q];
+    }
+    sRF[i] = v;
+  }
+  __syncthreads();
+  gptr<double> tb = as_global(lv0.tbar);
+  gptr<double> Wg = as_global(W);
+  f64x4 acc = {0, 0, 0, 0};
+  double bv[KW];
+#pragma unroll
+  for (int i = 0; i < KW; ++i) {
+    const int k = 4 * (KW * w + i) + g;
+    const int rF = sRF[n * 27 + (k >> 5)];
+    const double v = tb[32 * (size_t)(rF >= 0 ? rF : 0) + (k & 31)];
+    bv[i] = rF >= 0 ? v : 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < KW; ++i) acc = mfma16(Wg[(size_t)(KW * w + i) * 64 + lane], bv[i], acc);
+  if (w > 0)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) sAcc[w - 1][r][lane] = acc[r];
+  __syncthreads();
+  const int F = sF[n];
+  if (w > 0 || F < 0) return;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const double v = acc[r] + sAcc[0][r][lane] + sAcc[1][r][lane] + sAcc[2][r][lane];
+    const int op = acc_row<double>(g, r);
+    if (op >= 8) continue;
+    const int s = 8 * F + op;
+    if (lv0.rank[s] < 0) lv0.mbar[s] += v;
+  }
 }
 
 // Near-field M2P^T: a refined level-l cell s is read, through 2^-|a| times its
@@ -697,11 +757,17 @@ hipError_t launch_adj_zero(double* p, size_t n, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_adj_near(int p, const int32_t* leafgrp, int nleafgrp, const int32_t* refgrp, int nrefgrp,
-                           const LevelDev& lv1, const LevelDev& lv0, const LevelDev& lvp, int targets_here,
-                           const TablesDev<double>& t64, const CommonDev& cm, hipStream_t st) {
+hipError_t launch_adj_near(int p, const int32_t* leafgrp, int nleafgrp, const int32_t* vgrp, int nvgrp,
+                           const int32_t* refgrp, int nrefgrp, const LevelDev& lv1, const LevelDev& lv0,
+                           const LevelDev& lvp, int targets_here, const TablesDev<double>& t64, const CommonDev& cm,
+                           hipStream_t st) {
   if (lv1.nref == 0) return hipSuccess;
-  if (nleafgrp > 0) hipLaunchKernelGGL(k_adj_near_leaf, dim3(nleafgrp), dim3(256), 0, st, leafgrp, lv1, lv0, lvp);
+  if (targets_here && nleafgrp > 0) {
+    const int ntiles = (nleafgrp + 15) / 16;
+    hipLaunchKernelGGL(k_adj_near_mfma, dim3(8 * ((ntiles + 7) / 8)), dim3(256), 0, st, leafgrp, nleafgrp, lv1, lv0,
+                       t64.adjNearA);
+  }
+  if (nvgrp > 0) hipLaunchKernelGGL(k_adj_near_leaf, dim3(nvgrp), dim3(256), 0, st, vgrp, lv1, lv0, lvp);
   if (!targets_here || !lv0.sbar || nrefgrp == 0) return hipGetLastError();
   // refgrp == nullptr: every refined cell of level l-1
   const int nb = refgrp ? nrefgrp : lv1.nref;

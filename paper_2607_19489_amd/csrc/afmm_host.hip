@@ -57,6 +57,8 @@ struct Topology {
   std::vector<int32_t> leafgrp[kMaxLevel];  // index l: refined ranks at l-1 with a leaf child
   std::vector<int32_t> m2lgrp[kMaxLevel];   // index f: refined ranks at f-1 with a refined child
   std::vector<int32_t> nmgrp[kMaxLevel];    // index l: leafgrp entries with a refined level-l near candidate
+  std::vector<int32_t> adjvgrp[kMaxLevel];  // index l: leafgrp entries with a coarse leaf neighbour or a
+                                            // refined near candidate (adjoint VALU near relations)
   std::vector<int32_t> upleaf[kMaxLevel];   // index f: refined ranks at f whose 8 children are leaves
   std::vector<int32_t> upmix[kMaxLevel];    // index f: refined ranks at f with a refined child
   // per hierarchy
@@ -242,16 +244,23 @@ static void build_groups(Topology& T) {
     // groups whose near candidates (children of the 27 neighbours of F)
     // include a refined level-l cell: their near-field M2P runs apart
     auto& nm = T.nmgrp[l];
+    auto& av = T.adjvgrp[l];
     nm.clear();
+    av.clear();
     for (int32_t r : lg) {
-      bool any = false;
+      bool any = false, coarse = false;
       const int32_t* nb = &P.nbr[(size_t)r * 27];
-      for (int e = 0; e < 27 && !any; ++e) {
+      for (int e = 0; e < 27; ++e) {
         const int32_t q = nb[e];
-        if (q < 0 || P.rank[q] < 0) continue;
+        if (q < 0) continue;
+        if (P.rank[q] < 0) {
+          coarse = true;
+          continue;
+        }
         for (int op = 0; op < 8 && !any; ++op) any = C.rank[8 * P.rank[q] + op] >= 0;
       }
       if (any) nm.push_back(r);
+      if (any || coarse) av.push_back(r);
     }
   }
 }
@@ -767,6 +776,7 @@ struct afmm_plan {
   int32_t* d_leafgrp[kMaxLevel] = {};
   int32_t* d_m2lgrp[kMaxLevel] = {};
   int32_t* d_nmgrp[kMaxLevel] = {};
+  int32_t* d_adjvgrp[kMaxLevel] = {};
   int32_t* d_upleaf[kMaxLevel] = {};  // upward lists (Topology::upleaf / upmix)
   int32_t* d_upmix[kMaxLevel] = {};
   void* d_nmp[kMaxLevel] = {};   // near-field M2P partials of level l (leaf-kernel precision)
@@ -1141,6 +1151,7 @@ static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
     if ((s = upload(P, T.leafgrp[l], &P->d_leafgrp[l], st))) return s;
     if ((s = upload(P, T.m2lgrp[l], &P->d_m2lgrp[l], st))) return s;
     if ((s = upload(P, T.nmgrp[l], &P->d_nmgrp[l], st))) return s;
+    if ((s = upload(P, T.adjvgrp[l], &P->d_adjvgrp[l], st))) return s;
     if ((s = upload(P, T.upleaf[l], &P->d_upleaf[l], st))) return s;
     if ((s = upload(P, T.upmix[l], &P->d_upmix[l], st))) return s;
     if (!T.nmgrp[l].empty()) {
@@ -1228,6 +1239,23 @@ static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
     return v;
   };
   if ((s = upload_conv<double>(P, near_vec(8), &P->t64.nearA, st))) return s;
+  // the same-level part transposed, for the adjoint: row op (source child of
+  // the column's group, rows 8..15 zero), column 32 e' + 4 o + q: target child
+  // o of the group's neighbour e', quantity q (the forward row 8 q + o), whose
+  // group sees the source at slot 8 (26 - e') + op
+  {
+    const int NKB = near_ksteps(P->opt.p);
+    auto Aat = [&](int R, int k) { return H.nearA[((size_t)(R >> 4) * NKB + (k >> 2)) * 64 + (R & 15) + 16 * (k & 3)]; };
+    std::vector<double> at((size_t)216 * 64, 0.0);
+    for (int kb = 0; kb < 216; ++kb)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int row = lane & 15, kk = 4 * kb + (lane >> 4);
+        if (row >= 8) continue;
+        const int e = kk >> 5, j = kk & 31, o = j >> 2, q = j & 3;
+        at[(size_t)kb * 64 + lane] = Aat(8 * q + o, 8 * (26 - e) + row);
+      }
+    if ((s = upload_conv<double>(P, at, &P->t64.adjNearA, st))) return s;
+  }
   if (mixed && (s = upload_conv<float>(P, near_vec(4), &P->t32.nearA, st))) return s;
   if ((s = upload_conv<double>(P, H.Dsame, &P->t64.Dsame, st)) ||
       (s = upload_conv<double>(P, H.cfac2, &P->t64.cfac2, st)) || (s = upload_conv<double>(P, H.cfacn, &P->t64.cfacn, st)) ||
@@ -1960,8 +1988,9 @@ static afmm_status afmm_solve_adjoint_impl(afmm_plan* P, int32_t level, const do
     const int nlg = (int)T.leafgrp[l].size();
     const int nrg = l >= 3 ? (int)T.m2lgrp[l].size() : P->lv[l - 1].nref;
     if ((s = dev_check(P,
-                       launch_adj_near(p, P->d_leafgrp[l], nlg, l >= 3 ? P->d_m2lgrp[l] : nullptr, nrg, P->lv[l - 1],
-                                       P->lv[l], lvp, tgt, P->t64, P->cm, st),
+                       launch_adj_near(p, P->d_leafgrp[l], nlg, P->d_adjvgrp[l], (int)T.adjvgrp[l].size(),
+                                       l >= 3 ? P->d_m2lgrp[l] : nullptr, nrg, P->lv[l - 1], P->lv[l], lvp, tgt,
+                                       P->t64, P->cm, st),
                        "adjoint near")))
       return s;
     if (tgt && l - 1 >= 3 && P->lv[l - 1].lbar &&

@@ -128,6 +128,7 @@ struct TablesDev {
   const T* l2lw = nullptr;    // [8][p+1][K] L2L weights 2^(-1-|b|) u^g/g! per child octant and |b|
   const T* l2p = nullptr;     // [8][4][K] L2P weights (phi, ax, ay, az) per child octant
   const T* nearA = nullptr;   // [2][near_ksteps / VW][64][VW] near-field operator, MFMA A layout
+  const T* adjNearA = nullptr;  // [216][64] transposed same-level near field (adjoint), MFMA A layout
 };
 
 struct CommonDev {
@@ -182,9 +183,14 @@ hipError_t launch_batch_out(int64_t nleaf, const int32_t* leafslot, const int32_
 hipError_t launch_adj_init(const LevelDev& lv, int target, const double* phib, const double* accb, double sp,
                            double sa, hipStream_t st);
 hipError_t launch_adj_zero(double* p, size_t n, hipStream_t st);
-hipError_t launch_adj_near(int p, const int32_t* leafgrp, int nleafgrp, const int32_t* refgrp, int nrefgrp,
-                           const LevelDev& lv1, const LevelDev& lv0, const LevelDev& lvp, int targets_here,
-                           const TablesDev<double>& t64, const CommonDev& cm, hipStream_t st);
+// Adjoint near field of level l: the same-level P2P^T of the leaf groups as
+// one MFMA product (targets_here only), the coarse and nearest P2P^T of the
+// groups in vgrp (those with a leaf neighbour one level coarser or a refined
+// near candidate), the near M2P^T of refgrp.
+hipError_t launch_adj_near(int p, const int32_t* leafgrp, int nleafgrp, const int32_t* vgrp, int nvgrp,
+                           const int32_t* refgrp, int nrefgrp, const LevelDev& lv1, const LevelDev& lv0,
+                           const LevelDev& lvp, int targets_here, const TablesDev<double>& t64, const CommonDev& cm,
+                           hipStream_t st);
 hipError_t launch_adj_l2p(int p, const int32_t* grp, int ngrp, const LevelDev& lv1, const LevelDev& lv0,
                           const TablesDev<double>& t64, const CommonDev& cm, hipStream_t st);
 // MFMA forms: tiles of 16 source cells (records: target level, 16 cells); with

@@ -210,10 +210,12 @@ __global__ __launch_bounds__(256) void k_adj_near_m2p(const int32_t* __restrict_
                                                       const double* __restrict__ cfacn,
                                                       const int16_t* __restrict__ up) {
   constexpr int K = nmi(P), K1 = nmi(P - 1);
-  __shared__ int s_cand[216];
+  __shared__ int s_slot[216];     // candidate slots 8 e + op with a leaf, in slot order
+  __shared__ double s_tb[216][4]; // their target bars
   __shared__ int s_ref[8];
+  __shared__ int s_cnt[4];
   const int F = grp ? grp[blockIdx.x] : (int)blockIdx.x;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   if (t < 8) s_ref[t] = lv0.rank[8 * F + t];
   int v = -1;
   if (t < 216) {
@@ -223,32 +225,47 @@ __global__ __launch_bounds__(256) void k_adj_near_m2p(const int32_t* __restrict_
       const int rq = lv1.rank[q];
       if (rq >= 0 && lv0.rank[8 * rq + op] < 0) v = 8 * rq + op;
     }
-    s_cand[t] = v;
   }
+  // leaf candidates compacted in slot order (ballot per wave, wave counts in LDS)
+  const uint64_t m = __ballot(v >= 0);
+  if (lane == 0) s_cnt[w] = __popcll(m);
   // no leaf among the candidates (inside a refined region): nothing reads the
   // group's refined children here
   if (!__syncthreads_or(v >= 0)) return;
+  int base = 0, nlist = 0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    base += u < w ? s_cnt[u] : 0;
+    nlist += s_cnt[u];
+  }
+  if (v >= 0) {
+    const int pos = base + __popcll(m & ((1ull << lane) - 1ull));
+    s_slot[pos] = t;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) s_tb[pos][c] = lv0.tbar[4 * (size_t)v + c];
+  }
+  __syncthreads();
   bool any = false;
   for (int o = 0; o < 8; ++o) any |= s_ref[o] >= 0;
   if (!any) return;
+  gptr<double> Dg = as_global(Dsame);
   for (int i = t; i < 8 * K; i += 256) {
     const int o = i / K, a = i - o * K;
     const int rs = s_ref[o];
     if (rs < 0) continue;
+    const int u0 = a < K1 ? up[3 * a + 0] : 0, u1 = a < K1 ? up[3 * a + 1] : 0, u2 = a < K1 ? up[3 * a + 2] : 0;
     double acc = 0.0;
-    for (int k = 0; k < 216; ++k) {
-      const int n = s_cand[k];
-      if (n < 0) continue;
+    for (int j = 0; j < nlist; ++j) {
+      const int k = s_slot[j];
       const int e = k >> 3, op = k & 7;
       const int dx = 2 * ax_e(e, 0) + ax_o(op, 0) - ax_o(o, 0);
       const int dy = 2 * ax_e(e, 1) + ax_o(op, 1) - ax_o(o, 1);
       const int dz = 2 * ax_e(e, 2) + ax_o(op, 2) - ax_o(o, 2);
       if (max(abs(dx), max(abs(dy), abs(dz))) <= 1) continue;
-      const double* D = Dsame + (size_t)dsame_index(dx, dy, dz) * K;
-      const double* tb = lv0.tbar + 4 * (size_t)n;
-      double v = D[a] * tb[0];
-      if (a < K1) v -= D[up[3 * a + 0]] * tb[1] + D[up[3 * a + 1]] * tb[2] + D[up[3 * a + 2]] * tb[3];
-      acc += v;
+      gptr<double> D = Dg + (size_t)dsame_index(dx, dy, dz) * K;
+      double v2 = D[a] * s_tb[j][0];
+      if (a < K1) v2 -= D[u0] * s_tb[j][1] + D[u1] * s_tb[j][2] + D[u2] * s_tb[j][3];
+      acc += v2;
     }
     lv0.sbar[(size_t)rs * K + a] += cfacn[a] * acc;
   }

@@ -398,13 +398,17 @@ __global__ __launch_bounds__(256) void k_adj_down(LevelDev lv1, LevelDev lv0, Co
   __shared__ double sW[NE];
   const int rp = blockIdx.x;
   const int t = threadIdx.x;
+  const int rc0 = t < 8 ? lv0.rank[8 * rp + t] : -1;
+  if (t < 8) sR[t] = rc0;
+  // no refined child: nothing to pass down (most cells of a finely refined
+  // level); leave before staging the tables
+  if (!__syncthreads_or(rc0 >= 0)) return;
   for (int i = t; i < K; i += 256) sP[i] = lv1.sbar[(size_t)rp * K + i];
   for (int i = t; i <= K; i += 256) sStart[i] = cm.m2mT_start[i];
   for (int i = t; i < NE; i += 256) {
     sList[i] = cm.m2mT_list[i];
     sW[i] = cm.m2mT_w[i];
   }
-  if (t < 8) sR[t] = lv0.rank[8 * rp + t];
   __syncthreads();
   for (int i = t; i < 8 * K; i += 256) {
     const int o = i / K, k = i - o * K;

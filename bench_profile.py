@@ -108,9 +108,9 @@ def cmd_mfma(a):
            "Operation counts (rocprofv3 --pmc, SQ_INSTS_VALU_MFMA_MOPS_*: multiply and add operations / 512,",
            "summed over the shader engines) per dispatch, over the median duration of the dispatches of the",
            "same kernel and grid in a kernel trace of the same command (last N of each).  Issued operations",
-           "include the zero padding of the MFMA tiles; the useful-flop rate is the bench's own figure.  The",
-           "M2L chain runs on the caller's stream beside M2P on a second one, so a traced duration can",
-           "include time shared with the other stream; the median keeps such a dispatch out.", "",
+           "include the zero padding of the MFMA tiles; the useful-flop rate is the bench's own figure.  Every",
+           "launch of a solve runs on the caller's one stream, so a traced duration is one launch alone.  The",
+           "grids other than the autotuned one are the tuner's candidate tap splits.", "",
            "Commands (repository root on the MI355X box):", "", "```", a.command_pmc, a.command_trace, "```", "",
            "| kernel | grid | counter | dispatches | issued GFLOP / dispatch | median us (trace) | issued TFLOP/s | of peak |",
            "|---|---|---|---|---|---|---|---|"]

@@ -880,11 +880,20 @@ __device__ inline void m2l_part(const int32_t* __restrict__ tp, int nt, const in
   }
 }
 
+// Occupancy floor of k_m2l_mfma: for FP32 up to p = 6 the kernel fits 128
+// registers without spilling, so its LDS (4 blocks per CU) sets 4 waves per
+// SIMD; left to itself the compiler takes about 176 registers and 2 waves,
+// and the M2L launches ran about 8% slower.  Other instantiations keep the
+// compiler's choice (a floor there spills).
+template <typename T, int P>
+constexpr int m2l_min_waves() { return sizeof(T) == 4 && P <= 6 ? 4 : 1; }
+
 // One block = one tile (16 groups) and one of `nsplit` contiguous tap ranges.
 // With nsplit == 1 the sums go straight to L; otherwise to the level's
 // partial buffer [nsplit][nref][K], reduced in fixed order by k_l2l.
 template <typename T, int P>
-__global__ __launch_bounds__(kBlock) void k_m2l_mfma(const int32_t* __restrict__ tiles, int ntiles, int nsplit,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(m2l_min_waves<T, P>())))
+void k_m2l_mfma(const int32_t* __restrict__ tiles, int ntiles, int nsplit,
                                                      const int32_t* __restrict__ taps,
                                                      const int16_t* __restrict__ aoff,
                                                      const LevelDev* __restrict__ lvs, const T* __restrict__ Dst) {

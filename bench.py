@@ -142,7 +142,7 @@ def time_adjoint(h, mass_t, p, precision, steps):
     plan.close()
     adj = {k: v for k, v in prof.items() if k.startswith("adj_")}
     return {"forward_ms": 1e3 * t_fwd, "adjoint_ms": 1e3 * t_adj, "adjoint_over_forward": t_adj / t_fwd,
-            "adjoint_precision": "f64", "kernels": kernel_table({"kernels": adj, "steps": steps}),
+            "adjoint_precision": "per level as the forward (fp32 form)" if precision == "fp32" else "f64", "kernels": kernel_table({"kernels": adj, "steps": steps}),
             "forward_kernels": kernel_table({"kernels": fwd_prof, "steps": steps})}
 
 

@@ -12,6 +12,7 @@
 //
 // Deterministic: no atomics; every sum runs in a fixed order.
 #include <hip/hip_runtime.h>
+#include <algorithm>
 
 #include "afmm_internal.h"
 #include "afmm_mfma.h"
@@ -473,7 +474,7 @@ __device__ inline int compact_taps(int nt, const int32_t* __restrict__ tp, int* 
 // Tap range of chunk c of nsplit: whole pairs of taps (the tap loops run in
 // pairs), so that only the last chunk has an odd count and runs one empty tap.
 // The host keeps nsplit <= 21, so every range holds at least 8 taps.
-__device__ inline void tap_range(int c, int nsplit, int& tb, int& te) {
+__host__ __device__ inline void tap_range(int c, int nsplit, int& tb, int& te) {
   constexpr int kPairs = (kTaps + 1) / 2;
   tb = 2 * (c * kPairs / nsplit);
   te = min(kTaps, 2 * ((c + 1) * kPairs / nsplit));
@@ -577,8 +578,14 @@ __device__ inline void tile_setup(const int32_t* __restrict__ rec, int NC, const
 // the tiles of every level of one precision.  One block takes one of `nsplit`
 // contiguous tap ranges of its tile and writes its own partial set
 // part[chunk][F][...], summed in order by the leaf kernel.
+// From p = 6 on the launcher sizes the LDS source table for 2 waves per SIMD
+// (the best measured there); the same bound lets the compiler use the
+// registers of that occupancy.
+template <int P>
+constexpr int m2p_max_waves() { return P >= 6 ? 2 : 8; }
+
 template <typename T, int P>
-__global__ __launch_bounds__(64) void k_m2p(const int32_t* __restrict__ tiles, int ntiles, int nsplit,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, m2p_max_waves<P>()))) void k_m2p(const int32_t* __restrict__ tiles, int ntiles, int nsplit,
                                             const int32_t* __restrict__ taps, const int16_t* __restrict__ aoff,
                                             const LevelDev* __restrict__ lvs, const T* __restrict__ Dst) {
   using TS = TapStage<T, P>;
@@ -590,7 +597,7 @@ __global__ __launch_bounds__(64) void k_m2p(const int32_t* __restrict__ tiles, i
   __shared__ __align__(16) T sD[2][TS::SDP];
   __shared__ int sF[16];
   __shared__ int sCB[16 * 27];
-  __shared__ int sSrcT[kTaps * 16];
+  extern __shared__ int sSrcT[];  // [taps of the longest range][16], sized by the launcher
   const int item = xcd_tile(ntiles * nsplit);
   if (item >= ntiles * nsplit) return;
   const int tile = item / nsplit, chunk = item - tile * nsplit;
@@ -883,10 +890,13 @@ __device__ inline void m2l_part(const int32_t* __restrict__ tp, int nt, const in
 // Occupancy floor of k_m2l_mfma: for FP32 up to p = 6 the kernel fits 128
 // registers without spilling, so its LDS (4 blocks per CU) sets 4 waves per
 // SIMD; left to itself the compiler takes about 176 registers and 2 waves,
-// and the M2L launches ran about 8% slower.  Other instantiations keep the
-// compiler's choice (a floor there spills).
+// and the M2L launches ran about 8% slower.  At p = 8 (FP32) a floor of 2
+// waves (256 registers, 20 bytes of spill, against 348 registers and 1 wave)
+// ran 28% faster.  Other instantiations keep the compiler's choice (p = 7
+// already runs 2 waves, and a floor of 3 spills; FP64 spills at any floor that
+// would raise its occupancy).
 template <typename T, int P>
-constexpr int m2l_min_waves() { return sizeof(T) == 4 && P <= 6 ? 4 : 1; }
+constexpr int m2l_min_waves() { return sizeof(T) != 4 ? 1 : P <= 6 ? 4 : P == 8 ? 2 : 1; }
 
 // One block = one tile (16 groups) and one of `nsplit` contiguous tap ranges.
 // With nsplit == 1 the sums go straight to L; otherwise to the level's
@@ -1204,10 +1214,24 @@ static hipError_t m2p_dispatch(int p, const MfmaTiles& mt, int t0, int n, int ns
   const int items = n * nsplit;
   const dim3 grid(8 * ((items + 7) / 8)), block(64);
   const int32_t* tl = mt.tiles + (size_t)t0 * 17;
+  // LDS source table of k_m2p: the longest tap range of the split, except
+  // from p = 6 on, where the table keeps all 189 taps so that the block's LDS
+  // (about 20 KB) holds the kernel at 2 waves per SIMD.  Measured: at p = 6,
+  // 2 waves per SIMD beat 3 and 4 (the 16 source rows each wave streams thrash
+  // L1 when more waves share it); at p = 4 the short tap (14 MFMAs) leaves the
+  // waits exposed, and the smaller table with its higher occupancy ran 14%
+  // faster at a split of 3.
+  int ntmax = 0;
+  for (int c = 0; c < nsplit; ++c) {
+    int tb, te;
+    tap_range(c, nsplit, tb, te);
+    ntmax = std::max(ntmax, te - tb);
+  }
+  const size_t lds = (size_t)(p >= 6 ? kTaps : ntmax) * 16 * sizeof(int);
   switch (p) {
-#define AFMM_M2P(PP)                                                                                              \
-  case PP:                                                                                                  \
-    hipLaunchKernelGGL((k_m2p<T, PP>), grid, block, 0, st, tl, n, nsplit, tabs.taps, tabs.m2p_off, lvs, Dst);  \
+#define AFMM_M2P(PP)                                                                                                \
+  case PP:                                                                                                    \
+    hipLaunchKernelGGL((k_m2p<T, PP>), grid, block, lds, st, tl, n, nsplit, tabs.taps, tabs.m2p_off, lvs, Dst);  \
     break;
     AFMM_M2P(1) AFMM_M2P(2) AFMM_M2P(3) AFMM_M2P(4) AFMM_M2P(5) AFMM_M2P(6) AFMM_M2P(7) AFMM_M2P(8)
 #undef AFMM_M2P

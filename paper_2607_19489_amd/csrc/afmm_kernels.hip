@@ -578,14 +578,14 @@ __device__ inline void tile_setup(const int32_t* __restrict__ rec, int NC, const
 // the tiles of every level of one precision.  One block takes one of `nsplit`
 // contiguous tap ranges of its tile and writes its own partial set
 // part[chunk][F][...], summed in order by the leaf kernel.
-// From p = 6 on the launcher sizes the LDS source table for 2 waves per SIMD
-// (the best measured there); the same bound lets the compiler use the
+// For FP32 from p = 6 on the launcher sizes the LDS source table for 2 waves
+// per SIMD (the best measured there); the same bound lets the compiler use the
 // registers of that occupancy.
-template <int P>
-constexpr int m2p_max_waves() { return P >= 6 ? 2 : 8; }
+template <typename T, int P>
+constexpr int m2p_max_waves() { return sizeof(T) == 4 && P >= 6 ? 2 : 8; }
 
 template <typename T, int P>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, m2p_max_waves<P>()))) void k_m2p(const int32_t* __restrict__ tiles, int ntiles, int nsplit,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, m2p_max_waves<T, P>()))) void k_m2p(const int32_t* __restrict__ tiles, int ntiles, int nsplit,
                                             const int32_t* __restrict__ taps, const int16_t* __restrict__ aoff,
                                             const LevelDev* __restrict__ lvs, const T* __restrict__ Dst) {
   using TS = TapStage<T, P>;
@@ -1215,19 +1215,19 @@ static hipError_t m2p_dispatch(int p, const MfmaTiles& mt, int t0, int n, int ns
   const dim3 grid(8 * ((items + 7) / 8)), block(64);
   const int32_t* tl = mt.tiles + (size_t)t0 * 17;
   // LDS source table of k_m2p: the longest tap range of the split, except
-  // from p = 6 on, where the table keeps all 189 taps so that the block's LDS
-  // (about 20 KB) holds the kernel at 2 waves per SIMD.  Measured: at p = 6,
-  // 2 waves per SIMD beat 3 and 4 (the 16 source rows each wave streams thrash
-  // L1 when more waves share it); at p = 4 the short tap (14 MFMAs) leaves the
-  // waits exposed, and the smaller table with its higher occupancy ran 14%
-  // faster at a split of 3.
+  // for FP32 from p = 6 on, where the table keeps all 189 taps so that the
+  // block's LDS (about 20 KB) holds the kernel at 2 waves per SIMD.  Measured:
+  // FP32 at p = 6, 2 waves per SIMD beat 3 and 4 (the 16 source rows each wave
+  // streams thrash L1 when more waves share it); FP32 at p = 4 (a short tap of
+  // 14 MFMAs leaves the waits exposed) and FP64 at p = 6 ran 7-9% faster with
+  // the smaller table at a split of 3.
   int ntmax = 0;
   for (int c = 0; c < nsplit; ++c) {
     int tb, te;
     tap_range(c, nsplit, tb, te);
     ntmax = std::max(ntmax, te - tb);
   }
-  const size_t lds = (size_t)(p >= 6 ? kTaps : ntmax) * 16 * sizeof(int);
+  const size_t lds = (size_t)(sizeof(T) == 4 && p >= 6 ? kTaps : ntmax) * 16 * sizeof(int);
   switch (p) {
 #define AFMM_M2P(PP)                                                                                                \
   case PP:                                                                                                    \

@@ -45,6 +45,37 @@ def test_small_amr_all_orders(p):
     compare(h, m, p, "fp32", 1e-4)
 
 
+_SPLIT_CASE = {}
+
+
+def _split_case(p):
+    """A two-level AMR hierarchy and its oracle solution, computed once per order."""
+    if p not in _SPLIT_CASE:
+        h = _amr(3, {3: 0.3, 4: 0.2})
+        m = cell_masses(h, plummer(1.0, 0.1), 0.01, 40 + p)
+        po, ao = oracle.Oracle(h, p).solve_all(m)
+        _SPLIT_CASE[p] = (h, m, po, ao)
+    return _SPLIT_CASE[p]
+
+
+@pytest.mark.parametrize("p", [4, 6])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("split", [1, 2, 3, 7, 21])
+def test_explicit_tap_splits(p, precision, split):
+    """Every tap split (1 to 21 blocks per tile, ranges of 8 to 189 taps, the
+    per-launch LDS source table of M2P sized from them) against the oracle."""
+    h, m, po, ao = _split_case(p)
+    print(f"tap split {split} p={p} {precision}", flush=True)
+    phi, acc, _ = gpu_solve(h, m, p, precision, tap_split=split)
+    leaf = h.leaf_mask()
+    tol = 1e-10 if precision == "fp64" else 1e-4
+    assert rel_l2(acc[leaf], ao[leaf]) <= tol and rel_l2(phi[leaf], po[leaf]) <= tol
+    assert max_rel(acc[leaf], ao[leaf]) <= 10 * tol
+    # a split changes only the order of the partial sums
+    phi1, acc1, _ = gpu_solve(h, m, p, precision, tap_split=1)
+    assert rel_l2(acc[leaf], acc1[leaf]) <= (1e-13 if precision == "fp64" else 1e-5)
+
+
 def test_three_level_amr_fp32_and_fp64():
     h = _amr(4, {4: 0.25, 5: 0.15, 6: 0.08})
     m = cell_masses(h, plummer(1.0, 0.05), 0.01, 9)

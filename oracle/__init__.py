@@ -67,6 +67,9 @@ def lib():
         L.oracle_m2p.argtypes = [C.c_int, dp, dp, dp]
         L.oracle_chain_check.argtypes = [P, C.c_int, C.POINTER(C.c_double)]
         L.oracle_num_threads.argtypes = []
+        L.oracle_set_options.argtypes = [P, C.c_int, C.c_int]
+        L.oracle_self_constant.argtypes = []
+        L.oracle_self_constant.restype = C.c_double
         _lib = L
     return _lib
 
@@ -149,10 +152,15 @@ def num_threads() -> int:
     return int(lib().oracle_num_threads())
 
 
+def self_constant() -> float:
+    """Integral of 1/|r| over the unit cube centred at the origin (the oracle's quadrature)."""
+    return float(lib().oracle_self_constant())
+
+
 class Oracle:
     """Literal per-level-tree FMM on one hierarchy (see ``afmm_oracle.c``)."""
 
-    def __init__(self, h, p: int, G: float = 1.0):
+    def __init__(self, h, p: int, G: float = 1.0, quad_cap: bool = False, self_potential: bool = False):
         self.h = h
         self.p = p
         self.G = G
@@ -162,6 +170,8 @@ class Oracle:
         ncell = np.ascontiguousarray(h.ncell, dtype=np.int64)
         _check(lib().oracle_create(h.levelmin, h.levelmax, ncell, ijk, ref, p, G, h.boxlen,
                                    C.byref(self._ptr)), "create")
+        # the paper's multipole cap (order p - 1) and the optional self-potential term
+        _check(lib().oracle_set_options(self._ptr, int(bool(quad_cap)), int(bool(self_potential))), "set_options")
         self.N = h.total
         self.offsets = h.offsets
 

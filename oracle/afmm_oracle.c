@@ -182,8 +182,9 @@ static double mfact(const int *a) { return g_fact[a[0]] * g_fact[a[1]] * g_fact[
 /* ------------------------------------------------------------------ */
 /* the four translation steps of Sec. 2, multi-index form              */
 /* ------------------------------------------------------------------ */
-/* Eq. eq:M2L: L_b = sum_{|a| <= p-|b|} (-1)^|a| / a! D_{a+b}(R) M_a, R = c_target - c_source */
-static void op_m2l(int p, const double R[3], const double *M, double *L, double scale) {
+/* Eq. eq:M2L: L_b = sum_{|a| <= p-|b|} (-1)^|a| / a! D_{a+b}(R) M_a, R = c_target - c_source;
+   multipoles enter up to order pm (p, or p - 1 with the paper's cap of Sec. 2) */
+static void op_m2l(int p, int pm, const double R[3], const double *M, double *L, double scale) {
   double D[NMI];
   derivs(p, R, D);
   int K = nmi_of(p);
@@ -194,7 +195,7 @@ static void op_m2l(int p, const double R[3], const double *M, double *L, double 
     for (int a = 0; a < K; ++a) {
       const int *aa = g_mi[a];
       int na = aa[0] + aa[1] + aa[2];
-      if (na + nb > p) continue;
+      if (na + nb > p || na > pm) continue;
       double sg = (na & 1) ? -1.0 : 1.0;
       s += sg / mfact(aa) * D[g_idx[aa[0] + bb[0]][aa[1] + bb[1]][aa[2] + bb[2]]] * M[a];
     }
@@ -237,8 +238,9 @@ static void op_l2p(int p, const double u[3], const double *L, double *phi, doubl
   for (int i = 0; i < 3; ++i) acc[i] -= g[i];
 }
 
-/* multipole (about its centre) evaluated at R = x - c: Taylor series of Sec. 2 */
-static void op_m2p(int p, const double R[3], const double *M, double *phi, double acc[3]) {
+/* multipole (about its centre) evaluated at R = x - c: Taylor series of Sec. 2, multipoles up to
+   order pm (the gradient terms need |a| + 1 <= p, so they never see order p) */
+static void op_m2p(int p, int pm, const double R[3], const double *M, double *phi, double acc[3]) {
   double D[NMI];
   derivs(p, R, D);
   int K = nmi_of(p);
@@ -246,6 +248,7 @@ static void op_m2p(int p, const double R[3], const double *M, double *phi, doubl
   for (int a = 0; a < K; ++a) {
     const int *aa = g_mi[a];
     int na = aa[0] + aa[1] + aa[2];
+    if (na > pm) continue;
     double w = ((na & 1) ? -1.0 : 1.0) / mfact(aa) * M[a];
     f += w * D[a];
     if (na + 1 <= p)
@@ -350,6 +353,8 @@ typedef struct {
 
 typedef struct oracle_state {
   int levelmin, levelmax, p, K;
+  int pm;                  /* highest multipole order used by M2L/M2P: p, or p - 1 with the cap */
+  double cself;            /* self-potential constant (unit cube), 0 when the term is off */
   double G, boxlen;
   int64_t ncell[MAXLEV], off[MAXLEV + 1];
   int32_t *ijk;            /* flat [N][3] */
@@ -417,6 +422,7 @@ int oracle_create(int levelmin, int levelmax, const int64_t *ncell, const int32_
   oracle_state *s = (oracle_state *)calloc(1, sizeof(oracle_state));
   if (!s) return OR_E_NOMEM;
   s->levelmin = levelmin; s->levelmax = levelmax; s->p = p; s->K = nmi_of(p);
+  s->pm = p; s->cself = 0.0;
   s->G = G; s->boxlen = boxlen;
   int64_t N = 0;
   for (int l = levelmin; l <= levelmax; ++l) {
@@ -475,6 +481,40 @@ int oracle_create(int levelmin, int levelmax, const int64_t *ncell, const int32_
 }
 
 void oracle_set_merged_all(oracle_state *s, int on) { s->merged_all = on; }
+
+/*
+ * Self-potential constant C = integral over the unit cube centred at the
+ * origin of 1/|r| (reading R11: a leaf's own mass as a uniform cube, whose
+ * potential at its centre is -G m C / h).  C is 8 times the integral over the
+ * octant [0, 1/2]^3.  There the z-integral is elementary,
+ *   int_0^{1/2} dz / sqrt(rho^2 + z^2) = asinh(1 / (2 rho)),  rho^2 = x^2 + y^2,
+ * and in polar coordinates over the square [0, 1/2]^2 (two symmetric halves,
+ * 0 <= theta <= pi/4, rho up to 1 / (2 cos theta)) so is the rho-integral:
+ *   int rho asinh(1 / (2 rho)) drho = F(rho) = rho^2/2 asinh(1/(2 rho)) + sqrt(rho^2 + 1/4)/4,
+ * F(0) = 1/8.  What is left, C = 16 int_0^{pi/4} [F(1/(2 cos theta)) - 1/8] dtheta,
+ * has a smooth integrand and is summed with a composite Simpson rule.
+ */
+static double self_F(double rho) { return 0.5 * rho * rho * asinh(0.5 / rho) + 0.25 * sqrt(rho * rho + 0.25); }
+double oracle_self_constant(void) {
+  const int n = 4096; /* even */
+  const double b = atan(1.0), h = b / n;
+  double sum = 0.0;
+  for (int i = 0; i <= n; ++i) {
+    double t = i * h;
+    double f = self_F(0.5 / cos(t)) - 0.125;
+    sum += f * (i == 0 || i == n ? 1.0 : (i & 1) ? 4.0 : 2.0);
+  }
+  return 16.0 * sum * h / 3.0;
+}
+
+/* Model options: AFMM-style paper cap (multipoles to order p - 1, Sec. 2 with
+   reading R1) and the optional self-potential term (reading R11). */
+int oracle_set_options(oracle_state *s, int quad_cap, int self_potential) {
+  if (!s) return OR_E_INVALID;
+  s->pm = quad_cap ? s->p - 1 : s->p;
+  s->cself = self_potential ? oracle_self_constant() : 0.0;
+  return OR_OK;
+}
 
 static uint64_t morton3(int64_t x, int64_t y, int64_t z) {
   uint64_t k = 0;
@@ -674,7 +714,7 @@ static void m2l_src(void *uu, int lev, const int64_t sc[3], int64_t idx) {
     if (idx >= 0 && !s->refined[idx]) M[0] += leafmass_of(s, lev, idx);
     const double *A = grid_row(&u->c->all[lev], sc, K);
     if (A) for (int q = 0; q < K; ++q) M[q] += A[q];
-    op_m2l(s->p, R, M, u->L, 1.0);
+    op_m2l(s->p, s->pm, R, M, u->L, 1.0);
     return;
   }
   /* Alg. 3: trees j = max(lmin, f-1) .. l one by one, then the merged tree */
@@ -685,16 +725,16 @@ static void m2l_src(void *uu, int lev, const int64_t sc[3], int64_t idx) {
         double M[NMI];
         memset(M, 0, sizeof(double) * K);
         M[0] = leafmass_of(s, lev, idx);
-        op_m2l(s->p, R, M, u->L, 1.0);
+        op_m2l(s->p, s->pm, R, M, u->L, 1.0);
       }
       continue;
     }
     const double *M = grid_row(&s->tree[j].g[lev], sc, K);
-    if (M) op_m2l(s->p, R, M, u->L, 1.0);
+    if (M) op_m2l(s->p, s->pm, R, M, u->L, 1.0);
   }
   if (l < s->levelmax) {
     const double *M = grid_row(&u->c->mrg[lev], sc, K);
-    if (M) op_m2l(s->p, R, M, u->L, 1.0);
+    if (M) op_m2l(s->p, s->pm, R, M, u->L, 1.0);
   }
 }
 
@@ -719,14 +759,14 @@ static void m2p_src(void *uu, int lev, const int64_t sc[3], int64_t idx) {
   }
   if (s->merged_all) {
     const double *A = grid_row(&u->c->all[lev], sc, K);
-    if (A) op_m2p(s->p, R, A, &u->phi, u->acc);
+    if (A) op_m2p(s->p, s->pm, R, A, &u->phi, u->acc);
     return;
   }
   const double *M = grid_row(&s->tree[l].g[lev], sc, K);       /* T_{l;l-1} (blue dots) */
-  if (M) op_m2p(s->p, R, M, &u->phi, u->acc);
+  if (M) op_m2p(s->p, s->pm, R, M, &u->phi, u->acc);
   if (l < s->levelmax) {
     const double *Mm = grid_row(&u->c->mrg[lev], sc, K);       /* ~T_{l+1;l-1} (green dots) */
-    if (Mm) op_m2p(s->p, R, Mm, &u->phi, u->acc);
+    if (Mm) op_m2p(s->p, s->pm, R, Mm, &u->phi, u->acc);
   }
 }
 
@@ -804,10 +844,12 @@ static int eval_leaf(const oracle_state *s, const evalctx *c, int64_t flat, doub
       } else {                                        /* M2P from ~T_{l+1;l} */
         const double *M = s->merged_all ? grid_row(&c->all[l], n3, K) : grid_row(&c->mrg[l], n3, K);
         if (!M) return OR_E_STATE;
-        op_m2p(s->p, R, M, &p_near, a_near);
+        op_m2p(s->p, s->pm, R, M, &p_near, a_near);
       }
     }
   }
+  /* optional self term: the leaf's own mass as a uniform cube (reading R11) */
+  if (s->cself != 0.0) p_near -= s->cself * leafmass_of(s, l, flat) / csize(s, l);
   double G = s->G;
   *phi = G * (p_far + mu.phi + p_near + p_nst);
   for (int k = 0; k < 3; ++k) acc[k] = G * (a_far[k] + mu.acc[k] + a_near[k] + a_nst[k]);
@@ -1017,7 +1059,7 @@ int oracle_m2m(int p, const double *t, const double *M, double *Mout) {
 int oracle_m2l(int p, const double *R, const double *M, double *L) {
   init_tables();
   memset(L, 0, sizeof(double) * nmi_of(p));
-  op_m2l(p, R, M, L, 1.0);
+  op_m2l(p, p, R, M, L, 1.0);
   return OR_OK;
 }
 int oracle_l2l(int p, const double *a, const double *L, double *Lout) {
@@ -1036,7 +1078,7 @@ int oracle_l2p(int p, const double *u, const double *L, double *out4) {
 int oracle_m2p(int p, const double *R, const double *M, double *out4) {
   init_tables();
   double ph = 0, a[3] = {0, 0, 0};
-  op_m2p(p, R, M, &ph, a);
+  op_m2p(p, p, R, M, &ph, a);
   out4[0] = ph; out4[1] = a[0]; out4[2] = a[1]; out4[3] = a[2];
   return OR_OK;
 }

@@ -37,7 +37,7 @@ typedef int32_t afmm_status;
 #define AFMM_E_INVALID_ARG (-1)    /* null pointer, bad size, out-of-range coordinate, duplicate cell */
 #define AFMM_E_NOT_GRADED (-2)     /* refinement breaks the graded-octree rule of Sec. 3.2 */
 #define AFMM_E_INCOMPLETE_OCT (-3) /* a refined cell without its 8 children, or an orphan cell */
-#define AFMM_E_UNSUPPORTED (-4)    /* p outside 1..8, unknown precision or flag */
+#define AFMM_E_UNSUPPORTED (-4)    /* p outside 1..8, unknown precision or flag, tap_split outside 0..21 */
 #define AFMM_E_OUT_OF_MEMORY (-5)  /* device or host allocation failed, or max_device_bytes exceeded */
 #define AFMM_E_DEVICE (-6)         /* HIP runtime error; sticky on the plan */
 #define AFMM_E_ATS_ORDER (-7)      /* solve(l, icount) needs trees that were never built */
@@ -47,7 +47,10 @@ typedef int32_t afmm_status;
 #define AFMM_FP32_MIXED 1    /* M2L, M2P, L2L, L2P and P2P in FP32; P2M, M2M, FMM levels
                                 f <= fp64_levels and the per-cell output in FP64 */
 
-#define AFMM_CHECK_INPUT 1u  /* scan masses for NaN/Inf before a solve (one host sync) */
+#define AFMM_CHECK_INPUT 1u  /* before a solve, scan the leaf masses that it reads (every leaf slot
+                                for a full solve; the leaf slots of levels >= l when solve(l, .)
+                                rebuilds trees; none otherwise) for NaN/Inf; one host sync, no
+                                allocation (the flag lives in the plan) */
 #define AFMM_SERIAL 2u       /* every launch of a solve on the caller's stream (the default; wins
                                 over AFMM_OVERLAP) */
 #define AFMM_OVERLAP 4u      /* run the intermediate-field M2P on an internal second stream,
@@ -55,14 +58,31 @@ typedef int32_t afmm_status;
                                 Results are identical either way; measured on MI355X the overlap
                                 does not pay (both launches fill the GPU), so it is off by default */
 
+#define AFMM_PAPER_QUAD_CAP 8u
+                             /* the paper's expansion setting (Sec. 2: local expansions to order p,
+                                multipoles only up to the quadrupole at p = 3): every multipole that
+                                enters M2L, M2P or the near-field M2P is truncated at order p - 1.
+                                Accelerations only use multipoles of order <= p - 1 (the gradient
+                                lowers the admissible order by one), so they are unchanged bit for
+                                bit; potentials lose the order-p terms. */
+#define AFMM_SELF_POTENTIAL 16u
+                             /* add each leaf's own contribution to its potential, the potential at
+                                the centre of a uniform cube of the leaf's mass m and side h:
+                                phi_self = -G m C / h, C = integral of 1/|r| over the unit cube
+                                centred at the origin (about 2.38, computed numerically by the
+                                library).  The pair sums exclude the self pair (1/r is singular);
+                                the acceleration of a uniform cube at its centre is zero, so only
+                                the potential changes. */
+
 #define AFMM_ALL_LEVELS (-1) /* synchronous solve: all trees rebuilt, every leaf evaluated */
 
 typedef struct afmm_options {
-  int32_t p;                 /* expansion order, 1..8 */
+  int32_t p;                 /* expansion order, 1..8 (the paper's own setting is p = 3) */
   int32_t precision;         /* AFMM_FP64 or AFMM_FP32_MIXED */
   double G;                  /* gravitational constant */
   double boxlen;             /* box side */
-  uint32_t flags;            /* AFMM_CHECK_INPUT | AFMM_SERIAL | AFMM_OVERLAP */
+  uint32_t flags;            /* AFMM_CHECK_INPUT | AFMM_SERIAL | AFMM_OVERLAP | AFMM_PAPER_QUAD_CAP |
+                                AFMM_SELF_POTENTIAL */
   int32_t fp64_levels;       /* mixed form: FMM levels <= this stay FP64 (default 3) */
   int32_t tap_split;         /* M2L and M2P blocks per tile: the 189 source offsets of a tile are
                                 split over this many blocks and their partial sums reduced in a
@@ -170,7 +190,9 @@ afmm_status afmm_solve_adjoint(afmm_plan* plan, int32_t level, const double* d_p
  * scatter of the results -- is captured once into a hipGraph at creation and
  * replayed by afmm_batch_solve as one graph launch.
  *   plans[i]       plans built by afmm_plan_create (one hierarchy each); all must
- *                  share p, precision, G, boxlen, fp64_levels and tap_split.  The
+ *                  share p, precision, G, boxlen, fp64_levels, tap_split and the
+ *                  AFMM_PAPER_QUAD_CAP / AFMM_SELF_POTENTIAL flags (the batch solves
+ *                  with them; the scheduling flags of the members are ignored).  The
  *                  batch copies their topology: they may be destroyed afterwards.
  *   hip_stream     orders the uploads and the graph capture.
  * afmm_batch_solve: d_mass[i], d_phi[i], d_acc[i] are device pointers laid out as

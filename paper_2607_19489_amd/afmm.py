@@ -11,8 +11,8 @@ from typing import Optional, Sequence
 import numpy as np
 import torch
 
-from ._lib import (AFMM_ALL_LEVELS, AFMM_CHECK_INPUT, AFMM_FP32_MIXED, AFMM_FP64, AFMM_OVERLAP, AFMM_SERIAL, HierarchyC, Options,
-                   PlanInfo, StageTime, TuneResult, check, lib)
+from ._lib import (AFMM_ALL_LEVELS, AFMM_CHECK_INPUT, AFMM_FP32_MIXED, AFMM_FP64, AFMM_OVERLAP, AFMM_PAPER_QUAD_CAP,
+                   AFMM_SELF_POTENTIAL, AFMM_SERIAL, HierarchyC, Options, PlanInfo, StageTime, TuneResult, check, lib)
 
 PRECISIONS = {"fp64": AFMM_FP64, "fp32": AFMM_FP32_MIXED, "mixed": AFMM_FP32_MIXED}
 
@@ -42,7 +42,8 @@ def _hier_struct(levelmin, levelmax, ncell, ijk, ref):
 
 def make_options(p: int = 4, precision: str = "fp64", G: float = 1.0, boxlen: float = 1.0,
                  fp64_levels: int = 3, check_input: bool = False, max_device_bytes: int = 0,
-                 tap_split: int = 0, serial: bool = False, overlap: bool = False) -> Options:
+                 tap_split: int = 0, serial: bool = False, overlap: bool = False,
+                 quad_cap: bool = False, self_potential: bool = False) -> Options:
     o = Options()
     lib().afmm_options_default(C.byref(o))
     o.p = p
@@ -52,17 +53,18 @@ def make_options(p: int = 4, precision: str = "fp64", G: float = 1.0, boxlen: fl
     o.fp64_levels = fp64_levels
     o.tap_split = tap_split
     o.flags = ((AFMM_CHECK_INPUT if check_input else 0) | (AFMM_SERIAL if serial else 0)
-               | (AFMM_OVERLAP if overlap else 0))
+               | (AFMM_OVERLAP if overlap else 0) | (AFMM_PAPER_QUAD_CAP if quad_cap else 0)
+               | (AFMM_SELF_POTENTIAL if self_potential else 0))
     o.max_device_bytes = max_device_bytes
     return o
 
 
-def hierarchy_check(h, p: int = 4, precision: str = "fp64") -> dict:
+def hierarchy_check(h, p: int = 4, precision: str = "fp64", **opts) -> dict:
     """Host-only validation and work counts (no device needed)."""
     arrs = _hierarchy_arrays(h)
     hc = _hier_struct(*arrs)
     info = PlanInfo()
-    o = make_options(p, precision, boxlen=float(getattr(h, "boxlen", 1.0)))
+    o = make_options(p, precision, boxlen=float(getattr(h, "boxlen", 1.0)), **opts)
     check(lib().afmm_hierarchy_check(C.byref(hc), C.byref(o), C.byref(info)), "afmm_hierarchy_check")
     return info.as_dict()
 
@@ -81,7 +83,8 @@ class Plan:
     def __init__(self, h, p: int = 4, precision: str = "fp64", G: float = 1.0,
                  boxlen: Optional[float] = None, fp64_levels: int = 3, check_input: bool = False,
                  max_device_bytes: int = 0, tap_split: int = 0, serial: bool = False,
-                 overlap: bool = False, stream: Optional[torch.cuda.Stream] = None):
+                 overlap: bool = False, quad_cap: bool = False, self_potential: bool = False,
+                 stream: Optional[torch.cuda.Stream] = None):
         self._ptr = C.c_void_p()
         arrs = _hierarchy_arrays(h)
         self.levelmin, self.levelmax, self.ncell = arrs[0], arrs[1], arrs[2]
@@ -89,7 +92,7 @@ class Plan:
         hc = _hier_struct(*arrs)
         bl = float(boxlen if boxlen is not None else getattr(h, "boxlen", 1.0))
         self.options = make_options(p, precision, G, bl, fp64_levels, check_input, max_device_bytes, tap_split,
-                                    serial, overlap)
+                                    serial, overlap, quad_cap, self_potential)
         check(lib().afmm_plan_create(C.byref(hc), C.byref(self.options), _stream_handle(stream),
                                      C.byref(self._ptr)), "afmm_plan_create")
         self.p = p

@@ -431,14 +431,16 @@ __global__ void k_adj_scale(LevelDev lv0, CommonDev cm) {
   lv0.sbar[i] *= cm.cfac2[i % K];
 }
 
-// Mass bars to the caller's slots: leaf cells of rebuilt levels get their bar,
-// every other slot of the level gets 0.
-__global__ void k_adj_out(LevelDev lv0, int rebuilt, double* __restrict__ mbar_out) {
+// Mass bars to the caller's slots: leaf cells of rebuilt levels get their bar
+// (plus the transpose of the optional self term: the unit-form potential of a
+// target holds -cself m, so its bar adds -cself T_phi), every other slot of
+// the level gets 0.
+__global__ void k_adj_out(LevelDev lv0, int rebuilt, double cself, double* __restrict__ mbar_out) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= lv0.n) return;
   const int s = lv0.slot[c];
   if (s < 0) return;
-  mbar_out[s] = (rebuilt && lv0.rank[c] < 0) ? lv0.mbar[c] : 0.0;
+  mbar_out[s] = (rebuilt && lv0.rank[c] < 0) ? lv0.mbar[c] - cself * lv0.tbar[4 * (size_t)c] : 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -845,7 +847,7 @@ hipError_t launch_adj_down(int p, const LevelDev& lv1, const LevelDev& lv0, int 
 }
 
 hipError_t launch_adj_out(int p, const LevelDev& lv1, const LevelDev& lv0, int has_parent, int rebuilt,
-                          const CommonDev& cm, double* mbar_out, hipStream_t st) {
+                          double cself, const CommonDev& cm, double* mbar_out, hipStream_t st) {
   if (lv0.n == 0) return hipSuccess;
   if (has_parent && lv1.nref > 0) {
 #define X(PP) \
@@ -853,7 +855,7 @@ hipError_t launch_adj_out(int p, const LevelDev& lv1, const LevelDev& lv0, int h
     AFMM_P_SWITCH(p, X)
 #undef X
   }
-  hipLaunchKernelGGL(k_adj_out, dim3((lv0.n + 255) / 256), dim3(256), 0, st, lv0, rebuilt, mbar_out);
+  hipLaunchKernelGGL(k_adj_out, dim3((lv0.n + 255) / 256), dim3(256), 0, st, lv0, rebuilt, cself, mbar_out);
   return hipGetLastError();
 }
 

@@ -760,6 +760,48 @@ static void build_tables(int p, HostTables& H) {
   }
 }
 
+// Potential at the centre of a uniform unit cube of unit mass, up to -G/h:
+// C = integral over [-1/2, 1/2]^3 of 1/|r|.  Splitting the cube into the six
+// pyramids from its centre to its faces and integrating along the rays
+// r = t (1/2, y, z), 0 <= t <= 1 (volume element t^2/2 dt dy dz, so the radial
+// integral of 1/|r| gives 1/2 times 1/2) leaves a smooth surface integral per
+// face; with its four symmetric quarters,
+// C = 6 * int_0^{1/2} int_0^{1/2} (1/4 + y^2 + z^2)^(-1/2) dy dz,
+// computed with a tensor Gauss-Legendre rule whose nodes come from Newton
+// iterations on the Legendre polynomial.
+static double cube_self_constant() {
+  constexpr int N = 48;
+  long double x[N], w[N];
+  for (int i = 0; i < N; ++i) {
+    long double t = std::cos(3.14159265358979323846264338327950288L * (i + 0.75L) / (N + 0.5L));
+    for (int it = 0; it < 100; ++it) {
+      long double p0 = 1.0L, p1 = t;
+      for (int k = 2; k <= N; ++k) {
+        const long double p2 = ((2.0L * k - 1.0L) * t * p1 - (k - 1.0L) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      const long double dp = N * (t * p1 - p0) / (t * t - 1.0L);
+      const long double dt = p1 / dp;
+      t -= dt;
+      if (std::fabs(dt) < 1e-19L) {
+        x[i] = t;
+        w[i] = 2.0L / ((1.0L - t * t) * dp * dp);
+        break;
+      }
+      x[i] = t;
+      w[i] = 2.0L / ((1.0L - t * t) * dp * dp);
+    }
+  }
+  long double sum = 0.0L;
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      const long double y = 0.25L * (x[i] + 1.0L), z = 0.25L * (x[j] + 1.0L);  // nodes on [0, 1/2]
+      sum += w[i] * w[j] / std::sqrt(0.25L + y * y + z * z);
+    }
+  return (double)(6.0L * 0.0625L * sum);  // (1/4)^2: the Jacobian of [-1, 1]^2 -> [0, 1/2]^2
+}
+
 }  // namespace afmm
 
 // ---------------------------------------------------------------------------
@@ -806,6 +848,9 @@ struct afmm_plan {
   TablesDev<double> t64;
   CommonDev cm;
   double* m_snap = nullptr;       // adaptive-time-step snapshot of leaf masses (slot space)
+  int* d_flag = nullptr;          // AFMM_CHECK_INPUT: device flag of the input scan (plan-owned)
+  int* h_flag = nullptr;          // its pinned host copy
+  double cself = 0.0;             // AFMM_SELF_POTENTIAL: the unit-cube constant, else 0
   bool snap_valid = false;
   // the per-level masses and merged multipoles on the device were computed from
   // the current snapshot m_snap (a solve that rebuilds no tree can skip them)
@@ -898,6 +943,8 @@ void free_plan(afmm_plan* P) {
   if (P->side) (void)hipStreamSynchronize(P->side);
   for (void* p : P->allocs) (void)hipFree(p);
   P->allocs.clear();
+  if (P->h_flag) (void)hipHostFree(P->h_flag);
+  P->h_flag = nullptr;
   if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
   if (P->ev_join) (void)hipEventDestroy(P->ev_join);
   if (P->side) (void)hipStreamDestroy(P->side);
@@ -917,7 +964,8 @@ afmm_status check_options(const afmm_options* o) {
   if (o->p < 1 || o->p > kPMax) return fail(AFMM_E_UNSUPPORTED, "p must be in 1..8");
   if (o->precision != AFMM_FP64 && o->precision != AFMM_FP32_MIXED)
     return fail(AFMM_E_UNSUPPORTED, "unknown precision");
-  if (o->flags & ~(AFMM_CHECK_INPUT | AFMM_SERIAL | AFMM_OVERLAP)) return fail(AFMM_E_UNSUPPORTED, "unknown flag");
+  if (o->flags & ~(AFMM_CHECK_INPUT | AFMM_SERIAL | AFMM_OVERLAP | AFMM_PAPER_QUAD_CAP | AFMM_SELF_POTENTIAL))
+    return fail(AFMM_E_UNSUPPORTED, "unknown flag");
   if (!(o->boxlen > 0) || !std::isfinite(o->boxlen)) return fail(AFMM_E_INVALID_ARG, "boxlen must be > 0");
   if (!std::isfinite(o->G)) return fail(AFMM_E_INVALID_ARG, "G must be finite");
   if (o->tap_split < 0 || o->tap_split > 21) return fail(AFMM_E_UNSUPPORTED, "tap_split must be in 0..21");
@@ -1049,16 +1097,27 @@ static void dev_free(afmm_plan* P, void* ptr, size_t bytes) {
   P->bytes -= bytes;
 }
 
-// Partial-sum buffers of the tap splits: M2P partial sets per leaf level and
-// M2L tap-range partials per FMM level, for the plan's current splits.  Frees
-// earlier ones (after a device sync) and refreshes the device copy of lv[].
-static afmm_status alloc_split_buffers(afmm_plan* P) {
+// Bytes of the partial-sum buffers that the given splits need (the M2P partial
+// sets per leaf level, the M2L tap-range partials per FMM level).
+static size_t split_buffer_bytes(const afmm_plan* P, const int* m2l_split, const int* m2p_split) {
   const Topology& T = P->topo;
-  const int K = P->K;
-  afmm_status s;
-  const bool had = P->d_lvs != nullptr;
-  if (had && hipDeviceSynchronize() != hipSuccess) return fail(AFMM_E_DEVICE, "sync before reallocation");
-  for (int l = 0; l <= T.lmax; ++l) {
+  size_t total = 0;
+  for (int l = 3; l <= T.lmax; ++l) {
+    if (T.leafgrp[l].empty()) continue;
+    const int pr = P->m2p_range[l][0];
+    total += (size_t)m2p_split[pr] * T.lv[l - 1].nref() * 32 * (pr ? sizeof(float) : sizeof(double));
+  }
+  for (int f = 3; f <= T.lmax - 1; ++f) {
+    const int pm = P->m2l_range[f][0];
+    if (m2l_split[pm] > 1 && P->m2l_range[f][2] > 0)
+      total += (size_t)m2l_split[pm] * T.lv[f].nref() * P->K * (pm ? sizeof(float) : sizeof(double));
+  }
+  return total;
+}
+
+// Frees the partial-sum buffers of every level (callers synchronise first).
+static void release_split_buffers(afmm_plan* P) {
+  for (int l = 0; l <= P->topo.lmax; ++l) {
     LevelDev& D = P->lv[l];
     dev_free(P, D.part, D.part_bytes);
     dev_free(P, D.Lpart, D.Lpart_bytes);
@@ -1066,29 +1125,72 @@ static afmm_status alloc_split_buffers(afmm_plan* P) {
     D.part_bytes = D.Lpart_bytes = 0;
     D.npart = 0;
   }
-  for (int l = 3; l <= T.lmax; ++l) {
+}
+
+// Allocates the partial-sum buffers for the plan's current splits into lv[];
+// on failure frees what it allocated and leaves every level without buffers.
+static afmm_status place_split_buffers(afmm_plan* P) {
+  const Topology& T = P->topo;
+  const int K = P->K;
+  afmm_status s = AFMM_OK;
+  for (int l = 3; l <= T.lmax && !s; ++l) {
     if (T.leafgrp[l].empty()) continue;
     const int pr = P->m2p_range[l][0];
     const size_t b = (size_t)P->m2p_split[pr] * T.lv[l - 1].nref() * 32 * (pr ? sizeof(float) : sizeof(double));
     void* q = nullptr;
-    if ((s = dev_alloc(P, &q, b))) return s;
+    if ((s = dev_alloc(P, &q, b))) break;
     P->lv[l - 1].part = q;
     P->lv[l - 1].part_bytes = b;
     P->lv[l - 1].npart = P->m2p_split[pr];
   }
-  for (int f = 3; f <= T.lmax - 1; ++f) {
+  for (int f = 3; f <= T.lmax - 1 && !s; ++f) {
     const int pm = P->m2l_range[f][0];
     if (P->m2l_split[pm] > 1 && P->m2l_range[f][2] > 0) {
       const size_t b = (size_t)P->m2l_split[pm] * T.lv[f].nref() * K * (pm ? sizeof(float) : sizeof(double));
       void* q = nullptr;
-      if ((s = dev_alloc(P, &q, b))) return s;
+      if ((s = dev_alloc(P, &q, b))) break;
       P->lv[f].Lpart = q;
       P->lv[f].Lpart_bytes = b;
     }
   }
-  if (had && hipMemcpy(P->d_lvs, P->lv, sizeof(LevelDev) * (kMaxLevel + 1), hipMemcpyHostToDevice) != hipSuccess)
+  if (s) release_split_buffers(P);
+  return s;
+}
+
+// Partial-sum buffers for the plan's current splits (m2l_split / m2p_split),
+// replacing earlier ones.  The old buffers are released first (after a device
+// sync: kernels may still read them), so that a cap on device memory never
+// has to hold both sets.  If the new ones cannot be allocated (max_device_bytes
+// or hipMalloc) and the caller passes the previous splits, those splits and
+// buffers of their size are restored and the error returned: the plan stays
+// consistent.  Only if even that fails is the plan marked unusable.  The
+// device copy of lv[] is refreshed in every case.
+static afmm_status alloc_split_buffers(afmm_plan* P, const int* prev_m2l = nullptr, const int* prev_m2p = nullptr) {
+  const bool had = P->d_lvs != nullptr;
+  if (had && hipDeviceSynchronize() != hipSuccess) {
+    P->dead = true;
+    return fail(AFMM_E_DEVICE, "sync before reallocation");
+  }
+  release_split_buffers(P);
+  afmm_status s = place_split_buffers(P);
+  if (s) {
+    const std::string why = g_last_error;
+    if (prev_m2l && prev_m2p) {
+      for (int pr = 0; pr < 2; ++pr) {
+        P->m2l_split[pr] = prev_m2l[pr];
+        P->m2p_split[pr] = prev_m2p[pr];
+      }
+      if (place_split_buffers(P)) P->dead = true;
+    } else if (had) {
+      P->dead = true;
+    }
+    g_last_error = why + (P->dead ? " (the previous buffers could not be restored: plan unusable)" : "");
+  }
+  if (had && hipMemcpy(P->d_lvs, P->lv, sizeof(LevelDev) * (kMaxLevel + 1), hipMemcpyHostToDevice) != hipSuccess) {
+    P->dead = true;
     return fail(AFMM_E_DEVICE, "level table refresh failed");
-  return AFMM_OK;
+  }
+  return s;
 }
 
 // Allocate and upload everything of a plan whose topology is built.
@@ -1178,8 +1280,17 @@ static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
     P->cm.sumidx = d_sum;
     P->cm.up = d_up;
     P->cm.binom = d_binom;
+    // The upward pass writes the source copies c_a 2^|a| S~_a that every
+    // translation reads; with the paper's cap (multipoles to order p - 1) the
+    // factor of the order-p coefficients is 0, so M2L, M2P and the near-field
+    // M2P see them as absent, and the adjoint's transpose of the same scaling
+    // drops their bars.
+    std::vector<double> c2 = H.cfac2;
+    if (P->opt.flags & AFMM_PAPER_QUAD_CAP)
+      for (int a = 0; a < K; ++a)
+        if (H.mi[4 * a + 3] == P->opt.p) c2[a] = 0.0;
     const double* d_c2 = nullptr;
-    if ((s = upload_conv<double>(P, H.cfac2, &d_c2, st))) return s;
+    if ((s = upload_conv<double>(P, c2, &d_c2, st))) return s;
     P->cm.cfac2 = d_c2;
     int32_t *d_ms, *d_ml;
     double* d_mw;
@@ -1367,6 +1478,13 @@ static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
   void* p = nullptr;
   if ((s = dev_alloc(P, &p, (size_t)std::max<int64_t>(T.nslots, 1) * sizeof(double)))) return s;
   P->m_snap = (double*)p;
+  if ((s = dev_alloc(P, &p, sizeof(int)))) return s;
+  P->d_flag = (int*)p;
+  if (hipHostMalloc((void**)&P->h_flag, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    P->h_flag = nullptr;
+    return fail(AFMM_E_OUT_OF_MEMORY, "pinned flag allocation failed");
+  }
+  P->cself = (P->opt.flags & AFMM_SELF_POTENTIAL) ? cube_self_constant() : 0.0;
   if (hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming) != hipSuccess)
@@ -1415,16 +1533,22 @@ extern "C" afmm_status afmm_plan_destroy(afmm_plan* P) {
 extern "C" afmm_status afmm_plan_get_info(const afmm_plan* P, afmm_plan_info* out) {
   if (!P || !out) return fail(AFMM_E_INVALID_ARG, "null argument");
   *out = P->info;
+  out->device_bytes = P->bytes;  // live: the autotuner and the adjoint change it
   return AFMM_OK;
 }
 
 // ---------------------------------------------------------------------------
 // solve driver
 
-__global__ void k_nonfinite(int64_t n, const double* __restrict__ m, int* __restrict__ flag) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    if (!isfinite(m[i])) flag[0] = 1;
+// AFMM_CHECK_INPUT: flag any non-finite mass among the leaf slots of one level
+__global__ void k_nonfinite(int n, const int32_t* __restrict__ rank, const int32_t* __restrict__ slot,
+                            const double* __restrict__ m, int* __restrict__ flag) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int s = slot[i];
+    if (rank[i] < 0 && s >= 0 && !isfinite(m[s])) flag[0] = 1;
+  }
 }
+__global__ void k_flag_clear(int* __restrict__ flag) { flag[0] = 0; }
 
 static afmm_status dev_check(afmm_plan* P, hipError_t e, const char* what) {
   if (e == hipSuccess) return AFMM_OK;
@@ -1582,7 +1706,7 @@ static afmm_status run_solve(afmm_plan* P, const double* msrc, int fmax, int lo,
     if ((s = dev_check(P,
                        launch_near(p, fp32, l, P->d_leafgrp[l], ng, P->lv[l - 1], P->lv[l], lvp, P->t32, P->t64, P->cm,
                                    l >= 3 ? P->lv[l - 1].part : nullptr, nm > 0 ? P->d_nmp[l] : nullptr, P->opt.G,
-                                   h, phi, acc, st),
+                                   h, P->cself, phi, acc, st),
                        "near")))
       return s;
     prof_end(P, a, st, fp32 ? kLeaf32 : kLeaf64, l);
@@ -1602,16 +1726,27 @@ static afmm_status afmm_solve_impl(afmm_plan* P, int32_t level, int32_t icount, 
     return fail(AFMM_E_INVALID_ARG, "level outside [levelmin, levelmax]");
   if (level != AFMM_ALL_LEVELS && icount < 1) return fail(AFMM_E_INVALID_ARG, "icount must be >= 1");
   if (P->opt.flags & AFMM_CHECK_INPUT) {
-    void* fl = nullptr;
-    if (hipMalloc(&fl, sizeof(int)) != hipSuccess) return fail(AFMM_E_OUT_OF_MEMORY, "flag alloc");
-    int zero = 0, hostflag = 0;
-    (void)hipMemcpyAsync(fl, &zero, sizeof(int), hipMemcpyHostToDevice, st);
-    hipLaunchKernelGGL(k_nonfinite, dim3(256), dim3(256), 0, st, (int64_t)T.nslots, d_mass, (int*)fl);
-    (void)hipMemcpyAsync(&hostflag, fl, sizeof(int), hipMemcpyDeviceToHost, st);
-    hipError_t e = hipStreamSynchronize(st);
-    (void)hipFree(fl);
-    if (e != hipSuccess) return dev_check(P, e, "input check");
-    if (hostflag) return fail(AFMM_E_NONFINITE, "non-finite mass");
+    // the masses this call reads: every level for a full solve, levels >= level
+    // when Alg. 1 rebuilds trees, none otherwise
+    const bool reads = level == AFMM_ALL_LEVELS || level == lmin || icount > 1;
+    const int l0 = level == AFMM_ALL_LEVELS ? lmin : level;
+    if (reads) {
+      afmm_status r;
+      hipLaunchKernelGGL(k_flag_clear, dim3(1), dim3(1), 0, st, P->d_flag);
+      if ((r = dev_check(P, hipGetLastError(), "input check"))) return r;
+      for (int l = l0; l <= lmax; ++l) {
+        const LevelDev& D = P->lv[l];
+        if (D.n == 0) continue;
+        hipLaunchKernelGGL(k_nonfinite, dim3((unsigned)std::min((D.n + 255) / 256, 2048)), dim3(256), 0, st, D.n,
+                           D.rank, D.slot, d_mass, P->d_flag);
+        if ((r = dev_check(P, hipGetLastError(), "input check"))) return r;
+      }
+      if ((r = dev_check(P, hipMemcpyAsync(P->h_flag, P->d_flag, sizeof(int), hipMemcpyDeviceToHost, st),
+                         "input check")) ||
+          (r = dev_check(P, hipStreamSynchronize(st), "input check")))
+        return r;
+      if (*P->h_flag) return fail(AFMM_E_NONFINITE, "non-finite mass in a leaf slot that the solve reads");
+    }
   }
   if (level == AFMM_ALL_LEVELS) {
     // the snapshot is written by the mass gather of this solve
@@ -1702,10 +1837,28 @@ static afmm_status batch_pointer_table(afmm_batch* B, const double* const* d_mas
 // split with the smallest time of its kernel family plus the family that sums
 // its partials (L2L for M2L, the leaf kernel for M2P) is kept.
 namespace {
+// Restores the plan's profiling switch on every exit path.
+struct ProfilingScope {
+  afmm_plan* P;
+  bool saved;
+  ProfilingScope(afmm_plan* p, bool on) : P(p), saved(p->profiling) { P->profiling = on; }
+  ~ProfilingScope() { P->profiling = saved; }
+};
+
 template <typename SolveFn>
 afmm_status autotune_core(afmm_plan* P, SolveFn solve, hipStream_t st, afmm_tune_result* out) {
-  const bool prof = P->profiling;
-  P->profiling = true;
+  ProfilingScope scope(P, true);
+  // a candidate whose partial buffers would not fit under max_device_bytes is
+  // skipped (its buffers would replace the current ones, so only the growth counts)
+  auto fits = [&]() {
+    if (!P->opt.max_device_bytes) return true;
+    const size_t cur = P->bytes - [&] {
+      size_t b = 0;
+      for (int l = 0; l <= P->topo.lmax; ++l) b += P->lv[l].part_bytes + P->lv[l].Lpart_bytes;
+      return b;
+    }();
+    return cur + split_buffer_bytes(P, P->m2l_split, P->m2p_split) <= P->opt.max_device_bytes;
+  };
   auto measure = [&](double* kind_ms) -> afmm_status {
     afmm_status s;
     for (int r = 0; r < 4; ++r)
@@ -1742,42 +1895,62 @@ afmm_status autotune_core(afmm_plan* P, SolveFn solve, hipStream_t st, afmm_tune
   // split: the L2L and leaf kernels sum the partials of both precisions, so a
   // joint sweep would let the larger launch decide the smaller one's split.
   int ncand = 0;
+  // `have` = the splits the live partial buffers were allocated for.  The
+  // kernels only run (in measure) right after a successful allocation, when
+  // the plan's splits equal `have`; a refused allocation puts them back.
+  int have_l[2] = {P->m2l_split[0], P->m2l_split[1]}, have_p[2] = {P->m2p_split[0], P->m2p_split[1]};
+  auto realloc = [&]() -> afmm_status {
+    afmm_status r = alloc_split_buffers(P, have_l, have_p);
+    if (r == AFMM_OK)
+      for (int q = 0; q < 2; ++q) have_l[q] = P->m2l_split[q], have_p[q] = P->m2p_split[q];
+    return r;
+  };
+  // One candidate: skipped when its buffers would exceed max_device_bytes or
+  // hipMalloc refuses them (the previous buffers then stand), else timed; the
+  // cost is the split kernel's family plus the family that sums its partials.
+  auto trial = [&](int* split, int pr, int c, double& best, int& arg, int kind_a, int kind_b) -> afmm_status {
+    const int prev = split[pr];
+    split[pr] = c;
+    if (!fits()) {
+      split[pr] = prev;
+      return AFMM_OK;
+    }
+    afmm_status r = realloc();
+    if (r == AFMM_E_OUT_OF_MEMORY && !P->dead) {
+      split[pr] = prev;  // the previous splits and buffers were restored
+      return AFMM_OK;
+    }
+    if (r) return r;
+    double km[kNumKinds];
+    if ((r = measure(km))) return r;
+    ++ncand;
+    const double t = km[kind_a] + km[kind_b];
+    if (t < best) best = t, arg = c;
+    return AFMM_OK;
+  };
   for (int pr = 1; pr >= 0; --pr) {
     if (P->m2l_all[pr].ntiles == 0) continue;
     double best = 1e300;
     int arg = P->m2l_split[pr];
-    for (int c : cand_m2l) {
-      P->m2l_split[pr] = c;
-      if ((s = alloc_split_buffers(P))) return s;
-      double km[kNumKinds];
-      if ((s = measure(km))) return s;
-      ++ncand;
-      const double t = km[pr ? kM2L32 : kM2L64] + km[kL2L];
-      if (t < best) best = t, arg = c;
-    }
+    for (int c : cand_m2l)
+      if ((s = trial(P->m2l_split, pr, c, best, arg, pr ? kM2L32 : kM2L64, kL2L))) return s;
     P->m2l_split[pr] = arg;
   }
   for (int pr = 1; pr >= 0; --pr) {
     if (P->m2p_all[pr].ntiles == 0) continue;
     double best = 1e300;
     int arg = P->m2p_split[pr];
-    for (int c : cand_m2p) {
-      P->m2p_split[pr] = c;
-      if ((s = alloc_split_buffers(P))) return s;
-      double km[kNumKinds];
-      if ((s = measure(km))) return s;
-      ++ncand;
-      const double t = km[pr ? kM2P32 : kM2P64] + km[pr ? kLeaf32 : kLeaf64];
-      if (t < best) best = t, arg = c;
-    }
+    for (int c : cand_m2p)
+      if ((s = trial(P->m2p_split, pr, c, best, arg, pr ? kM2P32 : kM2P64, pr ? kLeaf32 : kLeaf64))) return s;
     P->m2p_split[pr] = arg;
   }
-  if ((s = alloc_split_buffers(P))) return s;
+  // the chosen splits were timed, so they fitted then; a refusal now leaves
+  // the last timed candidate's splits and buffers (consistent, just not the best)
+  if ((s = realloc()) && (s != AFMM_E_OUT_OF_MEMORY || P->dead)) return s;
   double k1[kNumKinds];
   if ((s = measure(k1))) return s;
   double after = 0;
   for (int k = 0; k < kNumKinds; ++k) after += k1[k];
-  P->profiling = prof;
   if (out) {
     for (int pr = 0; pr < 2; ++pr) {
       out->m2l_split[pr] = P->m2l_split[pr];
@@ -2044,7 +2217,7 @@ static afmm_status afmm_solve_adjoint_impl(afmm_plan* P, int32_t level, const do
   for (int l = lmin; l <= lmax; ++l) {
     const bool has_parent = l - 1 >= 2 && l - 1 <= lmax - 1;
     const bool fresh = l >= P->last_fresh;
-    if ((s = dev_check(P, launch_adj_out(p, P->lv[l - 1], P->lv[l], has_parent, fresh, P->cm, d_mass_bar, st),
+    if ((s = dev_check(P, launch_adj_out(p, P->lv[l - 1], P->lv[l], has_parent, fresh, P->cself, P->cm, d_mass_bar, st),
                        "adjoint out")))
       return s;
   }
@@ -2167,9 +2340,12 @@ static afmm_status afmm_batch_create_impl(afmm_plan* const* plans, int32_t n, vo
     if (Q->dead) return fail(AFMM_E_DEVICE, "a plan of the batch is unusable after a device error");
     if (Q->topo.levelmin.size() != 1) return fail(AFMM_E_INVALID_ARG, "a batch takes single-hierarchy plans");
     const afmm_options& o = Q->opt;
+    const uint32_t kModel = AFMM_PAPER_QUAD_CAP | AFMM_SELF_POTENTIAL;
     if (o.p != o0.p || o.precision != o0.precision || o.G != o0.G || o.boxlen != o0.boxlen ||
-        o.fp64_levels != o0.fp64_levels || o.tap_split != o0.tap_split)
-      return fail(AFMM_E_INVALID_ARG, "plans of a batch must share p, precision, G, boxlen, fp64_levels, tap_split");
+        o.fp64_levels != o0.fp64_levels || o.tap_split != o0.tap_split || ((o.flags ^ o0.flags) & kModel))
+      return fail(AFMM_E_INVALID_ARG,
+                  "plans of a batch must share p, precision, G, boxlen, fp64_levels, tap_split and the "
+                  "quadrupole-cap / self-potential flags");
   }
   afmm_batch* B = new afmm_batch();
   try {
@@ -2177,7 +2353,7 @@ static afmm_status afmm_batch_create_impl(afmm_plan* const* plans, int32_t n, vo
     B->plan = new afmm_plan();
     afmm_plan* P = B->plan;
     P->opt = o0;
-    P->opt.flags = 0;
+    P->opt.flags = o0.flags & (AFMM_PAPER_QUAD_CAP | AFMM_SELF_POTENTIAL);
     P->K = nmi(o0.p);
     B->base.assign(n + 1, 0);
     for (int32_t i = 0; i < n; ++i) {
@@ -2268,6 +2444,7 @@ static afmm_status afmm_batch_get_profile_impl(afmm_batch* B, afmm_stage_time* o
 extern "C" afmm_status afmm_batch_get_info(const afmm_batch* B, afmm_plan_info* out) {
   if (!B || !out) return fail(AFMM_E_INVALID_ARG, "null argument");
   *out = B->plan->info;
+  out->device_bytes = B->plan->bytes;
   return AFMM_OK;
 }
 

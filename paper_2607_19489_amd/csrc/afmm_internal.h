@@ -208,8 +208,10 @@ hipError_t launch_adj_l2l(int p, const int32_t* grp, int ngrp, const LevelDev& l
                           const TablesDev<double>& t64, const CommonDev& cm, hipStream_t st);
 hipError_t launch_adj_down(int p, const LevelDev& lv1, const LevelDev& lv0, int has_parent, const CommonDev& cm,
                            hipStream_t st);
+// Mass bars to the caller's slots; cself (the self-potential constant, 0 when
+// off) adds the transpose of the self term -cself m of the unit-form potential.
 hipError_t launch_adj_out(int p, const LevelDev& lv1, const LevelDev& lv0, int has_parent, int rebuilt,
-                          const CommonDev& cm, double* mbar_out, hipStream_t st);
+                          double cself, const CommonDev& cm, double* mbar_out, hipStream_t st);
 // Upward pass of FMM level f: the refined cells whose children are all leaves
 // (list leaf, P2M only) and the others (list mix, M2M of refined children).
 hipError_t launch_upward(int p, const int32_t* leaf, int nleaf, const int32_t* mix, int nmix, const LevelDev& lv,
@@ -226,10 +228,11 @@ hipError_t launch_l2l(int p, bool fp32, bool parent_fp32, bool has_parent, int n
 hipError_t launch_m2p(int p, bool fp32, const MfmaTiles& mt, int t0, int n, int nsplit, const MfmaTables& tabs,
                       const LevelDev* lvs, const TablesDev<float>& t32, const TablesDev<double>& t64,
                       hipStream_t st);
+// cself: the self-potential constant (AFMM_SELF_POTENTIAL), 0 when off.
 hipError_t launch_near(int p, bool fp32, int l, const int32_t* grp, int ngrp, const LevelDev& lv1,
                        const LevelDev& lv0, const LevelDev& lvp, const TablesDev<float>& t32,
                        const TablesDev<double>& t64, const CommonDev& cm, const void* part, const void* nmp,
-                       double G, double h, double* phi, double* acc, hipStream_t st);
+                       double G, double h, double cself, double* phi, double* acc, hipStream_t st);
 // Near-field M2P from the refined level-l cells among the near candidates of
 // the groups `grp` (those that have any): partial [nref(l-1)][c * 8 + o].
 hipError_t launch_near_m2p(int p, bool fp32, const int32_t* grp, int ngrp, const LevelDev& lv1, const LevelDev& lv0,

@@ -1037,7 +1037,8 @@ template <typename T, int P>
 __global__ __launch_bounds__(kBlock) void k_near(const int32_t* __restrict__ grp, int ngrp, LevelDev lv1, LevelDev lv0,
                                                  const T* __restrict__ nearA, const T* __restrict__ Lpar,
                                                  const T* __restrict__ part, const T* __restrict__ nmp, double G,
-                                                 double h, double* __restrict__ phi, double* __restrict__ acc) {
+                                                 double h, double cself, double* __restrict__ phi,
+                                                 double* __restrict__ acc) {
   static_assert(kBlock == 256, "four waves split the operator columns");
   static_assert(near_ksteps(P) % (16 / (int)sizeof(T)) == 0, "near operator vectors");
   __shared__ int sF[16];
@@ -1106,7 +1107,7 @@ __global__ __launch_bounds__(kBlock) void k_near(const int32_t* __restrict__ grp
       if (nmp) v += (double)as_global(nmp)[(size_t)F * 32 + R];
       const int sl = slot0[cell];
       if (c == 0)
-        phi[sl] = sp * v;
+        phi[sl] = sp * (v - cself * mass0[cell]);  // optional self term of the leaf's own mass
       else
         acc[3 * (size_t)sl + c - 1] = sa * v;
     }
@@ -1318,14 +1319,14 @@ hipError_t launch_l2l(int p, bool fp32, bool parent_fp32, bool has_parent, int n
 template <typename T>
 static hipError_t near_dispatch(int p, int ngrp, const int32_t* grp, const LevelDev& lv1, const LevelDev& lv0,
                                 const TablesDev<T>& tb, const T* Lpar, const T* part, const T* nmp, double G,
-                                double h, double* phi, double* acc, hipStream_t st) {
+                                double h, double cself, double* phi, double* acc, hipStream_t st) {
   const int ntiles = (ngrp + 15) / 16;
   const dim3 grid(8 * ((ntiles + 7) / 8)), block(kBlock);
   switch (p) {
 #define AFMM_NEAR(PP)                                                                                         \
   case PP:                                                                                                    \
     hipLaunchKernelGGL((k_near<T, PP>), grid, block, 0, st, grp, ngrp, lv1, lv0, tb.nearA, Lpar, part, nmp,  \
-                       G, h, phi, acc);                                                                       \
+                       G, h, cself, phi, acc);                                                                \
     break;
     AFMM_NEAR(1) AFMM_NEAR(2) AFMM_NEAR(3) AFMM_NEAR(4) AFMM_NEAR(5) AFMM_NEAR(6) AFMM_NEAR(7) AFMM_NEAR(8)
 #undef AFMM_NEAR
@@ -1337,16 +1338,16 @@ static hipError_t near_dispatch(int p, int ngrp, const int32_t* grp, const Level
 hipError_t launch_near(int p, bool fp32, int l, const int32_t* grp, int ngrp, const LevelDev& lv1,
                        const LevelDev& lv0, const LevelDev& lvp, const TablesDev<float>& t32,
                        const TablesDev<double>& t64, const CommonDev& cm, const void* part, const void* nmp,
-                       double G, double h, double* phi, double* acc, hipStream_t st) {
+                       double G, double h, double cself, double* phi, double* acc, hipStream_t st) {
   (void)cm;
   (void)lvp;
   if (ngrp == 0) return hipSuccess;
   const bool has_far = (l - 1) >= 3;
   if (fp32)
     return near_dispatch<float>(p, ngrp, grp, lv1, lv0, t32, has_far ? lv1.L32 : nullptr, (const float*)part,
-                                (const float*)nmp, G, h, phi, acc, st);
+                                (const float*)nmp, G, h, cself, phi, acc, st);
   return near_dispatch<double>(p, ngrp, grp, lv1, lv0, t64, has_far ? lv1.L64 : nullptr, (const double*)part,
-                               (const double*)nmp, G, h, phi, acc, st);
+                               (const double*)nmp, G, h, cself, phi, acc, st);
 }
 
 template <typename T>

@@ -77,3 +77,29 @@ def test_counts_cfg2():
     info = A.hierarchy_check(configs.cfg2().hierarchy, p=6)
     assert info["nleaves"] == 287680 and info["nrefined"] == 3648
     assert info["nearest_pairs"] > 0 and info["near_m2p_pairs"] > 0
+
+
+def test_model_flags_accepted_and_unknown_flag_refused():
+    h = build_graded(3, 5, refine_sphere((0.5, 0.5, 0.5), {3: 0.3, 4: 0.2}))
+    a = A.hierarchy_check(h, p=3)
+    b = A.hierarchy_check(h, p=3, quad_cap=True, self_potential=True)
+    assert a["nleaves"] == b["nleaves"] and a["flops_m2p"] == b["flops_m2p"]
+    o = A.make_options(p=3)
+    o.flags = 1 << 9
+    arrs = A.afmm._hierarchy_arrays(h)  # kept alive: hc points into them
+    hc = A.afmm._hier_struct(*arrs)
+    info = _lib.PlanInfo()
+    assert _lib.lib().afmm_hierarchy_check(C.byref(hc), C.byref(o), C.byref(info)) == -4
+
+
+def test_max_device_bytes_gives_out_of_memory_before_any_device_call():
+    """A cap smaller than the first allocation fails plan creation with
+    AFMM_E_OUT_OF_MEMORY; the check precedes hipMalloc, so it runs without a GPU."""
+    h = build_graded(3, 5, refine_sphere((0.5, 0.5, 0.5), {3: 0.3, 4: 0.2}))
+    o = A.make_options(p=4, max_device_bytes=1)
+    arrs = A.afmm._hierarchy_arrays(h)
+    hc = A.afmm._hier_struct(*arrs)
+    ptr = C.c_void_p()
+    rc = _lib.lib().afmm_plan_create(C.byref(hc), C.byref(o), None, C.byref(ptr))
+    assert rc == -5 and not ptr.value
+    assert b"max_device_bytes" in _lib.lib().afmm_last_error()

@@ -30,24 +30,7 @@ def _members(p):
 
 
 def _plans(hs, p, **kw):
-    """Plans of the members; if one is refused, report how its input differs
-    from a fresh generation of the same member (the generators are seeded)."""
-    out = []
-    for i, h in enumerate(hs):
-        try:
-            out.append(A.Plan(h, p=p, **kw))
-        except A.AfmmError:
-            fresh = _members(p)[0][i]
-            for lv, (a, b) in enumerate(zip(h.ijk, fresh.ijk)):
-                bad = np.nonzero(np.any(a != b, axis=1))[0] if a.shape == b.shape else np.arange(len(a))
-                if bad.size:
-                    print(f"member {i} level {h.levelmin + lv}: {bad.size} cells differ, first {bad[:8]}, "
-                          f"got {a[bad[:4]].tolist()} want {b[bad[:4]].tolist()}, "
-                          f"array at {a.__array_interface__['data'][0]:#x} ({a.dtype}, {a.nbytes} B)", flush=True)
-            same = all(np.array_equal(a, b) for a, b in zip(h.ijk + h.refined, fresh.ijk + fresh.refined))
-            print(f"member {i}: stored arrays {'match' if same else 'differ from'} a fresh generation", flush=True)
-            raise
-    return out
+    return [A.Plan(h, p=p, **kw) for h in hs]
 
 
 def _individual(plans, masses):
@@ -121,3 +104,12 @@ def test_batch_of_one_and_mismatched_options():
     other = A.Plan(h, p=5, precision="fp32")
     with pytest.raises(A.AfmmError):
         A.Batch([pl, other])
+    # the model flags travel into the batch; members must agree on them
+    cap = A.Plan(h, p=4, precision="fp32", quad_cap=True, self_potential=True)
+    with pytest.raises(A.AfmmError):
+        A.Batch([pl, cap])
+    bc = A.Batch([cap])
+    phis, accs = bc.solve([m])
+    phi, acc = cap.solve(m)
+    torch.cuda.synchronize()
+    assert torch.equal(phis[0], phi) and torch.equal(accs[0], acc)

@@ -181,6 +181,27 @@ afmm_status afmm_solve_adjoint(afmm_plan* plan, int32_t level, const double* d_p
                                const double* d_acc_bar, double* d_mass_bar, void* hip_stream);
 
 /*
+ * Allocation-free adjoint, for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc (afmm_solve_adjoint allocates its workspace on its first call).
+ * Same arguments, semantics and results as afmm_solve_adjoint, bit for bit,
+ * but the call allocates nothing: its scratch (target and mass bars, the
+ * multipole and local-expansion bars, the B staging of the transposed M2P and
+ * M2L, their tap-split partial sums) lives in one static device array of the
+ * library, 64 MiB per GPU, which each GPU the library runs on holds until the
+ * process ends.  The adjoint's topology (its source tiles) is built at plan
+ * creation for every plan whose scratch fits that bound; a plan whose scratch
+ * exceeds it is refused with AFMM_E_OUT_OF_MEMORY before anything runs (about
+ * 10^5 cells at p = 6 fit).  Every call on one GPU shares the array: calls
+ * that overlap on one GPU (other streams, other threads) race and must be
+ * serialised by the caller; calls on one stream are ordered.  Each call writes
+ * every scratch byte it reads, so no call depends on what an earlier one left.
+ * Errors as afmm_solve_adjoint, plus AFMM_E_OUT_OF_MEMORY for oversized plans.
+ */
+afmm_status afmm_solve_adjoint_noalloc(afmm_plan* plan, int32_t level, const double* d_phi_bar,
+                                       const double* d_acc_bar, double* d_mass_bar, void* hip_stream);
+
+/*
  * Batch of independent hierarchies of uneven size and depth, solved together
  * (synchronous solves, Alg. 1 with every tree rebuilt).  The batch is one plan
  * over the forest of all hierarchies: level l of the forest is the union of the

@@ -32,7 +32,7 @@ SYMBOLS = [
     "afmm_solve_adjoint", "afmm_batch_create", "afmm_batch_solve", "afmm_batch_get_info",
     "afmm_batch_destroy", "afmm_hierarchy_check", "afmm_status_string", "afmm_last_error",
     "afmm_plan_set_profiling", "afmm_plan_get_profile", "afmm_batch_set_profiling", "afmm_batch_get_profile",
-    "afmm_plan_autotune", "afmm_batch_autotune",
+    "afmm_plan_autotune", "afmm_batch_autotune", "afmm_solve_adjoint_noalloc",
 ]
 
 
@@ -105,6 +105,7 @@ def lib():
     L.afmm_plan_get_info.argtypes = [vp, C.POINTER(PlanInfo)]
     L.afmm_solve.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp, vp]
     L.afmm_solve_adjoint.argtypes = [vp, C.c_int32, vp, vp, vp, vp]
+    L.afmm_solve_adjoint_noalloc.argtypes = [vp, C.c_int32, vp, vp, vp, vp]
     L.afmm_batch_create.argtypes = [C.POINTER(vp), C.c_int32, vp, C.POINTER(vp)]
     L.afmm_batch_solve.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), vp]
     L.afmm_batch_get_info.argtypes = [vp, C.POINTER(PlanInfo)]
@@ -121,7 +122,7 @@ def lib():
     L.afmm_last_error.argtypes = []
     L.afmm_last_error.restype = C.c_char_p
     for name in ("afmm_plan_create", "afmm_plan_destroy", "afmm_plan_get_info", "afmm_solve",
-                 "afmm_solve_adjoint", "afmm_batch_create", "afmm_batch_solve", "afmm_batch_get_info",
+                 "afmm_solve_adjoint", "afmm_solve_adjoint_noalloc", "afmm_batch_create", "afmm_batch_solve", "afmm_batch_get_info",
                  "afmm_batch_destroy", "afmm_hierarchy_check", "afmm_plan_set_profiling",
                  "afmm_plan_get_profile", "afmm_batch_set_profiling", "afmm_batch_get_profile",
                  "afmm_plan_autotune", "afmm_batch_autotune"):

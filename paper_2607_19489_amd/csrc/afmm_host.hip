@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -859,6 +860,8 @@ struct afmm_plan {
   int last_level = AFMM_ALL_LEVELS;
   int last_fresh = 0;             // levels >= this took their masses from the last call's d_mass
   bool adj_ready = false;         // adjoint workspace allocated
+  bool adj_topo = false;          // adjoint source tiles and splits built
+  size_t adj_part_elems = 0;      // FP64 elements of the adjoint's tap-split partial sets
   // source tiles of the transposed M2P (index: leaf level l) and M2L (index: FMM level f)
   int32_t* d_adjp[kMaxLevel] = {};
   int32_t* d_adjl[kMaxLevel] = {};
@@ -1193,6 +1196,9 @@ static afmm_status alloc_split_buffers(afmm_plan* P, const int* prev_m2l = nullp
   return s;
 }
 
+static afmm_status adjoint_topology(afmm_plan* P);
+static bool adjoint_noalloc_may_fit(const afmm_plan* P);
+
 // Allocate and upload everything of a plan whose topology is built.
 static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
   Topology& T = P->topo;
@@ -1485,6 +1491,9 @@ static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
     return fail(AFMM_E_OUT_OF_MEMORY, "pinned flag allocation failed");
   }
   P->cself = (P->opt.flags & AFMM_SELF_POTENTIAL) ? cube_self_constant() : 0.0;
+  // a plan small enough for the allocation-free adjoint gets its adjoint
+  // topology now, so that afmm_solve_adjoint_noalloc never has to allocate it
+  if (T.levelmin.size() == 1 && adjoint_noalloc_may_fit(P) && (s = adjoint_topology(P))) return s;
   if (hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming) != hipSuccess)
@@ -2010,34 +2019,27 @@ static afmm_status afmm_batch_autotune_impl(afmm_batch* B, const double* const* 
   return capture_batch(B);
 }
 
-// Adjoint workspace: target bars and mass bars on every level, source-copy /
-// multipole bars on the multipole levels 2..lmax-1, local-expansion bars on
-// the FMM levels 3..lmax-1.
-static afmm_status adjoint_workspace(afmm_plan* P) {
-  if (P->adj_ready) return AFMM_OK;
+// ---------------------------------------------------------------------------
+// Adjoint pass.  Its topology (the source tiles of the transposed M2P / M2L and
+// their tap splits) is built once; its per-call scratch -- target bars and mass
+// bars on every level, source-copy / multipole bars on the multipole levels
+// 2..lmax-1, local-expansion bars on the FMM levels 3..lmax-1, the transposed
+// operators' B staging (tbT, lbarT) and the tap-split partial sets -- is laid
+// out in one block: allocated by the plan on the first afmm_solve_adjoint, or
+// taken from the library's static scratch array by afmm_solve_adjoint_noalloc.
+
+static int device_cu_count() {
+  int ncu = 256, dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  return ncu > 0 ? ncu : 256;
+}
+
+static afmm_status adjoint_topology(afmm_plan* P) {
+  if (P->adj_topo) return AFMM_OK;
   const Topology& T = P->topo;
-  const int K = P->K;
   afmm_status s;
-  for (int l = 0; l <= T.lmax; ++l) {
-    LevelDev& D = P->lv[l];
-    void* q = nullptr;
-    if ((s = dev_alloc(P, &q, (size_t)std::max(D.n, 1) * 4 * sizeof(double)))) return s;
-    D.tbar = (double*)q;
-    if ((s = dev_alloc(P, &q, (size_t)std::max(D.n, 1) * sizeof(double)))) return s;
-    D.mbar = (double*)q;
-    if (l >= 2 && l <= T.lmax - 1 && D.nref > 0) {
-      if ((s = dev_alloc(P, &q, (size_t)D.nref * K * sizeof(double)))) return s;
-      D.sbar = (double*)q;
-    }
-    if (l >= 3 && l <= T.lmax - 1 && D.nref > 0) {
-      if ((s = dev_alloc(P, &q, (size_t)D.nref * K * sizeof(double)))) return s;
-      D.lbar = (double*)q;
-    }
-  }
   // source tiles: the level-ls cells read by some group of `grp` (refined ranks
   // at ls), 16 per tile, one octant class per tile
-  const bool mixed = P->opt.precision == AFMM_FP32_MIXED;
-  const int f64 = mixed ? P->opt.fp64_levels : 1 << 20;
   auto src_tiles = [&](int target, const std::vector<int32_t>& grp, int32_t** dst, int* nt) -> afmm_status {
     *nt = 0;
     if (grp.empty() || target < 3) return AFMM_OK;
@@ -2069,78 +2071,100 @@ static afmm_status adjoint_workspace(afmm_plan* P) {
       }
     return upload(P, rec, dst, nullptr);
   };
-  for (int l = 3; l <= T.lmax; ++l) {
+  for (int l = 3; l <= T.lmax; ++l)
     if ((s = src_tiles(l, T.leafgrp[l], &P->d_adjp[l], &P->n_adjp[l]))) return s;
-    if (P->n_adjp[l] > 0) {
-      void* q = nullptr;
-      const size_t es = (mixed && (l - 1) > f64) ? sizeof(float) : sizeof(double);
-      if ((s = dev_alloc(P, &q, (size_t)T.lv[l - 1].nref() * 32 * es))) return s;
-      P->lv[l - 1].tbT = q;
-    }
-  }
-  for (int f = 3; f <= T.lmax - 1; ++f) {
+  for (int f = 3; f <= T.lmax - 1; ++f)
     if ((s = src_tiles(f, T.m2lgrp[f], &P->d_adjl[f], &P->n_adjl[f]))) return s;
-    if (P->n_adjl[f] > 0) {
-      void* q = nullptr;
-      const bool f32 = mixed && f > f64;
-      const size_t b = (size_t)T.lv[f].nref() * (f32 ? src_row(P->opt.p, 4) * sizeof(float)
-                                                       : src_row(P->opt.p, 8) * sizeof(double));
-      if ((s = dev_alloc(P, &q, b))) return s;
-      P->lv[f].lbarT = q;
-    }
-  }
   // tap splits of the transposed translations: about 12 waves per CU
-  int ncu = 256;
-  {
-    int dev = 0;
-    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (ncu <= 0) ncu = 256;
-  }
-  size_t part_max = 0;
+  const int ncu = device_cu_count();
   auto split_of = [&](int nt) { return nt > 0 ? std::max(1, std::min(16, (12 * ncu + nt - 1) / nt)) : 1; };
+  P->adj_part_elems = 0;
   for (int l = 0; l < kMaxLevel; ++l) {
     P->s_adjp[l] = split_of(P->n_adjp[l]);
     P->s_adjl[l] = split_of(P->n_adjl[l]);
-    if (P->s_adjp[l] > 1) part_max = std::max(part_max, (size_t)P->s_adjp[l] * P->n_adjp[l] * 16 * K);
-    if (P->s_adjl[l] > 1) part_max = std::max(part_max, (size_t)P->s_adjl[l] * P->n_adjl[l] * 16 * K);
+    if (P->s_adjp[l] > 1) P->adj_part_elems = std::max(P->adj_part_elems, (size_t)P->s_adjp[l] * P->n_adjp[l] * 16 * P->K);
+    if (P->s_adjl[l] > 1) P->adj_part_elems = std::max(P->adj_part_elems, (size_t)P->s_adjl[l] * P->n_adjl[l] * 16 * P->K);
   }
-  if (part_max > 0) {
-    void* q = nullptr;
-    if ((s = dev_alloc(P, &q, part_max * sizeof(double)))) return s;
-    P->adj_part = (double*)q;
+  P->adj_topo = true;
+  return AFMM_OK;
+}
+
+// Lays the adjoint scratch out from `base` (256-byte aligned pieces) into the
+// bar pointers of lw[] (a copy of the plan's levels) and *part; returns the
+// bytes used.  With base == nullptr only the size is computed.
+static size_t adjoint_layout(const afmm_plan* P, char* base, LevelDev* lw, double** part) {
+  const Topology& T = P->topo;
+  const int K = P->K;
+  const bool mixed = P->opt.precision == AFMM_FP32_MIXED;
+  const int f64 = mixed ? P->opt.fp64_levels : 1 << 20;
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void* {
+    void* q = base ? (void*)(base + off) : nullptr;
+    off += (bytes + 255) & ~(size_t)255;
+    return q;
+  };
+  for (int l = 0; l <= T.lmax; ++l) {
+    LevelDev& D = lw[l];
+    D.tbar = (double*)take((size_t)std::max(D.n, 1) * 4 * sizeof(double));
+    D.mbar = (double*)take((size_t)std::max(D.n, 1) * sizeof(double));
+    D.sbar = (l >= 2 && l <= T.lmax - 1 && D.nref > 0) ? (double*)take((size_t)D.nref * K * sizeof(double)) : nullptr;
+    D.lbar = (l >= 3 && l <= T.lmax - 1 && D.nref > 0) ? (double*)take((size_t)D.nref * K * sizeof(double)) : nullptr;
+    D.tbT = nullptr;
+    D.lbarT = nullptr;
   }
-  if (hipDeviceSynchronize() != hipSuccess) return fail(AFMM_E_DEVICE, "adjoint workspace upload");
+  for (int l = 3; l <= T.lmax; ++l)
+    if (P->n_adjp[l] > 0) {
+      const size_t es = (mixed && (l - 1) > f64) ? sizeof(float) : sizeof(double);
+      lw[l - 1].tbT = take((size_t)T.lv[l - 1].nref() * 32 * es);
+    }
+  for (int f = 3; f <= T.lmax - 1; ++f)
+    if (P->n_adjl[f] > 0) {
+      const bool f32 = mixed && f > f64;
+      lw[f].lbarT = take((size_t)T.lv[f].nref() *
+                         (f32 ? src_row(P->opt.p, 4) * sizeof(float) : src_row(P->opt.p, 8) * sizeof(double)));
+    }
+  *part = P->adj_part_elems ? (double*)take(P->adj_part_elems * sizeof(double)) : nullptr;
+  return off;
+}
+
+// The plan-owned scratch of afmm_solve_adjoint (allocated on its first call).
+static afmm_status adjoint_workspace(afmm_plan* P) {
+  if (P->adj_ready) return AFMM_OK;
+  afmm_status s;
+  if ((s = adjoint_topology(P))) return s;
+  if (hipDeviceSynchronize() != hipSuccess) return fail(AFMM_E_DEVICE, "adjoint topology upload");
+  double* part = nullptr;
+  const size_t bytes = adjoint_layout(P, nullptr, P->lv, &part);
+  void* q = nullptr;
+  if ((s = dev_alloc(P, &q, bytes))) return s;
+  adjoint_layout(P, (char*)q, P->lv, &part);
+  P->adj_part = part;
   P->adj_ready = true;
   return AFMM_OK;
 }
 
-static afmm_status afmm_solve_adjoint_impl(afmm_plan* P, int32_t level, const double* d_phi_bar,
-                                          const double* d_acc_bar, double* d_mass_bar, void* hip_stream) {
-  if (!P || !d_phi_bar || !d_acc_bar || !d_mass_bar) return fail(AFMM_E_INVALID_ARG, "null argument");
-  if (P->dead) return fail(AFMM_E_DEVICE, "plan is unusable after an earlier device error");
+// The adjoint of the last solve (Alg. 1-4 transposed) with the bars and
+// partial sets of lw[] / part.
+static afmm_status run_adjoint(afmm_plan* P, int32_t level, const double* d_phi_bar, const double* d_acc_bar,
+                               double* d_mass_bar, hipStream_t st, const LevelDev* lw, double* part) {
   const Topology& T = P->topo;
-  if (T.levelmin.size() != 1) return fail(AFMM_E_INVALID_ARG, "batched plan: no adjoint");
-  if (!P->solved) return fail(AFMM_E_ATS_ORDER, "adjoint before any solve");
-  if (level != P->last_level) return fail(AFMM_E_INVALID_ARG, "adjoint level differs from the last solve's level");
-  hipStream_t st = (hipStream_t)hip_stream;
   const int p = P->opt.p, K = P->K;
   const int lmin = T.levelmin[0], lmax = T.lmax;
   const int lo = level == AFMM_ALL_LEVELS ? lmin : level, hi = level == AFMM_ALL_LEVELS ? lmax : level;
   const int fmax = hi - 1;
   afmm_status s;
-  if ((s = adjoint_workspace(P))) return s;
   const WorkCounts& W = P->work;
   // 1. unit-form bars of the targets, zeroed accumulators
   hipEvent_t ev = prof_begin(P, st);
   for (int l = 0; l <= lmax; ++l) {
     const double h = P->opt.boxlen / (double)(1LL << l);
     const bool tgt = l >= lo && l <= hi;
-    if ((s = dev_check(P, launch_adj_init(P->lv[l], tgt, d_phi_bar, d_acc_bar, P->opt.G / h, P->opt.G / (h * h), st),
+    if ((s = dev_check(P, launch_adj_init(lw[l], tgt, d_phi_bar, d_acc_bar, P->opt.G / h, P->opt.G / (h * h), st),
                        "adjoint init")))
       return s;
-    if ((s = dev_check(P, launch_adj_zero(P->lv[l].sbar, P->lv[l].sbar ? (size_t)P->lv[l].nref * K : 0, st),
+    if ((s = dev_check(P, launch_adj_zero(lw[l].sbar, lw[l].sbar ? (size_t)lw[l].nref * K : 0, st),
                        "adjoint zero")) ||
-        (s = dev_check(P, launch_adj_zero(P->lv[l].lbar, P->lv[l].lbar ? (size_t)P->lv[l].nref * K : 0, st),
+        (s = dev_check(P, launch_adj_zero(lw[l].lbar, lw[l].lbar ? (size_t)lw[l].nref * K : 0, st),
                        "adjoint zero")))
       return s;
   }
@@ -2154,20 +2178,20 @@ static afmm_status afmm_solve_adjoint_impl(afmm_plan* P, int32_t level, const do
     P->pending_bytes += W.leaf_bytes[l];
   }
   for (int l = std::max(1, lo - 1); l <= std::min(lmax, hi + 1); ++l) {
-    const LevelDev& lvp = l + 1 <= lmax ? P->lv[l + 1] : empty;
+    const LevelDev& lvp = l + 1 <= lmax ? lw[l + 1] : empty;
     const bool tgt = l >= lo && l <= hi;
     // P2P^T over the groups with a leaf child; near M2P^T over the groups with a
     // refined child (the M2L group list from level 3 on, every refined cell below)
     const int nlg = (int)T.leafgrp[l].size();
-    const int nrg = l >= 3 ? (int)T.m2lgrp[l].size() : P->lv[l - 1].nref;
+    const int nrg = l >= 3 ? (int)T.m2lgrp[l].size() : lw[l - 1].nref;
     if ((s = dev_check(P,
                        launch_adj_near(p, P->d_leafgrp[l], nlg, P->d_adjvgrp[l], (int)T.adjvgrp[l].size(),
-                                       l >= 3 ? P->d_m2lgrp[l] : nullptr, nrg, P->lv[l - 1], P->lv[l], lvp, tgt,
+                                       l >= 3 ? P->d_m2lgrp[l] : nullptr, nrg, lw[l - 1], lw[l], lvp, tgt,
                                        P->t64, P->cm, st),
                        "adjoint near")))
       return s;
-    if (tgt && l - 1 >= 3 && P->lv[l - 1].lbar &&
-        (s = dev_check(P, launch_adj_l2p(p, P->d_leafgrp[l], nlg, P->lv[l - 1], P->lv[l], P->t64, P->cm, st),
+    if (tgt && l - 1 >= 3 && lw[l - 1].lbar &&
+        (s = dev_check(P, launch_adj_l2p(p, P->d_leafgrp[l], nlg, lw[l - 1], lw[l], P->t64, P->cm, st),
                        "adjoint l2p")))
       return s;
   }
@@ -2178,9 +2202,9 @@ static afmm_status afmm_solve_adjoint_impl(afmm_plan* P, int32_t level, const do
   const int f64 = mixed ? P->opt.fp64_levels : 1 << 20;
   for (int l = std::max(3, lo); l <= hi; ++l) {
     if ((s = dev_check(P,
-                       launch_adj_m2p_mfma(p, mixed && (l - 1) > f64, P->d_adjp[l], P->n_adjp[l], P->s_adjp[l],
-                                           P->adj_part, P->cm.tapsT, P->cm.adj_m2p_off, P->lv[l - 2], P->lv[l - 1],
-                                           P->lv[l], P->t32, P->t64, st),
+                       launch_adj_m2p_mfma(p, mixed && (l - 1) > f64, P->d_adjp[l], P->n_adjp[l], P->s_adjp[l], part,
+                                           P->cm.tapsT, P->cm.adj_m2p_off, lw[l - 2], lw[l - 1], lw[l], P->t32, P->t64,
+                                           st),
                        "adjoint m2p")))
       return s;
     P->pending_flops += W.m2p_flops[l];
@@ -2191,8 +2215,8 @@ static afmm_status afmm_solve_adjoint_impl(afmm_plan* P, int32_t level, const do
   ev = prof_begin(P, st);
   for (int f = fmax; f >= 4; --f)
     if ((s = dev_check(P,
-                       launch_adj_l2l(p, P->d_m2lgrp[f], (int)T.m2lgrp[f].size(), P->lv[f - 1], P->lv[f], P->t64,
-                                      P->cm, st),
+                       launch_adj_l2l(p, P->d_m2lgrp[f], (int)T.m2lgrp[f].size(), lw[f - 1], lw[f], P->t64, P->cm,
+                                      st),
                        "adjoint l2l")))
       return s;
   prof_end(P, ev, st, kAdjTree, -1);
@@ -2200,9 +2224,9 @@ static afmm_status afmm_solve_adjoint_impl(afmm_plan* P, int32_t level, const do
   ev = prof_begin(P, st);
   for (int f = 3; f <= fmax; ++f) {
     if ((s = dev_check(P,
-                       launch_adj_m2l_mfma(p, mixed && f > f64, P->d_adjl[f], P->n_adjl[f], P->s_adjl[f],
-                                           P->adj_part, P->cm.tapsT, P->cm.adj_m2l_off, P->lv[f - 2], P->lv[f - 1],
-                                           P->lv[f], P->t32, P->t64, st),
+                       launch_adj_m2l_mfma(p, mixed && f > f64, P->d_adjl[f], P->n_adjl[f], P->s_adjl[f], part,
+                                           P->cm.tapsT, P->cm.adj_m2l_off, lw[f - 2], lw[f - 1], lw[f], P->t32, P->t64,
+                                           st),
                        "adjoint m2l")))
       return s;
     P->pending_flops += W.m2l_flops[f];
@@ -2212,17 +2236,121 @@ static afmm_status afmm_solve_adjoint_impl(afmm_plan* P, int32_t level, const do
   ev = prof_begin(P, st);
   // 6. source-copy bars -> multipole bars, M2M^T coarse to fine
   for (int f = 2; f <= lmax - 1; ++f)
-    if ((s = dev_check(P, launch_adj_down(p, P->lv[f - 1], P->lv[f], f >= 3, P->cm, st), "adjoint down"))) return s;
+    if ((s = dev_check(P, launch_adj_down(p, lw[f - 1], lw[f], f >= 3, P->cm, st), "adjoint down"))) return s;
   // 7. mass bars to the caller's slots (levels whose masses came from the last call)
   for (int l = lmin; l <= lmax; ++l) {
     const bool has_parent = l - 1 >= 2 && l - 1 <= lmax - 1;
     const bool fresh = l >= P->last_fresh;
-    if ((s = dev_check(P, launch_adj_out(p, P->lv[l - 1], P->lv[l], has_parent, fresh, P->cself, P->cm, d_mass_bar, st),
+    if ((s = dev_check(P, launch_adj_out(p, lw[l - 1], lw[l], has_parent, fresh, P->cself, P->cm, d_mass_bar, st),
                        "adjoint out")))
       return s;
   }
   prof_end(P, ev, st, kAdjTree, -1);
   return AFMM_OK;
+}
+
+static afmm_status adjoint_args(afmm_plan* P, int32_t level, const double* d_phi_bar, const double* d_acc_bar,
+                                double* d_mass_bar) {
+  if (!P || !d_phi_bar || !d_acc_bar || !d_mass_bar) return fail(AFMM_E_INVALID_ARG, "null argument");
+  if (P->dead) return fail(AFMM_E_DEVICE, "plan is unusable after an earlier device error");
+  if (P->topo.levelmin.size() != 1) return fail(AFMM_E_INVALID_ARG, "batched plan: no adjoint");
+  if (!P->solved) return fail(AFMM_E_ATS_ORDER, "adjoint before any solve");
+  if (level != P->last_level) return fail(AFMM_E_INVALID_ARG, "adjoint level differs from the last solve's level");
+  return AFMM_OK;
+}
+
+static afmm_status afmm_solve_adjoint_impl(afmm_plan* P, int32_t level, const double* d_phi_bar,
+                                          const double* d_acc_bar, double* d_mass_bar, void* hip_stream) {
+  afmm_status s;
+  if ((s = adjoint_args(P, level, d_phi_bar, d_acc_bar, d_mass_bar))) return s;
+  if ((s = adjoint_workspace(P))) return s;
+  return run_adjoint(P, level, d_phi_bar, d_acc_bar, d_mass_bar, (hipStream_t)hip_stream, P->lv, P->adj_part);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free adjoint.  Its scratch lives in `scratch`, a file-scope
+// device array of kScratchBytes: every GPU the library runs on holds one copy
+// until the process ends.  Host code never uses the array's name as an address
+// (on the host it is only a stand-in for the symbol): the device address of
+// each GPU's copy is looked up once per device with hipGetSymbolAddress and
+// kept in g_scratch_ptr.  Every call on one GPU shares its copy, so calls that
+// overlap on one GPU (other streams, other threads) race; calls on one stream
+// are ordered.  Every byte a call reads is written earlier in the same call
+// (bars are cleared by fill kernels, the B staging and the partial sets are
+// written in full), so no call depends on what the previous one left.
+namespace {
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+}  // namespace
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static void* g_scratch_ptr[kMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
+static afmm_status scratch_address(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(AFMM_E_DEVICE, "hipGetDevice failed");
+  if (dev < 0 || dev >= kMaxDevices) return fail(AFMM_E_UNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return fail(AFMM_E_DEVICE, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return AFMM_OK;
+}
+
+// Whether the allocation-free adjoint can serve this plan, from an upper bound
+// of its scratch that needs no topology: every level with B staging, and tap
+// -split partial sets for tile counts of at most ceil(cells / 16) + 8.
+static bool adjoint_noalloc_may_fit(const afmm_plan* P) {
+  const Topology& T = P->topo;
+  const int K = P->K;
+  size_t b = 0;
+  auto add = [&](size_t bytes) { b += (bytes + 255) & ~(size_t)255; };
+  const int ncu = device_cu_count();
+  size_t part = 0;
+  for (int l = 0; l <= T.lmax; ++l) {
+    const size_t n = (size_t)std::max(T.lv[l].n(), 1), nref = (size_t)T.lv[l].nref();
+    add(n * 32);
+    add(n * 8);
+    add(nref * K * 8);
+    add(nref * K * 8);
+    add(nref * 32 * 8);
+    add(nref * (size_t)src_row(P->opt.p, 8) * 8);
+    const size_t nt = (size_t)(T.lv[l].n() + 15) / 16 + 8;
+    const size_t sp = (size_t)std::max(1, std::min(16, (int)((12 * (size_t)ncu + nt - 1) / nt)));
+    part = std::max(part, sp * nt * 16 * K);
+  }
+  add(part * 8);
+  return b <= kScratchBytes;
+}
+
+static afmm_status afmm_solve_adjoint_noalloc_impl(afmm_plan* P, int32_t level, const double* d_phi_bar,
+                                                  const double* d_acc_bar, double* d_mass_bar, void* hip_stream) {
+  afmm_status s;
+  if ((s = adjoint_args(P, level, d_phi_bar, d_acc_bar, d_mass_bar))) return s;
+  if (!P->adj_topo)
+    return fail(AFMM_E_OUT_OF_MEMORY,
+                "the plan's adjoint scratch exceeds the static maximum of afmm_solve_adjoint_noalloc (its topology "
+                "was not prepared at plan creation)");
+  LevelDev lw[kMaxLevel + 1];
+  std::memcpy((void*)lw, (const void*)P->lv, sizeof lw);
+  double* part = nullptr;
+  const size_t need = adjoint_layout(P, nullptr, lw, &part);
+  if (need > kScratchBytes) {
+    char b[200];
+    snprintf(b, sizeof b, "adjoint scratch of %zu bytes exceeds the static maximum of %zu bytes", need, kScratchBytes);
+    return fail(AFMM_E_OUT_OF_MEMORY, b);
+  }
+  void* base = nullptr;
+  if ((s = scratch_address(&base))) return s;
+  adjoint_layout(P, (char*)base, lw, &part);
+  return run_adjoint(P, level, d_phi_bar, d_acc_bar, d_mass_bar, (hipStream_t)hip_stream, lw, part);
 }
 
 // Append topology S (one hierarchy) to the forest T, offsetting cells, refined
@@ -2487,6 +2615,12 @@ extern "C" afmm_status afmm_batch_autotune(afmm_batch* B, const double* const* d
 extern "C" afmm_status afmm_solve_adjoint(afmm_plan* P, int32_t level, const double* d_phi_bar,
                                           const double* d_acc_bar, double* d_mass_bar, void* hip_stream) {
   return guarded([&] { return afmm_solve_adjoint_impl(P, level, d_phi_bar, d_acc_bar, d_mass_bar, hip_stream); });
+}
+
+extern "C" afmm_status afmm_solve_adjoint_noalloc(afmm_plan* P, int32_t level, const double* d_phi_bar,
+                                                  const double* d_acc_bar, double* d_mass_bar, void* hip_stream) {
+  return guarded(
+      [&] { return afmm_solve_adjoint_noalloc_impl(P, level, d_phi_bar, d_acc_bar, d_mass_bar, hip_stream); });
 }
 
 extern "C" afmm_status afmm_batch_create(afmm_plan* const* plans, int32_t n, void* hip_stream, afmm_batch** out) {

@@ -9,6 +9,9 @@
            _F64, 512 flops each) and a kernel trace of the same command ->
            issued MFMA flops per dispatch of each MFMA kernel over its average
            traced duration, against the dense MFMA peak of its precision.
+  counters: several --pmc passes of one command -> per-kernel medians of every
+           counter and derived ratios (MFMA busy fraction, wait shares, LDS bank
+           conflicts, instructions per MFMA).
   traffic: two --pmc runs of the same command (FETCH_SIZE, then WRITE_SIZE) ->
            HBM bytes per launch of one kernel, each counter scaled by the reading
            of the same counter for a plain device copy of known size (the
@@ -161,6 +164,80 @@ def cmd_traffic(a):
     print(json.dumps(res, indent=1))
 
 
+def cmd_counters(a):
+    """Counter passes (--pmc runs of one command, one directory each) -> per-kernel
+    medians over the last N dispatches, with the durations of a kernel trace of
+    the same command; plus ratios that say where the waves' time goes."""
+    vals = {}
+    for d in a.pmc:
+        for r in csv.DictReader(open(_find(d, "counter_collection.csv"))):
+            k = short(r["Kernel_Name"])
+            if a.kernels and k not in a.kernels:
+                continue
+            key = (k, r["Counter_Name"], r.get("Dispatch_Id", ""))
+            vals[key] = vals.get(key, 0.0) + float(r["Counter_Value"])
+    per = {}
+    for (k, c, did), v in vals.items():
+        per.setdefault((k, c), []).append((int(did) if did.isdigit() else 0, v))
+    med = {}
+    for (k, c), v in per.items():
+        v.sort()
+        med[(k, c)] = statistics.median(x for _, x in v[-a.last:])
+    dur = {}
+    if a.trace:
+        for r in csv.DictReader(open(_find(a.trace, "kernel_trace.csv"))):
+            k = short(r["Kernel_Name"])
+            dur.setdefault(k, []).append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    kernels = a.kernels or sorted({k for k, _ in med})
+    counters = sorted({c for _, c in med})
+    out = [f"# Hardware counters: {a.title}", "",
+           "Median over the last dispatches of each kernel (the timed launches) of each counter, summed over",
+           "the GPU's shader engines / instances, one rocprofv3 --pmc pass per group of counters (no pass",
+           "exceeds the hardware's counter slots).  Cycle counters named *_CYCLES are per SIMD or per wave as",
+           "rocprofv3 documents them; SQ_WAVE_CYCLES, SQ_WAIT_* and SQ_BUSY_CU_CYCLES are in quad-cycles.", "",
+           "Commands (repository root on the MI355X box):", "", "```", *a.command, "```", "",
+           "| counter | " + " | ".join(f"`{k}`" for k in kernels) + " |", "|---|" + "---|" * len(kernels)]
+    for c in counters:
+        out.append(f"| {c} | " + " | ".join(f"{med[(k, c)]:.4g}" if (k, c) in med else "" for k in kernels) + " |")
+    out += ["", "## Derived", ""]
+    rows = []
+
+    def g(k, c):
+        return med.get((k, c))
+    for k in kernels:
+        r = {"kernel": k}
+        if k in dur:
+            d = sorted(dur[k])[-a.last:]
+            r["us"] = statistics.median(x[1] for x in d) / 1e3
+        cyc = r.get("us", 0) * 1e-6 * a.clock_ghz * 1e9
+        if g(k, "SQ_VALU_MFMA_BUSY_CYCLES") and cyc:
+            r["mfma_busy"] = g(k, "SQ_VALU_MFMA_BUSY_CYCLES") / (cyc * a.simds)
+        wc = g(k, "SQ_WAVE_CYCLES")
+        if wc:
+            for c in ("SQ_WAIT_INST_ANY", "SQ_WAIT_ANY", "SQ_ACTIVE_INST_ANY", "SQ_WAIT_INST_LDS"):
+                if g(k, c) is not None:
+                    r[c[3:].lower() + "/wave_cycles"] = g(k, c) / wc
+            if cyc:
+                r["wave_occupancy_index"] = 4.0 * wc / (cyc * a.simds)
+        if g(k, "SQ_LDS_BANK_CONFLICT") is not None and g(k, "SQ_ACTIVE_INST_LDS"):
+            r["lds_bank_conflict/active_lds"] = g(k, "SQ_LDS_BANK_CONFLICT") / g(k, "SQ_ACTIVE_INST_LDS")
+        mf = g(k, "SQ_INSTS_MFMA") or g(k, "SQ_INSTS_VALU_MFMA_F32")
+        if mf:
+            for c in ("SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD", "SQ_INSTS_SALU", "SQ_INSTS_VALU"):
+                if g(k, c) is not None:
+                    r[c[9:].lower() + "/mfma"] = g(k, c) / mf
+        rows.append(r)
+    keys = []
+    for r in rows:
+        keys += [x for x in r if x not in keys and x != "kernel"]
+    out.append("| kernel | " + " | ".join(keys) + " |")
+    out.append("|---|" + "---|" * len(keys))
+    for r in rows:
+        out.append(f"| `{r['kernel']}` | " + " | ".join(f"{r[x]:.3g}" if x in r else "" for x in keys) + " |")
+    open(a.out, "w").write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="mode", required=True)
@@ -189,8 +266,18 @@ def main():
     t.add_argument("--command-fetch", required=True)
     t.add_argument("--command-write", required=True)
     t.add_argument("--out", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("--pmc", required=True, nargs="+")
+    c.add_argument("--trace")
+    c.add_argument("--kernels", nargs="*")
+    c.add_argument("--last", type=int, default=5)
+    c.add_argument("--clock-ghz", type=float, default=2.4)
+    c.add_argument("--simds", type=int, default=1024)
+    c.add_argument("--title", required=True)
+    c.add_argument("--command", required=True, nargs="+")
+    c.add_argument("--out", required=True)
     a = ap.parse_args()
-    {"stats": cmd_stats, "mfma": cmd_mfma, "traffic": cmd_traffic}[a.mode](a)
+    {"stats": cmd_stats, "mfma": cmd_mfma, "traffic": cmd_traffic, "counters": cmd_counters}[a.mode](a)
 
 
 if __name__ == "__main__":

@@ -72,12 +72,15 @@ def ats_sequence(lmin, lmax):
     return seq
 
 
-def time_ats(h, mass_t, p, precision, reps=2):
+def time_ats(h, mass_t, p, precision, reps=2, graph=False):
     """One coarse step of the adaptive-time-step sequence, masses of the active
-    levels perturbed by 1e-3 seeded noise before every solve."""
+    levels perturbed by 1e-3 seeded noise before every solve.  With `graph` the
+    plan replays captured graphs (AFMM_GRAPH); the masses of each substep are
+    then copied into one buffer first (a device copy inside the timed region),
+    as an integrator updating them in place would."""
     import torch
     import paper_2607_19489_amd as A
-    plan = A.Plan(h, p=p, precision=precision)
+    plan = A.Plan(h, p=p, precision=precision, graph=graph)
     plan.autotune(mass_t)
     seq = ats_sequence(h.levelmin, h.levelmax)
     lev = torch.from_numpy(h.level_of()).cuda()
@@ -91,6 +94,7 @@ def time_ats(h, mass_t, p, precision, reps=2):
         masses.append(m)
     phi = torch.zeros(h.total, dtype=torch.float64, device="cuda")
     acc = torch.zeros(h.total, 3, dtype=torch.float64, device="cuda")
+    mbuf = mass_t.clone()
     per_level = {}
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in seq]
     best = None
@@ -99,6 +103,9 @@ def time_ats(h, mass_t, p, precision, reps=2):
         t0 = time.perf_counter()
         for (l, ic), mm, (a, b) in zip(seq, masses, ev):
             a.record()
+            if graph:
+                mbuf.copy_(mm)
+                mm = mbuf
             plan.solve(mm, level=l, icount=ic, phi=phi, acc=acc)
             b.record()
         torch.cuda.synchronize()
@@ -214,7 +221,7 @@ def run_batch(args):
     print(json.dumps(line), flush=True)
 
 
-def time_form(h, mass_t, p, precision, steps, warmup, overlap=False, autotune=True):
+def time_form(h, mass_t, p, precision, steps, warmup, overlap=False, autotune=True, graph=False):
     """Autotuned plan (tap splits), timed solves (no instrumentation), then the same
     number of profiled solves: the profiled pass runs serially with hipEvents
     around every launch."""
@@ -222,7 +229,7 @@ def time_form(h, mass_t, p, precision, steps, warmup, overlap=False, autotune=Tr
     import paper_2607_19489_amd as A
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plan = A.Plan(h, p=p, precision=precision, overlap=overlap)
+    plan = A.Plan(h, p=p, precision=precision, overlap=overlap, graph=graph)
     torch.cuda.synchronize()
     plan_ms = 1e3 * (time.perf_counter() - t0)
     info = plan.info()
@@ -406,6 +413,7 @@ def main():
     ap.add_argument("--workload", default="cfg3", choices=["cfg1", "cfg2", "cfg3", "cfg4", "cfg5"])
     ap.add_argument("--overlap", action="store_true", help="also time the two-stream schedule (AFMM_OVERLAP)")
     ap.add_argument("--no-ats", action="store_true", help="skip the adaptive-time-step cycle")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay timings (AFMM_GRAPH)")
     ap.add_argument("--p", type=int, default=4, help="expansion order of the batched workload (cfg4)")
     ap.add_argument("--members", type=int, default=256, help="hierarchies in the batched workload (cfg4)")
     ap.add_argument("--adjoint", action="store_true", help="also time the adjoint pass (default for cfg5)")
@@ -447,6 +455,15 @@ def main():
         r32s, _, _ = time_form(h, mass_t, w.p, "fp32", args.steps, 1, overlap=True, autotune=not args.no_autotune)
         print(f"[bench] fp32 form, two streams: {r32s['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     outputs = {"fp32": (phi32, acc32)}
+    r32g = None
+    if not args.no_graph:
+        r32g, phi32g, acc32g = time_form(h, mass_t, w.p, "fp32", args.steps, args.warmup, graph=True,
+                                         autotune=not args.no_autotune)
+        print(f"[bench] fp32 form, graph replay: {r32g['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+        # identical bits to the eager solves when the tuner chose the same splits
+        same = (r32g["autotune"] or {}).get("m2l_split") == (r32["autotune"] or {}).get("m2l_split") and \
+            (r32g["autotune"] or {}).get("m2p_split") == (r32["autotune"] or {}).get("m2p_split")
+        graph_equal = bool(np.array_equal(phi32g, phi32) and np.array_equal(acc32g, acc32)) if same else None
     r64 = None
     if not args.no_fp64:
         r64, phi64, acc64 = time_form(h, mass_t, w.p, "fp64", max(args.steps // 2, 1), 1,
@@ -458,6 +475,11 @@ def main():
     if args.ats or (args.workload == "cfg3" and not args.no_ats):
         ats = time_ats(h, mass_t, w.p, "fp32")
         print(f"[bench] ATS step: {ats['solves']} solves in {ats['sequence_ms']:.2f} ms", file=sys.stderr, flush=True)
+        if not args.no_graph:
+            atsg = time_ats(h, mass_t, w.p, "fp32", graph=True)
+            ats["graph_sequence_ms"] = atsg["sequence_ms"]
+            ats["graph_leaf_updates_per_s"] = atsg["leaf_updates_per_s"]
+            print(f"[bench] ATS step, graph replay: {atsg['sequence_ms']:.2f} ms", file=sys.stderr, flush=True)
 
     adj = None
     if args.adjoint or args.workload == "cfg5":
@@ -495,6 +517,10 @@ def main():
         "plan_create_ms": {"fp32": r32["plan_create_ms"], "fp64": None if r64 is None else r64["plan_create_ms"]},
         "end_to_end_first_solve_ms": r32["plan_create_ms"] + r32["ms_per_step"],
         "overlap_ms_per_step": None if r32s is None else r32s["ms_per_step"],
+        "graph": None if r32g is None else {"ms_per_step": r32g["ms_per_step"], "value": r32g["value"],
+                                            "eager_ms_per_step": r32["ms_per_step"],
+                                            "bitwise_equal_to_eager": graph_equal,
+                                            "autotune": r32g["autotune"]},
         "autotune_fp32": r32["autotune"], "autotune_fp64": None if r64 is None else r64["autotune"],
         "profiled_ms_per_step": sum(v["ms"] for v in r32["kernels"].values()) / r32["steps"],
         "error_vs_oracle_sample": errs,

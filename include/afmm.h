@@ -58,6 +58,14 @@ typedef int32_t afmm_status;
                                 Results are identical either way; measured on MI355X the overlap
                                 does not pay (both launches fill the GPU), so it is off by default */
 
+#define AFMM_GRAPH 32u       /* replay solves from hipGraphs: the launches of one afmm_solve are
+                                captured (on an internal stream, on first use) once per distinct
+                                (level, rebuild or not, trees kept or not, d_mass, d_phi, d_acc)
+                                and replayed as one graph launch on the caller's stream; results
+                                are identical to eager solves.  Up to 32 graphs are cached per plan
+                                (least recently used evicted); the autotuner drops them.  Profiled
+                                solves run eagerly.  Callers that change I/O buffers every call get
+                                a capture per call: keep the buffers, update them in place. */
 #define AFMM_PAPER_QUAD_CAP 8u
                              /* the paper's expansion setting (Sec. 2: local expansions to order p,
                                 multipoles only up to the quadrupole at p = 3): every multipole that
@@ -81,8 +89,8 @@ typedef struct afmm_options {
   int32_t precision;         /* AFMM_FP64 or AFMM_FP32_MIXED */
   double G;                  /* gravitational constant */
   double boxlen;             /* box side */
-  uint32_t flags;            /* AFMM_CHECK_INPUT | AFMM_SERIAL | AFMM_OVERLAP | AFMM_PAPER_QUAD_CAP |
-                                AFMM_SELF_POTENTIAL */
+  uint32_t flags;            /* AFMM_CHECK_INPUT | AFMM_SERIAL | AFMM_OVERLAP | AFMM_GRAPH |
+                                AFMM_PAPER_QUAD_CAP | AFMM_SELF_POTENTIAL */
   int32_t fp64_levels;       /* mixed form: FMM levels <= this stay FP64 (default 3) */
   int32_t tap_split;         /* M2L and M2P blocks per tile: the 189 source offsets of a tile are
                                 split over this many blocks and their partial sums reduced in a

@@ -17,6 +17,7 @@ AFMM_CHECK_INPUT = 1
 AFMM_SERIAL = 2
 AFMM_OVERLAP = 4
 AFMM_PAPER_QUAD_CAP = 8
+AFMM_GRAPH = 32
 AFMM_SELF_POTENTIAL = 16
 AFMM_ALL_LEVELS = -1
 

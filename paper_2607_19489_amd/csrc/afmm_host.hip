@@ -843,6 +843,22 @@ struct afmm_plan {
   // internal side stream: the downward M2L/L2L chain runs on it concurrently
   // with the leaf-level M2P (they only share the multipoles of the upward pass)
   hipStream_t side = nullptr;
+  // AFMM_GRAPH: solves replayed from captured graphs, one per (level, rebuild,
+  // kept trees, caller pointers), captured on an internal stream on first use
+  struct GraphEntry {
+    int level;
+    bool rebuild, keep;
+    const double* m;
+    double* phi;
+    double* acc;
+    hipGraph_t g;
+    hipGraphExec_t x;
+    uint64_t used;
+  };
+  std::vector<GraphEntry> graphs;
+  uint64_t graph_tick = 0;
+  hipStream_t cap = nullptr;
+  bool capturing = false;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   MfmaTables mt;
   TablesDev<float> t32;
@@ -942,8 +958,20 @@ afmm_status upload_conv(afmm_plan* P, const std::vector<double>& v, const T** ou
   return s;
 }
 
+void drop_graphs(afmm_plan* P) {
+  for (auto& e : P->graphs) {
+    if (e.x) (void)hipGraphExecDestroy(e.x);
+    if (e.g) (void)hipGraphDestroy(e.g);
+  }
+  P->graphs.clear();
+}
+
 void free_plan(afmm_plan* P) {
   if (P->side) (void)hipStreamSynchronize(P->side);
+  if (P->cap) (void)hipStreamSynchronize(P->cap);
+  drop_graphs(P);
+  if (P->cap) (void)hipStreamDestroy(P->cap);
+  P->cap = nullptr;
   for (void* p : P->allocs) (void)hipFree(p);
   P->allocs.clear();
   if (P->h_flag) (void)hipHostFree(P->h_flag);
@@ -967,7 +995,7 @@ afmm_status check_options(const afmm_options* o) {
   if (o->p < 1 || o->p > kPMax) return fail(AFMM_E_UNSUPPORTED, "p must be in 1..8");
   if (o->precision != AFMM_FP64 && o->precision != AFMM_FP32_MIXED)
     return fail(AFMM_E_UNSUPPORTED, "unknown precision");
-  if (o->flags & ~(AFMM_CHECK_INPUT | AFMM_SERIAL | AFMM_OVERLAP | AFMM_PAPER_QUAD_CAP | AFMM_SELF_POTENTIAL))
+  if (o->flags & ~(AFMM_CHECK_INPUT | AFMM_SERIAL | AFMM_OVERLAP | AFMM_PAPER_QUAD_CAP | AFMM_SELF_POTENTIAL | AFMM_GRAPH))
     return fail(AFMM_E_UNSUPPORTED, "unknown flag");
   if (!(o->boxlen > 0) || !std::isfinite(o->boxlen)) return fail(AFMM_E_INVALID_ARG, "boxlen must be > 0");
   if (!std::isfinite(o->G)) return fail(AFMM_E_INVALID_ARG, "G must be finite");
@@ -1170,6 +1198,7 @@ static afmm_status place_split_buffers(afmm_plan* P) {
 // device copy of lv[] is refreshed in every case.
 static afmm_status alloc_split_buffers(afmm_plan* P, const int* prev_m2l = nullptr, const int* prev_m2p = nullptr) {
   const bool had = P->d_lvs != nullptr;
+  drop_graphs(P);  // captured launches hold the old buffers and grids
   if (had && hipDeviceSynchronize() != hipSuccess) {
     P->dead = true;
     return fail(AFMM_E_DEVICE, "sync before reallocation");
@@ -1494,6 +1523,8 @@ static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
   // a plan small enough for the allocation-free adjoint gets its adjoint
   // topology now, so that afmm_solve_adjoint_noalloc never has to allocate it
   if (T.levelmin.size() == 1 && adjoint_noalloc_may_fit(P) && (s = adjoint_topology(P))) return s;
+  if ((P->opt.flags & AFMM_GRAPH) && hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking) != hipSuccess)
+    return fail(AFMM_E_DEVICE, "capture stream creation failed");
   if (hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming) != hipSuccess)
@@ -1630,7 +1661,7 @@ static afmm_status run_solve(afmm_plan* P, const double* msrc, int fmax, int lo,
   // small first launches get the CUs first and M2P fills the rest.  Serial
   // plans (and profiled solves: events then time one launch at a time) use
   // one stream.
-  const bool serial = !(P->opt.flags & AFMM_OVERLAP) || (P->opt.flags & AFMM_SERIAL) || P->profiling;
+  const bool serial = !(P->opt.flags & AFMM_OVERLAP) || (P->opt.flags & AFMM_SERIAL) || P->profiling || P->capturing;
   hipStream_t sm = serial ? st : P->side;
   if (!serial && ((s = dev_check(P, hipEventRecord(P->ev_fork, st), "fork")) ||
                   (s = dev_check(P, hipStreamWaitEvent(sm, P->ev_fork, 0), "fork"))))
@@ -1723,6 +1754,52 @@ static afmm_status run_solve(afmm_plan* P, const double* msrc, int fmax, int lo,
   return AFMM_OK;
 }
 
+// Runs `body` (the launches of one solve, enqueued on the stream it is given)
+// on `st`, or with AFMM_GRAPH replays it from a graph captured on first use for
+// this key.  Profiled solves always run eagerly (their events time each launch).
+template <typename Body>
+static afmm_status replay_or_run(afmm_plan* P, int level, bool rebuild, bool keep, const double* m, double* phi,
+                                 double* acc, hipStream_t st, Body body) {
+  if (!(P->opt.flags & AFMM_GRAPH) || P->profiling) return body(st);
+  afmm_plan::GraphEntry* hit = nullptr;
+  for (auto& e : P->graphs)
+    if (e.level == level && e.rebuild == rebuild && e.keep == keep && e.m == m && e.phi == phi && e.acc == acc)
+      hit = &e;
+  if (!hit) {
+    constexpr size_t kMaxGraphs = 32;
+    if (P->graphs.size() >= kMaxGraphs) {  // evict the least recently used
+      size_t old = 0;
+      for (size_t i = 1; i < P->graphs.size(); ++i)
+        if (P->graphs[i].used < P->graphs[old].used) old = i;
+      if (hipStreamSynchronize(st) != hipSuccess) return dev_check(P, hipGetLastError(), "graph eviction");
+      (void)hipGraphExecDestroy(P->graphs[old].x);
+      (void)hipGraphDestroy(P->graphs[old].g);
+      P->graphs.erase(P->graphs.begin() + (long)old);
+    }
+    afmm_plan::GraphEntry e{level, rebuild, keep, m, phi, acc, nullptr, nullptr, 0};
+    if (hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return dev_check(P, hipGetLastError(), "graph capture begin");
+    P->capturing = true;
+    afmm_status r = body(P->cap);
+    P->capturing = false;
+    const hipError_t ee = hipStreamEndCapture(P->cap, &e.g);
+    if (r) {
+      if (e.g) (void)hipGraphDestroy(e.g);
+      return r;
+    }
+    if (ee != hipSuccess || !e.g) return dev_check(P, ee != hipSuccess ? ee : hipErrorUnknown, "graph capture");
+    const hipError_t ei = hipGraphInstantiate(&e.x, e.g, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+      (void)hipGraphDestroy(e.g);
+      return dev_check(P, ei, "graph instantiation");
+    }
+    P->graphs.push_back(e);
+    hit = &P->graphs.back();
+  }
+  hit->used = ++P->graph_tick;
+  return dev_check(P, hipGraphLaunch(hit->x, st), "graph launch");
+}
+
 static afmm_status afmm_solve_impl(afmm_plan* P, int32_t level, int32_t icount, const double* d_mass, double* d_phi,
                                   double* d_acc, void* hip_stream) {
   if (!P || !d_mass || !d_phi || !d_acc) return fail(AFMM_E_INVALID_ARG, "null argument");
@@ -1764,7 +1841,9 @@ static afmm_status afmm_solve_impl(afmm_plan* P, int32_t level, int32_t icount, 
     P->last_level = AFMM_ALL_LEVELS;
     P->last_fresh = 0;
     P->tree_fresh = false;
-    afmm_status r = run_solve(P, d_mass, T.lmax - 1, lmin, lmax, d_phi, d_acc, st, false, P->m_snap);
+    afmm_status r = replay_or_run(P, AFMM_ALL_LEVELS, true, false, d_mass, d_phi, d_acc, st, [&](hipStream_t s) {
+      return run_solve(P, d_mass, T.lmax - 1, lmin, lmax, d_phi, d_acc, s, false, P->m_snap);
+    });
     P->tree_fresh = r == AFMM_OK;
     return r;
   }
@@ -1772,15 +1851,7 @@ static afmm_status afmm_solve_impl(afmm_plan* P, int32_t level, int32_t icount, 
   const bool rebuild = (level == lmin) || (icount > 1);
   if (!P->snap_valid && level != lmin)
     return fail(AFMM_E_ATS_ORDER, "solve(l > levelmin) before any tree was built (call solve(levelmin) first)");
-  if (rebuild) {
-    const int64_t off = T.level_off[0][level - lmin];
-    if (dev_check(P,
-                  hipMemcpyAsync(P->m_snap + off, d_mass + off, (size_t)(T.nslots - off) * sizeof(double),
-                                 hipMemcpyDeviceToDevice, st),
-                  "snapshot"))
-      return AFMM_E_DEVICE;
-    P->snap_valid = true;
-  }
+  if (rebuild) P->snap_valid = true;
   P->solved = true;
   P->last_level = level;
   P->last_fresh = rebuild ? level : T.lmax + 1;
@@ -1788,7 +1859,16 @@ static afmm_status afmm_solve_impl(afmm_plan* P, int32_t level, int32_t icount, 
   // the level masses and merged multipoles of the previous solve, still hold
   const bool keep = !rebuild && P->tree_fresh;
   P->tree_fresh = false;
-  afmm_status r = run_solve(P, P->m_snap, level - 1, level, level, d_phi, d_acc, st, keep);
+  const int64_t off = T.level_off[0][level - lmin];
+  afmm_status r = replay_or_run(P, level, rebuild, keep, d_mass, d_phi, d_acc, st, [&](hipStream_t s) -> afmm_status {
+    // the rebuilt trees take the masses of levels >= level from this call
+    if (rebuild && dev_check(P,
+                             hipMemcpyAsync(P->m_snap + off, d_mass + off, (size_t)(T.nslots - off) * sizeof(double),
+                                            hipMemcpyDeviceToDevice, s),
+                             "snapshot"))
+      return AFMM_E_DEVICE;
+    return run_solve(P, P->m_snap, level - 1, level, level, d_phi, d_acc, s, keep);
+  });
   P->tree_fresh = r == AFMM_OK;
   return r;
 }

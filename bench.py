@@ -157,6 +157,33 @@ def time_adjoint(h, mass_t, p, precision, steps):
             "forward_kernels": kernel_table({"kernels": fwd_prof, "steps": steps})}
 
 
+def run_binary(levelmax, dt=0.01, tend=8.0):
+    """The binary-orbit time loop (two masses G m = 0.01, separation 0.15,
+    levelmin 6, two cells of mesh expansion, fixed-step leapfrog to t = 8): wall
+    time per step, plans built, and the orbit's deviations from the analytic
+    circular orbit."""
+    import torch
+    from paper_2607_19489_amd import pm
+    pos, vel, m, omega = pm.binary_initial(gm=0.01, sep=0.15)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim = pm.ParticleMesh(pos, vel, m, 6, levelmax, nexpand=2, p=6, precision="fp64")
+    n = int(round(tend / dt))
+    for _ in range(n):
+        sim.step(dt)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    x, v = sim.pos.cpu().numpy(), sim.vel.cpu().numpy()
+    d = x[0] - x[1]
+    ang = np.arctan2(d[1], d[0])
+    out = {"levels": [6, levelmax], "steps": n, "dt": dt, "t": sim.t, "plans": sim.replans,
+           "ms_per_step": 1e3 * wall / n, "final_sep_rel_err": float(abs(np.linalg.norm(d) - 0.15) / 0.15),
+           "final_phase_rad": float((ang - omega * sim.t + np.pi) % (2 * np.pi) - np.pi),
+           "cells": int(sim.h.total)}
+    sim.close()
+    return out
+
+
 def run_batch(args):
     """Batched workload: independent hierarchies of uneven size, one graph launch per solve."""
     import torch
@@ -414,6 +441,7 @@ def main():
     ap.add_argument("--overlap", action="store_true", help="also time the two-stream schedule (AFMM_OVERLAP)")
     ap.add_argument("--no-ats", action="store_true", help="skip the adaptive-time-step cycle")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay timings (AFMM_GRAPH)")
+    ap.add_argument("--binary", action="store_true", help="also run the binary-orbit time loop (levelmax 6, 7, 8)")
     ap.add_argument("--p", type=int, default=4, help="expansion order of the batched workload (cfg4)")
     ap.add_argument("--members", type=int, default=256, help="hierarchies in the batched workload (cfg4)")
     ap.add_argument("--adjoint", action="store_true", help="also time the adjoint pass (default for cfg5)")
@@ -487,6 +515,13 @@ def main():
         print(f"[bench] adjoint {adj['adjoint_ms']:.3f} ms vs forward {adj['forward_ms']:.3f} ms",
               file=sys.stderr, flush=True)
 
+    binary = None
+    if args.binary:
+        binary = [run_binary(lm) for lm in (6, 7, 8)]
+        for b in binary:
+            print(f"[bench] binary orbit {b['levels']}: {b['ms_per_step']:.2f} ms/step, {b['plans']} plans",
+                  file=sys.stderr, flush=True)
+
     base, errs = (None, None)
     if not args.no_cpu:
         base, errs = cpu_baseline(h, m, w.p, args.cpu_seconds, outputs)
@@ -530,6 +565,7 @@ def main():
         "kernels_fp64": None if r64 is None else kernel_table(r64),
         "adjoint": adj,
         "ats_step": ats,
+        "binary_orbit": binary,
     }
     print(json.dumps(line), flush=True)
 

@@ -292,6 +292,54 @@ afmm_status afmm_plan_autotune(afmm_plan* plan, const double* d_mass, double* d_
 afmm_status afmm_batch_autotune(afmm_batch* batch, const double* const* d_mass, double* const* d_phi,
                                 double* const* d_acc, void* hip_stream, afmm_tune_result* out);
 
+/*
+ * Particle-mesh coupling for time loops.  The paper's solver works on cell
+ * masses obtained by depositing particle masses onto the AMR cells with a
+ * cloud-in-cell scheme (Sec. 1), and its binary-orbit test (Sec. 4, Fig.
+ * fig:binary) advances two point masses with a fixed-step leapfrog on a grid
+ * refined around them.  These calls provide the pieces of such a loop.
+ *
+ * afmm_particle_hierarchy_create: host only.  A graded hierarchy over levels
+ * levelmin..levelmax (levelmin complete): at every level l < levelmax each
+ * cell within `nexpand` cells (Chebyshev distance, clipped to the box) of the
+ * 2x2x2 cloud of a particle at level l is refined, then the strong grading
+ * rule (Sec. 3.2) is closed; levelmax of the result is the deepest level that
+ * has cells.  pos: host [np][3], inside [0, boxlen).  The result is owned by
+ * the library: afmm_particle_hierarchy_view fills an afmm_hierarchy that
+ * points into it (valid until afmm_particle_hierarchy_destroy).
+ */
+typedef struct afmm_particle_hierarchy afmm_particle_hierarchy;
+afmm_status afmm_particle_hierarchy_create(int32_t levelmin, int32_t levelmax, int32_t nexpand, int64_t np,
+                                           const double* pos, double boxlen, afmm_particle_hierarchy** out);
+afmm_status afmm_particle_hierarchy_view(const afmm_particle_hierarchy* h, afmm_hierarchy* out);
+afmm_status afmm_particle_hierarchy_destroy(afmm_particle_hierarchy* h);
+
+/*
+ * afmm_cic_deposit: cell masses from particle masses by cloud-in-cell at one
+ * level: particle p (device d_pos[np][3], d_pmass[np]) gives the 8 cells of
+ * that level around it (centres within one cell size) the weights
+ * prod_d (1 - |x_d / h - 1/2 - c_d|).  d_cell_mass (device, one slot per cell
+ * of the plan's hierarchy, as for afmm_solve) is cleared first, then
+ * accumulated with atomic additions (the rounding of a sum depends on the
+ * order in which particles land).  Every cloud cell must be a leaf of `level`:
+ * otherwise (or if a cloud leaves the box) AFMM_E_INVALID_ARG after the call.
+ * One host sync.  The plan builds a key table of the level on first use
+ * (8 bytes per cell of the level, counted in its device memory).
+ * afmm_cic_interpolate: the inverse map with the same weights: d_acc[np][3] =
+ * sum of the cloud cells' d_cell_acc (and d_phi[np] of d_cell_phi when both
+ * are non-null); same requirements.  With deposition and interpolation at one
+ * level and the solver's antisymmetric near-field pairs, a particle exerts no
+ * force on itself.
+ * afmm_particles_update: d_state[i] += dt * d_rate[i] for i < n3 (the leapfrog
+ * kick v += dt a and drift x += dt v on [np][3] arrays, n3 = 3 np).
+ */
+afmm_status afmm_cic_deposit(afmm_plan* plan, int32_t level, int64_t np, const double* d_pos, const double* d_pmass,
+                             double* d_cell_mass, void* hip_stream);
+afmm_status afmm_cic_interpolate(afmm_plan* plan, int32_t level, int64_t np, const double* d_pos,
+                                 const double* d_cell_acc, const double* d_cell_phi, double* d_acc, double* d_phi,
+                                 void* hip_stream);
+afmm_status afmm_particles_update(int64_t n3, double dt, const double* d_rate, double* d_state, void* hip_stream);
+
 const char* afmm_status_string(afmm_status s);
 const char* afmm_last_error(void);
 

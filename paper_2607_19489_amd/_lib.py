@@ -34,6 +34,8 @@ SYMBOLS = [
     "afmm_batch_destroy", "afmm_hierarchy_check", "afmm_status_string", "afmm_last_error",
     "afmm_plan_set_profiling", "afmm_plan_get_profile", "afmm_batch_set_profiling", "afmm_batch_get_profile",
     "afmm_plan_autotune", "afmm_batch_autotune", "afmm_solve_adjoint_noalloc",
+    "afmm_particle_hierarchy_create", "afmm_particle_hierarchy_view", "afmm_particle_hierarchy_destroy",
+    "afmm_cic_deposit", "afmm_cic_interpolate", "afmm_particles_update",
 ]
 
 
@@ -118,6 +120,13 @@ def lib():
     L.afmm_batch_get_profile.argtypes = [vp, C.POINTER(StageTime), C.c_int32, C.POINTER(C.c_int32)]
     L.afmm_plan_autotune.argtypes = [vp, vp, vp, vp, vp, C.POINTER(TuneResult)]
     L.afmm_batch_autotune.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), vp, C.POINTER(TuneResult)]
+    L.afmm_particle_hierarchy_create.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int64, vp, C.c_double,
+                                                 C.POINTER(vp)]
+    L.afmm_particle_hierarchy_view.argtypes = [vp, C.POINTER(HierarchyC)]
+    L.afmm_particle_hierarchy_destroy.argtypes = [vp]
+    L.afmm_cic_deposit.argtypes = [vp, C.c_int32, C.c_int64, vp, vp, vp, vp]
+    L.afmm_cic_interpolate.argtypes = [vp, C.c_int32, C.c_int64, vp, vp, vp, vp, vp, vp]
+    L.afmm_particles_update.argtypes = [C.c_int64, C.c_double, vp, vp, vp]
     L.afmm_status_string.argtypes = [C.c_int32]
     L.afmm_status_string.restype = C.c_char_p
     L.afmm_last_error.argtypes = []
@@ -126,7 +135,9 @@ def lib():
                  "afmm_solve_adjoint", "afmm_solve_adjoint_noalloc", "afmm_batch_create", "afmm_batch_solve", "afmm_batch_get_info",
                  "afmm_batch_destroy", "afmm_hierarchy_check", "afmm_plan_set_profiling",
                  "afmm_plan_get_profile", "afmm_batch_set_profiling", "afmm_batch_get_profile",
-                 "afmm_plan_autotune", "afmm_batch_autotune"):
+                 "afmm_plan_autotune", "afmm_batch_autotune", "afmm_particle_hierarchy_create",
+                 "afmm_particle_hierarchy_view", "afmm_particle_hierarchy_destroy", "afmm_cic_deposit",
+                 "afmm_cic_interpolate", "afmm_particles_update"):
         getattr(L, name).restype = C.c_int32
     _lib = L
     return L

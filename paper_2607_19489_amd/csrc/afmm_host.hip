@@ -865,7 +865,8 @@ struct afmm_plan {
   TablesDev<double> t64;
   CommonDev cm;
   double* m_snap = nullptr;       // adaptive-time-step snapshot of leaf masses (slot space)
-  int* d_flag = nullptr;          // AFMM_CHECK_INPUT: device flag of the input scan (plan-owned)
+  uint64_t* d_keys[kMaxLevel] = {};  // per-level Morton keys of the cells (particle-mesh calls, on first use)
+  int* d_flag = nullptr;          // AFMM_CHECK_INPUT / particle-mesh calls: device flag (plan-owned)
   int* h_flag = nullptr;          // its pinned host copy
   double cself = 0.0;             // AFMM_SELF_POTENTIAL: the unit-cube constant, else 0
   bool snap_valid = false;
@@ -2719,3 +2720,49 @@ extern "C" afmm_status afmm_batch_get_profile(afmm_batch* B, afmm_stage_time* ou
 extern "C" afmm_status afmm_hierarchy_check(const afmm_hierarchy* h, const afmm_options* opt, afmm_plan_info* out) {
   return guarded([&] { return afmm_hierarchy_check_impl(h, opt, out); });
 }
+
+// ---------------------------------------------------------------------------
+// plan services of the particle-mesh calls (afmm_pm.hip)
+
+namespace afmm {
+
+afmm_status pm_fail(afmm_status s, const char* msg) { return fail(s, msg); }
+
+double plan_boxlen(const afmm_plan* P) { return P->opt.boxlen; }
+
+afmm_status plan_pm_flag(afmm_plan* P, int** d_flag, int** h_flag) {
+  if (P->dead) return fail(AFMM_E_DEVICE, "plan is unusable after an earlier device error");
+  *d_flag = P->d_flag;
+  *h_flag = P->h_flag;
+  return AFMM_OK;
+}
+
+// Morton keys of the cells of level `level` in the plan's order: the children
+// of refined rank r are cells 8r..8r+7 in octant order, so key = (father's
+// key << 3) | octant, ascending level by level.  Built on the host and uploaded
+// the first time a level is asked for (8 bytes per cell of that level).
+afmm_status plan_level_keys(afmm_plan* P, int level, const uint64_t** keys, const LevelDev** lv) {
+  if (P->dead) return fail(AFMM_E_DEVICE, "plan is unusable after an earlier device error");
+  const Topology& T = P->topo;
+  if (T.levelmin.size() != 1) return fail(AFMM_E_INVALID_ARG, "batched plan: no particle-mesh calls");
+  if (level < T.levelmin[0] || level > T.lmax) return fail(AFMM_E_INVALID_ARG, "level outside [levelmin, levelmax]");
+  if (!P->d_keys[level]) {
+    std::vector<uint64_t> prev{0}, cur;
+    for (int l = 1; l <= level; ++l) {
+      const HostLevel& U = T.lv[l - 1];
+      cur.assign((size_t)T.lv[l].n(), 0);
+      for (int32_t r = 0; r < U.nref(); ++r)
+        for (int o = 0; o < 8; ++o) cur[(size_t)8 * r + o] = (prev[U.refcell[r]] << 3) | (uint64_t)o;
+      prev.swap(cur);
+    }
+    uint64_t* d = nullptr;
+    afmm_status s = upload(P, prev, &d, nullptr);
+    if (s) return s;
+    P->d_keys[level] = d;
+  }
+  *keys = P->d_keys[level];
+  *lv = &P->lv[level];
+  return AFMM_OK;
+}
+
+}  // namespace afmm

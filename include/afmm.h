@@ -155,6 +155,27 @@ afmm_status afmm_plan_destroy(afmm_plan* plan);
 afmm_status afmm_plan_get_info(const afmm_plan* plan, afmm_plan_info* out);
 
 /*
+ * Re-plan between adaptive time steps (Sec. 3.2, Alg. 1): the AMR of levels
+ * >= level has changed since `old` was built, the levels below it have not.
+ * Builds a plan for `h` with the options of `old` (which the caller keeps and
+ * may destroy afterwards) and hands over the tree state of the stale levels:
+ * the leaf masses of levels < level that the last rebuild of `old` took stay
+ * those of the new plan's trees, while the trees of levels >= level are new
+ * and take their masses from d_mass at the next afmm_solve, whatever that
+ * call's level and icount (it then counts as a rebuild of levels >= min(its
+ * own level, `level`), for the input check and the adjoint alike).  If `old`
+ * holds no tree snapshot yet, the new plan holds none either.
+ *   level       in [levelmin + 1, levelmax(h) + 1]
+ * Requirements: same levelmin; levels below `level` identical in `h` and in the
+ * hierarchy of `old` (same cells, same caller order, same refined flags).
+ * Synchronous on hip_stream (the snapshot copy).  Errors: AFMM_E_INVALID_ARG
+ * (null pointer, a level out of range, differing coarse levels, a batched
+ * plan), AFMM_E_DEVICE (a dead `old`), and the errors of afmm_plan_create.
+ */
+afmm_status afmm_plan_replan(const afmm_plan* old, const afmm_hierarchy* h, int32_t level, void* hip_stream,
+                             afmm_plan** out);
+
+/*
  * Solve (Alg. 1).  d_mass, d_phi, d_acc are device pointers, FP64, one slot per
  * cell in the hierarchy's flat order (d_acc is [ncell][3]).  Masses of refined
  * cells are ignored.  Only leaves of the solved level(s) are written; other

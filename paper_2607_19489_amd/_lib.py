@@ -35,7 +35,7 @@ SYMBOLS = [
     "afmm_plan_set_profiling", "afmm_plan_get_profile", "afmm_batch_set_profiling", "afmm_batch_get_profile",
     "afmm_plan_autotune", "afmm_batch_autotune", "afmm_solve_adjoint_noalloc",
     "afmm_particle_hierarchy_create", "afmm_particle_hierarchy_view", "afmm_particle_hierarchy_destroy",
-    "afmm_cic_deposit", "afmm_cic_interpolate", "afmm_particles_update",
+    "afmm_cic_deposit", "afmm_cic_interpolate", "afmm_particles_update", "afmm_plan_replan",
 ]
 
 
@@ -105,6 +105,7 @@ def lib():
     L.afmm_options_default.restype = None
     L.afmm_plan_create.argtypes = [C.POINTER(HierarchyC), C.POINTER(Options), vp, C.POINTER(vp)]
     L.afmm_plan_destroy.argtypes = [vp]
+    L.afmm_plan_replan.argtypes = [vp, C.POINTER(HierarchyC), C.c_int32, vp, C.POINTER(vp)]
     L.afmm_plan_get_info.argtypes = [vp, C.POINTER(PlanInfo)]
     L.afmm_solve.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp, vp]
     L.afmm_solve_adjoint.argtypes = [vp, C.c_int32, vp, vp, vp, vp]
@@ -137,7 +138,7 @@ def lib():
                  "afmm_plan_get_profile", "afmm_batch_set_profiling", "afmm_batch_get_profile",
                  "afmm_plan_autotune", "afmm_batch_autotune", "afmm_particle_hierarchy_create",
                  "afmm_particle_hierarchy_view", "afmm_particle_hierarchy_destroy", "afmm_cic_deposit",
-                 "afmm_cic_interpolate", "afmm_particles_update"):
+                 "afmm_cic_interpolate", "afmm_particles_update", "afmm_plan_replan"):
         getattr(L, name).restype = C.c_int32
     _lib = L
     return L

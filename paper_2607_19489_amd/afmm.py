@@ -98,6 +98,20 @@ class Plan:
         self.p = p
         self.precision = precision
 
+    def replan(self, h, level: int, stream: Optional[torch.cuda.Stream] = None) -> "Plan":
+        """afmm_plan_replan: a plan for `h`, whose levels below `level` are this
+        plan's, carrying over the stale trees' masses; this plan stays valid."""
+        arrs = _hierarchy_arrays(h)
+        hc = _hier_struct(*arrs)
+        new = Plan.__new__(Plan)
+        new._ptr = C.c_void_p()
+        check(lib().afmm_plan_replan(self._ptr, C.byref(hc), level, _stream_handle(stream), C.byref(new._ptr)),
+              "afmm_plan_replan")
+        new.levelmin, new.levelmax, new.ncell = arrs[0], arrs[1], arrs[2]
+        new.N = int(new.ncell.sum())
+        new.options, new.p, new.precision = self.options, self.p, self.precision
+        return new
+
     def close(self):
         if self._ptr:
             lib().afmm_plan_destroy(self._ptr)

@@ -876,6 +876,7 @@ struct afmm_plan {
   bool solved = false;            // a solve has run (the adjoint transposes the last one)
   int last_level = AFMM_ALL_LEVELS;
   int last_fresh = 0;             // levels >= this took their masses from the last call's d_mass
+  int fresh_from = 1 << 20;       // after afmm_plan_replan: levels >= this take their masses from the next call
   bool adj_ready = false;         // adjoint workspace allocated
   bool adj_topo = false;          // adjoint source tiles and splits built
   size_t adj_part_elems = 0;      // FP64 elements of the adjoint's tap-split partial sets
@@ -1564,6 +1565,51 @@ static afmm_status afmm_plan_create_impl(const afmm_hierarchy* h, const afmm_opt
   return AFMM_OK;
 }
 
+// New plan for a hierarchy whose levels below `level` are those of `old`
+// (cells, caller order and refined flags): the stale trees of those levels
+// keep the masses of their last rebuild (old's snapshot), the trees of levels
+// >= level are new and take their masses from the next solve.
+static afmm_status afmm_plan_replan_impl(const afmm_plan* old, const afmm_hierarchy* h, int32_t level,
+                                        void* hip_stream, afmm_plan** out) {
+  if (!old || !h || !out) return fail(AFMM_E_INVALID_ARG, "null argument");
+  *out = nullptr;
+  if (old->dead) return fail(AFMM_E_DEVICE, "plan is unusable after an earlier device error");
+  const Topology& To = old->topo;
+  if (To.levelmin.size() != 1) return fail(AFMM_E_INVALID_ARG, "batched plan: no re-plan");
+  const int lmin = To.levelmin[0];
+  if (h->levelmin != lmin) return fail(AFMM_E_INVALID_ARG, "levelmin differs from the old plan's");
+  if (level < lmin + 1 || level > h->levelmax + 1)
+    return fail(AFMM_E_INVALID_ARG, "re-planned level must be in [levelmin + 1, levelmax + 1]");
+  afmm_plan* P = nullptr;
+  afmm_status s = afmm_plan_create_impl(h, &old->opt, hip_stream, &P);
+  if (s) return s;
+  const Topology& Tn = P->topo;
+  bool same = Tn.level_off[0].size() >= (size_t)(level - lmin + 1) &&
+              To.level_off[0].size() >= (size_t)(level - lmin + 1) && Tn.lmax >= level - 1 && To.lmax >= level - 1;
+  for (int l = 0; same && l <= level - 1; ++l)
+    same = Tn.lv[l].rank == To.lv[l].rank && Tn.lv[l].slot == To.lv[l].slot;
+  for (int i = 0; same && i <= level - lmin; ++i) same = Tn.level_off[0][i] == To.level_off[0][i];
+  if (!same) {
+    free_plan(P);
+    delete P;
+    return fail(AFMM_E_INVALID_ARG, "levels below the re-planned level differ from the old plan's");
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (old->snap_valid) {
+    const size_t n = (size_t)Tn.level_off[0][level - lmin];
+    if (n > 0 && (hipMemcpyAsync(P->m_snap, old->m_snap, n * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess ||
+                  hipStreamSynchronize(st) != hipSuccess)) {
+      free_plan(P);
+      delete P;
+      return fail(AFMM_E_DEVICE, "snapshot copy failed");
+    }
+    P->snap_valid = true;
+    P->fresh_from = level;
+  }
+  *out = P;
+  return AFMM_OK;
+}
+
 extern "C" afmm_status afmm_plan_destroy(afmm_plan* P) {
   if (!P) return AFMM_OK;
   free_plan(P);
@@ -1814,9 +1860,10 @@ static afmm_status afmm_solve_impl(afmm_plan* P, int32_t level, int32_t icount, 
   if (level != AFMM_ALL_LEVELS && icount < 1) return fail(AFMM_E_INVALID_ARG, "icount must be >= 1");
   if (P->opt.flags & AFMM_CHECK_INPUT) {
     // the masses this call reads: every level for a full solve, levels >= level
-    // when Alg. 1 rebuilds trees, none otherwise
-    const bool reads = level == AFMM_ALL_LEVELS || level == lmin || icount > 1;
-    const int l0 = level == AFMM_ALL_LEVELS ? lmin : level;
+    // when Alg. 1 rebuilds trees, the re-planned levels after a re-plan, none otherwise
+    const bool alg = level == AFMM_ALL_LEVELS || level == lmin || icount > 1;
+    const bool reads = alg || P->fresh_from <= lmax;
+    const int l0 = level == AFMM_ALL_LEVELS ? lmin : std::min(alg ? level : lmax + 1, P->fresh_from);
     if (reads) {
       afmm_status r;
       hipLaunchKernelGGL(k_flag_clear, dim3(1), dim3(1), 0, st, P->d_flag);
@@ -1837,6 +1884,7 @@ static afmm_status afmm_solve_impl(afmm_plan* P, int32_t level, int32_t icount, 
   }
   if (level == AFMM_ALL_LEVELS) {
     // the snapshot is written by the mass gather of this solve
+    P->fresh_from = 1 << 20;
     P->snap_valid = true;
     P->solved = true;
     P->last_level = AFMM_ALL_LEVELS;
@@ -1848,20 +1896,23 @@ static afmm_status afmm_solve_impl(afmm_plan* P, int32_t level, int32_t icount, 
     P->tree_fresh = r == AFMM_OK;
     return r;
   }
-  // Alg. 1: rebuild trees j >= level iff level == levelmin or icount > 1
-  const bool rebuild = (level == lmin) || (icount > 1);
+  // Alg. 1: rebuild trees j >= level iff level == levelmin or icount > 1; after
+  // a re-plan the trees of the re-planned levels are new and take this call's masses
+  const bool rebuild = (level == lmin) || (icount > 1) || P->fresh_from <= T.lmax;
   if (!P->snap_valid && level != lmin)
     return fail(AFMM_E_ATS_ORDER, "solve(l > levelmin) before any tree was built (call solve(levelmin) first)");
+  const int from = std::min((level == lmin) || (icount > 1) ? level : T.lmax + 1, P->fresh_from);
   if (rebuild) P->snap_valid = true;
+  P->fresh_from = 1 << 20;
   P->solved = true;
   P->last_level = level;
-  P->last_fresh = rebuild ? level : T.lmax + 1;
+  P->last_fresh = rebuild ? from : T.lmax + 1;
   // Alg. 1 without a rebuild leaves every tree as it was: the snapshot, hence
   // the level masses and merged multipoles of the previous solve, still hold
   const bool keep = !rebuild && P->tree_fresh;
   P->tree_fresh = false;
-  const int64_t off = T.level_off[0][level - lmin];
-  afmm_status r = replay_or_run(P, level, rebuild, keep, d_mass, d_phi, d_acc, st, [&](hipStream_t s) -> afmm_status {
+  const int64_t off = rebuild ? T.level_off[0][from - lmin] : 0;
+  afmm_status r = replay_or_run(P, level + 64 * from, rebuild, keep, d_mass, d_phi, d_acc, st, [&](hipStream_t s) -> afmm_status {
     // the rebuilt trees take the masses of levels >= level from this call
     if (rebuild && dev_check(P,
                              hipMemcpyAsync(P->m_snap + off, d_mass + off, (size_t)(T.nslots - off) * sizeof(double),
@@ -2070,6 +2121,7 @@ static afmm_status afmm_plan_autotune_impl(afmm_plan* P, const double* d_mass, d
   if (hipMemcpyAsync(P->m_snap, d_mass, (size_t)T.nslots * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess)
     return dev_check(P, hipGetLastError(), "snapshot");
   P->snap_valid = true;
+  P->fresh_from = 1 << 20;
   P->tree_fresh = true;
   P->solved = true;
   P->last_level = AFMM_ALL_LEVELS;
@@ -2672,6 +2724,11 @@ extern "C" afmm_status afmm_batch_destroy(afmm_batch* B) {
 extern "C" afmm_status afmm_plan_create(const afmm_hierarchy* h, const afmm_options* opt, void* hip_stream,
                                         afmm_plan** out) {
   return guarded([&] { return afmm_plan_create_impl(h, opt, hip_stream, out); });
+}
+
+extern "C" afmm_status afmm_plan_replan(const afmm_plan* old, const afmm_hierarchy* h, int32_t level, void* hip_stream,
+                                        afmm_plan** out) {
+  return guarded([&] { return afmm_plan_replan_impl(old, h, level, hip_stream, out); });
 }
 
 extern "C" afmm_status afmm_solve(afmm_plan* P, int32_t level, int32_t icount, const double* d_mass, double* d_phi,

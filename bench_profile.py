@@ -219,6 +219,16 @@ def cmd_counters(a):
                     r[c[3:].lower() + "/wave_cycles"] = g(k, c) / wc
             if cyc:
                 r["wave_occupancy_index"] = 4.0 * wc / (cyc * a.simds)
+        if g(k, "TA_TA_BUSY_sum") is not None and cyc:
+            r["ta_busy"] = g(k, "TA_TA_BUSY_sum") / (cyc * a.cus)
+            if g(k, "TA_ADDR_STALLED_BY_TC_CYCLES_sum") is not None and g(k, "TA_TA_BUSY_sum"):
+                r["ta_addr_stalled_by_tcp/ta_busy"] = g(k, "TA_ADDR_STALLED_BY_TC_CYCLES_sum") / g(k, "TA_TA_BUSY_sum")
+        if g(k, "TCP_PENDING_STALL_CYCLES_sum") is not None and cyc:
+            r["tcp_pending_stall"] = g(k, "TCP_PENDING_STALL_CYCLES_sum") / (cyc * a.cus)
+        if g(k, "TCP_READ_TAGCONFLICT_STALL_CYCLES_sum") is not None and cyc:
+            r["tcp_tagconflict_stall"] = g(k, "TCP_READ_TAGCONFLICT_STALL_CYCLES_sum") / (cyc * a.cus)
+        if g(k, "TCP_TCC_READ_REQ_LATENCY_sum") is not None and g(k, "TCP_TCC_READ_REQ_sum"):
+            r["l2_read_latency_cycles"] = g(k, "TCP_TCC_READ_REQ_LATENCY_sum") / g(k, "TCP_TCC_READ_REQ_sum")
         if g(k, "SQ_LDS_BANK_CONFLICT") is not None and g(k, "SQ_ACTIVE_INST_LDS"):
             r["lds_bank_conflict/active_lds"] = g(k, "SQ_LDS_BANK_CONFLICT") / g(k, "SQ_ACTIVE_INST_LDS")
         mf = g(k, "SQ_INSTS_MFMA") or g(k, "SQ_INSTS_VALU_MFMA_F32")
@@ -273,6 +283,7 @@ def main():
     c.add_argument("--last", type=int, default=5)
     c.add_argument("--clock-ghz", type=float, default=2.4)
     c.add_argument("--simds", type=int, default=1024)
+    c.add_argument("--cus", type=int, default=256)
     c.add_argument("--title", required=True)
     c.add_argument("--command", required=True, nargs="+")
     c.add_argument("--out", required=True)

@@ -218,7 +218,7 @@ def run_batch(args):
     torch.cuda.synchronize()
     prof = batch.get_profile()
     batch.set_profiling(False)
-    res = {"kernels": prof, "steps": 2}
+    res = {"kernels": prof, "steps": 2, "autotune": tune}
     info = batch.info()
     base = None
     if not args.no_cpu:
@@ -290,13 +290,20 @@ SYMBOLS = {"m2p_f32": "k_m2p<float, {p}>", "m2p_f64": "k_m2p<double, {p}>",
            "near_f32": "k_near<float, {p}>", "near_f64": "k_near<double, {p}>", "upward": "k_upward<{p}>"}
 
 
-def measured_traffic(family, p, workload):
+def m2p_kernel_symbol(family, p, shape):
+    """rocprofv3's name of the M2P kernel that the tuned tile shape launches."""
+    if family == "m2p_f32" and shape:
+        return f"k_m2p_s<float, {p}, {shape}>"
+    return SYMBOLS.get(family, "").format(p=p)
+
+
+def measured_traffic(family, p, workload, shape=0):
     """HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE summary of this
     kernel and workload, or None (none taken, or the kernels changed since)."""
     import glob
     sys.path.insert(0, ROOT)
     from bench_profile import source_hash
-    want = SYMBOLS.get(family, "").format(p=p)
+    want = m2p_kernel_symbol(family, p, shape)
     for f in glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json")):
         try:
             t = json.load(open(f))
@@ -312,8 +319,10 @@ def roofline(res, precision, p=None, workload=None):
     prof = res["kernels"]
     name, k = max(prof.items(), key=lambda kv: kv[1]["ms"])
     total_ms = sum(v["ms"] for v in prof.values())
-    traffic, tsrc = measured_traffic(name, p, workload) if p is not None else (None, None)
-    common = {"kernel": KERNEL_NAMES.get(name, name), "family": name, "launches": k["launches"],
+    shape = ((res.get("autotune") or {}).get("m2p_shape") or [0, 0])[1]
+    traffic, tsrc = measured_traffic(name, p, workload, shape) if p is not None else (None, None)
+    kname = f"k_m2p_s<float, P, {shape}>" if name == "m2p_f32" and shape else KERNEL_NAMES.get(name, name)
+    common = {"kernel": kname, "family": name, "launches": k["launches"],
               "traffic_source": tsrc,
               "avg_launch_ms": k["ms"] / max(k["launches"], 1),
               "flops_per_launch": k["flops"] / max(k["launches"], 1),

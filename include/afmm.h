@@ -97,6 +97,15 @@ typedef struct afmm_options {
                                 fixed order; 0 = automatic (enough blocks to fill the GPU), else
                                 1..21.  Results depend on it only through FP rounding order. */
   size_t max_device_bytes;   /* cap on the plan's device memory; 0 = no cap */
+  int32_t m2p_shape;         /* tile shape of the FP32 intermediate-field (M2P) launch: 0 = one
+                                16-group tile per wave with each lane loading its own B
+                                fragments (default), 1 = the same tile with the source rows
+                                loaded row by row and staged through LDS, 2 = as 1 with two
+                                16-group tiles of one parity class per wave (p <= 5).  FP64
+                                launches always use shape 0; a shape the order does not support
+                                falls back to 0.  The autotuner chooses it by timing.  Results
+                                depend on it only through FP rounding order (none: every shape
+                                sums in the same order). */
 } afmm_options;
 
 /* Defaults: p = 4, FP64, G = 1, boxlen = 1, no flags, fp64_levels = 3, tap_split = 0 (automatic),
@@ -242,7 +251,8 @@ afmm_status afmm_solve_adjoint_noalloc(afmm_plan* plan, int32_t level, const dou
  *   plans[i]       plans built by afmm_plan_create (one hierarchy each); all must
  *                  share p, precision, G, boxlen, fp64_levels, tap_split and the
  *                  AFMM_PAPER_QUAD_CAP / AFMM_SELF_POTENTIAL flags (the batch solves
- *                  with them; the scheduling flags of the members are ignored).  The
+ *                  with them; the scheduling flags of the members are ignored, the M2P
+ *                  tile shape is that of plans[0]).  The
  *                  batch copies their topology: they may be destroyed afterwards.
  *   hip_stream     orders the uploads and the graph capture.
  * afmm_batch_solve: d_mass[i], d_phi[i], d_acc[i] are device pointers laid out as
@@ -295,7 +305,9 @@ afmm_status afmm_batch_get_profile(afmm_batch* batch, afmm_stage_time* out, int3
  * parallelism against partial-sum traffic and per-block setup; the best value
  * depends on the hierarchy's shape.  afmm_plan_autotune times candidate splits
  * (per-launch events, serial launches) on full solves of the caller's data and
- * keeps, per precision, the fastest M2L split and the fastest M2P split; it
+ * keeps, per precision, the fastest M2L split and the fastest M2P (tile shape,
+ * split) pair (the shapes of afmm_options.m2p_shape that the order and
+ * precision support); it
  * leaves phi/acc holding a full solve and counts as one (AFMM_ALL_LEVELS).
  * afmm_batch_autotune does the same on a batch and re-captures its graph.
  * Results of later solves change only through FP rounding order.  Takes a few
@@ -307,6 +319,7 @@ typedef struct afmm_tune_result {
   double ms_before;       /* summed launch time of one solve before / after */
   double ms_after;
   int32_t candidates;     /* candidate configurations timed */
+  int32_t m2p_shape[2];   /* chosen M2P tile shapes (see afmm_options.m2p_shape) */
 } afmm_tune_result;
 afmm_status afmm_plan_autotune(afmm_plan* plan, const double* d_mass, double* d_phi, double* d_acc,
                                void* hip_stream, afmm_tune_result* out);

@@ -42,7 +42,7 @@ SYMBOLS = [
 class Options(C.Structure):
     _fields_ = [("p", C.c_int32), ("precision", C.c_int32), ("G", C.c_double), ("boxlen", C.c_double),
                 ("flags", C.c_uint32), ("fp64_levels", C.c_int32), ("tap_split", C.c_int32),
-                ("max_device_bytes", C.c_size_t)]
+                ("max_device_bytes", C.c_size_t), ("m2p_shape", C.c_int32)]
 
 
 class HierarchyC(C.Structure):
@@ -75,11 +75,12 @@ class StageTime(C.Structure):
 
 class TuneResult(C.Structure):
     _fields_ = [("m2l_split", C.c_int32 * 2), ("m2p_split", C.c_int32 * 2), ("ms_before", C.c_double),
-                ("ms_after", C.c_double), ("candidates", C.c_int32)]
+                ("ms_after", C.c_double), ("candidates", C.c_int32), ("m2p_shape", C.c_int32 * 2)]
 
     def as_dict(self):
         return {"m2l_split": list(self.m2l_split), "m2p_split": list(self.m2p_split),
-                "ms_before": self.ms_before, "ms_after": self.ms_after, "candidates": self.candidates}
+                "m2p_shape": list(self.m2p_shape), "ms_before": self.ms_before, "ms_after": self.ms_after,
+                "candidates": self.candidates}
 
 
 class AfmmError(RuntimeError):

@@ -826,6 +826,9 @@ struct afmm_plan {
   // MFMA tile records of every level, one array per precision (0 FP64, 1 FP32);
   // range[l] = {precision, first tile, count}
   MfmaTiles m2p_all[2], m2l_all[2];
+  MfmaTiles m2p_all2[2];            // M2P tiles of 32 groups (tile shape 2), same level ranges as below
+  int m2p_range2[kMaxLevel][3] = {};
+  int m2p_shape[2] = {0, 0};        // M2P tile shape per precision (afmm_options.m2p_shape)
   // Level solves (ATS, Alg. 2): the M2L / L2L work restricted to the FMM cells
   // that are ancestors of the leaves of target level l (per target level l)
   struct AtsChain {
@@ -1002,6 +1005,7 @@ afmm_status check_options(const afmm_options* o) {
   if (!(o->boxlen > 0) || !std::isfinite(o->boxlen)) return fail(AFMM_E_INVALID_ARG, "boxlen must be > 0");
   if (!std::isfinite(o->G)) return fail(AFMM_E_INVALID_ARG, "G must be finite");
   if (o->tap_split < 0 || o->tap_split > 21) return fail(AFMM_E_UNSUPPORTED, "tap_split must be in 0..21");
+  if (o->m2p_shape < 0 || o->m2p_shape > 2) return fail(AFMM_E_UNSUPPORTED, "m2p_shape must be in 0..2");
   return AFMM_OK;
 }
 
@@ -1058,6 +1062,7 @@ void afmm_options_default(afmm_options* o) {
   o->fp64_levels = 3;
   o->tap_split = 0;
   o->max_device_bytes = 0;
+  o->m2p_shape = 0;
 }
 
 const char* afmm_status_string(afmm_status s) {
@@ -1418,8 +1423,10 @@ static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
   // parity-class tiles of the MFMA kernels (all levels of one precision in one
   // array) and the intermediate-field partials
   {
-    std::vector<int32_t> m2p_rec[2], m2l_rec[2];
+    std::vector<int32_t> m2p_rec[2], m2l_rec[2], m2p_rec2[2];
     int m2p_nc[2] = {m2p_columns(P->opt.p, false), m2p_columns(P->opt.p, true)};
+    // 32-group tiles for tile shape 2, where the order and precision allow it
+    const bool two[2] = {m2p_shape_ok(P->opt.p, false, 2), m2p_shape_ok(P->opt.p, true, 2)};
     for (int l = 3; l <= T.lmax; ++l) {
       const int pr = (mixed && (l - 1) > f64) ? 1 : 0;
       const int n0 = (int)(m2p_rec[pr].size() / (m2p_nc[pr] + 1));
@@ -1427,6 +1434,13 @@ static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
       P->m2p_range[l][0] = pr;
       P->m2p_range[l][1] = n0;
       P->m2p_range[l][2] = n;
+      if (two[pr]) {
+        const int c = m2p_shape_columns(2);
+        const int q0 = (int)(m2p_rec2[pr].size() / (c + 1));
+        P->m2p_range2[l][0] = pr;
+        P->m2p_range2[l][1] = q0;
+        P->m2p_range2[l][2] = append_tiles(T, l, T.leafgrp[l], c, m2p_rec2[pr]);
+      }
       const int pm = (mixed && l > f64) ? 1 : 0;
       if (l <= T.lmax - 1) {
         const int m0 = (int)(m2l_rec[pm].size() / 17);
@@ -1462,6 +1476,12 @@ static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
       int32_t* d = nullptr;
       if ((s = upload(P, m2p_rec[pr], &d, st))) return s;
       P->m2p_all[pr] = {d, (int)(m2p_rec[pr].size() / (m2p_nc[pr] + 1)), m2p_nc[pr]};
+      if (two[pr] && !m2p_rec2[pr].empty()) {
+        if ((s = upload(P, m2p_rec2[pr], &d, st))) return s;
+        const int c = m2p_shape_columns(2);
+        P->m2p_all2[pr] = {d, (int)(m2p_rec2[pr].size() / (c + 1)), c};
+      }
+      P->m2p_shape[pr] = m2p_shape_ok(P->opt.p, pr == 1, P->opt.m2p_shape) ? P->opt.m2p_shape : 0;
       if ((s = upload(P, m2l_rec[pr], &d, st))) return s;
       P->m2l_all[pr] = {d, (int)(m2l_rec[pr].size() / 17), 16};
     }
@@ -1715,15 +1735,18 @@ static afmm_status run_solve(afmm_plan* P, const double* msrc, int fmax, int lo,
     return s;
   // intermediate field (M2P) of the leaf levels lo..hi: one launch per precision
   for (int pr = 0; pr < 2; ++pr) {
+    const int shape = P->m2p_shape[pr];
+    const int(*range)[3] = shape == 2 ? P->m2p_range2 : P->m2p_range;
     int t0 = -1, n = 0;
     for (int l = std::max(lo, 3); l <= hi; ++l)
-      if (P->m2p_range[l][0] == pr && P->m2p_range[l][2] > 0) {
-        if (t0 < 0) t0 = P->m2p_range[l][1];
-        n = P->m2p_range[l][1] + P->m2p_range[l][2] - t0;
+      if (P->m2p_range[l][0] == pr && range[l][2] > 0) {
+        if (t0 < 0) t0 = range[l][1];
+        n = range[l][1] + range[l][2] - t0;
       }
     if (n <= 0) continue;
     hipEvent_t a = prof_begin(P, sm);
-    if ((s = dev_check(P, launch_m2p(p, pr == 1, P->m2p_all[pr], t0, n, P->m2p_split[pr], P->mt, P->d_lvs, P->t32, P->t64, sm), "m2p")))
+    if ((s = dev_check(P, launch_m2p(p, pr == 1, shape == 2 ? P->m2p_all2[pr] : P->m2p_all[pr], t0, n,
+                                     P->m2p_split[pr], shape, P->mt, P->d_lvs, P->t32, P->t64, sm), "m2p")))
       return s;
     for (int l = std::max(lo, 3); l <= hi; ++l)
       if (P->m2p_range[l][0] == pr) {
@@ -2080,9 +2103,16 @@ afmm_status autotune_core(afmm_plan* P, SolveFn solve, hipStream_t st, afmm_tune
   for (int pr = 1; pr >= 0; --pr) {
     if (P->m2p_all[pr].ntiles == 0) continue;
     double best = 1e300;
-    int arg = P->m2p_split[pr];
-    for (int c : cand_m2p)
-      if ((s = trial(P->m2p_split, pr, c, best, arg, pr ? kM2P32 : kM2P64, pr ? kLeaf32 : kLeaf64))) return s;
+    int arg = P->m2p_split[pr], arg_shape = P->m2p_shape[pr];
+    for (int shape = 0; shape <= 2; ++shape) {
+      if (!m2p_shape_ok(P->opt.p, pr == 1, shape) || (shape == 2 && P->m2p_all2[pr].ntiles == 0)) continue;
+      P->m2p_shape[pr] = shape;
+      const double before_shape = best;
+      for (int c : cand_m2p)
+        if ((s = trial(P->m2p_split, pr, c, best, arg, pr ? kM2P32 : kM2P64, pr ? kLeaf32 : kLeaf64))) return s;
+      if (best < before_shape) arg_shape = shape;
+    }
+    P->m2p_shape[pr] = arg_shape;
     P->m2p_split[pr] = arg;
   }
   // the chosen splits were timed, so they fitted then; a refusal now leaves
@@ -2096,6 +2126,7 @@ afmm_status autotune_core(afmm_plan* P, SolveFn solve, hipStream_t st, afmm_tune
     for (int pr = 0; pr < 2; ++pr) {
       out->m2l_split[pr] = P->m2l_split[pr];
       out->m2p_split[pr] = P->m2p_split[pr];
+      out->m2p_shape[pr] = P->m2p_shape[pr];
     }
     out->ms_before = before;
     out->ms_after = after;

@@ -217,6 +217,8 @@ hipError_t launch_adj_out(int p, const LevelDev& lv1, const LevelDev& lv0, int h
 hipError_t launch_upward(int p, const int32_t* leaf, int nleaf, const int32_t* mix, int nmix, const LevelDev& lv,
                          const LevelDev& lvc, const CommonDev& cm, hipStream_t st);
 int m2p_columns(int p, bool fp32);
+bool m2p_shape_ok(int p, bool fp32, int shape);
+int m2p_shape_columns(int shape);
 // MFMA launches over a contiguous range [t0, t0 + n) of tile records; each
 // record is (target level, NC groups).  lvs is the device array of LevelDev.
 hipError_t launch_m2l_taps(int p, bool fp32, const MfmaTiles& mt, int t0, int n, int nsplit, const MfmaTables& tabs,
@@ -225,9 +227,9 @@ hipError_t launch_m2l_taps(int p, bool fp32, const MfmaTiles& mt, int t0, int n,
 hipError_t launch_l2l(int p, bool fp32, bool parent_fp32, bool has_parent, int nsplit, const int32_t* grp, int ngrp,
                       const LevelDev& lv1, const LevelDev& lv0, const TablesDev<float>& t32,
                       const TablesDev<double>& t64, const CommonDev& cm, hipStream_t st);
-hipError_t launch_m2p(int p, bool fp32, const MfmaTiles& mt, int t0, int n, int nsplit, const MfmaTables& tabs,
-                      const LevelDev* lvs, const TablesDev<float>& t32, const TablesDev<double>& t64,
-                      hipStream_t st);
+hipError_t launch_m2p(int p, bool fp32, const MfmaTiles& mt, int t0, int n, int nsplit, int shape,
+                      const MfmaTables& tabs, const LevelDev* lvs, const TablesDev<float>& t32,
+                      const TablesDev<double>& t64, hipStream_t st);
 // cself: the self-potential constant (AFMM_SELF_POTENTIAL), 0 when off.
 hipError_t launch_near(int p, bool fp32, int l, const int32_t* grp, int ngrp, const LevelDev& lv1,
                        const LevelDev& lv0, const LevelDev& lvp, const TablesDev<float>& t32,

@@ -693,6 +693,228 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, m2p_max_w
   }
 }
 
+// M2P with the source rows staged through LDS, for NT 16-column tiles per wave
+// (tile shapes 1 and 2 of the launcher; the kernel above is shape 0).  In the
+// direct form each lane's B fragments come from one of 16 source rows, so a
+// 16-byte load of the wave touches 64 cache lines and the texture addresser
+// and L1 tag lookups bound the kernel when a tap carries few MFMAs (low p).
+// Here consecutive lanes load consecutive 16-byte pieces of a row (piece
+// v = 64 j + lane is piece v % NVR of row v / NVR of the tap's 16 NT rows),
+// two taps ahead; halfway through a tap's MFMAs the rows of the next tap go
+// to an LDS row stage (padded by one vector per row: conflict-free fragment
+// reads) and come back as MFMA fragments.  With NT = 2 one wave runs two
+// tiles of the same parity class: each A fragment read from LDS feeds two
+// MFMAs and one D~ stage serves 32 groups.  The block is one wave, whose LDS
+// accesses complete in issue order, so the stages need no barrier.  The
+// sources are resolved in chunks of CH taps; the code and sources of a tap
+// are read from LDS one step before the loads that use them.
+template <int NT>
+constexpr int m2p_chunk() { return NT == 1 ? 64 : 32; }
+
+template <typename T, int P, int NT>
+__global__ __launch_bounds__(64) void k_m2p_s(const int32_t* __restrict__ tiles, int ntiles, int nsplit,
+                                              const int32_t* __restrict__ taps, const int16_t* __restrict__ aoff,
+                                              const LevelDev* __restrict__ lvs, const T* __restrict__ Dst) {
+  using TS = TapStage<T, P>;
+  using V = typename Vec16<T>::type;
+  constexpr int K1 = nmi(P - 1);
+  constexpr int ST0 = TS::KP / 4, ST1 = ((K1 + 3) & ~3) / 4;
+  constexpr int NV = (ST0 + TS::VW - 1) / TS::VW;  // B vectors per lane and tile (MFMA layout)
+  constexpr int ND = (TS::NDV + 63) / 64;
+  constexpr int NC = 16 * NT;                      // groups (columns) of the block
+  constexpr int NVR = TS::ROW / TS::VW;             // 16-byte pieces of a source row
+  constexpr int RP = TS::ROW + TS::VW;              // LDS row stride
+  constexpr int NG = (NC * NVR + 63) / 64;          // row pieces per lane and tap
+  constexpr int CH = m2p_chunk<NT>();
+  constexpr int KMID = ST0 / 2;
+  static_assert(4 * NV <= NVR, "fragments inside the row");
+  __shared__ __align__(16) T sD[2][TS::SDP];
+  __shared__ __align__(16) T sB[NC * RP];
+  __shared__ int sF[NC];
+  __shared__ int sCB[NC * 27];
+  __shared__ int sCode[kTaps];
+  __shared__ int sSrc[CH * NC];
+  const int item = xcd_tile(ntiles * nsplit);
+  if (item >= ntiles * nsplit) return;
+  const int tile = item / nsplit, chunk = item - tile * nsplit;
+  int tb, te;
+  tap_range(chunk, nsplit, tb, te);
+  const int lane = threadIdx.x;
+  const int n = lane & 15, g = lane >> 4;
+  const int32_t* rec = tiles + (size_t)tile * (NC + 1);
+  const int l = rec[0];
+  const LevelDev lv1 = lvs[l - 1];
+  const LevelDev lv2 = lvs[l - 2];
+  gptr<int32_t> rank1 = as_global(lv1.rank);
+  gptr<double> mass1 = as_global(lv1.mass);
+  gptr<T> S1 = as_global(level_S<T>(lv1));
+  gmut<T> part = as_global_mut((T*)lv1.part) + (size_t)chunk * lv1.nref * 32;
+  if (lane < NC) sF[lane] = rec[1 + lane];
+  __syncthreads();
+  gptr<int32_t> refcell1 = as_global(lv1.refcell);
+  gptr<int32_t> nbr2 = as_global(lv2.nbr);
+  gptr<int32_t> rank2 = as_global(lv2.rank);
+  for (int i = lane; i < NC * 27; i += 64) {
+    const int c = i / 27, e = i - c * 27;
+    const int F = sF[c];
+    int v = -1;
+    if (F >= 0) {
+      const int Q = nbr2[(size_t)(refcell1[F] >> 3) * 27 + e];
+      if (Q >= 0) {
+        const int rQ = rank2[Q];
+        if (rQ >= 0) v = 8 * rQ;
+      }
+    }
+    sCB[i] = v;
+  }
+  const int oF = refcell1[sF[0]] & 7;
+  const int32_t* tpg = taps + oF * kTaps + tb;
+  const int nt = te - tb;
+  for (int i = lane; i < nt; i += 64) sCode[i] = tpg[i];
+  int off0[ST0], off1[ST1];
+#pragma unroll
+  for (int kb = 0; kb < ST0; ++kb) off0[kb] = aoff[kb * 64 + lane];
+#pragma unroll
+  for (int kb = 0; kb < ST1; ++kb) off1[kb] = aoff[(ST0 + kb) * 64 + lane];
+  const int zrow = lv1.nref;
+  // the row (0 .. NC-1) and piece of each of this lane's row pieces; pieces
+  // past the last row re-read the last piece and are not stored
+  int prow[NG], pchk[NG];
+#pragma unroll
+  for (int j = 0; j < NG; ++j) {
+    const int v = min(64 * j + lane, NC * NVR - 1);
+    prow[j] = v / NVR;
+    pchk[j] = v - prow[j] * NVR;
+  }
+  typename Acc4<T>::type acc0[NT], acc1[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc0[t] = acc1[t] = {0, 0, 0, 0};
+  // fragments (per tile) of the current and the next tap, row pieces of the
+  // next two taps, and each tile's column source and mass for the monopole slot
+  V bA[NT][NV], bB[NT][NV];
+  V gX[NG], gY[NG];
+  V vD[ND];
+  double vmA[NT], vmB[NT], vmX[NT], vmY[NT];
+  int srA[NT], srB[NT], srX[NT], srY[NT];
+  int cN = 0, sN[NT], rN[NG];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) vmA[t] = vmB[t] = vmX[t] = vmY[t] = 0, srA[t] = srB[t] = srX[t] = srY[t] = sN[t] = -1;
+  auto load_rows = [&](const int* rs, V* gb) {
+#pragma unroll
+    for (int j = 0; j < NG; ++j) {
+      const int row = rs[j] >= 0 ? rs[j] : zrow;
+      gb[j] = *(gptr<V>)(S1 + (size_t)row * TS::ROW + pchk[j] * TS::VW);
+    }
+  };
+  auto store_rows = [&](const V* gb) {
+#pragma unroll
+    for (int j = 0; j < NG; ++j)
+      if (64 * j + lane < NC * NVR) *(V*)(sB + prow[j] * RP + pchk[j] * TS::VW) = gb[j];
+  };
+  auto read_frags = [&](V (*b)[NV]) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int j = 0; j < NV; ++j) b[t][j] = *(const V*)(sB + (16 * t + n) * RP + (4 * j + g) * TS::VW);
+  };
+  // the mass of a leaf source for lane group 0 (the only lanes that use it)
+  auto load_mass = [&](const int* sr, double* vm) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      double v = 0;
+      if (g == 0 && sr[t] <= -2) v = mass1[-2 - sr[t]];
+      vm[t] = v;
+    }
+  };
+  // sources of chunk tap k (none past the chunk): columns of this lane, rows of its pieces
+  auto read_srcs = [&](int k, int cn) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) sN[t] = k < cn ? sSrc[k * NC + 16 * t + n] : -1;
+#pragma unroll
+    for (int j = 0; j < NG; ++j) rN[j] = k < cn ? sSrc[k * NC + prow[j]] : -1;
+  };
+  for (int c0 = 0; c0 < nt; c0 += CH) {
+    const int cn = min(CH, nt - c0);
+    __syncthreads();
+    for (int i = lane; i < cn * NC; i += 64) sSrc[i] = tap_src(sCode[c0 + i / NC], i % NC, sCB, rank1);
+    __syncthreads();
+    {
+      // tap 0 into the stages and bA; tap 1's rows in flight (set X); tap 2's sources read
+      read_srcs(0, cn);
+      load_rows(rN, gY);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) srA[t] = sN[t];
+      load_mass(srA, vmA);
+      load_dstage<T, P, 64>(sCode[c0], Dst, vD);
+      store_dstage<T, P, 64>(sD[0], vD);
+      store_rows(gY);
+      read_frags(bA);
+      read_srcs(1, cn);
+      load_rows(rN, gX);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) srX[t] = sN[t];
+      load_mass(srX, vmX);
+      cN = sCode[c0 + (cn > 1 ? 1 : 0)];
+      read_srcs(2, cn);
+    }
+    __builtin_amdgcn_wave_barrier();
+    // step k: rows of tap k + 2 into gn (sources read one step ago) and the D~
+    // stage of tap k + 1 into vD; the MFMAs of tap k, halfway through them the
+    // rows of tap k + 1 (gc) through the LDS row stage into bn; then the D~
+    // stage of tap k + 1 into LDS.  Taps run in pairs; an odd chunk ends with
+    // one empty tap (zero rows; its D~ stage repeats the last tap's rows).
+    auto step = [&](int k, int b, V (*bc)[NV], const int* srcc, const double* vmc, V (*bn)[NV], int* srn,
+                    double* vmn, const V* gc, const int* src1, const double* vm1, V* gn, int* sr2, double* vm2) {
+      load_dstage<T, P, 64>(cN, Dst, vD);
+      load_rows(rN, gn);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) sr2[t] = sN[t];
+      load_mass(sr2, vm2);
+      cN = sCode[c0 + (k + 2 < cn ? k + 2 : cn - 1)];
+      read_srcs(k + 3, cn);
+      __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the MFMAs
+      const T* D = sD[b];
+#pragma unroll
+      for (int kb = 0; kb < ST0; ++kb) {
+        const T a0 = D[off0[kb]];
+        const T a1 = kb < ST1 ? D[off1[kb]] : (T)0;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const T bv = kb == 0 ? bfrag_m0<T>(srcc[t], vmc[t], bc[t][0][0]) : bc[t][kb / TS::VW][kb % TS::VW];
+          acc0[t] = mfma16(a0, bv, acc0[t]);
+          if (kb < ST1) acc1[t] = mfma16(a1, bv, acc1[t]);
+        }
+        if (kb == KMID) {
+          store_rows(gc);
+          read_frags(bn);
+#pragma unroll
+          for (int t = 0; t < NT; ++t) srn[t] = src1[t], vmn[t] = vm1[t];
+        }
+      }
+      store_dstage<T, P, 64>(sD[b ^ 1], vD);
+      __builtin_amdgcn_wave_barrier();
+    };
+    const int cn2 = (cn + 1) & ~1;
+    for (int k = 0; k < cn2; k += 2) {
+      step(k, 0, bA, srA, vmA, bB, srB, vmB, gX, srX, vmX, gY, srY, vmY);
+      step(k + 1, 1, bB, srB, vmB, bA, srA, vmA, gY, srY, vmY, gX, srX, vmX);
+    }
+  }
+  const int krow = lane >> 4;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int F = sF[16 * t + n];
+    if (F < 0) continue;
+    gmut<T> out = part + (size_t)F * 32;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = acc_row<T>(krow, r);
+      out[i] = i < 8 ? acc0[t][r] : -acc0[t][r];
+      out[16 + i] = -acc1[t][r];
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // M2L tap sums at the FMM levels (Alg. 3 without the ShiftLocal term, which
 // the L2L chain adds afterwards): rows R = 8 b + o (local coefficient b, child
@@ -1211,10 +1433,29 @@ __global__ __launch_bounds__(kBlock) void k_near_m2p(const int32_t* __restrict__
 
 template <typename T>
 static hipError_t m2p_dispatch(int p, const MfmaTiles& mt, int t0, int n, int nsplit, const MfmaTables& tabs,
-                               const LevelDev* lvs, const T* Dst, hipStream_t st) {
+                               const LevelDev* lvs, const T* Dst, int shape, hipStream_t st) {
   const int items = n * nsplit;
   const dim3 grid(8 * ((items + 7) / 8)), block(64);
-  const int32_t* tl = mt.tiles + (size_t)t0 * 17;
+  const int32_t* tl = mt.tiles + (size_t)t0 * (mt.nc + 1);
+  if (shape != 0) {
+    if (!m2p_shape_ok(p, sizeof(T) == 4, shape) || mt.nc != m2p_shape_columns(shape)) return hipErrorInvalidValue;
+    if constexpr (sizeof(T) == 4) {
+      switch (p * 4 + shape) {
+#define AFMM_M2PS(PP, SH)                                                                                      \
+  case PP * 4 + SH:                                                                                           \
+    hipLaunchKernelGGL((k_m2p_s<T, PP, SH>), grid, block, 0, st, tl, n, nsplit, tabs.taps, tabs.m2p_off, lvs, Dst); \
+    break;
+        AFMM_M2PS(1, 1) AFMM_M2PS(2, 1) AFMM_M2PS(3, 1) AFMM_M2PS(4, 1) AFMM_M2PS(5, 1) AFMM_M2PS(6, 1)
+        AFMM_M2PS(7, 1) AFMM_M2PS(8, 1) AFMM_M2PS(1, 2) AFMM_M2PS(2, 2) AFMM_M2PS(3, 2) AFMM_M2PS(4, 2)
+        AFMM_M2PS(5, 2)
+#undef AFMM_M2PS
+        default: return hipErrorInvalidValue;
+      }
+      return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+  }
+  if (mt.nc != 16) return hipErrorInvalidValue;
   // LDS source table of k_m2p: the longest tap range of the split, except
   // for FP32 from p = 6 on, where the table keeps all 189 taps so that the
   // block's LDS (about 20 KB) holds the kernel at 2 waves per SIMD.  Measured:
@@ -1241,12 +1482,12 @@ static hipError_t m2p_dispatch(int p, const MfmaTiles& mt, int t0, int n, int ns
   return hipGetLastError();
 }
 
-hipError_t launch_m2p(int p, bool fp32, const MfmaTiles& mt, int t0, int n, int nsplit, const MfmaTables& tabs,
-                      const LevelDev* lvs, const TablesDev<float>& t32, const TablesDev<double>& t64,
-                      hipStream_t st) {
+hipError_t launch_m2p(int p, bool fp32, const MfmaTiles& mt, int t0, int n, int nsplit, int shape,
+                      const MfmaTables& tabs, const LevelDev* lvs, const TablesDev<float>& t32,
+                      const TablesDev<double>& t64, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  if (fp32) return m2p_dispatch<float>(p, mt, t0, n, nsplit, tabs, lvs, t32.Dstage, st);
-  return m2p_dispatch<double>(p, mt, t0, n, nsplit, tabs, lvs, t64.Dstage, st);
+  if (fp32) return m2p_dispatch<float>(p, mt, t0, n, nsplit, tabs, lvs, t32.Dstage, shape, st);
+  return m2p_dispatch<double>(p, mt, t0, n, nsplit, tabs, lvs, t64.Dstage, shape, st);
 }
 
 int m2p_columns(int p, bool fp32) {
@@ -1254,6 +1495,17 @@ int m2p_columns(int p, bool fp32) {
   (void)fp32;
   return 16;
 }
+
+// Tile shapes of the M2P launch: 0 the direct form (16 groups per wave), 1 the
+// row-staged form (16 groups), 2 the row-staged form with two tiles of one
+// parity class per wave (32 groups; up to p = 5, where its registers fit).
+// The staged forms are instantiated for the FP32 kernels only.
+bool m2p_shape_ok(int p, bool fp32, int shape) {
+  if (shape == 0) return true;
+  if (!fp32) return false;
+  return shape == 1 || (shape == 2 && p <= 5);
+}
+int m2p_shape_columns(int shape) { return shape == 2 ? 32 : 16; }
 
 template <typename T>
 static hipError_t m2l_dispatch(int p, const MfmaTiles& mt, int t0, int n, int nsplit, const MfmaTables& tabs,

@@ -6,9 +6,10 @@
 
 #include <algorithm>
 #include <cmath>
-#include <mutex>
 #include <cstdio>
 #include <cstring>
+#include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -288,7 +289,28 @@ struct WorkCounts {
   double flops_m2l = 0, flops_m2p = 0, flops_p2p = 0, flops_updown = 0;
 };
 
+// Geometry of the pair counts, as bit masks over child octants: far[oF][e]
+// has bit op when child op of the grandfather's neighbour e is in the
+// interaction list of a father with octant oF (not touching it); adj[e][op]
+// has bit o when child op of the father's neighbour e touches target child o,
+// self[e][op] when it is that child.
+struct PairMasks {
+  uint8_t far[8][27] = {}, adj[27][8] = {}, self[27][8] = {};
+  PairMasks() {
+    for (int e = 0; e < 27; ++e)
+      for (int op = 0; op < 8; ++op)
+        for (int o = 0; o < 8; ++o) {
+          int dm = 0;
+          for (int d = 0; d < 3; ++d) dm = std::max(dm, std::abs(2 * ax_of(e, d) + ((op >> d) & 1) - ((o >> d) & 1)));
+          if (dm > 1) far[o][e] |= (uint8_t)(1u << op);
+          if (dm <= 1) adj[e][op] |= (uint8_t)(1u << o);
+          if (dm == 0) self[e][op] |= (uint8_t)(1u << o);
+        }
+  }
+};
+
 static void count_work(const Topology& T, int p, bool mixed, int f64, WorkCounts& W) {
+  static const PairMasks PM;
   const int K = nmi(p), K1 = nmi(p - 1);
   const double tri = (double)binom(p + 6, 6);
   const double fm2p = 2.0 * (K + 3.0 * K1), fp2p = 23.0, fl2p = 2.0 * (K + 3.0 * K1);
@@ -296,21 +318,22 @@ static void count_work(const Topology& T, int p, bool mixed, int f64, WorkCounts
   for (int a = 0; a <= p; ++a)
     for (int b = 0; a + b <= p; ++b)
       for (int c = 0; a + b + c <= p; ++c) m2m_terms += (a + 1) * (b + 1) * (c + 1);
-  auto il_sources = [&](int l, int32_t F, std::vector<int32_t>& out) {
-    out.clear();
+  // interaction-list sources of group F (refined rank at level l-1): how many
+  // are refined (multipole sources) and how many are leaves
+  auto il_count = [&](int l, int32_t F, int64_t& refined, int64_t& leaf) {
+    refined = leaf = 0;
     if (l < 2) return;
     const HostLevel& L1 = T.lv[l - 1];
     const HostLevel& L2 = T.lv[l - 2];
     const int32_t cF = L1.refcell[F];
     const int32_t G = cF >> 3, oF = cF & 7;
-    for (int t = 0; t < 216; ++t) {
-      const int e = t >> 3, op = t & 7;
+    for (int e = 0; e < 27; ++e) {
       const int32_t Q = L2.nbr[(size_t)G * 27 + e];
       if (Q < 0) continue;
-      int dm = 0;
-      for (int d = 0; d < 3; ++d) dm = std::max(dm, std::abs(2 * ax_of(e, d) + ((op >> d) & 1) - ((oF >> d) & 1)));
-      if (dm <= 1) continue;
-      out.push_back(8 * L2.rank[Q] + op);
+      const uint8_t m = PM.far[oF][e];
+      const int32_t base = 8 * L2.rank[Q];
+      for (int op = 0; op < 8; ++op)
+        if (m >> op & 1) ++(L1.rank[base + op] >= 0 ? refined : leaf);
     }
   };
   // upward: one M2M (or P2M) per child of every refined cell at levels >= 2
@@ -321,7 +344,6 @@ static void count_work(const Topology& T, int p, bool mixed, int f64, WorkCounts
                     T.lv[f + 1].n() * (8.0 + 4.0);
     W.flops_updown += W.up_flops[f];
   }
-  std::vector<int32_t> src;
   for (int f = 3; f <= T.lmax; ++f) {
     const HostLevel& L1 = T.lv[f - 1];
     const HostLevel& L0 = T.lv[f];
@@ -330,12 +352,11 @@ static void count_work(const Topology& T, int p, bool mixed, int f64, WorkCounts
     for (int32_t F : T.m2lgrp[f]) {
       int nt = 0;
       for (int o = 0; o < 8; ++o) nt += L0.rank[8 * F + o] >= 0;
-      il_sources(f, F, src);
+      int64_t nr, nl;
+      il_count(f, F, nr, nl);
       nt_all += nt;
-      for (int32_t s : src) {
-        if (L1.rank[s] >= 0) pairs += nt;
-        else mono += nt;
-      }
+      pairs += nr * nt;
+      mono += nl * nt;
     }
     const double ng = (double)T.m2lgrp[f].size();
     W.m2l_targets += nt_all;
@@ -355,42 +376,33 @@ static void count_work(const Topology& T, int p, bool mixed, int f64, WorkCounts
     const double cs = (mixed && (l - 1) > f64) ? 4.0 : 8.0;
     int64_t m2p = 0, p2p = 0, p2p_il = 0, nm2p = 0, nst = 0, leaves = 0;
     for (int32_t F : T.leafgrp[l]) {
-      int nt = 0;
-      bool tgt[8];
-      for (int o = 0; o < 8; ++o) nt += (tgt[o] = L0.rank[8 * F + o] < 0);
+      unsigned tgt = 0;  // leaf children of F: the targets
+      for (int o = 0; o < 8; ++o) tgt |= (L0.rank[8 * F + o] < 0 ? 1u : 0u) << o;
+      const int nt = __builtin_popcount(tgt);
       leaves += nt;
-      il_sources(l, F, src);
-      for (int32_t s : src) {
-        if (L1.rank[s] >= 0) m2p += nt;
-        else p2p_il += nt;
-      }
+      int64_t nr, nl;
+      il_count(l, F, nr, nl);
+      m2p += nr * nt;
+      p2p_il += nl * nt;
       const int32_t* nb = &L1.nbr[(size_t)F * 27];
       for (int e = 0; e < 27; ++e) {
         const int32_t q = nb[e];
         if (q < 0) continue;
         const int32_t rq = L1.rank[q];
         if (rq < 0) {
-          p2p += nt;
+          p2p += nt;  // a leaf one level coarser: P2P with every target
           continue;
         }
         for (int op = 0; op < 8; ++op) {
-          const int32_t nc = 8 * rq + op;
-          const int32_t rn = L0.rank[nc];
-          for (int o = 0; o < 8; ++o) {
-            if (!tgt[o] || nc == 8 * F + o) continue;
-            if (rn < 0) {
-              ++p2p;
-              continue;
-            }
-            int dm = 0;
-            for (int d = 0; d < 3; ++d) dm = std::max(dm, std::abs(((o >> d) & 1) - 2 * ax_of(e, d) - ((op >> d) & 1)));
-            if (dm <= 1) {
-              p2p += 8;
-              nst += 8;
-            } else {
-              ++nm2p;
-            }
+          const unsigned t = tgt & ~(unsigned)PM.self[e][op];
+          if (L0.rank[8 * rq + op] < 0) {
+            p2p += __builtin_popcount(t);  // leaf candidate: P2P with every other target
+            continue;
           }
+          const int na = __builtin_popcount(t & PM.adj[e][op]);
+          p2p += 8 * na;  // touching refined candidate: nearest field from its 8 children
+          nst += 8 * na;
+          nm2p += __builtin_popcount(t & ~(unsigned)PM.adj[e][op]);
         }
       }
     }
@@ -761,6 +773,20 @@ static void build_tables(int p, HostTables& H) {
   }
 }
 
+// The translation tables depend on the order only: built once per order and
+// shared (read only) by every plan of the process.
+static std::shared_ptr<const HostTables> tables_for(int p) {
+  static std::mutex mu;
+  static std::shared_ptr<const HostTables> cache[kPMax + 1];
+  std::lock_guard<std::mutex> lock(mu);
+  if (!cache[p]) {
+    auto t = std::make_shared<HostTables>();
+    build_tables(p, *t);
+    cache[p] = t;
+  }
+  return cache[p];
+}
+
 // Potential at the centre of a uniform unit cube of unit mass, up to -G/h:
 // C = integral over [-1/2, 1/2]^3 of 1/|r|.  Splitting the cube into the six
 // pyramids from its centre to its faces and integrating along the rays
@@ -814,7 +840,7 @@ struct afmm_plan {
   afmm_options opt{};
   int K = 0;
   Topology topo;
-  HostTables tabs;
+  std::shared_ptr<const HostTables> tabs;  // shared by every plan of the same order
   LevelDev lv[kMaxLevel + 1];
   int32_t* d_leafgrp[kMaxLevel] = {};
   int32_t* d_m2lgrp[kMaxLevel] = {};
@@ -1243,7 +1269,7 @@ static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
   const int f64 = mixed ? P->opt.fp64_levels : 1 << 20;
   build_groups(T);
   fill_info(P->info, P->work, T, P->opt);
-  build_tables(P->opt.p, P->tabs);
+  P->tabs = tables_for(P->opt.p);
   afmm_status s;
   for (int l = 0; l <= T.lmax; ++l) {
     HostLevel& H = T.lv[l];
@@ -1306,7 +1332,7 @@ static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
       if (hipMemsetAsync(P->d_nmp[l], 0, bytes, st) != hipSuccess) return fail(AFMM_E_DEVICE, "near partial clear");
     }
   }
-  HostTables& H = P->tabs;
+  const HostTables& H = *P->tabs;
   {
     std::vector<int8_t> mi8(H.mi.begin(), H.mi.end());
     int8_t* d_mi;
@@ -2215,7 +2241,7 @@ static afmm_status adjoint_topology(afmm_plan* P) {
       const int32_t cF = LS.refcell[F];
       const int32_t G = cF >> 3, oF = cF & 7;
       for (int i = 0; i < 189; ++i) {
-        const int code = P->tabs.taps[oF * 189 + i];
+        const int code = P->tabs->taps[oF * 189 + i];
         const int32_t Q = LP.nbr[(size_t)G * 27 + (code & 31)];
         if (Q < 0 || LP.rank[Q] < 0) continue;
         mark[8 * LP.rank[Q] + ((code >> 5) & 7)] = 1;

@@ -72,12 +72,14 @@ def ats_sequence(lmin, lmax):
     return seq
 
 
-def time_ats(h, mass_t, p, precision, reps=2, graph=False):
+def time_ats(h, mass_t, p, precision, reps=2, graph=False, drift=False):
     """One coarse step of the adaptive-time-step sequence, masses of the active
     levels perturbed by 1e-3 seeded noise before every solve.  With `graph` the
     plan replays captured graphs (AFMM_GRAPH); the masses of each substep are
     then copied into one buffer first (a device copy inside the timed region),
-    as an integrator updating them in place would."""
+    as an integrator updating them in place would.  With `drift` every solve
+    is a drifted one (afmm_solve_drift, substep k at time 0.01 k, seeded mass
+    rates of the same magnitude as the perturbations)."""
     import torch
     import paper_2607_19489_amd as A
     plan = A.Plan(h, p=p, precision=precision, graph=graph)
@@ -95,18 +97,22 @@ def time_ats(h, mass_t, p, precision, reps=2, graph=False):
     phi = torch.zeros(h.total, dtype=torch.float64, device="cuda")
     acc = torch.zeros(h.total, 3, dtype=torch.float64, device="cuda")
     mbuf = mass_t.clone()
+    rate = mass_t * 0.1 * (2 * torch.rand(h.total, dtype=torch.float64, device="cuda", generator=gen) - 1)
     per_level = {}
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in seq]
     best = None
     for _ in range(reps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for (l, ic), mm, (a, b) in zip(seq, masses, ev):
+        for k, ((l, ic), mm, (a, b)) in enumerate(zip(seq, masses, ev)):
             a.record()
             if graph:
                 mbuf.copy_(mm)
                 mm = mbuf
-            plan.solve(mm, level=l, icount=ic, phi=phi, acc=acc)
+            if drift:
+                plan.solve_drift(mm, rate, 0.01 * k, level=l, icount=ic, phi=phi, acc=acc)
+            else:
+                plan.solve(mm, level=l, icount=ic, phi=phi, acc=acc)
             b.record()
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
@@ -517,6 +523,10 @@ def main():
             ats["graph_sequence_ms"] = atsg["sequence_ms"]
             ats["graph_leaf_updates_per_s"] = atsg["leaf_updates_per_s"]
             print(f"[bench] ATS step, graph replay: {atsg['sequence_ms']:.2f} ms", file=sys.stderr, flush=True)
+        atsd = time_ats(h, mass_t, w.p, "fp32", drift=True)
+        ats["drift_sequence_ms"] = atsd["sequence_ms"]
+        ats["drift_mean_ms_per_solve_by_level"] = atsd["mean_ms_per_solve_by_level"]
+        print(f"[bench] ATS step, drifted stale trees: {atsd['sequence_ms']:.2f} ms", file=sys.stderr, flush=True)
 
     adj = None
     if args.adjoint or args.workload == "cfg5":

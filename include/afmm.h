@@ -207,6 +207,33 @@ afmm_status afmm_solve(afmm_plan* plan, int32_t level, int32_t icount, const dou
                        double* d_phi, double* d_acc, void* hip_stream);
 
 /*
+ * Adaptive time step with drifted stale trees.  During a sub-cycle of Alg. 1
+ * the trees of the inactive coarser levels keep the masses of their last
+ * rebuild, an error of first order in the time since then (Sec. 4 discussion of
+ * the binary orbit under adaptive time steps: the inactive multipoles are not
+ * drifted).  This call is afmm_solve plus a first-order drift of those trees:
+ *   - the trees it rebuilds (as afmm_solve decides) record `time` and the mass
+ *     rate d_mass_rate (dm/dt, FP64, one slot per cell in the order of d_mass,
+ *     device memory; read for the levels rebuilt) of their leaves;
+ *   - every stale tree whose last rebuild recorded rates is evaluated with its
+ *     masses advanced linearly to `time`: m + (time - t_rebuild) dm/dt.  Trees
+ *     last rebuilt by afmm_solve (no rates) stay as they were.
+ * A mass field that changes linearly in time is therefore solved exactly at
+ * every sub-step.  Costs a pass over all slots and the whole upward pass at
+ * every call (stale multipoles change with time, so no call reuses the
+ * previous trees) plus 16 bytes per cell of device memory, allocated by the
+ * first call; the call runs eagerly (AFMM_GRAPH does not capture it).  With
+ * level == AFMM_ALL_LEVELS every tree is rebuilt at `time` with its rates.
+ * The adjoint of a drifted solve is that of afmm_solve (the drifted stale
+ * masses are not an input).  Errors as afmm_solve, plus AFMM_E_INVALID_ARG for
+ * a null d_mass_rate or a non-finite time; with AFMM_CHECK_INPUT the rates of
+ * the leaves the call reads are checked as the masses are.
+ */
+afmm_status afmm_solve_drift(afmm_plan* plan, int32_t level, int32_t icount, double time,
+                             const double* d_mass, const double* d_mass_rate, double* d_phi, double* d_acc,
+                             void* hip_stream);
+
+/*
  * Adjoint of the last solve's linear map m -> (phi, a): d_mass_bar = A^T
  * (d_phi_bar, d_acc_bar) over the same trees and lists (transposed kernels,
  * gather form, no atomics).  Inputs are indexed like d_phi / d_acc and only

@@ -35,7 +35,7 @@ SYMBOLS = [
     "afmm_plan_set_profiling", "afmm_plan_get_profile", "afmm_batch_set_profiling", "afmm_batch_get_profile",
     "afmm_plan_autotune", "afmm_batch_autotune", "afmm_solve_adjoint_noalloc",
     "afmm_particle_hierarchy_create", "afmm_particle_hierarchy_view", "afmm_particle_hierarchy_destroy",
-    "afmm_cic_deposit", "afmm_cic_interpolate", "afmm_particles_update", "afmm_plan_replan",
+    "afmm_cic_deposit", "afmm_cic_interpolate", "afmm_particles_update", "afmm_plan_replan", "afmm_solve_drift",
 ]
 
 
@@ -109,6 +109,7 @@ def lib():
     L.afmm_plan_replan.argtypes = [vp, C.POINTER(HierarchyC), C.c_int32, vp, C.POINTER(vp)]
     L.afmm_plan_get_info.argtypes = [vp, C.POINTER(PlanInfo)]
     L.afmm_solve.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp, vp]
+    L.afmm_solve_drift.argtypes = [vp, C.c_int32, C.c_int32, C.c_double, vp, vp, vp, vp, vp]
     L.afmm_solve_adjoint.argtypes = [vp, C.c_int32, vp, vp, vp, vp]
     L.afmm_solve_adjoint_noalloc.argtypes = [vp, C.c_int32, vp, vp, vp, vp]
     L.afmm_batch_create.argtypes = [C.POINTER(vp), C.c_int32, vp, C.POINTER(vp)]
@@ -139,7 +140,7 @@ def lib():
                  "afmm_plan_get_profile", "afmm_batch_set_profiling", "afmm_batch_get_profile",
                  "afmm_plan_autotune", "afmm_batch_autotune", "afmm_particle_hierarchy_create",
                  "afmm_particle_hierarchy_view", "afmm_particle_hierarchy_destroy", "afmm_cic_deposit",
-                 "afmm_cic_interpolate", "afmm_particles_update", "afmm_plan_replan"):
+                 "afmm_cic_interpolate", "afmm_particles_update", "afmm_plan_replan", "afmm_solve_drift"):
         getattr(L, name).restype = C.c_int32
     _lib = L
     return L

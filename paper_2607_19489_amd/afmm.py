@@ -163,6 +163,24 @@ class Plan:
               "afmm_solve")
         return phi, acc
 
+    def solve_drift(self, mass: torch.Tensor, mass_rate: torch.Tensor, time: float, level: int = AFMM_ALL_LEVELS,
+                    icount: int = 1, phi: Optional[torch.Tensor] = None, acc: Optional[torch.Tensor] = None,
+                    stream: Optional[torch.cuda.Stream] = None):
+        """afmm_solve_drift: afmm_solve with the stale trees advanced to `time`
+        by the mass rates their last rebuild recorded; returns (phi, acc)."""
+        self._check_tensor(mass, (self.N,), "mass")
+        self._check_tensor(mass_rate, (self.N,), "mass_rate")
+        if phi is None:
+            phi = torch.zeros(self.N, dtype=torch.float64, device=mass.device)
+        if acc is None:
+            acc = torch.zeros(self.N, 3, dtype=torch.float64, device=mass.device)
+        self._check_tensor(phi, (self.N,), "phi")
+        self._check_tensor(acc, (self.N, 3), "acc")
+        check(lib().afmm_solve_drift(self._ptr, level, icount, float(time), C.c_void_p(mass.data_ptr()),
+                                     C.c_void_p(mass_rate.data_ptr()), C.c_void_p(phi.data_ptr()),
+                                     C.c_void_p(acc.data_ptr()), _stream_handle(stream)), "afmm_solve_drift")
+        return phi, acc
+
     def autotune(self, mass: torch.Tensor, phi: Optional[torch.Tensor] = None, acc: Optional[torch.Tensor] = None,
                  stream: Optional[torch.cuda.Stream] = None) -> dict:
         """afmm_plan_autotune: pick the M2L / M2P tap splits by timing; leaves a full solve in phi/acc."""

@@ -894,6 +894,13 @@ struct afmm_plan {
   TablesDev<double> t64;
   CommonDev cm;
   double* m_snap = nullptr;       // adaptive-time-step snapshot of leaf masses (slot space)
+  // drifted solves (afmm_solve_drift): mass rates of the snapshot, the time of
+  // each level's last rebuild, whether that rebuild recorded rates, and the
+  // drifted masses a solve reads (allocated by the first drifted solve)
+  double* rate_snap = nullptr;
+  double* m_drift = nullptr;
+  double t_snap[kMaxLevel] = {};
+  bool rate_valid[kMaxLevel] = {};
   uint64_t* d_keys[kMaxLevel] = {};  // per-level Morton keys of the cells (particle-mesh calls, on first use)
   int* d_flag = nullptr;          // AFMM_CHECK_INPUT / particle-mesh calls: device flag (plan-owned)
   int* h_flag = nullptr;          // its pinned host copy
@@ -1896,9 +1903,51 @@ static afmm_status replay_or_run(afmm_plan* P, int level, bool rebuild, bool kee
   return dev_check(P, hipGraphLaunch(hit->x, st), "graph launch");
 }
 
+// Drifted solves: the rate snapshot and the drifted-mass buffer, allocated by
+// the first drifted solve of a plan (the rates start at zero).
+static afmm_status ensure_drift_buffers(afmm_plan* P, hipStream_t st) {
+  if (P->rate_snap) return AFMM_OK;
+  const size_t n = (size_t)std::max<int64_t>(P->topo.nslots, 1);
+  void* a = nullptr;
+  void* b = nullptr;
+  afmm_status s;
+  if ((s = dev_alloc(P, &a, n * sizeof(double))) || (s = dev_alloc(P, &b, n * sizeof(double)))) return s;
+  if ((s = dev_check(P, launch_adj_zero((double*)a, n, st), "drift buffers"))) return s;
+  P->rate_snap = (double*)a;
+  P->m_drift = (double*)b;
+  return AFMM_OK;
+}
+
+// Trees of levels >= from rebuilt at `time`: record their mass rates (a plain
+// solve, d_rate null, records none).
+static afmm_status record_rates(afmm_plan* P, const double* d_rate, int from, double time, hipStream_t st) {
+  const Topology& T = P->topo;
+  const int lmin = T.levelmin[0], lmax = T.levelmax[0];
+  if (!d_rate) {
+    for (int l = from; l <= lmax; ++l) P->rate_valid[l] = false;
+    return AFMM_OK;
+  }
+  afmm_status s = ensure_drift_buffers(P, st);
+  if (s) return s;
+  const int64_t off = T.level_off[0][from - lmin];
+  if ((s = dev_check(P,
+                     hipMemcpyAsync(P->rate_snap + off, d_rate + off, (size_t)(T.nslots - off) * sizeof(double),
+                                    hipMemcpyDeviceToDevice, st),
+                     "rate snapshot")))
+    return s;
+  for (int l = from; l <= lmax; ++l) {
+    P->rate_valid[l] = true;
+    P->t_snap[l] = time;
+  }
+  return AFMM_OK;
+}
+
+// d_rate != nullptr: a drifted solve (afmm_solve_drift) at `time`
 static afmm_status afmm_solve_impl(afmm_plan* P, int32_t level, int32_t icount, const double* d_mass, double* d_phi,
-                                  double* d_acc, void* hip_stream) {
+                                  double* d_acc, void* hip_stream, double time = 0.0,
+                                  const double* d_rate = nullptr) {
   if (!P || !d_mass || !d_phi || !d_acc) return fail(AFMM_E_INVALID_ARG, "null argument");
+  if (d_rate && !std::isfinite(time)) return fail(AFMM_E_INVALID_ARG, "time must be finite");
   if (P->dead) return fail(AFMM_E_DEVICE, "plan is unusable after an earlier device error");
   hipStream_t st = (hipStream_t)hip_stream;
   Topology& T = P->topo;
@@ -1923,12 +1972,17 @@ static afmm_status afmm_solve_impl(afmm_plan* P, int32_t level, int32_t icount, 
         hipLaunchKernelGGL(k_nonfinite, dim3((unsigned)std::min((D.n + 255) / 256, 2048)), dim3(256), 0, st, D.n,
                            D.rank, D.slot, d_mass, P->d_flag);
         if ((r = dev_check(P, hipGetLastError(), "input check"))) return r;
+        if (d_rate) {
+          hipLaunchKernelGGL(k_nonfinite, dim3((unsigned)std::min((D.n + 255) / 256, 2048)), dim3(256), 0, st, D.n,
+                             D.rank, D.slot, d_rate, P->d_flag);
+          if ((r = dev_check(P, hipGetLastError(), "input check"))) return r;
+        }
       }
       if ((r = dev_check(P, hipMemcpyAsync(P->h_flag, P->d_flag, sizeof(int), hipMemcpyDeviceToHost, st),
                          "input check")) ||
           (r = dev_check(P, hipStreamSynchronize(st), "input check")))
         return r;
-      if (*P->h_flag) return fail(AFMM_E_NONFINITE, "non-finite mass in a leaf slot that the solve reads");
+      if (*P->h_flag) return fail(AFMM_E_NONFINITE, "non-finite mass (or mass rate) in a leaf slot that the solve reads");
     }
   }
   if (level == AFMM_ALL_LEVELS) {
@@ -1943,6 +1997,7 @@ static afmm_status afmm_solve_impl(afmm_plan* P, int32_t level, int32_t icount, 
       return run_solve(P, d_mass, T.lmax - 1, lmin, lmax, d_phi, d_acc, s, false, P->m_snap);
     });
     P->tree_fresh = r == AFMM_OK;
+    if (r == AFMM_OK) r = record_rates(P, d_rate, lmin, time, st);
     return r;
   }
   // Alg. 1: rebuild trees j >= level iff level == levelmin or icount > 1; after
@@ -1961,6 +2016,33 @@ static afmm_status afmm_solve_impl(afmm_plan* P, int32_t level, int32_t icount, 
   const bool keep = !rebuild && P->tree_fresh;
   P->tree_fresh = false;
   const int64_t off = rebuild ? T.level_off[0][from - lmin] : 0;
+  if (d_rate) {
+    // drifted solve (eager): rebuilt levels record masses, rates and time; the
+    // solve reads the snapshot with every stale level advanced to `time`
+    afmm_status r = ensure_drift_buffers(P, st);
+    if (!r && rebuild && dev_check(P,
+                                   hipMemcpyAsync(P->m_snap + off, d_mass + off,
+                                                  (size_t)(T.nslots - off) * sizeof(double), hipMemcpyDeviceToDevice, st),
+                                   "snapshot"))
+      r = AFMM_E_DEVICE;
+    if (!r && rebuild) r = record_rates(P, d_rate, from, time, st);
+    if (!r) {
+      DriftLevels dl{};
+      dl.n = lmax - lmin + 1;
+      for (int i = 0; i < dl.n; ++i) {
+        const int l = lmin + i;
+        dl.off[i] = T.level_off[0][i];
+        dl.dt[i] = (P->rate_valid[l] && l < from) ? time - P->t_snap[l] : 0.0;
+      }
+      dl.off[dl.n] = T.level_off[0][dl.n];
+      r = dev_check(P, launch_drift(dl, P->m_snap, P->rate_snap, P->m_drift, T.nslots, st), "drift");
+    }
+    if (!r) r = run_solve(P, P->m_drift, level - 1, level, level, d_phi, d_acc, st, false);
+    return r;
+  }
+  // a plain rebuild leaves no rates for its levels
+  if (rebuild)
+    for (int l = from; l <= lmax; ++l) P->rate_valid[l] = false;
   afmm_status r = replay_or_run(P, level + 64 * from, rebuild, keep, d_mass, d_phi, d_acc, st, [&](hipStream_t s) -> afmm_status {
     // the rebuilt trees take the masses of levels >= level from this call
     if (rebuild && dev_check(P,
@@ -2791,6 +2873,14 @@ extern "C" afmm_status afmm_plan_replan(const afmm_plan* old, const afmm_hierarc
 extern "C" afmm_status afmm_solve(afmm_plan* P, int32_t level, int32_t icount, const double* d_mass, double* d_phi,
                                   double* d_acc, void* hip_stream) {
   return guarded([&] { return afmm_solve_impl(P, level, icount, d_mass, d_phi, d_acc, hip_stream); });
+}
+
+extern "C" afmm_status afmm_solve_drift(afmm_plan* P, int32_t level, int32_t icount, double time,
+                                        const double* d_mass, const double* d_mass_rate, double* d_phi, double* d_acc,
+                                        void* hip_stream) {
+  if (!d_mass_rate) return fail(AFMM_E_INVALID_ARG, "null mass rate");
+  return guarded(
+      [&] { return afmm_solve_impl(P, level, icount, d_mass, d_phi, d_acc, hip_stream, time, d_mass_rate); });
 }
 
 extern "C" afmm_status afmm_plan_get_profile(afmm_plan* P, afmm_stage_time* out, int32_t cap, int32_t* n_out) {

@@ -170,6 +170,15 @@ struct MfmaTables {
 // Leaf masses of one level from the caller's slot array; with `snap`, every
 // cell's slot value is also copied there (the adaptive-time-step snapshot).
 hipError_t launch_gather_mass(const LevelDev& lv, const double* m_src, double* snap, hipStream_t st);
+// Drifted masses of a solve with stale trees: out[s] = m[s] + dt * rate[s] for
+// the slots [off[i], off[i + 1]) of AMR level i (levels with dt = 0 copied)
+struct DriftLevels {
+  int n = 0;
+  int64_t off[kMaxLevel + 1] = {};
+  double dt[kMaxLevel] = {};
+};
+hipError_t launch_drift(const DriftLevels& d, const double* m, const double* rate, double* out, int64_t nslots,
+                        hipStream_t st);
 hipError_t launch_copy_slots(const int32_t* slots, int64_t n, const double* src, double* dst,
                              hipStream_t st);
 // Batches: forest slot <-> caller arrays.  leafslot/leafhier list every leaf of

@@ -1428,8 +1428,28 @@ __global__ __launch_bounds__(kBlock) void k_near_m2p(const int32_t* __restrict__
     }
 }
 
+// Stale trees advanced to the solve's time: each slot's level is found by a
+// scan of the (at most 21) level offsets.
+__global__ void k_drift(DriftLevels d, const double* __restrict__ m, const double* __restrict__ rate,
+                        double* __restrict__ out, int64_t nslots) {
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nslots; s += (int64_t)gridDim.x * blockDim.x) {
+    int i = 0;
+    while (i + 1 < d.n && s >= d.off[i + 1]) ++i;
+    const double dt = d.dt[i];
+    out[s] = dt != 0.0 ? m[s] + dt * rate[s] : m[s];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // launchers
+
+hipError_t launch_drift(const DriftLevels& d, const double* m, const double* rate, double* out, int64_t nslots,
+                        hipStream_t st) {
+  if (nslots <= 0) return hipSuccess;
+  const int blocks = (int)std::min<int64_t>((nslots + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_drift, dim3(blocks), dim3(256), 0, st, d, m, rate, out, nslots);
+  return hipGetLastError();
+}
 
 template <typename T>
 static hipError_t m2p_dispatch(int p, const MfmaTiles& mt, int t0, int n, int nsplit, const MfmaTables& tabs,

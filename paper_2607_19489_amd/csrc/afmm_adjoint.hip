@@ -537,6 +537,19 @@ __device__ inline void adj_write(const typename Acc4<T>::type& acc, int rt, int 
   }
 }
 
+// Step kb of the transposed M2P carries quantity q = kb & 3 (phi, then the
+// three acceleration components) of two children.  Multipole coefficients of
+// order p enter the forward M2P only through the potential (the accelerations
+// use orders < p), so a 16-row tile whose rows are all of order p has zero A
+// entries in the acceleration steps: they are skipped (adding zeros would not
+// change a bit of the result).
+template <int P>
+__host__ __device__ constexpr bool adj_m2p_step_used(int rt, int kb) {
+  int d = 0;
+  while (nmi(d) <= 16 * rt) ++d;  // order of the tile's first row
+  return d < P || (kb & 3) == 0;
+}
+
 // Transposed intermediate-field M2P: targets = leaf children (level ls + 1) of
 // the groups reading the source; k = (child o, quantity q) with lane group g
 // holding j = 8 g + kb, so its B fragments are 8 consecutive values of tbT.
@@ -602,7 +615,8 @@ __global__ __launch_bounds__(64) void k_adj_m2p_mfma(const int32_t* __restrict__
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-      for (int kb = 0; kb < 8; ++kb) acc[rt] = mfma16(D[off[rt][kb]], bc[kb / VW][kb % VW], acc[rt]);
+      for (int kb = 0; kb < 8; ++kb)
+        if (adj_m2p_step_used<P>(rt, kb)) acc[rt] = mfma16(D[off[rt][kb]], bc[kb / VW][kb % VW], acc[rt]);
     store_dstage_t<T, SDP, 64>(sD[b ^ 1], vD);
     __syncthreads();
   };

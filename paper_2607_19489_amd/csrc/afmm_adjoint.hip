@@ -278,27 +278,38 @@ __global__ __launch_bounds__(256) void k_adj_near_m2p(const int32_t* __restrict_
 // of b - e_i (a_i): the 8 children's target bars are folded per quantity into
 // Y_q[pi] = sum_o (-1)^popcount(~o & pi) T_o[q] first.
 template <int P>
-__global__ __launch_bounds__(256) void k_adj_l2p(const int32_t* __restrict__ grp, LevelDev lv1, LevelDev lv0,
+__global__ __launch_bounds__(256) void k_adj_l2p(const int32_t* __restrict__ grp, int ngrp, LevelDev lv1, LevelDev lv0,
                                                  const double* __restrict__ l2p, const int8_t* __restrict__ mi) {
   constexpr int K = nmi(P);
-  __shared__ double s_t[32];
-  __shared__ double sY[4][8];
-  const int F = grp ? grp[blockIdx.x] : (int)blockIdx.x;
+  constexpr int GB = 256 / K > 0 ? 256 / K : 1;  // groups per block
+  __shared__ double s_t[GB][32];
+  __shared__ double sY[GB][4][8];
   const int t = threadIdx.x;
-  if (t < 32) s_t[t] = lv0.tbar[4 * (size_t)(8 * F) + t];
+  const int g0 = blockIdx.x * GB;
+  for (int i = t; i < GB * 32; i += 256) {
+    const int gi = g0 + (i >> 5);
+    if (gi < ngrp) {
+      const int F = grp ? grp[gi] : gi;
+      s_t[i >> 5][i & 31] = lv0.tbar[4 * (size_t)(8 * F) + (i & 31)];
+    }
+  }
   __syncthreads();
-  if (t < 32) {
-    const int q = t >> 3, pi = t & 7;
+  for (int i = t; i < GB * 32; i += 256) {
+    const int gl = i >> 5, q = (i >> 3) & 3, pi = i & 7;
+    if (g0 + gl >= ngrp) continue;
     double y = 0.0;
-    for (int o = 0; o < 8; ++o) y += parity_sign(pi, o) * s_t[4 * o + q];
-    sY[q][pi] = y;
+    for (int o = 0; o < 8; ++o) y += parity_sign(pi, o) * s_t[gl][4 * o + q];
+    sY[gl][q][pi] = y;
   }
   __syncthreads();
   const double* w7 = l2p + (size_t)7 * 4 * K;
-  for (int b = t; b < K; b += 256) {
+  for (int i = t; i < GB * K; i += 256) {
+    const int gl = i / K, b = i - gl * K;
+    if (g0 + gl >= ngrp) continue;
+    const int F = grp ? grp[g0 + gl] : g0 + gl;
     const int par = (mi[4 * b] & 1) | (mi[4 * b + 1] & 1) << 1 | (mi[4 * b + 2] & 1) << 2;
-    double acc = w7[b] * sY[0][par];
-    for (int i = 0; i < 3; ++i) acc += w7[(size_t)(1 + i) * K + b] * sY[1 + i][par ^ (1 << i)];
+    double acc = w7[b] * sY[gl][0][par];
+    for (int c = 0; c < 3; ++c) acc += w7[(size_t)(1 + c) * K + b] * sY[gl][1 + c][par ^ (1 << c)];
     lv1.lbar[(size_t)F * K + b] += acc;
   }
 }
@@ -361,65 +372,98 @@ __global__ __launch_bounds__(256) void k_adj_l2l(const int32_t* __restrict__ grp
 // M2M^T into the leaf children of the refined cells of level l-1: the
 // monopole entry of every coefficient, folded per parity class first
 // (Y_q = sum over a of parity q of w_a S_bar_a), then m_bar(o) += sum_q sign_q(o) Y_q.
+// Block = kLeafupParents parents (rows staged in LDS), thread = (parent, parity
+// class), then thread = (parent, child octant).
+constexpr int kLeafupParents = 32;
+
 template <int P>
-__global__ void k_adj_leafup(LevelDev lv1, LevelDev lv0, CommonDev cm) {
+__global__ __launch_bounds__(256) void k_adj_leafup(LevelDev lv1, LevelDev lv0, CommonDev cm) {
   constexpr int K = nmi(P);
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= lv1.nref) return;
-  double Y[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  const double* Sp = lv1.sbar + (size_t)r * K;
-  for (int j = cm.m2mT_start[0]; j < cm.m2mT_start[1]; ++j) {
-    const int code = cm.m2mT_list[j];
-    Y[code >> 12] += cm.m2mT_w[j] * Sp[code & 4095];
+  constexpr int NPB = kLeafupParents;
+  __shared__ double sS[NPB * K];
+  __shared__ double sY[NPB][8];
+  const int t = threadIdx.x;
+  const int r0 = blockIdx.x * NPB;
+  const int np = min(NPB, lv1.nref - r0);
+  for (int i = t; i < np * K; i += 256) sS[i] = lv1.sbar[(size_t)r0 * K + i];
+  __syncthreads();
+  const int j = t >> 3, q = t & 7;
+  if (j < np) {
+    double y = 0.0;
+    for (int e = cm.m2mT_start[0]; e < cm.m2mT_start[1]; ++e) {
+      const int code = cm.m2mT_list[e];
+      if ((code >> 12) == q) y += cm.m2mT_w[e] * sS[j * K + (code & 4095)];
+    }
+    sY[j][q] = y;
   }
-  for (int o = 0; o < 8; ++o) {
-    const int c = 8 * r + o;
-    if (lv0.rank[c] >= 0) continue;
-    double v = 0.0;
+  __syncthreads();
+  if (j < np) {
+    const int o = q, c = 8 * (r0 + j) + o;
+    if (lv0.rank[c] < 0) {
+      double v = 0.0;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) v += parity_sign(q, o) * Y[q];
-    lv0.mbar[c] += v;
+      for (int u = 0; u < 8; ++u) v += parity_sign(u, o) * sY[j][u];
+      lv0.mbar[c] += v;
+    }
   }
 }
 
 // Source-copy bars -> multipole bars, and M2M^T from the parent (levels
 // processed coarse to fine): S_bar[r]_k = c_k 2^|k| Sc_bar[r]_k
 //   + sum over the M2M entries (a, k, parity q) of w sign_q(o_r) S_bar[parent]_a.
-// Block = one refined parent at level f-1 (its row and the entry lists in LDS),
-// thread = (child octant, k); without a parent (f = 2) only the scaling.
+// Over the refined parents at level f-1 that have a refined child (list grp):
+// a block stages the entry lists once, then takes GB parents at a time (rows
+// in LDS) with thread = (parent, k): one pass over the entries of k updates
+// coefficient k of all 8 children.  Without a parent (f = 2) only the scaling
+// (k_adj_scale).
 template <int P>
-__global__ __launch_bounds__(256) void k_adj_down(LevelDev lv1, LevelDev lv0, CommonDev cm) {
+__global__ __launch_bounds__(256) void k_adj_down(const int32_t* __restrict__ grp, int ngrp, LevelDev lv1,
+                                                  LevelDev lv0, CommonDev cm) {
   constexpr int K = nmi(P);
   constexpr int NE = nmi_entries(P);
-  __shared__ double sP[K];
-  __shared__ int sR[8];
+  constexpr int GB = 256 / K > 0 ? 256 / K : 1;
+  __shared__ double sP[GB][K];
+  __shared__ int sR[GB][8];
   __shared__ int sStart[K + 1];
   __shared__ int sList[NE];
   __shared__ double sW[NE];
-  const int rp = blockIdx.x;
   const int t = threadIdx.x;
-  const int rc0 = t < 8 ? lv0.rank[8 * rp + t] : -1;
-  if (t < 8) sR[t] = rc0;
-  // no refined child: nothing to pass down (most cells of a finely refined
-  // level); leave before staging the tables
-  if (!__syncthreads_or(rc0 >= 0)) return;
-  for (int i = t; i < K; i += 256) sP[i] = lv1.sbar[(size_t)rp * K + i];
   for (int i = t; i <= K; i += 256) sStart[i] = cm.m2mT_start[i];
   for (int i = t; i < NE; i += 256) {
     sList[i] = cm.m2mT_list[i];
     sW[i] = cm.m2mT_w[i];
   }
-  __syncthreads();
-  for (int i = t; i < 8 * K; i += 256) {
-    const int o = i / K, k = i - o * K;
-    const int rc = sR[o];
-    if (rc < 0) continue;
-    double v = cm.cfac2[k] * lv0.sbar[(size_t)rc * K + k];
-    for (int j = sStart[k]; j < sStart[k + 1]; ++j) {
-      const int code = sList[j];
-      v += sW[j] * parity_sign(code >> 12, o) * sP[code & 4095];
+  const int gl = t / K, k = t - gl * K;
+  for (int g0 = blockIdx.x * GB; g0 < ngrp; g0 += gridDim.x * GB) {
+    __syncthreads();  // tables staged; the previous round is done with sP and sR
+    for (int i = t; i < GB * 8; i += 256) {
+      const int gi = g0 + (i >> 3);
+      sR[i >> 3][i & 7] = gi < ngrp ? lv0.rank[8 * (size_t)grp[gi] + (i & 7)] : -1;
     }
-    lv0.sbar[(size_t)rc * K + k] = v;
+    for (int i = t; i < GB * K; i += 256) {
+      const int gj = i / K, gi = g0 + gj;
+      if (gi < ngrp) sP[gj][i - gj * K] = lv1.sbar[(size_t)grp[gi] * K + (i - gj * K)];
+    }
+    __syncthreads();
+    if (gl >= GB || g0 + gl >= ngrp) continue;
+    double v[8];
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+      const int rc = sR[gl][o];
+      v[o] = rc >= 0 ? cm.cfac2[k] * lv0.sbar[(size_t)rc * K + k] : 0.0;
+    }
+    for (int e = sStart[k]; e < sStart[k + 1]; ++e) {
+      const int code = sList[e];
+      const double w = sW[e], sp = sP[gl][code & 4095];
+      const int q = code >> 12;
+#pragma unroll
+      for (int o = 0; o < 8; ++o) v[o] += w * parity_sign(q, o) * sp;
+    }
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+      const int rc = sR[gl][o];
+      if (rc >= 0) lv0.sbar[(size_t)rc * K + k] = v[o];
+    }
   }
 }
 
@@ -507,6 +551,39 @@ __device__ inline int adj_group(int code, int n, const int* sCB, const int32_t* 
   return cb < 0 ? -1 : rank_s[cb + ((code >> 5) & 7)];
 }
 
+// Work item of this workgroup in its XCD's range, or -1.
+__device__ inline int xcd_item(const XcdRanges& xr) {
+  const int x = (int)(blockIdx.x & 7), item = xr.start[x] + (int)(blockIdx.x >> 3);
+  return item < xr.start[x + 1] ? item : -1;
+}
+
+// Taps of [tb, te) whose group has a target child in at least one of the 16
+// columns, moved in tap order to the front of sTap (one wave: lane group g
+// tests tap i0 + g; a tap is written at an index no larger than its own, after
+// every lane has read it); returns their number.  The other taps add nothing
+// (every B is zero).
+__device__ inline int adj_live_taps(int tb, int te, int* sTap, const int* sCB, const int32_t* __restrict__ rank_s,
+                                    const uint8_t* __restrict__ live) {
+  const int lane = threadIdx.x, n = lane & 15, g = lane >> 4;
+  int cnt = 0;
+  for (int i0 = tb; i0 < te; i0 += 4) {
+    bool hit = false;
+    if (i0 + g < te) {
+      const int rF = adj_group(sTap[i0 + g], n, sCB, rank_s);
+      hit = rF >= 0 && live[rF] != 0;
+    }
+    const uint64_t m = __ballot(hit);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if ((m >> (16 * j)) & 0xffffull) {
+        if (lane == 0) sTap[cnt] = sTap[i0 + j];
+        ++cnt;
+      }
+  }
+  __syncthreads();
+  return cnt;
+}
+
 // Output rows of one 16-row tile: multipole-source bars of refined sources,
 // the monopole row of leaf sources into their mass bars; with a tap split,
 // the rows go to the block's partial set part[(chunk * ntiles + tile) * 16 + n][K]
@@ -554,8 +631,9 @@ __host__ __device__ constexpr bool adj_m2p_step_used(int rt, int kb) {
 // the groups reading the source; k = (child o, quantity q) with lane group g
 // holding j = 8 g + kb, so its B fragments are 8 consecutive values of tbT.
 template <typename T, int P>
-__global__ __launch_bounds__(64) void k_adj_m2p_mfma(const int32_t* __restrict__ tiles, int ntiles, int nsplit,
+__global__ __launch_bounds__(64) void k_adj_m2p_mfma(const int32_t* __restrict__ tiles, XcdRanges xr, int nsplit,
                                                      double* __restrict__ part, const int32_t* __restrict__ tapsT,
+                                                     const uint8_t* __restrict__ live,
                                                      const int16_t* __restrict__ aoff, LevelDev lvp, LevelDev lvs,
                                                      const T* __restrict__ tbT, const T* __restrict__ Dst) {
   constexpr int K = nmi(P), RT = (K + 15) / 16;
@@ -566,8 +644,9 @@ __global__ __launch_bounds__(64) void k_adj_m2p_mfma(const int32_t* __restrict__
   __shared__ int sS[16];
   __shared__ int sCB[16 * 27];
   __shared__ int sTap[kTapsT];
-  const int item = xcd_tile(ntiles * nsplit);
-  if (item >= ntiles * nsplit) return;
+  const int item = xcd_item(xr);
+  if (item < 0) return;
+  const int ntiles = xr.start[8] / nsplit;
   const int tile = item / nsplit, chunk = item - tile * nsplit;
   const int tb = chunk * kTapsT / nsplit, te = (chunk + 1) * kTapsT / nsplit;
   const int lane = threadIdx.x, n = lane & 15, g = lane >> 4;
@@ -578,6 +657,7 @@ __global__ __launch_bounds__(64) void k_adj_m2p_mfma(const int32_t* __restrict__
 #pragma unroll
     for (int kb = 0; kb < 8; ++kb) off[rt][kb] = aoff[(rt * 8 + kb) * 64 + lane];
   __syncthreads();
+  const int nt = adj_live_taps(tb, te, sTap, sCB, lvs.rank, live);
   gptr<T> tbTg = as_global(tbT);
   auto loadB = [&](int rF, V* b) {
     if (rF >= 0) {
@@ -592,37 +672,39 @@ __global__ __launch_bounds__(64) void k_adj_m2p_mfma(const int32_t* __restrict__
   typename Acc4<T>::type acc[RT];
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt) acc[rt] = {0, 0, 0, 0};
-  V bA[NVB], bB[NVB];
-  V vD[ND];
-  int gn = adj_group(sTap[tb], n, sCB, lvs.rank);
-  loadB(gn, bA);
-  load_dstage_t<T, SDP, 64>(sTap[tb] >> 8, Dst, vD);
-  // both buffers hold finite rows from the start (the empty tap below reads one)
-  store_dstage_t<T, SDP, 64>(sD[0], vD);
-  store_dstage_t<T, SDP, 64>(sD[1], vD);
-  gn = adj_group(sTap[tb + 1 < te ? tb + 1 : tb], n, sCB, lvs.rank);
-  __syncthreads();
-  // Taps run in pairs; an odd range ends with one empty tap (B zero), so that
-  // both steps of a pair run unconditionally (no accumulator moves between
-  // them).
-  const int te2 = tb + ((te - tb + 1) & ~1);
-  auto step = [&](int k, int b, const V* bc, V* bn) {
-    const int k1 = k + 1 < te ? k + 1 : te - 1;
-    loadB(k + 1 < te ? gn : -1, bn);
-    load_dstage_t<T, SDP, 64>(sTap[k1] >> 8, Dst, vD);
-    gn = adj_group(sTap[k + 2 < te ? k + 2 : te - 1], n, sCB, lvs.rank);
-    const T* D = sD[b];
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int kb = 0; kb < 8; ++kb)
-        if (adj_m2p_step_used<P>(rt, kb)) acc[rt] = mfma16(D[off[rt][kb]], bc[kb / VW][kb % VW], acc[rt]);
-    store_dstage_t<T, SDP, 64>(sD[b ^ 1], vD);
+  if (nt > 0) {
+    V bA[NVB], bB[NVB];
+    V vD[ND];
+    int gn = adj_group(sTap[0], n, sCB, lvs.rank);
+    loadB(gn, bA);
+    load_dstage_t<T, SDP, 64>(sTap[0] >> 8, Dst, vD);
+    // both buffers hold finite rows from the start (the empty tap below reads one)
+    store_dstage_t<T, SDP, 64>(sD[0], vD);
+    store_dstage_t<T, SDP, 64>(sD[1], vD);
+    gn = adj_group(sTap[1 < nt ? 1 : 0], n, sCB, lvs.rank);
     __syncthreads();
-  };
-  for (int k = tb; k < te2; k += 2) {
-    step(k, 0, bA, bB);
-    step(k + 1, 1, bB, bA);
+    // Taps run in pairs; an odd count ends with one empty tap (B zero), so
+    // that both steps of a pair run unconditionally (no accumulator moves
+    // between them).
+    const int nt2 = (nt + 1) & ~1;
+    auto step = [&](int k, int b, const V* bc, V* bn) {
+      const int k1 = k + 1 < nt ? k + 1 : nt - 1;
+      loadB(k + 1 < nt ? gn : -1, bn);
+      load_dstage_t<T, SDP, 64>(sTap[k1] >> 8, Dst, vD);
+      gn = adj_group(sTap[k + 2 < nt ? k + 2 : nt - 1], n, sCB, lvs.rank);
+      const T* D = sD[b];
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb)
+          if (adj_m2p_step_used<P>(rt, kb)) acc[rt] = mfma16(D[off[rt][kb]], bc[kb / VW][kb % VW], acc[rt]);
+      store_dstage_t<T, SDP, 64>(sD[b ^ 1], vD);
+      __syncthreads();
+    };
+    for (int k = 0; k < nt2; k += 2) {
+      step(k, 0, bA, bB);
+      step(k + 1, 1, bB, bA);
+    }
   }
   const int s = sS[n];
   double* pp = nsplit > 1 ? part + ((size_t)chunk * ntiles + tile) * 16 * K : nullptr;
@@ -657,8 +739,9 @@ constexpr AdjM2LPlan<P> make_adj_m2l_plan() {
 }
 
 template <typename T, int P>
-__global__ __launch_bounds__(64) void k_adj_m2l_mfma(const int32_t* __restrict__ tiles, int ntiles, int nsplit,
+__global__ __launch_bounds__(64) void k_adj_m2l_mfma(const int32_t* __restrict__ tiles, XcdRanges xr, int nsplit,
                                                      double* __restrict__ part, const int32_t* __restrict__ tapsT,
+                                                     const uint8_t* __restrict__ live,
                                                      const int16_t* __restrict__ aoff, LevelDev lvp, LevelDev lvs,
                                                      LevelDev lvt, const T* __restrict__ lT,
                                                      const T* __restrict__ Dst) {
@@ -672,8 +755,9 @@ __global__ __launch_bounds__(64) void k_adj_m2l_mfma(const int32_t* __restrict__
   __shared__ int sS[16];
   __shared__ int sCB[16 * 27];
   __shared__ int sTap[kTapsT];
-  const int item = xcd_tile(ntiles * nsplit);
-  if (item >= ntiles * nsplit) return;
+  const int item = xcd_item(xr);
+  if (item < 0) return;
+  const int ntiles = xr.start[8] / nsplit;
   const int tile = item / nsplit, chunk = item - tile * nsplit;
   const int tb = chunk * kTapsT / nsplit, te = (chunk + 1) * kTapsT / nsplit;
   const int lane = threadIdx.x, n = lane & 15, g = lane >> 4;
@@ -682,6 +766,7 @@ __global__ __launch_bounds__(64) void k_adj_m2l_mfma(const int32_t* __restrict__
 #pragma unroll
   for (int i = 0; i < PL.total; ++i) off[i] = aoff[i * 64 + lane];
   __syncthreads();
+  const int nt = adj_live_taps(tb, te, sTap, sCB, lvs.rank, live);
   // Local-expansion-bar rows (refined ranks at level ls + 1) of the 8 children
   // of a tap's group: loaded together one tap ahead, so that the B loads of a
   // sub-step never wait for a rank.  Loads go through global-address pointers
@@ -707,44 +792,46 @@ __global__ __launch_bounds__(64) void k_adj_m2l_mfma(const int32_t* __restrict__
   typename Acc4<T>::type acc[RT];
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt) acc[rt] = {0, 0, 0, 0};
-  V bA[NVB], bB[NVB];
-  V vD[ND];
-  int ryc[8], ryn[8];
-  int gnext = tb + 1 < te ? adj_group(sTap[tb + 1], n, sCB, lvs.rank) : -1;
-  children(adj_group(sTap[tb], n, sCB, lvs.rank), ryc);
-  children(gnext, ryn);
-  loadB(ryc[0], bA);
-  load_dstage_t<T, SDP, 64>(sTap[tb] >> 8, Dst, vD);
-  store_dstage_t<T, SDP, 64>(sD[0], vD);
-  __syncthreads();
-  // sub-step (tap k, octant o): B of (k, o) in bc; prefetch (k, o+1) or (k+1, 0) into bn
-  auto sub = [&](int k, int o, const V* bc, V* bn) {
-    const int b = (k - tb) & 1;
-    if (o < 7) loadB(ryc[o + 1], bn);
-    else if (k + 1 < te) loadB(ryn[0], bn);
-    const T* D = sD[b] + o * KS;
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int kb = 0; kb < PL.ks[rt]; ++kb)
-        acc[rt] = mfma16(D[off[PL.base[rt] + kb]], bc[kb / VW][kb % VW], acc[rt]);
-  };
-  for (int k = tb; k < te; ++k) {
-    const int b = (k - tb) & 1;
-    if (k + 1 < te) load_dstage_t<T, SDP, 64>(sTap[k + 1] >> 8, Dst, vD);
-#pragma unroll
-    for (int o = 0; o < 8; o += 2) {
-      sub(k, o, bA, bB);
-      sub(k, o + 1, bB, bA);
-    }
-    if (k + 1 < te) store_dstage_t<T, SDP, 64>(sD[b ^ 1], vD);
-#pragma unroll
-    for (int o = 0; o < 8; ++o) ryc[o] = ryn[o];
-    if (k + 2 < te) {
-      gnext = adj_group(sTap[k + 2], n, sCB, lvs.rank);
-      children(gnext, ryn);
-    }
+  if (nt > 0) {
+    V bA[NVB], bB[NVB];
+    V vD[ND];
+    int ryc[8], ryn[8];
+    int gnext = 1 < nt ? adj_group(sTap[1], n, sCB, lvs.rank) : -1;
+    children(adj_group(sTap[0], n, sCB, lvs.rank), ryc);
+    children(gnext, ryn);
+    loadB(ryc[0], bA);
+    load_dstage_t<T, SDP, 64>(sTap[0] >> 8, Dst, vD);
+    store_dstage_t<T, SDP, 64>(sD[0], vD);
     __syncthreads();
+    // sub-step (tap k, octant o): B of (k, o) in bc; prefetch (k, o+1) or (k+1, 0) into bn
+    auto sub = [&](int k, int o, const V* bc, V* bn) {
+      const int b = k & 1;
+      if (o < 7) loadB(ryc[o + 1], bn);
+      else if (k + 1 < nt) loadB(ryn[0], bn);
+      const T* D = sD[b] + o * KS;
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int kb = 0; kb < PL.ks[rt]; ++kb)
+          acc[rt] = mfma16(D[off[PL.base[rt] + kb]], bc[kb / VW][kb % VW], acc[rt]);
+    };
+    for (int k = 0; k < nt; ++k) {
+      const int b = k & 1;
+      if (k + 1 < nt) load_dstage_t<T, SDP, 64>(sTap[k + 1] >> 8, Dst, vD);
+#pragma unroll
+      for (int o = 0; o < 8; o += 2) {
+        sub(k, o, bA, bB);
+        sub(k, o + 1, bB, bA);
+      }
+      if (k + 1 < nt) store_dstage_t<T, SDP, 64>(sD[b ^ 1], vD);
+#pragma unroll
+      for (int o = 0; o < 8; ++o) ryc[o] = ryn[o];
+      if (k + 2 < nt) {
+        gnext = adj_group(sTap[k + 2], n, sCB, lvs.rank);
+        children(gnext, ryn);
+      }
+      __syncthreads();
+    }
   }
   const int s = sS[n];
   double* pp = nsplit > 1 ? part + ((size_t)chunk * ntiles + tile) * 16 * K : nullptr;
@@ -821,8 +908,12 @@ hipError_t launch_adj_near(int p, const int32_t* leafgrp, int nleafgrp, const in
 hipError_t launch_adj_l2p(int p, const int32_t* grp, int ngrp, const LevelDev& lv1, const LevelDev& lv0,
                           const TablesDev<double>& t64, const CommonDev& cm, hipStream_t st) {
   if (ngrp == 0) return hipSuccess;
-#define X(PP)                                                                                                         \
-  case PP: hipLaunchKernelGGL((k_adj_l2p<PP>), dim3(ngrp), dim3(256), 0, st, grp, lv1, lv0, t64.l2p, cm.mi); break;
+  const int gb = std::max(256 / nmi(p), 1);
+#define X(PP)                                                                                              \
+  case PP:                                                                                                 \
+    hipLaunchKernelGGL((k_adj_l2p<PP>), dim3((ngrp + gb - 1) / gb), dim3(256), 0, st, grp, ngrp, lv1, lv0, \
+                       t64.l2p, cm.mi);                                                                    \
+    break;
   AFMM_P_SWITCH(p, X)
 #undef X
   return hipGetLastError();
@@ -842,13 +933,19 @@ hipError_t launch_adj_l2l(int p, const int32_t* grp, int ngrp, const LevelDev& l
   return hipGetLastError();
 }
 
-hipError_t launch_adj_down(int p, const LevelDev& lv1, const LevelDev& lv0, int has_parent, const CommonDev& cm,
-                           hipStream_t st) {
+hipError_t launch_adj_down(int p, const int32_t* grp, int ngrp, const LevelDev& lv1, const LevelDev& lv0,
+                           int has_parent, const CommonDev& cm, hipStream_t st) {
   const int n = lv0.nref * nmi(p);
   if (n == 0) return hipSuccess;
   if (has_parent) {
-#define X(PP) \
-  case PP: hipLaunchKernelGGL((k_adj_down<PP>), dim3(lv1.nref), dim3(256), 0, st, lv1, lv0, cm); break;
+    if (ngrp == 0) return hipSuccess;
+    if (!grp) return hipErrorInvalidValue;
+    const int gb = std::max(256 / nmi(p), 1);
+    const int blocks = std::min((ngrp + gb - 1) / gb, 2048);
+#define X(PP)                                                                                                       \
+  case PP:                                                                                                          \
+    hipLaunchKernelGGL((k_adj_down<PP>), dim3(blocks), dim3(256), 0, st, grp, ngrp, lv1, lv0, cm);                \
+    break;
     AFMM_P_SWITCH(p, X)
 #undef X
   } else {
@@ -865,7 +962,7 @@ hipError_t launch_adj_out(int p, const LevelDev& lv1, const LevelDev& lv0, int h
   if (lv0.n == 0) return hipSuccess;
   if (has_parent && lv1.nref > 0) {
 #define X(PP) \
-  case PP: hipLaunchKernelGGL((k_adj_leafup<PP>), dim3((lv1.nref + 255) / 256), dim3(256), 0, st, lv1, lv0, cm); break;
+  case PP: hipLaunchKernelGGL((k_adj_leafup<PP>), dim3((lv1.nref + kLeafupParents - 1) / kLeafupParents), dim3(256), 0, st, lv1, lv0, cm); break;
     AFMM_P_SWITCH(p, X)
 #undef X
   }
@@ -885,31 +982,36 @@ static hipError_t adj_reduce(int p, const int32_t* tiles, int ntiles, int nsplit
 }
 
 template <typename T>
-static hipError_t adj_m2p_t(int p, const int32_t* tiles, int ntiles, int nsplit, double* part, const int32_t* tapsT,
+static hipError_t adj_m2p_t(int p, const int32_t* tiles, int ntiles, int nsplit, const XcdRanges& xr,
+                            const uint8_t* live, double* part,
+                            const int32_t* tapsT,
                             const int16_t* aoff, const LevelDev& lvp, const LevelDev& lvs, const LevelDev& lvt,
                             const T* Dst, hipStream_t st) {
   T* tbT = (T*)lvs.tbT;
   hipLaunchKernelGGL((k_adj_tbT<T>), dim3((lvs.nref * 32 + 255) / 256), dim3(256), 0, st, lvs, lvt, tbT);
-  const int items = ntiles * nsplit;
-  const dim3 grid(8 * ((items + 7) / 8)), block(64);
+  if (xr.start[8] != ntiles * nsplit) return hipErrorInvalidValue;
+  const dim3 grid(xr.grid()), block(64);
 #define X(PP) \
-  case PP: hipLaunchKernelGGL((k_adj_m2p_mfma<T, PP>), grid, block, 0, st, tiles, ntiles, nsplit, part, tapsT, aoff, lvp, lvs, (const T*)tbT, Dst); break;
+  case PP: hipLaunchKernelGGL((k_adj_m2p_mfma<T, PP>), grid, block, 0, st, tiles, xr, nsplit, part, tapsT, live, aoff, lvp, lvs, (const T*)tbT, Dst); break;
   AFMM_P_SWITCH(p, X)
 #undef X
   return adj_reduce(p, tiles, ntiles, nsplit, part, lvs, st);
 }
 
-hipError_t launch_adj_m2p_mfma(int p, bool fp32, const int32_t* tiles, int ntiles, int nsplit, double* part,
-                               const int32_t* tapsT, const int16_t* aoff, const LevelDev& lvp, const LevelDev& lvs,
-                               const LevelDev& lvt, const TablesDev<float>& t32, const TablesDev<double>& t64,
-                               hipStream_t st) {
+hipError_t launch_adj_m2p_mfma(int p, bool fp32, const int32_t* tiles, int ntiles, int nsplit, const XcdRanges& xr,
+                               const uint8_t* live, double* part, const int32_t* tapsT, const int16_t* aoff, const LevelDev& lvp,
+                               const LevelDev& lvs, const LevelDev& lvt, const TablesDev<float>& t32,
+                               const TablesDev<double>& t64, hipStream_t st) {
   if (ntiles <= 0 || lvs.nref == 0) return hipSuccess;
-  if (fp32) return adj_m2p_t<float>(p, tiles, ntiles, nsplit, part, tapsT, aoff, lvp, lvs, lvt, t32.Dstage, st);
-  return adj_m2p_t<double>(p, tiles, ntiles, nsplit, part, tapsT, aoff, lvp, lvs, lvt, t64.Dstage, st);
+  if (!live) return hipErrorInvalidValue;
+  if (fp32) return adj_m2p_t<float>(p, tiles, ntiles, nsplit, xr, live, part, tapsT, aoff, lvp, lvs, lvt, t32.Dstage, st);
+  return adj_m2p_t<double>(p, tiles, ntiles, nsplit, xr, live, part, tapsT, aoff, lvp, lvs, lvt, t64.Dstage, st);
 }
 
 template <typename T>
-static hipError_t adj_m2l_t(int p, const int32_t* tiles, int ntiles, int nsplit, double* part, const int32_t* tapsT,
+static hipError_t adj_m2l_t(int p, const int32_t* tiles, int ntiles, int nsplit, const XcdRanges& xr,
+                            const uint8_t* live, double* part,
+                            const int32_t* tapsT,
                             const int16_t* aoff, const LevelDev& lvp, const LevelDev& lvs, const LevelDev& lvt,
                             const T* Dst, hipStream_t st) {
   T* lT = (T*)lvt.lbarT;
@@ -918,22 +1020,23 @@ static hipError_t adj_m2l_t(int p, const int32_t* tiles, int ntiles, int nsplit,
   case PP: hipLaunchKernelGGL((k_adj_lbarT<T, PP>), dim3((rows + 255) / 256), dim3(256), 0, st, lvt, lT); break;
   AFMM_P_SWITCH(p, X)
 #undef X
-  const int items = ntiles * nsplit;
-  const dim3 grid(8 * ((items + 7) / 8)), block(64);
+  if (xr.start[8] != ntiles * nsplit) return hipErrorInvalidValue;
+  const dim3 grid(xr.grid()), block(64);
 #define X(PP) \
-  case PP: hipLaunchKernelGGL((k_adj_m2l_mfma<T, PP>), grid, block, 0, st, tiles, ntiles, nsplit, part, tapsT, aoff, lvp, lvs, lvt, (const T*)lT, Dst); break;
+  case PP: hipLaunchKernelGGL((k_adj_m2l_mfma<T, PP>), grid, block, 0, st, tiles, xr, nsplit, part, tapsT, live, aoff, lvp, lvs, lvt, (const T*)lT, Dst); break;
   AFMM_P_SWITCH(p, X)
 #undef X
   return adj_reduce(p, tiles, ntiles, nsplit, part, lvs, st);
 }
 
-hipError_t launch_adj_m2l_mfma(int p, bool fp32, const int32_t* tiles, int ntiles, int nsplit, double* part,
-                               const int32_t* tapsT, const int16_t* aoff, const LevelDev& lvp, const LevelDev& lvs,
-                               const LevelDev& lvt, const TablesDev<float>& t32, const TablesDev<double>& t64,
-                               hipStream_t st) {
+hipError_t launch_adj_m2l_mfma(int p, bool fp32, const int32_t* tiles, int ntiles, int nsplit, const XcdRanges& xr,
+                               const uint8_t* live, double* part, const int32_t* tapsT, const int16_t* aoff, const LevelDev& lvp,
+                               const LevelDev& lvs, const LevelDev& lvt, const TablesDev<float>& t32,
+                               const TablesDev<double>& t64, hipStream_t st) {
   if (ntiles <= 0 || lvt.nref == 0) return hipSuccess;
-  if (fp32) return adj_m2l_t<float>(p, tiles, ntiles, nsplit, part, tapsT, aoff, lvp, lvs, lvt, t32.Dstage, st);
-  return adj_m2l_t<double>(p, tiles, ntiles, nsplit, part, tapsT, aoff, lvp, lvs, lvt, t64.Dstage, st);
+  if (!live) return hipErrorInvalidValue;
+  if (fp32) return adj_m2l_t<float>(p, tiles, ntiles, nsplit, xr, live, part, tapsT, aoff, lvp, lvs, lvt, t32.Dstage, st);
+  return adj_m2l_t<double>(p, tiles, ntiles, nsplit, xr, live, part, tapsT, aoff, lvp, lvs, lvt, t64.Dstage, st);
 }
 
 #undef AFMM_P_SWITCH

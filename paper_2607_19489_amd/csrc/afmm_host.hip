@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -919,6 +920,11 @@ struct afmm_plan {
   // source tiles of the transposed M2P (index: leaf level l) and M2L (index: FMM level f)
   int32_t* d_adjp[kMaxLevel] = {};
   int32_t* d_adjl[kMaxLevel] = {};
+  // per refined rank at the source level: 1 if the group has a target child
+  // (a leaf child for the M2P, a refined child for the M2L)
+  uint8_t* d_adjp_live[kMaxLevel] = {};
+  uint8_t* d_adjl_live[kMaxLevel] = {};
+  XcdRanges xr_adjp[kMaxLevel], xr_adjl[kMaxLevel];  // their work items per XCD
   int n_adjp[kMaxLevel] = {}, n_adjl[kMaxLevel] = {};
   int s_adjp[kMaxLevel] = {}, s_adjl[kMaxLevel] = {};  // their tap splits
   double* adj_part = nullptr;     // partial sets of the split transposed translations
@@ -2311,19 +2317,29 @@ static afmm_status adjoint_topology(afmm_plan* P) {
   const Topology& T = P->topo;
   afmm_status s;
   // source tiles: the level-ls cells read by some group of `grp` (refined ranks
-  // at ls), 16 per tile, one octant class per tile
-  auto src_tiles = [&](int target, const std::vector<int32_t>& grp, int32_t** dst, int* nt) -> afmm_status {
+  // at ls), 16 per tile in Morton order, one octant class per tile.  For every
+  // tile, the taps (transposed order) whose group has a target child in some
+  // column go to *livetaps (the kernel's own test, for the work estimate).
+  // (Sorting the cells of a class by the side from which their groups lie
+  // leaves more taps without a group in any column of a tile, but the tiles
+  // lose the locality of their B rows, and the kernels ran slower.)
+  using TapBits = std::array<uint64_t, 3>;
+  auto src_tiles = [&](int target, const std::vector<int32_t>& grp, int32_t** dst, int* nt, uint8_t** live,
+                       std::vector<TapBits>* livetaps) -> afmm_status {
     *nt = 0;
+    livetaps->clear();
     if (grp.empty() || target < 3) return AFMM_OK;
     const int ls = target - 1;
     const HostLevel& LS = T.lv[ls];
     const HostLevel& LP = T.lv[ls - 1];
     std::vector<uint8_t> mark(LS.n(), 0);
+    std::vector<uint8_t> flag(LS.nref(), 0);
     for (int32_t F : grp) {
+      flag[F] = 1;
       const int32_t cF = LS.refcell[F];
       const int32_t G = cF >> 3, oF = cF & 7;
-      for (int i = 0; i < 189; ++i) {
-        const int code = P->tabs->taps[oF * 189 + i];
+      for (int i = 0; i < kTapsPerClass; ++i) {
+        const int code = P->tabs->taps[oF * kTapsPerClass + i];
         const int32_t Q = LP.nbr[(size_t)G * 27 + (code & 31)];
         if (Q < 0 || LP.rank[Q] < 0) continue;
         mark[8 * LP.rank[Q] + ((code >> 5) & 7)] = 1;
@@ -2341,19 +2357,63 @@ static afmm_status adjoint_topology(afmm_plan* P) {
         for (int j = 0; j < 16; ++j) rec.push_back(ch * 16 + j < c.size() ? c[ch * 16 + j] : -1);
         ++*nt;
       }
-    return upload(P, rec, dst, nullptr);
+    livetaps->assign(*nt, TapBits{0, 0, 0});
+    for (int t = 0; t < *nt; ++t) {
+      const int32_t* col = &rec[(size_t)t * 17 + 1];
+      const int os = col[0] & 7;
+      for (int j = 0; j < kTapsPerClass; ++j) {
+        const int code = P->tabs->tapsT[os * kTapsPerClass + j];
+        for (int n = 0; n < 16; ++n) {
+          if (col[n] < 0) continue;
+          const int32_t Q = LP.nbr[(size_t)(col[n] >> 3) * 27 + (code & 31)];
+          if (Q < 0 || LP.rank[Q] < 0) continue;
+          const int32_t rF = LS.rank[8 * LP.rank[Q] + ((code >> 5) & 7)];
+          if (rF >= 0 && flag[rF]) {
+            (*livetaps)[t][j >> 6] |= 1ull << (j & 63);
+            break;
+          }
+        }
+      }
+    }
+    afmm_status s2 = upload(P, rec, dst, nullptr);
+    return s2 ? s2 : upload(P, flag, live, nullptr);
   };
+  // XCD ranges of equal estimated work: an item (tile, tap chunk) costs its
+  // live taps plus a fixed setup worth kItemSetupTaps taps.
+  auto xcd_ranges = [](const std::vector<TapBits>& bits, int ns) {
+    constexpr double kItemSetupTaps = 3.0;
+    XcdRanges xr;
+    const int items = (int)bits.size() * ns;
+    std::vector<double> cum(items + 1, 0.0);
+    for (int i = 0; i < items; ++i) {
+      const int t = i / ns, c = i - t * ns;
+      const int lo = c * kTapsPerClass / ns, hi = (c + 1) * kTapsPerClass / ns;
+      int live = 0;
+      for (int j = lo; j < hi; ++j) live += (int)((bits[t][j >> 6] >> (j & 63)) & 1);
+      cum[i + 1] = cum[i] + live + kItemSetupTaps;
+    }
+    for (int x = 0; x <= 8; ++x)
+      xr.start[x] = x == 8 ? items
+                           : (int32_t)(std::lower_bound(cum.begin(), cum.end(), cum[items] * x / 8.0) - cum.begin());
+    for (int x = 1; x <= 8; ++x) xr.start[x] = std::max(xr.start[x], xr.start[x - 1]);
+    return xr;
+  };
+  std::vector<TapBits> bits_p[kMaxLevel], bits_l[kMaxLevel];
   for (int l = 3; l <= T.lmax; ++l)
-    if ((s = src_tiles(l, T.leafgrp[l], &P->d_adjp[l], &P->n_adjp[l]))) return s;
+    if ((s = src_tiles(l, T.leafgrp[l], &P->d_adjp[l], &P->n_adjp[l], &P->d_adjp_live[l], &bits_p[l]))) return s;
   for (int f = 3; f <= T.lmax - 1; ++f)
-    if ((s = src_tiles(f, T.m2lgrp[f], &P->d_adjl[f], &P->n_adjl[f]))) return s;
-  // tap splits of the transposed translations: about 12 waves per CU
+    if ((s = src_tiles(f, T.m2lgrp[f], &P->d_adjl[f], &P->n_adjl[f], &P->d_adjl_live[f], &bits_l[f]))) return s;
+  // tap splits of the transposed translations: about 24 work items per CU, so
+  // that the items left after the first wave of workgroups even out the CUs
+  // (tiles differ in their number of live taps)
   const int ncu = device_cu_count();
-  auto split_of = [&](int nt) { return nt > 0 ? std::max(1, std::min(16, (12 * ncu + nt - 1) / nt)) : 1; };
+  auto split_of = [&](int nt) { return nt > 0 ? std::max(1, std::min(16, (24 * ncu + nt - 1) / nt)) : 1; };
   P->adj_part_elems = 0;
   for (int l = 0; l < kMaxLevel; ++l) {
     P->s_adjp[l] = split_of(P->n_adjp[l]);
     P->s_adjl[l] = split_of(P->n_adjl[l]);
+    P->xr_adjp[l] = xcd_ranges(bits_p[l], P->s_adjp[l]);
+    P->xr_adjl[l] = xcd_ranges(bits_l[l], P->s_adjl[l]);
     if (P->s_adjp[l] > 1) P->adj_part_elems = std::max(P->adj_part_elems, (size_t)P->s_adjp[l] * P->n_adjp[l] * 16 * P->K);
     if (P->s_adjl[l] > 1) P->adj_part_elems = std::max(P->adj_part_elems, (size_t)P->s_adjl[l] * P->n_adjl[l] * 16 * P->K);
   }
@@ -2474,7 +2534,8 @@ static afmm_status run_adjoint(afmm_plan* P, int32_t level, const double* d_phi_
   const int f64 = mixed ? P->opt.fp64_levels : 1 << 20;
   for (int l = std::max(3, lo); l <= hi; ++l) {
     if ((s = dev_check(P,
-                       launch_adj_m2p_mfma(p, mixed && (l - 1) > f64, P->d_adjp[l], P->n_adjp[l], P->s_adjp[l], part,
+                       launch_adj_m2p_mfma(p, mixed && (l - 1) > f64, P->d_adjp[l], P->n_adjp[l], P->s_adjp[l],
+                                           P->xr_adjp[l], P->d_adjp_live[l], part,
                                            P->cm.tapsT, P->cm.adj_m2p_off, lw[l - 2], lw[l - 1], lw[l], P->t32, P->t64,
                                            st),
                        "adjoint m2p")))
@@ -2496,7 +2557,8 @@ static afmm_status run_adjoint(afmm_plan* P, int32_t level, const double* d_phi_
   ev = prof_begin(P, st);
   for (int f = 3; f <= fmax; ++f) {
     if ((s = dev_check(P,
-                       launch_adj_m2l_mfma(p, mixed && f > f64, P->d_adjl[f], P->n_adjl[f], P->s_adjl[f], part,
+                       launch_adj_m2l_mfma(p, mixed && f > f64, P->d_adjl[f], P->n_adjl[f], P->s_adjl[f],
+                                           P->xr_adjl[f], P->d_adjl_live[f], part,
                                            P->cm.tapsT, P->cm.adj_m2l_off, lw[f - 2], lw[f - 1], lw[f], P->t32, P->t64,
                                            st),
                        "adjoint m2l")))
@@ -2508,7 +2570,11 @@ static afmm_status run_adjoint(afmm_plan* P, int32_t level, const double* d_phi_
   ev = prof_begin(P, st);
   // 6. source-copy bars -> multipole bars, M2M^T coarse to fine
   for (int f = 2; f <= lmax - 1; ++f)
-    if ((s = dev_check(P, launch_adj_down(p, lw[f - 1], lw[f], f >= 3, P->cm, st), "adjoint down"))) return s;
+    if ((s = dev_check(P,
+                       launch_adj_down(p, P->d_upmix[f - 1], (int)T.upmix[f - 1].size(), lw[f - 1], lw[f], f >= 3,
+                                       P->cm, st),
+                       "adjoint down")))
+      return s;
   // 7. mass bars to the caller's slots (levels whose masses came from the last call)
   for (int l = lmin; l <= lmax; ++l) {
     const bool has_parent = l - 1 >= 2 && l - 1 <= lmax - 1;

@@ -86,6 +86,24 @@ constexpr int kNearCoarseCols = 27;
 __host__ __device__ constexpr int near_cols(int p) { return (kNearLeafCols + kNearCoarseCols + nmi(p) + 15) / 16 * 16; }
 __host__ __device__ constexpr int near_ksteps(int p) { return near_cols(p) / 4; }
 
+// Interaction-list taps per octant class: the children of the father's 27
+// neighbours (216) less the cell's own 27 neighbours.
+constexpr int kTapsPerClass = 189;
+
+// Work items of one launch split into 8 contiguous ranges, one per XCD (the
+// hardware deals workgroups to the XCDs round-robin): workgroup b runs item
+// start[b % 8] + b / 8 if that is below start[b % 8 + 1].  Ranges of equal
+// estimated work rather than equal length keep every XCD busy when the work
+// per item varies; each XCD still reads a contiguous run of tiles.
+struct XcdRanges {
+  int32_t start[9] = {};
+  int32_t grid() const {
+    int32_t m = 0;
+    for (int x = 0; x < 8; ++x) m = start[x + 1] - start[x] > m ? start[x + 1] - start[x] : m;
+    return 8 * m;
+  }
+};
+
 // Per-level device view.  Level l holds the children of the refined cells of
 // level l - 1 in Morton order, so cell index c has father refined rank c >> 3
 // and octant c & 7 (o = ox + 2 oy + 4 oz), and refined rank r owns children
@@ -205,18 +223,20 @@ hipError_t launch_adj_l2p(int p, const int32_t* grp, int ngrp, const LevelDev& l
 // MFMA forms: tiles of 16 source cells (records: target level, 16 cells); with
 // nsplit > 1 the 189 taps of a tile are split over blocks writing partial sets
 // into `part` ([nsplit][ntiles * 16][K] FP64), summed in order afterwards.
-hipError_t launch_adj_m2p_mfma(int p, bool fp32, const int32_t* tiles, int ntiles, int nsplit, double* part,
+hipError_t launch_adj_m2p_mfma(int p, bool fp32, const int32_t* tiles, int ntiles, int nsplit, const XcdRanges& xr,
+                               const uint8_t* live, double* part,
                                const int32_t* tapsT, const int16_t* aoff, const LevelDev& lvp, const LevelDev& lvs,
                                const LevelDev& lvt, const TablesDev<float>& t32, const TablesDev<double>& t64,
                                hipStream_t st);
-hipError_t launch_adj_m2l_mfma(int p, bool fp32, const int32_t* tiles, int ntiles, int nsplit, double* part,
+hipError_t launch_adj_m2l_mfma(int p, bool fp32, const int32_t* tiles, int ntiles, int nsplit, const XcdRanges& xr,
+                               const uint8_t* live, double* part,
                                const int32_t* tapsT, const int16_t* aoff, const LevelDev& lvp, const LevelDev& lvs,
                                const LevelDev& lvt, const TablesDev<float>& t32, const TablesDev<double>& t64,
                                hipStream_t st);
 hipError_t launch_adj_l2l(int p, const int32_t* grp, int ngrp, const LevelDev& lv1, const LevelDev& lv0,
                           const TablesDev<double>& t64, const CommonDev& cm, hipStream_t st);
-hipError_t launch_adj_down(int p, const LevelDev& lv1, const LevelDev& lv0, int has_parent, const CommonDev& cm,
-                           hipStream_t st);
+hipError_t launch_adj_down(int p, const int32_t* grp, int ngrp, const LevelDev& lv1, const LevelDev& lv0,
+                           int has_parent, const CommonDev& cm, hipStream_t st);
 // Mass bars to the caller's slots; cself (the self-potential constant, 0 when
 // off) adds the transpose of the self term -cself m of the unit-form potential.
 hipError_t launch_adj_out(int p, const LevelDev& lv1, const LevelDev& lv0, int has_parent, int rebuilt,

@@ -70,6 +70,11 @@ def lib():
         L.oracle_set_options.argtypes = [P, C.c_int, C.c_int]
         L.oracle_self_constant.argtypes = []
         L.oracle_self_constant.restype = C.c_double
+        L.oracle_set_periodic.argtypes = [P, C.c_int]
+        L.oracle_lattice.argtypes = [C.c_int, C.c_double, C.c_double, dp]
+        L.oracle_lattice_at.argtypes = [C.c_int, C.c_double, C.c_double, dp, dp]
+        L.oracle_direct_periodic.argtypes = [C.c_int64, dp, dp, C.c_int64, dp, C.c_double, C.c_double,
+                                             C.c_double, dp, dp]
         _lib = L
     return _lib
 
@@ -148,6 +153,35 @@ def direct(xs, ms, xt, G: float = 1.0):
     return phi, acc.reshape(-1, 3)
 
 
+def direct_periodic(xs, ms, xt, G: float = 1.0, boxlen: float = 1.0, alpha: Optional[float] = None):
+    """Ewald sum on the periodic box with a neutralising background (zero-mean
+    potential); a source at a target's own position adds its images and the
+    background only.  ``alpha`` is the split parameter (default 2.5 / boxlen)."""
+    xs = np.ascontiguousarray(xs, dtype=np.float64).reshape(-1, 3)
+    xt = np.ascontiguousarray(xt, dtype=np.float64).reshape(-1, 3)
+    ms = np.ascontiguousarray(ms, dtype=np.float64)
+    phi = np.zeros(xt.shape[0])
+    acc = np.zeros(3 * xt.shape[0])
+    al = 2.5 / boxlen if alpha is None else alpha
+    _check(lib().oracle_direct_periodic(xs.shape[0], xs.ravel(), ms, xt.shape[0], xt.ravel(), G, boxlen, al,
+                                        phi, acc), "direct_periodic")
+    return phi, acc.reshape(-1, 3)
+
+
+def lattice(n: int, boxlen: float = 1.0, alpha: Optional[float] = None, at=None) -> np.ndarray:
+    """Lattice tensors D^lat_g (|g| <= n, the oracle's multi-index order): derivatives
+    at ``at`` (default 0) of minus (the Ewald sum less the 27 nearest images of
+    1/r); ``alpha`` defaults to 1.8 / boxlen, the value the periodic FMM uses."""
+    out = np.zeros(nmi(n))
+    al = 1.8 / boxlen if alpha is None else alpha
+    if at is None:
+        _check(lib().oracle_lattice(n, boxlen, al, out), "lattice")
+    else:
+        d = np.ascontiguousarray(at, dtype=np.float64).reshape(3)
+        _check(lib().oracle_lattice_at(n, boxlen, al, d, out), "lattice_at")
+    return out
+
+
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
 
@@ -160,7 +194,8 @@ def self_constant() -> float:
 class Oracle:
     """Literal per-level-tree FMM on one hierarchy (see ``afmm_oracle.c``)."""
 
-    def __init__(self, h, p: int, G: float = 1.0, quad_cap: bool = False, self_potential: bool = False):
+    def __init__(self, h, p: int, G: float = 1.0, quad_cap: bool = False, self_potential: bool = False,
+                 periodic: bool = False):
         self.h = h
         self.p = p
         self.G = G
@@ -172,6 +207,9 @@ class Oracle:
                                    C.byref(self._ptr)), "create")
         # the paper's multipole cap (order p - 1) and the optional self-potential term
         _check(lib().oracle_set_options(self._ptr, int(bool(quad_cap)), int(bool(self_potential))), "set_options")
+        # periodic box with a neutralising background (an extension of the paper's isolated box)
+        if periodic:
+            _check(lib().oracle_set_periodic(self._ptr, 1), "set_periodic")
         self.N = h.total
         self.offsets = h.offsets
 

@@ -37,6 +37,20 @@
  * L = 0 on FMM level 1; isolated box, lists clipped to [0, boxlen)^3; no
  * self-interaction; only leaves are targets.
  *
+ * Periodic boundaries (an extension: Sec. 5 names periodic domains as future
+ * work; readings in the design notes).  The box is a torus and the potential
+ * that of the masses with a uniform neutralising background, zero on average
+ * (the Ewald sum, oracle_direct_periodic).  The FMM then wraps every cell
+ * lookup (images of cells in the 3^3 block of boxes around the box).  What the
+ * levels >= 3 do not take (every image beyond that block, and the images of
+ * level-2 cells whose level-1 father image does not touch the target's level-1
+ * ancestor) enters the local expansions of FMM level 2 from all 64 level-2
+ * cells, L_b(y) = sum_s sum_a (-1)^|a|/a! T_{a+b} M_a(s), with
+ * T = D^lat(c_y - c_s) + sum of D(c_y - c_s - nL) over those block images n;
+ * D^lat_g(d) = d^g(-F)(d), F = Ewald sum minus the 27 nearest images
+ * (oracle_lattice).  Between level-2 cells these expansions converge much
+ * faster than at the root or from level-1 sources.
+ *
  * Derivatives D_g = d^g(-1/r) are evaluated from exact integer polynomials:
  * d^g (1/r) = P_g(x) / r^(2|g|+1) with P_{g+e_i} = r^2 dP_g/dx_i - (2|g|+1) x_i P_g.
  */
@@ -203,6 +217,25 @@ static void op_m2l(int p, int pm, const double R[3], const double *M, double *L,
   }
 }
 
+/* The lattice images at the root: Eq. eq:M2L with the lattice tensors in place
+   of D_{a+b}(R). */
+static void op_lattice(int p, int pm, const double *lat, const double *M, double *L) {
+  int K = nmi_of(p);
+  for (int b = 0; b < K; ++b) {
+    const int *bb = g_mi[b];
+    int nb = bb[0] + bb[1] + bb[2];
+    double sum = 0.0;
+    for (int a = 0; a < K; ++a) {
+      const int *aa = g_mi[a];
+      int na = aa[0] + aa[1] + aa[2];
+      if (na + nb > p || na > pm) continue;
+      double sg = (na & 1) ? -1.0 : 1.0;
+      sum += sg / mfact(aa) * lat[g_idx[aa[0] + bb[0]][aa[1] + bb[1]][aa[2] + bb[2]]] * M[a];
+    }
+    L[b] += sum;
+  }
+}
+
 /* Eq. eq:L2L: L'_b = sum_{|g| <= p-|b|} a^g / g! L_{b+g}, a = new centre - old centre */
 static void op_l2l(int p, const double a[3], const double *L, double *Lout) {
   int K = nmi_of(p);
@@ -362,6 +395,8 @@ typedef struct oracle_state {
   hmap cellmap[MAXLEV];    /* level -> key -> flat index (AMR levels only) */
   tree_t tree[MAXLEV];
   int merged_all;          /* evaluate with per-source sums over all trees (pin P10) */
+  int periodic;            /* torus box with a neutralising background */
+  double *lat;             /* [8][7^3][K] level-2 far operators by target octant and offset (periodic) */
 } oracle_state;
 
 static double csize(const oracle_state *s, int lev) { return s->boxlen / (double)(1LL << lev); }
@@ -374,8 +409,14 @@ static void centre(const oracle_state *s, int lev, const int64_t c[3], double x[
 #define CELL_OUT (-2)
 #define CELL_ABSENT (-1)
 #define CELL_VIRTUAL (-3)
-static int64_t cell_lookup(const oracle_state *s, int lev, const int64_t c[3]) {
+/* periodic boxes: the cell of the torus that c (any integer coordinates) lands on */
+static void wrap3(const oracle_state *s, int lev, const int64_t c[3], int64_t w[3]) {
   int64_t n = 1LL << lev;
+  for (int k = 0; k < 3; ++k) w[k] = s->periodic ? ((c[k] % n) + n) % n : c[k];
+}
+static int64_t cell_lookup(const oracle_state *s, int lev, const int64_t c0[3]) {
+  int64_t n = 1LL << lev, c[3];
+  wrap3(s, lev, c0, c);
   for (int k = 0; k < 3; ++k)
     if (c[k] < 0 || c[k] >= n) return CELL_OUT;
   if (lev < s->levelmin) return CELL_VIRTUAL;
@@ -408,8 +449,25 @@ void oracle_destroy(oracle_state *s) {
     tree_free(s, l);
     hm_free(&s->cellmap[l]);
   }
-  free(s->ijk); free(s->refined);
+  free(s->ijk); free(s->refined); free(s->lat);
   free(s);
+}
+
+/* strong grading: a refined level-l cell needs the 27 neighbours of its father
+   refined (clipped to the box, or wrapped around a periodic one) */
+static int check_grading(const oracle_state *s) {
+  for (int l = s->levelmin + 1; l <= s->levelmax; ++l)
+    for (int64_t i = s->off[l]; i < s->off[l + 1]; ++i) {
+      if (!s->refined[i]) continue;
+      const int32_t *c = &s->ijk[3 * i];
+      for (int e = 0; e < 27; ++e) {
+        int64_t q[3] = {c[0] / 2 + e % 3 - 1, c[1] / 2 + (e / 3) % 3 - 1, c[2] / 2 + e / 9 - 1};
+        int64_t qi = cell_lookup(s, l - 1, q);
+        if (qi == CELL_OUT) continue;
+        if (!is_refined_cell(s, qi)) return OR_E_NOT_GRADED;
+      }
+    }
+  return OR_OK;
 }
 
 /* Build the AMR cell maps and check completeness and the strong grading rule. */
@@ -462,19 +520,7 @@ int oracle_create(int levelmin, int levelmax, const int64_t *ncell, const int32_
     }
     if (rc == OR_OK && l < levelmax && s->ncell[l + 1] != 8 * nref) rc = OR_E_INCOMPLETE;
   }
-  /* strong grading: a refined level-l cell needs the 27 neighbours of its father refined */
-  for (int l = levelmin + 1; l <= levelmax && rc == OR_OK; ++l) {
-    for (int64_t i = s->off[l]; i < s->off[l + 1] && rc == OR_OK; ++i) {
-      if (!s->refined[i]) continue;
-      const int32_t *c = &s->ijk[3 * i];
-      for (int e = 0; e < 27; ++e) {
-        int64_t q[3] = {c[0] / 2 + e % 3 - 1, c[1] / 2 + (e / 3) % 3 - 1, c[2] / 2 + e / 9 - 1};
-        int64_t qi = cell_lookup(s, l - 1, q);
-        if (qi == CELL_OUT) continue;
-        if (!is_refined_cell(s, qi)) { rc = OR_E_NOT_GRADED; break; }
-      }
-    }
-  }
+  if (rc == OR_OK) rc = check_grading(s);
   if (rc != OR_OK) { oracle_destroy(s); return rc; }
   *out = s;
   return OR_OK;
@@ -673,7 +719,7 @@ static int foreach_il(const oracle_state *s, int f, const int64_t y[3], src_cb c
   int64_t Gc[3] = {F[0] >> 1, F[1] >> 1, F[2] >> 1};
   for (int e = 0; e < 27; ++e) {
     int64_t Q[3] = {Gc[0] + e % 3 - 1, Gc[1] + (e / 3) % 3 - 1, Gc[2] + e / 9 - 1};
-    if (f - 2 >= 0) {
+    if (f - 2 >= 0 && !s->periodic) {
       int64_t nq = 1LL << (f - 2);
       if (Q[0] < 0 || Q[0] >= nq || Q[1] < 0 || Q[1] >= nq || Q[2] < 0 || Q[2] >= nq) continue;
     }
@@ -700,12 +746,14 @@ typedef struct {
   int f;        /* target FMM level */
 } m2l_u;
 
-static void m2l_src(void *uu, int lev, const int64_t sc[3], int64_t idx) {
+static void m2l_src(void *uu, int lev, const int64_t sc0[3], int64_t idx) {
   m2l_u *u = (m2l_u *)uu;
   const oracle_state *s = u->s;
   int K = s->K, l = u->c->l;
   double cs[3], R[3];
-  centre(s, lev, sc, cs);
+  int64_t sc[3];
+  centre(s, lev, sc0, cs);      /* the image's own position */
+  wrap3(s, lev, sc0, sc);       /* the cell it is an image of */
   for (int k = 0; k < 3; ++k) R[k] = u->cy[k] - cs[k];
   if (s->merged_all) {
     /* one source multipole: sum over every tree (and the leaf mass) */
@@ -746,12 +794,14 @@ typedef struct {
 } m2p_u;
 
 /* intermediate field of a level-l target: one level-(l-1) source of its list */
-static void m2p_src(void *uu, int lev, const int64_t sc[3], int64_t idx) {
+static void m2p_src(void *uu, int lev, const int64_t sc0[3], int64_t idx) {
   m2p_u *u = (m2p_u *)uu;
   const oracle_state *s = u->s;
   int K = s->K, l = u->c->l;
   double cs[3], R[3];
-  centre(s, lev, sc, cs);
+  int64_t sc[3];
+  centre(s, lev, sc0, cs);
+  wrap3(s, lev, sc0, sc);
   for (int k = 0; k < 3; ++k) R[k] = u->x[k] - cs[k];
   if (idx >= 0 && !s->refined[idx]) {          /* level-(l-1) leaf: P2P (brown dots) */
     op_p2p(R, leafmass_of(s, lev, idx), &u->phi, u->acc);
@@ -790,7 +840,7 @@ static int eval_leaf(const oracle_state *s, const evalctx *c, int64_t flat, doub
   int64_t F[3] = {cc[0] >> 1, cc[1] >> 1, cc[2] >> 1};
   double p_far = 0, a_far[3] = {0, 0, 0};
   /* far field: ShiftLocal of L_{l;l-1} to the cell */
-  if (l - 1 >= 2) {
+  if (l - 1 >= (s->periodic ? 0 : 2)) {
     const double *L = grid_row(&c->Lg[l - 1], F, K);
     if (!L) return OR_E_STATE;
     double cF[3], u[3];
@@ -842,7 +892,9 @@ static int eval_leaf(const oracle_state *s, const evalctx *c, int64_t flat, doub
           op_p2p(Rk, leafmass_of(s, l + 1, ki), &p_nst, a_nst);
         }
       } else {                                        /* M2P from ~T_{l+1;l} */
-        const double *M = s->merged_all ? grid_row(&c->all[l], n3, K) : grid_row(&c->mrg[l], n3, K);
+        int64_t w3[3];
+        wrap3(s, l, n3, w3);
+        const double *M = s->merged_all ? grid_row(&c->all[l], w3, K) : grid_row(&c->mrg[l], w3, K);
         if (!M) return OR_E_STATE;
         op_m2p(s->p, s->pm, R, M, &p_near, a_near);
       }
@@ -861,6 +913,35 @@ static int eval_leaf(const oracle_state *s, const evalctx *c, int64_t flat, doub
     }
   }
   return OR_OK;
+}
+
+/* Periodic boxes: the level-2 far operator, from every level-2 cell s
+   (multipoles of the same trees as M2L reads) into the level-2 target y. */
+static void lattice_m2l(const oracle_state *s, const evalctx *c, const int64_t y[3], double *L) {
+  int K = s->K, l = c->l;
+  for (int64_t a = 0; a < 4; ++a)
+    for (int64_t b = 0; b < 4; ++b)
+      for (int64_t d = 0; d < 4; ++d) {
+        const int64_t sc[3] = {a, b, d};
+        double M[NMI];
+        memset(M, 0, sizeof(double) * K);
+        if (s->merged_all) {
+          const double *A = grid_row(&c->all[2], sc, K);
+          if (A) for (int q = 0; q < K; ++q) M[q] += A[q];
+        } else {
+          for (int j = s->levelmin; j <= l; ++j) {
+            const double *A = grid_row(&s->tree[j].g[2], sc, K);
+            if (A) for (int q = 0; q < K; ++q) M[q] += A[q];
+          }
+          if (l < s->levelmax) {
+            const double *A = grid_row(&c->mrg[2], sc, K);
+            if (A) for (int q = 0; q < K; ++q) M[q] += A[q];
+          }
+        }
+        int di = (int)((a - y[0] + 3) + 7 * (b - y[1] + 3) + 49 * (d - y[2] + 3));
+        int oy = (int)((y[0] & 1) | (y[1] & 1) << 1 | (y[2] & 1) << 2);
+        op_lattice(s->p, s->pm, &s->lat[((size_t)oy * 343 + di) * K], M, L);
+      }
 }
 
 /*
@@ -910,6 +991,7 @@ int oracle_eval(oracle_state *s, int l, int64_t ntarget, const int64_t *targets,
       int64_t y[3];
       unkey3(g->keys[r], y);
       double *L = &g->coef[r * K];
+      if (f == 2 && s->periodic) lattice_m2l(s, c, y, L);
       if (f - 1 >= 2) {
         int64_t Fc[3] = {y[0] >> 1, y[1] >> 1, y[2] >> 1};
         const double *LF = grid_row(&c->Lg[f - 1], Fc, K);
@@ -922,7 +1004,8 @@ int oracle_eval(oracle_state *s, int l, int64_t ntarget, const int64_t *targets,
       m2l_u u;
       u.s = s; u.c = c; u.L = L; u.f = f;
       centre(s, f, y, u.cy);
-      int e2 = foreach_il(s, f, y, m2l_src, &u);
+      /* periodic: the level-1 sources of level 2 are part of the level-2 far operator */
+      int e2 = (f == 2 && s->periodic) ? OR_OK : foreach_il(s, f, y, m2l_src, &u);
       if (e2) {
 #pragma omp critical
         err = e2;
@@ -1020,6 +1103,223 @@ int oracle_direct(int64_t nsrc, const double *xs, const double *ms, int64_t ntgt
     for (int k = 0; k < 3; ++k) acc[3 * t + k] = G * a[k];
   }
   return OR_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* periodic boxes: Ewald sums                                          */
+/* ------------------------------------------------------------------ */
+/*
+ * Potential of unit masses on the lattice x + n L (all integer n) with a
+ * uniform neutralising background, zero on average over the box (Ewald):
+ *   Psi(r) = sum_n erfc(al |r + nL|)/|r + nL|
+ *          + 4 pi / L^3 sum_{k != 0} exp(-k^2 / (4 al^2)) / k^2 cos(k.r) - pi / (al^2 L^3),
+ * k = 2 pi m / L.  The split parameter al changes nothing in exact arithmetic.
+ *
+ * Cartesian derivatives of a radial function h(|x|) follow from its iterated
+ * radial derivatives h_m = ((1/rho) d/drho)^m h: with R_0^(m) = h_m,
+ * R_{g+e_i}^(m) = x_i R_g^(m+1) + g_i R_{g-e_i}^(m+1), and d^g h = R_g^(0).
+ */
+#define OR_PI 3.14159265358979323846
+/* ranges for 2 <= al L <= 3: every term left out is below 1e-18 of the kept ones */
+#define EW_NREAL 4   /* lattice tensors (derivatives to order 10): images |n_i| <= 4 */
+#define EW_NRECIP 10 /*   and reciprocal vectors |m_i| <= 10 */
+#define EW_NREAL_D 3 /* direct sums (potential and force): images |n_i| <= 3 */
+#define EW_NRECIP_D 6 /*   and reciprocal vectors |m_i| <= 6 */
+
+/* h_m of h = erfc(al rho)/rho (sg = +1) or erf(al rho)/rho (sg = -1), rho > 0, m <= n */
+static void radial_erfc(int n, double rho, double al, int sg, double *hm) {
+  double r2 = rho * rho;
+  double B = erfc(al * rho) / rho, inv = 1.0 / rho, odd = 1.0;   /* odd = (2m-1)!! */
+  double t = exp(-al * al * r2) * 2.0 * al / sqrt(OR_PI);         /* (2 al^2)^(m-1) 2 al/sqrt(pi) e^{-al^2 rho^2} */
+  for (int m = 0; m <= n; ++m) {
+    /* ((1/rho) d/drho)^m erfc(al rho)/rho = (-1)^m B_m,
+       B_m = ((2m - 1) B_{m-1} + (2 al^2)^(m-1) 2 al/sqrt(pi) e^{-al^2 rho^2}) / rho^2 */
+    if (m > 0) {
+      B = ((2.0 * m - 1.0) * B + t) / r2;
+      t *= 2.0 * al * al;
+      odd *= (2.0 * m - 1.0);
+      inv /= r2;
+    }
+    const double sgm = (m & 1) ? -1.0 : 1.0;
+    hm[m] = sg > 0 ? sgm * B : sgm * (odd * inv - B);   /* erf = 1 - erfc; (1/rho)' chain gives (2m-1)!!/rho^(2m+1) */
+  }
+}
+
+/* all d^g h at x for |g| <= n from hm[0..n] */
+static void radial_tensor(int n, const double x[3], const double *hm, double *out) {
+  int K = nmi_of(n);
+  double *R = (double *)malloc(sizeof(double) * (size_t)(n + 1) * K);
+#define RR(m, g) R[(size_t)(m) * K + (g)]
+  for (int g = 0; g < K; ++g) {
+    const int *gg = g_mi[g];
+    int d = gg[0] + gg[1] + gg[2];
+    for (int m = 0; m + d <= n; ++m) {
+      if (d == 0) { RR(m, g) = hm[m]; continue; }
+      int i = gg[0] > 0 ? 0 : (gg[1] > 0 ? 1 : 2);
+      int q[3] = {gg[0], gg[1], gg[2]};
+      q[i] -= 1;                               /* g = q + e_i */
+      double v = x[i] * RR(m + 1, g_idx[q[0]][q[1]][q[2]]);
+      if (q[i] > 0) {
+        int w[3] = {q[0], q[1], q[2]};
+        w[i] -= 1;
+        v += q[i] * RR(m + 1, g_idx[w[0]][w[1]][w[2]]);
+      }
+      RR(m, g) = v;
+    }
+  }
+  for (int g = 0; g < K; ++g) out[g] = RR(0, g);
+#undef RR
+  free(R);
+}
+
+/* d^g of Psi(r) - sum over the 27 images n in {-1,0,1}^3 of 1/|r + nL| at r = d
+   (|d_i| < L), |g| <= n, negated: D^lat_g(d) in the convention D_g = d^g(-1/r). */
+int oracle_lattice_at(int n, double L, double al, const double d[3], double *out) {
+  init_tables();
+  if (n < 0 || n > PMAX || !(L > 0) || !(al > 0)) return OR_E_INVALID;
+  for (int k = 0; k < 3; ++k)
+    if (!(fabs(d[k]) < L)) return OR_E_INVALID;
+  int K = nmi_of(n);
+  double *acc = (double *)calloc(K, sizeof(double)), *t = (double *)malloc(sizeof(double) * K);
+  double hm[PMAX + 2];
+  for (int a = -EW_NREAL; a <= EW_NREAL; ++a)
+    for (int b = -EW_NREAL; b <= EW_NREAL; ++b)
+      for (int c = -EW_NREAL; c <= EW_NREAL; ++c) {
+        int near = abs(a) <= 1 && abs(b) <= 1 && abs(c) <= 1;
+        double x[3] = {d[0] + a * L, d[1] + b * L, d[2] + c * L};
+        double rho = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+        if (rho == 0.0) {
+          /* -erf(al rho)/rho at rho -> 0: h_m(0) = 2 al/sqrt(pi) (-1)^m (2 al^2)^m / (2m + 1) */
+          for (int m = 0; m <= n; ++m)
+            hm[m] = -2.0 * al / sqrt(OR_PI) * ((m & 1) ? -1.0 : 1.0) * pow(2.0 * al * al, m) / (2.0 * m + 1.0);
+        } else {
+          radial_erfc(n, rho, al, near ? -1 : +1, hm);
+          if (near)
+            for (int m = 0; m <= n; ++m) hm[m] = -hm[m];
+        }
+        radial_tensor(n, x, hm, t);
+        for (int g = 0; g < K; ++g) acc[g] += t[g];
+      }
+  /* reciprocal space: d^g cos(k.r) at r = d is Re(i^|g| k^g e^{i k.d}) */
+  const double pref = 4.0 * OR_PI / (L * L * L);
+  for (int a = -EW_NRECIP; a <= EW_NRECIP; ++a)
+    for (int b = -EW_NRECIP; b <= EW_NRECIP; ++b)
+      for (int c = -EW_NRECIP; c <= EW_NRECIP; ++c) {
+        if (a == 0 && b == 0 && c == 0) continue;
+        double k[3] = {2.0 * OR_PI * a / L, 2.0 * OR_PI * b / L, 2.0 * OR_PI * c / L};
+        double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+        double w = pref * exp(-k2 / (4.0 * al * al)) / k2, kd = k[0] * d[0] + k[1] * d[1] + k[2] * d[2];
+        double cs = cos(kd), sn = sin(kd);
+        for (int g = 0; g < K; ++g) {
+          int dg = g_mi[g][0] + g_mi[g][1] + g_mi[g][2];
+          double ph = (dg & 3) == 0 ? cs : (dg & 3) == 1 ? -sn : (dg & 3) == 2 ? -cs : sn;
+          acc[g] += w * ph * mono(g_mi[g], k);
+        }
+      }
+  acc[0] -= OR_PI / (al * al * L * L * L);
+  for (int g = 0; g < K; ++g) out[g] = -acc[g];
+  free(acc); free(t);
+  return OR_OK;
+}
+
+int oracle_lattice(int n, double L, double al, double *out) {
+  const double zero[3] = {0.0, 0.0, 0.0};
+  return oracle_lattice_at(n, L, al, zero, out);
+}
+
+/* Periodic direct sum: phi = -G sum_j m_j Psi(x_t - x_j) (a source at the target's
+   own position contributes its images and the background: Psi minus 1/r at 0),
+   a = -grad phi. */
+int oracle_direct_periodic(int64_t nsrc, const double *xs, const double *ms, int64_t ntgt, const double *xt,
+                           double G, double L, double al, double *phi, double *acc) {
+  init_tables();
+  if (!(L > 0) || !(al > 0)) return OR_E_INVALID;
+  const double pref = 4.0 * OR_PI / (L * L * L);
+#pragma omp parallel for schedule(static)
+  for (int64_t t = 0; t < ntgt; ++t) {
+    double ps = 0, a[3] = {0, 0, 0};   /* Psi and grad Psi summed over sources, times m */
+    for (int64_t i = 0; i < nsrc; ++i) {
+      double r[3] = {xt[3 * t] - xs[3 * i], xt[3 * t + 1] - xs[3 * i + 1], xt[3 * t + 2] - xs[3 * i + 2]};
+      double m = ms[i], pv = 0, gv[3] = {0, 0, 0};
+      for (int na = -EW_NREAL_D; na <= EW_NREAL_D; ++na)
+        for (int nb = -EW_NREAL_D; nb <= EW_NREAL_D; ++nb)
+          for (int nc = -EW_NREAL_D; nc <= EW_NREAL_D; ++nc) {
+            double x[3] = {r[0] + na * L, r[1] + nb * L, r[2] + nc * L};
+            double rho2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+            if (rho2 == 0.0) {
+              pv -= 2.0 * al / sqrt(OR_PI);   /* erfc(al rho)/rho - 1/rho at rho -> 0 */
+              continue;
+            }
+            double rho = sqrt(rho2), ec = erfc(al * rho) / rho;
+            pv += ec;
+            /* d/drho (erfc(al rho)/rho) / rho */
+            double d1 = -(ec + 2.0 * al / sqrt(OR_PI) * exp(-al * al * rho2)) / rho2;
+            for (int k = 0; k < 3; ++k) gv[k] += d1 * x[k];
+          }
+      for (int ma = -EW_NRECIP_D; ma <= EW_NRECIP_D; ++ma)
+        for (int mb = -EW_NRECIP_D; mb <= EW_NRECIP_D; ++mb)
+          for (int mc = -EW_NRECIP_D; mc <= EW_NRECIP_D; ++mc) {
+            if (ma == 0 && mb == 0 && mc == 0) continue;
+            double k[3] = {2.0 * OR_PI * ma / L, 2.0 * OR_PI * mb / L, 2.0 * OR_PI * mc / L};
+            double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+            double w = pref * exp(-k2 / (4.0 * al * al)) / k2, kr = k[0] * r[0] + k[1] * r[1] + k[2] * r[2];
+            pv += w * cos(kr);
+            for (int q = 0; q < 3; ++q) gv[q] -= w * sin(kr) * k[q];
+          }
+      pv -= OR_PI / (al * al * L * L * L);
+      ps += m * pv;
+      for (int k = 0; k < 3; ++k) a[k] += m * gv[k];
+    }
+    phi[t] = -G * ps;
+    for (int k = 0; k < 3; ++k) acc[3 * t + k] = G * a[k];   /* a = -grad(-G Psi) = G grad Psi */
+  }
+  return OR_OK;
+}
+
+/* Periodic boxes for the FMM: needs levelmin >= 3 (the intermediate field of
+   the coarsest leaves then reads level 2), re-checks the grading on the torus
+   and fills the level-2 far operators (8 target octants x 7^3 offsets). */
+int oracle_set_periodic(oracle_state *s, int on) {
+  if (!s) return OR_E_INVALID;
+  if (!on) { s->periodic = 0; return OR_OK; }
+  if (s->levelmin < 3) return OR_E_UNSUPPORTED;
+  s->periodic = 1;
+  int rc = check_grading(s);
+  if (rc) { s->periodic = 0; return rc; }
+  free(s->lat);
+  int K = s->K;
+  s->lat = (double *)malloc(sizeof(double) * 8 * 343 * (size_t)K);
+  double *D = (double *)malloc(sizeof(double) * K), *Dl = (double *)malloc(sizeof(double) * K);
+  if (!s->lat || !D || !Dl) { free(D); free(Dl); s->periodic = 0; return OR_E_NOMEM; }
+  const double h2 = s->boxlen / 4.0;
+  for (int di = 0; di < 343 && rc == OR_OK; ++di) {
+    /* source offset in level-2 cells, e = c_s - c_y */
+    const int e[3] = {di % 7 - 3, (di / 7) % 7 - 3, di / 49 - 3};
+    const double R[3] = {-e[0] * h2, -e[1] * h2, -e[2] * h2};   /* c_y - c_s */
+    rc = oracle_lattice_at(s->p, s->boxlen, 1.8 / s->boxlen, R, Dl);
+    for (int oy = 0; oy < 8 && rc == OR_OK; ++oy) {
+      double *T = &s->lat[((size_t)oy * 343 + di) * K];
+      memcpy(T, Dl, sizeof(double) * K);
+      /* block images n whose level-1 father image does not touch the target's:
+         in level-1 cells that offset is floor((o_y + e + 4 n) / 2) per axis */
+      for (int n = 0; n < 27; ++n) {
+        const int nn[3] = {n % 3 - 1, (n / 3) % 3 - 1, n / 9 - 1};
+        int far = 0;
+        for (int k = 0; k < 3; ++k) {
+          int v = ((oy >> k) & 1) + e[k] + 4 * nn[k];
+          int q = v >= 0 ? v / 2 : -((-v + 1) / 2);
+          if (q <= -2 || q >= 2) far = 1;
+        }
+        if (!far) continue;
+        const double Rn[3] = {R[0] - nn[0] * s->boxlen, R[1] - nn[1] * s->boxlen, R[2] - nn[2] * s->boxlen};
+        derivs(s->p, Rn, D);
+        for (int g = 0; g < K; ++g) T[g] += D[g];
+      }
+    }
+  }
+  free(D); free(Dl);
+  if (rc) s->periodic = 0;
+  return rc;
 }
 
 /* ------------------------------------------------------------------ */

@@ -50,13 +50,16 @@ def children_keys(keys: np.ndarray, level: int) -> np.ndarray:
     return np.sort(encode(ch, level + 1))
 
 
-def neighbours27(keys: np.ndarray, level: int) -> np.ndarray:
-    """Unique keys of the 27-neighbourhoods (inclusive) of `keys`, clipped to the box."""
+def neighbours27(keys: np.ndarray, level: int, periodic: bool = False) -> np.ndarray:
+    """Unique keys of the 27-neighbourhoods (inclusive) of `keys`, clipped to the box
+    (or wrapped around it when `periodic`)."""
     if keys.size == 0:
         return keys.astype(np.int64)
     ijk = decode(keys, level)
     nb = (ijk[:, None, :] + _OFFS27[None, :, :]).reshape(-1, 3)
     n = 1 << level
+    if periodic:
+        return np.unique(encode(nb % n, level))
     ok = np.all((nb >= 0) & (nb < n), axis=1)
     return np.unique(encode(nb[ok], level))
 
@@ -164,13 +167,14 @@ def unigrid(level: int, boxlen: float = 1.0) -> Hierarchy:
 
 def build_graded(levelmin: int, levelmax: int,
                  want: Callable[[int, np.ndarray, float], np.ndarray],
-                 boxlen: float = 1.0, max_iter: int = 50) -> Hierarchy:
+                 boxlen: float = 1.0, max_iter: int = 50, periodic: bool = False) -> Hierarchy:
     """Refine where `want(level, ijk[n,3], h) -> bool[n]` asks, then grade.
 
     The predicate is applied top-down to the cells that exist; the strong
     grading rule is then closed bottom-up (refined cell at l => the 27
-    neighbours of its father at l-1 are refined).  Both steps only add
-    refinement, so alternating them reaches a fixed point.
+    neighbours of its father at l-1 are refined; on a periodic box the
+    neighbours wrap around).  Both steps only add refinement, so alternating
+    them reaches a fixed point.
     """
     assert 1 <= levelmin <= levelmax <= MAX_LEVEL
     R = [np.zeros(0, np.int64) for _ in range(levelmin, levelmax)]
@@ -199,7 +203,7 @@ def build_graded(levelmin: int, levelmax: int,
             if R[i].size == 0:
                 continue
             fk = np.unique(encode(decode(R[i], lev) // 2, lev - 1))
-            req = neighbours27(fk, lev - 1)
+            req = neighbours27(fk, lev - 1, periodic)
             merged = np.union1d(R[i - 1], req)
             if merged.size != R[i - 1].size:
                 changed = True

@@ -82,6 +82,19 @@ typedef int32_t afmm_status;
                                 the acceleration of a uniform cube at its centre is zero, so only
                                 the potential changes. */
 
+#define AFMM_PERIODIC 64u    /* periodic box (an extension: the paper's Sec. 5 names periodic domains as
+                                future work): the box is a torus and phi the potential of the masses
+                                with a uniform neutralising background, zero on average over the box
+                                (the Ewald sum).  Neighbour lists wrap around the box; the images
+                                beyond the 3^3 block of boxes and the block's level-1 interaction
+                                list enter the 64 level-2 cells through one Ewald-summed operator.
+                                Needs levelmin >= 3 and a hierarchy graded on the torus (the
+                                grading rule with wrapped neighbours), else AFMM_E_UNSUPPORTED /
+                                AFMM_E_NOT_GRADED.  Full and ATS solves, drifted solves, re-planning
+                                and graph replay work as for isolated boxes; batches and the
+                                adjoint return AFMM_E_UNSUPPORTED.  The first plan of each order p
+                                computes the operator table on the host (about a second at p = 6). */
+
 #define AFMM_ALL_LEVELS (-1) /* synchronous solve: all trees rebuilt, every leaf evaluated */
 
 typedef struct afmm_options {
@@ -90,7 +103,7 @@ typedef struct afmm_options {
   double G;                  /* gravitational constant */
   double boxlen;             /* box side */
   uint32_t flags;            /* AFMM_CHECK_INPUT | AFMM_SERIAL | AFMM_OVERLAP | AFMM_GRAPH |
-                                AFMM_PAPER_QUAD_CAP | AFMM_SELF_POTENTIAL */
+                                AFMM_PAPER_QUAD_CAP | AFMM_SELF_POTENTIAL | AFMM_PERIODIC */
   int32_t fp64_levels;       /* mixed form: FMM levels <= this stay FP64 (default 3) */
   int32_t tap_split;         /* M2L and M2P blocks per tile: the 189 source offsets of a tile are
                                 split over this many blocks and their partial sums reduced in a

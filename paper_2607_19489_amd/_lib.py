@@ -19,6 +19,7 @@ AFMM_OVERLAP = 4
 AFMM_PAPER_QUAD_CAP = 8
 AFMM_GRAPH = 32
 AFMM_SELF_POTENTIAL = 16
+AFMM_PERIODIC = 64
 AFMM_ALL_LEVELS = -1
 
 STATUS = {

@@ -12,7 +12,7 @@ import numpy as np
 import torch
 
 from ._lib import (AFMM_ALL_LEVELS, AFMM_CHECK_INPUT, AFMM_FP32_MIXED, AFMM_FP64, AFMM_GRAPH, AFMM_OVERLAP, AFMM_PAPER_QUAD_CAP,
-                   AFMM_SELF_POTENTIAL, AFMM_SERIAL, HierarchyC, Options, PlanInfo, StageTime, TuneResult, check, lib)
+                   AFMM_PERIODIC, AFMM_SELF_POTENTIAL, AFMM_SERIAL, HierarchyC, Options, PlanInfo, StageTime, TuneResult, check, lib)
 
 PRECISIONS = {"fp64": AFMM_FP64, "fp32": AFMM_FP32_MIXED, "mixed": AFMM_FP32_MIXED}
 
@@ -44,7 +44,7 @@ def make_options(p: int = 4, precision: str = "fp64", G: float = 1.0, boxlen: fl
                  fp64_levels: int = 3, check_input: bool = False, max_device_bytes: int = 0,
                  tap_split: int = 0, serial: bool = False, overlap: bool = False,
                  quad_cap: bool = False, self_potential: bool = False, graph: bool = False,
-                 m2p_shape: int = 0) -> Options:
+                 m2p_shape: int = 0, periodic: bool = False) -> Options:
     o = Options()
     lib().afmm_options_default(C.byref(o))
     o.p = p
@@ -55,7 +55,8 @@ def make_options(p: int = 4, precision: str = "fp64", G: float = 1.0, boxlen: fl
     o.tap_split = tap_split
     o.flags = ((AFMM_CHECK_INPUT if check_input else 0) | (AFMM_SERIAL if serial else 0)
                | (AFMM_OVERLAP if overlap else 0) | (AFMM_PAPER_QUAD_CAP if quad_cap else 0)
-               | (AFMM_SELF_POTENTIAL if self_potential else 0) | (AFMM_GRAPH if graph else 0))
+               | (AFMM_SELF_POTENTIAL if self_potential else 0) | (AFMM_GRAPH if graph else 0)
+               | (AFMM_PERIODIC if periodic else 0))
     o.max_device_bytes = max_device_bytes
     o.m2p_shape = m2p_shape
     return o
@@ -86,7 +87,8 @@ class Plan:
                  boxlen: Optional[float] = None, fp64_levels: int = 3, check_input: bool = False,
                  max_device_bytes: int = 0, tap_split: int = 0, serial: bool = False,
                  overlap: bool = False, quad_cap: bool = False, self_potential: bool = False,
-                 graph: bool = False, m2p_shape: int = 0, stream: Optional[torch.cuda.Stream] = None):
+                 graph: bool = False, m2p_shape: int = 0, periodic: bool = False,
+                 stream: Optional[torch.cuda.Stream] = None):
         self._ptr = C.c_void_p()
         arrs = _hierarchy_arrays(h)
         self.levelmin, self.levelmax, self.ncell = arrs[0], arrs[1], arrs[2]
@@ -94,7 +96,7 @@ class Plan:
         hc = _hier_struct(*arrs)
         bl = float(boxlen if boxlen is not None else getattr(h, "boxlen", 1.0))
         self.options = make_options(p, precision, G, bl, fp64_levels, check_input, max_device_bytes, tap_split,
-                                    serial, overlap, quad_cap, self_potential, graph, m2p_shape)
+                                    serial, overlap, quad_cap, self_potential, graph, m2p_shape, periodic)
         check(lib().afmm_plan_create(C.byref(hc), C.byref(self.options), _stream_handle(stream),
                                      C.byref(self._ptr)), "afmm_plan_create")
         self.p = p

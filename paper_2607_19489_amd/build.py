@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libafmm.so")
-SOURCES = ["afmm_host.hip", "afmm_kernels.hip", "afmm_adjoint.hip", "afmm_pm.hip"]
+SOURCES = ["afmm_host.hip", "afmm_kernels.hip", "afmm_adjoint.hip", "afmm_pm.hip", "afmm_periodic.hip"]
 ARCH = "gfx950"
 
 

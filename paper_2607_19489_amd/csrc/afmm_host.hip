@@ -53,6 +53,7 @@ struct HostLevel {
 };
 
 struct Topology {
+  bool periodic = false;         // neighbour rows wrap around the box (AFMM_PERIODIC)
   int lmax = 0;                  // deepest level present
   int lmin_all = 1 << 30;        // smallest levelmin over hierarchies
   HostLevel lv[kMaxLevel];
@@ -98,6 +99,7 @@ static afmm_status append_hierarchy(Topology& T, const afmm_hierarchy& h, int64_
   }
   if (h.ncell[0] != (int64_t)1 << (3 * lmin))
     return fail(AFMM_E_INCOMPLETE_OCT, "levelmin must be complete (8^levelmin cells)");
+  if (T.periodic && lmin < 3) return fail(AFMM_E_UNSUPPORTED, "periodic boxes need levelmin >= 3");
   if (slot_base + off[nl] >= ((int64_t)1 << 31)) return fail(AFMM_E_INVALID_ARG, "more than 2^31 cells");
 
   // caller cells of each AMR level sorted by Morton key
@@ -170,7 +172,8 @@ static afmm_status append_hierarchy(Topology& T, const afmm_hierarchy& h, int64_
       const int32_t gcell = base + (int32_t)c;
       int32_t row[27];
       if (l == 0) {
-        for (int e = 0; e < 27; ++e) row[e] = (e == 13) ? gcell : -1;
+        // periodic box: the root's 27 neighbours are its own images
+        for (int e = 0; e < 27; ++e) row[e] = (e == 13 || T.periodic) ? gcell : -1;
       } else {
         const HostLevel& P = T.lv[l - 1];
         const int32_t fr = gcell >> 3, o = gcell & 7;
@@ -906,6 +909,11 @@ struct afmm_plan {
   int* d_flag = nullptr;          // AFMM_CHECK_INPUT / particle-mesh calls: device flag (plan-owned)
   int* h_flag = nullptr;          // its pinned host copy
   double cself = 0.0;             // AFMM_SELF_POTENTIAL: the unit-cube constant, else 0
+  // AFMM_PERIODIC: the level-2 far operator ([8][kNumD][K], level-2 units) and the
+  // multipole factors (-1)^|a|/a! it is applied with (0 at order p with the quadrupole cap)
+  const double* d_pfar = nullptr;
+  const double* d_pfar_cf = nullptr;
+  int l_first = 3;                // first FMM level with local expansions (2 with periodic boxes)
   bool snap_valid = false;
   // the per-level masses and merged multipoles on the device were computed from
   // the current snapshot m_snap (a solve that rebuilds no tree can skip them)
@@ -1039,7 +1047,8 @@ afmm_status check_options(const afmm_options* o) {
   if (o->p < 1 || o->p > kPMax) return fail(AFMM_E_UNSUPPORTED, "p must be in 1..8");
   if (o->precision != AFMM_FP64 && o->precision != AFMM_FP32_MIXED)
     return fail(AFMM_E_UNSUPPORTED, "unknown precision");
-  if (o->flags & ~(AFMM_CHECK_INPUT | AFMM_SERIAL | AFMM_OVERLAP | AFMM_PAPER_QUAD_CAP | AFMM_SELF_POTENTIAL | AFMM_GRAPH))
+  if (o->flags & ~(AFMM_CHECK_INPUT | AFMM_SERIAL | AFMM_OVERLAP | AFMM_PAPER_QUAD_CAP | AFMM_SELF_POTENTIAL | AFMM_GRAPH |
+                   AFMM_PERIODIC))
     return fail(AFMM_E_UNSUPPORTED, "unknown flag");
   if (!(o->boxlen > 0) || !std::isfinite(o->boxlen)) return fail(AFMM_E_INVALID_ARG, "boxlen must be > 0");
   if (!std::isfinite(o->G)) return fail(AFMM_E_INVALID_ARG, "G must be finite");
@@ -1129,6 +1138,7 @@ static afmm_status afmm_hierarchy_check_impl(const afmm_hierarchy* h, const afmm
   afmm_status s = check_options(&o);
   if (s) return s;
   Topology T;
+  T.periodic = (o.flags & AFMM_PERIODIC) != 0;
   s = append_hierarchy(T, *h, 0);
   if (s) return s;
   build_groups(T);
@@ -1581,9 +1591,21 @@ static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
     return fail(AFMM_E_OUT_OF_MEMORY, "pinned flag allocation failed");
   }
   P->cself = (P->opt.flags & AFMM_SELF_POTENTIAL) ? cube_self_constant() : 0.0;
+  if (T.periodic) {
+    const auto tab = periodic_far_table(P->opt.p);
+    std::vector<double> cf(K);
+    for (int a = 0; a < K; ++a) {
+      const int* m = &P->tabs->mi[4 * a];
+      cf[a] = ((m[3] & 1) ? -1.0 : 1.0) / (fact(m[0]) * fact(m[1]) * fact(m[2]));
+      if ((P->opt.flags & AFMM_PAPER_QUAD_CAP) && m[3] == P->opt.p) cf[a] = 0.0;
+    }
+    if ((s = upload_conv<double>(P, *tab, &P->d_pfar, st)) || (s = upload_conv<double>(P, cf, &P->d_pfar_cf, st)))
+      return s;
+    P->l_first = 2;
+  }
   // a plan small enough for the allocation-free adjoint gets its adjoint
   // topology now, so that afmm_solve_adjoint_noalloc never has to allocate it
-  if (T.levelmin.size() == 1 && adjoint_noalloc_may_fit(P) && (s = adjoint_topology(P))) return s;
+  if (T.levelmin.size() == 1 && !T.periodic && adjoint_noalloc_may_fit(P) && (s = adjoint_topology(P))) return s;
   if ((P->opt.flags & AFMM_GRAPH) && hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking) != hipSuccess)
     return fail(AFMM_E_DEVICE, "capture stream creation failed");
   if (hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking) != hipSuccess ||
@@ -1608,6 +1630,7 @@ static afmm_status afmm_plan_create_impl(const afmm_hierarchy* h, const afmm_opt
   try {
     P->opt = o;
     P->K = nmi(o.p);
+    P->topo.periodic = (o.flags & AFMM_PERIODIC) != 0;
     s = append_hierarchy(P->topo, *h, 0);
     if (!s) s = plan_finish(P, (hipStream_t)hip_stream);
   } catch (...) {
@@ -1761,6 +1784,13 @@ static afmm_status run_solve(afmm_plan* P, const double* msrc, int fmax, int lo,
       return s;
     prof_end(P, a, st, kUpward, f);
   }
+  // periodic boxes: local expansions of the 64 level-2 cells from the far operator
+  if (T.periodic) {
+    hipEvent_t a = prof_begin(P, st);
+    if ((s = dev_check(P, launch_periodic_far(p, P->lv[2], P->d_pfar, P->d_pfar_cf, P->cm, st), "periodic far")))
+      return s;
+    prof_end(P, a, st, kL2L, 2);
+  }
   // fork: the intermediate field (M2P, one large launch) runs on the side
   // stream while the downward chain (M2L taps, then the latency-bound L2L
   // levels) runs on this one; the chain is enqueued without a wait, so its
@@ -1826,10 +1856,10 @@ static afmm_status run_solve(afmm_plan* P, const double* msrc, int fmax, int lo,
     const int ng = chain ? chain->ngrp[f] : (int)T.m2lgrp[f].size();
     const int32_t* grp = chain ? chain->d_grp[f] : P->d_m2lgrp[f];
     const int ns = P->m2l_split[P->m2l_range[f][0]];
-    if (ng == 0 || (f - 1 < 3 && ns == 1)) continue;
+    if (ng == 0 || (f - 1 < P->l_first && ns == 1)) continue;
     hipEvent_t a = prof_begin(P, st);
     if ((s = dev_check(P,
-                       launch_l2l(p, mixed && f > f64, mixed && (f - 1) > f64, f - 1 >= 3, ns, grp, ng,
+                       launch_l2l(p, mixed && f > f64, mixed && (f - 1) > f64, f - 1 >= P->l_first, ns, grp, ng,
                                   P->lv[f - 1], P->lv[f], P->t32, P->t64, P->cm, st),
                        "l2l")))
       return s;
@@ -1853,7 +1883,8 @@ static afmm_status run_solve(afmm_plan* P, const double* msrc, int fmax, int lo,
                                  "near m2p")))
       return s;
     if ((s = dev_check(P,
-                       launch_near(p, fp32, l, P->d_leafgrp[l], ng, P->lv[l - 1], P->lv[l], lvp, P->t32, P->t64, P->cm,
+                       launch_near(p, fp32, l, P->l_first, P->d_leafgrp[l], ng, P->lv[l - 1], P->lv[l], lvp, P->t32,
+                                   P->t64, P->cm,
                                    l >= 3 ? P->lv[l - 1].part : nullptr, nm > 0 ? P->d_nmp[l] : nullptr, P->opt.G,
                                    h, P->cself, phi, acc, st),
                        "near")))
@@ -2592,6 +2623,7 @@ static afmm_status adjoint_args(afmm_plan* P, int32_t level, const double* d_phi
   if (!P || !d_phi_bar || !d_acc_bar || !d_mass_bar) return fail(AFMM_E_INVALID_ARG, "null argument");
   if (P->dead) return fail(AFMM_E_DEVICE, "plan is unusable after an earlier device error");
   if (P->topo.levelmin.size() != 1) return fail(AFMM_E_INVALID_ARG, "batched plan: no adjoint");
+  if (P->topo.periodic) return fail(AFMM_E_UNSUPPORTED, "periodic boxes: no adjoint");
   if (!P->solved) return fail(AFMM_E_ATS_ORDER, "adjoint before any solve");
   if (level != P->last_level) return fail(AFMM_E_INVALID_ARG, "adjoint level differs from the last solve's level");
   return AFMM_OK;
@@ -2805,6 +2837,7 @@ static afmm_status afmm_batch_create_impl(afmm_plan* const* plans, int32_t n, vo
     if (!Q) return fail(AFMM_E_INVALID_ARG, "null plan in batch");
     if (Q->dead) return fail(AFMM_E_DEVICE, "a plan of the batch is unusable after a device error");
     if (Q->topo.levelmin.size() != 1) return fail(AFMM_E_INVALID_ARG, "a batch takes single-hierarchy plans");
+    if (Q->topo.periodic) return fail(AFMM_E_UNSUPPORTED, "periodic boxes: no batch");
     const afmm_options& o = Q->opt;
     const uint32_t kModel = AFMM_PAPER_QUAD_CAP | AFMM_SELF_POTENTIAL;
     if (o.p != o0.p || o.precision != o0.precision || o.G != o0.G || o.boxlen != o0.boxlen ||

@@ -17,6 +17,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <memory>
+#include <vector>
+
 #include "afmm.h"
 
 namespace afmm {
@@ -223,6 +226,11 @@ hipError_t launch_adj_l2p(int p, const int32_t* grp, int ngrp, const LevelDev& l
 // MFMA forms: tiles of 16 source cells (records: target level, 16 cells); with
 // nsplit > 1 the 189 taps of a tile are split over blocks writing partial sets
 // into `part` ([nsplit][ntiles * 16][K] FP64), summed in order afterwards.
+// Periodic boxes: the level-2 far operator table ([8][kNumD][K] in level-2
+// units, cached per order) and its kernel (writes L of the 64 level-2 cells).
+std::shared_ptr<const std::vector<double>> periodic_far_table(int p);
+hipError_t launch_periodic_far(int p, const LevelDev& lv2, const double* T, const double* cf, const CommonDev& cm,
+                               hipStream_t st);
 hipError_t launch_adj_m2p_mfma(int p, bool fp32, const int32_t* tiles, int ntiles, int nsplit, const XcdRanges& xr,
                                const uint8_t* live, double* part,
                                const int32_t* tapsT, const int16_t* aoff, const LevelDev& lvp, const LevelDev& lvs,
@@ -260,7 +268,7 @@ hipError_t launch_m2p(int p, bool fp32, const MfmaTiles& mt, int t0, int n, int 
                       const MfmaTables& tabs, const LevelDev* lvs, const TablesDev<float>& t32,
                       const TablesDev<double>& t64, hipStream_t st);
 // cself: the self-potential constant (AFMM_SELF_POTENTIAL), 0 when off.
-hipError_t launch_near(int p, bool fp32, int l, const int32_t* grp, int ngrp, const LevelDev& lv1,
+hipError_t launch_near(int p, bool fp32, int l, int l_first, const int32_t* grp, int ngrp, const LevelDev& lv1,
                        const LevelDev& lv0, const LevelDev& lvp, const TablesDev<float>& t32,
                        const TablesDev<double>& t64, const CommonDev& cm, const void* part, const void* nmp,
                        double G, double h, double cself, double* phi, double* acc, hipStream_t st);

@@ -1607,14 +1607,14 @@ static hipError_t near_dispatch(int p, int ngrp, const int32_t* grp, const Level
   return hipGetLastError();
 }
 
-hipError_t launch_near(int p, bool fp32, int l, const int32_t* grp, int ngrp, const LevelDev& lv1,
+hipError_t launch_near(int p, bool fp32, int l, int l_first, const int32_t* grp, int ngrp, const LevelDev& lv1,
                        const LevelDev& lv0, const LevelDev& lvp, const TablesDev<float>& t32,
                        const TablesDev<double>& t64, const CommonDev& cm, const void* part, const void* nmp,
                        double G, double h, double cself, double* phi, double* acc, hipStream_t st) {
   (void)cm;
   (void)lvp;
   if (ngrp == 0) return hipSuccess;
-  const bool has_far = (l - 1) >= 3;
+  const bool has_far = (l - 1) >= l_first;
   if (fp32)
     return near_dispatch<float>(p, ngrp, grp, lv1, lv0, t32, has_far ? lv1.L32 : nullptr, (const float*)part,
                                 (const float*)nmp, G, h, cself, phi, acc, st);

@@ -23,6 +23,7 @@ def _oracle_built():
 # GPU modules run core parity first; the autotuner (which times dozens of
 # candidate launches) runs after everything that checks results.
 _MODULE_ORDER = {"test_gpu_parity.py": 1, "test_gpu_options.py": 2, "test_gpu_shapes.py": 2, "test_gpu_adjoint.py": 3, "test_gpu_replan.py": 3, "test_gpu_drift.py": 3,
+                 "test_gpu_periodic.py": 3,
                  "test_gpu_batch.py": 4, "test_gpu_graph.py": 4, "test_gpu_pm.py": 5, "test_gpu_workloads.py": 5,
                  "test_gpu_autotune.py": 6}
 

@@ -115,3 +115,27 @@ def test_m2p_shape_option_validated():
     for bad in (-1, 3):
         with pytest.raises(A.AfmmError):
             A.hierarchy_check(h, p=4, m2p_shape=bad)
+
+
+def test_periodic_hierarchy_validation_and_counts():
+    """Periodic boxes: neighbour lists wrap, so every leaf of a unigrid has all
+    189 interaction-list sources and 215 near neighbours; levelmin < 3 and a
+    hierarchy graded only inside the box are refused."""
+    i3 = A.hierarchy_check(unigrid(3), p=4, periodic=True)
+    assert i3["m2p_pairs"] == 512 * 189 and i3["p2p_pairs"] == 512 * 215
+    i4 = A.hierarchy_check(unigrid(4), p=4, periodic=True)
+    assert i4["m2l_targets"] == 512 and i4["m2l_pairs"] == 512 * 189 and i4["p2p_pairs"] == 4096 * 215
+    iso = A.hierarchy_check(unigrid(3), p=4)
+    assert iso["m2p_pairs"] < i3["m2p_pairs"]
+    with pytest.raises(A.AfmmError, match="UNSUPPORTED"):
+        A.hierarchy_check(unigrid(2), p=4, periodic=True)
+
+    def face(level, ijk, h):
+        x = (ijk.astype(np.float64) + 0.5) * h
+        r = {3: 0.2, 4: 0.1}.get(level)
+        if r is None:
+            return np.zeros(len(x), bool)
+        return (x[:, 0] < r) & (np.abs(x[:, 1] - 0.5) < 0.2) & (np.abs(x[:, 2] - 0.5) < 0.2)
+    with pytest.raises(A.AfmmError, match="NOT_GRADED"):
+        A.hierarchy_check(build_graded(3, 5, face), p=4, periodic=True)
+    assert A.hierarchy_check(build_graded(3, 5, face, periodic=True), p=4, periodic=True)["nleaves"] > 0

@@ -1,0 +1,153 @@
+"""Periodic boxes (AFMM_PERIODIC) on the GPU against the oracle's periodic FMM.
+
+The oracle's periodic mode is pinned against the Ewald sum (test_oracle_periodic);
+here the HIP path must match it element by element at the usual gates (FP64
+1e-10, FP32 mixed 1e-4), on a unigrid, on AMR hierarchies whose refinement
+crosses the box faces, in ATS sequences, with the quadrupole cap, and under
+graph replay.  The FP32 regression bound is taken relative to the periodic
+forces, which are small against the monopole scale (images and background
+cancel), so it is looser than for isolated boxes.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from gpu_util import check_errors, gpu_solve, rel_l2  # noqa: E402
+
+import oracle  # noqa: E402
+import paper_2607_19489_amd as A  # noqa: E402
+from synth.hierarchy import build_graded, unigrid  # noqa: E402
+
+
+def _corner(level, ijk, h):
+    # refinement around the box corner, on every periodic image
+    x = (ijk.astype(np.float64) + 0.5) * h
+    d = np.minimum(x, 1.0 - x)
+    r = {3: 0.3, 4: 0.16, 5: 0.08}.get(level)
+    return np.zeros(len(x), bool) if r is None else np.sum(d * d, axis=1) <= r * r
+
+
+def _face(level, ijk, h):
+    # a slab along the x = 0 face, off-centre in y and z
+    x = (ijk.astype(np.float64) + 0.5) * h
+    r = {3: 0.2, 4: 0.1}.get(level)
+    if r is None:
+        return np.zeros(len(x), bool)
+    return (np.minimum(x[:, 0], 1 - x[:, 0]) < r) & (np.abs(x[:, 1] - 0.3) < 0.25) & (np.abs(x[:, 2] - 0.6) < 0.2)
+
+
+_CASES = {}
+
+
+def _case(name):
+    if name not in _CASES:
+        if name == "uni3":
+            h = unigrid(3)
+        elif name == "uni4":
+            h = unigrid(4)
+        elif name == "corner":
+            h = build_graded(3, 6, _corner, periodic=True)
+        else:
+            h = build_graded(3, 5, _face, periodic=True)
+        lev = h.level_of()
+        m = np.random.default_rng(len(name)).uniform(0.2, 1.0, h.total) / 8.0 ** (lev - h.levelmin)
+        _CASES[name] = (h, m)
+    return _CASES[name]
+
+
+def _oracle_solve(h, m, p, **kw):
+    o = oracle.Oracle(h, p, periodic=True, **kw)
+    po, ao = o.solve_all(m)
+    o.close()
+    return po, ao
+
+
+@pytest.mark.parametrize("name,p", [("uni3", 6), ("uni4", 4), ("corner", 6), ("face", 5), ("corner", 8)])
+def test_periodic_full_solve_matches_oracle(name, p):
+    h, m = _case(name)
+    print(f"periodic {name} {h.summary()['ncell']} p={p}", flush=True)
+    po, ao = _oracle_solve(h, m, p)
+    leaf = h.leaf_mask()
+    for precision in ("fp64", "fp32"):
+        phi, acc, plan = gpu_solve(h, m, p, precision, periodic=True)
+        check_errors(phi[leaf], acc[leaf], po[leaf], ao[leaf], precision, regression=False,
+                     what=f"periodic {name}")
+        if precision == "fp32":
+            assert rel_l2(acc[leaf], ao[leaf]) <= 2e-5 and rel_l2(phi[leaf], po[leaf]) <= 2e-5
+        plan.close()
+
+
+def test_periodic_is_not_the_isolated_solve_and_approaches_ewald():
+    h, m = _case("uni3")
+    phi, acc, plan = gpu_solve(h, m, 8, "fp64", periodic=True)
+    plan.close()
+    phi_i, acc_i, plan = gpu_solve(h, m, 8, "fp64")
+    plan.close()
+    assert rel_l2(acc, acc_i) > 0.1
+    x = h.centres()
+    pd, ad = oracle.direct_periodic(x, m, x)
+    assert np.linalg.norm(acc - ad, axis=1).max() <= 1e-5 * m.sum()
+
+
+def test_periodic_ats_sequence_matches_oracle():
+    h, m0 = _case("corner")
+    rng = np.random.default_rng(11)
+    seq = [(3, 1), (4, 1), (5, 1), (6, 2), (5, 2), (4, 1), (6, 1)]
+    plan = A.Plan(h, p=5, precision="fp64", periodic=True)
+    o = oracle.Oracle(h, 5, periodic=True)
+    N = h.total
+    po = np.zeros(N)
+    ao = np.zeros((N, 3))
+    lev = h.level_of()
+    m = m0.copy()
+    for (l, ic) in seq:
+        m = m * (1 + 1e-3 * rng.uniform(-1, 1, N))
+        print(f"periodic ATS solve({l}, {ic})", flush=True)
+        phi, acc, _ = gpu_solve(h, m, 5, level=l, icount=ic, plan=plan)
+        o.solve(l, ic, m, po, ao)
+        sel = (lev == l) & h.leaf_mask()
+        assert rel_l2(acc[sel], ao[sel]) < 1e-10, (l, ic)
+        assert rel_l2(phi[sel], po[sel]) < 1e-10, (l, ic)
+    o.close()
+    plan.close()
+
+
+def test_periodic_quad_cap_and_self_potential():
+    h, m = _case("face")
+    po, ao = _oracle_solve(h, m, 3, quad_cap=True, self_potential=True)
+    phi, acc, plan = gpu_solve(h, m, 3, "fp64", periodic=True, quad_cap=True, self_potential=True)
+    plan.close()
+    leaf = h.leaf_mask()
+    check_errors(phi[leaf], acc[leaf], po[leaf], ao[leaf], "fp64", what="periodic cap")
+
+
+def test_periodic_graph_replay_is_bitwise_eager():
+    h, m = _case("corner")
+    mt = torch.from_numpy(m).cuda()
+    eager = A.Plan(h, p=6, precision="fp32", periodic=True)
+    pe, ae = eager.solve(mt)
+    graph = A.Plan(h, p=6, precision="fp32", periodic=True, graph=True)
+    for _ in range(3):
+        pg, ag = graph.solve(mt)
+        torch.cuda.synchronize()
+        assert torch.equal(pg, pe) and torch.equal(ag, ae)
+        mt.mul_(1.0)
+    eager.close()
+    graph.close()
+
+
+def test_periodic_refusals():
+    h, m = _case("uni3")
+    plan = A.Plan(h, p=4, precision="fp64", periodic=True)
+    mt = torch.from_numpy(m).cuda()
+    phi, acc = plan.solve(mt)
+    with pytest.raises(A.AfmmError):
+        plan.solve_adjoint(torch.ones_like(phi), torch.ones_like(acc))
+    with pytest.raises(A.AfmmError):
+        A.Batch([plan])
+    plan.close()
+    with pytest.raises(A.AfmmError):
+        A.Plan(unigrid(2), p=4, periodic=True)

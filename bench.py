@@ -254,7 +254,7 @@ def run_batch(args):
     print(json.dumps(line), flush=True)
 
 
-def time_form(h, mass_t, p, precision, steps, warmup, overlap=False, autotune=True, graph=False):
+def time_form(h, mass_t, p, precision, steps, warmup, overlap=False, autotune=True, graph=False, periodic=False):
     """Autotuned plan (tap splits), timed solves (no instrumentation), then the same
     number of profiled solves: the profiled pass runs serially with hipEvents
     around every launch."""
@@ -262,7 +262,7 @@ def time_form(h, mass_t, p, precision, steps, warmup, overlap=False, autotune=Tr
     import paper_2607_19489_amd as A
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plan = A.Plan(h, p=p, precision=precision, overlap=overlap, graph=graph)
+    plan = A.Plan(h, p=p, precision=precision, overlap=overlap, graph=graph, periodic=periodic)
     torch.cuda.synchronize()
     plan_ms = 1e3 * (time.perf_counter() - t0)
     info = plan.info()
@@ -462,6 +462,7 @@ def main():
     ap.add_argument("--adjoint", action="store_true", help="also time the adjoint pass (default for cfg5)")
     ap.add_argument("--ats", action="store_true", help="also time one adaptive-time-step cycle (default for cfg3)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-periodic", action="store_true", help="skip the periodic-box timing")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-form run")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tap splits")
@@ -534,6 +535,24 @@ def main():
         print(f"[bench] adjoint {adj['adjoint_ms']:.3f} ms vs forward {adj['forward_ms']:.3f} ms",
               file=sys.stderr, flush=True)
 
+    periodic = None
+    if not args.no_periodic:
+        # the same hierarchy and masses on a periodic box (AFMM_PERIODIC), autotuned like
+        # the isolated form; its plan creation includes, for the first periodic plan of
+        # this order, the host's level-2 far-operator table
+        try:
+            rp, _, _ = time_form(h, mass_t, w.p, "fp32", max(args.steps // 2, 2), 1,
+                                 autotune=not args.no_autotune, periodic=True)
+            periodic = {"ms_per_step": rp["ms_per_step"], "value": rp["value"], "unit": "cells/s",
+                        "over_isolated": rp["ms_per_step"] / r32["ms_per_step"],
+                        "plan_create_ms": rp["plan_create_ms"], "autotune": rp["autotune"],
+                        "kernels": kernel_table(rp)}
+            print(f"[bench] periodic box: {rp['ms_per_step']:.3f} ms/step "
+                  f"({periodic['over_isolated']:.3f}x isolated), plan {rp['plan_create_ms']:.0f} ms",
+                  file=sys.stderr, flush=True)
+        except RuntimeError as e:   # AfmmError: a hierarchy graded only inside the box
+            periodic = {"skipped": str(e)}
+
     binary = None
     if args.binary:
         binary = [run_binary(lm) for lm in (6, 7, 8)]
@@ -583,6 +602,7 @@ def main():
         "kernels_fp32": kernel_table(r32),
         "kernels_fp64": None if r64 is None else kernel_table(r64),
         "adjoint": adj,
+        "periodic": periodic,
         "ats_step": ats,
         "binary_orbit": binary,
     }

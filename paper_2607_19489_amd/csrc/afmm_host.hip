@@ -1605,7 +1605,7 @@ static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
   }
   // a plan small enough for the allocation-free adjoint gets its adjoint
   // topology now, so that afmm_solve_adjoint_noalloc never has to allocate it
-  if (T.levelmin.size() == 1 && !T.periodic && adjoint_noalloc_may_fit(P) && (s = adjoint_topology(P))) return s;
+  if (T.levelmin.size() == 1 && adjoint_noalloc_may_fit(P) && (s = adjoint_topology(P))) return s;
   if ((P->opt.flags & AFMM_GRAPH) && hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking) != hipSuccess)
     return fail(AFMM_E_DEVICE, "capture stream creation failed");
   if (hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking) != hipSuccess ||
@@ -2471,7 +2471,8 @@ static size_t adjoint_layout(const afmm_plan* P, char* base, LevelDev* lw, doubl
     D.tbar = (double*)take((size_t)std::max(D.n, 1) * 4 * sizeof(double));
     D.mbar = (double*)take((size_t)std::max(D.n, 1) * sizeof(double));
     D.sbar = (l >= 2 && l <= T.lmax - 1 && D.nref > 0) ? (double*)take((size_t)D.nref * K * sizeof(double)) : nullptr;
-    D.lbar = (l >= 3 && l <= T.lmax - 1 && D.nref > 0) ? (double*)take((size_t)D.nref * K * sizeof(double)) : nullptr;
+    D.lbar = (l >= P->l_first && l <= T.lmax - 1 && D.nref > 0) ? (double*)take((size_t)D.nref * K * sizeof(double))
+                                                                  : nullptr;
     D.tbT = nullptr;
     D.lbarT = nullptr;
   }
@@ -2553,7 +2554,7 @@ static afmm_status run_adjoint(afmm_plan* P, int32_t level, const double* d_phi_
                                        P->t64, P->cm, st),
                        "adjoint near")))
       return s;
-    if (tgt && l - 1 >= 3 && lw[l - 1].lbar &&
+    if (tgt && l - 1 >= P->l_first && lw[l - 1].lbar &&
         (s = dev_check(P, launch_adj_l2p(p, P->d_leafgrp[l], nlg, lw[l - 1], lw[l], P->t64, P->cm, st),
                        "adjoint l2p")))
       return s;
@@ -2575,9 +2576,9 @@ static afmm_status run_adjoint(afmm_plan* P, int32_t level, const double* d_phi_
     P->pending_bytes += W.m2p_bytes[l];
   }
   prof_end(P, ev, st, kAdjM2P, -1);
-  // 4. L2L^T, finest FMM level first
+  // 4. L2L^T, finest FMM level first (into the first level with local expansions)
   ev = prof_begin(P, st);
-  for (int f = fmax; f >= 4; --f)
+  for (int f = fmax; f >= P->l_first + 1; --f)
     if ((s = dev_check(P,
                        launch_adj_l2l(p, P->d_m2lgrp[f], (int)T.m2lgrp[f].size(), lw[f - 1], lw[f], P->t64, P->cm,
                                       st),
@@ -2599,13 +2600,20 @@ static afmm_status run_adjoint(afmm_plan* P, int32_t level, const double* d_phi_
   }
   prof_end(P, ev, st, kAdjM2L, -1);
   ev = prof_begin(P, st);
-  // 6. source-copy bars -> multipole bars, M2M^T coarse to fine
-  for (int f = 2; f <= lmax - 1; ++f)
+  // 6. source-copy bars -> multipole bars, M2M^T coarse to fine; with periodic
+  //    boxes the transposed level-2 far operator joins the level-2 multipole bars
+  //    before they pass down
+  for (int f = 2; f <= lmax - 1; ++f) {
     if ((s = dev_check(P,
                        launch_adj_down(p, P->d_upmix[f - 1], (int)T.upmix[f - 1].size(), lw[f - 1], lw[f], f >= 3,
                                        P->cm, st),
                        "adjoint down")))
       return s;
+    if (f == 2 && T.periodic && fmax >= 2 &&
+        (s = dev_check(P, launch_adj_periodic_far(p, lw[2], P->d_pfar, P->d_pfar_cf, P->cm, st),
+                       "adjoint periodic far")))
+      return s;
+  }
   // 7. mass bars to the caller's slots (levels whose masses came from the last call)
   for (int l = lmin; l <= lmax; ++l) {
     const bool has_parent = l - 1 >= 2 && l - 1 <= lmax - 1;
@@ -2623,7 +2631,6 @@ static afmm_status adjoint_args(afmm_plan* P, int32_t level, const double* d_phi
   if (!P || !d_phi_bar || !d_acc_bar || !d_mass_bar) return fail(AFMM_E_INVALID_ARG, "null argument");
   if (P->dead) return fail(AFMM_E_DEVICE, "plan is unusable after an earlier device error");
   if (P->topo.levelmin.size() != 1) return fail(AFMM_E_INVALID_ARG, "batched plan: no adjoint");
-  if (P->topo.periodic) return fail(AFMM_E_UNSUPPORTED, "periodic boxes: no adjoint");
   if (!P->solved) return fail(AFMM_E_ATS_ORDER, "adjoint before any solve");
   if (level != P->last_level) return fail(AFMM_E_INVALID_ARG, "adjoint level differs from the last solve's level");
   return AFMM_OK;

@@ -231,6 +231,9 @@ hipError_t launch_adj_l2p(int p, const int32_t* grp, int ngrp, const LevelDev& l
 std::shared_ptr<const std::vector<double>> periodic_far_table(int p);
 hipError_t launch_periodic_far(int p, const LevelDev& lv2, const double* T, const double* cf, const CommonDev& cm,
                                hipStream_t st);
+// its transpose: level-2 multipole bars from the level-2 local-expansion bars
+hipError_t launch_adj_periodic_far(int p, const LevelDev& lv2, const double* T, const double* cf,
+                                   const CommonDev& cm, hipStream_t st);
 hipError_t launch_adj_m2p_mfma(int p, bool fp32, const int32_t* tiles, int ntiles, int nsplit, const XcdRanges& xr,
                                const uint8_t* live, double* part,
                                const int32_t* tapsT, const int16_t* aoff, const LevelDev& lvp, const LevelDev& lvs,

@@ -250,6 +250,51 @@ __global__ __launch_bounds__(256) void k_periodic_far(LevelDev lv2, const double
   else lv2.L32[(size_t)y * K + b] = (float)acc;
 }
 
+// Adjoint: the bars of the level-2 multipoles, S~bar_a(s) += cf_a sum_y sum_b
+// T~[o_y][s - y]_{a+b} L~bar_b(y) (after the source-copy bars of level 2 became
+// multipole bars).  One block per source, the 64 L~bar rows in LDS, thread =
+// coefficient a.
+template <int P>
+__global__ __launch_bounds__(256) void k_adj_periodic_far(LevelDev lv2, const double* __restrict__ T,
+                                                          const double* __restrict__ cf,
+                                                          const int16_t* __restrict__ sumidx,
+                                                          const int8_t* __restrict__ mi) {
+  constexpr int K = nmi(P);
+  __shared__ double sL[64 * K];
+  const int s = blockIdx.x;
+  for (int i = threadIdx.x; i < 64 * K; i += 256) sL[i] = lv2.lbar[i];
+  __syncthreads();
+  const int a = threadIdx.x;
+  if (a >= K) return;
+  auto axis = [](int c, int i) { return 2 * ((c >> (3 + i)) & 1) + ((c >> i) & 1); };
+  const int s0 = axis(s, 0), s1 = axis(s, 1), s2 = axis(s, 2);
+  const int nb = nmi(P - mi[4 * a + 3]);
+  const int16_t* si = sumidx + (size_t)a * K;   // index of a + b
+  double acc = 0.0;
+  for (int y = 0; y < 64; ++y) {
+    const int di = (s0 - axis(y, 0) + 3) + 7 * (s1 - axis(y, 1) + 3) + 49 * (s2 - axis(y, 2) + 3);
+    const double* Tr = T + ((size_t)(y & 7) * kNumD + di) * K;
+    const double* Lr = sL + y * K;
+    for (int b = 0; b < nb; ++b) acc += Tr[si[b]] * Lr[b];
+  }
+  lv2.sbar[(size_t)s * K + a] += cf[a] * acc;
+}
+
+hipError_t launch_adj_periodic_far(int p, const LevelDev& lv2, const double* T, const double* cf,
+                                   const CommonDev& cm, hipStream_t st) {
+  if (lv2.nref != 64 || !lv2.lbar || !lv2.sbar || !T || !cf) return hipErrorInvalidValue;
+  switch (p) {
+#define X(PP)                                                                                              \
+  case PP:                                                                                                 \
+    hipLaunchKernelGGL((k_adj_periodic_far<PP>), dim3(64), dim3(256), 0, st, lv2, T, cf, cm.sumidx, cm.mi); \
+    break;
+    X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8)
+#undef X
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_periodic_far(int p, const LevelDev& lv2, const double* T, const double* cf, const CommonDev& cm,
                                hipStream_t st) {
   if (lv2.nref != 64 || !lv2.S64 || (!lv2.L64 && !lv2.L32) || !T || !cf) return hipErrorInvalidValue;

@@ -3,8 +3,8 @@
 The oracle's periodic mode is pinned against the Ewald sum (test_oracle_periodic);
 here the HIP path must match it element by element at the usual gates (FP64
 1e-10, FP32 mixed 1e-4), on a unigrid, on AMR hierarchies whose refinement
-crosses the box faces, in ATS sequences, with the quadrupole cap, and under
-graph replay.  The FP32 regression bound is taken relative to the periodic
+crosses the box faces, in ATS sequences, with the quadrupole cap, under graph
+replay, and in the adjoint (dot-product identity and oracle columns).  The FP32 regression bound is taken relative to the periodic
 forces, which are small against the monopole scale (images and background
 cancel), so it is looser than for isolated boxes.
 """
@@ -139,13 +139,68 @@ def test_periodic_graph_replay_is_bitwise_eager():
     graph.close()
 
 
+@pytest.mark.parametrize("name,p", [("uni3", 4), ("corner", 6), ("face", 8)])
+def test_periodic_adjoint_dot_product_and_oracle_columns(name, p):
+    """<A m, bar> = <m, A^T bar> to round-off (FP64), the FP32 form's adjoint close to
+    it, and a few entries of A^T bar against the oracle's periodic columns
+    (A^T bar)_i = <A e_i, bar>."""
+    h, m = _case(name)
+    rng = np.random.default_rng(p)
+    pb, ab = rng.standard_normal(h.total), rng.standard_normal((h.total, 3))
+    leaf = h.leaf_mask()
+    res = {}
+    for precision, kw in (("fp64", {}), ("fp32", {"fp64_levels": 2})):
+        plan = A.Plan(h, p=p, precision=precision, periodic=True, **kw)
+        mt = torch.from_numpy(m).cuda()
+        phi, acc = plan.solve(mt)
+        mb = plan.solve_adjoint(torch.from_numpy(pb).cuda(), torch.from_numpy(ab).cuda())
+        torch.cuda.synchronize()
+        res[precision] = (phi.cpu().numpy(), acc.cpu().numpy(), mb.cpu().numpy())
+        plan.close()
+    phi, acc, mb = res["fp64"]
+    assert np.all(mb[~leaf] == 0.0)
+    lhs = float(np.dot(phi[leaf], pb[leaf]) + np.sum(acc[leaf] * ab[leaf]))
+    rhs = float(np.dot(m[leaf], mb[leaf]))
+    scale = float(np.dot(np.abs(phi[leaf]), np.abs(pb[leaf])) + np.sum(np.abs(acc[leaf] * ab[leaf])))
+    assert abs(lhs - rhs) <= 1e-12 * scale, (lhs, rhs, scale)
+    mb32 = res["fp32"][2]
+    assert np.linalg.norm(mb32[leaf] - mb[leaf]) <= 1e-5 * np.linalg.norm(mb[leaf])
+    o = oracle.Oracle(h, p, periodic=True)
+    for i in rng.choice(np.nonzero(leaf)[0], size=3, replace=False):
+        e = np.zeros(h.total)
+        e[i] = 1.0
+        po, ao = o.solve_all(e)
+        col = float(np.dot(po[leaf], pb[leaf]) + np.sum(ao[leaf] * ab[leaf]))
+        assert abs(col - mb[i]) <= 1e-10 * max(abs(col), 1.0), (i, col, mb[i])
+    o.close()
+
+
+def test_periodic_noalloc_adjoint_equals_adjoint():
+    import ctypes as C
+    from paper_2607_19489_amd import _lib
+    h, m = _case("uni3")
+    plan = A.Plan(h, p=5, precision="fp64", periodic=True)
+    mt = torch.from_numpy(m).cuda()
+    plan.solve(mt)
+    rng = np.random.default_rng(3)
+    pb = torch.from_numpy(rng.standard_normal(h.total)).cuda()
+    ab = torch.from_numpy(rng.standard_normal((h.total, 3))).cuda()
+    mb = torch.zeros(h.total, dtype=torch.float64, device="cuda")
+    rc = _lib.lib().afmm_solve_adjoint_noalloc(plan.handle, A.AFMM_ALL_LEVELS, C.c_void_p(pb.data_ptr()),
+                                               C.c_void_p(ab.data_ptr()), C.c_void_p(mb.data_ptr()),
+                                               C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert rc == 0
+    ref = plan.solve_adjoint(pb, ab)
+    torch.cuda.synchronize()
+    assert torch.equal(mb, ref)
+    plan.close()
+
+
 def test_periodic_refusals():
     h, m = _case("uni3")
     plan = A.Plan(h, p=4, precision="fp64", periodic=True)
     mt = torch.from_numpy(m).cuda()
-    phi, acc = plan.solve(mt)
-    with pytest.raises(A.AfmmError):
-        plan.solve_adjoint(torch.ones_like(phi), torch.ones_like(acc))
+    plan.solve(mt)
     with pytest.raises(A.AfmmError):
         A.Batch([plan])
     plan.close()

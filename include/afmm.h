@@ -91,9 +91,9 @@ typedef int32_t afmm_status;
                                 Needs levelmin >= 3 and a hierarchy graded on the torus (the
                                 grading rule with wrapped neighbours), else AFMM_E_UNSUPPORTED /
                                 AFMM_E_NOT_GRADED.  Full and ATS solves, drifted solves, re-planning,
-                                graph replay and the adjoint work as for isolated boxes; batches
-                                return AFMM_E_UNSUPPORTED.  The first plan of each order p computes
-                                the operator table on the host (about a second at p = 6). */
+                                graph replay, the adjoint and batches (of periodic plans only) work
+                                as for isolated boxes.  The first plan of each order p computes the
+                                operator table on the host (about a second at p = 6). */
 
 #define AFMM_ALL_LEVELS (-1) /* synchronous solve: all trees rebuilt, every leaf evaluated */
 

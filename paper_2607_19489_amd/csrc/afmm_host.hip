@@ -2844,14 +2844,13 @@ static afmm_status afmm_batch_create_impl(afmm_plan* const* plans, int32_t n, vo
     if (!Q) return fail(AFMM_E_INVALID_ARG, "null plan in batch");
     if (Q->dead) return fail(AFMM_E_DEVICE, "a plan of the batch is unusable after a device error");
     if (Q->topo.levelmin.size() != 1) return fail(AFMM_E_INVALID_ARG, "a batch takes single-hierarchy plans");
-    if (Q->topo.periodic) return fail(AFMM_E_UNSUPPORTED, "periodic boxes: no batch");
     const afmm_options& o = Q->opt;
-    const uint32_t kModel = AFMM_PAPER_QUAD_CAP | AFMM_SELF_POTENTIAL;
+    const uint32_t kModel = AFMM_PAPER_QUAD_CAP | AFMM_SELF_POTENTIAL | AFMM_PERIODIC;
     if (o.p != o0.p || o.precision != o0.precision || o.G != o0.G || o.boxlen != o0.boxlen ||
         o.fp64_levels != o0.fp64_levels || o.tap_split != o0.tap_split || ((o.flags ^ o0.flags) & kModel))
       return fail(AFMM_E_INVALID_ARG,
                   "plans of a batch must share p, precision, G, boxlen, fp64_levels, tap_split and the "
-                  "quadrupole-cap / self-potential flags");
+                  "quadrupole-cap / self-potential / periodic flags");
   }
   afmm_batch* B = new afmm_batch();
   try {
@@ -2859,8 +2858,9 @@ static afmm_status afmm_batch_create_impl(afmm_plan* const* plans, int32_t n, vo
     B->plan = new afmm_plan();
     afmm_plan* P = B->plan;
     P->opt = o0;
-    P->opt.flags = o0.flags & (AFMM_PAPER_QUAD_CAP | AFMM_SELF_POTENTIAL);
+    P->opt.flags = o0.flags & (AFMM_PAPER_QUAD_CAP | AFMM_SELF_POTENTIAL | AFMM_PERIODIC);
     P->K = nmi(o0.p);
+    P->topo.periodic = (o0.flags & AFMM_PERIODIC) != 0;
     B->base.assign(n + 1, 0);
     for (int32_t i = 0; i < n; ++i) {
       merge_topology(P->topo, plans[i]->topo, B->base[i]);

@@ -220,9 +220,10 @@ std::shared_ptr<const std::vector<double>> periodic_far_table(int p) {
 }
 
 // L~(y) = sum_s sum_a cf_a T~[o_y][s - y]_{a+b} S~_a(s) for the 64 level-2
-// cells (all refined: level 2 lies above levelmin, so rank = cell index, and
-// cell c = 8 o1 + o2 sits at 2 bit(o1) + bit(o2) per axis).  One block per
-// target, the 64 source rows in LDS, thread = coefficient b.
+// cells of each hierarchy (all refined: level 2 lies above levelmin, so rank =
+// cell index; hierarchy j of a batch owns cells 64 j .. 64 j + 63, and local
+// cell c = 8 o1 + o2 sits at 2 bit(o1) + bit(o2) per axis).  Block (target,
+// hierarchy), the hierarchy's 64 source rows in LDS, thread = coefficient b.
 template <int P>
 __global__ __launch_bounds__(256) void k_periodic_far(LevelDev lv2, const double* __restrict__ T,
                                                       const double* __restrict__ cf,
@@ -231,7 +232,8 @@ __global__ __launch_bounds__(256) void k_periodic_far(LevelDev lv2, const double
   constexpr int K = nmi(P);
   __shared__ double sS[64 * K];
   const int y = blockIdx.x;
-  for (int i = threadIdx.x; i < 64 * K; i += 256) sS[i] = cf[i % K] * lv2.S64[i];
+  const size_t base = (size_t)blockIdx.y * 64;   // the hierarchy's first level-2 cell
+  for (int i = threadIdx.x; i < 64 * K; i += 256) sS[i] = cf[i % K] * lv2.S64[base * K + i];
   __syncthreads();
   const int b = threadIdx.x;
   if (b >= K) return;
@@ -246,8 +248,8 @@ __global__ __launch_bounds__(256) void k_periodic_far(LevelDev lv2, const double
     const double* Sr = sS + s * K;
     for (int a = 0; a < na; ++a) acc += Tr[si[a]] * Sr[a];
   }
-  if (lv2.L64) lv2.L64[(size_t)y * K + b] = acc;
-  else lv2.L32[(size_t)y * K + b] = (float)acc;
+  if (lv2.L64) lv2.L64[(base + y) * K + b] = acc;
+  else lv2.L32[(base + y) * K + b] = (float)acc;
 }
 
 // Adjoint: the bars of the level-2 multipoles, S~bar_a(s) += cf_a sum_y sum_b
@@ -297,11 +299,13 @@ hipError_t launch_adj_periodic_far(int p, const LevelDev& lv2, const double* T, 
 
 hipError_t launch_periodic_far(int p, const LevelDev& lv2, const double* T, const double* cf, const CommonDev& cm,
                                hipStream_t st) {
-  if (lv2.nref != 64 || !lv2.S64 || (!lv2.L64 && !lv2.L32) || !T || !cf) return hipErrorInvalidValue;
+  if (lv2.nref <= 0 || lv2.nref % 64 || !lv2.S64 || (!lv2.L64 && !lv2.L32) || !T || !cf)
+    return hipErrorInvalidValue;
+  const dim3 grid(64, lv2.nref / 64);
   switch (p) {
 #define X(PP)                                                                                          \
   case PP:                                                                                             \
-    hipLaunchKernelGGL((k_periodic_far<PP>), dim3(64), dim3(256), 0, st, lv2, T, cf, cm.sumidx, cm.mi); \
+    hipLaunchKernelGGL((k_periodic_far<PP>), grid, dim3(256), 0, st, lv2, T, cf, cm.sumidx, cm.mi);     \
     break;
     X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8)
 #undef X

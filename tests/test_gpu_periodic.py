@@ -4,7 +4,7 @@ The oracle's periodic mode is pinned against the Ewald sum (test_oracle_periodic
 here the HIP path must match it element by element at the usual gates (FP64
 1e-10, FP32 mixed 1e-4), on a unigrid, on AMR hierarchies whose refinement
 crosses the box faces, in ATS sequences, with the quadrupole cap, under graph
-replay, and in the adjoint (dot-product identity and oracle columns).  The FP32 regression bound is taken relative to the periodic
+replay, in the adjoint (dot-product identity and oracle columns) and in batches.  The FP32 regression bound is taken relative to the periodic
 forces, which are small against the monopole scale (images and background
 cancel), so it is looser than for isolated boxes.
 """
@@ -196,13 +196,32 @@ def test_periodic_noalloc_adjoint_equals_adjoint():
     plan.close()
 
 
-def test_periodic_refusals():
-    h, m = _case("uni3")
-    plan = A.Plan(h, p=4, precision="fp64", periodic=True)
-    mt = torch.from_numpy(m).cuda()
-    plan.solve(mt)
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_periodic_batch_equals_individual_bitwise(precision):
+    names = ["uni3", "corner", "face", "uni4"]
+    plans = [A.Plan(_case(n)[0], p=5, precision=precision, periodic=True, tap_split=2) for n in names]
+    masses = [torch.from_numpy(_case(n)[1]).cuda() for n in names]
+    ref = []
+    for pl, m in zip(plans, masses):
+        phi, acc = pl.solve(m)
+        ref.append((phi.clone(), acc.clone()))
+    batch = A.Batch(plans)
+    for rep in range(2):
+        phis, accs = batch.solve(masses)
+        torch.cuda.synchronize()
+        for i, n in enumerate(names):
+            leaf = torch.from_numpy(_case(n)[0].leaf_mask()).cuda()
+            assert torch.equal(phis[i][leaf], ref[i][0][leaf]) and torch.equal(accs[i][leaf], ref[i][1][leaf]), (n, rep)
+    batch.close()
+    # isolated and periodic plans do not mix in a batch
+    iso = A.Plan(_case("uni3")[0], p=5, precision=precision, tap_split=2)
     with pytest.raises(A.AfmmError):
-        A.Batch([plan])
-    plan.close()
+        A.Batch([plans[0], iso])
+    iso.close()
+    for pl in plans:
+        pl.close()
+
+
+def test_periodic_refusals():
     with pytest.raises(A.AfmmError):
         A.Plan(unigrid(2), p=4, periodic=True)

@@ -33,7 +33,7 @@ METRIC = "cells/sec full FMM solve (φ+accel) at rel. force err ≤1e-4, FP32 vs
 PEAK = {"fp32_mfma": 157.3, "fp64_mfma": 78.6, "fp32_vector": 157.3, "fp64_vector": 78.6, "hbm": 8000.0}
 KERNEL_NAMES = {"near_f32": "k_near<float, P>", "near_f64": "k_near<double, P>",
                 "m2l_f32": "k_m2l_mfma<float, P>", "m2l_f64": "k_m2l_mfma<double, P>",
-                "m2p_f32": "k_m2p<float, P>", "m2p_f64": "k_m2p<double, P>",
+                "m2p_f32": "k_m2p<float, P, XB>", "m2p_f64": "k_m2p<double, P, XB>",
                 "l2l": "k_l2l<T, TL, P>", "upward": "k_upward<P>", "gather": "k_gather_mass",
                 "adj_near": "k_adj_near_leaf + k_adj_near_m2p<P>", "adj_m2p": "k_adj_m2p<P>",
                 "adj_m2l": "k_adj_m2l<P>", "adj_tree": "k_adj_l2l/k_adj_down/k_adj_out"}
@@ -291,16 +291,18 @@ def time_form(h, mass_t, p, precision, steps, warmup, overlap=False, autotune=Tr
     return out, phi_np, acc_np
 
 
-SYMBOLS = {"m2p_f32": "k_m2p<float, {p}>", "m2p_f64": "k_m2p<double, {p}>",
+SYMBOLS = {"m2p_f32": "k_m2p<float, {p}, {xb}>", "m2p_f64": "k_m2p<double, {p}, {xb}>",
            "m2l_f32": "k_m2l_mfma<float, {p}>", "m2l_f64": "k_m2l_mfma<double, {p}>",
            "near_f32": "k_near<float, {p}>", "near_f64": "k_near<double, {p}>", "upward": "k_upward<{p}>"}
 
 
 def m2p_kernel_symbol(family, p, shape):
-    """rocprofv3's name of the M2P kernel that the tuned tile shape launches."""
-    if family == "m2p_f32" and shape:
+    """rocprofv3's name of the M2P kernel that the tuned tile shape launches
+    (shapes 1 and 2 the row-staged kernel, 0 and 3 the direct one without and
+    with crossbar B fragments)."""
+    if family == "m2p_f32" and shape in (1, 2):
         return f"k_m2p_s<float, {p}, {shape}>"
-    return SYMBOLS.get(family, "").format(p=p)
+    return SYMBOLS.get(family, "").format(p=p, xb="true" if shape == 3 else "false")
 
 
 def measured_traffic(family, p, workload, shape=0):
@@ -325,9 +327,12 @@ def roofline(res, precision, p=None, workload=None):
     prof = res["kernels"]
     name, k = max(prof.items(), key=lambda kv: kv[1]["ms"])
     total_ms = sum(v["ms"] for v in prof.values())
-    shape = ((res.get("autotune") or {}).get("m2p_shape") or [0, 0])[1]
+    shape = ((res.get("autotune") or {}).get("m2p_shape") or [0, 0])[1 if name.endswith("f32") else 0]
     traffic, tsrc = measured_traffic(name, p, workload, shape) if p is not None else (None, None)
-    kname = f"k_m2p_s<float, P, {shape}>" if name == "m2p_f32" and shape else KERNEL_NAMES.get(name, name)
+    kname = KERNEL_NAMES.get(name, name)
+    if name.startswith("m2p_"):
+        kname = (f"k_m2p_s<float, P, {shape}>" if shape in (1, 2) and name == "m2p_f32"
+                 else kname.replace("XB", "true" if shape == 3 else "false"))
     common = {"kernel": kname, "family": name, "launches": k["launches"],
               "traffic_source": tsrc,
               "avg_launch_ms": k["ms"] / max(k["launches"], 1),

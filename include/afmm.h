@@ -110,15 +110,17 @@ typedef struct afmm_options {
                                 fixed order; 0 = automatic (enough blocks to fill the GPU), else
                                 1..21.  Results depend on it only through FP rounding order. */
   size_t max_device_bytes;   /* cap on the plan's device memory; 0 = no cap */
-  int32_t m2p_shape;         /* tile shape of the FP32 intermediate-field (M2P) launch: 0 = one
+  int32_t m2p_shape;         /* tile shape of the intermediate-field (M2P) launch: 0 = one
                                 16-group tile per wave with each lane loading its own B
                                 fragments (default), 1 = the same tile with the source rows
                                 loaded row by row and staged through LDS, 2 = as 1 with two
-                                16-group tiles of one parity class per wave (p <= 5).  FP64
-                                launches always use shape 0; a shape the order does not support
-                                falls back to 0.  The autotuner chooses it by timing.  Results
-                                depend on it only through FP rounding order (none: every shape
-                                sums in the same order). */
+                                16-group tiles of one parity class per wave (p <= 5), 3 = as 0
+                                with the source rows loaded row by row and each lane's
+                                fragments taken from other lanes over the cross-lane crossbar
+                                (no LDS staging).  FP64 launches run shapes 0 and 3 (3 up to p = 7); a shape
+                                the order or precision does not support falls back to 0.  The
+                                autotuner chooses it by timing.  Results do not depend on it:
+                                every shape runs the same products in the same order. */
 } afmm_options;
 
 /* Defaults: p = 4, FP64, G = 1, boxlen = 1, no flags, fp64_levels = 3, tap_split = 0 (automatic),

@@ -1053,7 +1053,7 @@ afmm_status check_options(const afmm_options* o) {
   if (!(o->boxlen > 0) || !std::isfinite(o->boxlen)) return fail(AFMM_E_INVALID_ARG, "boxlen must be > 0");
   if (!std::isfinite(o->G)) return fail(AFMM_E_INVALID_ARG, "G must be finite");
   if (o->tap_split < 0 || o->tap_split > 21) return fail(AFMM_E_UNSUPPORTED, "tap_split must be in 0..21");
-  if (o->m2p_shape < 0 || o->m2p_shape > 2) return fail(AFMM_E_UNSUPPORTED, "m2p_shape must be in 0..2");
+  if (o->m2p_shape < 0 || o->m2p_shape > 3) return fail(AFMM_E_UNSUPPORTED, "m2p_shape must be in 0..3");
   return AFMM_OK;
 }
 
@@ -2249,7 +2249,7 @@ afmm_status autotune_core(afmm_plan* P, SolveFn solve, hipStream_t st, afmm_tune
     if (P->m2p_all[pr].ntiles == 0) continue;
     double best = 1e300;
     int arg = P->m2p_split[pr], arg_shape = P->m2p_shape[pr];
-    for (int shape = 0; shape <= 2; ++shape) {
+    for (int shape = 0; shape <= 3; ++shape) {
       if (!m2p_shape_ok(P->opt.p, pr == 1, shape) || (shape == 2 && P->m2p_all2[pr].ntiles == 0)) continue;
       P->m2p_shape[pr] = shape;
       const double before_shape = best;

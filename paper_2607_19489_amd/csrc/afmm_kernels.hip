@@ -518,6 +518,34 @@ __device__ inline T bfrag_m0(int sr, double vm, T b0) {
   return (sr <= -2 && ((threadIdx.x & 63) >> 4) == 0) ? (T)vm : b0;
 }
 
+// The same run of steps loaded row by row: lane 4 r + q takes vector j of lane
+// group q of row r, so the 4 lanes of every quad read one contiguous 64-byte
+// piece of one row (one cache-line lookup per quad instead of four), and step
+// kb of column n, group g is then found in lane 4 n + g (xb_take).
+template <typename T, int P, int NS>
+__device__ inline void load_brows_xb(int rr, int zrow, gptr<T> S1, typename Vec16<T>::type* vb) {
+  using TS = TapStage<T, P>;
+  using V = typename Vec16<T>::type;
+  constexpr int NF = NS / TS::VW, R = NS % TS::VW;
+  gptr<T> src = S1 + (size_t)(rr >= 0 ? rr : zrow) * TS::ROW;
+  const int q = threadIdx.x & 3;
+#pragma unroll
+  for (int j = 0; j < NF; ++j) vb[j] = *(gptr<V>)(src + src_vec(j, q, (int)sizeof(T)));
+#pragma unroll
+  for (int r = 0; r < R; ++r) vb[NF][r] = src[src_vec(NF, q, (int)sizeof(T)) + r];
+}
+// B fragment value of this lane from the lane whose byte address is xa (the
+// cross-lane crossbar; no LDS memory is touched)
+__device__ inline float xb_take(int xa, float v) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(xa, __float_as_int(v)));
+}
+__device__ inline double xb_take(int xa, double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_ds_bpermute(xa, (int)(b & 0xffffffffll));
+  const int hi = __builtin_amdgcn_ds_bpermute(xa, (int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // D~ stage of tap `code` (rows already in the LDS layout): NTH threads copy
 // its NDV 16-byte vectors, thread t taking vectors t, t + NTH, ...
 template <typename T, int P, int NTH>
@@ -581,11 +609,15 @@ __device__ inline void tile_setup(const int32_t* __restrict__ rec, int NC, const
 // For FP32 from p = 6 on the launcher sizes the LDS source table for 2 waves
 // per SIMD (the best measured there); the same bound lets the compiler use the
 // registers of that occupancy.
-template <typename T, int P>
-constexpr int m2p_max_waves() { return sizeof(T) == 4 && P >= 6 ? 2 : 8; }
+// XB (tile shape 3): the B rows are loaded row by row (load_brows_xb) and each
+// step's fragment is taken from its lane over the crossbar, which cuts the L1
+// tag lookups of the B loads by 4x; the MFMAs, operands and order are those of
+// the direct form, so the results are identical.
+template <typename T, int P, bool XB>
+constexpr int m2p_max_waves() { return sizeof(T) == 4 && P >= 6 ? (XB ? 4 : 2) : 8; }
 
-template <typename T, int P>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, m2p_max_waves<T, P>()))) void k_m2p(const int32_t* __restrict__ tiles, int ntiles, int nsplit,
+template <typename T, int P, bool XB>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(XB && sizeof(T) == 4 && P == 6 ? 4 : 1, m2p_max_waves<T, P, XB>()))) void k_m2p(const int32_t* __restrict__ tiles, int ntiles, int nsplit,
                                             const int32_t* __restrict__ taps, const int16_t* __restrict__ aoff,
                                             const LevelDev* __restrict__ lvs, const T* __restrict__ Dst) {
   using TS = TapStage<T, P>;
@@ -642,43 +674,121 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, m2p_max_w
   // sources of every tap of the range
   const int nt = te - tb;
   const int32_t* tp = tpg;
-  for (int i = lane; i < nt * 16; i += 64) sSrcT[i] = tap_src(tp[i >> 4], i & 15, sCB, rank1);
-  __syncthreads();
+  if constexpr (!XB) {
+    for (int i = lane; i < nt * 16; i += 64) sSrcT[i] = tap_src(tp[i >> 4], i & 15, sCB, rank1);
+    __syncthreads();
+  }
   const int zrow = lv1.nref;
-  V bA[NV], bB[NV];
   V vD[ND];
-  double vmA = 0, vmB = 0;
-  int srA = sSrcT[n], srB = -1;
-  load_bfrag_nb<T, P, ST0>(srA, zrow, mass1, S1, bA, vmA);
-  load_dstage<T, P, 64>(tp[0], Dst, vD);
-  store_dstage<T, P, 64>(sD[0], vD);
-  __syncthreads();
   typename Acc4<T>::type acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
   // Taps run in pairs; an odd range ends with one empty tap (no source, so B
   // is zero; the D~ stage repeats the last tap's finite rows), so that both
   // halves of a pair and every load run unconditionally.
   const int nt2 = (nt + 1) & ~1;
-  // one tap: prefetch tap k + 1 (D~ rows into vD, B into bn), MFMAs of tap k
-  // from bc and the LDS stage sD[b]
-  auto step = [&](int k, int b, const V* bc, int src, double vmc, V* bn, int& srn, double& vmn) {
-    const int k1 = k + 1 < nt ? k + 1 : nt - 1;
-    load_dstage<T, P, 64>(tp[k1], Dst, vD);
-    srn = k + 1 < nt ? sSrcT[k1 * 16 + n] : -1;
-    load_bfrag_nb<T, P, ST0>(srn, zrow, mass1, S1, bn, vmn);
-    __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the MFMAs
-    const T* D = sD[b];
+  if constexpr (XB) {
+    // One set of source rows in flight (tap k + 1, loaded row by row) and one
+    // set of fragments in use (tap k): after tap k's MFMAs the rows of tap
+    // k + 1, loaded a whole tap earlier, pass over the crossbar into the
+    // fragments, so no MFMA waits on the crossbar.  No source table: each
+    // lane resolves the two sources it needs (column xrow for its row loads,
+    // column n for the monopole slot) two taps ahead, the rank lookup being
+    // a load that lands while a tap runs; the block's LDS is then small
+    // enough for 4 waves per SIMD.
+    const int xrow = lane >> 2, xa = 4 * (4 * n + (lane >> 4));
+    V braw[NV];
+    T frag[ST0];
+    auto cell_of = [&](int code, int col) {
+      const int cb = sCB[col * 27 + (code & 31)];
+      return cb < 0 ? -1 : cb + ((code >> 5) & 7);
+    };
+    // source code of a column (as tap_src) from its cell and rank, or -1
+    // past the range
+    auto fin = [](bool valid, int c, int rk) { return !valid || c < 0 ? -1 : (rk >= 0 ? rk : -2 - c); };
+    // tap k + 1: cells and rank loads in flight; tap k + 2 likewise
+    int cR1, cC1, kR1, kC1, cR2, cC2, kR2, kC2;
+    auto resolve = [&](int k, int& cR, int& cC, int& kR, int& kC) {
+      const int code = tp[k < nt ? k : nt - 1];
+      cR = cell_of(code, xrow);
+      cC = cell_of(code, n);
+      kR = rank1[cR >= 0 ? cR : 0];
+      kC = rank1[cC >= 0 ? cC : 0];
+    };
+    auto load_rows = [&](int srow, int scol, double& vm) {
+      load_brows_xb<T, P, ST0>(srow, zrow, S1, braw);
+      vm = mass1[scol <= -2 ? -2 - scol : 0];  // unconditional (a select on it would wait)
+    };
+    auto take = [&](int sr, double vm) {
 #pragma unroll
-    for (int kb = 0; kb < ST0; ++kb) {
-      const T bv = kb == 0 ? bfrag_m0<T>(src, vmc, bc[0][0]) : bc[kb / TS::VW][kb % TS::VW];
-      acc0 = mfma16(D[off0[kb]], bv, acc0);
-      if (kb < ST1) acc1 = mfma16(D[off1[kb]], bv, acc1);
+      for (int kb = 0; kb < ST0; ++kb) frag[kb] = xb_take(xa, braw[kb / TS::VW][kb % TS::VW]);
+      frag[0] = bfrag_m0<T>(sr, vm, frag[0]);
+    };
+    {
+      int cR0, cC0, kR0, kC0;
+      resolve(0, cR0, cC0, kR0, kC0);
+      const int sc0 = fin(true, cC0, kC0);
+      double vm0;
+      load_rows(fin(true, cR0, kR0), sc0, vm0);
+      load_dstage<T, P, 64>(tp[0], Dst, vD);
+      resolve(1, cR1, cC1, kR1, kC1);
+      store_dstage<T, P, 64>(sD[0], vD);
+      take(sc0, vm0);
     }
-    store_dstage<T, P, 64>(sD[b ^ 1], vD);
     __syncthreads();
-  };
-  for (int k = 0; k < nt2; k += 2) {
-    step(k, 0, bA, srA, vmA, bB, srB, vmB);
-    step(k + 1, 1, bB, srB, vmB, bA, srA, vmA);
+    auto step = [&](int k, int b) {
+      const bool v1 = k + 1 < nt;
+      const int srn = fin(v1, cC1, kC1);
+      const int srr = fin(v1, cR1, kR1);
+      load_dstage<T, P, 64>(tp[v1 ? k + 1 : nt - 1], Dst, vD);
+      double vmn;
+      load_rows(srr, srn, vmn);
+      resolve(k + 2, cR2, cC2, kR2, kC2);
+      __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the MFMAs
+      const T* D = sD[b];
+#pragma unroll
+      for (int kb = 0; kb < ST0; ++kb) {
+        acc0 = mfma16(D[off0[kb]], frag[kb], acc0);
+        if (kb < ST1) acc1 = mfma16(D[off1[kb]], frag[kb], acc1);
+      }
+      __builtin_amdgcn_sched_barrier(0);  // the next fragments after the MFMAs
+      take(srn, vmn);
+      store_dstage<T, P, 64>(sD[b ^ 1], vD);
+      cR1 = cR2, cC1 = cC2, kR1 = kR2, kC1 = kC2;
+      __syncthreads();
+    };
+    for (int k = 0; k < nt2; k += 2) {
+      step(k, 0);
+      step(k + 1, 1);
+    }
+  } else {
+    V bA[NV], bB[NV];
+    double vmA = 0, vmB = 0;
+    int srA = sSrcT[n], srB = -1;
+    load_bfrag_nb<T, P, ST0>(srA, zrow, mass1, S1, bA, vmA);
+    load_dstage<T, P, 64>(tp[0], Dst, vD);
+    store_dstage<T, P, 64>(sD[0], vD);
+    __syncthreads();
+    // one tap: prefetch tap k + 1 (D~ rows into vD, B into bn), MFMAs of tap k
+    // from bc and the LDS stage sD[b]
+    auto step = [&](int k, int b, const V* bc, int src, double vmc, V* bn, int& srn, double& vmn) {
+      const int k1 = k + 1 < nt ? k + 1 : nt - 1;
+      load_dstage<T, P, 64>(tp[k1], Dst, vD);
+      srn = k + 1 < nt ? sSrcT[k1 * 16 + n] : -1;
+      load_bfrag_nb<T, P, ST0>(srn, zrow, mass1, S1, bn, vmn);
+      __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the MFMAs
+      const T* D = sD[b];
+#pragma unroll
+      for (int kb = 0; kb < ST0; ++kb) {
+        const T bv = kb == 0 ? bfrag_m0<T>(src, vmc, bc[0][0]) : bc[kb / TS::VW][kb % TS::VW];
+        acc0 = mfma16(D[off0[kb]], bv, acc0);
+        if (kb < ST1) acc1 = mfma16(D[off1[kb]], bv, acc1);
+      }
+      store_dstage<T, P, 64>(sD[b ^ 1], vD);
+      __syncthreads();
+    };
+    for (int k = 0; k < nt2; k += 2) {
+      step(k, 0, bA, srA, vmA, bB, srB, vmB);
+      step(k + 1, 1, bB, srB, vmB, bA, srA, vmA);
+    }
   }
   const int F = sF[n];
   if (F >= 0) {
@@ -1457,8 +1567,8 @@ static hipError_t m2p_dispatch(int p, const MfmaTiles& mt, int t0, int n, int ns
   const int items = n * nsplit;
   const dim3 grid(8 * ((items + 7) / 8)), block(64);
   const int32_t* tl = mt.tiles + (size_t)t0 * (mt.nc + 1);
-  if (shape != 0) {
-    if (!m2p_shape_ok(p, sizeof(T) == 4, shape) || mt.nc != m2p_shape_columns(shape)) return hipErrorInvalidValue;
+  if (!m2p_shape_ok(p, sizeof(T) == 4, shape) || mt.nc != m2p_shape_columns(shape)) return hipErrorInvalidValue;
+  if (shape == 1 || shape == 2) {
     if constexpr (sizeof(T) == 4) {
       switch (p * 4 + shape) {
 #define AFMM_M2PS(PP, SH)                                                                                      \
@@ -1475,7 +1585,6 @@ static hipError_t m2p_dispatch(int p, const MfmaTiles& mt, int t0, int n, int ns
     }
     return hipErrorInvalidValue;
   }
-  if (mt.nc != 16) return hipErrorInvalidValue;
   // LDS source table of k_m2p: the longest tap range of the split, except
   // for FP32 from p = 6 on, where the table keeps all 189 taps so that the
   // block's LDS (about 20 KB) holds the kernel at 2 waves per SIMD.  Measured:
@@ -1489,14 +1598,22 @@ static hipError_t m2p_dispatch(int p, const MfmaTiles& mt, int t0, int n, int ns
     tap_range(c, nsplit, tb, te);
     ntmax = std::max(ntmax, te - tb);
   }
-  const size_t lds = (size_t)(sizeof(T) == 4 && p >= 6 ? kTaps : ntmax) * 16 * sizeof(int);
-  switch (p) {
-#define AFMM_M2P(PP)                                                                                                \
-  case PP:                                                                                                    \
-    hipLaunchKernelGGL((k_m2p<T, PP>), grid, block, lds, st, tl, n, nsplit, tabs.taps, tabs.m2p_off, lvs, Dst);  \
+  const size_t lds = shape == 3 ? 0 : (size_t)(sizeof(T) == 4 && p >= 6 ? kTaps : ntmax) * 16 * sizeof(int);
+  switch (p * 2 + (shape == 3)) {
+#define AFMM_M2P(PP, XB)                                                                                         \
+  case PP * 2 + XB:                                                                                              \
+    hipLaunchKernelGGL((k_m2p<T, PP, XB>), grid, block, lds, st, tl, n, nsplit, tabs.taps, tabs.m2p_off, lvs, Dst); \
     break;
-    AFMM_M2P(1) AFMM_M2P(2) AFMM_M2P(3) AFMM_M2P(4) AFMM_M2P(5) AFMM_M2P(6) AFMM_M2P(7) AFMM_M2P(8)
+    AFMM_M2P(1, 0) AFMM_M2P(2, 0) AFMM_M2P(3, 0) AFMM_M2P(4, 0) AFMM_M2P(5, 0) AFMM_M2P(6, 0) AFMM_M2P(7, 0)
+    AFMM_M2P(8, 0) AFMM_M2P(1, 1) AFMM_M2P(2, 1) AFMM_M2P(3, 1) AFMM_M2P(4, 1) AFMM_M2P(5, 1) AFMM_M2P(6, 1)
+    AFMM_M2P(7, 1)
 #undef AFMM_M2P
+    case 8 * 2 + 1:
+      if constexpr (sizeof(T) == 4) {
+        hipLaunchKernelGGL((k_m2p<T, 8, true>), grid, block, lds, st, tl, n, nsplit, tabs.taps, tabs.m2p_off, lvs, Dst);
+        break;
+      }
+      return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1518,10 +1635,12 @@ int m2p_columns(int p, bool fp32) {
 
 // Tile shapes of the M2P launch: 0 the direct form (16 groups per wave), 1 the
 // row-staged form (16 groups), 2 the row-staged form with two tiles of one
-// parity class per wave (32 groups; up to p = 5, where its registers fit).
-// The staged forms are instantiated for the FP32 kernels only.
+// parity class per wave (32 groups; up to p = 5, where its registers fit),
+// 3 the direct form with row-wise B loads passed over the crossbar (16
+// groups).  The staged forms are instantiated for the FP32 kernels only.
 bool m2p_shape_ok(int p, bool fp32, int shape) {
   if (shape == 0) return true;
+  if (shape == 3) return fp32 || p <= 7;  // FP64 at p = 8 would spill
   if (!fp32) return false;
   return shape == 1 || (shape == 2 && p <= 5);
 }

@@ -108,11 +108,11 @@ def test_max_device_bytes_gives_out_of_memory_before_any_device_call():
 def test_m2p_shape_option_validated():
     h = build_graded(3, 5, refine_sphere((0.5, 0.5, 0.5), {3: 0.3, 4: 0.2}))
     a = A.hierarchy_check(h, p=4, precision="fp32")
-    for shape in (1, 2):
+    for shape in (1, 2, 3):
         assert A.hierarchy_check(h, p=4, precision="fp32", m2p_shape=shape)["flops_m2p"] == a["flops_m2p"]
     # an unsupported combination (two tiles per wave at p = 8, FP64) falls back to shape 0 at plan time
     assert A.hierarchy_check(h, p=8, m2p_shape=2)["nleaves"] == a["nleaves"]
-    for bad in (-1, 3):
+    for bad in (-1, 4):
         with pytest.raises(A.AfmmError):
             A.hierarchy_check(h, p=4, m2p_shape=bad)
 

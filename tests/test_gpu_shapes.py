@@ -1,12 +1,14 @@
-"""Tile shapes of the FP32 intermediate-field launch (afmm_options.m2p_shape).
+"""Tile shapes of the intermediate-field launch (afmm_options.m2p_shape).
 
 Shape 0 loads each lane's B fragments itself, shape 1 loads the source rows row
 by row and stages them through LDS, shape 2 does the same with two 16-group
-tiles of one parity class per wave.  Every shape runs the same MFMAs in the same
-order on the same operands, so the solves must agree bit for bit; shape 2 is
-also checked against the FP64 oracle, on ragged tiles (parity classes whose
-group counts are not multiples of 32), with tap splits whose ranges cross the
-kernels' source-table chunks, in a batch, and under the autotuner.
+tiles of one parity class per wave, shape 3 loads the rows row by row and takes
+each lane's fragments from other lanes over the crossbar (FP32 and FP64).  Every
+shape runs the same MFMAs in the same order on the same operands, so the solves
+must agree bit for bit; shapes 2 and 3 are also checked against the FP64
+oracle, on ragged tiles (parity classes whose group counts are not multiples of
+32), with tap splits whose ranges cross the kernels' source-table chunks, in a
+batch, and under the autotuner.
 """
 import numpy as np
 import pytest
@@ -36,13 +38,24 @@ def test_shapes_agree_bitwise(h, p, split):
     m = cell_masses(h, plummer(1.0, 0.08), 0.01, 11 * p + split)
     leaf = h.leaf_mask()
     ref = None
-    for shape in (0, 1, 2):
+    for shape in (0, 1, 2, 3):
         phi, acc, _ = gpu_solve(h, m, p, "fp32", m2p_shape=shape, tap_split=split)
         if ref is None:
             ref = (phi, acc)
             continue
         assert np.array_equal(phi[leaf], ref[0][leaf]) and np.array_equal(acc[leaf], ref[1][leaf]), shape
-    print(f"p={p} split={split}: shapes 0..2 bit-identical over {int(leaf.sum())} leaves", flush=True)
+    print(f"p={p} split={split}: shapes 0..3 bit-identical over {int(leaf.sum())} leaves", flush=True)
+
+
+@pytest.mark.parametrize("h,p,split", [(H3, 4, 0), (H4, 6, 3), (H3, 7, 0), (H3, 1, 2)])
+def test_crossbar_fragments_fp64_bitwise_and_against_oracle(h, p, split):
+    m = cell_masses(h, plummer(1.0, 0.08), 0.01, 13 * p + split)
+    leaf = h.leaf_mask()
+    phi0, acc0, _ = gpu_solve(h, m, p, "fp64", m2p_shape=0, tap_split=split)
+    phi3, acc3, _ = gpu_solve(h, m, p, "fp64", m2p_shape=3, tap_split=split)
+    assert np.array_equal(phi3[leaf], phi0[leaf]) and np.array_equal(acc3[leaf], acc0[leaf])
+    po, ao = oracle.Oracle(h, p).solve_all(m)
+    check_errors(phi3[leaf], acc3[leaf], po[leaf], ao[leaf], "fp64", what=f"shape 3 fp64 p={p}")
 
 
 @pytest.mark.parametrize("p", [3, 4, 5])
@@ -78,7 +91,7 @@ def test_autotune_reports_a_supported_shape_and_stays_correct():
     plan = A.Plan(h, p=4, precision="fp32")
     mt = torch.from_numpy(m).cuda()
     res = plan.autotune(mt)
-    assert res["m2p_shape"][0] == 0 and res["m2p_shape"][1] in (0, 1, 2)
+    assert res["m2p_shape"][0] in (0, 3) and res["m2p_shape"][1] in (0, 1, 2, 3)
     phi, acc = plan.solve(mt)
     torch.cuda.synchronize()
     po, ao = oracle.Oracle(h, 4).solve_all(m)

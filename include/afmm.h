@@ -346,11 +346,12 @@ afmm_status afmm_batch_get_profile(afmm_batch* batch, afmm_stage_time* out, int3
  * many blocks share the 189 source offsets of one tile, see tap_split) trades
  * parallelism against partial-sum traffic and per-block setup; the best value
  * depends on the hierarchy's shape.  afmm_plan_autotune times candidate splits
- * (per-launch events, serial launches) on full solves of the caller's data and
- * keeps, per precision, the fastest M2L split and the fastest M2P (tile shape,
- * split) pair (the shapes of afmm_options.m2p_shape that the order and
- * precision support); it
- * leaves phi/acc holding a full solve and counts as one (AFMM_ALL_LEVELS).
+ * (per-launch events, serial launches; each candidate's time is the minimum
+ * over 5 full solves of the caller's data after one warm-up) and keeps, per
+ * precision, the fastest M2L split and the fastest M2P (tile shape, split)
+ * pair (the shapes of afmm_options.m2p_shape that the order and precision
+ * support); it leaves phi/acc holding a full solve and counts as one
+ * (AFMM_ALL_LEVELS).
  * afmm_batch_autotune does the same on a batch and re-captures its graph.
  * Results of later solves change only through FP rounding order.  Takes a few
  * dozen solves; no host-visible allocation beyond the partial-sum buffers.

@@ -2168,19 +2168,26 @@ afmm_status autotune_core(afmm_plan* P, SolveFn solve, hipStream_t st, afmm_tune
     }();
     return cur + split_buffer_bytes(P, P->m2l_split, P->m2p_split) <= P->opt.max_device_bytes;
   };
+  // one warm-up solve and kTimed timed ones; each kind's time is its minimum
+  // over the timed solves (robust to a solve slowed by something else on the
+  // device, where a mean let 1-2% noise decide between candidates)
+  constexpr int kTimed = 5;
   auto measure = [&](double* kind_ms) -> afmm_status {
     afmm_status s;
-    for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < 1 + kTimed; ++r)
       if ((s = solve())) return s;
     if (hipStreamSynchronize(st) != hipSuccess) return fail(AFMM_E_DEVICE, "autotune sync");
-    std::memset(kind_ms, 0, sizeof(double) * kNumKinds);
-    // drop the first solve of the four (warm-up), average the rest
-    size_t per = P->recs.size() / 4;
+    const size_t per = P->recs.size() / (1 + kTimed);
+    double cur[kNumKinds];
+    for (int k = 0; k < kNumKinds; ++k) kind_ms[k] = per ? 1e300 : 0.0;
     for (size_t i = 0; i < P->recs.size(); ++i) {
+      if (i % per == 0) std::memset(cur, 0, sizeof(cur));
       auto& r = P->recs[i];
       float ms = 0.f;
       (void)hipEventElapsedTime(&ms, r.a, r.b);
-      if (i >= per) kind_ms[r.kind] += ms / 3.0;
+      cur[r.kind] += ms;
+      if (i % per == per - 1 && i >= per)
+        for (int k = 0; k < kNumKinds; ++k) kind_ms[k] = std::min(kind_ms[k], cur[k]);
       P->event_pool.push_back(r.a);
       P->event_pool.push_back(r.b);
     }

@@ -351,50 +351,80 @@ hipError_t launch_upward(int p, const int32_t* leaf, int nleaf, const int32_t* m
 // F): L~_b[y] = sum_c Lpart[c][y]_b (the M2L tap sums, split over `nsplit`
 // tap ranges, added in fixed order; or the single sum already in L) + the
 // ShiftLocal term sum_g w_o[|b|][g] L~_{b+g}[F] (Eq. eq:L2L) when F has one.
-template <typename T, typename TL, int P>
+// Three passes over the group's 8K coefficients through LDS: the tap sums
+// and the stores run coefficient-fastest (whole child rows per wave), the
+// shift sums child-fastest; the sums and their order are unchanged.  NS
+// bounds the split (1: the single sum in L): every partial of every
+// coefficient a thread owns is loaded at once, so a block waits for one
+// round of loads rather than one per four partials and coefficient.
+template <typename T, typename TL, int P, int NS>
 __global__ __launch_bounds__(kBlock) void k_l2l(const int32_t* __restrict__ grp, const TL* __restrict__ Lpar,
                                                 const int32_t* __restrict__ rank0, T* __restrict__ Lout,
                                                 const T* __restrict__ Lpart, int nsplit, size_t split_stride,
                                                 const T* __restrict__ w, const int16_t* __restrict__ sumidx,
                                                 const int8_t* __restrict__ mi) {
   constexpr int K = nmi(P);
+  constexpr int KV = K | 1;  // odd LDS row stride: the 8 rows of a wave's loads fall in different banks
   __shared__ T sL[K];
+  __shared__ T sV[8 * KV];
   __shared__ int sRy[8];
   const int F = grp[blockIdx.x];
   const int t = threadIdx.x;
   if (t < K && Lpar) sL[t] = (T)Lpar[(size_t)F * K + t];
   if (t < 8) sRy[t] = rank0[8 * F + t];
   __syncthreads();
-  // child o fastest: the lanes of a wave share few coefficients b, all of
-  // nearly the same degree, so their shift sums have nearly equal lengths
-  for (int i = t; i < 8 * K; i += kBlock) {
-    const int o = i & 7, b = i >> 3;
-    const int ry = sRy[o];
-    if (ry < 0) continue;
-    const size_t at = (size_t)ry * K + b;
-    T v = 0;
-    if (nsplit > 1) {
-      // in order, four loads in flight at a time (the trip count is a runtime value)
-      for (int c0 = 0; c0 < nsplit; c0 += 4) {
-        T x[4];
+  // tap sums, coefficient fastest (each child's row is read contiguously);
+  // a thread owns coefficients t, t + 256, ... (NI of them); a missing child
+  // row reads row 0 and is not stored
+  constexpr int NI = (8 * K + kBlock - 1) / kBlock;
+  {
+    T x[NI][NS];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) x[j] = Lpart[min(c0 + j, nsplit - 1) * split_stride + at];
+    for (int j = 0; j < NI; ++j) {
+      const int i = min(t + kBlock * j, 8 * K - 1), o = i / K, b = i - o * K;
+      const int ry = sRy[o];
+      const size_t at = (size_t)(ry >= 0 ? ry : 0) * K + b;
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          if (c0 + j < nsplit) v += x[j];
-      }
-    } else {
-      v = Lout[at];
+      for (int c = 0; c < NS; ++c) x[j][c] = NS == 1 ? Lout[at] : Lpart[min(c, nsplit - 1) * split_stride + at];
     }
-    if (Lpar) {
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+      const int i = t + kBlock * j;
+      if (i >= 8 * K) break;
+      const int o = i / K, b = i - o * K;
+      if (sRy[o] < 0) continue;
+      T v = 0;
+      if constexpr (NS == 1) {
+        v = x[j][0];
+      } else {
+#pragma unroll
+        for (int c = 0; c < NS; ++c)
+          if (c < nsplit) v += x[j][c];
+      }
+      sV[o * KV + b] = v;
+    }
+  }
+  __syncthreads();
+  // ShiftLocal, child o fastest: the lanes of a wave share few coefficients
+  // b, all of nearly the same degree, so their shift sums have nearly equal
+  // lengths
+  if (Lpar) {
+    for (int i = t; i < 8 * K; i += kBlock) {
+      const int o = i & 7, b = i >> 3;
+      if (sRy[o] < 0) continue;
       const int nb = mi[4 * b + 3];
       const T* wr = w + ((size_t)o * (P + 1) + nb) * K;
       const int16_t* si = sumidx + (size_t)b * K;
       T sh = 0;
       for (int g = 0; g < nmi(P - nb); ++g) sh += wr[g] * sL[si[g]];
-      v += sh;
+      sV[o * KV + b] += sh;
     }
-    Lout[at] = v;
+    __syncthreads();
+  }
+  for (int i = t; i < 8 * K; i += kBlock) {
+    const int o = i / K, b = i - o * K;
+    const int ry = sRy[o];
+    if (ry >= 0) Lout[(size_t)ry * K + b] = sV[o * KV + b];
   }
 }
 
@@ -1678,13 +1708,17 @@ static hipError_t l2l_dispatch(int p, const int32_t* grp, int ngrp, const TL* Lp
                                const T* Lpart, int nsplit, size_t stride, const T* w, const CommonDev& cm,
                                hipStream_t st) {
   const dim3 grid(ngrp), block(kBlock);
-  switch (p) {
-#define AFMM_L2L(PP)                                                                                             \
-  case PP:                                                                                                       \
-    hipLaunchKernelGGL((k_l2l<T, TL, PP>), grid, block, 0, st, grp, Lpar, rank0, Lout, Lpart, nsplit, stride, w, \
-                       cm.sumidx, cm.mi);                                                                        \
+  if (nsplit < 1 || nsplit > 24) return hipErrorInvalidValue;
+  const int ns = nsplit == 1 ? 0 : nsplit <= 8 ? 1 : 2;  // split bucket: 1, 8 or 24 partials
+  switch (p * 3 + ns) {
+#define AFMM_L2L(PP, NB, NSV)                                                                                    \
+  case PP * 3 + NB:                                                                                              \
+    hipLaunchKernelGGL((k_l2l<T, TL, PP, NSV>), grid, block, 0, st, grp, Lpar, rank0, Lout, Lpart, nsplit,       \
+                       stride, w, cm.sumidx, cm.mi);                                                             \
     break;
-    AFMM_L2L(1) AFMM_L2L(2) AFMM_L2L(3) AFMM_L2L(4) AFMM_L2L(5) AFMM_L2L(6) AFMM_L2L(7) AFMM_L2L(8)
+#define AFMM_L2L3(PP) AFMM_L2L(PP, 0, 1) AFMM_L2L(PP, 1, 8) AFMM_L2L(PP, 2, 24)
+    AFMM_L2L3(1) AFMM_L2L3(2) AFMM_L2L3(3) AFMM_L2L3(4) AFMM_L2L3(5) AFMM_L2L3(6) AFMM_L2L3(7) AFMM_L2L3(8)
+#undef AFMM_L2L3
 #undef AFMM_L2L
     default: return hipErrorInvalidValue;
   }

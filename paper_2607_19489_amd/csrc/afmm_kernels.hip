@@ -236,45 +236,72 @@ __global__ __launch_bounds__(256) void k_upward(const int32_t* __restrict__ list
 // Upward pass for the refined cells whose 8 children are leaves (P2M, Eq.
 // eq:P2M): the signed child sums vanish for k > 0, so coefficient a is the
 // k = 0 entry of its M2M list times one signed sum of the 8 masses (signs by
-// the parity of a).  Thread = (cell of the list, slot a of the source-copy
-// run), no synchronisation; the 8 masses of a cell are one 64-byte run.
+// the parity of a).  A block takes kP2mCells cells of the list: their masses
+// go to LDS, thread (cell, a) forms coefficient a once, and the three copies
+// (S64 in coefficient order, the scaled FP32 and FP64 copies in their
+// lane-group layouts) are written slot by slot in row order, so consecutive
+// threads store consecutive addresses (padding slots get 0).
+constexpr int kP2mCells = 8;
+
 template <int P>
 __global__ __launch_bounds__(256) void k_p2m_leaf(const int32_t* __restrict__ list, int nlist, LevelDev lv,
                                                   LevelDev lvc, CommonDev cm) {
   constexpr int K = nmi(P);
-  constexpr int STP32 = src_stp(P, 4), STP64 = src_stp(P, 8);
-  constexpr int KP = 4 * STP32;
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= (int64_t)nlist * KP) return;
-  const int r = list[i / KP], a = (int)(i % KP);
-  if (a >= K) {  // zero padding of the source copies
-    if (lv.S32) lv.S32[(size_t)r * 4 * STP32 + src_pos(a, 4)] = 0.f;
-    if (lv.Sc64 && a < 4 * STP64) lv.Sc64[(size_t)r * 4 * STP64 + src_pos(a, 8)] = 0.0;
-    return;
-  }
-  gptr<double> m = as_global(lvc.mass) + 8 * (size_t)r;
-  double v[8];
+  constexpr int R32 = src_row(P, 4), R64 = src_row(P, 8);
+  constexpr int NC = kP2mCells;
+  __shared__ int sR[NC];
+  __shared__ double sM[NC][8];
+  __shared__ double sV[NC][K];
+  const int t = threadIdx.x;
+  const int c0 = blockIdx.x * NC;
+  const int nc = min(NC, nlist - c0);
+  if (t < NC) sR[t] = t < nc ? list[c0 + t] : -1;
+  __syncthreads();
+  if (t < 8 * nc) sM[t >> 3][t & 7] = as_global(lvc.mass)[8 * (size_t)sR[t >> 3] + (t & 7)];
+  __syncthreads();
+  for (int i = t; i < nc * K; i += 256) {
+    const int c = i / K, a = i - c * K;
+    double v[8];
 #pragma unroll
-  for (int o = 0; o < 8; ++o) v[o] = m[o];
-  const int e0 = cm.m2m_start[a];
-  const int q = cm.m2m_list[e0] >> 12;
-  // signed sum over the octant bits of q (the butterfly of k_upward, one output)
+    for (int o = 0; o < 8; ++o) v[o] = sM[c][o];
+    const int e0 = cm.m2m_start[a];
+    const int q = cm.m2m_list[e0] >> 12;
+    // signed sum over the octant bits of q (the butterfly of k_upward, one output)
 #pragma unroll
-  for (int bit = 0; bit < 3; ++bit) {
-    double u[8];
+    for (int bit = 0; bit < 3; ++bit) {
+      double u[8];
 #pragma unroll
-    for (int o = 0; o < 8; ++o) {
-      const int lo = o & ~(1 << bit);
-      u[o] = (q & (1 << bit)) ? v[lo | (1 << bit)] - v[lo] : v[lo] + v[lo | (1 << bit)];
+      for (int o = 0; o < 8; ++o) {
+        const int lo = o & ~(1 << bit);
+        u[o] = (q & (1 << bit)) ? v[lo | (1 << bit)] - v[lo] : v[lo] + v[lo | (1 << bit)];
+      }
+#pragma unroll
+      for (int o = 0; o < 8; ++o) v[o] = u[o];
     }
-#pragma unroll
-    for (int o = 0; o < 8; ++o) v[o] = u[o];
+    sV[c][a] = cm.m2m_w[e0] * v[q];
   }
-  const double acc = cm.m2m_w[e0] * v[q];
-  lv.S64[(size_t)r * K + a] = acc;
-  const double sc = acc * cm.cfac2[a];
-  if (lv.S32) lv.S32[(size_t)r * 4 * STP32 + src_pos(a, 4)] = (float)sc;
-  if (lv.Sc64) lv.Sc64[(size_t)r * 4 * STP64 + src_pos(a, 8)] = sc;
+  __syncthreads();
+  // coefficient of slot s of a lane-group-layout row (inverse of src_pos), or
+  // K for a padding slot
+  auto slot_coef = [](int s, int vw) {
+    const int j = s / (4 * vw), g = (s % (4 * vw)) / vw, e = s % vw;
+    const int k = 4 * (vw * j + e) + g;
+    return k < K ? k : K;
+  };
+  for (int i = t; i < nc * K; i += 256) {
+    const int c = i / K, a = i - c * K;
+    lv.S64[(size_t)sR[c] * K + a] = sV[c][a];
+  }
+  if (lv.S32)
+    for (int i = t; i < nc * R32; i += 256) {
+      const int c = i / R32, sl = i - c * R32, k = slot_coef(sl, 4);
+      lv.S32[(size_t)sR[c] * R32 + sl] = k < K ? (float)(sV[c][k] * cm.cfac2[k]) : 0.f;
+    }
+  if (lv.Sc64)
+    for (int i = t; i < nc * R64; i += 256) {
+      const int c = i / R64, sl = i - c * R64, k = slot_coef(sl, 2);
+      lv.Sc64[(size_t)sR[c] * R64 + sl] = k < K ? sV[c][k] * cm.cfac2[k] : 0.0;
+    }
 }
 
 __global__ void k_batch_in(int64_t nleaf, const int32_t* __restrict__ leafslot, const int32_t* __restrict__ leafhier,
@@ -321,7 +348,7 @@ hipError_t launch_upward(int p, const int32_t* leaf, int nleaf, const int32_t* m
                          const LevelDev& lvc, const CommonDev& cm, hipStream_t st) {
   const int KP = src_row(p, 4), CB = 256 / KP;
   if (nleaf > 0) {
-    const dim3 grid((unsigned)(((int64_t)nleaf * KP + 255) / 256)), block(256);
+    const dim3 grid((unsigned)((nleaf + kP2mCells - 1) / kP2mCells)), block(256);
     switch (p) {
 #define AFMM_P2M(PP) \
   case PP: hipLaunchKernelGGL(k_p2m_leaf<PP>, grid, block, 0, st, leaf, nleaf, lv, lvc, cm); break;

@@ -742,7 +742,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(XB && sizeof
   // is zero; the D~ stage repeats the last tap's finite rows), so that both
   // halves of a pair and every load run unconditionally.
   const int nt2 = (nt + 1) & ~1;
-  if constexpr (XB) {
+  if constexpr (XB && P >= 6) {
     // One set of source rows in flight (tap k + 1, loaded row by row) and one
     // set of fragments in use (tap k): after tap k's MFMAs the rows of tap
     // k + 1, loaded a whole tap earlier, pass over the crossbar into the
@@ -810,6 +810,70 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(XB && sizeof
       take(srn, vmn);
       store_dstage<T, P, 64>(sD[b ^ 1], vD);
       cR1 = cR2, cC1 = cC2, kR1 = kR2, kC1 = kC2;
+      __syncthreads();
+    };
+    for (int k = 0; k < nt2; k += 2) {
+      step(k, 0);
+      step(k + 1, 1);
+    }
+  } else if constexpr (XB) {
+    // Short taps (p <= 5): the same crossbar form with source rows and D~
+    // stages loaded two taps ahead (set k & 1 holds tap k's) and the sources
+    // resolved three taps ahead, so that a load has two taps of MFMAs to land.
+    const int xrow = lane >> 2, xa = 4 * (4 * n + (lane >> 4));
+    V braw[2][NV];
+    V vD2[2][ND];
+    T frag[ST0];
+    double vm[2];
+    int sc[2];
+    auto cell_of = [&](int code, int col) {
+      const int cb = sCB[col * 27 + (code & 31)];
+      return cb < 0 ? -1 : cb + ((code >> 5) & 7);
+    };
+    auto fin = [](bool valid, int c, int rk) { return !valid || c < 0 ? -1 : (rk >= 0 ? rk : -2 - c); };
+    int cR, cC, kR, kC;  // the next tap to load: cells and rank loads in flight
+    auto resolve = [&](int k) {
+      const int code = tp[k < nt ? k : nt - 1];
+      cR = cell_of(code, xrow);
+      cC = cell_of(code, n);
+      kR = rank1[cR >= 0 ? cR : 0];
+      kC = rank1[cC >= 0 ? cC : 0];
+    };
+    // tap k into set q (sources from the pending resolution), then resolve k + 1
+    auto prefetch = [&](int k, int q) {
+      const bool v = k < nt;
+      const int srr = fin(v, cR, kR);
+      sc[q] = fin(v, cC, kC);
+      load_dstage<T, P, 64>(tp[v ? k : nt - 1], Dst, vD2[q]);
+      load_brows_xb<T, P, ST0>(srr, zrow, S1, braw[q]);
+      vm[q] = mass1[sc[q] <= -2 ? -2 - sc[q] : 0];  // unconditional (a select on it would wait)
+      resolve(k + 1);
+    };
+    auto take = [&](int q) {
+#pragma unroll
+      for (int kb = 0; kb < ST0; ++kb) frag[kb] = xb_take(xa, braw[q][kb / TS::VW][kb % TS::VW]);
+      frag[0] = bfrag_m0<T>(sc[q], vm[q], frag[0]);
+    };
+    resolve(0);
+    prefetch(0, 0);
+    prefetch(1, 1);
+    store_dstage<T, P, 64>(sD[0], vD2[0]);
+    take(0);
+    __syncthreads();
+    // tap k (stage sD[b], set b): prefetch tap k + 2 into set b, MFMAs of tap
+    // k, then tap k + 1 (set b ^ 1) into the fragments and the other stage
+    auto step = [&](int k, int b) {
+      prefetch(k + 2, b);
+      __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the MFMAs
+      const T* D = sD[b];
+#pragma unroll
+      for (int kb = 0; kb < ST0; ++kb) {
+        acc0 = mfma16(D[off0[kb]], frag[kb], acc0);
+        if (kb < ST1) acc1 = mfma16(D[off1[kb]], frag[kb], acc1);
+      }
+      __builtin_amdgcn_sched_barrier(0);  // the next fragments after the MFMAs
+      take(b ^ 1);
+      store_dstage<T, P, 64>(sD[b ^ 1], vD2[b ^ 1]);
       __syncthreads();
     };
     for (int k = 0; k < nt2; k += 2) {

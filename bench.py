@@ -254,7 +254,13 @@ def run_batch(args):
     print(json.dumps(line), flush=True)
 
 
-def time_form(h, mass_t, p, precision, steps, warmup, overlap=False, autotune=True, graph=False, periodic=False):
+def m2p_shape_ok(p, fp32, shape):
+    """Tile shapes the library runs for this order and precision (afmm_options.m2p_shape)."""
+    return shape == 0 or (shape == 3 and (fp32 or p <= 7)) or (fp32 and (shape == 1 or (shape == 2 and p <= 5)))
+
+
+def time_form(h, mass_t, p, precision, steps, warmup, overlap=False, autotune=True, graph=False, periodic=False,
+              m2p_shape=0):
     """Autotuned plan (tap splits), timed solves (no instrumentation), then the same
     number of profiled solves: the profiled pass runs serially with hipEvents
     around every launch."""
@@ -262,7 +268,7 @@ def time_form(h, mass_t, p, precision, steps, warmup, overlap=False, autotune=Tr
     import paper_2607_19489_amd as A
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plan = A.Plan(h, p=p, precision=precision, overlap=overlap, graph=graph, periodic=periodic)
+    plan = A.Plan(h, p=p, precision=precision, overlap=overlap, graph=graph, periodic=periodic, m2p_shape=m2p_shape)
     torch.cuda.synchronize()
     plan_ms = 1e3 * (time.perf_counter() - t0)
     info = plan.info()
@@ -284,8 +290,12 @@ def time_form(h, mass_t, p, precision, steps, warmup, overlap=False, autotune=Tr
     torch.cuda.synchronize()
     prof = plan.get_profile()
     plan.set_profiling(False)
+    # M2P tile shape that ran, [FP64 kernels, FP32 kernels]: the tuner's, or the
+    # option where the order and precision support it (else the plan used 0)
+    fixed = [m2p_shape if m2p_shape_ok(p, fp32, m2p_shape) else 0 for fp32 in (False, True)]
     out = {"ms_per_step": 1e3 * dt / steps, "value": info["nleaves"] * steps / dt, "info": info,
-           "kernels": prof, "steps": steps, "autotune": tune, "plan_create_ms": plan_ms}
+           "kernels": prof, "steps": steps, "autotune": tune, "plan_create_ms": plan_ms,
+           "m2p_shape": tune["m2p_shape"] if tune else fixed}
     phi_np, acc_np = phi.cpu().numpy(), acc.cpu().numpy()
     plan.close()
     return out, phi_np, acc_np
@@ -327,7 +337,7 @@ def roofline(res, precision, p=None, workload=None):
     prof = res["kernels"]
     name, k = max(prof.items(), key=lambda kv: kv[1]["ms"])
     total_ms = sum(v["ms"] for v in prof.values())
-    shape = ((res.get("autotune") or {}).get("m2p_shape") or [0, 0])[1 if name.endswith("f32") else 0]
+    shape = (res.get("m2p_shape") or [0, 0])[1 if name.endswith("f32") else 0]
     traffic, tsrc = measured_traffic(name, p, workload, shape) if p is not None else (None, None)
     kname = KERNEL_NAMES.get(name, name)
     if name.startswith("m2p_"):
@@ -471,6 +481,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-form run")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tap splits")
+    ap.add_argument("--m2p-shape", type=int, default=0,
+                    help="M2P tile shape of the plans when the autotuner is off (afmm_options.m2p_shape)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy (reference for the FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
@@ -497,17 +509,17 @@ def main():
     mass_t = torch.from_numpy(m).cuda()
     print(f"[bench] workload {w.name}: {h.nleaves()} leaves", file=sys.stderr, flush=True)
 
-    r32, phi32, acc32 = time_form(h, mass_t, w.p, "fp32", args.steps, args.warmup, autotune=not args.no_autotune)
+    r32, phi32, acc32 = time_form(h, mass_t, w.p, "fp32", args.steps, args.warmup, autotune=not args.no_autotune, m2p_shape=args.m2p_shape)
     print(f"[bench] fp32 form: {r32['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     r32s = None
     if args.overlap:
-        r32s, _, _ = time_form(h, mass_t, w.p, "fp32", args.steps, 1, overlap=True, autotune=not args.no_autotune)
+        r32s, _, _ = time_form(h, mass_t, w.p, "fp32", args.steps, 1, overlap=True, autotune=not args.no_autotune, m2p_shape=args.m2p_shape)
         print(f"[bench] fp32 form, two streams: {r32s['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     outputs = {"fp32": (phi32, acc32)}
     r32g = None
     if not args.no_graph:
         r32g, phi32g, acc32g = time_form(h, mass_t, w.p, "fp32", args.steps, args.warmup, graph=True,
-                                         autotune=not args.no_autotune)
+                                         autotune=not args.no_autotune, m2p_shape=args.m2p_shape)
         print(f"[bench] fp32 form, graph replay: {r32g['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
         # identical bits to the eager solves when the tuner chose the same splits
         same = (r32g["autotune"] or {}).get("m2l_split") == (r32["autotune"] or {}).get("m2l_split") and \
@@ -516,7 +528,7 @@ def main():
     r64 = None
     if not args.no_fp64:
         r64, phi64, acc64 = time_form(h, mass_t, w.p, "fp64", max(args.steps // 2, 1), 1,
-                                      autotune=not args.no_autotune)
+                                      autotune=not args.no_autotune, m2p_shape=args.m2p_shape)
         outputs["fp64"] = (phi64, acc64)
         print(f"[bench] fp64 form: {r64['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
 
@@ -547,7 +559,7 @@ def main():
         # this order, the host's level-2 far-operator table
         try:
             rp, _, _ = time_form(h, mass_t, w.p, "fp32", max(args.steps // 2, 2), 1,
-                                 autotune=not args.no_autotune, periodic=True)
+                                 autotune=not args.no_autotune, m2p_shape=args.m2p_shape, periodic=True)
             periodic = {"ms_per_step": rp["ms_per_step"], "value": rp["value"], "unit": "cells/s",
                         "over_isolated": rp["ms_per_step"] / r32["ms_per_step"],
                         "plan_create_ms": rp["plan_create_ms"], "autotune": rp["autotune"],

@@ -12,6 +12,8 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
+#include <utility>
 #include <vector>
 
 #include "afmm_internal.h"
@@ -84,6 +86,52 @@ static inline uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) {
   return spread(x) | (spread(y) << 1) | (spread(z) << 2);
 }
 
+// Host loops over cells and groups run on up to 16 threads (a GPU's share of
+// the host cores).  Each worker takes one contiguous range of [0, n); workers
+// write disjoint outputs or integer partial counts that the caller sums in
+// range order, so results do not depend on the thread count.  The loop
+// bodies allocate nothing (an exception cannot leave a worker).
+static int host_threads() {
+  static const int n = [] {
+    const unsigned h = std::thread::hardware_concurrency();
+    return (int)std::max(1u, std::min(16u, h));
+  }();
+  return n;
+}
+static int parts_for(int64_t n, int64_t grain = 1 << 14) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(host_threads(), n / grain));
+}
+// fn(begin, end, part) for part = 0 .. parts-1; a worker that cannot be
+// started runs in the calling thread instead
+template <typename F>
+static void parallel_ranges(int64_t n, int parts, F&& fn) {
+  std::vector<std::thread> th;
+  th.reserve(parts > 1 ? parts - 1 : 0);
+  for (int t = 1; t < parts; ++t) {
+    try {
+      th.emplace_back([&fn, n, t, parts] { fn(n * t / parts, n * (t + 1) / parts, t); });
+    } catch (...) {
+      fn(n * t / parts, n * (t + 1) / parts, t);
+    }
+  }
+  fn(0, parts > 1 ? n / parts : n, 0);
+  for (auto& x : th) x.join();
+}
+
+// LSD radix sort of (Morton key, caller index) pairs by key, 8 key bits per
+// pass over the `bits` low bits that the keys use; tmp has v's size.  Stable;
+// with distinct keys the order is that of std::sort.
+static void radix_sort_keys(std::vector<std::pair<uint64_t, int32_t>>& v,
+                            std::vector<std::pair<uint64_t, int32_t>>& tmp, int bits) {
+  for (int shift = 0; shift < bits; shift += 8) {
+    size_t cnt[257] = {};
+    for (const auto& x : v) ++cnt[((x.first >> shift) & 255) + 1];
+    for (int i = 0; i < 256; ++i) cnt[i + 1] += cnt[i];
+    for (const auto& x : v) tmp[cnt[(x.first >> shift) & 255]++] = x;
+    v.swap(tmp);
+  }
+}
+
 // Append one hierarchy to the topology (levels 0..levelmax); slots are the
 // hierarchy's flat cell indices offset by slot_base.
 static afmm_status append_hierarchy(Topology& T, const afmm_hierarchy& h, int64_t slot_base) {
@@ -118,11 +166,23 @@ static afmm_status append_hierarchy(Topology& T, const afmm_hierarchy& h, int64_
       }
       v[c] = {morton3(x[0], x[1], x[2]), (int32_t)c};
     }
-    std::sort(v.begin(), v.end());
+  }
+  // one level per worker (the buffers are allocated here, not in the workers)
+  {
+    std::vector<std::vector<std::pair<uint64_t, int32_t>>> tmp(nl);
+    for (int i = 0; i < nl; ++i)
+      if (!std::is_sorted(sorted[i].begin(), sorted[i].end())) tmp[i].resize(sorted[i].size());
+    parallel_ranges(nl, std::min(nl, host_threads()), [&](int64_t b, int64_t e, int) {
+      for (int64_t i = b; i < e; ++i)
+        if (!tmp[i].empty()) radix_sort_keys(sorted[i], tmp[i], 3 * (lmin + (int)i));
+    });
+  }
+  for (int i = 0; i < nl; ++i) {
+    const auto& v = sorted[i];
     for (size_t c = 1; c < v.size(); ++c)
       if (v[c].first == v[c - 1].first) {
         char b[128];
-        snprintf(b, sizeof b, "duplicate cell at level %d", l);
+        snprintf(b, sizeof b, "duplicate cell at level %d", lmin + i);
         return fail(AFMM_E_INVALID_ARG, b);
       }
   }
@@ -166,49 +226,63 @@ static afmm_status append_hierarchy(Topology& T, const afmm_hierarchy& h, int64_
       L.slot.push_back(slot[c]);
       if (ref[c]) L.refcell.push_back(base + (int32_t)c);
     }
-    // neighbour rows of the refined cells, from the father's row
-    for (size_t c = 0; c < n; ++c) {
-      if (!ref[c]) continue;
-      const int32_t gcell = base + (int32_t)c;
-      int32_t row[27];
-      if (l == 0) {
-        // periodic box: the root's 27 neighbours are its own images
-        for (int e = 0; e < 27; ++e) row[e] = (e == 13 || T.periodic) ? gcell : -1;
-      } else {
-        const HostLevel& P = T.lv[l - 1];
-        const int32_t fr = gcell >> 3, o = gcell & 7;
-        const int32_t* prow = &P.nbr[(size_t)fr * 27];
-        for (int e = 0; e < 27; ++e) {
-          int pe = 0, co = 0;
-          for (int d = 0, mul = 1; d < 3; ++d, mul *= 3) {
-            const int ed = (d == 0 ? e % 3 : (d == 1 ? (e / 3) % 3 : e / 9)) - 1;
-            const int td = ((o >> d) & 1) + ed;          // -1 .. 2
-            const int pd = td < 0 ? -1 : (td >> 1);       // -1, 0, 0, 1
-            pe += (pd + 1) * mul;
-            co |= (td - 2 * pd) << d;
-          }
-          const int32_t Q = prow[pe];
-          if (Q < 0) {
-            row[e] = -1;
-            continue;
-          }
-          const int32_t rQ = P.rank[Q];
-          row[e] = rQ >= 0 ? 8 * rQ + co : -2;  // -2: covered by a coarser leaf
-        }
-        // strong grading rule: the father's 27 neighbours must be refined
-        if (l >= lmin + 1) {
+    // neighbour rows of the refined cells, from the father's row, written at
+    // their refined rank; the first grading violation in cell order is reported
+    const size_t nb0 = L.nbr.size();
+    L.nbr.resize(nb0 + (size_t)nr * 27);
+    const int parts = parts_for((int64_t)n);
+    std::vector<int64_t> bad(parts, -1);  // first failing cell of each range, and how it failed
+    std::vector<int> badkind(parts, 0);
+    parallel_ranges((int64_t)n, parts, [&](int64_t cb, int64_t ce, int part) {
+      for (int64_t c = cb; c < ce; ++c) {
+        if (!ref[c]) continue;
+        const int32_t gcell = base + (int32_t)c;
+        int32_t* row = &L.nbr[nb0 + (size_t)(L.rank[gcell] - rbase) * 27];
+        if (l == 0) {
+          // periodic box: the root's 27 neighbours are its own images
+          for (int e = 0; e < 27; ++e) row[e] = (e == 13 || T.periodic) ? gcell : -1;
+        } else {
+          const HostLevel& P = T.lv[l - 1];
+          const int32_t fr = gcell >> 3, o = gcell & 7;
+          const int32_t* prow = &P.nbr[(size_t)fr * 27];
           for (int e = 0; e < 27; ++e) {
-            const int32_t Q = prow[e];
-            if (Q >= 0 && P.rank[Q] < 0) {
-              char b[160];
-              snprintf(b, sizeof b, "level-%d cell refined next to a level-%d leaf (grading rule)", l, l - 1);
-              return fail(AFMM_E_NOT_GRADED, b);
+            int pe = 0, co = 0;
+            for (int d = 0, mul = 1; d < 3; ++d, mul *= 3) {
+              const int ed = (d == 0 ? e % 3 : (d == 1 ? (e / 3) % 3 : e / 9)) - 1;
+              const int td = ((o >> d) & 1) + ed;          // -1 .. 2
+              const int pd = td < 0 ? -1 : (td >> 1);       // -1, 0, 0, 1
+              pe += (pd + 1) * mul;
+              co |= (td - 2 * pd) << d;
             }
-            if (Q == -2) return fail(AFMM_E_NOT_GRADED, "grading rule violated");
+            const int32_t Q = prow[pe];
+            if (Q < 0) {
+              row[e] = -1;
+              continue;
+            }
+            const int32_t rQ = P.rank[Q];
+            row[e] = rQ >= 0 ? 8 * rQ + co : -2;  // -2: covered by a coarser leaf
+          }
+          // strong grading rule: the father's 27 neighbours must be refined
+          if (l >= lmin + 1) {
+            for (int e = 0; e < 27; ++e) {
+              const int32_t Q = prow[e];
+              const int kind = Q >= 0 && P.rank[Q] < 0 ? 1 : Q == -2 ? 2 : 0;
+              if (kind) {
+                bad[part] = c;
+                badkind[part] = kind;
+                return;
+              }
+            }
           }
         }
       }
-      L.nbr.insert(L.nbr.end(), row, row + 27);
+    });
+    for (int t = 0; t < parts; ++t) {
+      if (bad[t] < 0) continue;
+      if (badkind[t] == 2) return fail(AFMM_E_NOT_GRADED, "grading rule violated");
+      char b[160];
+      snprintf(b, sizeof b, "level-%d cell refined next to a level-%d leaf (grading rule)", l, l - 1);
+      return fail(AFMM_E_NOT_GRADED, b);
     }
     next.clear();
     for (size_t c = 0; c < n; ++c)
@@ -352,16 +426,24 @@ static void count_work(const Topology& T, int p, bool mixed, int f64, WorkCounts
     const HostLevel& L1 = T.lv[f - 1];
     const HostLevel& L0 = T.lv[f];
     const double cs = (mixed && f > f64) ? 4.0 : 8.0;
+    const auto& grp = T.m2lgrp[f];
+    const int parts = parts_for((int64_t)grp.size());
+    std::vector<std::array<int64_t, 3>> acc(parts, std::array<int64_t, 3>{});
+    parallel_ranges((int64_t)grp.size(), parts, [&](int64_t gb, int64_t ge, int part) {
+      std::array<int64_t, 3>& a = acc[part];  // pairs, monopole pairs, targets
+      for (int64_t i = gb; i < ge; ++i) {
+        const int32_t F = grp[i];
+        int nt = 0;
+        for (int o = 0; o < 8; ++o) nt += L0.rank[8 * F + o] >= 0;
+        int64_t nr, nl;
+        il_count(f, F, nr, nl);
+        a[2] += nt;
+        a[0] += nr * nt;
+        a[1] += nl * nt;
+      }
+    });
     int64_t pairs = 0, mono = 0, nt_all = 0;
-    for (int32_t F : T.m2lgrp[f]) {
-      int nt = 0;
-      for (int o = 0; o < 8; ++o) nt += L0.rank[8 * F + o] >= 0;
-      int64_t nr, nl;
-      il_count(f, F, nr, nl);
-      nt_all += nt;
-      pairs += nr * nt;
-      mono += nl * nt;
-    }
+    for (const auto& a : acc) pairs += a[0], mono += a[1], nt_all += a[2];
     const double ng = (double)T.m2lgrp[f].size();
     W.m2l_targets += nt_all;
     W.m2l_pairs += pairs + mono;
@@ -378,38 +460,48 @@ static void count_work(const Topology& T, int p, bool mixed, int f64, WorkCounts
     const HostLevel& L1 = T.lv[l - 1];
     const HostLevel& L0 = T.lv[l];
     const double cs = (mixed && (l - 1) > f64) ? 4.0 : 8.0;
-    int64_t m2p = 0, p2p = 0, p2p_il = 0, nm2p = 0, nst = 0, leaves = 0;
-    for (int32_t F : T.leafgrp[l]) {
-      unsigned tgt = 0;  // leaf children of F: the targets
-      for (int o = 0; o < 8; ++o) tgt |= (L0.rank[8 * F + o] < 0 ? 1u : 0u) << o;
-      const int nt = __builtin_popcount(tgt);
-      leaves += nt;
-      int64_t nr, nl;
-      il_count(l, F, nr, nl);
-      m2p += nr * nt;
-      p2p_il += nl * nt;
-      const int32_t* nb = &L1.nbr[(size_t)F * 27];
-      for (int e = 0; e < 27; ++e) {
-        const int32_t q = nb[e];
-        if (q < 0) continue;
-        const int32_t rq = L1.rank[q];
-        if (rq < 0) {
-          p2p += nt;  // a leaf one level coarser: P2P with every target
-          continue;
-        }
-        for (int op = 0; op < 8; ++op) {
-          const unsigned t = tgt & ~(unsigned)PM.self[e][op];
-          if (L0.rank[8 * rq + op] < 0) {
-            p2p += __builtin_popcount(t);  // leaf candidate: P2P with every other target
+    const auto& grp = T.leafgrp[l];
+    const int parts = parts_for((int64_t)grp.size());
+    std::vector<std::array<int64_t, 6>> acc(parts, std::array<int64_t, 6>{});
+    parallel_ranges((int64_t)grp.size(), parts, [&](int64_t gb, int64_t ge, int part) {
+      int64_t m2p = 0, p2p = 0, p2p_il = 0, nm2p = 0, nst = 0, leaves = 0;
+      for (int64_t i = gb; i < ge; ++i) {
+        const int32_t F = grp[i];
+        unsigned tgt = 0;  // leaf children of F: the targets
+        for (int o = 0; o < 8; ++o) tgt |= (L0.rank[8 * F + o] < 0 ? 1u : 0u) << o;
+        const int nt = __builtin_popcount(tgt);
+        leaves += nt;
+        int64_t nr, nl;
+        il_count(l, F, nr, nl);
+        m2p += nr * nt;
+        p2p_il += nl * nt;
+        const int32_t* nb = &L1.nbr[(size_t)F * 27];
+        for (int e = 0; e < 27; ++e) {
+          const int32_t q = nb[e];
+          if (q < 0) continue;
+          const int32_t rq = L1.rank[q];
+          if (rq < 0) {
+            p2p += nt;  // a leaf one level coarser: P2P with every target
             continue;
           }
-          const int na = __builtin_popcount(t & PM.adj[e][op]);
-          p2p += 8 * na;  // touching refined candidate: nearest field from its 8 children
-          nst += 8 * na;
-          nm2p += __builtin_popcount(t & ~(unsigned)PM.adj[e][op]);
+          for (int op = 0; op < 8; ++op) {
+            const unsigned t = tgt & ~(unsigned)PM.self[e][op];
+            if (L0.rank[8 * rq + op] < 0) {
+              p2p += __builtin_popcount(t);  // leaf candidate: P2P with every other target
+              continue;
+            }
+            const int na = __builtin_popcount(t & PM.adj[e][op]);
+            p2p += 8 * na;  // touching refined candidate: nearest field from its 8 children
+            nst += 8 * na;
+            nm2p += __builtin_popcount(t & ~(unsigned)PM.adj[e][op]);
+          }
         }
       }
-    }
+      acc[part] = {m2p, p2p, p2p_il, nm2p, nst, leaves};
+    });
+    int64_t m2p = 0, p2p = 0, p2p_il = 0, nm2p = 0, nst = 0, leaves = 0;
+    for (const auto& a : acc)
+      m2p += a[0], p2p += a[1], p2p_il += a[2], nm2p += a[3], nst += a[4], leaves += a[5];
     W.m2p += m2p;
     W.p2p += p2p + p2p_il;
     W.nm2p += nm2p;

@@ -86,38 +86,6 @@ static inline uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) {
   return spread(x) | (spread(y) << 1) | (spread(z) << 2);
 }
 
-// Host loops over cells and groups run on up to 16 threads (a GPU's share of
-// the host cores).  Each worker takes one contiguous range of [0, n); workers
-// write disjoint outputs or integer partial counts that the caller sums in
-// range order, so results do not depend on the thread count.  The loop
-// bodies allocate nothing (an exception cannot leave a worker).
-static int host_threads() {
-  static const int n = [] {
-    const unsigned h = std::thread::hardware_concurrency();
-    return (int)std::max(1u, std::min(16u, h));
-  }();
-  return n;
-}
-static int parts_for(int64_t n, int64_t grain = 1 << 14) {
-  return (int)std::max<int64_t>(1, std::min<int64_t>(host_threads(), n / grain));
-}
-// fn(begin, end, part) for part = 0 .. parts-1; a worker that cannot be
-// started runs in the calling thread instead
-template <typename F>
-static void parallel_ranges(int64_t n, int parts, F&& fn) {
-  std::vector<std::thread> th;
-  th.reserve(parts > 1 ? parts - 1 : 0);
-  for (int t = 1; t < parts; ++t) {
-    try {
-      th.emplace_back([&fn, n, t, parts] { fn(n * t / parts, n * (t + 1) / parts, t); });
-    } catch (...) {
-      fn(n * t / parts, n * (t + 1) / parts, t);
-    }
-  }
-  fn(0, parts > 1 ? n / parts : n, 0);
-  for (auto& x : th) x.join();
-}
-
 // LSD radix sort of (Morton key, caller index) pairs by key, 8 key bits per
 // pass over the `bits` low bits that the keys use; tmp has v's size.  Stable;
 // with distinct keys the order is that of std::sort.
@@ -167,7 +135,7 @@ static afmm_status append_hierarchy(Topology& T, const afmm_hierarchy& h, int64_
       v[c] = {morton3(x[0], x[1], x[2]), (int32_t)c};
     }
   }
-  // one level per worker (the buffers are allocated here, not in the workers)
+  // one level per worker
   {
     std::vector<std::vector<std::pair<uint64_t, int32_t>>> tmp(nl);
     for (int i = 0; i < nl; ++i)

@@ -184,37 +184,40 @@ std::shared_ptr<const std::vector<double>> periodic_far_table(int p) {
             }
       }
   auto T = std::make_shared<std::vector<double>>((size_t)8 * kNumD * K, 0.0);
-  std::vector<long double> lat(K), D(K);
   std::vector<long double> scale(K);
   for (int g = 0, deg = 0; g < K; ++g) {
     while (nmi(deg) <= g) ++deg;      // deg = |g|
     scale[g] = std::pow(0.25L, deg + 1);
   }
-  for (int di = 0; di < kNumD; ++di) {
-    const int e[3] = {di % 7 - 3, (di / 7) % 7 - 3, di / 49 - 3};
-    const long double R[3] = {-0.25L * e[0], -0.25L * e[1], -0.25L * e[2]};   // c_y - c_s
-    lattice_tensor(p, R, kvec, kw, kpow, lat.data());
-    for (int oy = 0; oy < 8; ++oy) {
-      std::vector<long double> acc(lat);
-      for (int n = 0; n < 27; ++n) {
-        const int nn[3] = {n % 3 - 1, (n / 3) % 3 - 1, n / 9 - 1};
-        // the image's level-1 father relative to the target's, per axis:
-        // floor((o_y + e + 4 n) / 2); the image is far when one exceeds 1
-        bool far = false;
-        for (int i = 0; i < 3; ++i) {
-          const int v = ((oy >> i) & 1) + e[i] + 4 * nn[i];
-          const int f1 = v >= 0 ? v / 2 : -((1 - v) / 2);
-          far = far || f1 < -1 || f1 > 1;
+  // the offsets are independent: each worker fills the rows of its own range
+  parallel_ranges(kNumD, std::min(kNumD, host_threads()), [&](int64_t d0, int64_t d1, int) {
+    std::vector<long double> lat(K), D(K);
+    for (int di = (int)d0; di < (int)d1; ++di) {
+      const int e[3] = {di % 7 - 3, (di / 7) % 7 - 3, di / 49 - 3};
+      const long double R[3] = {-0.25L * e[0], -0.25L * e[1], -0.25L * e[2]};   // c_y - c_s
+      lattice_tensor(p, R, kvec, kw, kpow, lat.data());
+      for (int oy = 0; oy < 8; ++oy) {
+        std::vector<long double> acc(lat);
+        for (int n = 0; n < 27; ++n) {
+          const int nn[3] = {n % 3 - 1, (n / 3) % 3 - 1, n / 9 - 1};
+          // the image's level-1 father relative to the target's, per axis:
+          // floor((o_y + e + 4 n) / 2); the image is far when one exceeds 1
+          bool far = false;
+          for (int i = 0; i < 3; ++i) {
+            const int v = ((oy >> i) & 1) + e[i] + 4 * nn[i];
+            const int f1 = v >= 0 ? v / 2 : -((1 - v) / 2);
+            far = far || f1 < -1 || f1 > 1;
+          }
+          if (!far) continue;
+          const long double Rn[3] = {R[0] - nn[0], R[1] - nn[1], R[2] - nn[2]};
+          coulomb_derivs(p, Rn, D.data());
+          for (int g = 0; g < K; ++g) acc[g] += D[g];
         }
-        if (!far) continue;
-        const long double Rn[3] = {R[0] - nn[0], R[1] - nn[1], R[2] - nn[2]};
-        coulomb_derivs(p, Rn, D.data());
-        for (int g = 0; g < K; ++g) acc[g] += D[g];
+        double* row = &(*T)[((size_t)oy * kNumD + di) * K];
+        for (int g = 0; g < K; ++g) row[g] = (double)(acc[g] * scale[g]);
       }
-      double* row = &(*T)[((size_t)oy * kNumD + di) * K];
-      for (int g = 0; g < K; ++g) row[g] = (double)(acc[g] * scale[g]);
     }
-  }
+  });
   cache[p] = T;
   return T;
 }

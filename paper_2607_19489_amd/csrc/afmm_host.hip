@@ -395,7 +395,7 @@ static void count_work(const Topology& T, int p, bool mixed, int f64, WorkCounts
     const HostLevel& L0 = T.lv[f];
     const double cs = (mixed && f > f64) ? 4.0 : 8.0;
     const auto& grp = T.m2lgrp[f];
-    const int parts = parts_for((int64_t)grp.size());
+    const int parts = parts_for((int64_t)grp.size(), 1024);  // a group is ~500 checks
     std::vector<std::array<int64_t, 3>> acc(parts, std::array<int64_t, 3>{});
     parallel_ranges((int64_t)grp.size(), parts, [&](int64_t gb, int64_t ge, int part) {
       std::array<int64_t, 3>& a = acc[part];  // pairs, monopole pairs, targets
@@ -429,7 +429,7 @@ static void count_work(const Topology& T, int p, bool mixed, int f64, WorkCounts
     const HostLevel& L0 = T.lv[l];
     const double cs = (mixed && (l - 1) > f64) ? 4.0 : 8.0;
     const auto& grp = T.leafgrp[l];
-    const int parts = parts_for((int64_t)grp.size());
+    const int parts = parts_for((int64_t)grp.size(), 1024);  // a group is ~500 checks
     std::vector<std::array<int64_t, 6>> acc(parts, std::array<int64_t, 6>{});
     parallel_ranges((int64_t)grp.size(), parts, [&](int64_t gb, int64_t ge, int part) {
       int64_t m2p = 0, p2p = 0, p2p_il = 0, nm2p = 0, nst = 0, leaves = 0;

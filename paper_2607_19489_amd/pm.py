@@ -105,12 +105,26 @@ class ParticleMesh:
         self.p, self.precision, self.G, self.boxlen, self.plan_kw = p, precision, G, boxlen, plan_kw
         self.h: Optional[ParticleHierarchy] = None
         self.plan: Optional[Plan] = None
+        self._cells: Optional[np.ndarray] = None
         self.replans = 0
         self.t = 0.0
         self.acc, self.phi = self._forces()
 
+    def _cloud_cells(self, pos: np.ndarray) -> np.ndarray:
+        """Cloud cells floor(x 2^l / boxlen - 1/2) of every particle at every level
+        the hierarchy builder refines (levelmin .. levelmax - 1), in the builder's
+        own arithmetic (one product and one difference in double precision): the
+        particles' hierarchy depends on their positions through these alone."""
+        inv_h = np.array([float(1 << int(l)) / self.boxlen for l in range(self.levelmin, self.levelmax)])
+        return np.floor(pos[None, :, :] * inv_h[:, None, None] - 0.5).astype(np.int64)
+
     def _ensure_plan(self):
-        h = ParticleHierarchy(self.pos.cpu().numpy(), self.levelmin, self.levelmax, self.nexpand, self.boxlen)
+        pos = self.pos.cpu().numpy()
+        cells = self._cloud_cells(pos)
+        if self.h is not None and self._cells is not None and np.array_equal(cells, self._cells):
+            return  # no cloud moved to another cell: same hierarchy, same plan
+        h = ParticleHierarchy(pos, self.levelmin, self.levelmax, self.nexpand, self.boxlen)
+        self._cells = cells
         if h.same_as(self.h):
             return
         if self.plan is not None:

@@ -4,6 +4,10 @@
   C++) against ``synth.build_graded`` with the same refinement predicate
   (numpy): identical cells, flags and order, and graded by the independent
   checker.
+- The time loop skips rebuilding that hierarchy while no particle's cloud
+  cells change: whenever the cloud cells of two position sets agree, the
+  library builds identical hierarchies from them (positions on and a few ulps
+  around cell boundaries, a power-of-two and another box size).
 - Pins of the oracle's cloud-in-cell: mass conservation, a particle at a cell
   centre, exact interpolation of linear fields, and the transpose relation
   between deposition and interpolation.
@@ -12,7 +16,7 @@ import numpy as np
 import pytest
 
 from oracle import pm as opm
-from paper_2607_19489_amd.pm import ParticleHierarchy, binary_initial
+from paper_2607_19489_amd.pm import ParticleHierarchy, ParticleMesh, binary_initial
 from synth.hierarchy import build_graded, check_graded
 
 
@@ -100,3 +104,32 @@ def test_binary_initial_is_a_circular_orbit():
     assert np.allclose(m[0] * vel[0] + m[1] * vel[1], 0.0)
     # the period is about 2.58, so t = 8 is about three orbits
     assert 3.0 < 8.0 * omega / (2 * np.pi) < 3.2
+
+
+@pytest.mark.parametrize("boxlen", [1.0, 2.7])
+def test_equal_cloud_cells_give_the_same_hierarchy(boxlen):
+    class Box:  # the attributes ParticleMesh._cloud_cells reads
+        levelmin, levelmax = 3, 6
+    Box.boxlen = boxlen
+    cloud_cells = lambda pos: ParticleMesh._cloud_cells(Box, pos)
+    rng = np.random.default_rng(17)
+    checked = changed = 0
+    for _ in range(60):
+        # a particle placed on a cloud boundary of a random level, then nudged
+        # by a few ulps either way; a second particle elsewhere
+        l = int(rng.integers(Box.levelmin, Box.levelmax))
+        k = rng.integers(2, (1 << l) - 3, size=3)
+        x = (k + 0.5) * boxlen / (1 << l)
+        base = np.array([x, rng.uniform(0.1, 0.9, 3) * boxlen])
+        for ulps in (-3, -1, 0, 1, 3):
+            pos = base.copy()
+            pos[0] = x + ulps * np.spacing(x)
+            for ref in (base, pos):
+                if np.array_equal(cloud_cells(ref), cloud_cells(pos)):
+                    ha = ParticleHierarchy(ref, Box.levelmin, Box.levelmax, 1, boxlen)
+                    hb = ParticleHierarchy(pos, Box.levelmin, Box.levelmax, 1, boxlen)
+                    assert hb.same_as(ha)
+                    checked += 1
+                else:
+                    changed += 1
+    assert checked > 100 and changed > 20

@@ -87,15 +87,32 @@ static inline uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) {
 }
 
 // LSD radix sort of (Morton key, caller index) pairs by key, 8 key bits per
-// pass over the `bits` low bits that the keys use; tmp has v's size.  Stable;
-// with distinct keys the order is that of std::sort.
-static void radix_sort_keys(std::vector<std::pair<uint64_t, int32_t>>& v,
-                            std::vector<std::pair<uint64_t, int32_t>>& tmp, int bits) {
+// pass over the `bits` low bits that the keys use.  Each pass counts the
+// digits of every range, then each range scatters its items after those of
+// the same digit in earlier ranges: stable, so with distinct keys the order
+// is that of std::sort, whatever the number of ranges.
+static void radix_sort_keys(std::vector<std::pair<uint64_t, int32_t>>& v, int bits) {
+  const int64_t n = (int64_t)v.size();
+  const int parts = parts_for(n, 1 << 15);
+  std::vector<std::pair<uint64_t, int32_t>> tmp(v.size());
+  std::vector<std::array<size_t, 256>> cnt((size_t)parts);
   for (int shift = 0; shift < bits; shift += 8) {
-    size_t cnt[257] = {};
-    for (const auto& x : v) ++cnt[((x.first >> shift) & 255) + 1];
-    for (int i = 0; i < 256; ++i) cnt[i + 1] += cnt[i];
-    for (const auto& x : v) tmp[cnt[(x.first >> shift) & 255]++] = x;
+    parallel_ranges(n, parts, [&](int64_t b, int64_t e, int t) {
+      auto& c = cnt[(size_t)t];
+      c.fill(0);
+      for (int64_t i = b; i < e; ++i) ++c[(v[(size_t)i].first >> shift) & 255];
+    });
+    size_t run = 0;
+    for (int d = 0; d < 256; ++d)
+      for (int t = 0; t < parts; ++t) {
+        const size_t k = cnt[(size_t)t][d];
+        cnt[(size_t)t][d] = run;
+        run += k;
+      }
+    parallel_ranges(n, parts, [&](int64_t b, int64_t e, int t) {
+      auto& c = cnt[(size_t)t];
+      for (int64_t i = b; i < e; ++i) tmp[c[(v[(size_t)i].first >> shift) & 255]++] = v[(size_t)i];
+    });
     v.swap(tmp);
   }
 }
@@ -125,25 +142,25 @@ static afmm_status append_hierarchy(Topology& T, const afmm_hierarchy& h, int64_
     const int64_t side = (int64_t)1 << l;
     auto& v = sorted[i];
     v.resize(h.ncell[i]);
-    for (int64_t c = 0; c < h.ncell[i]; ++c) {
-      const int32_t* x = h.ijk + 3 * (off[i] + c);
-      if (x[0] < 0 || x[0] >= side || x[1] < 0 || x[1] >= side || x[2] < 0 || x[2] >= side) {
+    const int parts = parts_for(h.ncell[i], 4096);
+    std::vector<int64_t> bad((size_t)parts, -1);  // first cell out of range in each range
+    parallel_ranges(h.ncell[i], parts, [&](int64_t cb, int64_t ce, int part) {
+      for (int64_t c = cb; c < ce; ++c) {
+        const int32_t* x = h.ijk + 3 * (off[i] + c);
+        if (x[0] < 0 || x[0] >= side || x[1] < 0 || x[1] >= side || x[2] < 0 || x[2] >= side) {
+          bad[(size_t)part] = c;
+          return;
+        }
+        v[(size_t)c] = {morton3(x[0], x[1], x[2]), (int32_t)c};
+      }
+    });
+    for (int64_t c : bad)
+      if (c >= 0) {
         char b[128];
         snprintf(b, sizeof b, "cell %lld of level %d out of range", (long long)c, l);
         return fail(AFMM_E_INVALID_ARG, b);
       }
-      v[c] = {morton3(x[0], x[1], x[2]), (int32_t)c};
-    }
-  }
-  // one level per worker
-  {
-    std::vector<std::vector<std::pair<uint64_t, int32_t>>> tmp(nl);
-    for (int i = 0; i < nl; ++i)
-      if (!std::is_sorted(sorted[i].begin(), sorted[i].end())) tmp[i].resize(sorted[i].size());
-    parallel_ranges(nl, std::min(nl, host_threads()), [&](int64_t b, int64_t e, int) {
-      for (int64_t i = b; i < e; ++i)
-        if (!tmp[i].empty()) radix_sort_keys(sorted[i], tmp[i], 3 * (lmin + (int)i));
-    });
+    if (!std::is_sorted(v.begin(), v.end())) radix_sort_keys(v, 3 * l);
   }
   for (int i = 0; i < nl; ++i) {
     const auto& v = sorted[i];
@@ -165,6 +182,9 @@ static afmm_status append_hierarchy(Topology& T, const afmm_hierarchy& h, int64_
     const size_t n = keys.size();
     std::vector<uint8_t> ref(n, 1);
     std::vector<int32_t> slot(n, -1);
+    const int parts = parts_for((int64_t)n, 4096);
+    std::vector<int64_t> bad((size_t)parts, -1);  // first failing cell of each range, and how it failed
+    std::vector<int> badkind((size_t)parts, 0);
     if (l >= lmin) {
       const int i = l - lmin;
       const auto& v = sorted[i];
@@ -174,33 +194,57 @@ static afmm_status append_hierarchy(Topology& T, const afmm_hierarchy& h, int64_
                  n);
         return fail(AFMM_E_INCOMPLETE_OCT, b);
       }
-      for (size_t c = 0; c < n; ++c) {
-        if (v[c].first != keys[c]) {
+      parallel_ranges((int64_t)n, parts, [&](int64_t cb, int64_t ce, int part) {
+        for (int64_t c = cb; c < ce; ++c) {
+          if (v[(size_t)c].first != keys[(size_t)c]) {
+            bad[(size_t)part] = c;
+            return;
+          }
+          const int32_t ci = v[(size_t)c].second;
+          ref[(size_t)c] = h.refined[off[i] + ci] ? 1 : 0;
+          slot[(size_t)c] = (int32_t)(slot_base + off[i] + ci);
+        }
+      });
+      for (int64_t c : bad)
+        if (c >= 0) {
           char b[128];
           snprintf(b, sizeof b, "level %d: cell set differs from the children of refined level-%d cells", l, l - 1);
           return fail(AFMM_E_INCOMPLETE_OCT, b);
         }
-        const int32_t ci = v[c].second;
-        ref[c] = h.refined[off[i] + ci] ? 1 : 0;
-        slot[c] = (int32_t)(slot_base + off[i] + ci);
-      }
       if (l == lmax)
         for (size_t c = 0; c < n; ++c)
           if (ref[c]) return fail(AFMM_E_INCOMPLETE_OCT, "refined cell at levelmax has no children");
     }
-    int32_t nr = 0;
-    for (size_t c = 0; c < n; ++c) {
-      L.rank.push_back(ref[c] ? rbase + nr++ : -1);
-      L.slot.push_back(slot[c]);
-      if (ref[c]) L.refcell.push_back(base + (int32_t)c);
-    }
+    // refined ranks in cell order: refined cells per range, then each range's first rank
+    std::vector<int32_t> first((size_t)parts + 1, 0);
+    parallel_ranges((int64_t)n, parts, [&](int64_t cb, int64_t ce, int part) {
+      int32_t k = 0;
+      for (int64_t c = cb; c < ce; ++c) k += ref[(size_t)c];
+      first[(size_t)part + 1] = k;
+    });
+    for (int t = 0; t < parts; ++t) first[(size_t)t + 1] += first[(size_t)t];
+    const int32_t nr = first[(size_t)parts];
+    L.rank.resize((size_t)base + n);
+    L.slot.resize((size_t)base + n);
+    L.refcell.resize((size_t)rbase + nr);
+    parallel_ranges((int64_t)n, parts, [&](int64_t cb, int64_t ce, int part) {
+      int32_t r = rbase + first[(size_t)part];
+      for (int64_t c = cb; c < ce; ++c) {
+        const size_t g = (size_t)base + (size_t)c;
+        L.slot[g] = slot[(size_t)c];
+        if (ref[(size_t)c]) {
+          L.rank[g] = r;
+          L.refcell[(size_t)r] = (int32_t)g;
+          ++r;
+        } else {
+          L.rank[g] = -1;
+        }
+      }
+    });
     // neighbour rows of the refined cells, from the father's row, written at
     // their refined rank; the first grading violation in cell order is reported
     const size_t nb0 = L.nbr.size();
     L.nbr.resize(nb0 + (size_t)nr * 27);
-    const int parts = parts_for((int64_t)n);
-    std::vector<int64_t> bad(parts, -1);  // first failing cell of each range, and how it failed
-    std::vector<int> badkind(parts, 0);
     parallel_ranges((int64_t)n, parts, [&](int64_t cb, int64_t ce, int part) {
       for (int64_t c = cb; c < ce; ++c) {
         if (!ref[c]) continue;
@@ -252,10 +296,16 @@ static afmm_status append_hierarchy(Topology& T, const afmm_hierarchy& h, int64_
       snprintf(b, sizeof b, "level-%d cell refined next to a level-%d leaf (grading rule)", l, l - 1);
       return fail(AFMM_E_NOT_GRADED, b);
     }
-    next.clear();
-    for (size_t c = 0; c < n; ++c)
-      if (ref[c])
-        for (uint64_t o = 0; o < 8; ++o) next.push_back((keys[c] << 3) | o);
+    // the next level's cells: the children of the refined cells, in order
+    next.assign((size_t)nr * 8, 0);
+    parallel_ranges((int64_t)n, parts, [&](int64_t cb, int64_t ce, int part) {
+      size_t r = (size_t)first[(size_t)part];
+      for (int64_t c = cb; c < ce; ++c)
+        if (ref[(size_t)c]) {
+          for (uint64_t o = 0; o < 8; ++o) next[8 * r + o] = (keys[(size_t)c] << 3) | o;
+          ++r;
+        }
+    });
     keys.swap(next);
   }
   T.levelmin.push_back(lmin);

@@ -61,6 +61,19 @@ def test_validation_codes():
     assert e.value.code == -4
 
 
+def test_validation_reports_the_first_bad_cell_in_cell_order():
+    # the host checks run over ranges of cells on several threads; the error
+    # names the first offending cell whichever range finds it
+    u = unigrid(6)
+    for first, second in ((50000, 200000), (3, 262000), (131071, 131072)):
+        bad = Hierarchy(u.levelmin, u.levelmax, [a.copy() for a in u.ijk], [r.copy() for r in u.refined])
+        bad.ijk[0][second, 1] = 64
+        bad.ijk[0][first, 2] = -1
+        with pytest.raises(A.AfmmError) as e:
+            A.hierarchy_check(bad)
+        assert e.value.code == -1 and f"cell {first} of level 6 out of range" in str(e.value), str(e.value)
+
+
 def test_counts_unigrid():
     info = A.hierarchy_check(unigrid(5), p=4)
     assert info["nleaves"] == 32768 and info["nrefined"] == 0

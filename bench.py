@@ -337,7 +337,8 @@ def roofline(res, precision, p=None, workload=None):
     prof = res["kernels"]
     name, k = max(prof.items(), key=lambda kv: kv[1]["ms"])
     total_ms = sum(v["ms"] for v in prof.values())
-    shape = (res.get("m2p_shape") or [0, 0])[1 if name.endswith("f32") else 0]
+    shapes = res.get("m2p_shape") or (res.get("autotune") or {}).get("m2p_shape") or [0, 0]
+    shape = shapes[1 if name.endswith("f32") else 0]
     traffic, tsrc = measured_traffic(name, p, workload, shape) if p is not None else (None, None)
     kname = KERNEL_NAMES.get(name, name)
     if name.startswith("m2p_"):

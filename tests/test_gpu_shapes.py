@@ -8,7 +8,7 @@ shape runs the same MFMAs in the same order on the same operands, so the solves
 must agree bit for bit; shapes 2 and 3 are also checked against the FP64
 oracle, on ragged tiles (parity classes whose group counts are not multiples of
 32), with tap splits whose ranges cross the kernels' source-table chunks, in a
-batch, and under the autotuner.
+batch, on periodic plans, and under the autotuner.
 """
 import numpy as np
 import pytest
@@ -99,3 +99,30 @@ def test_autotune_reports_a_supported_shape_and_stays_correct():
     check_errors(phi.cpu().numpy()[leaf], acc.cpu().numpy()[leaf], po[leaf], ao[leaf], "fp32", 1e-4,
                  what=f"autotuned shape {res['m2p_shape']}")
     plan.close()
+
+
+@pytest.mark.parametrize("precision,p", [("fp32", 6), ("fp32", 5), ("fp64", 6), ("fp64", 4)])
+def test_crossbar_shape_on_periodic_plans_and_in_batches(precision, p):
+    # periodic plans (wrapped tiles, the level-2 far operator) and a batch of
+    # plans, each with shape 3 against shape 0: bit for bit
+    from test_gpu_periodic import _case
+    names = ["corner", "face", "uni4"]
+    cases = [_case(n) for n in names]
+    masses = [torch.from_numpy(m).cuda() for _, m in cases]
+    out = {}
+    for shape in (0, 3):
+        plans = [A.Plan(h, p=p, precision=precision, periodic=True, m2p_shape=shape, tap_split=1) for h, _ in cases]
+        single = [tuple(t.clone() for t in pl.solve(mt)) for pl, mt in zip(plans, masses)]
+        batch = A.Batch(plans)
+        phis, accs = batch.solve(masses)
+        torch.cuda.synchronize()
+        for (h, _), (p1, a1), p2, a2 in zip(cases, single, phis, accs):
+            leaf = torch.from_numpy(h.leaf_mask()).cuda()
+            assert torch.equal(p1[leaf], p2[leaf]) and torch.equal(a1[leaf], a2[leaf]), shape
+        out[shape] = single
+        batch.close()
+        for pl in plans:
+            pl.close()
+    for (h, _), (p0, a0), (p3, a3) in zip(cases, out[0], out[3]):
+        leaf = torch.from_numpy(h.leaf_mask()).cuda()
+        assert torch.equal(p0[leaf], p3[leaf]) and torch.equal(a0[leaf], a3[leaf])

@@ -175,7 +175,17 @@ typedef struct afmm_plan_info {
  */
 afmm_status afmm_plan_create(const afmm_hierarchy* h, const afmm_options* opt, void* hip_stream,
                              afmm_plan** out);
+/*
+ * Destroying a plan (or a batch) waits for its device, then keeps its device
+ * buffers for later plans on that device, up to 2 GiB per device (the oldest
+ * are freed first); plans created with max_device_bytes free theirs.
+ * afmm_release_cached_memory frees every kept buffer; the library also does so
+ * by itself before it reports an allocation failure.  Thread-safe.
+ */
 afmm_status afmm_plan_destroy(afmm_plan* plan);
+afmm_status afmm_release_cached_memory(void);
+/* The counts are taken on the first call (or when profiling is switched on),
+ * not by afmm_plan_create: host time of the order of the topology build. */
 afmm_status afmm_plan_get_info(const afmm_plan* plan, afmm_plan_info* out);
 
 /*

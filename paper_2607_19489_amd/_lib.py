@@ -37,6 +37,7 @@ SYMBOLS = [
     "afmm_plan_autotune", "afmm_batch_autotune", "afmm_solve_adjoint_noalloc",
     "afmm_particle_hierarchy_create", "afmm_particle_hierarchy_view", "afmm_particle_hierarchy_destroy",
     "afmm_cic_deposit", "afmm_cic_interpolate", "afmm_particles_update", "afmm_plan_replan", "afmm_solve_drift",
+    "afmm_release_cached_memory",
 ]
 
 
@@ -107,6 +108,7 @@ def lib():
     L.afmm_options_default.restype = None
     L.afmm_plan_create.argtypes = [C.POINTER(HierarchyC), C.POINTER(Options), vp, C.POINTER(vp)]
     L.afmm_plan_destroy.argtypes = [vp]
+    L.afmm_release_cached_memory.argtypes = []
     L.afmm_plan_replan.argtypes = [vp, C.POINTER(HierarchyC), C.c_int32, vp, C.POINTER(vp)]
     L.afmm_plan_get_info.argtypes = [vp, C.POINTER(PlanInfo)]
     L.afmm_solve.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp, vp]
@@ -141,7 +143,8 @@ def lib():
                  "afmm_plan_get_profile", "afmm_batch_set_profiling", "afmm_batch_get_profile",
                  "afmm_plan_autotune", "afmm_batch_autotune", "afmm_particle_hierarchy_create",
                  "afmm_particle_hierarchy_view", "afmm_particle_hierarchy_destroy", "afmm_cic_deposit",
-                 "afmm_cic_interpolate", "afmm_particles_update", "afmm_plan_replan", "afmm_solve_drift"):
+                 "afmm_cic_interpolate", "afmm_particles_update", "afmm_plan_replan", "afmm_solve_drift",
+                 "afmm_release_cached_memory"):
         getattr(L, name).restype = C.c_int32
     _lib = L
     return L

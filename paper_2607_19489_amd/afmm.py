@@ -309,3 +309,8 @@ class AFMMSolve(torch.autograd.Function):
 def solve(mass: torch.Tensor, plan: Plan):
     """Differentiable full solve."""
     return AFMMSolve.apply(mass, plan)
+
+
+def release_cached_memory():
+    """Free the device buffers that destroyed plans left in the library's cache."""
+    check(lib().afmm_release_cached_memory(), "afmm_release_cached_memory")

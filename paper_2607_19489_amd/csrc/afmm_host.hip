@@ -1046,11 +1046,20 @@ struct afmm_plan {
   int n_adjp[kMaxLevel] = {}, n_adjl[kMaxLevel] = {};
   int s_adjp[kMaxLevel] = {}, s_adjl[kMaxLevel] = {};  // their tap splits
   double* adj_part = nullptr;     // partial sets of the split transposed translations
-  std::vector<void*> allocs;
-  size_t bytes = 0;
+  struct Alloc {
+    void* p;
+    size_t cap;   // bytes allocated (a cached buffer may hold more than asked for)
+    int dev;
+    bool cached;  // returned to the buffer cache when the plan goes
+  };
+  std::vector<Alloc> allocs;
+  size_t bytes = 0;               // bytes the plan's buffers asked for
   bool dead = false;              // sticky device error
-  afmm_plan_info info{};
-  WorkCounts work;
+  // sizes and work counts of the plan, counted on first use (afmm_plan_get_info,
+  // profiling): a time-step loop that re-plans every few steps never asks
+  mutable afmm_plan_info info{};
+  mutable WorkCounts work;
+  mutable std::once_flag info_once;
   // per-launch event timing (afmm_plan_set_profiling)
   bool profiling = false;
   double pending_flops = 0.0, pending_bytes = 0.0;  // work of a multi-level launch being timed
@@ -1081,17 +1090,118 @@ struct afmm_batch {
 
 namespace {
 
+// Device buffers of destroyed plans are kept for later plans on the same
+// device, up to kCacheBytes per device (the oldest go back to the driver
+// first).  A hipMalloc maps new pages and a hipFree waits for the device and
+// unmaps them: for a plan of a few hundred thousand cells that is several
+// milliseconds, which a time-step loop that re-plans every few steps would pay
+// each time.  A cached buffer is reused when it holds the request with at most
+// a quarter to spare; a new one gets an eighth more than asked, so that the
+// same buffer of the next plan, a little larger, still fits.  Plans with a
+// device-byte cap take buffers of the exact size and free them.
+constexpr size_t kCacheBytes = (size_t)2 << 30;
+struct CachedBuf {
+  void* p;
+  size_t cap;
+};
+std::mutex g_cache_mu;
+std::vector<std::vector<CachedBuf>> g_cache;  // per device, oldest first
+std::vector<size_t> g_cache_total;
+
+void* cache_take(int dev, size_t bytes, size_t* cap) {
+  std::lock_guard<std::mutex> g(g_cache_mu);
+  if (dev < 0 || (size_t)dev >= g_cache.size()) return nullptr;
+  auto& v = g_cache[dev];
+  const size_t hi = bytes + bytes / 4 + ((size_t)64 << 10);
+  size_t best = v.size();
+  for (size_t i = 0; i < v.size(); ++i)
+    if (v[i].cap >= bytes && v[i].cap <= hi && (best == v.size() || v[i].cap < v[best].cap)) best = i;
+  if (best == v.size()) return nullptr;
+  void* p = v[best].p;
+  *cap = v[best].cap;
+  g_cache_total[dev] -= *cap;
+  v.erase(v.begin() + (long)best);
+  return p;
+}
+
+// Takes buffers that no pending device work uses any more.
+void cache_put(int dev, void* p, size_t cap) {
+  std::vector<void*> drop;
+  {
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    if ((size_t)dev >= g_cache.size()) {
+      g_cache.resize((size_t)dev + 1);
+      g_cache_total.resize((size_t)dev + 1, 0);
+    }
+    auto& v = g_cache[dev];
+    v.push_back({p, cap});
+    g_cache_total[dev] += cap;
+    size_t k = 0;
+    while (g_cache_total[dev] > kCacheBytes && k < v.size()) {
+      drop.push_back(v[k].p);
+      g_cache_total[dev] -= v[k].cap;
+      ++k;
+    }
+    v.erase(v.begin(), v.begin() + (long)k);
+  }
+  for (void* q : drop) (void)hipFree(q);
+}
+
+// Returns the cached buffers of one device (dev >= 0) or of all devices.
+void cache_release(int dev) {
+  std::vector<void*> drop;
+  {
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    for (size_t d = 0; d < g_cache.size(); ++d) {
+      if (dev >= 0 && (size_t)dev != d) continue;
+      for (auto& b : g_cache[d]) drop.push_back(b.p);
+      g_cache[d].clear();
+      g_cache_total[d] = 0;
+    }
+  }
+  for (void* q : drop) (void)hipFree(q);
+}
+
+// Waits for every device that holds one of the plan's cached buffers: a buffer
+// goes back to the cache only once no kernel or copy can still touch it (what
+// hipFree does by itself).
+void sync_alloc_devices(const afmm_plan* P) {
+  std::vector<int> done;
+  int cur = -1;
+  (void)hipGetDevice(&cur);
+  for (const auto& a : P->allocs) {
+    if (!a.cached || std::find(done.begin(), done.end(), a.dev) != done.end()) continue;
+    done.push_back(a.dev);
+    if (a.dev != cur) (void)hipSetDevice(a.dev);
+    (void)hipDeviceSynchronize();
+  }
+  if (cur >= 0 && !done.empty()) (void)hipSetDevice(cur);
+}
+
 afmm_status dev_alloc(afmm_plan* P, void** ptr, size_t bytes) {
   *ptr = nullptr;
   if (bytes == 0) return AFMM_OK;
   if (P->opt.max_device_bytes && P->bytes + bytes > P->opt.max_device_bytes)
     return fail(AFMM_E_OUT_OF_MEMORY, "plan would exceed max_device_bytes");
-  if (hipMalloc(ptr, bytes) != hipSuccess) {
-    *ptr = nullptr;
-    (void)hipGetLastError();
-    return fail(AFMM_E_OUT_OF_MEMORY, "hipMalloc failed");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(AFMM_E_DEVICE, "no current device");
+  const bool cached = P->opt.max_device_bytes == 0;
+  size_t cap = bytes;
+  void* p = cached ? cache_take(dev, bytes, &cap) : nullptr;
+  if (!p) {
+    cap = cached ? (bytes + bytes / 8 + 4095) & ~(size_t)4095 : bytes;
+    if (hipMalloc(&p, cap) != hipSuccess) {
+      // give the cached buffers back to the driver and try once more
+      (void)hipGetLastError();
+      cache_release(dev);
+      if (hipMalloc(&p, cap) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(AFMM_E_OUT_OF_MEMORY, "hipMalloc failed");
+      }
+    }
   }
-  P->allocs.push_back(*ptr);
+  P->allocs.push_back({p, cap, dev, cached});
+  *ptr = p;
   P->bytes += bytes;
   return AFMM_OK;
 }
@@ -1134,7 +1244,11 @@ void free_plan(afmm_plan* P) {
   drop_graphs(P);
   if (P->cap) (void)hipStreamDestroy(P->cap);
   P->cap = nullptr;
-  for (void* p : P->allocs) (void)hipFree(p);
+  sync_alloc_devices(P);
+  for (const auto& a : P->allocs) {
+    if (a.cached) cache_put(a.dev, a.p, a.cap);
+    else (void)hipFree(a.p);
+  }
   P->allocs.clear();
   if (P->h_flag) (void)hipHostFree(P->h_flag);
   P->h_flag = nullptr;
@@ -1286,11 +1400,21 @@ static int append_tiles(const Topology& T, int target, const std::vector<int32_t
 static void dev_free(afmm_plan* P, void* ptr, size_t bytes) {
   if (!ptr) return;
   for (size_t i = 0; i < P->allocs.size(); ++i)
-    if (P->allocs[i] == ptr) {
+    if (P->allocs[i].p == ptr) {
+      const afmm_plan::Alloc a = P->allocs[i];
       P->allocs.erase(P->allocs.begin() + (long)i);
+      if (a.cached) {
+        int cur = -1;
+        (void)hipGetDevice(&cur);
+        if (cur != a.dev) (void)hipSetDevice(a.dev);
+        (void)hipDeviceSynchronize();
+        if (cur >= 0 && cur != a.dev) (void)hipSetDevice(cur);
+        cache_put(a.dev, a.p, a.cap);
+      } else {
+        (void)hipFree(ptr);
+      }
       break;
     }
-  (void)hipFree(ptr);
   P->bytes -= bytes;
 }
 
@@ -1401,7 +1525,6 @@ static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
   const bool mixed = P->opt.precision == AFMM_FP32_MIXED;
   const int f64 = mixed ? P->opt.fp64_levels : 1 << 20;
   build_groups(T);
-  fill_info(P->info, P->work, T, P->opt);
   P->tabs = tables_for(P->opt.p);
   afmm_status s;
   for (int l = 0; l <= T.lmax; ++l) {
@@ -1723,7 +1846,16 @@ static afmm_status plan_finish(afmm_plan* P, hipStream_t st) {
       hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming) != hipSuccess)
     return fail(AFMM_E_DEVICE, "stream/event creation failed");
   if (hipStreamSynchronize(st) != hipSuccess) return fail(AFMM_E_DEVICE, "upload synchronisation failed");
-  P->info.device_bytes = P->bytes;
+  return AFMM_OK;
+}
+
+// Counts the plan's sizes and work once (the topology is fixed after plan_finish).
+static afmm_status ensure_info(const afmm_plan* P) {
+  try {
+    std::call_once(P->info_once, [P] { fill_info(P->info, P->work, P->topo, P->opt); });
+  } catch (const std::bad_alloc&) {
+    return fail(AFMM_E_OUT_OF_MEMORY, "host allocation failed while counting the plan's work");
+  }
   return AFMM_OK;
 }
 
@@ -1802,6 +1934,11 @@ static afmm_status afmm_plan_replan_impl(const afmm_plan* old, const afmm_hierar
   return AFMM_OK;
 }
 
+extern "C" afmm_status afmm_release_cached_memory(void) {
+  cache_release(-1);
+  return AFMM_OK;
+}
+
 extern "C" afmm_status afmm_plan_destroy(afmm_plan* P) {
   if (!P) return AFMM_OK;
   free_plan(P);
@@ -1811,6 +1948,7 @@ extern "C" afmm_status afmm_plan_destroy(afmm_plan* P) {
 
 extern "C" afmm_status afmm_plan_get_info(const afmm_plan* P, afmm_plan_info* out) {
   if (!P || !out) return fail(AFMM_E_INVALID_ARG, "null argument");
+  if (afmm_status s = ensure_info(P)) return s;
   *out = P->info;
   out->device_bytes = P->bytes;  // live: the autotuner and the adjoint change it
   return AFMM_OK;
@@ -2205,6 +2343,8 @@ static afmm_status afmm_solve_impl(afmm_plan* P, int32_t level, int32_t icount, 
 
 extern "C" afmm_status afmm_plan_set_profiling(afmm_plan* P, int32_t enable) {
   if (!P) return fail(AFMM_E_INVALID_ARG, "null plan");
+  // timed launches take their flops and bytes from the work counts
+  if (afmm_status s = enable ? ensure_info(P) : AFMM_OK) return s;
   P->profiling = enable != 0;
   return AFMM_OK;
 }
@@ -3098,6 +3238,7 @@ static afmm_status afmm_batch_get_profile_impl(afmm_batch* B, afmm_stage_time* o
 
 extern "C" afmm_status afmm_batch_get_info(const afmm_batch* B, afmm_plan_info* out) {
   if (!B || !out) return fail(AFMM_E_INVALID_ARG, "null argument");
+  if (afmm_status s = ensure_info(B->plan)) return s;
   *out = B->plan->info;
   out->device_bytes = B->plan->bytes;
   return AFMM_OK;

@@ -24,51 +24,9 @@
 #include <vector>
 
 #include "afmm.h"
+#include "host_pool.h"
 
 namespace afmm {
-
-// Host loops over cells, groups and table entries run on up to 16 threads (a
-// GPU's share of the host cores).  Each worker takes one contiguous range of
-// [0, n); workers write disjoint outputs or integer partial counts that the
-// caller sums in range order, so results do not depend on the thread count.
-// A worker that cannot be started runs in the calling thread; an exception
-// in a range is rethrown in the calling thread after every worker joined.
-inline int host_threads() {
-  static const int n = [] {
-    const unsigned h = std::thread::hardware_concurrency();
-    return (int)std::max(1u, std::min(16u, h));
-  }();
-  return n;
-}
-inline int parts_for(int64_t n, int64_t grain = 1 << 14) {
-  return (int)std::max<int64_t>(1, std::min<int64_t>(host_threads(), n / grain));
-}
-// fn(begin, end, part) for part = 0 .. parts - 1
-template <typename F>
-void parallel_ranges(int64_t n, int parts, F&& fn) {
-  parts = std::max(parts, 1);
-  std::vector<std::exception_ptr> err((size_t)parts);
-  auto run = [&](int t) {
-    try {
-      fn(n * t / parts, n * (t + 1) / parts, t);
-    } catch (...) {
-      err[(size_t)t] = std::current_exception();
-    }
-  };
-  std::vector<std::thread> th;
-  th.reserve((size_t)parts - 1);
-  for (int t = 1; t < parts; ++t) {
-    try {
-      th.emplace_back(run, t);
-    } catch (...) {
-      run(t);
-    }
-  }
-  run(0);
-  for (auto& x : th) x.join();
-  for (auto& e : err)
-    if (e) std::rethrow_exception(e);
-}
 
 constexpr int kMaxLevel = 21;
 constexpr int kPMax = 8;

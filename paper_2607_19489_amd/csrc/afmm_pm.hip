@@ -105,25 +105,24 @@ static afmm_status particle_hierarchy_impl(int32_t levelmin, int32_t levelmax, i
   };
   for (int it = 0; it < 64; ++it) {
     bool changed = false;
-    // top-down: wanted cells that exist
-    std::vector<uint64_t> cells;  // cells of level l (sorted)
-    {
-      const int64_t n0 = (int64_t)1 << levelmin;
-      cells.reserve((size_t)n0 * n0 * n0);
-      for (int64_t a = 0; a < n0; ++a)
-        for (int64_t b = 0; b < n0; ++b)
-          for (int64_t c = 0; c < n0; ++c) cells.push_back(key3(a, b, c, levelmin));
-    }
+    // top-down: wanted cells that exist (level levelmin is complete and the
+    // wanted keys are clipped to the box, so there every wanted cell exists)
+    std::vector<uint64_t> cells;  // cells of level l > levelmin (sorted)
     for (int i = 0; i < nl; ++i) {
       const int l = levelmin + i;
-      std::vector<uint64_t> add;
-      std::set_intersection(want[i].begin(), want[i].end(), cells.begin(), cells.end(), std::back_inserter(add));
       std::vector<uint64_t> merged;
-      std::set_union(R[i].begin(), R[i].end(), add.begin(), add.end(), std::back_inserter(merged));
-      std::vector<uint64_t> kept;  // refined cells must exist
-      std::set_intersection(merged.begin(), merged.end(), cells.begin(), cells.end(), std::back_inserter(kept));
-      if (kept.size() != R[i].size()) changed = true;
-      R[i].swap(kept);
+      if (i == 0) {
+        std::set_union(R[0].begin(), R[0].end(), want[0].begin(), want[0].end(), std::back_inserter(merged));
+      } else {
+        std::vector<uint64_t> add;
+        std::set_intersection(want[i].begin(), want[i].end(), cells.begin(), cells.end(), std::back_inserter(add));
+        std::vector<uint64_t> u;
+        std::set_union(R[i].begin(), R[i].end(), add.begin(), add.end(), std::back_inserter(u));
+        // refined cells must exist
+        std::set_intersection(u.begin(), u.end(), cells.begin(), cells.end(), std::back_inserter(merged));
+      }
+      if (merged.size() != R[i].size()) changed = true;
+      R[i].swap(merged);
       cells = exists_children(R[i], l);
     }
     // bottom-up grading closure
@@ -151,17 +150,33 @@ static afmm_status particle_hierarchy_impl(int32_t levelmin, int32_t levelmax, i
     if (!changed) break;
     if (it == 63) return pm_fail(AFMM_E_INVALID_ARG, "refinement did not reach a fixed point");
   }
-  auto* H = new afmm_particle_hierarchy();
+  std::unique_ptr<afmm_particle_hierarchy> H(new afmm_particle_hierarchy());
   H->levelmin = levelmin;
-  std::vector<uint64_t> cells;
+  // level levelmin: the whole grid, in key order, refined where R says
   {
     const int64_t n0 = (int64_t)1 << levelmin;
+    const std::vector<uint64_t> none;
+    const std::vector<uint64_t>& ref = nl > 0 ? R[0] : none;
+    size_t total = (size_t)(n0 * n0 * n0);
+    for (int i = 0; i < nl; ++i) total += 8 * R[i].size();
+    H->ijk.reserve(3 * total);
+    H->refined.reserve(total);
+    H->ncell.push_back(n0 * n0 * n0);
+    size_t r = 0;
     for (int64_t a = 0; a < n0; ++a)
       for (int64_t b = 0; b < n0; ++b)
-        for (int64_t c = 0; c < n0; ++c) cells.push_back(key3(a, b, c, levelmin));
+        for (int64_t c = 0; c < n0; ++c) {
+          H->ijk.push_back((int32_t)a);
+          H->ijk.push_back((int32_t)b);
+          H->ijk.push_back((int32_t)c);
+          const bool on = r < ref.size() && ref[r] == key3(a, b, c, levelmin);
+          r += on;
+          H->refined.push_back(on ? 1 : 0);
+        }
   }
+  std::vector<uint64_t> cells = nl > 0 ? exists_children(R[0], levelmin) : std::vector<uint64_t>();
   int top = levelmin;
-  for (int l = levelmin; l <= levelmax && !cells.empty(); ++l) {
+  for (int l = levelmin + 1; l <= levelmax && !cells.empty(); ++l) {
     top = l;
     const std::vector<uint64_t> none;
     const std::vector<uint64_t>& ref = l < levelmax ? R[l - levelmin] : none;
@@ -177,7 +192,7 @@ static afmm_status particle_hierarchy_impl(int32_t levelmin, int32_t levelmax, i
     if (l < levelmax) cells = exists_children(ref, l);
   }
   H->levelmax = top;
-  *out = H;
+  *out = H.release();
   return AFMM_OK;
 }
 

@@ -180,7 +180,9 @@ afmm_status afmm_plan_create(const afmm_hierarchy* h, const afmm_options* opt, v
  * buffers for later plans on that device, up to 2 GiB per device (the oldest
  * are freed first); plans created with max_device_bytes free theirs.
  * afmm_release_cached_memory frees every kept buffer; the library also does so
- * by itself before it reports an allocation failure.  Thread-safe.
+ * by itself before it reports an allocation failure.  Call it before a device
+ * reset (hipDeviceReset), which would leave the kept buffers dangling.
+ * Thread-safe.
  */
 afmm_status afmm_plan_destroy(afmm_plan* plan);
 afmm_status afmm_release_cached_memory(void);

@@ -152,27 +152,33 @@ static afmm_status particle_hierarchy_impl(int32_t levelmin, int32_t levelmax, i
   }
   std::unique_ptr<afmm_particle_hierarchy> H(new afmm_particle_hierarchy());
   H->levelmin = levelmin;
-  // level levelmin: the whole grid, in key order, refined where R says
+  // level levelmin: the whole grid in key order (the key of a cell of the
+  // complete grid is its index), refined where R says; in ranges on the host
+  // threads, each starting its walk of R at its first key
   {
-    const int64_t n0 = (int64_t)1 << levelmin;
+    const int64_t n0 = (int64_t)1 << levelmin, nb = n0 * n0 * n0;
     const std::vector<uint64_t> none;
     const std::vector<uint64_t>& ref = nl > 0 ? R[0] : none;
-    size_t total = (size_t)(n0 * n0 * n0);
+    size_t total = (size_t)nb;
     for (int i = 0; i < nl; ++i) total += 8 * R[i].size();
     H->ijk.reserve(3 * total);
     H->refined.reserve(total);
-    H->ncell.push_back(n0 * n0 * n0);
-    size_t r = 0;
-    for (int64_t a = 0; a < n0; ++a)
-      for (int64_t b = 0; b < n0; ++b)
-        for (int64_t c = 0; c < n0; ++c) {
-          H->ijk.push_back((int32_t)a);
-          H->ijk.push_back((int32_t)b);
-          H->ijk.push_back((int32_t)c);
-          const bool on = r < ref.size() && ref[r] == key3(a, b, c, levelmin);
-          r += on;
-          H->refined.push_back(on ? 1 : 0);
-        }
+    H->ijk.resize(3 * (size_t)nb);
+    H->refined.resize((size_t)nb);
+    H->ncell.push_back(nb);
+    int32_t* ijk = H->ijk.data();
+    uint8_t* on = H->refined.data();
+    parallel_ranges(nb, parts_for(nb), [&](int64_t b, int64_t e, int) {
+      size_t r = (size_t)(std::lower_bound(ref.begin(), ref.end(), (uint64_t)b) - ref.begin());
+      for (int64_t i = b; i < e; ++i) {
+        ijk[3 * i] = (int32_t)(i >> (2 * levelmin));
+        ijk[3 * i + 1] = (int32_t)((i >> levelmin) & (n0 - 1));
+        ijk[3 * i + 2] = (int32_t)(i & (n0 - 1));
+        const bool hit = r < ref.size() && ref[r] == (uint64_t)i;
+        r += hit;
+        on[i] = hit ? 1 : 0;
+      }
+    });
   }
   std::vector<uint64_t> cells = nl > 0 ? exists_children(R[0], levelmin) : std::vector<uint64_t>();
   int top = levelmin;

@@ -317,49 +317,62 @@ static afmm_status append_hierarchy(Topology& T, const afmm_hierarchy& h, int64_
   return AFMM_OK;
 }
 
+// Lists built on the host threads: each contiguous range of candidates fills
+// its own lists, which are joined in range order (the lists are in rank order,
+// whatever the thread count).
+template <int NL, typename F>
+static void parallel_lists(int64_t n, std::vector<int32_t>* const (&out)[NL], F&& fill) {
+  const int parts = parts_for(n, 4096);
+  std::vector<std::array<std::vector<int32_t>, NL>> loc((size_t)parts);
+  parallel_ranges(n, parts, [&](int64_t b, int64_t e, int part) { fill(b, e, loc[(size_t)part]); });
+  for (int k = 0; k < NL; ++k) {
+    size_t tot = 0;
+    for (auto& x : loc) tot += x[k].size();
+    out[k]->clear();
+    out[k]->reserve(tot);
+    for (auto& x : loc) out[k]->insert(out[k]->end(), x[k].begin(), x[k].end());
+  }
+}
+
 static void build_groups(Topology& T) {
   for (int l = 1; l <= T.lmax; ++l) {
     const HostLevel& P = T.lv[l - 1];
     const HostLevel& C = T.lv[l];
     auto& lg = T.leafgrp[l];
-    auto& mg = T.m2lgrp[l];
-    auto& ul = T.upleaf[l - 1];
-    auto& um = T.upmix[l - 1];
-    lg.clear();
-    mg.clear();
-    ul.clear();
-    um.clear();
-    for (int32_t r = 0; r < P.nref(); ++r) {
-      bool leaf = false, refd = false;
-      for (int o = 0; o < 8; ++o) {
-        if (C.rank[8 * r + o] < 0) leaf = true;
-        else refd = true;
+    std::vector<int32_t>* const g4[4] = {&lg, &T.m2lgrp[l], &T.upleaf[l - 1], &T.upmix[l - 1]};
+    parallel_lists<4>(P.nref(), g4, [&](int64_t b, int64_t e, std::array<std::vector<int32_t>, 4>& o4) {
+      for (int32_t r = (int32_t)b; r < (int32_t)e; ++r) {
+        bool leaf = false, refd = false;
+        for (int o = 0; o < 8; ++o) {
+          if (C.rank[8 * r + o] < 0) leaf = true;
+          else refd = true;
+        }
+        if (leaf) o4[0].push_back(r);
+        if (refd && l >= 3) o4[1].push_back(r);
+        o4[refd ? 3 : 2].push_back(r);
       }
-      if (leaf) lg.push_back(r);
-      if (refd && l >= 3) mg.push_back(r);
-      (refd ? um : ul).push_back(r);
-    }
+    });
     // groups whose near candidates (children of the 27 neighbours of F)
     // include a refined level-l cell: their near-field M2P runs apart
-    auto& nm = T.nmgrp[l];
-    auto& av = T.adjvgrp[l];
-    nm.clear();
-    av.clear();
-    for (int32_t r : lg) {
-      bool any = false, coarse = false;
-      const int32_t* nb = &P.nbr[(size_t)r * 27];
-      for (int e = 0; e < 27; ++e) {
-        const int32_t q = nb[e];
-        if (q < 0) continue;
-        if (P.rank[q] < 0) {
-          coarse = true;
-          continue;
+    std::vector<int32_t>* const g2[2] = {&T.nmgrp[l], &T.adjvgrp[l]};
+    parallel_lists<2>((int64_t)lg.size(), g2, [&](int64_t b, int64_t e, std::array<std::vector<int32_t>, 2>& o2) {
+      for (int64_t i = b; i < e; ++i) {
+        const int32_t r = lg[(size_t)i];
+        bool any = false, coarse = false;
+        const int32_t* nb = &P.nbr[(size_t)r * 27];
+        for (int e2 = 0; e2 < 27; ++e2) {
+          const int32_t q = nb[e2];
+          if (q < 0) continue;
+          if (P.rank[q] < 0) {
+            coarse = true;
+            continue;
+          }
+          for (int op = 0; op < 8 && !any; ++op) any = C.rank[8 * P.rank[q] + op] >= 0;
         }
-        for (int op = 0; op < 8 && !any; ++op) any = C.rank[8 * P.rank[q] + op] >= 0;
+        if (any) o2[0].push_back(r);
+        if (any || coarse) o2[1].push_back(r);
       }
-      if (any) nm.push_back(r);
-      if (any || coarse) av.push_back(r);
-    }
+    });
   }
 }
 

@@ -393,7 +393,9 @@ afmm_status afmm_batch_autotune(afmm_batch* batch, const double* const* d_mass, 
  * cell within `nexpand` cells (Chebyshev distance, clipped to the box) of the
  * 2x2x2 cloud of a particle at level l is refined, then the strong grading
  * rule (Sec. 3.2) is closed; levelmax of the result is the deepest level that
- * has cells.  pos: host [np][3], inside [0, boxlen).  The result is owned by
+ * has cells.  Cells come level by level, each level in Morton order (bit b
+ * of i, j, k at key bits 3b, 3b + 1, 3b + 2), the order a plan keeps its
+ * levels in.  pos: host [np][3], inside [0, boxlen).  The result is owned by
  * the library: afmm_particle_hierarchy_view fills an afmm_hierarchy that
  * points into it (valid until afmm_particle_hierarchy_destroy).
  */

@@ -73,19 +73,6 @@ struct Topology {
   std::vector<std::vector<int64_t>> level_off;  // flat slot offset of each AMR level (per hierarchy)
 };
 
-static inline uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) {
-  auto spread = [](uint64_t v) {
-    v &= 0x1fffff;
-    v = (v | v << 32) & 0x1f00000000ffffULL;
-    v = (v | v << 16) & 0x1f0000ff0000ffULL;
-    v = (v | v << 8) & 0x100f00f00f00f00fULL;
-    v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
-    v = (v | v << 2) & 0x1249249249249249ULL;
-    return v;
-  };
-  return spread(x) | (spread(y) << 1) | (spread(z) << 2);
-}
-
 // LSD radix sort of (Morton key, caller index) pairs by key, 8 key bits per
 // pass over the `bits` low bits that the keys use.  Each pass counts the
 // digits of every range, then each range scatters its items after those of

@@ -28,6 +28,21 @@
 
 namespace afmm {
 
+// Morton key of cell (x, y, z): bit b of x, y, z at bits 3b, 3b + 1, 3b + 2;
+// every level of a plan is ordered by it.
+inline uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) {
+  auto spread = [](uint64_t v) {
+    v &= 0x1fffff;
+    v = (v | v << 32) & 0x1f00000000ffffULL;
+    v = (v | v << 16) & 0x1f0000ff0000ffULL;
+    v = (v | v << 8) & 0x100f00f00f00f00fULL;
+    v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
+    v = (v | v << 2) & 0x1249249249249249ULL;
+    return v;
+  };
+  return spread(x) | (spread(y) << 1) | (spread(z) << 2);
+}
+
 constexpr int kMaxLevel = 21;
 constexpr int kPMax = 8;
 constexpr int kKMax = 165;          // C(kPMax + 3, 3)

@@ -58,7 +58,7 @@ struct afmm_particle_hierarchy {
 // level l; then close the strong grading rule (a refined level-l cell needs the
 // 27 level-(l-1) neighbours of its father refined) bottom-up, and repeat both
 // to a fixed point (each step only adds refinement).  Cells appear level by
-// level, each level in ascending (i, j, k)-major key order.
+// level, each level in Morton order.
 static afmm_status particle_hierarchy_impl(int32_t levelmin, int32_t levelmax, int32_t nexpand, int64_t np,
                                            const double* pos, double boxlen, afmm_particle_hierarchy** out) {
   if (!out || (np > 0 && !pos)) return pm_fail(AFMM_E_INVALID_ARG, "null argument");
@@ -152,31 +152,62 @@ static afmm_status particle_hierarchy_impl(int32_t levelmin, int32_t levelmax, i
   }
   std::unique_ptr<afmm_particle_hierarchy> H(new afmm_particle_hierarchy());
   H->levelmin = levelmin;
-  // level levelmin: the whole grid in key order (the key of a cell of the
-  // complete grid is its index), refined where R says; in ranges on the host
-  // threads, each starting its walk of R at its first key
+  // every level in Morton order (the order the plan keeps its levels in, so
+  // that a plan built from this hierarchy need not sort it)
+  auto emit = [&](const std::vector<uint64_t>& cells, int l, const std::vector<uint64_t>& ref) {
+    const int64_t n = (int64_t)cells.size();
+    std::vector<std::pair<uint64_t, uint64_t>> mk((size_t)n);  // (Morton key, (i, j, k)-major key)
+    parallel_ranges(n, parts_for(n), [&](int64_t b, int64_t e, int) {
+      for (int64_t i = b; i < e; ++i) {
+        int64_t c[3];
+        unkey3(cells[(size_t)i], l, c);
+        mk[(size_t)i] = {morton3((uint32_t)c[0], (uint32_t)c[1], (uint32_t)c[2]), cells[(size_t)i]};
+      }
+    });
+    std::sort(mk.begin(), mk.end());
+    const size_t b0 = H->refined.size();
+    H->ncell.push_back(n);
+    H->ijk.resize(3 * (b0 + (size_t)n));
+    H->refined.resize(b0 + (size_t)n);
+    int32_t* ijk = H->ijk.data() + 3 * b0;
+    uint8_t* on = H->refined.data() + b0;
+    parallel_ranges(n, parts_for(n), [&](int64_t b, int64_t e, int) {
+      for (int64_t i = b; i < e; ++i) {
+        const uint64_t k = mk[(size_t)i].second;
+        int64_t c[3];
+        unkey3(k, l, c);
+        ijk[3 * i] = (int32_t)c[0];
+        ijk[3 * i + 1] = (int32_t)c[1];
+        ijk[3 * i + 2] = (int32_t)c[2];
+        on[i] = std::binary_search(ref.begin(), ref.end(), k) ? 1 : 0;
+      }
+    });
+  };
+  const std::vector<uint64_t> none;
   {
+    // level levelmin: the whole grid; a complete grid's Morton keys are 0 .. n - 1
     const int64_t n0 = (int64_t)1 << levelmin, nb = n0 * n0 * n0;
-    const std::vector<uint64_t> none;
     const std::vector<uint64_t>& ref = nl > 0 ? R[0] : none;
     size_t total = (size_t)nb;
     for (int i = 0; i < nl; ++i) total += 8 * R[i].size();
     H->ijk.reserve(3 * total);
     H->refined.reserve(total);
+    std::vector<uint8_t> flag((size_t)nb, 0);  // by (i, j, k)-major key
+    for (uint64_t k : ref) flag[(size_t)k] = 1;
     H->ijk.resize(3 * (size_t)nb);
     H->refined.resize((size_t)nb);
     H->ncell.push_back(nb);
     int32_t* ijk = H->ijk.data();
     uint8_t* on = H->refined.data();
     parallel_ranges(nb, parts_for(nb), [&](int64_t b, int64_t e, int) {
-      size_t r = (size_t)(std::lower_bound(ref.begin(), ref.end(), (uint64_t)b) - ref.begin());
-      for (int64_t i = b; i < e; ++i) {
-        ijk[3 * i] = (int32_t)(i >> (2 * levelmin));
-        ijk[3 * i + 1] = (int32_t)((i >> levelmin) & (n0 - 1));
-        ijk[3 * i + 2] = (int32_t)(i & (n0 - 1));
-        const bool hit = r < ref.size() && ref[r] == (uint64_t)i;
-        r += hit;
-        on[i] = hit ? 1 : 0;
+      for (int64_t m = b; m < e; ++m) {
+        uint32_t c[3] = {0, 0, 0};
+        for (int bit = 0; bit < levelmin; ++bit)
+          for (int d = 0; d < 3; ++d) c[d] |= (uint32_t)((m >> (3 * bit + d)) & 1) << bit;
+        ijk[3 * m] = (int32_t)c[0];
+        ijk[3 * m + 1] = (int32_t)c[1];
+        ijk[3 * m + 2] = (int32_t)c[2];
+        on[m] = flag[(size_t)key3(c[0], c[1], c[2], levelmin)];
       }
     });
   }
@@ -184,17 +215,8 @@ static afmm_status particle_hierarchy_impl(int32_t levelmin, int32_t levelmax, i
   int top = levelmin;
   for (int l = levelmin + 1; l <= levelmax && !cells.empty(); ++l) {
     top = l;
-    const std::vector<uint64_t> none;
     const std::vector<uint64_t>& ref = l < levelmax ? R[l - levelmin] : none;
-    H->ncell.push_back((int64_t)cells.size());
-    for (uint64_t k : cells) {
-      int64_t c[3];
-      unkey3(k, l, c);
-      H->ijk.push_back((int32_t)c[0]);
-      H->ijk.push_back((int32_t)c[1]);
-      H->ijk.push_back((int32_t)c[2]);
-      H->refined.push_back(std::binary_search(ref.begin(), ref.end(), k) ? 1 : 0);
-    }
+    emit(cells, l, ref);
     if (l < levelmax) cells = exists_children(ref, l);
   }
   H->levelmax = top;

@@ -2,8 +2,9 @@
 
 - The library's hierarchy that tracks particles (afmm_particle_hierarchy_create,
   C++) against ``synth.build_graded`` with the same refinement predicate
-  (numpy): identical cells, flags and order, and graded by the independent
-  checker.
+  (numpy): identical cells and flags per level (the library emits each level in
+  Morton order, checked here, the numpy builder in (i, j, k) order), and graded
+  by the independent checker.
 - The time loop skips rebuilding that hierarchy while no particle's cloud
   cells change: whenever the cloud cells of two position sets agree, the
   library builds identical hierarchies from them (positions on and a few ulps
@@ -20,11 +21,26 @@ from paper_2607_19489_amd.pm import ParticleHierarchy, ParticleMesh, binary_init
 from synth.hierarchy import build_graded, check_graded
 
 
+def _morton(ijk):
+    key = np.zeros(ijk.shape[0], dtype=np.int64)
+    for b in range(21):
+        for d in range(3):
+            key |= ((ijk[:, d].astype(np.int64) >> b) & 1) << (3 * b + d)
+    return key
+
+
 def _same(a, b):
+    """Same levels, same cells with the same refined flags on every level; the
+    library's levels in strictly increasing Morton order."""
     assert a.levelmin == b.levelmin and a.levelmax == b.levelmax
     assert np.array_equal(np.asarray(a.ncell), np.asarray(b.ncell))
-    assert np.array_equal(a.flat_ijk(), b.flat_ijk())
-    assert np.array_equal(a.flat_refined(), b.flat_refined())
+    off = np.concatenate([[0], np.cumsum(np.asarray(a.ncell))])
+    for i in range(len(off) - 1):
+        ia, ra = a.flat_ijk()[off[i]:off[i + 1]], a.flat_refined()[off[i]:off[i + 1]]
+        ib, rb = b.flat_ijk()[off[i]:off[i + 1]], b.flat_refined()[off[i]:off[i + 1]]
+        assert np.all(np.diff(_morton(ia)) > 0)
+        oa, ob = np.lexsort(ia.T[::-1]), np.lexsort(ib.T[::-1])
+        assert np.array_equal(ia[oa], ib[ob]) and np.array_equal(ra[oa], rb[ob])
 
 
 @pytest.mark.parametrize("lmin,lmax", [(3, 3), (3, 5), (4, 6), (2, 6)])

@@ -118,6 +118,13 @@ def test_max_device_bytes_gives_out_of_memory_before_any_device_call():
     assert b"max_device_bytes" in _lib.lib().afmm_last_error()
 
 
+def test_release_of_an_empty_buffer_cache_touches_no_device():
+    """afmm_release_cached_memory with nothing cached returns AFMM_OK without a GPU,
+    also when called twice (the capped plan above never put a buffer in the cache)."""
+    assert _lib.lib().afmm_release_cached_memory() == 0
+    A.release_cached_memory()
+
+
 def test_m2p_shape_option_validated():
     h = build_graded(3, 5, refine_sphere((0.5, 0.5, 0.5), {3: 0.3, 4: 0.2}))
     a = A.hierarchy_check(h, p=4, precision="fp32")

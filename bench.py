@@ -489,8 +489,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this solver runs on one GPU; multi-GPU sharding is described in DESIGN.md "
-              "but not built, so --gpus must be 1", file=sys.stderr)
+        print("bench.py: this solver runs on one GPU; sharding over several GPUs is not built, "
+              "so --gpus must be 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
